@@ -1,0 +1,683 @@
+/*
+ * sdgr_oracle.c -- TEST INFRASTRUCTURE, not part of the product path.
+ *
+ * Plain, slow FP64 CPU reference of the SAR Differentiable Gaussian
+ * Rasterizer (SAR-GS, arXiv 2506.21633, Sec. II). Only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg may load this library.
+ * It shares no code with the HIP implementation.
+ *
+ * What it computes, per view (Sec. II-A):
+ *   1. Mapping and projection (Eq. for W, R_r, Sigma' = J^T R^T Sigma R J,
+ *      P_C, P_I): every Gaussian is mapped to radar coordinates
+ *      (x azimuth, y elevation perpendicular to the line of sight, z slant
+ *      range = depth) and projected orthographically onto the computation
+ *      plane (x, y) and the imaging plane (x, z), giving 2D centres and 2D
+ *      covariances on both planes.
+ *   2. Scattering intensity (Eq. for I_i and delta): a ray leaves the centre
+ *      of every computation-plane cell along the line of sight; along it the
+ *      Gaussians are taken front to back in depth order, each absorbing a
+ *      fraction alpha = 1 - exp(-kappa g) of what reaches it, with g the
+ *      peak-1 footprint of its projected Gaussian at the ray. Its share of
+ *      the incident intensity, summed over all rays, is A_i; I_i = P_i A_i.
+ *   3. Image formation (Eq. for S_{n,m}): every imaging-plane pixel sums the
+ *      intensities of the Gaussians covering it, weighted by their footprint
+ *      there (additive layover, order-free).
+ * No tiles, no culling other than the footprint's own cutoff q < q_max, an
+ * explicit sort per ray.
+ *
+ * Backward (Sec. II-B): the exact derivative of the forward above, written
+ * out directly. For one ray with depth-ordered Gaussians k and optical
+ * depths x_k = kappa_k g_k, the ray's share of the loss is
+ *     Phi = sum_k c_k alpha_k T_k,   T_k = exp(-sum_{j<k} x_j),
+ * with c_k = dL/dA_k, so that
+ *     dPhi/dx_k = c_k (1 - alpha_k) T_k - sum_{j>k} c_j alpha_j T_j,
+ * a plain suffix sum (the paper states the two extinction derivatives are
+ * equal; only their sum kappa is an input here).
+ *
+ * Readings of the paper taken here where it is silent or garbled (each one
+ * is listed in the design notes of the repository):
+ *   - theta in R_r is the grazing (depression) angle; x_r = R_r x_w, the
+ *     translation T_r and altitude h only add a constant range offset under
+ *     the orthographic projection and are dropped; the image is centred on
+ *     the world origin.
+ *   - the quadratic form delta uses the inverse 2D covariance (a conic) with
+ *     the 1/2 of the Gaussian density: footprint
+ *         f(q) = (exp(-q/2) - eps) / (1 - eps) for q < q_max, else 0,
+ *     eps = exp(-q_max/2): continuous, peak 1, zero beyond the cutoff.
+ *   - alpha_i = 1 - exp(-kappa_i g_i) with kappa = k_e+ + k_e-; transmittance
+ *     over the Gaussians strictly in front; incident intensity 1; no
+ *     cell-area factor.
+ *   - depth order: key fl32_rn(z computed in FP64), ties by ascending index.
+ *   - computation plane spacing (d_az, d_rg tan(theta)) and size of the
+ *     image by default (Eq. for P_C); imaging plane rows = slant range at
+ *     d_rg, columns = azimuth at d_az (Eq. for P_I, read as a plain
+ *     slant-range/azimuth grid); cell and pixel centres at +1/2.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no FMA
+ * contraction, so the FP64 depth is the sequence of rounded products and
+ * sums written below).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_VERSION 1
+
+typedef struct {
+    double az, gr;          /* azimuth phi, grazing theta [rad] */
+    int64_t W, H;           /* image columns (azimuth), rows (slant range) */
+    double dA, dR;          /* image spacings [m] */
+    int64_t Wc, Hc;         /* computation-plane cells */
+    double dAc, dEc;        /* computation-plane spacings [m] */
+    double ex[3], ey[3], ez[3];  /* rows of R_r */
+} OView;
+
+typedef struct {
+    int valid;
+    double qn[4], qnorm, s[3], R[9], M[9];
+    double Sig[9];               /* 3D covariance, full 3x3 */
+    double x, y, z;              /* radar coordinates */
+    double cC[2], SC[3], QC[3];  /* plane C: centre, cov (xx,xy,yy), conic */
+    double cI[2], SI[3], QI[3];  /* plane I */
+    double bxC[4], bxI[4];       /* ellipse bounding boxes (x0,x1,y0,y1) */
+    float key;
+} OG;
+
+/* ---------------------------------------------------------------- views */
+
+/* Rows of the world-to-radar rotation R_r(phi, theta) (Sec. II-A). */
+void orc_axes(double phi, double theta, double* ex, double* ey, double* ez)
+{
+    double sp = sin(phi), cp = cos(phi), st = sin(theta), ct = cos(theta);
+    ex[0] = -sp;      ex[1] = -cp;      ex[2] = 0.0;
+    ey[0] = -st * cp; ey[1] = st * sp;  ey[2] = ct;
+    ez[0] = -ct * cp; ez[1] = ct * sp;  ez[2] = -st;
+}
+
+/* p = [azimuth, grazing, img_w, img_h, d_az, d_rg, comp_w, comp_h,
+ *      comp_d_az, comp_d_el]; zeros in the comp_* slots take the defaults
+ * of the computation-plane projection (same grid, elevation spacing
+ * d_rg * tan(theta)). */
+static int view_init(OView* v, const double* p)
+{
+    v->az = p[0]; v->gr = p[1];
+    v->W = (int64_t)p[2]; v->H = (int64_t)p[3];
+    v->dA = p[4]; v->dR = p[5];
+    v->Wc = p[6] > 0 ? (int64_t)p[6] : v->W;
+    v->Hc = p[7] > 0 ? (int64_t)p[7] : v->H;
+    v->dAc = p[8] > 0 ? p[8] : v->dA;
+    v->dEc = p[9] > 0 ? p[9] : v->dR * tan(v->gr);
+    if (!(v->gr > 0.0 && v->gr < M_PI / 2) || v->W <= 0 || v->H <= 0 ||
+        v->Wc <= 0 || v->Hc <= 0 || !(v->dA > 0) || !(v->dR > 0) ||
+        !(v->dAc > 0) || !(v->dEc > 0))
+        return -1;
+    orc_axes(v->az, v->gr, v->ex, v->ey, v->ez);
+    return 0;
+}
+
+/* ----------------------------------------------------------- projection */
+
+static double dot3(const double* a, const double* b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* u^T Sigma w for a full 3x3 Sigma */
+static double quad3(const double* u, const double* S, const double* w)
+{
+    double t[3];
+    for (int r = 0; r < 3; ++r)
+        t[r] = S[3 * r] * w[0] + S[3 * r + 1] * w[1] + S[3 * r + 2] * w[2];
+    return dot3(u, t);
+}
+
+static void conic_of(const double* S, double* Q, int* ok)
+{
+    double det = S[0] * S[2] - S[1] * S[1];
+    if (!(det > 0.0) || !isfinite(det)) { *ok = 0; Q[0] = Q[1] = Q[2] = 0; return; }
+    Q[0] = S[2] / det; Q[1] = -S[1] / det; Q[2] = S[0] / det;
+}
+
+static void bbox_of(const double* c, const double* S, double q_max, double* b)
+{
+    double rx = sqrt(q_max * S[0]), ry = sqrt(q_max * S[2]);
+    b[0] = c[0] - rx; b[1] = c[0] + rx; b[2] = c[1] - ry; b[3] = c[1] + ry;
+}
+
+static void project(const OView* v, const double* mu, const double* s,
+                    const double* q, double dil, double q_max, OG* g)
+{
+    memset(g, 0, sizeof(*g));
+    int ok = 1;
+    for (int k = 0; k < 3; ++k)
+        ok &= isfinite(mu[k]) && isfinite(s[k]) && s[k] > 0.0;
+    double qq = 0;
+    for (int k = 0; k < 4; ++k) { ok &= isfinite(q[k]); qq += q[k] * q[k]; }
+    if (!ok || !(qq > 0.0)) { g->valid = 0; return; }
+    g->qnorm = sqrt(qq);
+    for (int k = 0; k < 4; ++k) g->qn[k] = q[k] / g->qnorm;
+    double w = g->qn[0], x = g->qn[1], y = g->qn[2], z = g->qn[3];
+    double* R = g->R;
+    R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z); R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z); R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y); R[7] = 2 * (y * z + w * x); R[8] = 1 - 2 * (x * x + y * y);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) g->M[3 * r + c] = R[3 * r + c] * s[c];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            g->Sig[3 * r + c] = g->M[3 * r] * g->M[3 * c] +
+                                g->M[3 * r + 1] * g->M[3 * c + 1] +
+                                g->M[3 * r + 2] * g->M[3 * c + 2];
+    for (int k = 0; k < 3; ++k) g->s[k] = s[k];
+    g->x = dot3(v->ex, mu);
+    g->y = dot3(v->ey, mu);
+    /* depth: ((ez0*mu0) + (ez1*mu1)) + (ez2*mu2), each step rounded */
+    g->z = (v->ez[0] * mu[0] + v->ez[1] * mu[1]) + v->ez[2] * mu[2];
+    float kf = (float)g->z;
+    g->key = (kf == 0.0f) ? 0.0f : kf;
+
+    g->cC[0] = g->x / v->dAc + 0.5 * (double)v->Wc;
+    g->cC[1] = g->y / v->dEc + 0.5 * (double)v->Hc;
+    g->SC[0] = quad3(v->ex, g->Sig, v->ex) / (v->dAc * v->dAc) + dil;
+    g->SC[1] = quad3(v->ex, g->Sig, v->ey) / (v->dAc * v->dEc);
+    g->SC[2] = quad3(v->ey, g->Sig, v->ey) / (v->dEc * v->dEc) + dil;
+
+    g->cI[0] = g->x / v->dA + 0.5 * (double)v->W;
+    g->cI[1] = g->z / v->dR + 0.5 * (double)v->H;
+    g->SI[0] = quad3(v->ex, g->Sig, v->ex) / (v->dA * v->dA) + dil;
+    g->SI[1] = quad3(v->ex, g->Sig, v->ez) / (v->dA * v->dR);
+    g->SI[2] = quad3(v->ez, g->Sig, v->ez) / (v->dR * v->dR) + dil;
+
+    conic_of(g->SC, g->QC, &ok);
+    conic_of(g->SI, g->QI, &ok);
+    g->valid = ok;
+    if (ok) {
+        bbox_of(g->cC, g->SC, q_max, g->bxC);
+        bbox_of(g->cI, g->SI, q_max, g->bxI);
+    }
+}
+
+static OG* project_all(const OView* v, int64_t n, const double* means,
+                       const double* scales, const double* quats, double dil,
+                       double q_max)
+{
+    OG* G = (OG*)malloc(sizeof(OG) * (size_t)(n > 0 ? n : 1));
+    if (!G) return NULL;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        project(v, means + 3 * i, scales + 3 * i, quats + 4 * i, dil, q_max, &G[i]);
+    return G;
+}
+
+/* ------------------------------------------------------------ footprint */
+
+static double quadform(const double* Q, double dx, double dy)
+{
+    return Q[0] * dx * dx + 2.0 * Q[1] * dx * dy + Q[2] * dy * dy;
+}
+
+static double foot(double q, double q_max)
+{
+    if (!(q < q_max)) return 0.0;
+    double eps = exp(-0.5 * q_max);
+    return (exp(-0.5 * q) - eps) / (1.0 - eps);
+}
+
+static double dfoot(double q, double q_max)
+{
+    if (!(q < q_max)) return 0.0;
+    double eps = exp(-0.5 * q_max);
+    return -0.5 * exp(-0.5 * q) / (1.0 - eps);
+}
+
+/* ---------------------------------------------------------- ray lists */
+
+typedef struct { float key; int64_t idx; double g, q, dx, dy; } Hit;
+
+static int hit_cmp(const void* a, const void* b)
+{
+    const Hit* x = (const Hit*)a;
+    const Hit* y = (const Hit*)b;
+    if (x->key < y->key) return -1;
+    if (x->key > y->key) return 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+/* All Gaussians whose computation-plane footprint reaches the ray through
+ * cell (col, row), in depth order. Returns the count. */
+static int64_t ray_list(const OG* G, int64_t n, int64_t col, int64_t row,
+                        double q_max, Hit* out)
+{
+    double px = (double)col + 0.5, py = (double)row + 0.5;
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!G[i].valid) continue;
+        double dx = px - G[i].cC[0], dy = py - G[i].cC[1];
+        double q = quadform(G[i].QC, dx, dy);
+        if (q < q_max) {
+            out[m].key = G[i].key; out[m].idx = i;
+            out[m].g = foot(q, q_max); out[m].q = q;
+            out[m].dx = dx; out[m].dy = dy;
+            ++m;
+        }
+    }
+    qsort(out, (size_t)m, sizeof(Hit), hit_cmp);
+    return m;
+}
+
+static int nthreads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static int thread_id(void)
+{
+#ifdef _OPENMP
+    return omp_get_thread_num();
+#else
+    return 0;
+#endif
+}
+
+/* ------------------------------------------------------------- exports */
+
+int orc_version(void) { return ORC_VERSION; }
+int orc_threads(void) { return nthreads(); }
+
+/* Resolved view: out[0..9] = W, H, dA, dR, Wc, Hc, dAc, dEc, 0, 0;
+ * out[10..18] = ex, ey, ez. */
+int orc_view(const double* p, double* out)
+{
+    OView v;
+    if (view_init(&v, p)) return -1;
+    out[0] = (double)v.W; out[1] = (double)v.H; out[2] = v.dA; out[3] = v.dR;
+    out[4] = (double)v.Wc; out[5] = (double)v.Hc; out[6] = v.dAc; out[7] = v.dEc;
+    out[8] = out[9] = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        out[10 + k] = v.ex[k]; out[13 + k] = v.ey[k]; out[16 + k] = v.ez[k];
+    }
+    return 0;
+}
+
+/* Per-Gaussian projected quantities, 21 doubles each:
+ * [0] valid [1] x [2] y [3] z(depth) [4] key (fl32 of depth)
+ * [5,6] cC [7..9] Sigma_C (xx,xy,yy) [10..12] conic_C (a,b,c)
+ * [13,14] cI [15..17] Sigma_I [18..20] conic_I                (21 doubles) */
+int orc_project(int64_t n, const double* means, const double* scales,
+                const double* quats, const double* view, double dil,
+                double q_max, double* out)
+{
+    OView v;
+    if (n < 0 || view_init(&v, view)) return -1;
+    OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
+    if (!G) return -2;
+    for (int64_t i = 0; i < n; ++i) {
+        double* o = out + 21 * i;
+        const OG* g = &G[i];
+        o[0] = g->valid; o[1] = g->x; o[2] = g->y; o[3] = g->z; o[4] = g->key;
+        o[5] = g->cC[0]; o[6] = g->cC[1];
+        for (int k = 0; k < 3; ++k) { o[7 + k] = g->SC[k]; o[10 + k] = g->QC[k]; }
+        o[13] = g->cI[0]; o[14] = g->cI[1];
+        for (int k = 0; k < 3; ++k) { o[15 + k] = g->SI[k]; o[18 + k] = g->QI[k]; }
+    }
+    free(G);
+    return 0;
+}
+
+/* Forward of one view.
+ * A[n]          scattering share of every Gaussian (I_i = amp_i * A_i)
+ * tau[Hc*Wc]    total optical depth of every ray (row-major [row][col])
+ * S[H*W]        SAR image (row-major [range row][azimuth column])
+ * shadowing=0 drops the transmittance (every Gaussian sees the full wave). */
+int orc_forward(int64_t n, const double* means, const double* scales,
+                const double* quats, const double* amp, const double* ext,
+                const double* view, double q_max, double dil, int shadowing,
+                double* A, double* tau, double* S)
+{
+    OView v;
+    if (n < 0 || view_init(&v, view) || !(q_max > 0)) return -1;
+    OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
+    if (!G) return -2;
+    int nt = nthreads();
+    double* At = (double*)calloc((size_t)nt * (size_t)(n > 0 ? n : 1), sizeof(double));
+    int err = At ? 0 : -2;
+    int64_t nrays = v.Wc * v.Hc;
+    if (!err) {
+#pragma omp parallel
+        {
+            Hit* list = (Hit*)malloc(sizeof(Hit) * (size_t)(n > 0 ? n : 1));
+            double* Amine = At + (size_t)thread_id() * (size_t)n;
+#pragma omp for schedule(dynamic, 8)
+            for (int64_t r = 0; r < nrays; ++r) {
+                int64_t m = ray_list(G, n, r % v.Wc, r / v.Wc, q_max, list);
+                double t = 0.0;
+                for (int64_t k = 0; k < m; ++k) {
+                    int64_t i = list[k].idx;
+                    double x = ext[i] * list[k].g;
+                    double alpha = 1.0 - exp(-x);
+                    Amine[i] += shadowing ? alpha * exp(-t) : alpha;
+                    t += x;
+                }
+                tau[r] = t;
+            }
+            free(list);
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            double a = 0.0;
+            for (int th = 0; th < nt; ++th) a += At[(size_t)th * (size_t)n + i];
+            A[i] = a;
+        }
+#pragma omp parallel for schedule(dynamic, 8)
+        for (int64_t p = 0; p < v.W * v.H; ++p) {
+            double px = (double)(p % v.W) + 0.5, py = (double)(p / v.W) + 0.5;
+            double acc = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (!G[i].valid) continue;
+                double q = quadform(G[i].QI, px - G[i].cI[0], py - G[i].cI[1]);
+                if (q < q_max) acc += foot(q, q_max) * amp[i] * A[i];
+            }
+            S[p] = acc;
+        }
+    }
+    free(At);
+    free(G);
+    return err;
+}
+
+/* Chain rule from a 2D conic/centre gradient on one plane to the 3D
+ * covariance and the mean.  dQ = (d/da, d/db, d/dc) for the conic entries
+ * with q = a dx^2 + 2 b dx dy + c dy^2; u, w are the radar axes spanning the
+ * plane; su, sw their spacings. Adds into dSig (3x3) and dmu. */
+static void plane_to_3d(const double* Q, const double* dQ, const double* dc,
+                        const double* u, const double* w, double su, double sw,
+                        double* dSig, double* dmu)
+{
+    /* symmetric-matrix gradient of the conic */
+    double Gq[4] = {dQ[0], 0.5 * dQ[1], 0.5 * dQ[1], dQ[2]};
+    double Qm[4] = {Q[0], Q[1], Q[1], Q[2]};
+    double T[4], G2[4];
+    /* dL/dSigma2 = -Q Gq Q */
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c)
+            T[2 * r + c] = Qm[2 * r] * Gq[c] + Qm[2 * r + 1] * Gq[2 + c];
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c)
+            G2[2 * r + c] = -(T[2 * r] * Qm[c] + T[2 * r + 1] * Qm[2 + c]);
+    /* Sigma2 = D B^T Sigma B D  ->  dSigma += B D G2 D B^T */
+    double sc[2] = {1.0 / su, 1.0 / sw};
+    const double* ax[2] = {u, w};
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double gab = G2[2 * a + b] * sc[a] * sc[b];
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c)
+                    dSig[3 * r + c] += ax[a][r] * gab * ax[b][c];
+        }
+    for (int k = 0; k < 3; ++k) dmu[k] += dc[0] * u[k] / su + dc[1] * w[k] / sw;
+}
+
+/* From dL/dSigma (3x3) to scales and the raw quaternion. */
+static void cov_to_params(const OG* g, const double* dSig, double* ds, double* dq)
+{
+    /* Sigma = M M^T, M = R diag(s): dM = (dSig + dSig^T) M */
+    double dM[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double a = 0;
+            for (int k = 0; k < 3; ++k)
+                a += (dSig[3 * r + k] + dSig[3 * k + r]) * g->M[3 * k + c];
+            dM[3 * r + c] = a;
+        }
+    double dR[9];
+    for (int c = 0; c < 3; ++c) {
+        double a = 0;
+        for (int r = 0; r < 3; ++r) {
+            a += g->R[3 * r + c] * dM[3 * r + c];
+            dR[3 * r + c] = dM[3 * r + c] * g->s[c];
+        }
+        ds[c] += a;
+    }
+    double w = g->qn[0], x = g->qn[1], y = g->qn[2], z = g->qn[3];
+    double G00 = dR[0], G01 = dR[1], G02 = dR[2], G10 = dR[3], G11 = dR[4],
+           G12 = dR[5], G20 = dR[6], G21 = dR[7], G22 = dR[8];
+    double gn[4];
+    gn[0] = 2 * (-z * G01 + y * G02 + z * G10 - x * G12 - y * G20 + x * G21);
+    gn[1] = 2 * (y * G01 + z * G02 + y * G10 - 2 * x * G11 - w * G12 + z * G20 +
+                 w * G21 - 2 * x * G22);
+    gn[2] = 2 * (-2 * y * G00 + x * G01 + w * G02 + x * G10 + z * G12 - w * G20 +
+                 z * G21 - 2 * y * G22);
+    gn[3] = 2 * (-2 * z * G00 - w * G01 + x * G02 + w * G10 - 2 * z * G11 +
+                 y * G12 + x * G20 + y * G21);
+    double proj = 0;
+    for (int k = 0; k < 4; ++k) proj += g->qn[k] * gn[k];
+    for (int k = 0; k < 4; ++k) dq[k] += (gn[k] - g->qn[k] * proj) / g->qnorm;
+}
+
+/* Backward of one view for a cotangent Gimg = dL/dS [H*W].
+ * Overwrites dmeans[3n], dscales[3n], dquats[4n], damp[n], dext[n].
+ * aux (may be NULL) receives 16 doubles per Gaussian:
+ *   [0] A  [1] dL/dI  [2..3] dL/dcI  [4..6] dL/dconic_I (a,b,c)
+ *   [7..8] dL/dcC  [9..11] dL/dconic_C  [12] dL/dkappa  [13] dL/dA (= c)
+ *   [14..15] unused */
+int orc_backward(int64_t n, const double* means, const double* scales,
+                 const double* quats, const double* amp, const double* ext,
+                 const double* view, double q_max, double dil, int shadowing,
+                 const double* Gimg, double* dmeans, double* dscales,
+                 double* dquats, double* damp, double* dext, double* aux)
+{
+    OView v;
+    if (n < 0 || view_init(&v, view) || !(q_max > 0)) return -1;
+    int64_t nrays = v.Wc * v.Hc, npix = v.W * v.H;
+    double* A = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double* tau = (double*)malloc(sizeof(double) * (size_t)nrays);
+    double* S = (double*)malloc(sizeof(double) * (size_t)npix);
+    if (!A || !tau || !S) { free(A); free(tau); free(S); return -2; }
+    int err = orc_forward(n, means, scales, quats, amp, ext, view, q_max, dil,
+                          shadowing, A, tau, S);
+    free(tau); free(S);
+    if (err) { free(A); return err; }
+    OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
+    /* per-Gaussian 2D gradients: dI, dcI(2), dQI(3), dcC(2), dQC(3), dk */
+    double* g2 = (double*)calloc((size_t)(n > 0 ? n : 1) * 12, sizeof(double));
+    int nt = nthreads();
+    double* gt = (double*)calloc((size_t)nt * (size_t)(n > 0 ? n : 1) * 6, sizeof(double));
+    if (!G || !g2 || !gt) { free(A); free(G); free(g2); free(gt); return -2; }
+
+    /* imaging plane: every Gaussian against every pixel */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!G[i].valid) continue;
+        double I = amp[i] * A[i];
+        double* o = g2 + 12 * i;
+        for (int64_t p = 0; p < npix; ++p) {
+            double dx = (double)(p % v.W) + 0.5 - G[i].cI[0];
+            double dy = (double)(p / v.W) + 0.5 - G[i].cI[1];
+            double q = quadform(G[i].QI, dx, dy);
+            if (!(q < q_max)) continue;
+            double Gp = Gimg[p];
+            o[0] += Gp * foot(q, q_max);
+            double dq = Gp * I * dfoot(q, q_max);
+            const double* Q = G[i].QI;
+            o[1] += dq * (-2.0 * (Q[0] * dx + Q[1] * dy));
+            o[2] += dq * (-2.0 * (Q[1] * dx + Q[2] * dy));
+            o[3] += dq * dx * dx;
+            o[4] += dq * 2.0 * dx * dy;
+            o[5] += dq * dy * dy;
+        }
+    }
+
+    /* computation plane: every ray, depth ordered, suffix sums */
+#pragma omp parallel
+    {
+        Hit* list = (Hit*)malloc(sizeof(Hit) * (size_t)(n > 0 ? n : 1));
+        double* T = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        double* al = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        double* mine = gt + (size_t)thread_id() * (size_t)n * 6;
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t r = 0; r < nrays; ++r) {
+            int64_t m = ray_list(G, n, r % v.Wc, r / v.Wc, q_max, list);
+            double t = 0.0;
+            for (int64_t k = 0; k < m; ++k) {
+                double x = ext[list[k].idx] * list[k].g;
+                T[k] = shadowing ? exp(-t) : 1.0;
+                al[k] = 1.0 - exp(-x);
+                t += x;
+            }
+            double suffix = 0.0;  /* sum_{j>k} c_j alpha_j T_j */
+            for (int64_t k = m - 1; k >= 0; --k) {
+                int64_t i = list[k].idx;
+                double c = amp[i] * g2[12 * i];
+                double dx_ = c * (1.0 - al[k]) * T[k] - (shadowing ? suffix : 0.0);
+                suffix += c * al[k] * T[k];
+                double g = list[k].g;
+                double* o = mine + 6 * i;
+                o[0] += dx_ * g;                       /* dL/dkappa */
+                double dq = dx_ * ext[i] * dfoot(list[k].q, q_max);
+                const double* Q = G[i].QC;
+                double ddx = list[k].dx, ddy = list[k].dy;
+                o[1] += dq * (-2.0 * (Q[0] * ddx + Q[1] * ddy));
+                o[2] += dq * (-2.0 * (Q[1] * ddx + Q[2] * ddy));
+                o[3] += dq * ddx * ddx;
+                o[4] += dq * 2.0 * ddx * ddy;
+                o[5] += dq * ddy * ddy;
+            }
+        }
+        free(list); free(T); free(al);
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int th = 0; th < nt; ++th)
+            for (int k = 0; k < 6; ++k)
+                g2[12 * i + 6 + k] += gt[((size_t)th * (size_t)n + (size_t)i) * 6 + k];
+    free(gt);
+
+    /* parameters */
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double* dm = dmeans + 3 * i;
+        double* dsc = dscales + 3 * i;
+        double* dqu = dquats + 4 * i;
+        for (int k = 0; k < 3; ++k) dm[k] = dsc[k] = 0.0;
+        for (int k = 0; k < 4; ++k) dqu[k] = 0.0;
+        damp[i] = dext[i] = 0.0;
+        const double* o = g2 + 12 * i;
+        if (aux) {
+            double* a = aux + 16 * i;
+            a[0] = A[i]; a[1] = o[0];
+            a[2] = o[1]; a[3] = o[2]; a[4] = o[3]; a[5] = o[4]; a[6] = o[5];
+            a[7] = o[7]; a[8] = o[8]; a[9] = o[9]; a[10] = o[10]; a[11] = o[11];
+            a[12] = o[6]; a[13] = amp[i] * o[0]; a[14] = a[15] = 0.0;
+        }
+        if (!G[i].valid) continue;
+        damp[i] = A[i] * o[0];
+        dext[i] = o[6];
+        double dSig[9] = {0};
+        plane_to_3d(G[i].QI, o + 3, o + 1, v.ex, v.ez, v.dA, v.dR, dSig, dm);
+        plane_to_3d(G[i].QC, o + 9, o + 7, v.ex, v.ey, v.dAc, v.dEc, dSig, dm);
+        cov_to_params(&G[i], dSig, dsc, dqu);
+    }
+    free(g2); free(G); free(A);
+    return 0;
+}
+
+/* Sampled forward for sizes where the full brute force is too slow.
+ * Computes S at `npix` pixels (ids row*W+col) and A for `ng` Gaussians.
+ * Exactly the definition restricted to what these outputs depend on:
+ * A_i only receives terms from rays where g_i > 0, and every ray used is
+ * still brute-forced against all n Gaussians. Candidate rays of a Gaussian
+ * are searched inside its exact ellipse bounding box widened by one cell. */
+int orc_sparse_forward(int64_t n, const double* means, const double* scales,
+                       const double* quats, const double* amp,
+                       const double* ext, const double* view, double q_max,
+                       double dil, int shadowing, int64_t npix,
+                       const int64_t* pix, double* S, int64_t ng,
+                       const int64_t* gids, double* Aout)
+{
+    OView v;
+    if (n < 0 || view_init(&v, view) || !(q_max > 0)) return -1;
+    OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
+    int64_t nrays = v.Wc * v.Hc;
+    char* needA = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    char* ray_on = (char*)calloc((size_t)nrays, 1);
+    double* A = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!G || !needA || !ray_on || !A) {
+        free(G); free(needA); free(ray_on); free(A); return -2;
+    }
+    for (int64_t k = 0; k < ng; ++k) needA[gids[k]] = 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!G[i].valid) continue;
+        for (int64_t k = 0; k < npix; ++k) {
+            double px = (double)(pix[k] % v.W) + 0.5, py = (double)(pix[k] / v.W) + 0.5;
+            if (quadform(G[i].QI, px - G[i].cI[0], py - G[i].cI[1]) < q_max) {
+                needA[i] = 1; break;
+            }
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (!needA[i] || !G[i].valid) continue;
+        const double* b = G[i].bxC;
+        int64_t c0 = (int64_t)floor(b[0] - 0.5) - 1, c1 = (int64_t)ceil(b[1] - 0.5) + 1;
+        int64_t r0 = (int64_t)floor(b[2] - 0.5) - 1, r1 = (int64_t)ceil(b[3] - 0.5) + 1;
+        if (c0 < 0) c0 = 0;
+        if (r0 < 0) r0 = 0;
+        if (c1 > v.Wc - 1) c1 = v.Wc - 1;
+        if (r1 > v.Hc - 1) r1 = v.Hc - 1;
+        for (int64_t r = r0; r <= r1; ++r)
+            for (int64_t c = c0; c <= c1; ++c) {
+                double q = quadform(G[i].QC, (double)c + 0.5 - G[i].cC[0],
+                                    (double)r + 0.5 - G[i].cC[1]);
+                if (q < q_max) ray_on[r * v.Wc + c] = 1;
+            }
+    }
+    int64_t nsel = 0;
+    for (int64_t r = 0; r < nrays; ++r) nsel += ray_on[r];
+    int64_t* sel = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nsel > 0 ? nsel : 1));
+    nsel = 0;
+    for (int64_t r = 0; r < nrays; ++r) if (ray_on[r]) sel[nsel++] = r;
+    int nt = nthreads();
+    double* At = (double*)calloc((size_t)nt * (size_t)(n > 0 ? n : 1), sizeof(double));
+#pragma omp parallel
+    {
+        Hit* list = (Hit*)malloc(sizeof(Hit) * (size_t)(n > 0 ? n : 1));
+        double* mine = At + (size_t)thread_id() * (size_t)n;
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t s = 0; s < nsel; ++s) {
+            int64_t r = sel[s];
+            int64_t m = ray_list(G, n, r % v.Wc, r / v.Wc, q_max, list);
+            double t = 0.0;
+            for (int64_t k = 0; k < m; ++k) {
+                int64_t i = list[k].idx;
+                double x = ext[i] * list[k].g;
+                double alpha = 1.0 - exp(-x);
+                if (needA[i]) mine[i] += shadowing ? alpha * exp(-t) : alpha;
+                t += x;
+            }
+        }
+        free(list);
+    }
+    for (int64_t i = 0; i < n; ++i)
+        for (int th = 0; th < nt; ++th) A[i] += At[(size_t)th * (size_t)n + i];
+    free(At);
+    for (int64_t k = 0; k < ng; ++k) Aout[k] = A[gids[k]];
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < npix; ++k) {
+        double px = (double)(pix[k] % v.W) + 0.5, py = (double)(pix[k] / v.W) + 0.5;
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!G[i].valid) continue;
+            double q = quadform(G[i].QI, px - G[i].cI[0], py - G[i].cI[1]);
+            if (q < q_max) acc += foot(q, q_max) * amp[i] * A[i];
+        }
+        S[k] = acc;
+    }
+    free(sel); free(G); free(needA); free(ray_on); free(A);
+    return 0;
+}
