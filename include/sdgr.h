@@ -1,0 +1,212 @@
+/*
+ * sdgr.h -- C ABI of the SAR Differentiable Gaussian Rasterizer (SDGR) on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: SAR-GS, "Gaussian Splatting based SAR Images Rendering and Target
+ * Reconstruction" (arXiv 2506.21633), Sec. II.
+ *   forward  (Sec. II-A): Gaussians + radar geometry -> SAR images
+ *     1. mapping and projection (radar rotation R_r, projections P_C, P_I):
+ *        every Gaussian onto the computation plane (perpendicular to the
+ *        line of sight) and the imaging plane (slant range x azimuth);
+ *     2. scattering intensity (Eq. for I_i): rays from the computation-plane
+ *        cells traverse the depth-sorted Gaussians front to back with
+ *        two-way extinction; each Gaussian's absorbed share summed over the
+ *        rays is A_i, and I_i = P_i * A_i;
+ *     3. image formation (Eq. for S_{n,m}): additive layover of footprint-
+ *        weighted intensities on the imaging plane.
+ *   backward (Sec. II-B): gradients of a scalar loss L, given dL/dS, with
+ *     respect to means, scales, rotations, amplitudes P and extinctions.
+ *
+ * Conventions (the readings of the paper that the implementation fixes):
+ *   - grazing angle theta, azimuth phi; image rows = slant range (index
+ *     grows away from the radar), columns = azimuth; the world origin maps
+ *     to the image centre; pixel and cell centres at +1/2;
+ *   - computation plane: same size as the image and spacings
+ *     (d_az, d_rg * tan(theta)) unless given;
+ *   - footprint f(q) = (exp(-q/2) - eps)/(1 - eps) for q < q_max, else 0,
+ *     q the quadratic form of the inverse projected covariance,
+ *     eps = exp(-q_max/2);
+ *   - alpha = 1 - exp(-kappa f), kappa = k_e+ + k_e- (only their sum is
+ *     identifiable: the paper states both derivatives are equal);
+ *   - depth order: fl32 of the FP64 range coordinate, ties by ascending
+ *     Gaussian index;
+ *   - scales are standard deviations in metres (> 0), quaternions (w,x,y,z)
+ *     of any nonzero norm, normalised inside. Gaussians with non-finite
+ *     parameters, a scale <= 0 or a zero quaternion contribute nothing and
+ *     receive zero gradient.
+ *
+ * Memory: every pointer in sdgr_scene, sdgr_scene_grad, the images and the
+ * workspaces is DEVICE memory on the current HIP device; sdgr_view,
+ * sdgr_options and sdgr_plan structs live in HOST memory. The caller owns
+ * every buffer; the library never allocates or frees device memory. Arrays
+ * are contiguous row-major float32.
+ *
+ * Streams: `stream` is a hipStream_t (NULL = default stream). All work is
+ * enqueued on it; sdgr_forward and sdgr_backward do not synchronise the
+ * host. sdgr_plan_query synchronises the stream (it reads pair counts).
+ *
+ * Errors: functions return 0 on success or a negative SDGR_E* code; the
+ * message of the last error on the calling thread is sdgr_last_error().
+ * Outputs are unspecified after an error.
+ */
+#ifndef SDGR_H
+#define SDGR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDGR_VERSION 1
+
+#define SDGR_OK 0
+#define SDGR_EINVAL (-1)       /* invalid argument (null, sizes, angles) */
+#define SDGR_EWORKSPACE (-2)   /* workspace smaller than the plan requires */
+#define SDGR_EHIP (-3)         /* HIP runtime error */
+#define SDGR_EOVERFLOW (-4)    /* pair count exceeds the plan's capacity */
+#define SDGR_EUNSUPPORTED (-5) /* option or size outside what is built */
+
+/* One scene of n Gaussians (device pointers, float32). */
+typedef struct sdgr_scene {
+    int64_t n;
+    const float* means;   /* [n,3] world position, metres */
+    const float* scales;  /* [n,3] per-axis standard deviation, metres */
+    const float* quats;   /* [n,4] rotation (w,x,y,z) */
+    const float* amp;     /* [n]   scattering amplitude P (phase function) */
+    const float* ext;     /* [n]   extinction kappa = k_e+ + k_e- */
+} sdgr_scene;
+
+/* Gradient outputs of one scene (device pointers, same shapes as the
+ * inputs). They are OVERWRITTEN with the sum over all views of the scene. */
+typedef struct sdgr_scene_grad {
+    float* d_means;
+    float* d_scales;
+    float* d_quats;
+    float* d_amp;
+    float* d_ext;
+} sdgr_scene_grad;
+
+/* One radar view (host struct). Zero in comp_* takes the default. */
+typedef struct sdgr_view {
+    double azimuth;      /* phi [rad] */
+    double grazing;      /* theta [rad], in (0, pi/2) */
+    double d_az, d_rg;   /* image pixel spacings [m], > 0 */
+    double comp_d_az;    /* computation-plane azimuth spacing, 0 = d_az */
+    double comp_d_el;    /* computation-plane elevation spacing,
+                            0 = d_rg * tan(grazing) */
+    int64_t img_offset;  /* float offset of this view's H x W image in the
+                            images / dL_dimages buffers */
+    int32_t img_w, img_h;    /* image columns (azimuth), rows (range) */
+    int32_t comp_w, comp_h;  /* computation-plane cells, 0 = image size */
+    int32_t scene;           /* index into the scenes array */
+    int32_t reserved;        /* must be 0 */
+} sdgr_view;
+
+typedef struct sdgr_options {
+    int32_t shadowing;   /* 1: two-way extinction along the line of sight
+                            (Eq. for I_i); 0: every Gaussian sees the full
+                            incident wave */
+    int32_t recompute;   /* 1: keep only per-ray state and A between forward
+                            and backward; the backward re-runs projection,
+                            binning and sorting (large scenes) */
+    float q_max;         /* footprint cutoff of q, > 0 (9 = 3 sigma) */
+    float tau_max;       /* rays stop after their optical depth reaches
+                            tau_max (terms below exp(-tau_max) dropped);
+                            <= 0 disables early termination */
+    float dilation;      /* added to the diagonal of every projected 2D
+                            covariance, in pixels^2 (0 = none) */
+    int32_t reserved;    /* must be 0 */
+} sdgr_options;
+
+/* Sizes of one (scenes, views, options) problem; filled by
+ * sdgr_plan_query and passed back unchanged to forward/backward. */
+typedef struct sdgr_plan {
+    size_t state_bytes;        /* kept from forward to backward */
+    size_t fwd_scratch_bytes;  /* temporary during forward */
+    size_t bwd_scratch_bytes;  /* temporary during backward */
+    size_t image_floats;       /* minimum length of images / dL_dimages */
+    int64_t records;           /* sum over views of the scene's n */
+    int64_t pairs_c;           /* (Gaussian, tile) pairs, computation plane */
+    int64_t pairs_i;           /* (Gaussian, tile) pairs, imaging plane */
+    int64_t tiles_c, tiles_i;  /* tiles over all views */
+    int64_t rays;              /* computation-plane cells over all views */
+    int32_t nviews, nscenes;
+    int32_t tile;              /* tile side in pixels (8) */
+    int32_t reserved;
+} sdgr_plan;
+
+/* Library version (SDGR_VERSION). */
+int sdgr_version(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* sdgr_last_error(void);
+
+/* Fill `opt` with the defaults: shadowing 1, recompute 0, q_max 9,
+ * tau_max 16, dilation 0. */
+void sdgr_default_options(sdgr_options* opt);
+
+/* Bytes of device scratch that sdgr_plan_query needs for nscenes scenes
+ * and nv views (a few KB; host-only computation). */
+size_t sdgr_query_bytes(int32_t nscenes, int32_t nv);
+
+/* Plan a problem: validates every argument, projects all Gaussians on the
+ * device to count their (Gaussian, tile) pairs on both planes (paper
+ * Sec. II-A, the projections P_C and P_I), synchronises `stream`, and fills
+ * `plan` with the exact workspace sizes.
+ * scenes[nscenes] (host array of structs with device pointers), views[nv]
+ * (host), query_scratch: device buffer of at least
+ * sdgr_query_bytes(nscenes, nv) bytes, 256-byte aligned, free again when the
+ * call returns. Returns SDGR_EINVAL on bad arguments, SDGR_EWORKSPACE if the
+ * scratch is too small, SDGR_EUNSUPPORTED if a count exceeds 2^31 - 1. */
+int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes,
+                    const sdgr_view* views, int32_t nv,
+                    const sdgr_options* opt, void* query_scratch,
+                    size_t query_bytes, void* stream, sdgr_plan* plan);
+
+/* Forward render (Sec. II-A). Writes every view's H x W image at
+ * images + view.img_offset (row-major [range row][azimuth column]); other
+ * floats of `images` are left untouched. `state` (plan->state_bytes) must
+ * be kept unchanged until the matching sdgr_backward; `scratch`
+ * (plan->fwd_scratch_bytes) may be reused after the call's work completes
+ * on `stream`. Both must be 256-byte aligned. Asynchronous. If the pair
+ * counts exceed the plan (inputs changed since the query), the rendering is
+ * incomplete and sdgr_status reports SDGR_EOVERFLOW. */
+int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes,
+                 const sdgr_view* views, int32_t nv, const sdgr_options* opt,
+                 const sdgr_plan* plan, void* state, void* scratch,
+                 float* images, void* stream);
+
+/* Backward (Sec. II-B) for the cotangent dL_dimages (same layout as the
+ * images). Same scenes, views, options, plan and `state` as the forward.
+ * `scratch` holds plan->bwd_scratch_bytes. Overwrites grads[s] for every
+ * scene s (entries of a scene no view uses are set to zero). Asynchronous. */
+int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes,
+                  const sdgr_view* views, int32_t nv,
+                  const sdgr_options* opt, const sdgr_plan* plan, void* state,
+                  void* scratch, const float* dL_dimages,
+                  const sdgr_scene_grad* grads, void* stream);
+
+/* Synchronises `stream` and returns SDGR_EOVERFLOW if a forward or backward
+ * that used `state` found more pairs than planned, else SDGR_OK. */
+int sdgr_status(const sdgr_plan* plan, const void* state, void* stream);
+
+/* Copies the per-view scattering shares A (float32, plan->records entries,
+ * view-major: view v's entries start at the sum of the n of the scenes of
+ * views 0..v-1) out of `state` into the device buffer `out`. Asynchronous.
+ * I_i = P_i * A_i (Eq. for I_i). */
+int sdgr_read_intensity(const sdgr_plan* plan, const void* state, float* out,
+                        void* stream);
+
+/* Copies the per-ray total optical depth (float32, plan->rays entries,
+ * view-major, each view row-major [row][col] over its computation plane)
+ * out of `state` into the device buffer `out`. Asynchronous. */
+int sdgr_read_optical_depth(const sdgr_plan* plan, const void* state,
+                            float* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDGR_H */

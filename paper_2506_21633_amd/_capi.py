@@ -1,0 +1,110 @@
+"""ctypes mirror of include/sdgr.h (argument marshalling only).
+
+Loading fails loudly when libsdgr.so has not been built: there is no
+fallback implementation anywhere in the package.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsdgr.so")
+
+SDGR_OK = 0
+SDGR_EINVAL = -1
+SDGR_EWORKSPACE = -2
+SDGR_EHIP = -3
+SDGR_EOVERFLOW = -4
+SDGR_EUNSUPPORTED = -5
+
+EXPORTED = ("sdgr_version", "sdgr_last_error", "sdgr_default_options",
+            "sdgr_query_bytes", "sdgr_plan_query", "sdgr_forward",
+            "sdgr_backward", "sdgr_status", "sdgr_read_intensity",
+            "sdgr_read_optical_depth")
+
+
+class Scene(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64),
+                ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p),
+                ("quats", ctypes.c_void_p), ("amp", ctypes.c_void_p),
+                ("ext", ctypes.c_void_p)]
+
+
+class SceneGrad(ctypes.Structure):
+    _fields_ = [("d_means", ctypes.c_void_p), ("d_scales", ctypes.c_void_p),
+                ("d_quats", ctypes.c_void_p), ("d_amp", ctypes.c_void_p),
+                ("d_ext", ctypes.c_void_p)]
+
+
+class View(ctypes.Structure):
+    _fields_ = [("azimuth", ctypes.c_double), ("grazing", ctypes.c_double),
+                ("d_az", ctypes.c_double), ("d_rg", ctypes.c_double),
+                ("comp_d_az", ctypes.c_double), ("comp_d_el", ctypes.c_double),
+                ("img_offset", ctypes.c_int64),
+                ("img_w", ctypes.c_int32), ("img_h", ctypes.c_int32),
+                ("comp_w", ctypes.c_int32), ("comp_h", ctypes.c_int32),
+                ("scene", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("shadowing", ctypes.c_int32), ("recompute", ctypes.c_int32),
+                ("q_max", ctypes.c_float), ("tau_max", ctypes.c_float),
+                ("dilation", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("state_bytes", ctypes.c_size_t),
+                ("fwd_scratch_bytes", ctypes.c_size_t),
+                ("bwd_scratch_bytes", ctypes.c_size_t),
+                ("image_floats", ctypes.c_size_t),
+                ("records", ctypes.c_int64), ("pairs_c", ctypes.c_int64),
+                ("pairs_i", ctypes.c_int64), ("tiles_c", ctypes.c_int64),
+                ("tiles_i", ctypes.c_int64), ("rays", ctypes.c_int64),
+                ("nviews", ctypes.c_int32), ("nscenes", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class SDGRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sdgr error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libsdgr.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} not found: build the HIP library first "
+            "(python -m paper_2506_21633_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.sdgr_version.restype = ctypes.c_int
+    L.sdgr_last_error.restype = ctypes.c_char_p
+    L.sdgr_default_options.argtypes = [P(Options)]
+    L.sdgr_query_bytes.restype = ctypes.c_size_t
+    L.sdgr_query_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.sdgr_plan_query.argtypes = [P(Scene), ctypes.c_int32, P(View), ctypes.c_int32,
+                                  P(Options), vp, ctypes.c_size_t, vp, P(Plan)]
+    L.sdgr_forward.argtypes = [P(Scene), ctypes.c_int32, P(View), ctypes.c_int32,
+                               P(Options), P(Plan), vp, vp, vp, vp]
+    L.sdgr_backward.argtypes = [P(Scene), ctypes.c_int32, P(View), ctypes.c_int32,
+                                P(Options), P(Plan), vp, vp, vp, P(SceneGrad), vp]
+    L.sdgr_status.argtypes = [P(Plan), vp, vp]
+    L.sdgr_read_intensity.argtypes = [P(Plan), vp, vp, vp]
+    L.sdgr_read_optical_depth.argtypes = [P(Plan), vp, vp, vp]
+    for name in ("sdgr_plan_query", "sdgr_forward", "sdgr_backward", "sdgr_status",
+                 "sdgr_read_intensity", "sdgr_read_optical_depth"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(code):
+    if code != SDGR_OK:
+        raise SDGRError(code, lib().sdgr_last_error().decode(errors="replace"))

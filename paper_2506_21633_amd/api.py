@@ -1,0 +1,259 @@
+"""Python binding of the SDGR library: argument marshalling around the C ABI.
+
+Every step of the forward and backward runs in the HIP kernels behind
+``libsdgr.so``; PyTorch supplies device memory (all workspaces are torch
+tensors) and the stream (the current stream of the tensors' device).
+
+    scene = GaussianTensors.from_numpy(scenes.vehicle(), device="cuda")
+    images = render(scene.means, scene.scales, scene.quats, scene.amp,
+                    scene.ext, views)            # [V, H, W], differentiable
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _capi as C
+
+__all__ = ["RenderOptions", "GaussianTensors", "Renderer", "ForwardResult",
+           "render", "SDGRFunction"]
+
+
+@dataclass(frozen=True)
+class RenderOptions:
+    shadowing: bool = True
+    recompute: bool = False
+    q_max: float = 9.0
+    tau_max: float = 16.0
+    dilation: float = 0.0
+
+    def to_c(self) -> C.Options:
+        o = C.Options()
+        o.shadowing = int(bool(self.shadowing))
+        o.recompute = int(bool(self.recompute))
+        o.q_max = float(self.q_max)
+        o.tau_max = float(self.tau_max)
+        o.dilation = float(self.dilation)
+        o.reserved = 0
+        return o
+
+
+@dataclass
+class GaussianTensors:
+    means: torch.Tensor
+    scales: torch.Tensor
+    quats: torch.Tensor
+    amp: torch.Tensor
+    ext: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    @staticmethod
+    def from_numpy(scene, device="cuda") -> "GaussianTensors":
+        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32),
+                                      device=device)
+        return GaussianTensors(f(scene.means), f(scene.scales), f(scene.quats),
+                               f(scene.amp), f(scene.ext))
+
+    def tensors(self):
+        return (self.means, self.scales, self.quats, self.amp, self.ext)
+
+
+def _dev_f32(t: torch.Tensor, shape, name) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32:
+        raise ValueError(f"{name} must be float32")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.contiguous()
+
+
+def _scene_struct(g: GaussianTensors) -> C.Scene:
+    n = g.n
+    m = _dev_f32(g.means, (n, 3), "means")
+    s = _dev_f32(g.scales, (n, 3), "scales")
+    q = _dev_f32(g.quats, (n, 4), "quats")
+    a = _dev_f32(g.amp, (n,), "amp")
+    e = _dev_f32(g.ext, (n,), "ext")
+    st = C.Scene(n, m.data_ptr(), s.data_ptr(), q.data_ptr(), a.data_ptr(), e.data_ptr())
+    st._keep = (m, s, q, a, e)
+    return st
+
+
+def _view_structs(views, scene_ids=None):
+    arr = (C.View * len(views))()
+    off = 0
+    shapes = []
+    for k, v in enumerate(views):
+        c = arr[k]
+        c.azimuth = float(v.azimuth)
+        c.grazing = float(v.grazing)
+        c.d_az = float(v.d_az)
+        c.d_rg = float(v.d_rg)
+        c.comp_d_az = float(getattr(v, "comp_d_az", 0.0))
+        c.comp_d_el = float(getattr(v, "comp_d_el", 0.0))
+        c.img_offset = off
+        c.img_w = int(v.img_w)
+        c.img_h = int(v.img_h)
+        c.comp_w = int(getattr(v, "comp_w", 0))
+        c.comp_h = int(getattr(v, "comp_h", 0))
+        c.scene = int(scene_ids[k] if scene_ids is not None else getattr(v, "scene", 0))
+        c.reserved = 0
+        shapes.append((off, int(v.img_h), int(v.img_w)))
+        off += int(v.img_h) * int(v.img_w)
+    return arr, shapes, off
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _buf(nbytes: int, device) -> torch.Tensor:
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+    if t.data_ptr() % 256:
+        raise RuntimeError("workspace allocation not 256-byte aligned")
+    return t
+
+
+@dataclass
+class ForwardResult:
+    images: torch.Tensor          # flat float32 [image_floats]
+    shapes: list                  # per view (offset, H, W)
+    plan: C.Plan
+    state: torch.Tensor
+
+    def image(self, v: int) -> torch.Tensor:
+        off, h, w = self.shapes[v]
+        return self.images[off:off + h * w].view(h, w)
+
+    def stacked(self) -> torch.Tensor:
+        hs = {(h, w) for _, h, w in self.shapes}
+        if len(hs) != 1:
+            raise ValueError("views have different image sizes")
+        h, w = hs.pop()
+        return self.images[:len(self.shapes) * h * w].view(len(self.shapes), h, w)
+
+
+class Renderer:
+    """One (scenes, views, options) problem bound to the C ABI.
+
+    Views refer to scenes through their ``scene`` attribute (or
+    ``scene_ids``); several scenes and image sizes may share one launch."""
+
+    def __init__(self, scenes: Sequence[GaussianTensors], views, options=None,
+                 scene_ids=None):
+        if isinstance(scenes, GaussianTensors):
+            scenes = [scenes]
+        self.scenes = list(scenes)
+        self.device = self.scenes[0].means.device
+        self.options = options or RenderOptions()
+        self.lib = C.lib()
+        self.views_c, self.shapes, self.image_floats = _view_structs(views, scene_ids)
+        self.nv = len(views)
+        self.opts_c = self.options.to_c()
+        self._rebind()
+
+    def _rebind(self):
+        structs = [_scene_struct(g) for g in self.scenes]
+        self._keep = [s._keep for s in structs]   # contiguous tensors behind the pointers
+        self.scenes_c = (C.Scene * len(structs))(*structs)
+
+    def plan(self) -> C.Plan:
+        p = C.Plan()
+        qb = self.lib.sdgr_query_bytes(len(self.scenes), self.nv)
+        q = _buf(qb, self.device)
+        C.check(self.lib.sdgr_plan_query(self.scenes_c, len(self.scenes), self.views_c,
+                                         self.nv, ctypes.byref(self.opts_c), q.data_ptr(),
+                                         qb, _stream_ptr(self.device), ctypes.byref(p)))
+        return p
+
+    def forward(self, plan: Optional[C.Plan] = None) -> ForwardResult:
+        plan = plan or self.plan()
+        state = _buf(plan.state_bytes, self.device)
+        scratch = _buf(plan.fwd_scratch_bytes, self.device)
+        images = torch.zeros(max(int(plan.image_floats), 1), dtype=torch.float32,
+                             device=self.device)
+        C.check(self.lib.sdgr_forward(self.scenes_c, len(self.scenes), self.views_c, self.nv,
+                                      ctypes.byref(self.opts_c), ctypes.byref(plan),
+                                      state.data_ptr(), scratch.data_ptr(),
+                                      images.data_ptr(), _stream_ptr(self.device)))
+        return ForwardResult(images, self.shapes, plan, state)
+
+    def backward(self, fwd: ForwardResult, grad_images: torch.Tensor):
+        """Gradients for every scene: list of dicts of tensors."""
+        g = grad_images.contiguous().view(-1)
+        if g.dtype != torch.float32 or g.numel() < fwd.plan.image_floats:
+            raise ValueError("grad_images must be float32 and cover every image")
+        scratch = _buf(fwd.plan.bwd_scratch_bytes, self.device)
+        outs = []
+        grads_c = (C.SceneGrad * len(self.scenes))()
+        for k, sc in enumerate(self.scenes):
+            d = {name: torch.empty_like(t) for name, t in
+                 zip(("means", "scales", "quats", "amp", "ext"), sc.tensors())}
+            grads_c[k] = C.SceneGrad(d["means"].data_ptr(), d["scales"].data_ptr(),
+                                     d["quats"].data_ptr(), d["amp"].data_ptr(),
+                                     d["ext"].data_ptr())
+            outs.append(d)
+        C.check(self.lib.sdgr_backward(self.scenes_c, len(self.scenes), self.views_c, self.nv,
+                                       ctypes.byref(self.opts_c), ctypes.byref(fwd.plan),
+                                       fwd.state.data_ptr(), scratch.data_ptr(), g.data_ptr(),
+                                       grads_c, _stream_ptr(self.device)))
+        return outs
+
+    def status(self, fwd: ForwardResult):
+        C.check(self.lib.sdgr_status(ctypes.byref(fwd.plan), fwd.state.data_ptr(),
+                                     _stream_ptr(self.device)))
+
+    def intensity_shares(self, fwd: ForwardResult) -> torch.Tensor:
+        """A per record, view-major (flat)."""
+        out = torch.empty(max(int(fwd.plan.records), 1), dtype=torch.float32,
+                          device=self.device)
+        C.check(self.lib.sdgr_read_intensity(ctypes.byref(fwd.plan), fwd.state.data_ptr(),
+                                             out.data_ptr(), _stream_ptr(self.device)))
+        return out[:fwd.plan.records]
+
+    def optical_depth(self, fwd: ForwardResult) -> torch.Tensor:
+        out = torch.empty(max(int(fwd.plan.rays), 1), dtype=torch.float32, device=self.device)
+        C.check(self.lib.sdgr_read_optical_depth(ctypes.byref(fwd.plan), fwd.state.data_ptr(),
+                                                 out.data_ptr(), _stream_ptr(self.device)))
+        return out[:fwd.plan.rays]
+
+
+class SDGRFunction(torch.autograd.Function):
+    """Differentiable SAR rendering of one scene over a batch of views of
+    equal image size; the backward is the library's hand-written one."""
+
+    @staticmethod
+    def forward(ctx, views, options, means, scales, quats, amp, ext):
+        g = GaussianTensors(means.detach(), scales.detach(), quats.detach(), amp.detach(),
+                            ext.detach())
+        r = Renderer([g], views, options)
+        res = r.forward()
+        ctx.renderer = r
+        ctx.result = res
+        return res.stacked()
+
+    @staticmethod
+    def backward(ctx, grad_images):
+        r, res = ctx.renderer, ctx.result
+        full = torch.zeros_like(res.images)
+        n = grad_images.numel()
+        full[:n] = grad_images.reshape(-1)
+        d = r.backward(res, full)[0]
+        ctx.renderer = ctx.result = None
+        return None, None, d["means"], d["scales"], d["quats"], d["amp"], d["ext"]
+
+
+def render(means, scales, quats, amp, ext, views, options: Optional[RenderOptions] = None):
+    """SAR images [V, H, W] of one scene; differentiable w.r.t. all five
+    parameter tensors."""
+    return SDGRFunction.apply(list(views), options or RenderOptions(), means, scales, quats,
+                              amp, ext)

@@ -1,0 +1,531 @@
+// C ABI of the SDGR library: argument validation, workspace layout and the
+// launch sequence of the forward (paper Sec. II-A) and backward (Sec. II-B)
+// passes. Declarations and contracts are in include/sdgr.h.
+#include "common.hpp"
+#include "sdgr.h"
+
+#include <math.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+namespace sdgr {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    return fail(SDGR_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define SDGR_HIP(expr)                                          \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr);       \
+    } while (0)
+
+int bits_for(int64_t max_value)
+{
+    int b = 0;
+    while (b < 63 && (int64_t(1) << b) <= max_value) ++b;
+    return b;
+}
+
+// Everything the host knows about a call before touching the device.
+struct Problem {
+    std::vector<DevView> views;
+    std::vector<DevScene> scenes;
+    RasterParams rp;
+    int nv = 0, ns = 0;
+    int64_t records = 0, rays = 0, tiles_c = 0, tiles_i = 0, items = 0;
+    int64_t image_floats = 0;
+    bool recompute = false;
+};
+
+// Rows of the world-to-radar rotation R_r(phi, theta) (Sec. II-A).
+void radar_axes(double phi, double theta, double* ex, double* ey, double* ez)
+{
+#pragma clang fp contract(off)
+    double sp = sin(phi), cp = cos(phi), st = sin(theta), ct = cos(theta);
+    ex[0] = -sp;      ex[1] = -cp;     ex[2] = 0.0;
+    ey[0] = -st * cp; ey[1] = st * sp; ey[2] = ct;
+    ez[0] = -ct * cp; ez[1] = ct * sp; ez[2] = -st;
+}
+
+int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* views,
+                  int32_t nv, const sdgr_options* opt, Problem& P)
+{
+    if (!opt) return fail(SDGR_EINVAL, "options is null");
+    if (nv <= 0 || !views) return fail(SDGR_EINVAL, "need at least one view");
+    if (nscenes <= 0 || !scenes) return fail(SDGR_EINVAL, "need at least one scene");
+    if (opt->reserved != 0) return fail(SDGR_EINVAL, "options.reserved must be 0");
+    if (!(opt->q_max > 0.0f) || !std::isfinite(opt->q_max))
+        return fail(SDGR_EINVAL, "q_max must be positive and finite");
+    if (!(opt->dilation >= 0.0f) || !std::isfinite(opt->dilation))
+        return fail(SDGR_EINVAL, "dilation must be >= 0");
+    if (opt->shadowing != 0 && opt->shadowing != 1)
+        return fail(SDGR_EINVAL, "shadowing must be 0 or 1");
+    if (opt->recompute != 0 && opt->recompute != 1)
+        return fail(SDGR_EINVAL, "recompute must be 0 or 1");
+    P.nv = nv;
+    P.ns = nscenes;
+    P.recompute = opt->recompute != 0;
+    double eps = exp(-0.5 * (double)opt->q_max);
+    P.rp.q_max = opt->q_max;
+    P.rp.eps = (float)eps;
+    P.rp.inv1meps = (float)(1.0 / (1.0 - eps));
+    P.rp.tau_max = (opt->tau_max > 0.0f) ? opt->tau_max : INFINITY;
+    P.rp.shadowing = opt->shadowing;
+    P.rp.dilation = opt->dilation;
+
+    P.scenes.resize(nscenes);
+    int64_t items = 0;
+    for (int s = 0; s < nscenes; ++s) {
+        const sdgr_scene& S = scenes[s];
+        if (S.n < 0) return fail(SDGR_EINVAL, "scene " + std::to_string(s) + ": n < 0");
+        if (S.n > 0 && (!S.means || !S.scales || !S.quats || !S.amp || !S.ext))
+            return fail(SDGR_EINVAL, "scene " + std::to_string(s) + ": null parameter array");
+        DevScene d{};
+        d.means = S.means; d.scales = S.scales; d.quats = S.quats; d.amp = S.amp; d.ext = S.ext;
+        d.n = S.n;
+        d.item_off = items;
+        items += S.n;
+        P.scenes[s] = d;
+    }
+    P.items = items;
+
+    P.views.resize(nv);
+    int64_t rec = 0, rays = 0, tc = 0, ti = 0, img = 0;
+    for (int v = 0; v < nv; ++v) {
+        const sdgr_view& in = views[v];
+        std::string tag = "view " + std::to_string(v) + ": ";
+        if (in.reserved != 0) return fail(SDGR_EINVAL, tag + "reserved must be 0");
+        if (!(in.grazing > 0.0 && in.grazing < M_PI / 2))
+            return fail(SDGR_EINVAL, tag + "grazing angle outside (0, pi/2)");
+        if (!std::isfinite(in.azimuth)) return fail(SDGR_EINVAL, tag + "azimuth not finite");
+        if (in.img_w <= 0 || in.img_h <= 0 || in.comp_w < 0 || in.comp_h < 0)
+            return fail(SDGR_EINVAL, tag + "non-positive image size");
+        if (!(in.d_az > 0.0) || !(in.d_rg > 0.0) || !(in.comp_d_az >= 0.0) ||
+            !(in.comp_d_el >= 0.0) || !std::isfinite(in.d_az) || !std::isfinite(in.d_rg))
+            return fail(SDGR_EINVAL, tag + "non-positive spacing");
+        if (in.scene < 0 || in.scene >= nscenes)
+            return fail(SDGR_EINVAL, tag + "scene index out of range");
+        if (in.img_offset < 0) return fail(SDGR_EINVAL, tag + "negative image offset");
+        DevView d{};
+        radar_axes(in.azimuth, in.grazing, d.ex, d.ey, d.ez);
+        d.W = in.img_w; d.H = in.img_h;
+        d.Wc = in.comp_w > 0 ? in.comp_w : in.img_w;
+        d.Hc = in.comp_h > 0 ? in.comp_h : in.img_h;
+        d.dA = in.d_az; d.dR = in.d_rg;
+        d.dAc = in.comp_d_az > 0.0 ? in.comp_d_az : in.d_az;
+        d.dEc = in.comp_d_el > 0.0 ? in.comp_d_el : in.d_rg * tan(in.grazing);
+        d.hW = 0.5 * (double)d.W; d.hH = 0.5 * (double)d.H;
+        d.hWc = 0.5 * (double)d.Wc; d.hHc = 0.5 * (double)d.Hc;
+        d.txc = (d.Wc + TILE - 1) / TILE; d.tyc = (d.Hc + TILE - 1) / TILE;
+        d.txi = (d.W + TILE - 1) / TILE;  d.tyi = (d.H + TILE - 1) / TILE;
+        if (d.txc >= 65535 || d.tyc >= 65535 || d.txi >= 65535 || d.tyi >= 65535)
+            return fail(SDGR_EUNSUPPORTED, tag + "image too large");
+        d.scene = in.scene;
+        d.n = (int32_t)P.scenes[in.scene].n;
+        d.rec_off = rec;
+        d.ray_off = rays;
+        d.img_off = in.img_offset;
+        d.tile_c = (int32_t)tc;
+        rec += P.scenes[in.scene].n;
+        rays += (int64_t)d.Wc * d.Hc;
+        tc += (int64_t)d.txc * d.tyc;
+        ti += (int64_t)d.txi * d.tyi;
+        img = std::max<int64_t>(img, in.img_offset + (int64_t)d.W * d.H);
+        P.views[v] = d;
+    }
+    // imaging-plane bucket ids follow all computation-plane ones
+    int64_t acc = tc;
+    for (int v = 0; v < nv; ++v) {
+        P.views[v].tile_i = (int32_t)acc;
+        acc += (int64_t)P.views[v].txi * P.views[v].tyi;
+    }
+    if (rec > INT32_MAX || rays > INT32_MAX || tc + ti > INT32_MAX)
+        return fail(SDGR_EUNSUPPORTED, "more than 2^31 - 1 records, rays or tiles");
+    P.records = rec;
+    P.rays = rays;
+    P.tiles_c = tc;
+    P.tiles_i = ti;
+    P.image_floats = img;
+    return SDGR_OK;
+}
+
+// Device buffers of one call, carved out of the caller's workspaces.
+struct Bufs {
+    uint32_t* status = nullptr;
+    DevView* views = nullptr;
+    DevScene* scenes = nullptr;
+    float* A = nullptr;
+    float* tau = nullptr;
+    uint32_t* nlast = nullptr;
+    // geometry: records, sorted lists and tile ranges
+    float4* cq = nullptr;
+    float2* cw = nullptr;
+    float4* iq = nullptr;
+    float2* iw = nullptr;
+    uint32_t* pval[2] = {nullptr, nullptr};
+    uint2* ranges = nullptr;
+    // transient: projection counts and sort buffers
+    uint2* rect_c = nullptr;
+    uint2* rect_i = nullptr;
+    uint32_t* cnt_c = nullptr;
+    uint32_t* cnt_i = nullptr;
+    uint32_t* cnt_c_sorted = nullptr;
+    uint32_t* off_c = nullptr;
+    uint32_t* off_i = nullptr;
+    uint64_t* dkey[2] = {nullptr, nullptr};
+    uint32_t* dval[2] = {nullptr, nullptr};
+    uint32_t* pkey[2] = {nullptr, nullptr};
+    uint32_t* hist = nullptr;
+    uint32_t* scan_tmp = nullptr;
+    // backward accumulators, 8 floats per record
+    float* grad_c = nullptr;
+    float* grad_i = nullptr;
+};
+
+struct Arena {
+    char* base;
+    size_t off = 0;
+    template <class T>
+    T* take(int64_t count)
+    {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+        return p;
+    }
+};
+
+enum Phase { FWD, BWD };
+constexpr int STATUS_WORDS = 64;
+constexpr int ST_RECORDS = 12;   // device copy of the record count (sort length)
+
+void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* state,
+            char* scratch, Bufs& b, size_t* state_bytes, size_t* scratch_bytes)
+{
+    Arena st{state}, sc{scratch};
+    const int64_t R = P.records, K = cap_c + cap_i;
+    b.status = st.take<uint32_t>(STATUS_WORDS);
+    b.views = st.take<DevView>(P.nv);
+    b.scenes = st.take<DevScene>(P.ns);
+    b.A = st.take<float>(R);
+    b.tau = st.take<float>(P.rays);
+    b.nlast = st.take<uint32_t>(P.rays);
+    auto geo = [&](Arena& a) {
+        b.cq = a.take<float4>(R);
+        b.cw = a.take<float2>(R);
+        b.iq = a.take<float4>(R);
+        b.iw = a.take<float2>(R);
+        b.pval[0] = a.take<uint32_t>(K);
+        b.pval[1] = a.take<uint32_t>(K);
+        b.ranges = a.take<uint2>(P.tiles_c + P.tiles_i);
+    };
+    auto transient = [&](Arena& a) {
+        b.rect_c = a.take<uint2>(R);
+        b.rect_i = a.take<uint2>(R);
+        b.cnt_c = a.take<uint32_t>(R);
+        b.cnt_i = a.take<uint32_t>(R);
+        b.cnt_c_sorted = a.take<uint32_t>(R);
+        b.off_c = a.take<uint32_t>(R);
+        b.off_i = a.take<uint32_t>(R);
+        b.dkey[0] = a.take<uint64_t>(R);
+        b.dkey[1] = a.take<uint64_t>(R);
+        b.dval[0] = a.take<uint32_t>(R);
+        b.dval[1] = a.take<uint32_t>(R);
+        b.pkey[0] = a.take<uint32_t>(K);
+        b.pkey[1] = a.take<uint32_t>(K);
+        int64_t hw = (int64_t)std::max(radix_hist_words(R), radix_hist_words(K));
+        b.hist = a.take<uint32_t>(hw);
+        int64_t sw = (int64_t)std::max(scan_tmp_words(R), scan_tmp_words(hw));
+        b.scan_tmp = a.take<uint32_t>(sw);
+    };
+    if (!P.recompute) geo(st);
+    if (ph == FWD) {
+        if (P.recompute) geo(sc);
+        transient(sc);
+    } else {
+        if (P.recompute) {
+            geo(sc);
+            transient(sc);
+        }
+        b.grad_c = sc.take<float>(8 * R);
+        b.grad_i = sc.take<float>(8 * R);
+    }
+    if (state_bytes) *state_bytes = st.off;
+    if (scratch_bytes) *scratch_bytes = sc.off;
+}
+
+int upload_tables(const Problem& P, const Bufs& b, hipStream_t s)
+{
+    SDGR_HIP(launch_upload(b.views, P.views.data(), sizeof(DevView) * P.nv, s));
+    SDGR_HIP(launch_upload(b.scenes, P.scenes.data(), sizeof(DevScene) * P.ns, s));
+    return SDGR_OK;
+}
+
+int check_plan(const Problem& P, const sdgr_plan* plan)
+{
+    if (!plan) return fail(SDGR_EINVAL, "plan is null");
+    if (plan->records != P.records || plan->rays != P.rays || plan->tiles_c != P.tiles_c ||
+        plan->tiles_i != P.tiles_i || plan->nviews != P.nv || plan->nscenes != P.ns ||
+        plan->tile != TILE)
+        return fail(SDGR_EINVAL, "plan does not match the scenes, views and options");
+    return SDGR_OK;
+}
+
+int passes_bits_depth(const Problem& P) { return 32 + bits_for(P.nv - 1); }
+int passes_bits_pairs(const Problem& P) { return bits_for(P.tiles_c + P.tiles_i - 1); }
+int final_pair_buffer(const Problem& P)
+{
+    int bits = passes_bits_pairs(P);
+    int passes = (bits + 7) / 8;
+    return passes & 1;
+}
+
+// Projection, binning, sorting and tile ranges (shared by the forward and
+// the recomputing backward).
+int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStream_t s)
+{
+    const int64_t R = P.records;
+    SDGR_HIP(launch_fill_u32(b.status, 0u, STATUS_WORDS, s));
+    SDGR_HIP(launch_fill_u32(b.status + ST_RECORDS, (uint32_t)R, 1, s));
+    SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, R, P.rp, true, b.cq, b.cw, b.iq, b.iw,
+                               b.rect_c, b.rect_i, b.cnt_c, b.cnt_i, b.dkey[0], b.dval[0],
+                               reinterpret_cast<unsigned long long*>(b.status + ST_COUNT), s));
+    // depth order of the records of every view
+    uint64_t* dk[2] = {b.dkey[0], b.dkey[1]};
+    uint32_t* dv[2] = {b.dval[0], b.dval[1]};
+    int which = 0;
+    SDGR_HIP(launch_radix_sort_u64(dk, dv, R, b.status + ST_RECORDS, passes_bits_depth(P),
+                                   b.hist, b.scan_tmp, &which, s));
+    SDGR_HIP(launch_gather_counts(dv[which], b.cnt_c, R, b.cnt_c_sorted, s));
+    SDGR_HIP(launch_exclusive_scan(b.cnt_c_sorted, b.off_c, R, b.scan_tmp, s));
+    SDGR_HIP(launch_exclusive_scan(b.cnt_i, b.off_i, R, b.scan_tmp, s));
+    SDGR_HIP(launch_pair_totals(nullptr, nullptr, nullptr, nullptr, R, plan->pairs_c,
+                                plan->pairs_i, b.status, s));
+    uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
+    uint32_t* pv[2] = {b.pval[0], b.pval[1]};
+    SDGR_HIP(launch_emit_pairs(b.views, P.nv, R, dk[which], dv[which], b.rect_c, b.rect_i,
+                               b.off_c, b.off_i, plan->pairs_c, plan->pairs_i, b.status,
+                               pk[0], pv[0], s));
+    int pw = 0;
+    const int64_t K = plan->pairs_c + plan->pairs_i;
+    SDGR_HIP(launch_radix_sort_u32(pk, pv, K, b.status + ST_PAIRS_ALL, passes_bits_pairs(P),
+                                   b.hist, b.scan_tmp, &pw, s));
+    if (K > 0 && pw != final_pair_buffer(P))
+        return fail(SDGR_EHIP, "internal: pair buffer parity");
+    SDGR_HIP(launch_tile_ranges(pk[pw], K, b.status + ST_PAIRS_ALL, P.tiles_c + P.tiles_i,
+                                b.ranges, s));
+    return SDGR_OK;
+}
+
+}  // namespace
+}  // namespace sdgr
+
+using namespace sdgr;
+
+extern "C" {
+
+int sdgr_version(void) { return SDGR_VERSION; }
+
+const char* sdgr_last_error(void) { return g_last_error.c_str(); }
+
+void sdgr_default_options(sdgr_options* opt)
+{
+    if (!opt) return;
+    opt->shadowing = 1;
+    opt->recompute = 0;
+    opt->q_max = 9.0f;
+    opt->tau_max = 16.0f;
+    opt->dilation = 0.0f;
+    opt->reserved = 0;
+}
+
+size_t sdgr_query_bytes(int32_t nscenes, int32_t nv)
+{
+    if (nscenes < 0 || nv < 0) return 0;
+    return 4096 + ((sizeof(DevView) * (size_t)nv + 255) & ~size_t(255)) +
+           ((sizeof(DevScene) * (size_t)nscenes + 255) & ~size_t(255));
+}
+
+int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* views,
+                    int32_t nv, const sdgr_options* opt, void* query_scratch,
+                    size_t query_bytes, void* stream, sdgr_plan* plan)
+{
+    g_last_error.clear();
+    if (!plan) return fail(SDGR_EINVAL, "plan is null");
+    Problem P;
+    int rc = build_problem(scenes, nscenes, views, nv, opt, P);
+    if (rc) return rc;
+    if (!query_scratch || query_bytes < sdgr_query_bytes(nscenes, nv))
+        return fail(SDGR_EWORKSPACE, "query scratch smaller than sdgr_query_bytes()");
+    if ((uintptr_t)query_scratch & 255) return fail(SDGR_EINVAL, "scratch not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    Arena a{(char*)query_scratch};
+    unsigned long long* totals = a.take<unsigned long long>(8);
+    DevView* dviews = a.take<DevView>(nv);
+    DevScene* dscenes = a.take<DevScene>(nscenes);
+    SDGR_HIP(launch_upload(dviews, P.views.data(), sizeof(DevView) * nv, s));
+    SDGR_HIP(launch_upload(dscenes, P.scenes.data(), sizeof(DevScene) * nscenes, s));
+    SDGR_HIP(launch_fill_u32((uint32_t*)totals, 0u, 16, s));
+    SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.records, P.rp, false, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, totals, s));
+    unsigned long long host_tot[2] = {0, 0};
+    SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));
+    SDGR_HIP(hipStreamSynchronize(s));
+    if (host_tot[0] + host_tot[1] > (unsigned long long)INT32_MAX)
+        return fail(SDGR_EUNSUPPORTED, "more than 2^31 - 1 (Gaussian, tile) pairs");
+    sdgr_plan out{};
+    out.records = P.records;
+    out.pairs_c = (int64_t)host_tot[0];
+    out.pairs_i = (int64_t)host_tot[1];
+    out.tiles_c = P.tiles_c;
+    out.tiles_i = P.tiles_i;
+    out.rays = P.rays;
+    out.nviews = nv;
+    out.nscenes = nscenes;
+    out.tile = TILE;
+    out.image_floats = (size_t)P.image_floats;
+    Bufs b;
+    layout(P, out.pairs_c, out.pairs_i, FWD, nullptr, nullptr, b, &out.state_bytes,
+           &out.fwd_scratch_bytes);
+    layout(P, out.pairs_c, out.pairs_i, BWD, nullptr, nullptr, b, nullptr,
+           &out.bwd_scratch_bytes);
+    *plan = out;
+    return SDGR_OK;
+}
+
+int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* views, int32_t nv,
+                 const sdgr_options* opt, const sdgr_plan* plan, void* state, void* scratch,
+                 float* images, void* stream)
+{
+    g_last_error.clear();
+    Problem P;
+    int rc = build_problem(scenes, nscenes, views, nv, opt, P);
+    if (rc) return rc;
+    if ((rc = check_plan(P, plan))) return rc;
+    if (!state || !scratch || !images) return fail(SDGR_EINVAL, "null workspace or images");
+    if (((uintptr_t)state | (uintptr_t)scratch) & 255)
+        return fail(SDGR_EINVAL, "workspaces must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    Bufs b;
+    layout(P, plan->pairs_c, plan->pairs_i, FWD, (char*)state, (char*)scratch, b, nullptr,
+           nullptr);
+    if ((rc = upload_tables(P, b, s))) return rc;
+    if ((rc = build_lists(P, plan, b, s))) return rc;
+    const int pw = final_pair_buffer(P);
+    SDGR_HIP(launch_fill_u32((uint32_t*)b.A, 0u, P.records, s));
+    SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, P.rp, b.ranges, b.pval[pw], b.cq,
+                                 b.cw, b.A, b.tau, b.nlast, s));
+    SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, s));
+    SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.tiles_c, P.tiles_i, P.rp, b.ranges,
+                                 b.pval[pw], b.iq, b.iw, images, s));
+    return SDGR_OK;
+}
+
+int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* views,
+                  int32_t nv, const sdgr_options* opt, const sdgr_plan* plan, void* state,
+                  void* scratch, const float* dL_dimages, const sdgr_scene_grad* grads,
+                  void* stream)
+{
+    g_last_error.clear();
+    Problem P;
+    int rc = build_problem(scenes, nscenes, views, nv, opt, P);
+    if (rc) return rc;
+    if ((rc = check_plan(P, plan))) return rc;
+    if (!state || !scratch || !dL_dimages || !grads)
+        return fail(SDGR_EINVAL, "null workspace, cotangent or gradients");
+    if (((uintptr_t)state | (uintptr_t)scratch) & 255)
+        return fail(SDGR_EINVAL, "workspaces must be 256-byte aligned");
+    for (int sidx = 0; sidx < nscenes; ++sidx) {
+        const sdgr_scene_grad& g = grads[sidx];
+        if (scenes[sidx].n > 0 &&
+            (!g.d_means || !g.d_scales || !g.d_quats || !g.d_amp || !g.d_ext))
+            return fail(SDGR_EINVAL, "scene " + std::to_string(sidx) + ": null gradient array");
+        P.scenes[sidx].d_means = g.d_means;
+        P.scenes[sidx].d_scales = g.d_scales;
+        P.scenes[sidx].d_quats = g.d_quats;
+        P.scenes[sidx].d_amp = g.d_amp;
+        P.scenes[sidx].d_ext = g.d_ext;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Bufs b;
+    layout(P, plan->pairs_c, plan->pairs_i, BWD, (char*)state, (char*)scratch, b, nullptr,
+           nullptr);
+    if ((rc = upload_tables(P, b, s))) return rc;
+    if (P.recompute) {
+        // the forward's lists are gone: rebuild them (identical, the sorts
+        // are deterministic) and refill the intensities from the kept A
+        if ((rc = build_lists(P, plan, b, s))) return rc;
+        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, s));
+    }
+    const int pw = final_pair_buffer(P);
+    SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_c, 0u, 8 * P.records, s));
+    SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_i, 0u, 8 * P.records, s));
+    SDGR_HIP(launch_raster_b_bwd(b.views, P.nv, P.tiles_c, P.tiles_i, P.rp, b.ranges,
+                                 b.pval[pw], b.iq, b.iw, dL_dimages, b.grad_i, s));
+    SDGR_HIP(launch_raster_a_bwd(b.views, b.scenes, P.nv, P.tiles_c, P.rp, b.ranges, b.pval[pw],
+                                 b.cq, b.cw, b.tau, b.nlast, b.grad_i, b.grad_c, s));
+    SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,
+                                    b.grad_c, b.grad_i, s));
+    return SDGR_OK;
+}
+
+int sdgr_status(const sdgr_plan* plan, const void* state, void* stream)
+{
+    g_last_error.clear();
+    if (!plan || !state) return fail(SDGR_EINVAL, "null plan or state");
+    uint32_t flag = 0;
+    hipStream_t s = (hipStream_t)stream;
+    SDGR_HIP(hipMemcpyAsync(&flag, state, sizeof(flag), hipMemcpyDeviceToHost, s));
+    SDGR_HIP(hipStreamSynchronize(s));
+    if (flag) return fail(SDGR_EOVERFLOW, "pair count exceeded the planned capacity");
+    return SDGR_OK;
+}
+
+static int read_state_array(const sdgr_plan* plan, const void* state, float* out, int which,
+                            void* stream)
+{
+    g_last_error.clear();
+    if (!plan || !state || !out) return fail(SDGR_EINVAL, "null argument");
+    Problem P;
+    P.nv = plan->nviews;
+    P.ns = plan->nscenes;
+    P.records = plan->records;
+    P.rays = plan->rays;
+    P.tiles_c = plan->tiles_c;
+    P.tiles_i = plan->tiles_i;
+    Bufs b;
+    layout(P, plan->pairs_c, plan->pairs_i, FWD, (char*)state, nullptr, b, nullptr, nullptr);
+    const float* src = which == 0 ? b.A : b.tau;
+    int64_t n = which == 0 ? plan->records : plan->rays;
+    if (n <= 0) return SDGR_OK;
+    SDGR_HIP(hipMemcpyAsync(out, src, sizeof(float) * (size_t)n, hipMemcpyDeviceToDevice,
+                            (hipStream_t)stream));
+    return SDGR_OK;
+}
+
+int sdgr_read_intensity(const sdgr_plan* plan, const void* state, float* out, void* stream)
+{
+    return read_state_array(plan, state, out, 0, stream);
+}
+
+int sdgr_read_optical_depth(const sdgr_plan* plan, const void* state, float* out, void* stream)
+{
+    return read_state_array(plan, state, out, 1, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// Shared device-side definitions of the SDGR HIP implementation (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sdgr {
+
+// One 8x8 tile of rays (computation plane) or pixels (imaging plane) is one
+// wave64: lane l handles cell (l % 8, l / 8) of its tile.
+constexpr int TILE = 8;
+constexpr int WAVE = 64;
+constexpr int RASTER_WAVES = 4;            // independent waves per workgroup
+constexpr int RASTER_THREADS = RASTER_WAVES * WAVE;
+
+// Per-view constants, built on the host in FP64 (glibc sin/cos/tan) and
+// copied to the device once per call.
+struct DevView {
+    double ex[3], ey[3], ez[3];   // rows of the world-to-radar rotation
+    double dA, dR, dAc, dEc;      // image and computation-plane spacings
+    double hW, hH, hWc, hHc;      // half sizes (centre of each grid)
+    int64_t rec_off;              // first record (view, Gaussian) of the view
+    int64_t img_off;              // float offset of the image
+    int64_t ray_off;              // first computation-plane cell
+    int32_t W, H, Wc, Hc;
+    int32_t txc, tyc, txi, tyi;   // tiles per axis on each plane
+    int32_t tile_c, tile_i;       // first bucket id on each plane
+    int32_t scene, n;
+};
+
+struct DevScene {
+    const float* means;
+    const float* scales;
+    const float* quats;
+    const float* amp;
+    const float* ext;
+    float* d_means;
+    float* d_scales;
+    float* d_quats;
+    float* d_amp;
+    float* d_ext;
+    int64_t n;
+    int64_t item_off;   // first Gaussian of this scene in the flat item space
+};
+
+struct RasterParams {
+    float q_max;       // footprint cutoff
+    float eps;         // exp(-q_max / 2)
+    float inv1meps;    // 1 / (1 - eps)
+    float tau_max;     // early-termination optical depth (huge = off)
+    int32_t shadowing;
+    float dilation;
+};
+
+// Device-side scalars kept at the start of the state buffer.
+enum StatusSlot : int {
+    ST_OVERFLOW = 0,   // nonzero if pairs exceeded the planned capacity
+    ST_PAIRS_C = 1,    // actual pair counts of the last projection
+    ST_PAIRS_I = 2,
+    ST_PAIRS_ALL = 3,  // min(pairs_c + pairs_i, capacity), sort length
+    ST_COUNT = 8
+};
+
+// Index of the view a global record / bucket belongs to: the last v with
+// off(v) <= x, for offsets non-decreasing in v.
+template <class F>
+__device__ __forceinline__ int find_view(int nv, int64_t x, F off)
+{
+    int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off(mid) <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Orderable bits of a float: unsigned compare of the result matches the
+// float order (with -0 mapped to +0 beforehand).
+__device__ __forceinline__ uint32_t float_order_bits(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// ---- wave64 helpers ------------------------------------------------------
+
+// Sum of v over the 64 lanes of the wave (all lanes must be active);
+// result is wave-uniform.
+__device__ __forceinline__ float wave_sum(float v)
+{
+    // quad sums
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+    // 8-lane sums (row_half_mirror), then 16-lane row sums (row_mirror)
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
+    float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+}  // namespace sdgr
+
+// ---- host-side launchers (defined in the .hip files) ----------------------
+namespace sdgr {
+
+
+hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
+                             int64_t records, const RasterParams& rp,
+                             bool write_records, float4* cq, float2* cw, float4* iq,
+                             float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* cnt_c,
+                             uint32_t* cnt_i, uint64_t* dkey, uint32_t* dval,
+                             unsigned long long* totals, hipStream_t s);
+
+hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
+                                int64_t records, const float* A, float2* iw,
+                                hipStream_t s);
+
+hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, int nv,
+                                  int nscenes, int64_t scene_items,
+                                  const RasterParams& rp, const float* A,
+                                  const float* grad_c, const float* grad_i,
+                                  hipStream_t s);
+
+// exclusive scan of n uint32 (n <= 2^31); tmp must hold scan_tmp_words(n)
+size_t scan_tmp_words(int64_t n);
+hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
+                                 uint32_t* tmp, hipStream_t s);
+
+// stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
+// n_dev points at the device-side element count (<= cap). Buffers [0] hold
+// the input; returns in *which the index of the buffer holding the output.
+size_t radix_hist_words(int64_t cap);
+hipError_t launch_radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], int64_t cap,
+                                 const uint32_t* n_dev, int bits, uint32_t* hist,
+                                 uint32_t* scan_tmp, int* which, hipStream_t s);
+hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
+                                 const uint32_t* n_dev, int bits, uint32_t* hist,
+                                 uint32_t* scan_tmp, int* which, hipStream_t s);
+
+hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* cnt, int64_t n,
+                                uint32_t* out, hipStream_t s);
+hipError_t launch_pair_totals(const uint32_t* cnt_c_sorted, const uint32_t* off_c,
+                              const uint32_t* cnt_i, const uint32_t* off_i, int64_t n,
+                              int64_t cap_c, int64_t cap_i, uint32_t* status,
+                              hipStream_t s);
+hipError_t launch_emit_pairs(const DevView* views, int nv, int64_t records,
+                             const uint64_t* dkey_sorted, const uint32_t* dval_sorted,
+                             const uint2* rect_c, const uint2* rect_i,
+                             const uint32_t* off_c, const uint32_t* off_i,
+                             int64_t cap_c, int64_t cap_i, const uint32_t* status,
+                             uint32_t* pkey, uint32_t* pval, hipStream_t s);
+hipError_t launch_tile_ranges(const uint32_t* keys, int64_t cap, const uint32_t* n_dev,
+                              int64_t buckets, uint2* ranges, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+
+hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
+                               const RasterParams& rp, const uint2* ranges,
+                               const uint32_t* pvals, const float4* cq, const float2* cw,
+                               float* A, float* tau, uint32_t* nlast, hipStream_t s);
+hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t tiles_c,
+                               int64_t tiles_i, const RasterParams& rp, const uint2* ranges,
+                               const uint32_t* pvals, const float4* iq, const float2* iw,
+                               float* images, hipStream_t s);
+hipError_t launch_raster_b_bwd(const DevView* views, int nv, int64_t tiles_c,
+                               int64_t tiles_i, const RasterParams& rp, const uint2* ranges,
+                               const uint32_t* pvals, const float4* iq, const float2* iw,
+                               const float* dimg, float* grad_i, hipStream_t s);
+hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
+                               int64_t tiles_c, const RasterParams& rp,
+                               const uint2* ranges, const uint32_t* pvals,
+                               const float4* cq, const float2* cw, const float* tau,
+                               const uint32_t* nlast, const float* grad_i,
+                               float* grad_c, hipStream_t s);
+
+}  // namespace sdgr

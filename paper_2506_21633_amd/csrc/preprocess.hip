@@ -1,0 +1,334 @@
+// Per-(view, Gaussian) projection onto the computation and imaging planes
+// (paper Sec. II-A: radar rotation R_r, Sigma' = J^T R^T Sigma R J, the
+// projections P_C and P_I) and its adjoint (Sec. II-B, gradient of the
+// Gaussian parameters, both planes contributing to dL/dSigma).
+//
+// One thread per record r = (view v, Gaussian i). Geometry in FP64 (the
+// O(views x Gaussians) part is cheap), records stored in FP32.
+#include "common.hpp"
+
+#include <math.h>
+
+namespace sdgr {
+namespace {
+
+struct Geo {
+    bool valid;
+    double qn[4], qnorm, s[3], R[9], M[9];
+    double S[6];        // 3D covariance xx, xy, xz, yy, yz, zz
+    double x, y, z;     // radar coordinates
+};
+
+__device__ __forceinline__ bool finite(double a) { return isfinite(a); }
+
+// Range coordinate z = e_z . mu as ((ez0 mu0 + ez1 mu1) + ez2 mu2), every
+// product and sum rounded separately: it decides the depth order, and this
+// exact sequence of roundings is the documented key.
+__device__ __attribute__((noinline)) double range_coordinate(const double* ez, double m0,
+                                                             double m1, double m2)
+{
+#pragma clang fp contract(off)
+    double a = ez[0] * m0;
+    double b = ez[1] * m1;
+    double c = ez[2] * m2;
+    return (a + b) + c;
+}
+
+__device__ void geometry(const DevView& V, const DevScene& S, int64_t i, Geo& g)
+{
+    const float* mu = S.means + 3 * i;
+    const float* sc = S.scales + 3 * i;
+    const float* qq = S.quats + 4 * i;
+    double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+    double s0 = sc[0], s1 = sc[1], s2 = sc[2];
+    double q0 = qq[0], q1 = qq[1], q2 = qq[2], q3 = qq[3];
+    double n2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    g.valid = finite(m0) && finite(m1) && finite(m2) && finite(s0) && finite(s1) &&
+              finite(s2) && s0 > 0.0 && s1 > 0.0 && s2 > 0.0 && finite(n2) && n2 > 0.0;
+    if (!g.valid) return;
+    g.qnorm = sqrt(n2);
+    double w = q0 / g.qnorm, x = q1 / g.qnorm, y = q2 / g.qnorm, z = q3 / g.qnorm;
+    g.qn[0] = w; g.qn[1] = x; g.qn[2] = y; g.qn[3] = z;
+    double* R = g.R;
+    R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+    g.s[0] = s0; g.s[1] = s1; g.s[2] = s2;
+    for (int r = 0; r < 3; ++r) {
+        g.M[3 * r + 0] = R[3 * r + 0] * s0;
+        g.M[3 * r + 1] = R[3 * r + 1] * s1;
+        g.M[3 * r + 2] = R[3 * r + 2] * s2;
+    }
+    const double* M = g.M;
+    auto row = [&](int a, int b) {
+        return M[3 * a] * M[3 * b] + M[3 * a + 1] * M[3 * b + 1] + M[3 * a + 2] * M[3 * b + 2];
+    };
+    g.S[0] = row(0, 0); g.S[1] = row(0, 1); g.S[2] = row(0, 2);
+    g.S[3] = row(1, 1); g.S[4] = row(1, 2); g.S[5] = row(2, 2);
+    g.x = V.ex[0] * m0 + V.ex[1] * m1 + V.ex[2] * m2;
+    g.y = V.ey[0] * m0 + V.ey[1] * m1 + V.ey[2] * m2;
+    g.z = range_coordinate(V.ez, m0, m1, m2);
+}
+
+// u^T Sigma w with Sigma given by its 6 unique entries
+__device__ __forceinline__ double quad(const double* u, const double* S, const double* w)
+{
+    double t0 = S[0] * w[0] + S[1] * w[1] + S[2] * w[2];
+    double t1 = S[1] * w[0] + S[3] * w[1] + S[4] * w[2];
+    double t2 = S[2] * w[0] + S[4] * w[1] + S[5] * w[2];
+    return u[0] * t0 + u[1] * t1 + u[2] * t2;
+}
+
+// 2D covariance of one plane spanned by radar axes u, w with spacings su, sw.
+__device__ __forceinline__ void plane_cov(const Geo& g, const double* u, const double* w,
+                                          double su, double sw, double dil, double* cov)
+{
+    cov[0] = quad(u, g.S, u) / (su * su) + dil;
+    cov[1] = quad(u, g.S, w) / (su * sw);
+    cov[2] = quad(w, g.S, w) / (sw * sw) + dil;
+}
+
+__device__ __forceinline__ bool conic(const double* cov, double* Q)
+{
+    double det = cov[0] * cov[2] - cov[1] * cov[1];
+    if (!(det > 0.0) || !isfinite(det)) return false;
+    Q[0] = cov[2] / det; Q[1] = -cov[1] / det; Q[2] = cov[0] / det;
+    return true;
+}
+
+// Tiles touched by the ellipse q < q_max around centre c; returns the
+// rectangle [tx0, tx1) x [ty0, ty1) packed in a uint2 and its tile count.
+__device__ uint32_t tile_rect(double cx, double cy, const double* cov, double q_max, int cols,
+                              int rows, uint2* rect)
+{
+    double rx = sqrt(q_max * cov[0]) * (1.0 + 1e-6) + 1e-6;
+    double ry = sqrt(q_max * cov[2]) * (1.0 + 1e-6) + 1e-6;
+    // cells whose centre (k + 1/2) lies within the bounding box
+    double lo_x = ceil(cx - rx - 0.5), hi_x = floor(cx + rx - 0.5);
+    double lo_y = ceil(cy - ry - 0.5), hi_y = floor(cy + ry - 0.5);
+    lo_x = fmax(lo_x, 0.0); hi_x = fmin(hi_x, (double)(cols - 1));
+    lo_y = fmax(lo_y, 0.0); hi_y = fmin(hi_y, (double)(rows - 1));
+    if (!(lo_x <= hi_x) || !(lo_y <= hi_y)) { *rect = make_uint2(0, 0); return 0; }
+    uint32_t tx0 = (uint32_t)lo_x / TILE, tx1 = (uint32_t)hi_x / TILE + 1;
+    uint32_t ty0 = (uint32_t)lo_y / TILE, ty1 = (uint32_t)hi_y / TILE + 1;
+    *rect = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
+    return (tx1 - tx0) * (ty1 - ty0);
+}
+
+__global__ void __launch_bounds__(256)
+k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
+             int64_t records, RasterParams rp, int write_records, float4* __restrict__ cq,
+             float2* __restrict__ cw, float4* __restrict__ iq, float2* __restrict__ iw,
+             uint2* __restrict__ rect_c, uint2* __restrict__ rect_i,
+             uint32_t* __restrict__ cnt_c, uint32_t* __restrict__ cnt_i,
+             uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
+             unsigned long long* __restrict__ totals)
+{
+    __shared__ unsigned long long part[2];
+    if (threadIdx.x < 2) part[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t nc = 0, ni = 0;
+    if (r < records) {
+        int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
+        const DevView& V = views[v];
+        const DevScene& S = scenes[V.scene];
+        int64_t i = r - V.rec_off;
+        Geo g;
+        geometry(V, S, i, g);
+        double covC[3], covI[3], QC[3], QI[3];
+        bool ok = g.valid;
+        double cCx = 0, cCy = 0, cIx = 0, cIy = 0;
+        uint2 rc = make_uint2(0, 0), ri = make_uint2(0, 0);
+        if (ok) {
+            plane_cov(g, V.ex, V.ey, V.dAc, V.dEc, rp.dilation, covC);
+            plane_cov(g, V.ex, V.ez, V.dA, V.dR, rp.dilation, covI);
+            ok = conic(covC, QC) && conic(covI, QI);
+        }
+        float zkey = 0.0f;
+        if (ok) {
+            cCx = g.x / V.dAc + V.hWc; cCy = g.y / V.dEc + V.hHc;
+            cIx = g.x / V.dA + V.hW;   cIy = g.z / V.dR + V.hH;
+            nc = tile_rect(cCx, cCy, covC, rp.q_max, V.Wc, V.Hc, &rc);
+            ni = tile_rect(cIx, cIy, covI, rp.q_max, V.W, V.H, &ri);
+            zkey = __double2float_rn(g.z);
+        }
+        uint32_t zbits = __float_as_uint(zkey);
+        if (zbits == 0x80000000u) zbits = 0u;   // -0 -> +0
+        if (write_records) {
+            float kappa = ok ? S.ext[i] : 0.0f;
+            cq[r] = make_float4((float)cCx, (float)cCy, ok ? (float)QC[0] : 0.f, ok ? (float)QC[1] : 0.f);
+            cw[r] = make_float2(ok ? (float)QC[2] : 0.f, kappa);
+            iq[r] = make_float4((float)cIx, (float)cIy, ok ? (float)QI[0] : 0.f, ok ? (float)QI[1] : 0.f);
+            iw[r] = make_float2(ok ? (float)QI[2] : 0.f, 0.0f);
+            rect_c[r] = rc;
+            rect_i[r] = ri;
+            cnt_c[r] = nc;
+            cnt_i[r] = ni;
+            dkey[r] = ((uint64_t)(uint32_t)v << 32) | float_order_bits(__uint_as_float(zbits));
+            dval[r] = (uint32_t)r;
+        }
+    }
+    atomicAdd(&part[0], (unsigned long long)nc);
+    atomicAdd(&part[1], (unsigned long long)ni);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&totals[0], part[0]);
+        atomicAdd(&totals[1], part[1]);
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
+                int64_t records, const float* __restrict__ A, float2* __restrict__ iw)
+{
+    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= records) return;
+    int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
+    const DevView& V = views[v];
+    float p = scenes[V.scene].amp[r - V.rec_off];
+    iw[r].y = p * A[r];
+}
+
+// Adjoint of one plane: conic gradient (a, b, c with q = a dx^2 + 2 b dx dy
+// + c dy^2) and centre gradient -> dSigma (6 unique, symmetric full-matrix
+// convention) and dmu.
+__device__ void plane_adjoint(const double* Q, const float* gq, const double* u,
+                              const double* w, double su, double sw, double* dS, double* dmu)
+{
+    // symmetric gradient of the conic matrix, then dSigma2 = -Q G Q
+    double g00 = gq[2], g01 = 0.5 * (double)gq[3], g11 = gq[4];
+    double q00 = Q[0], q01 = Q[1], q11 = Q[2];
+    double t00 = q00 * g00 + q01 * g01, t01 = q00 * g01 + q01 * g11;
+    double t10 = q01 * g00 + q11 * g01, t11 = q01 * g01 + q11 * g11;
+    double h00 = -(t00 * q00 + t01 * q01);
+    double h01 = -(t00 * q01 + t01 * q11);
+    double h11 = -(t10 * q01 + t11 * q11);
+    double a = 1.0 / su, b = 1.0 / sw;
+    h00 *= a * a; h01 *= a * b; h11 *= b * b;
+    // dSigma += h00 u u^T + h01 (u w^T + w u^T) + h11 w w^T
+    int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        int p = idx[k][0], q = idx[k][1];
+        dS[k] += h00 * u[p] * u[q] + h01 * (u[p] * w[q] + w[p] * u[q]) + h11 * w[p] * w[q];
+    }
+    double gx = (double)gq[0] * a, gy = (double)gq[1] * b;
+    for (int k = 0; k < 3; ++k) dmu[k] += gx * u[k] + gy * w[k];
+}
+
+__global__ void __launch_bounds__(256)
+k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
+                  int nscenes, int64_t items, RasterParams rp, const float* __restrict__ A,
+                  const float* __restrict__ grad_c, const float* __restrict__ grad_i)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= items) return;
+    int s = find_view(nscenes, t, [&](int k) { return scenes[k].item_off; });
+    const DevScene& S = scenes[s];
+    int64_t i = t - S.item_off;
+    double dmu[3] = {0, 0, 0}, dS[6] = {0, 0, 0, 0, 0, 0};
+    double dk = 0.0, dp = 0.0;
+    Geo g;
+    g.valid = false;
+    bool any = false;
+    for (int v = 0; v < nv; ++v) {
+        const DevView& V = views[v];
+        if (V.scene != s) continue;
+        geometry(V, S, i, g);
+        if (!g.valid) break;
+        double covC[3], covI[3], QC[3], QI[3];
+        plane_cov(g, V.ex, V.ey, V.dAc, V.dEc, rp.dilation, covC);
+        plane_cov(g, V.ex, V.ez, V.dA, V.dR, rp.dilation, covI);
+        if (!conic(covC, QC) || !conic(covI, QI)) continue;  // no pairs in this view
+        any = true;
+        int64_t r = V.rec_off + i;
+        const float* gc = grad_c + 8 * r;
+        const float* gi = grad_i + 8 * r;
+        plane_adjoint(QC, gc, V.ex, V.ey, V.dAc, V.dEc, dS, dmu);
+        plane_adjoint(QI, gi, V.ex, V.ez, V.dA, V.dR, dS, dmu);
+        dk += gc[5];
+        dp += (double)A[r] * gi[5];
+    }
+    float* om = S.d_means + 3 * i;
+    float* os = S.d_scales + 3 * i;
+    float* oq = S.d_quats + 4 * i;
+    if (!any || !g.valid) {
+        om[0] = om[1] = om[2] = 0.f;
+        os[0] = os[1] = os[2] = 0.f;
+        oq[0] = oq[1] = oq[2] = oq[3] = 0.f;
+        S.d_amp[i] = 0.f;
+        S.d_ext[i] = 0.f;
+        return;
+    }
+    // Sigma = M M^T with M = R diag(s): dM = 2 dSigma M (dSigma symmetric)
+    double D[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+    double dM[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            dM[3 * r + c] = 2.0 * (D[3 * r] * g.M[c] + D[3 * r + 1] * g.M[3 + c] +
+                                   D[3 * r + 2] * g.M[6 + c]);
+    double ds[3], G[9];
+    for (int c = 0; c < 3; ++c) {
+        ds[c] = g.R[c] * dM[c] + g.R[3 + c] * dM[3 + c] + g.R[6 + c] * dM[6 + c];
+        for (int r = 0; r < 3; ++r) G[3 * r + c] = dM[3 * r + c] * g.s[c];
+    }
+    double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+    // derivative of the unit-quaternion rotation matrix entries
+    double gw = 2.0 * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+    double gx = 2.0 * (y * G[1] + z * G[2] + y * G[3] - 2.0 * x * G[4] - w * G[5] + z * G[6] +
+                       w * G[7] - 2.0 * x * G[8]);
+    double gy = 2.0 * (-2.0 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] +
+                       z * G[7] - 2.0 * y * G[8]);
+    double gz = 2.0 * (-2.0 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.0 * z * G[4] +
+                       y * G[5] + x * G[6] + y * G[7]);
+    double dot = w * gw + x * gx + y * gy + z * gz;
+    double inv = 1.0 / g.qnorm;
+    oq[0] = (float)((gw - w * dot) * inv);
+    oq[1] = (float)((gx - x * dot) * inv);
+    oq[2] = (float)((gy - y * dot) * inv);
+    oq[3] = (float)((gz - z * dot) * inv);
+    om[0] = (float)dmu[0]; om[1] = (float)dmu[1]; om[2] = (float)dmu[2];
+    os[0] = (float)ds[0]; os[1] = (float)ds[1]; os[2] = (float)ds[2];
+    S.d_amp[i] = (float)dp;
+    S.d_ext[i] = (float)dk;
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
+                             int64_t records, const RasterParams& rp, bool write_records,
+                             float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
+                             uint2* rect_i, uint32_t* cnt_c, uint32_t* cnt_i, uint64_t* dkey,
+                             uint32_t* dval, unsigned long long* totals, hipStream_t s)
+{
+    if (records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
+                       scenes, nv, records, rp, write_records ? 1 : 0, cq, cw, iq, iw, rect_c,
+                       rect_i, cnt_c, cnt_i, dkey, dval, totals);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
+                                int64_t records, const float* A, float2* iw, hipStream_t s)
+{
+    if (records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_intensity, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
+                       scenes, nv, records, A, iw);
+    return hipGetLastError();
+}
+
+hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, int nv,
+                                  int nscenes, int64_t scene_items, const RasterParams& rp,
+                                  const float* A, const float* grad_c, const float* grad_i,
+                                  hipStream_t s)
+{
+    if (scene_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_params_backward, dim3(blocks_for(scene_items, 256)), dim3(256), 0, s,
+                       views, scenes, nv, nscenes, scene_items, rp, A, grad_c, grad_i);
+    return hipGetLastError();
+}
+
+}  // namespace sdgr

@@ -1,0 +1,114 @@
+"""Host-side checks of the C ABI (no GPU compute): the library loads, exports
+every function include/sdgr.h declares, its structs match the header's
+layout, and argument validation rejects bad input before any device work."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2506_21633_amd import _capi as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sdgr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sdgr_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = C.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(C.EXPORTED)
+    assert L.sdgr_version() == 1
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "sizes.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "sdgr.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",'
+                   'sizeof(sdgr_view), sizeof(sdgr_plan), sizeof(sdgr_options),'
+                   'sizeof(sdgr_scene), sizeof(sdgr_scene_grad),'
+                   'offsetof(sdgr_view, img_w), offsetof(sdgr_plan, records));}\n')
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    want = [ctypes.sizeof(C.View), ctypes.sizeof(C.Plan), ctypes.sizeof(C.Options),
+            ctypes.sizeof(C.Scene), ctypes.sizeof(C.SceneGrad), C.View.img_w.offset,
+            C.Plan.records.offset]
+    assert got == want
+
+
+def test_default_options():
+    o = C.Options()
+    C.lib().sdgr_default_options(ctypes.byref(o))
+    assert (o.shadowing, o.recompute, o.q_max, o.tau_max, o.dilation, o.reserved) == \
+        (1, 0, 9.0, 16.0, 0.0, 0)
+
+
+def _args(grazing=math.radians(45), nv=1, n=10, q_max=9.0, scene=0, w=64):
+    sc = (C.Scene * 1)(C.Scene(n, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000))
+    views = (C.View * max(nv, 1))()
+    for v in views:
+        v.azimuth, v.grazing, v.d_az, v.d_rg = 0.0, grazing, 0.1, 0.1
+        v.img_w, v.img_h, v.scene = w, 64, scene
+    o = C.Options()
+    C.lib().sdgr_default_options(ctypes.byref(o))
+    o.q_max = q_max
+    return sc, views, o
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(grazing=0.0), C.SDGR_EINVAL),
+    (dict(grazing=math.pi / 2), C.SDGR_EINVAL),
+    (dict(nv=0), C.SDGR_EINVAL),
+    (dict(n=-1), C.SDGR_EINVAL),
+    (dict(q_max=0.0), C.SDGR_EINVAL),
+    (dict(q_max=float("nan")), C.SDGR_EINVAL),
+    (dict(scene=3), C.SDGR_EINVAL),
+    (dict(w=0), C.SDGR_EINVAL),
+    (dict(w=8 * 70000), C.SDGR_EUNSUPPORTED),
+])
+def test_plan_query_rejects_bad_arguments(kw, code):
+    L = C.lib()
+    sc, views, o = _args(**kw)
+    nv = kw.get("nv", 1)
+    plan = C.Plan()
+    rc = L.sdgr_plan_query(sc, 1, views, nv, ctypes.byref(o), None, 0, None,
+                           ctypes.byref(plan))
+    assert rc == code
+    assert L.sdgr_last_error()
+
+
+def test_plan_query_needs_scratch():
+    L = C.lib()
+    sc, views, o = _args()
+    plan = C.Plan()
+    rc = L.sdgr_plan_query(sc, 1, views, 1, ctypes.byref(o), None, 0, None, ctypes.byref(plan))
+    assert rc == C.SDGR_EWORKSPACE
+    assert b"scratch" in L.sdgr_last_error()
+
+
+def test_forward_rejects_mismatched_plan():
+    L = C.lib()
+    sc, views, o = _args()
+    plan = C.Plan()
+    plan.records, plan.nviews, plan.nscenes, plan.tile = 999, 1, 1, 8
+    rc = L.sdgr_forward(sc, 1, views, 1, ctypes.byref(o), ctypes.byref(plan), 0x1000, 0x1000,
+                        0x1000, None)
+    assert rc == C.SDGR_EINVAL
+    assert b"plan" in L.sdgr_last_error()
+
+
+def test_query_bytes_small_and_monotone():
+    L = C.lib()
+    a, b = L.sdgr_query_bytes(1, 1), L.sdgr_query_bytes(8, 512)
+    assert 0 < a <= b < 1 << 20
