@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Forward+backward SAR images/s of the SDGR hot path on one MI355X.
+
+Workload (default "vehicle_200k"): 200,000 Gaussians on a seeded composite of
+boxes and cylinders inside a 6 x 3 x 2.5 m envelope, 72 views (azimuth 0-355
+deg in 5 deg steps, incidence alternating 30/45 deg), 256 x 256 images at
+0.1 m. One step = plan (pair counts) + forward of all 72 views + L1-loss
+cotangent against a target rendered from a copy with means jittered by
+N(0, 0.1 m) + backward to all Gaussian parameters, everything resident in
+HBM. Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+# FP32 VALU issue rate without packed instructions: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz = 39.3e12 lane-operations/s (an FMA counts once); the
+# transcendental unit runs at a quarter of that rate.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+WORKLOADS = ("vehicle_200k", "building_50k", "fwd_1k")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="vehicle_200k", choices=WORKLOADS)
+    ap.add_argument("--cpu-rows", type=int, default=32,
+                    help="range rows of one view the CPU oracle baseline times")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the per-stage HIP event timing")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_2506_21633_amd import scenes
+    if name == "vehicle_200k":
+        sc = scenes.vehicle(303, 200_000)
+        views = scenes.vehicle_views()
+        target = scenes.jitter(sc, 306)
+        cfg = dict(workload=name, gaussians=sc.n, views=len(views), image="256x256",
+                   pixel_m=0.1, incidence_deg=[30, 45], loss="L1 vs jittered target")
+    elif name == "building_50k":
+        sc = scenes.building(202, 50_000)
+        views = scenes.building_views()
+        target = scenes.jitter(sc, 203)
+        cfg = dict(workload=name, gaussians=sc.n, views=len(views), image="128x128",
+                   pixel_m=0.15, incidence_deg=[40], loss="L1 vs jittered target")
+    else:
+        sc, views = scenes.fwd_1k()
+        target = scenes.jitter(sc, 102)
+        cfg = dict(workload=name, gaussians=sc.n, views=len(views), image="64x64",
+                   pixel_m=0.15, incidence_deg=[45], loss="L1 vs jittered target")
+    return sc, views, target, cfg
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2506_21633_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, launches_per_step, src_hash):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    rec = d.get(kernel)
+    if not rec or rec.get("source_hash") != src_hash:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(sc, views, rows):
+    """The FP64 oracle (untuned) on a bounded sample: the central `rows`
+    range rows of view 0 (image and computation plane), all Gaussians,
+    forward + backward; scaled to whole images."""
+    import numpy as np
+    import oracle
+    from paper_2506_21633_amd import scenes
+    v = views[0]
+    band = scenes.View(azimuth=v.azimuth, grazing=v.grazing, img_w=v.img_w, img_h=rows,
+                       d_az=v.d_az, d_rg=v.d_rg, comp_w=v.img_w, comp_h=rows,
+                       comp_d_az=v.d_az, comp_d_el=v.d_rg * math.tan(v.grazing))
+    t0 = time.perf_counter()
+    _, _, S = oracle.forward_view(sc, band)
+    oracle.backward_view(sc, band, np.sign(S) / S.size)
+    dt = time.perf_counter() - t0
+    per_image = dt * (v.img_h / rows)
+    return {"value": 1.0 / per_image, "unit": "images/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"forward+backward of the central {rows} of {v.img_h} range rows of "
+                      f"view 0 ({v.img_w} columns, {sc.n} Gaussians), {dt:.1f} s, "
+                      f"scaled x{v.img_h / rows:g} to one image"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "multi-GPU view sharding is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2506_21633_amd import _capi, api
+
+    dev = torch.device("cuda:0")
+    sc, views, target, cfg = workload(args.workload)
+    g = api.GaussianTensors.from_numpy(sc, dev)
+    tgt = api.GaussianTensors.from_numpy(target, dev)
+    r = api.Renderer([g], views)
+    target_images = api.Renderer([tgt], views).forward().images.clone()
+    numel = float(target_images.numel())
+
+    def step():
+        res = r.forward(r.plan())
+        G = torch.sign(res.images - target_images) / numel
+        r.backward(res, G)
+        return res
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize(dev)
+    res = step()
+    plan = res.plan
+    torch.cuda.synchronize(dev)
+
+    lib = _capi.lib()
+    if not args.no_profile:
+        _capi.profile_read()
+        lib.sdgr_profile_enable(1)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    lib.sdgr_profile_enable(0)
+    stages = {} if args.no_profile else _capi.profile_read()
+
+    nv = len(views)
+    ms_step = dt * 1e3 / args.steps
+    out = {
+        "metric": "fwd+bwd SAR images/s at 200k Gaussians 256^2",
+        "value": nv * args.steps / dt,
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": dict(cfg, parallelism="single GPU", pairs_c=plan.pairs_c,
+                       pairs_i=plan.pairs_i, tiles_c=plan.tiles_c, tiles_i=plan.tiles_i),
+    }
+    if stages:
+        per = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}
+        out["stages_ms"] = {k: round(v, 4) for k, v in per.items()}
+        dom = max(per, key=per.get)
+        out["roofline"] = roofline(dom, per[dom], plan, nv, sc.n)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, views, args.cpu_rows)
+    print(json.dumps(out), flush=True)
+
+
+def roofline(kernel, ms, plan, nv, n):
+    """Roofline entry of the dominant stage: the raster kernels are VALU-bound
+    (footprint and attenuation arithmetic per (cell, Gaussian) pair), the
+    sorts and the projection are HBM-bound."""
+    src = {"raster_a_fwd": "raster.hip", "raster_b_fwd": "raster.hip",
+           "raster_b_bwd": "raster.hip", "raster_a_bwd": "raster.hip",
+           "pair_sort": "sort.hip", "depth_sort": "sort.hip",
+           "preprocess": "preprocess.hip", "params_bwd": "preprocess.hip"}.get(kernel)
+    traffic = stored_traffic(kernel, 1, source_hash(src)) if src else None
+    if kernel.startswith("raster"):
+        plane_pairs = plan.pairs_c if kernel in ("raster_a_fwd", "raster_a_bwd") else plan.pairs_i
+        ops = VALU_OPS_PER_PAIR[kernel] * plane_pairs * 64
+        achieved = ops / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
+                "traffic": traffic, "kernel": kernel, "ms": ms,
+                "work": f"{plane_pairs} (tile, Gaussian) pairs x 64 cells x "
+                        f"{VALU_OPS_PER_PAIR[kernel]} ops"}
+    return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": None, "traffic": traffic, "kernel": kernel, "ms": ms}
+
+
+# Lane-operations the definition needs per (cell, Gaussian) evaluation inside
+# a tile (quadratic form, cutoff test, footprint, attenuation), with each exp
+# weighted 4 (quarter-rate transcendental unit).
+VALU_OPS_PER_PAIR = {"raster_a_fwd": 24, "raster_b_fwd": 14,
+                     "raster_b_bwd": 30, "raster_a_bwd": 40}
+
+
+if __name__ == "__main__":
+    main()

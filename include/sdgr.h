@@ -205,6 +205,17 @@ int sdgr_read_intensity(const sdgr_plan* plan, const void* state, float* out,
 int sdgr_read_optical_depth(const sdgr_plan* plan, const void* state,
                             float* out, void* stream);
 
+/* ---- instrumentation (for benchmarks; not part of the method) ----------
+ * When enabled, every stage of forward/backward/plan_query records a pair of
+ * HIP events on the call's stream (a few microseconds of overhead per
+ * stage). sdgr_profile_read waits for the recorded events, writes the total
+ * milliseconds and the number of timed calls of each stage into ms[i] and
+ * calls[i] for i < n (either may be NULL), resets the totals and returns the
+ * number of stages. sdgr_profile_stage(i) names stage i. */
+int sdgr_profile_enable(int32_t on);
+int sdgr_profile_read(double* ms, int64_t* calls, int32_t n);
+const char* sdgr_profile_stage(int32_t i);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,8 @@ SDGR_EUNSUPPORTED = -5
 EXPORTED = ("sdgr_version", "sdgr_last_error", "sdgr_default_options",
             "sdgr_query_bytes", "sdgr_plan_query", "sdgr_forward",
             "sdgr_backward", "sdgr_status", "sdgr_read_intensity",
-            "sdgr_read_optical_depth")
+            "sdgr_read_optical_depth", "sdgr_profile_enable", "sdgr_profile_read",
+            "sdgr_profile_stage")
 
 
 class Scene(ctypes.Structure):
@@ -98,7 +99,11 @@ def lib():
     L.sdgr_status.argtypes = [P(Plan), vp, vp]
     L.sdgr_read_intensity.argtypes = [P(Plan), vp, vp, vp]
     L.sdgr_read_optical_depth.argtypes = [P(Plan), vp, vp, vp]
-    for name in ("sdgr_plan_query", "sdgr_forward", "sdgr_backward", "sdgr_status",
+    L.sdgr_profile_enable.argtypes = [ctypes.c_int32]
+    L.sdgr_profile_read.argtypes = [P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int32]
+    L.sdgr_profile_stage.argtypes = [ctypes.c_int32]
+    L.sdgr_profile_stage.restype = ctypes.c_char_p
+    for name in ("sdgr_profile_enable", "sdgr_profile_read", "sdgr_plan_query", "sdgr_forward", "sdgr_backward", "sdgr_status",
                  "sdgr_read_intensity", "sdgr_read_optical_depth"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -108,3 +113,15 @@ def lib():
 def check(code):
     if code != SDGR_OK:
         raise SDGRError(code, lib().sdgr_last_error().decode(errors="replace"))
+
+
+def profile_read():
+    """{stage name: (total ms, timed calls)} since the last read."""
+    L = lib()
+    n = 32
+    ms = (ctypes.c_double * n)()
+    calls = (ctypes.c_int64 * n)()
+    k = L.sdgr_profile_read(ms, calls, n)
+    if k < 0:
+        check(k)
+    return {L.sdgr_profile_stage(i).decode(): (ms[i], calls[i]) for i in range(k)}

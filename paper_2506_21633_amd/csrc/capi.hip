@@ -7,6 +7,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -32,6 +33,68 @@ int hip_fail(hipError_t e, const char* where)
         hipError_t e_ = (expr);                                 \
         if (e_ != hipSuccess) return hip_fail(e_, #expr);       \
     } while (0)
+
+// ---- optional per-stage timing with HIP events on the caller's stream ----
+enum Stage {
+    SG_QUERY, SG_PREPROCESS, SG_DEPTH_SORT, SG_BIN, SG_PAIR_SORT, SG_RANGES,
+    SG_RASTER_A_FWD, SG_INTENSITY, SG_RASTER_B_FWD, SG_ZERO, SG_RASTER_B_BWD,
+    SG_RASTER_A_BWD, SG_PARAMS_BWD, SG_COUNT
+};
+const char* const kStageNames[SG_COUNT] = {
+    "plan_query", "preprocess", "depth_sort", "bin_pairs", "pair_sort", "tile_ranges",
+    "raster_a_fwd", "set_intensity", "raster_b_fwd", "zero_grads", "raster_b_bwd",
+    "raster_a_bwd", "params_bwd"};
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    struct Rec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    double ms[SG_COUNT] = {};
+    int64_t calls[SG_COUNT] = {};
+};
+Profiler g_prof;
+
+hipEvent_t take_event()
+{
+    if (!g_prof.pool.empty()) {
+        hipEvent_t e = g_prof.pool.back();
+        g_prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event pair around one stage when timing is enabled.
+class StageTimer {
+public:
+    StageTimer(int stage, hipStream_t s) : stage_(stage), s_(s)
+    {
+        std::lock_guard<std::mutex> g(g_prof.mu);
+        if (!g_prof.on) return;
+        a_ = take_event();
+        b_ = take_event();
+        if (a_ && b_) (void)hipEventRecord(a_, s_);
+    }
+    ~StageTimer()
+    {
+        if (!a_ || !b_) return;
+        std::lock_guard<std::mutex> g(g_prof.mu);
+        (void)hipEventRecord(b_, s_);
+        g_prof.pending.push_back({stage_, a_, b_});
+    }
+
+private:
+    int stage_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
 
 int bits_for(int64_t max_value)
 {
@@ -301,31 +364,45 @@ int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStrea
     const int64_t R = P.records;
     SDGR_HIP(launch_fill_u32(b.status, 0u, STATUS_WORDS, s));
     SDGR_HIP(launch_fill_u32(b.status + ST_RECORDS, (uint32_t)R, 1, s));
-    SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, R, P.rp, true, b.cq, b.cw, b.iq, b.iw,
-                               b.rect_c, b.rect_i, b.cnt_c, b.cnt_i, b.dkey[0], b.dval[0],
-                               reinterpret_cast<unsigned long long*>(b.status + ST_COUNT), s));
+    {
+        StageTimer t(SG_PREPROCESS, s);
+        SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, R, P.rp, true, b.cq, b.cw, b.iq,
+                                   b.iw, b.rect_c, b.rect_i, b.cnt_c, b.cnt_i, b.dkey[0],
+                                   b.dval[0],
+                                   reinterpret_cast<unsigned long long*>(b.status + ST_COUNT),
+                                   s));
+    }
     // depth order of the records of every view
     uint64_t* dk[2] = {b.dkey[0], b.dkey[1]};
     uint32_t* dv[2] = {b.dval[0], b.dval[1]};
     int which = 0;
-    SDGR_HIP(launch_radix_sort_u64(dk, dv, R, b.status + ST_RECORDS, passes_bits_depth(P),
-                                   b.hist, b.scan_tmp, &which, s));
-    SDGR_HIP(launch_gather_counts(dv[which], b.cnt_c, R, b.cnt_c_sorted, s));
-    SDGR_HIP(launch_exclusive_scan(b.cnt_c_sorted, b.off_c, R, b.scan_tmp, s));
-    SDGR_HIP(launch_exclusive_scan(b.cnt_i, b.off_i, R, b.scan_tmp, s));
-    SDGR_HIP(launch_pair_totals(nullptr, nullptr, nullptr, nullptr, R, plan->pairs_c,
-                                plan->pairs_i, b.status, s));
+    {
+        StageTimer t(SG_DEPTH_SORT, s);
+        SDGR_HIP(launch_radix_sort_u64(dk, dv, R, b.status + ST_RECORDS, passes_bits_depth(P),
+                                       b.hist, b.scan_tmp, &which, s));
+    }
     uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};
-    SDGR_HIP(launch_emit_pairs(b.views, P.nv, R, dk[which], dv[which], b.rect_c, b.rect_i,
-                               b.off_c, b.off_i, plan->pairs_c, plan->pairs_i, b.status,
-                               pk[0], pv[0], s));
+    {
+        StageTimer t(SG_BIN, s);
+        SDGR_HIP(launch_gather_counts(dv[which], b.cnt_c, R, b.cnt_c_sorted, s));
+        SDGR_HIP(launch_exclusive_scan(b.cnt_c_sorted, b.off_c, R, b.scan_tmp, s));
+        SDGR_HIP(launch_exclusive_scan(b.cnt_i, b.off_i, R, b.scan_tmp, s));
+        SDGR_HIP(launch_pair_totals(plan->pairs_c, plan->pairs_i, b.status, s));
+        SDGR_HIP(launch_emit_pairs(b.views, P.nv, R, dk[which], dv[which], b.rect_c, b.rect_i,
+                                   b.off_c, b.off_i, plan->pairs_c, plan->pairs_i, b.status,
+                                   pk[0], pv[0], s));
+    }
     int pw = 0;
     const int64_t K = plan->pairs_c + plan->pairs_i;
-    SDGR_HIP(launch_radix_sort_u32(pk, pv, K, b.status + ST_PAIRS_ALL, passes_bits_pairs(P),
-                                   b.hist, b.scan_tmp, &pw, s));
+    {
+        StageTimer t(SG_PAIR_SORT, s);
+        SDGR_HIP(launch_radix_sort_u32(pk, pv, K, b.status + ST_PAIRS_ALL,
+                                       passes_bits_pairs(P), b.hist, b.scan_tmp, &pw, s));
+    }
     if (K > 0 && pw != final_pair_buffer(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
+    StageTimer t(SG_RANGES, s);
     SDGR_HIP(launch_tile_ranges(pk[pw], K, b.status + ST_PAIRS_ALL, P.tiles_c + P.tiles_i,
                                 b.ranges, s));
     return SDGR_OK;
@@ -380,9 +457,12 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
     SDGR_HIP(launch_upload(dviews, P.views.data(), sizeof(DevView) * nv, s));
     SDGR_HIP(launch_upload(dscenes, P.scenes.data(), sizeof(DevScene) * nscenes, s));
     SDGR_HIP(launch_fill_u32((uint32_t*)totals, 0u, 16, s));
-    SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.records, P.rp, false, nullptr, nullptr,
-                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                               nullptr, totals, s));
+    {
+        StageTimer t(SG_QUERY, s);
+        SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.records, P.rp, false, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr, nullptr, nullptr, totals, s));
+    }
     unsigned long long host_tot[2] = {0, 0};
     SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));
     SDGR_HIP(hipStreamSynchronize(s));
@@ -428,9 +508,16 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     if ((rc = build_lists(P, plan, b, s))) return rc;
     const int pw = final_pair_buffer(P);
     SDGR_HIP(launch_fill_u32((uint32_t*)b.A, 0u, P.records, s));
-    SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, P.rp, b.ranges, b.pval[pw], b.cq,
-                                 b.cw, b.A, b.tau, b.nlast, s));
-    SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, s));
+    {
+        StageTimer t(SG_RASTER_A_FWD, s);
+        SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, P.rp, b.ranges, b.pval[pw],
+                                     b.cq, b.cw, b.A, b.tau, b.nlast, s));
+    }
+    {
+        StageTimer t(SG_INTENSITY, s);
+        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, s));
+    }
+    StageTimer t(SG_RASTER_B_FWD, s);
     SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.tiles_c, P.tiles_i, P.rp, b.ranges,
                                  b.pval[pw], b.iq, b.iw, images, s));
     return SDGR_OK;
@@ -473,12 +560,22 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, s));
     }
     const int pw = final_pair_buffer(P);
-    SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_c, 0u, 8 * P.records, s));
-    SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_i, 0u, 8 * P.records, s));
-    SDGR_HIP(launch_raster_b_bwd(b.views, P.nv, P.tiles_c, P.tiles_i, P.rp, b.ranges,
-                                 b.pval[pw], b.iq, b.iw, dL_dimages, b.grad_i, s));
-    SDGR_HIP(launch_raster_a_bwd(b.views, b.scenes, P.nv, P.tiles_c, P.rp, b.ranges, b.pval[pw],
-                                 b.cq, b.cw, b.tau, b.nlast, b.grad_i, b.grad_c, s));
+    {
+        StageTimer t(SG_ZERO, s);
+        SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_c, 0u, 8 * P.records, s));
+    }
+    {
+        StageTimer t(SG_RASTER_B_BWD, s);
+        SDGR_HIP(launch_image_bwd(b.views, P.nv, P.records, P.rp, b.iq, b.iw, dL_dimages,
+                                  b.grad_i, s));
+    }
+    {
+        StageTimer t(SG_RASTER_A_BWD, s);
+        SDGR_HIP(launch_raster_a_bwd(b.views, b.scenes, P.nv, P.tiles_c, P.rp, b.ranges,
+                                     b.pval[pw], b.cq, b.cw, b.tau, b.nlast, b.grad_i,
+                                     b.grad_c, s));
+    }
+    StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,
                                     b.grad_c, b.grad_i, s));
     return SDGR_OK;
@@ -516,6 +613,48 @@ static int read_state_array(const sdgr_plan* plan, const void* state, float* out
     SDGR_HIP(hipMemcpyAsync(out, src, sizeof(float) * (size_t)n, hipMemcpyDeviceToDevice,
                             (hipStream_t)stream));
     return SDGR_OK;
+}
+
+int sdgr_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    g_prof.on = on != 0;
+    return SDGR_OK;
+}
+
+int sdgr_profile_read(double* ms, int64_t* calls, int32_t n)
+{
+    g_last_error.clear();
+    std::vector<Profiler::Rec> recs;
+    {
+        std::lock_guard<std::mutex> g(g_prof.mu);
+        recs.swap(g_prof.pending);
+    }
+    for (const auto& r : recs) {
+        float t = 0.0f;
+        SDGR_HIP(hipEventSynchronize(r.b));
+        SDGR_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        std::lock_guard<std::mutex> g(g_prof.mu);
+        g_prof.ms[r.stage] += t;
+        g_prof.calls[r.stage] += 1;
+        g_prof.pool.push_back(r.a);
+        g_prof.pool.push_back(r.b);
+    }
+    std::lock_guard<std::mutex> g(g_prof.mu);
+    for (int i = 0; i < SG_COUNT; ++i) {
+        if (i < n) {
+            if (ms) ms[i] = g_prof.ms[i];
+            if (calls) calls[i] = g_prof.calls[i];
+        }
+        g_prof.ms[i] = 0.0;
+        g_prof.calls[i] = 0;
+    }
+    return SG_COUNT;
+}
+
+const char* sdgr_profile_stage(int32_t i)
+{
+    return (i >= 0 && i < SG_COUNT) ? kStageNames[i] : "";
 }
 
 int sdgr_read_intensity(const sdgr_plan* plan, const void* state, float* out, void* stream)

@@ -144,10 +144,8 @@ hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t c
 
 hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* cnt, int64_t n,
                                 uint32_t* out, hipStream_t s);
-hipError_t launch_pair_totals(const uint32_t* cnt_c_sorted, const uint32_t* off_c,
-                              const uint32_t* cnt_i, const uint32_t* off_i, int64_t n,
-                              int64_t cap_c, int64_t cap_i, uint32_t* status,
-                              hipStream_t s);
+// overflow check and actual pair counts from the projection's u64 totals
+hipError_t launch_pair_totals(int64_t cap_c, int64_t cap_i, uint32_t* status, hipStream_t s);
 hipError_t launch_emit_pairs(const DevView* views, int nv, int64_t records,
                              const uint64_t* dkey_sorted, const uint32_t* dval_sorted,
                              const uint2* rect_c, const uint2* rect_i,
@@ -171,6 +169,9 @@ hipError_t launch_raster_b_bwd(const DevView* views, int nv, int64_t tiles_c,
                                int64_t tiles_i, const RasterParams& rp, const uint2* ranges,
                                const uint32_t* pvals, const float4* iq, const float2* iw,
                                const float* dimg, float* grad_i, hipStream_t s);
+hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
+                            const RasterParams& rp, const float4* iq, const float2* iw,
+                            const float* dimg, float* grad_i, hipStream_t s);
 hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
                                int64_t tiles_c, const RasterParams& rp,
                                const uint2* ranges, const uint32_t* pvals,

@@ -12,9 +12,11 @@
 //                    sum over the wave's rays is one DPP reduction and one
 //                    float atomic per (tile, Gaussian).
 //   pass B forward : per pixel, S = sum_i f_i I_i (order-free, no atomics).
-//   pass B backward: per pixel, dL/dI and the gradients of the imaging-plane
-//                    centre and conic, reduced over the wave, 6 atomics per
-//                    (tile, Gaussian).
+//   pass B backward: per record (k_image_bwd): dL/dI and the gradients of the
+//                    imaging-plane centre and conic gathered over the
+//                    footprint, no atomics. (k_raster_b_bwd is the tile form:
+//                    per pixel, reduced over the wave, 6 atomics per
+//                    (tile, Gaussian).)
 //   pass A backward: per ray, back to front from the last contributing
 //                    entry: tau -= kappa f, T = exp(-tau),
 //                    dL/dalpha = T (c - U), U <- c alpha + (1 - alpha) U
@@ -238,6 +240,61 @@ k_raster_b_bwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, int64
     }
 }
 
+// Imaging-plane backward, one thread per record (view, Gaussian): the
+// additive image formation has no order, so each thread walks its own
+// footprint ellipse q < q_max row by row (exact column span from the conic,
+// widened by one pixel), gathers dL/dS there and keeps dL/dI and the centre
+// and conic gradients in registers -- no atomics, no tile list.
+__global__ void __launch_bounds__(256)
+k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterParams rp,
+            const float4* __restrict__ iq, const float2* __restrict__ iw,
+            const float* __restrict__ dimg, float* __restrict__ grad_i)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= records) return;
+    const int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
+    const DevView& V = views[v];
+    const float4 g = iq[r];
+    const float2 g2 = iw[r];
+    const float a = g.z, b = g.w, c = g2.x, I = g2.y;
+    const float det = a * c - b * b;
+    float dI = 0.f, dcx = 0.f, dcy = 0.f, da = 0.f, db = 0.f, dc = 0.f;
+    if (det > 0.0f && a > 0.0f) {
+        const float qm = rp.q_max;
+        const float ry = sqrtf(qm * a / det);
+        // clamp in float before converting (far-away centres stay in range)
+        const int row0 = (int)fmaxf(0.0f, ceilf(g.y - ry - 0.5f) - 1.0f);
+        const int row1 = (int)fminf((float)(V.H - 1), floorf(g.y + ry - 0.5f) + 1.0f);
+        const float* G = dimg + V.img_off;
+        for (int row = row0; row <= row1; ++row) {
+            const float dy = row + 0.5f - g.y;
+            const float D = a * qm - det * dy * dy;
+            if (D < 0.0f) continue;
+            const float half = sqrtf(D) / a;
+            const float xc = g.x - b * dy / a;
+            const int col0 = (int)fmaxf(0.0f, ceilf(xc - half - 0.5f) - 1.0f);
+            const int col1 = (int)fminf((float)(V.W - 1), floorf(xc + half - 0.5f) + 1.0f);
+            for (int col = col0; col <= col1; ++col) {
+                const float dx = col + 0.5f - g.x;
+                const float q = quadform(g, c, dx, dy);
+                if (!(q < qm)) continue;
+                const float Gp = G[(int64_t)row * V.W + col];
+                const float e = __expf(-0.5f * q);
+                dI += Gp * (e - rp.eps) * rp.inv1meps;
+                const float dq = Gp * I * (-0.5f * e * rp.inv1meps);
+                dcx += -2.0f * dq * (a * dx + b * dy);
+                dcy += -2.0f * dq * (b * dx + c * dy);
+                da += dq * dx * dx;
+                db += 2.0f * dq * dx * dy;
+                dc += dq * dy * dy;
+            }
+        }
+    }
+    float4* o = reinterpret_cast<float4*>(grad_i + 8 * r);
+    o[0] = make_float4(dcx, dcy, da, db);
+    o[1] = make_float4(dc, dI, 0.0f, 0.0f);
+}
+
 __global__ void __launch_bounds__(RASTER_THREADS)
 k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
                int64_t tiles_c, RasterParams rp, const uint2* __restrict__ ranges,
@@ -355,6 +412,16 @@ hipError_t launch_raster_b_bwd(const DevView* views, int nv, int64_t tiles_c, in
     if (tiles_i <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_raster_b_bwd, dim3(raster_grid(tiles_i)), dim3(RASTER_THREADS), 0, s,
                        views, nv, tiles_c, tiles_i, rp, ranges, pvals, iq, iw, dimg, grad_i);
+    return hipGetLastError();
+}
+
+hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
+                            const RasterParams& rp, const float4* iq, const float2* iw,
+                            const float* dimg, float* grad_i, hipStream_t s)
+{
+    if (records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_image_bwd, dim3((unsigned)((records + 255) / 256)), dim3(256), 0, s,
+                       views, nv, records, rp, iq, iw, dimg, grad_i);
     return hipGetLastError();
 }
 

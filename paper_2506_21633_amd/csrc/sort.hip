@@ -360,9 +360,7 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* cnt, int6
     return hipGetLastError();
 }
 
-hipError_t launch_pair_totals(const uint32_t*, const uint32_t*, const uint32_t*,
-                              const uint32_t*, int64_t, int64_t cap_c, int64_t cap_i,
-                              uint32_t* status, hipStream_t s)
+hipError_t launch_pair_totals(int64_t cap_c, int64_t cap_i, uint32_t* status, hipStream_t s)
 {
     hipLaunchKernelGGL(k_pair_totals, dim3(1), dim3(1), 0, s, cap_c, cap_i, status);
     return hipGetLastError();
