@@ -12,6 +12,7 @@ HBM. Prints one JSON line.
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 import argparse
+import ctypes
 import hashlib
 import json
 import math
@@ -149,6 +150,16 @@ def main():
     torch.cuda.synchronize(dev)
 
     lib = _capi.lib()
+    # one untimed step with the work counters on (they add atomics)
+    lib.sdgr_profile_count(1)
+    res = step()
+    torch.cuda.synchronize(dev)
+    lib.sdgr_profile_count(0)
+    work = (ctypes.c_uint64 * 8)()
+    _capi.check(lib.sdgr_read_work(ctypes.byref(res.plan), res.state.data_ptr(), work, 8,
+                                   torch.cuda.current_stream(dev).cuda_stream))
+    work = list(work)
+    del res
     if not args.no_profile:
         _capi.profile_read()
         lib.sdgr_profile_enable(1)
@@ -179,43 +190,75 @@ def main():
         "config": dict(cfg, parallelism="single GPU", pairs_c=plan.pairs_c,
                        pairs_i=plan.pairs_i, tiles_c=plan.tiles_c, tiles_i=plan.tiles_i),
     }
+    out["work"] = {"hits_a_fwd": work[0], "hits_a_bwd": work[1], "hits_b_fwd": work[2],
+                   "hits_b_bwd": work[3], "entries_a_fwd": work[4], "entries_a_bwd": work[5],
+                   "entries_b_fwd": work[6]}
+    out["path_hbm"] = path_hbm(plan, sc.n, views, ms_step)
     if stages:
         per = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}
         out["stages_ms"] = {k: round(v, 4) for k, v in per.items()}
         dom = max(per, key=per.get)
-        out["roofline"] = roofline(dom, per[dom], plan, nv, sc.n)
+        out["roofline"] = roofline(dom, per[dom], work)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, views, args.cpu_rows)
     print(json.dumps(out), flush=True)
 
 
-def roofline(kernel, ms, plan, nv, n):
-    """Roofline entry of the dominant stage: the raster kernels are VALU-bound
-    (footprint and attenuation arithmetic per (cell, Gaussian) pair), the
-    sorts and the projection are HBM-bound."""
-    src = {"raster_a_fwd": "raster.hip", "raster_b_fwd": "raster.hip",
+HIT_KERNELS = {"raster_a_fwd": 0, "raster_a_bwd": 1, "raster_b_fwd": 2, "raster_b_bwd": 3}
+ENTRY_KERNELS = {"raster_a_fwd": 4, "raster_a_bwd": 5, "raster_b_fwd": 6}
+SOURCES = {"raster_a_fwd": "raster.hip", "raster_b_fwd": "raster.hip",
            "raster_b_bwd": "raster.hip", "raster_a_bwd": "raster.hip",
-           "pair_sort": "sort.hip", "depth_sort": "sort.hip",
-           "preprocess": "preprocess.hip", "params_bwd": "preprocess.hip"}.get(kernel)
+           "pair_sort": "sort.hip", "depth_sort": "sort.hip", "bin_pairs": "sort.hip",
+           "preprocess": "preprocess.hip", "plan_query": "preprocess.hip",
+           "params_bwd": "preprocess.hip"}
+
+# Lane-operations the definition needs per footprint hit ((cell, Gaussian)
+# evaluation with q < q_max), each exp weighted 4 (quarter-rate unit):
+#   pass A fwd: quadratic form 8, exp 5, footprint 2, kappa f 1, exp 5,
+#               alpha 1, alpha T 1, A += 1, T *= 1, tau += 1           = 26
+#   pass B fwd: quadratic form 8, exp 5, footprint 2, x I 1, S += 1      = 17
+#   pass B bwd: quadratic form 8, exp 5, footprint 2, dI 2, dq 2,
+#               centre 8, conic 10                                      = 37
+#   pass A bwd: quadratic form 8, exp 5, footprint 2, x 1, exp 5,
+#               tau -= 1, exp 5, dalpha 2, U 3, dx 1, dkappa 2, dq 3,
+#               centre 8, conic 10                                      = 56
+OPS_PER_HIT = {"raster_a_fwd": 26, "raster_b_fwd": 17, "raster_b_bwd": 37,
+               "raster_a_bwd": 56}
+
+
+def roofline(kernel, ms, work):
+    """Roofline object of the dominant stage. The rasterizers are bound by
+    VALU issue (alu); achieved = footprint hits x ops per hit / time."""
+    src = SOURCES.get(kernel)
     traffic = stored_traffic(kernel, 1, source_hash(src)) if src else None
-    if kernel.startswith("raster"):
-        plane_pairs = plan.pairs_c if kernel in ("raster_a_fwd", "raster_a_bwd") else plan.pairs_i
-        ops = VALU_OPS_PER_PAIR[kernel] * plane_pairs * 64
+    if kernel in HIT_KERNELS:
+        hits = work[HIT_KERNELS[kernel]]
+        ops = hits * OPS_PER_HIT[kernel]
         achieved = ops / (ms * 1e-3) / 1e12
-        return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-                "traffic": traffic, "kernel": kernel, "ms": ms,
-                "work": f"{plane_pairs} (tile, Gaussian) pairs x 64 cells x "
-                        f"{VALU_OPS_PER_PAIR[kernel]} ops"}
+        out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+               "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+               "kernel": kernel, "ms": ms,
+               "work": f"{hits} footprint hits x {OPS_PER_HIT[kernel]} lane-ops"}
+        if kernel in ENTRY_KERNELS and hits:
+            out["evaluated_over_hits"] = work[ENTRY_KERNELS[kernel]] * 64 / hits
+        return out
     return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": None, "traffic": traffic, "kernel": kernel, "ms": ms}
 
 
-# Lane-operations the definition needs per (cell, Gaussian) evaluation inside
-# a tile (quadratic form, cutoff test, footprint, attenuation), with each exp
-# weighted 4 (quarter-rate transcendental unit).
-VALU_OPS_PER_PAIR = {"raster_a_fwd": 24, "raster_b_fwd": 14,
-                     "raster_b_bwd": 30, "raster_a_bwd": 40}
+def path_hbm(plan, n, views, ms_step):
+    """Compulsory HBM bytes of one fwd+bwd step of the binned method (per
+    Gaussian: parameters read and gradients written, 96 B; per record: the
+    projected record written once and read in forward and backward plus the
+    per-record reductions, 256 B; per pair: emission, one sort pass, one read
+    in forward and one in backward, 44 B; per pixel and per ray: image and
+    dL/dS, optical depth written and read, 8 B each) against 8 TB/s."""
+    pixels = sum(v.img_w * v.img_h for v in views)
+    rays = plan.rays
+    byts = 96 * n + 256 * plan.records + 44 * (plan.pairs_c + plan.pairs_i) + 8 * pixels + 8 * rays
+    gbs = byts / (ms_step * 1e-3) / 1e9
+    return {"bytes_per_step": byts, "achieved_GBps": gbs, "peak_GBps": HBM_PEAK_GBS,
+            "frac": gbs / HBM_PEAK_GBS}
 
 
 if __name__ == "__main__":

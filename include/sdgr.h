@@ -216,6 +216,18 @@ int sdgr_profile_enable(int32_t on);
 int sdgr_profile_read(double* ms, int64_t* calls, int32_t n);
 const char* sdgr_profile_stage(int32_t i);
 
+/* Work counters. While sdgr_profile_count(1) is in effect, forward and
+ * backward calls count, in `state`, the (cell, Gaussian) evaluations inside
+ * the footprint (q < q_max) of pass A forward, pass A backward, pass B
+ * forward and pass B backward (out[0..3]) and the list entries evaluated by
+ * a whole tile in pass A forward, pass A backward and pass B forward
+ * (out[4..6]); the counting adds atomics, so timed runs leave it off.
+ * sdgr_read_work synchronises `stream` and copies min(n, 8) counters of the
+ * last forward (and backward) that used `state`. */
+int sdgr_profile_count(int32_t on);
+int sdgr_read_work(const sdgr_plan* plan, const void* state, uint64_t* out, int32_t n,
+                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

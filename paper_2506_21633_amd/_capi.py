@@ -20,7 +20,7 @@ EXPORTED = ("sdgr_version", "sdgr_last_error", "sdgr_default_options",
             "sdgr_query_bytes", "sdgr_plan_query", "sdgr_forward",
             "sdgr_backward", "sdgr_status", "sdgr_read_intensity",
             "sdgr_read_optical_depth", "sdgr_profile_enable", "sdgr_profile_read",
-            "sdgr_profile_stage")
+            "sdgr_profile_stage", "sdgr_profile_count", "sdgr_read_work")
 
 
 class Scene(ctypes.Structure):
@@ -103,7 +103,10 @@ def lib():
     L.sdgr_profile_read.argtypes = [P(ctypes.c_double), P(ctypes.c_int64), ctypes.c_int32]
     L.sdgr_profile_stage.argtypes = [ctypes.c_int32]
     L.sdgr_profile_stage.restype = ctypes.c_char_p
-    for name in ("sdgr_profile_enable", "sdgr_profile_read", "sdgr_plan_query", "sdgr_forward", "sdgr_backward", "sdgr_status",
+    L.sdgr_profile_count.argtypes = [ctypes.c_int32]
+    L.sdgr_read_work.argtypes = [P(Plan), vp, P(ctypes.c_uint64), ctypes.c_int32, vp]
+    for name in ("sdgr_profile_count", "sdgr_read_work",
+                 "sdgr_profile_enable", "sdgr_profile_read", "sdgr_plan_query", "sdgr_forward", "sdgr_backward", "sdgr_status",
                  "sdgr_read_intensity", "sdgr_read_optical_depth"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L

@@ -58,6 +58,7 @@ struct Profiler {
     int64_t calls[SG_COUNT] = {};
 };
 Profiler g_prof;
+bool g_count_work = false;   // fill the work counters of the next calls
 
 hipEvent_t take_event()
 {
@@ -109,7 +110,7 @@ struct Problem {
     std::vector<DevScene> scenes;
     RasterParams rp;
     int nv = 0, ns = 0;
-    int64_t records = 0, rays = 0, tiles_c = 0, tiles_i = 0, items = 0;
+    int64_t records = 0, rays = 0, tiles_c = 0, tiles_i = 0, items = 0, pixels = 0;
     int64_t image_floats = 0;
     bool recompute = false;
 };
@@ -167,7 +168,7 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     P.items = items;
 
     P.views.resize(nv);
-    int64_t rec = 0, rays = 0, tc = 0, ti = 0, img = 0;
+    int64_t rec = 0, rays = 0, tc = 0, ti = 0, img = 0, pix = 0;
     for (int v = 0; v < nv; ++v) {
         const sdgr_view& in = views[v];
         std::string tag = "view " + std::to_string(v) + ": ";
@@ -202,6 +203,8 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         d.rec_off = rec;
         d.ray_off = rays;
         d.img_off = in.img_offset;
+        d.pix_off = pix;
+        pix += (int64_t)d.W * d.H;
         d.tile_c = (int32_t)tc;
         rec += P.scenes[in.scene].n;
         rays += (int64_t)d.Wc * d.Hc;
@@ -223,6 +226,7 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     P.tiles_c = tc;
     P.tiles_i = ti;
     P.image_floats = img;
+    P.pixels = pix;
     return SDGR_OK;
 }
 
@@ -240,6 +244,7 @@ struct Bufs {
     float4* iq = nullptr;
     float2* iw = nullptr;
     uint32_t* pval[2] = {nullptr, nullptr};
+    uint64_t* pmask = nullptr;      // footprint cells per computation-plane pair
     uint2* ranges = nullptr;
     // transient: projection counts and sort buffers
     uint2* rect_c = nullptr;
@@ -294,6 +299,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.iw = a.take<float2>(R);
         b.pval[0] = a.take<uint32_t>(K);
         b.pval[1] = a.take<uint32_t>(K);
+        b.pmask = a.take<uint64_t>(cap_c);
         b.ranges = a.take<uint2>(P.tiles_c + P.tiles_i);
     };
     auto transient = [&](Arena& a) {
@@ -324,8 +330,8 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
             geo(sc);
             transient(sc);
         }
-        b.grad_c = sc.take<float>(8 * R);
-        b.grad_i = sc.take<float>(8 * R);
+        b.grad_c = sc.take<float>(6 * R);   // plane-major, see launch_params_backward
+        b.grad_i = sc.take<float>(6 * R);
     }
     if (state_bytes) *state_bytes = st.off;
     if (scratch_bytes) *scratch_bytes = sc.off;
@@ -405,6 +411,8 @@ int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStrea
     StageTimer t(SG_RANGES, s);
     SDGR_HIP(launch_tile_ranges(pk[pw], K, b.status + ST_PAIRS_ALL, P.tiles_c + P.tiles_i,
                                 b.ranges, s));
+    SDGR_HIP(launch_pair_masks(b.views, P.nv, plan->pairs_c, P.rp, b.status, pk[pw], pv[pw],
+                               b.cq, b.cw, b.pmask, s));
     return SDGR_OK;
 }
 
@@ -504,6 +512,7 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     Bufs b;
     layout(P, plan->pairs_c, plan->pairs_i, FWD, (char*)state, (char*)scratch, b, nullptr,
            nullptr);
+    if (g_count_work) P.rp.work = reinterpret_cast<unsigned long long*>(b.status + WORK_WORD);
     if ((rc = upload_tables(P, b, s))) return rc;
     if ((rc = build_lists(P, plan, b, s))) return rc;
     const int pw = final_pair_buffer(P);
@@ -511,15 +520,15 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     {
         StageTimer t(SG_RASTER_A_FWD, s);
         SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, P.rp, b.ranges, b.pval[pw],
-                                     b.cq, b.cw, b.A, b.tau, b.nlast, s));
+                                     b.pmask, b.cq, b.cw, b.A, b.tau, b.nlast, s));
     }
     {
         StageTimer t(SG_INTENSITY, s);
         SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, s));
     }
     StageTimer t(SG_RASTER_B_FWD, s);
-    SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.tiles_c, P.tiles_i, P.rp, b.ranges,
-                                 b.pval[pw], b.iq, b.iw, images, s));
+    SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.pixels, plan->pairs_i, P.rp, b.status,
+                                 b.pkey[pw], b.pval[pw], b.iq, b.iw, images, s));
     return SDGR_OK;
 }
 
@@ -552,6 +561,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     Bufs b;
     layout(P, plan->pairs_c, plan->pairs_i, BWD, (char*)state, (char*)scratch, b, nullptr,
            nullptr);
+    if (g_count_work) P.rp.work = reinterpret_cast<unsigned long long*>(b.status + WORK_WORD);
     if ((rc = upload_tables(P, b, s))) return rc;
     if (P.recompute) {
         // the forward's lists are gone: rebuild them (identical, the sorts
@@ -562,7 +572,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     const int pw = final_pair_buffer(P);
     {
         StageTimer t(SG_ZERO, s);
-        SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_c, 0u, 8 * P.records, s));
+        SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_c, 0u, 6 * P.records, s));
     }
     {
         StageTimer t(SG_RASTER_B_BWD, s);
@@ -572,12 +582,12 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     {
         StageTimer t(SG_RASTER_A_BWD, s);
         SDGR_HIP(launch_raster_a_bwd(b.views, b.scenes, P.nv, P.tiles_c, P.rp, b.ranges,
-                                     b.pval[pw], b.cq, b.cw, b.tau, b.nlast, b.grad_i,
-                                     b.grad_c, s));
+                                     b.pval[pw], b.pmask, b.cq, b.cw, b.tau, b.nlast,
+                                     b.grad_i, b.grad_c, P.records, s));
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,
-                                    b.grad_c, b.grad_i, s));
+                                    b.grad_c, b.grad_i, P.records, s));
     return SDGR_OK;
 }
 
@@ -650,6 +660,26 @@ int sdgr_profile_read(double* ms, int64_t* calls, int32_t n)
         g_prof.calls[i] = 0;
     }
     return SG_COUNT;
+}
+
+int sdgr_profile_count(int32_t on)
+{
+    g_count_work = on != 0;
+    return SDGR_OK;
+}
+
+int sdgr_read_work(const sdgr_plan* plan, const void* state, uint64_t* out, int32_t n,
+                   void* stream)
+{
+    g_last_error.clear();
+    if (!plan || !state || !out || n < 0) return fail(SDGR_EINVAL, "null argument");
+    uint64_t w[8] = {0};
+    hipStream_t s = (hipStream_t)stream;
+    SDGR_HIP(hipMemcpyAsync(w, static_cast<const uint32_t*>(state) + WORK_WORD, sizeof(w),
+                            hipMemcpyDeviceToHost, s));
+    SDGR_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n && i < 8; ++i) out[i] = w[i];
+    return SDGR_OK;
 }
 
 const char* sdgr_profile_stage(int32_t i)

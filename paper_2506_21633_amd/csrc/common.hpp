@@ -22,6 +22,7 @@ struct DevView {
     int64_t rec_off;              // first record (view, Gaussian) of the view
     int64_t img_off;              // float offset of the image
     int64_t ray_off;              // first computation-plane cell
+    int64_t pix_off;              // first pixel in the concatenation of all images
     int32_t W, H, Wc, Hc;
     int32_t txc, tyc, txi, tyi;   // tiles per axis on each plane
     int32_t tile_c, tile_i;       // first bucket id on each plane
@@ -50,7 +51,14 @@ struct RasterParams {
     float tau_max;     // early-termination optical depth (huge = off)
     int32_t shadowing;
     float dilation;
+    // work counters (null = off): [0..3] footprint hits of pass A forward,
+    // pass A backward, pass B forward, pass B backward; [4..6] list entries
+    // evaluated by all 64 lanes in pass A forward, pass A backward, pass B
+    // forward
+    unsigned long long* work;
 };
+
+constexpr int WORK_WORD = 16;   // work counters live at status + 16 (8 x u64)
 
 // Device-side scalars kept at the start of the state buffer.
 enum StatusSlot : int {
@@ -120,11 +128,14 @@ hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, in
                                 int64_t records, const float* A, float2* iw,
                                 hipStream_t s);
 
+// Per-record gradient buffers are plane-major: component k of record r at
+// [k * records + r]; grad_c = (dcx, dcy, da, db, dc, dkappa) on the
+// computation plane, grad_i = (dcx, dcy, da, db, dc, dI) on the imaging plane.
 hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, int nv,
                                   int nscenes, int64_t scene_items,
                                   const RasterParams& rp, const float* A,
                                   const float* grad_c, const float* grad_i,
-                                  hipStream_t s);
+                                  int64_t records, hipStream_t s);
 
 // exclusive scan of n uint32 (n <= 2^31); tmp must hold scan_tmp_words(n)
 size_t scan_tmp_words(int64_t n);
@@ -157,26 +168,27 @@ hipError_t launch_tile_ranges(const uint32_t* keys, int64_t cap, const uint32_t*
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 
+hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const RasterParams& rp,
+                             const uint32_t* status, const uint32_t* pkey,
+                             const uint32_t* pvals, const float4* cq, const float2* cw,
+                             uint64_t* pmask, hipStream_t s);
 hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint2* ranges,
-                               const uint32_t* pvals, const float4* cq, const float2* cw,
-                               float* A, float* tau, uint32_t* nlast, hipStream_t s);
-hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t tiles_c,
-                               int64_t tiles_i, const RasterParams& rp, const uint2* ranges,
-                               const uint32_t* pvals, const float4* iq, const float2* iw,
-                               float* images, hipStream_t s);
-hipError_t launch_raster_b_bwd(const DevView* views, int nv, int64_t tiles_c,
-                               int64_t tiles_i, const RasterParams& rp, const uint2* ranges,
-                               const uint32_t* pvals, const float4* iq, const float2* iw,
-                               const float* dimg, float* grad_i, hipStream_t s);
+                               const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
+                               const float2* cw, float* A, float* tau, uint32_t* nlast,
+                               hipStream_t s);
+hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_i,
+                               const RasterParams& rp, const uint32_t* status,
+                               const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
+                               const float2* iw, float* images, hipStream_t s);
 hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
                             const RasterParams& rp, const float4* iq, const float2* iw,
                             const float* dimg, float* grad_i, hipStream_t s);
 hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
-                               int64_t tiles_c, const RasterParams& rp,
-                               const uint2* ranges, const uint32_t* pvals,
-                               const float4* cq, const float2* cw, const float* tau,
-                               const uint32_t* nlast, const float* grad_i,
-                               float* grad_c, hipStream_t s);
+                               int64_t tiles_c, const RasterParams& rp, const uint2* ranges,
+                               const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
+                               const float2* cw, const float* tau, const uint32_t* nlast,
+                               const float* grad_i, float* grad_c, int64_t stride,
+                               hipStream_t s);
 
 }  // namespace sdgr

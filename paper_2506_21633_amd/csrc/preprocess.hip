@@ -220,7 +220,8 @@ __device__ void plane_adjoint(const double* Q, const float* gq, const double* u,
 __global__ void __launch_bounds__(256)
 k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
                   int nscenes, int64_t items, RasterParams rp, const float* __restrict__ A,
-                  const float* __restrict__ grad_c, const float* __restrict__ grad_i)
+                  const float* __restrict__ grad_c, const float* __restrict__ grad_i,
+                  int64_t records)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= items) return;
@@ -243,8 +244,11 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
         if (!conic(covC, QC) || !conic(covI, QI)) continue;  // no pairs in this view
         any = true;
         int64_t r = V.rec_off + i;
-        const float* gc = grad_c + 8 * r;
-        const float* gi = grad_i + 8 * r;
+        float gc[6], gi[6];
+        for (int k = 0; k < 6; ++k) {
+            gc[k] = grad_c[k * records + r];
+            gi[k] = grad_i[k * records + r];
+        }
         plane_adjoint(QC, gc, V.ex, V.ey, V.dAc, V.dEc, dS, dmu);
         plane_adjoint(QI, gi, V.ex, V.ez, V.dA, V.dR, dS, dmu);
         dk += gc[5];
@@ -323,11 +327,12 @@ hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, in
 hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, int nv,
                                   int nscenes, int64_t scene_items, const RasterParams& rp,
                                   const float* A, const float* grad_c, const float* grad_i,
-                                  hipStream_t s)
+                                  int64_t records, hipStream_t s)
 {
     if (scene_items <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_params_backward, dim3(blocks_for(scene_items, 256)), dim3(256), 0, s,
-                       views, scenes, nv, nscenes, scene_items, rp, A, grad_c, grad_i);
+                       views, scenes, nv, nscenes, scene_items, rp, A, grad_c, grad_i,
+                       records);
     return hipGetLastError();
 }
 

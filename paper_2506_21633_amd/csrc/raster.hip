@@ -1,31 +1,33 @@
-// Tile rasterizers of the SAR Gaussian splatting renderer (paper Sec. II-A,
+// Rasterizers of the SAR Gaussian splatting renderer (paper Sec. II-A,
 // scattering intensity and imaging; Sec. II-B, their gradients).
 //
-// One wave64 owns one 8x8 tile: lane l handles ray / pixel (l % 8, l / 8).
-// The tile's Gaussian list is walked in batches of 64: each lane stages one
-// record into LDS, then all lanes sweep the batch reading it back as a
-// broadcast. Waves of a workgroup are independent (different tiles); no
-// workgroup barrier is used, so a wave may leave early.
-//
-//   pass A forward : per ray, front to back, alpha = 1 - exp(-kappa f),
-//                    A_i += alpha * T, T *= exp(-kappa f); the per-Gaussian
-//                    sum over the wave's rays is one DPP reduction and one
-//                    float atomic per (tile, Gaussian).
-//   pass B forward : per pixel, S = sum_i f_i I_i (order-free, no atomics).
-//   pass B backward: per record (k_image_bwd): dL/dI and the gradients of the
-//                    imaging-plane centre and conic gathered over the
-//                    footprint, no atomics. (k_raster_b_bwd is the tile form:
-//                    per pixel, reduced over the wave, 6 atomics per
-//                    (tile, Gaussian).)
-//   pass A backward: per ray, back to front from the last contributing
-//                    entry: tau -= kappa f, T = exp(-tau),
-//                    dL/dalpha = T (c - U), U <- c alpha + (1 - alpha) U
-//                    (division-free), with c = P dL/dI; gradients of kappa
-//                    and the computation-plane centre and conic.
+// Computation plane (order matters: front-to-back along each ray)
+//   One wave64 owns one 8x8 tile: lane l handles ray (l % 8, l / 8). Every
+//   (tile, Gaussian) pair carries a 64-bit mask of the tile cells inside the
+//   footprint ellipse (k_pair_masks). The tile's depth-sorted list is walked
+//   in batches of 64 entries: the masks are read coalesced, entries whose mask
+//   misses every ray still in play are dropped, and only the survivors are
+//   gathered into LDS (in order) and swept by all lanes as a broadcast.
+//   pass A forward : alpha = 1 - exp(-kappa f), A_i += alpha T, T *= exp(-kappa f);
+//                    per-Gaussian sums over the wave's rays by DPP reduction,
+//                    one float atomic per (tile, Gaussian); a ray leaves after
+//                    its optical depth reaches tau_max.
+//   pass A backward: back to front from each ray's last contributing entry:
+//                    tau -= kappa f, T = exp(-tau), dL/dalpha = T (c - U),
+//                    U <- c alpha + (1 - alpha) U (division-free), c = P dL/dI.
+// Imaging plane (order-free additive layover)
+//   pass B forward : fixed 2048-entry segments of the sorted (tile, Gaussian)
+//                    pair array, one wave each (balanced however long a
+//                    tile's list is); lane = pixel; partial pixel sums are
+//                    added to the image at tile boundaries.
+//   pass B backward: one thread per record walks its footprint ellipse and
+//                    gathers dL/dS (no atomics).
 #include "common.hpp"
 
 namespace sdgr {
 namespace {
+
+constexpr uint32_t B_SEGMENT = 2048;   // pair entries per pass-B forward wave
 
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -41,27 +43,38 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
     return v;
 }
 
-// Tile coordinates of a bucket: view, the lane's cell, and whether it lies
-// inside the grid.
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
 struct TileCell {
     int v;
+    int tx, ty;
     int col, row;
     bool inside;
 };
 
-template <class OffF>
+// Tile coordinates of a bucket id (computation-plane ids first, then
+// imaging-plane ids), and this lane's cell.
 __device__ __forceinline__ TileCell tile_cell(const DevView* views, int nv, int64_t bucket,
-                                              OffF off, bool comp_plane)
+                                              bool comp_plane)
 {
     TileCell t;
-    t.v = find_view(nv, bucket, off);
+    if (comp_plane)
+        t.v = find_view(nv, bucket, [&](int k) { return (int64_t)views[k].tile_c; });
+    else
+        t.v = find_view(nv, bucket, [&](int k) { return (int64_t)views[k].tile_i; });
     const DevView& V = views[t.v];
     const int64_t local = bucket - (comp_plane ? V.tile_c : V.tile_i);
     const int tx_n = comp_plane ? V.txc : V.txi;
-    const int tx = (int)(local % tx_n), ty = (int)(local / tx_n);
+    t.tx = (int)(local % tx_n);
+    t.ty = (int)(local / tx_n);
     const int lane = lane_id();
-    t.col = tx * TILE + (lane & (TILE - 1));
-    t.row = ty * TILE + (lane / TILE);
+    t.col = t.tx * TILE + (lane & (TILE - 1));
+    t.row = t.ty * TILE + (lane / TILE);
     t.inside = comp_plane ? (t.col < V.Wc && t.row < V.Hc) : (t.col < V.W && t.row < V.H);
     return t;
 }
@@ -71,43 +84,107 @@ __device__ __forceinline__ float quadform(float4 g, float c, float dx, float dy)
     return g.z * dx * dx + 2.0f * g.w * dx * dy + c * dy * dy;
 }
 
+// Cells of tile (tx, ty) inside the ellipse q < q_max of a Gaussian with
+// centre (cx, cy) and conic (a, b, c): per row the exact column span from
+// the quadratic, widened by a small slack. Bit 8 * row + col.
+__device__ uint64_t footprint_mask(float cx, float cy, float a, float b, float c, float qm,
+                                   int tx, int ty)
+{
+    const float det = a * c - b * b;
+    if (!(det > 0.0f) || !(a > 0.0f)) return 0ull;
+    const float slack = 1e-3f;
+    uint64_t m = 0ull;
+    const float x0 = (float)(tx * TILE);
+#pragma unroll
+    for (int k = 0; k < TILE; ++k) {
+        const float dy = (float)(ty * TILE + k) + 0.5f - cy;
+        const float D = a * qm - det * dy * dy;
+        if (D < 0.0f) continue;
+        const float half = sqrtf(D) / a + slack;
+        const float xc = cx - b * dy / a;
+        // local columns j with |x0 + j + 1/2 - xc| <= half
+        const float lo = fmaxf(ceilf(xc - half - 0.5f - x0), 0.0f);
+        const float hi = fminf(floorf(xc + half - 0.5f - x0), (float)(TILE - 1));
+        if (lo > hi) continue;
+        const uint32_t j0 = (uint32_t)lo, j1 = (uint32_t)hi;
+        const uint64_t row_bits = ((1ull << (j1 - j0 + 1)) - 1ull) << j0;
+        m |= row_bits << (TILE * k);
+    }
+    return m;
+}
+
+__global__ void __launch_bounds__(256)
+k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParams rp,
+             const uint32_t* __restrict__ status, const uint32_t* __restrict__ pkey,
+             const uint32_t* __restrict__ pvals, const float4* __restrict__ cq,
+             const float2* __restrict__ cw, uint64_t* __restrict__ pmask)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= cap || p >= (int64_t)status[ST_PAIRS_C]) return;
+    const uint32_t bucket = pkey[p];
+    const int v = find_view(nv, (int64_t)bucket, [&](int k) { return (int64_t)views[k].tile_c; });
+    const DevView& V = views[v];
+    const int local = (int)(bucket - (uint32_t)V.tile_c);
+    const uint32_t r = pvals[p];
+    const float4 g = cq[r];
+    const float2 g2 = cw[r];
+    pmask[p] = footprint_mask(g.x, g.y, g.z, g.w, g2.x, rp.q_max, local % V.txc, local / V.txc);
+}
+
 __global__ void __launch_bounds__(RASTER_THREADS)
 k_raster_a_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, RasterParams rp,
                const uint2* __restrict__ ranges, const uint32_t* __restrict__ pvals,
-               const float4* __restrict__ cq, const float2* __restrict__ cw,
-               float* __restrict__ A, float* __restrict__ tau, uint32_t* __restrict__ nlast)
+               const uint64_t* __restrict__ pmask, const float4* __restrict__ cq,
+               const float2* __restrict__ cw, float* __restrict__ A, float* __restrict__ tau,
+               uint32_t* __restrict__ nlast)
 {
     __shared__ float4 s_q[RASTER_WAVES][WAVE];
     __shared__ float2 s_w[RASTER_WAVES][WAVE];
+    __shared__ uint64_t s_m[RASTER_WAVES][WAVE];
     __shared__ uint32_t s_r[RASTER_WAVES][WAVE];
+    __shared__ uint32_t s_e[RASTER_WAVES][WAVE];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int64_t bucket = (int64_t)blockIdx.x * RASTER_WAVES + w;
     if (bucket >= tiles_c) return;
-    const TileCell tc = tile_cell(views, nv, bucket,
-                                  [&](int k) { return (int64_t)views[k].tile_c; }, true);
+    const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
     const float px = tc.col + 0.5f, py = tc.row + 0.5f;
     const uint2 rg = ranges[bucket];
     float T = 1.0f, t = 0.0f;
     bool alive = tc.inside;
     uint32_t last = 0;
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += WAVE) {
-        if (__ballot(alive) == 0) break;
-        const uint32_t cnt = min((uint32_t)WAVE, rg.y - b0);
-        if (lane < cnt) {
-            const uint32_t r = pvals[b0 + lane];
-            s_q[w][lane] = cq[r];
-            s_w[w][lane] = cw[r];
-            s_r[w][lane] = r;
+    uint64_t live = __ballot(alive);
+    for (uint32_t b0 = rg.x; b0 < rg.y && live != 0ull; b0 += WAVE) {
+        const uint32_t e = b0 + lane;
+        const uint64_t m = e < rg.y ? pmask[e] : 0ull;
+        const bool need = (m & live) != 0ull;
+        const uint64_t nb = __ballot(need);
+        if (nb == 0ull) continue;
+        if (need) {
+            const uint32_t slot = lanes_below(nb);
+            const uint32_t r = pvals[e];
+            s_q[w][slot] = cq[r];
+            s_w[w][slot] = cw[r];
+            s_m[w][slot] = m;
+            s_r[w][slot] = r;
+            s_e[w][slot] = e - rg.x;
         }
         wave_lds_sync();
+        const uint32_t cnt = (uint32_t)__popcll(nb);
         for (uint32_t j = 0; j < cnt; ++j) {
+            const uint64_t mj = s_m[w][j];
+            if ((mj & live) == 0ull) continue;
             const float4 g = s_q[w][j];
             const float2 g2 = s_w[w][j];
             const float dx = px - g.x, dy = py - g.y;
             const float q = quadform(g, g2.x, dx, dy);
-            const bool hit = alive && q < rp.q_max;
-            if (__ballot(hit) == 0) continue;
+            const bool hit = alive && ((mj >> lane) & 1ull) && q < rp.q_max;
+            const uint64_t hb = __ballot(hit);
+            if (rp.work && lane == 0) {
+                atomicAdd(&rp.work[4], 1ull);
+                atomicAdd(&rp.work[0], (unsigned long long)__popcll(hb));
+            }
+            if (hb == 0ull) continue;
             float contrib = 0.0f, x = 0.0f, E = 1.0f;
             if (hit) {
                 const float f = (__expf(-0.5f * q) - rp.eps) * rp.inv1meps;
@@ -120,9 +197,10 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, Raste
             if (hit) {
                 if (rp.shadowing) T *= E;
                 t += x;
-                last = b0 - rg.x + j + 1;
+                last = s_e[w][j] + 1;
                 if (rp.shadowing && t >= rp.tau_max) alive = false;
             }
+            live = __ballot(alive);
         }
         wave_lds_sync();
     }
@@ -133,110 +211,85 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, Raste
     }
 }
 
+// Zero every view's image before the segmented accumulation.
+__global__ void __launch_bounds__(256)
+k_zero_images(const DevView* __restrict__ views, int nv, int64_t pixels, float* __restrict__ images)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= pixels) return;
+    const int v = find_view(nv, p, [&](int k) { return views[k].pix_off; });
+    images[views[v].img_off + (p - views[v].pix_off)] = 0.0f;
+}
+
 __global__ void __launch_bounds__(RASTER_THREADS)
-k_raster_b_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, int64_t tiles_i,
-               RasterParams rp, const uint2* __restrict__ ranges,
+k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
+               const uint32_t* __restrict__ status, const uint32_t* __restrict__ pkey,
                const uint32_t* __restrict__ pvals, const float4* __restrict__ iq,
                const float2* __restrict__ iw, float* __restrict__ images)
 {
     __shared__ float4 s_q[RASTER_WAVES][WAVE];
     __shared__ float2 s_w[RASTER_WAVES][WAVE];
+    __shared__ uint32_t s_k[RASTER_WAVES][WAVE];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int64_t local = (int64_t)blockIdx.x * RASTER_WAVES + w;
-    if (local >= tiles_i) return;
-    const int64_t bucket = tiles_c + local;
-    const TileCell tc = tile_cell(views, nv, bucket,
-                                  [&](int k) { return (int64_t)views[k].tile_i; }, false);
-    const DevView& V = views[tc.v];
-    const float px = tc.col + 0.5f, py = tc.row + 0.5f;
-    const uint2 rg = ranges[bucket];
-    float acc = 0.0f;
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += WAVE) {
-        const uint32_t cnt = min((uint32_t)WAVE, rg.y - b0);
+    const uint32_t kc = status[ST_PAIRS_C], ki = status[ST_PAIRS_I];
+    const uint64_t seg = (uint64_t)blockIdx.x * RASTER_WAVES + w;
+    const uint64_t p0 = (uint64_t)kc + seg * B_SEGMENT;
+    const uint64_t pend = (uint64_t)kc + ki;
+    if (p0 >= pend) return;
+    const uint32_t p1 = (uint32_t)min(pend, p0 + B_SEGMENT);
+    uint32_t cur = 0xFFFFFFFFu;
+    float acc = 0.0f, px = 0.0f, py = 0.0f;
+    int64_t pix = -1;
+    for (uint32_t b0 = (uint32_t)p0; b0 < p1; b0 += WAVE) {
+        const uint32_t cnt = min((uint32_t)WAVE, p1 - b0);
         if (lane < cnt) {
             const uint32_t r = pvals[b0 + lane];
             s_q[w][lane] = iq[r];
             s_w[w][lane] = iw[r];
+            s_k[w][lane] = pkey[b0 + lane];
         }
         wave_lds_sync();
         for (uint32_t j = 0; j < cnt; ++j) {
+            const uint32_t k = s_k[w][j];
+            if (k != cur) {   // tile boundary: flush the partial sums
+                if (pix >= 0) unsafeAtomicAdd(&images[pix], acc);
+                const TileCell tc = tile_cell(views, nv, (int64_t)k, false);
+                const DevView& V = views[tc.v];
+                px = tc.col + 0.5f;
+                py = tc.row + 0.5f;
+                pix = tc.inside ? V.img_off + (int64_t)tc.row * V.W + tc.col : -1;
+                acc = 0.0f;
+                cur = k;
+            }
             const float4 g = s_q[w][j];
             const float2 g2 = s_w[w][j];
             const float dx = px - g.x, dy = py - g.y;
             const float q = quadform(g, g2.x, dx, dy);
             if (q < rp.q_max) acc += (__expf(-0.5f * q) - rp.eps) * rp.inv1meps * g2.y;
+            if (rp.work) {
+                const uint64_t hb = __ballot(q < rp.q_max && pix >= 0);
+                if (lane == 0) {
+                    atomicAdd(&rp.work[6], 1ull);
+                    atomicAdd(&rp.work[2], (unsigned long long)__popcll(hb));
+                }
+            }
         }
         wave_lds_sync();
     }
-    if (tc.inside) images[V.img_off + (int64_t)tc.row * V.W + tc.col] = acc;
+    if (pix >= 0) unsafeAtomicAdd(&images[pix], acc);
 }
 
-// Lanes 0..5 add the six wave sums to consecutive floats at dst.
-__device__ __forceinline__ void atomic_add6(float* dst, float a0, float a1, float a2, float a3,
-                                            float a4, float a5)
+// Lanes 0..5 add the six wave sums to component k of record r in a
+// plane-major gradient buffer (component k at dst[k * stride + r]), so the six
+// atomics land in six different cache lines.
+__device__ __forceinline__ void atomic_add6(float* dst, int64_t stride, int64_t r, float a0,
+                                            float a1, float a2, float a3, float a4, float a5)
 {
     const int lane = lane_id();
     if (lane < 6) {
         float v = lane == 0 ? a0 : lane == 1 ? a1 : lane == 2 ? a2 : lane == 3 ? a3
                 : lane == 4 ? a4 : a5;
-        unsafeAtomicAdd(dst + lane, v);
-    }
-}
-
-__global__ void __launch_bounds__(RASTER_THREADS)
-k_raster_b_bwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, int64_t tiles_i,
-               RasterParams rp, const uint2* __restrict__ ranges,
-               const uint32_t* __restrict__ pvals, const float4* __restrict__ iq,
-               const float2* __restrict__ iw, const float* __restrict__ dimg,
-               float* __restrict__ grad_i)
-{
-    __shared__ float4 s_q[RASTER_WAVES][WAVE];
-    __shared__ float2 s_w[RASTER_WAVES][WAVE];
-    __shared__ uint32_t s_r[RASTER_WAVES][WAVE];
-    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int64_t local = (int64_t)blockIdx.x * RASTER_WAVES + w;
-    if (local >= tiles_i) return;
-    const int64_t bucket = tiles_c + local;
-    const TileCell tc = tile_cell(views, nv, bucket,
-                                  [&](int k) { return (int64_t)views[k].tile_i; }, false);
-    const DevView& V = views[tc.v];
-    const float px = tc.col + 0.5f, py = tc.row + 0.5f;
-    const uint2 rg = ranges[bucket];
-    const float G = tc.inside ? dimg[V.img_off + (int64_t)tc.row * V.W + tc.col] : 0.0f;
-    const bool live = tc.inside && G != 0.0f;
-    if (__ballot(live) == 0) return;
-    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += WAVE) {
-        const uint32_t cnt = min((uint32_t)WAVE, rg.y - b0);
-        if (lane < cnt) {
-            const uint32_t r = pvals[b0 + lane];
-            s_q[w][lane] = iq[r];
-            s_w[w][lane] = iw[r];
-            s_r[w][lane] = r;
-        }
-        wave_lds_sync();
-        for (uint32_t j = 0; j < cnt; ++j) {
-            const float4 g = s_q[w][j];
-            const float2 g2 = s_w[w][j];
-            const float dx = px - g.x, dy = py - g.y;
-            const float q = quadform(g, g2.x, dx, dy);
-            const bool hit = live && q < rp.q_max;
-            if (__ballot(hit) == 0) continue;
-            float dI = 0.f, dcx = 0.f, dcy = 0.f, da = 0.f, db = 0.f, dc = 0.f;
-            if (hit) {
-                const float e = __expf(-0.5f * q);
-                dI = G * (e - rp.eps) * rp.inv1meps;
-                const float dq = G * g2.y * (-0.5f * e * rp.inv1meps);
-                dcx = -2.0f * dq * (g.z * dx + g.w * dy);
-                dcy = -2.0f * dq * (g.w * dx + g2.x * dy);
-                da = dq * dx * dx;
-                db = 2.0f * dq * dx * dy;
-                dc = dq * dy * dy;
-            }
-            const float s0 = wave_sum(dcx), s1 = wave_sum(dcy), s2 = wave_sum(da);
-            const float s3 = wave_sum(db), s4 = wave_sum(dc), s5 = wave_sum(dI);
-            atomic_add6(grad_i + 8 * (int64_t)s_r[w][j], s0, s1, s2, s3, s4, s5);
-        }
-        wave_lds_sync();
+        unsafeAtomicAdd(dst + lane * stride + r, v);
     }
 }
 
@@ -259,6 +312,7 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
     const float a = g.z, b = g.w, c = g2.x, I = g2.y;
     const float det = a * c - b * b;
     float dI = 0.f, dcx = 0.f, dcy = 0.f, da = 0.f, db = 0.f, dc = 0.f;
+    unsigned long long hits = 0;
     if (det > 0.0f && a > 0.0f) {
         const float qm = rp.q_max;
         const float ry = sqrtf(qm * a / det);
@@ -278,6 +332,7 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
                 const float dx = col + 0.5f - g.x;
                 const float q = quadform(g, c, dx, dy);
                 if (!(q < qm)) continue;
+                ++hits;
                 const float Gp = G[(int64_t)row * V.W + col];
                 const float e = __expf(-0.5f * q);
                 dI += Gp * (e - rp.eps) * rp.inv1meps;
@@ -290,28 +345,33 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
             }
         }
     }
-    float4* o = reinterpret_cast<float4*>(grad_i + 8 * r);
-    o[0] = make_float4(dcx, dcy, da, db);
-    o[1] = make_float4(dc, dI, 0.0f, 0.0f);
+    if (rp.work && hits) atomicAdd(&rp.work[3], hits);
+    grad_i[r] = dcx;
+    grad_i[records + r] = dcy;
+    grad_i[2 * records + r] = da;
+    grad_i[3 * records + r] = db;
+    grad_i[4 * records + r] = dc;
+    grad_i[5 * records + r] = dI;
 }
 
 __global__ void __launch_bounds__(RASTER_THREADS)
 k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
                int64_t tiles_c, RasterParams rp, const uint2* __restrict__ ranges,
-               const uint32_t* __restrict__ pvals, const float4* __restrict__ cq,
-               const float2* __restrict__ cw, const float* __restrict__ tau,
-               const uint32_t* __restrict__ nlast, const float* __restrict__ grad_i,
-               float* __restrict__ grad_c)
+               const uint32_t* __restrict__ pvals, const uint64_t* __restrict__ pmask,
+               const float4* __restrict__ cq, const float2* __restrict__ cw,
+               const float* __restrict__ tau, const uint32_t* __restrict__ nlast,
+               const float* __restrict__ grad_i, float* __restrict__ grad_c, int64_t stride)
 {
     __shared__ float4 s_q[RASTER_WAVES][WAVE];
     __shared__ float2 s_w[RASTER_WAVES][WAVE];
+    __shared__ uint64_t s_m[RASTER_WAVES][WAVE];
     __shared__ float s_c[RASTER_WAVES][WAVE];
     __shared__ uint32_t s_r[RASTER_WAVES][WAVE];
+    __shared__ uint32_t s_e[RASTER_WAVES][WAVE];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int64_t bucket = (int64_t)blockIdx.x * RASTER_WAVES + w;
     if (bucket >= tiles_c) return;
-    const TileCell tc = tile_cell(views, nv, bucket,
-                                  [&](int k) { return (int64_t)views[k].tile_c; }, true);
+    const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
     const float* amp = scenes[V.scene].amp;
     const float px = tc.col + 0.5f, py = tc.row + 0.5f;
@@ -324,23 +384,39 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
     // batches back to front over list entries [0, n_max)
     for (int64_t be = n_max; be > 0; be -= WAVE) {
         const uint32_t bs = (uint32_t)max((int64_t)0, be - WAVE);
-        const uint32_t cnt = (uint32_t)be - bs;
-        if (lane < cnt) {
-            const uint32_t r = pvals[rg.x + bs + lane];
-            s_q[w][lane] = cq[r];
-            s_w[w][lane] = cw[r];
-            s_c[w][lane] = amp[r - V.rec_off] * grad_i[8 * (int64_t)r + 5];
-            s_r[w][lane] = r;
+        const uint32_t e = bs + lane;
+        // rays that processed some entry >= bs in the forward
+        const uint64_t live = __ballot(n_mine > bs);
+        const uint64_t m = e < (uint32_t)be ? pmask[rg.x + e] : 0ull;
+        const bool need = (m & live) != 0ull;
+        const uint64_t nb = __ballot(need);
+        if (nb == 0ull) continue;
+        if (need) {
+            const uint32_t slot = lanes_below(nb);
+            const uint32_t r = pvals[rg.x + e];
+            s_q[w][slot] = cq[r];
+            s_w[w][slot] = cw[r];
+            s_m[w][slot] = m;
+            s_c[w][slot] = amp[r - V.rec_off] * grad_i[5 * stride + r];
+            s_r[w][slot] = r;
+            s_e[w][slot] = e;
         }
         wave_lds_sync();
-        for (int j = (int)cnt - 1; j >= 0; --j) {
-            const uint32_t e = bs + (uint32_t)j;
+        const int cnt = __popcll(nb);
+        for (int j = cnt - 1; j >= 0; --j) {
+            const uint32_t ej = s_e[w][j];
+            const uint64_t mj = s_m[w][j];
             const float4 g = s_q[w][j];
             const float2 g2 = s_w[w][j];
             const float dx = px - g.x, dy = py - g.y;
             const float q = quadform(g, g2.x, dx, dy);
-            const bool hit = e < n_mine && q < rp.q_max;
-            if (__ballot(hit) == 0) continue;
+            const bool hit = ej < n_mine && ((mj >> lane) & 1ull) && q < rp.q_max;
+            const uint64_t hb = __ballot(hit);
+            if (rp.work && lane == 0) {
+                atomicAdd(&rp.work[5], 1ull);
+                atomicAdd(&rp.work[1], (unsigned long long)__popcll(hb));
+            }
+            if (hb == 0ull) continue;
             float dcx = 0.f, dcy = 0.f, da = 0.f, db = 0.f, dc = 0.f, dk = 0.f;
             if (hit) {
                 const float ex = __expf(-0.5f * q);
@@ -369,49 +445,56 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
             }
             const float s0 = wave_sum(dcx), s1 = wave_sum(dcy), s2 = wave_sum(da);
             const float s3 = wave_sum(db), s4 = wave_sum(dc), s5 = wave_sum(dk);
-            atomic_add6(grad_c + 8 * (int64_t)s_r[w][j], s0, s1, s2, s3, s4, s5);
+            atomic_add6(grad_c, stride, s_r[w][j], s0, s1, s2, s3, s4, s5);
         }
         wave_lds_sync();
     }
 }
 
-inline unsigned raster_grid(int64_t tiles)
+inline unsigned raster_grid(int64_t waves)
 {
-    return (unsigned)((tiles + RASTER_WAVES - 1) / RASTER_WAVES);
+    return (unsigned)((waves + RASTER_WAVES - 1) / RASTER_WAVES);
 }
+
+inline unsigned grid256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const RasterParams& rp,
+                             const uint32_t* status, const uint32_t* pkey,
+                             const uint32_t* pvals, const float4* cq, const float2* cw,
+                             uint64_t* pmask, hipStream_t s)
+{
+    if (cap_c <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pair_masks, dim3(grid256(cap_c)), dim3(256), 0, s, views, nv, cap_c, rp,
+                       status, pkey, pvals, cq, cw, pmask);
+    return hipGetLastError();
+}
+
 hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint2* ranges,
-                               const uint32_t* pvals, const float4* cq, const float2* cw,
-                               float* A, float* tau, uint32_t* nlast, hipStream_t s)
+                               const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
+                               const float2* cw, float* A, float* tau, uint32_t* nlast,
+                               hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_raster_a_fwd, dim3(raster_grid(tiles_c)), dim3(RASTER_THREADS), 0, s,
-                       views, nv, tiles_c, rp, ranges, pvals, cq, cw, A, tau, nlast);
+                       views, nv, tiles_c, rp, ranges, pvals, pmask, cq, cw, A, tau, nlast);
     return hipGetLastError();
 }
 
-hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t tiles_c, int64_t tiles_i,
-                               const RasterParams& rp, const uint2* ranges,
-                               const uint32_t* pvals, const float4* iq, const float2* iw,
-                               float* images, hipStream_t s)
+hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_i,
+                               const RasterParams& rp, const uint32_t* status,
+                               const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
+                               const float2* iw, float* images, hipStream_t s)
 {
-    if (tiles_i <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_b_fwd, dim3(raster_grid(tiles_i)), dim3(RASTER_THREADS), 0, s,
-                       views, nv, tiles_c, tiles_i, rp, ranges, pvals, iq, iw, images);
-    return hipGetLastError();
-}
-
-hipError_t launch_raster_b_bwd(const DevView* views, int nv, int64_t tiles_c, int64_t tiles_i,
-                               const RasterParams& rp, const uint2* ranges,
-                               const uint32_t* pvals, const float4* iq, const float2* iw,
-                               const float* dimg, float* grad_i, hipStream_t s)
-{
-    if (tiles_i <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_b_bwd, dim3(raster_grid(tiles_i)), dim3(RASTER_THREADS), 0, s,
-                       views, nv, tiles_c, tiles_i, rp, ranges, pvals, iq, iw, dimg, grad_i);
+    if (pixels <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_images, dim3(grid256(pixels)), dim3(256), 0, s, views, nv, pixels,
+                       images);
+    if (cap_i <= 0) return hipGetLastError();
+    const int64_t segs = (cap_i + B_SEGMENT - 1) / B_SEGMENT;
+    hipLaunchKernelGGL(k_raster_b_fwd, dim3(raster_grid(segs)), dim3(RASTER_THREADS), 0, s, views,
+                       nv, rp, status, pkey, pvals, iq, iw, images);
     return hipGetLastError();
 }
 
@@ -420,21 +503,22 @@ hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
                             const float* dimg, float* grad_i, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_image_bwd, dim3((unsigned)((records + 255) / 256)), dim3(256), 0, s,
-                       views, nv, records, rp, iq, iw, dimg, grad_i);
+    hipLaunchKernelGGL(k_image_bwd, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
+                       rp, iq, iw, dimg, grad_i);
     return hipGetLastError();
 }
 
 hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
                                int64_t tiles_c, const RasterParams& rp, const uint2* ranges,
-                               const uint32_t* pvals, const float4* cq, const float2* cw,
-                               const float* tau, const uint32_t* nlast, const float* grad_i,
-                               float* grad_c, hipStream_t s)
+                               const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
+                               const float2* cw, const float* tau, const uint32_t* nlast,
+                               const float* grad_i, float* grad_c, int64_t stride,
+                               hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_raster_a_bwd, dim3(raster_grid(tiles_c)), dim3(RASTER_THREADS), 0, s,
-                       views, scenes, nv, tiles_c, rp, ranges, pvals, cq, cw, tau, nlast,
-                       grad_i, grad_c);
+                       views, scenes, nv, tiles_c, rp, ranges, pvals, pmask, cq, cw, tau, nlast,
+                       grad_i, grad_c, stride);
     return hipGetLastError();
 }
 
