@@ -6,8 +6,10 @@ boxes and cylinders inside a 6 x 3 x 2.5 m envelope, 72 views (azimuth 0-355
 deg in 5 deg steps, incidence alternating 30/45 deg), 256 x 256 images at
 0.1 m. One step = plan (pair counts) + forward of all 72 views + L1-loss
 cotangent against a target rendered from a copy with means jittered by
-N(0, 0.1 m) + backward to all Gaussian parameters, everything resident in
-HBM. Prints one JSON line.
+N(0, 0.1 m) + backward to all Gaussian parameters + the overflow check,
+everything resident in HBM. Pair capacities come from an exact count taken
+before the timed region plus 10 % headroom (an overflow would re-count and
+redo the step). Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -45,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-stage HIP event timing")
+    ap.add_argument("--serving-requests", type=int, default=160,
+                    help="requests of the served-vs-plain stream (0 skips it)")
     return ap.parse_args()
 
 
@@ -116,6 +120,69 @@ def cpu_baseline(sc, views, rows):
                       f"scaled x{v.img_h / rows:g} to one image"}
 
 
+def serving_bench(dev, n_requests, seed=404):
+    """Served (continuous batching, 2 launch slots, HBM-budget admission) vs
+    plain (one request per launch, FIFO) on the same Poisson arrival stream
+    over 8 resident scenes of 1e4-5e5 Gaussians. Requests: 1-16 views of
+    64^2-512^2 at 0.1 m, azimuth U[0, 360), incidence 30 or 45 deg; half ask
+    for the L1 gradient against a zero target as well. The arrival rate is
+    80 % of the plain form's measured capacity."""
+    import numpy as np
+    import torch
+    from paper_2506_21633_amd import api, scenes
+    from paper_2506_21633_amd.serve import GpuExecutor, Request, Server, percentile
+    sc = scenes.serving_scenes(seed)
+    resident = {f"s{k}": api.GaussianTensors.from_numpy(x, dev) for k, x in enumerate(sc)}
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(n_requests):
+        sid = f"s{int(rng.integers(0, len(sc)))}"
+        size = int(rng.choice([64, 128, 256, 512]))
+        vs = [scenes.View.from_degrees(float(rng.uniform(0, 360)), float(rng.choice([30.0, 45.0])),
+                                       size, 0.1) for _ in range(int(rng.integers(1, 17)))]
+        want = bool(rng.integers(0, 2))
+        tgt = torch.zeros(size * size * len(vs), device=dev) if want else None
+        reqs.append((sid, vs, want, tgt))
+
+    def run(batching, rate):
+        ex = GpuExecutor(resident, dev)
+        srv = Server(ex, hbm_budget=96 << 30, max_views=96, slots=2, batching=batching)
+        arrivals = np.cumsum(np.random.default_rng(seed + 1).exponential(1.0 / rate, len(reqs)))
+        t0 = time.perf_counter()
+        futs = []
+        for a, (sid, vs, want, tgt) in zip(arrivals, reqs):
+            while time.perf_counter() - t0 < a:
+                time.sleep(2e-4)
+            futs.append(srv.submit(Request(sid, vs, want, tgt)))
+        lat = [f.result(600).latency_s for f in futs]
+        dt = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        images = sum(len(r[1]) for r in reqs)
+        return {"p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
+                "images_per_s": images / dt, "requests": len(reqs),
+                "mean_batch_requests": st["mean_batch_requests"]}
+
+    # capacity of the plain form: back-to-back requests
+    ex = GpuExecutor(resident, dev)
+    warm = Server(ex, hbm_budget=96 << 30, batching=False)
+    for sid, vs, want, tgt in reqs[:4]:
+        warm.submit(Request(sid, vs, want, tgt)).result(600)
+    t0 = time.perf_counter()
+    k = min(24, len(reqs))
+    futs = [warm.submit(Request(sid, vs, want, tgt)) for sid, vs, want, tgt in reqs[:k]]
+    for f in futs:
+        f.result(600)
+    service = (time.perf_counter() - t0) / k
+    warm.close()
+    rate = 0.8 / service
+    served = run(True, rate)
+    plain = run(False, rate)
+    return {"qps": rate, "served": served, "plain": plain,
+            "workload": "8 resident vehicle scenes (1e4-5e5 Gaussians), Poisson arrivals, "
+                        "1-16 views of 64^2-512^2, half with L1 gradient"}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -137,10 +204,19 @@ def main():
     numel = float(target_images.numel())
 
     def step():
-        res = r.forward(r.plan())
-        G = torch.sign(res.images - target_images) / numel
-        r.backward(res, G)
-        return res
+        # pair capacities from the last exact count plus 10 % headroom; the
+        # status check at the end of the step catches an overflow
+        while True:
+            res = r.forward(r.planned(0.1))
+            G = torch.sign(res.images - target_images) / numel
+            r.backward(res, G)
+            try:
+                r.status(res)
+                return res
+            except _capi.SDGRError as exc:
+                if exc.code != _capi.SDGR_EOVERFLOW:
+                    raise
+                r.replan()
 
     for _ in range(args.warmup):
         step()
@@ -199,6 +275,8 @@ def main():
         out["stages_ms"] = {k: round(v, 4) for k, v in per.items()}
         dom = max(per, key=per.get)
         out["roofline"] = roofline(dom, per[dom], work)
+    if args.serving_requests > 0:
+        out["serving"] = serving_bench(dev, args.serving_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, views, args.cpu_rows)
     print(json.dumps(out), flush=True)

@@ -134,7 +134,7 @@ typedef struct sdgr_plan {
     int64_t rays;              /* computation-plane cells over all views */
     int32_t nviews, nscenes;
     int32_t tile;              /* tile side in pixels (8) */
-    int32_t reserved;
+    int32_t recompute;         /* copy of options.recompute */
 } sdgr_plan;
 
 /* Library version (SDGR_VERSION). */
@@ -164,6 +164,13 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes,
                     const sdgr_view* views, int32_t nv,
                     const sdgr_options* opt, void* query_scratch,
                     size_t query_bytes, void* stream, sdgr_plan* plan);
+
+/* Re-sizes `plan` for pair capacities pairs_c, pairs_i (for instance the
+ * counts of a previous query plus headroom, so that a training loop whose
+ * Gaussians move a little need not query every step): recomputes the three
+ * workspace sizes; host-only. A forward that finds more pairs than the
+ * capacities reports SDGR_EOVERFLOW through sdgr_status. */
+int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i);
 
 /* Forward render (Sec. II-A). Writes every view's H x W image at
  * images + view.img_offset (row-major [range row][azimuth column]); other

@@ -20,7 +20,8 @@ EXPORTED = ("sdgr_version", "sdgr_last_error", "sdgr_default_options",
             "sdgr_query_bytes", "sdgr_plan_query", "sdgr_forward",
             "sdgr_backward", "sdgr_status", "sdgr_read_intensity",
             "sdgr_read_optical_depth", "sdgr_profile_enable", "sdgr_profile_read",
-            "sdgr_profile_stage", "sdgr_profile_count", "sdgr_read_work")
+            "sdgr_profile_stage", "sdgr_profile_count", "sdgr_read_work",
+            "sdgr_plan_resize")
 
 
 class Scene(ctypes.Structure):
@@ -61,7 +62,7 @@ class Plan(ctypes.Structure):
                 ("pairs_i", ctypes.c_int64), ("tiles_c", ctypes.c_int64),
                 ("tiles_i", ctypes.c_int64), ("rays", ctypes.c_int64),
                 ("nviews", ctypes.c_int32), ("nscenes", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("recompute", ctypes.c_int32)]
 
 
 class SDGRError(RuntimeError):
@@ -104,8 +105,9 @@ def lib():
     L.sdgr_profile_stage.argtypes = [ctypes.c_int32]
     L.sdgr_profile_stage.restype = ctypes.c_char_p
     L.sdgr_profile_count.argtypes = [ctypes.c_int32]
+    L.sdgr_plan_resize.argtypes = [P(Plan), ctypes.c_int64, ctypes.c_int64]
     L.sdgr_read_work.argtypes = [P(Plan), vp, P(ctypes.c_uint64), ctypes.c_int32, vp]
-    for name in ("sdgr_profile_count", "sdgr_read_work",
+    for name in ("sdgr_plan_resize", "sdgr_profile_count", "sdgr_read_work",
                  "sdgr_profile_enable", "sdgr_profile_read", "sdgr_plan_query", "sdgr_forward", "sdgr_backward", "sdgr_status",
                  "sdgr_read_intensity", "sdgr_read_optical_depth"):
         getattr(L, name).restype = ctypes.c_int

@@ -167,13 +167,34 @@ class Renderer:
         self.scenes_c = (C.Scene * len(structs))(*structs)
 
     def plan(self) -> C.Plan:
+        """Exact plan: counts the pairs on the device (synchronises)."""
         p = C.Plan()
         qb = self.lib.sdgr_query_bytes(len(self.scenes), self.nv)
         q = _buf(qb, self.device)
         C.check(self.lib.sdgr_plan_query(self.scenes_c, len(self.scenes), self.views_c,
                                          self.nv, ctypes.byref(self.opts_c), q.data_ptr(),
                                          qb, _stream_ptr(self.device), ctypes.byref(p)))
+        self._last_exact = p
         return p
+
+    def planned(self, headroom: float = 0.1) -> C.Plan:
+        """A plan sized from this renderer's last exact query plus
+        `headroom` (querying once if there is none). Pair counts move little
+        while Gaussians are optimised, so most steps need no query; a forward
+        that outgrows it reports SDGR_EOVERFLOW through status()."""
+        if getattr(self, "_last_exact", None) is None:
+            self._last_exact = self.plan()
+        base = self._last_exact
+        p = C.Plan()
+        ctypes.pointer(p)[0] = base
+        C.check(self.lib.sdgr_plan_resize(ctypes.byref(p),
+                                          int(math.ceil(base.pairs_c * (1 + headroom))) + 64,
+                                          int(math.ceil(base.pairs_i * (1 + headroom))) + 64))
+        return p
+
+    def replan(self):
+        """Forget the cached pair counts (after an overflow)."""
+        self._last_exact = None
 
     def forward(self, plan: Optional[C.Plan] = None) -> ForwardResult:
         plan = plan or self.plan()

@@ -108,7 +108,7 @@ int bits_for(int64_t max_value)
 struct Problem {
     std::vector<DevView> views;
     std::vector<DevScene> scenes;
-    RasterParams rp;
+    RasterParams rp{};
     int nv = 0, ns = 0;
     int64_t records = 0, rays = 0, tiles_c = 0, tiles_i = 0, items = 0, pixels = 0;
     int64_t image_floats = 0;
@@ -150,6 +150,7 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     P.rp.tau_max = (opt->tau_max > 0.0f) ? opt->tau_max : INFINITY;
     P.rp.shadowing = opt->shadowing;
     P.rp.dilation = opt->dilation;
+    P.rp.work = nullptr;   // set only while work counting is on
 
     P.scenes.resize(nscenes);
     int64_t items = 0;
@@ -349,7 +350,8 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
     if (!plan) return fail(SDGR_EINVAL, "plan is null");
     if (plan->records != P.records || plan->rays != P.rays || plan->tiles_c != P.tiles_c ||
         plan->tiles_i != P.tiles_i || plan->nviews != P.nv || plan->nscenes != P.ns ||
-        plan->tile != TILE)
+        plan->tile != TILE || plan->recompute != (P.recompute ? 1 : 0) ||
+        plan->pairs_c < 0 || plan->pairs_i < 0 || plan->pairs_c + plan->pairs_i > INT32_MAX)
         return fail(SDGR_EINVAL, "plan does not match the scenes, views and options");
     return SDGR_OK;
 }
@@ -486,6 +488,7 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
     out.nviews = nv;
     out.nscenes = nscenes;
     out.tile = TILE;
+    out.recompute = P.recompute ? 1 : 0;
     out.image_floats = (size_t)P.image_floats;
     Bufs b;
     layout(P, out.pairs_c, out.pairs_i, FWD, nullptr, nullptr, b, &out.state_bytes,
@@ -493,6 +496,29 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
     layout(P, out.pairs_c, out.pairs_i, BWD, nullptr, nullptr, b, nullptr,
            &out.bwd_scratch_bytes);
     *plan = out;
+    return SDGR_OK;
+}
+
+int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i)
+{
+    g_last_error.clear();
+    if (!plan) return fail(SDGR_EINVAL, "plan is null");
+    if (pairs_c < 0 || pairs_i < 0 || pairs_c + pairs_i > INT32_MAX)
+        return fail(SDGR_EUNSUPPORTED, "pair capacities outside [0, 2^31 - 1]");
+    Problem P;
+    P.nv = plan->nviews;
+    P.ns = plan->nscenes;
+    P.records = plan->records;
+    P.rays = plan->rays;
+    P.tiles_c = plan->tiles_c;
+    P.tiles_i = plan->tiles_i;
+    P.recompute = plan->recompute != 0;
+    plan->pairs_c = pairs_c;
+    plan->pairs_i = pairs_i;
+    Bufs b;
+    layout(P, pairs_c, pairs_i, FWD, nullptr, nullptr, b, &plan->state_bytes,
+           &plan->fwd_scratch_bytes);
+    layout(P, pairs_c, pairs_i, BWD, nullptr, nullptr, b, nullptr, &plan->bwd_scratch_bytes);
     return SDGR_OK;
 }
 

@@ -55,7 +55,7 @@ struct RasterParams {
     // pass A backward, pass B forward, pass B backward; [4..6] list entries
     // evaluated by all 64 lanes in pass A forward, pass A backward, pass B
     // forward
-    unsigned long long* work;
+    unsigned long long* work = nullptr;
 };
 
 constexpr int WORK_WORD = 16;   // work counters live at status + 16 (8 x u64)

@@ -96,25 +96,71 @@ __device__ __forceinline__ bool conic(const double* cov, double* Q)
     return true;
 }
 
-// Tiles touched by the ellipse q < q_max around centre c; returns the
-// rectangle [tx0, tx1) x [ty0, ty1) packed in a uint2 and its tile count.
-__device__ uint32_t tile_rect(double cx, double cy, const double* cov, double q_max, int cols,
+// Tiles touched by the ellipse q < q_max around centre c (FP32); returns
+// the rectangle [tx0, tx1) x [ty0, ty1) packed in a uint2 and its tile count.
+// The half extents get a small margin so every cell an FP32 evaluation of
+// q < q_max can reach lies inside.
+__device__ uint32_t tile_rect(float cx, float cy, float sxx, float syy, float q_max, int cols,
                               int rows, uint2* rect)
 {
-    double rx = sqrt(q_max * cov[0]) * (1.0 + 1e-6) + 1e-6;
-    double ry = sqrt(q_max * cov[2]) * (1.0 + 1e-6) + 1e-6;
-    // cells whose centre (k + 1/2) lies within the bounding box
-    double lo_x = ceil(cx - rx - 0.5), hi_x = floor(cx + rx - 0.5);
-    double lo_y = ceil(cy - ry - 0.5), hi_y = floor(cy + ry - 0.5);
-    lo_x = fmax(lo_x, 0.0); hi_x = fmin(hi_x, (double)(cols - 1));
-    lo_y = fmax(lo_y, 0.0); hi_y = fmin(hi_y, (double)(rows - 1));
+    const float rx = sqrtf(q_max * sxx) * (1.0f + 1e-4f) + 1e-4f;
+    const float ry = sqrtf(q_max * syy) * (1.0f + 1e-4f) + 1e-4f;
+    // cells whose centre (k + 1/2) lies within the bounding box, clamped in
+    // float before converting
+    const float lo_x = fmaxf(ceilf(cx - rx - 0.5f), 0.0f);
+    const float hi_x = fminf(floorf(cx + rx - 0.5f), (float)(cols - 1));
+    const float lo_y = fmaxf(ceilf(cy - ry - 0.5f), 0.0f);
+    const float hi_y = fminf(floorf(cy + ry - 0.5f), (float)(rows - 1));
     if (!(lo_x <= hi_x) || !(lo_y <= hi_y)) { *rect = make_uint2(0, 0); return 0; }
-    uint32_t tx0 = (uint32_t)lo_x / TILE, tx1 = (uint32_t)hi_x / TILE + 1;
-    uint32_t ty0 = (uint32_t)lo_y / TILE, ty1 = (uint32_t)hi_y / TILE + 1;
+    const uint32_t tx0 = (uint32_t)lo_x / TILE, tx1 = (uint32_t)hi_x / TILE + 1;
+    const uint32_t ty0 = (uint32_t)lo_y / TILE, ty1 = (uint32_t)hi_y / TILE + 1;
     *rect = make_uint2(tx0 | (tx1 << 16), ty0 | (ty1 << 16));
     return (tx1 - tx0) * (ty1 - ty0);
 }
 
+// Projected 2D covariance and conic of one plane in FP32, spanned by radar
+// axes e1, e2 with spacings s1, s2: with u = M^T e1 and w = M^T e2 (M the
+// scaled rotation), Sigma' = [[u.u, u.w], [u.w, w.w]] / spacings and
+// det = |u x w|^2 / spacings^2 (Lagrange identity), so neither the
+// covariance nor its determinant suffers cancellation for flat Gaussians.
+struct Conic2 {
+    float sxx, sxy, syy;   // covariance (pixels^2)
+    float a, b, c;         // inverse
+    bool ok;
+};
+
+__device__ __forceinline__ Conic2 plane_conic(const float* Mt, const float* e1, const float* e2,
+                                              float inv1, float inv2, float dil)
+{
+    float u[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        u[k] = (Mt[3 * k] * e1[0] + Mt[3 * k + 1] * e1[1] + Mt[3 * k + 2] * e1[2]) * inv1;
+        w[k] = (Mt[3 * k] * e2[0] + Mt[3 * k + 1] * e2[1] + Mt[3 * k + 2] * e2[2]) * inv2;
+    }
+    Conic2 r;
+    r.sxx = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    r.sxy = u[0] * w[0] + u[1] * w[1] + u[2] * w[2];
+    r.syy = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+    const float c0 = u[1] * w[2] - u[2] * w[1];
+    const float c1 = u[2] * w[0] - u[0] * w[2];
+    const float c2 = u[0] * w[1] - u[1] * w[0];
+    float det = c0 * c0 + c1 * c1 + c2 * c2;
+    if (dil > 0.0f) {
+        det += dil * (r.sxx + r.syy) + dil * dil;
+        r.sxx += dil;
+        r.syy += dil;
+    }
+    r.ok = det > 0.0f && isfinite(det) && r.sxx > 0.0f && r.syy > 0.0f;
+    const float inv = r.ok ? 1.0f / det : 0.0f;
+    r.a = r.syy * inv;
+    r.b = -r.sxy * inv;
+    r.c = r.sxx * inv;
+    return r;
+}
+
+// FP32 projection of one record; the range coordinate that orders the depth
+// lists is evaluated in FP64 (range_coordinate) for a reproducible key.
 __global__ void __launch_bounds__(256)
 k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
              int64_t records, RasterParams rp, int write_records, float4* __restrict__ cq,
@@ -127,40 +173,68 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
     __shared__ unsigned long long part[2];
     if (threadIdx.x < 2) part[threadIdx.x] = 0;
     __syncthreads();
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t nc = 0, ni = 0;
     if (r < records) {
-        int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
+        const int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
         const DevView& V = views[v];
         const DevScene& S = scenes[V.scene];
-        int64_t i = r - V.rec_off;
-        Geo g;
-        geometry(V, S, i, g);
-        double covC[3], covI[3], QC[3], QI[3];
-        bool ok = g.valid;
-        double cCx = 0, cCy = 0, cIx = 0, cIy = 0;
+        const int64_t i = r - V.rec_off;
+        const float m0 = S.means[3 * i], m1 = S.means[3 * i + 1], m2 = S.means[3 * i + 2];
+        const float s0 = S.scales[3 * i], s1 = S.scales[3 * i + 1], s2 = S.scales[3 * i + 2];
+        const float* qp = S.quats + 4 * i;
+        const float4 q = make_float4(qp[0], qp[1], qp[2], qp[3]);
+        const float n2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
+        bool ok = isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(s0) &&
+                  isfinite(s1) && isfinite(s2) && s0 > 0.0f && s1 > 0.0f && s2 > 0.0f &&
+                  isfinite(n2) && n2 > 0.0f;
+        float4 vc_q = make_float4(0.f, 0.f, 0.f, 0.f), vi_q = vc_q;
+        float2 vc_w = make_float2(0.f, 0.f), vi_w = vc_w;
         uint2 rc = make_uint2(0, 0), ri = make_uint2(0, 0);
+        uint32_t zbits = 0u;
         if (ok) {
-            plane_cov(g, V.ex, V.ey, V.dAc, V.dEc, rp.dilation, covC);
-            plane_cov(g, V.ex, V.ez, V.dA, V.dR, rp.dilation, covI);
-            ok = conic(covC, QC) && conic(covI, QI);
+            const float inv_n = rsqrtf(n2);
+            const float w = q.x * inv_n, x = q.y * inv_n, y = q.z * inv_n, z = q.w * inv_n;
+            // rows of M^T: column k of R scaled by s_k
+            float Mt[9];
+            Mt[0] = (1.f - 2.f * (y * y + z * z)) * s0;
+            Mt[1] = 2.f * (x * y + w * z) * s0;
+            Mt[2] = 2.f * (x * z - w * y) * s0;
+            Mt[3] = 2.f * (x * y - w * z) * s1;
+            Mt[4] = (1.f - 2.f * (x * x + z * z)) * s1;
+            Mt[5] = 2.f * (y * z + w * x) * s1;
+            Mt[6] = 2.f * (x * z + w * y) * s2;
+            Mt[7] = 2.f * (y * z - w * x) * s2;
+            Mt[8] = (1.f - 2.f * (x * x + y * y)) * s2;
+            const float ex[3] = {(float)V.ex[0], (float)V.ex[1], (float)V.ex[2]};
+            const float ey[3] = {(float)V.ey[0], (float)V.ey[1], (float)V.ey[2]};
+            const float ez[3] = {(float)V.ez[0], (float)V.ez[1], (float)V.ez[2]};
+            const float iA = (float)(1.0 / V.dA), iR = (float)(1.0 / V.dR);
+            const float iAc = (float)(1.0 / V.dAc), iEc = (float)(1.0 / V.dEc);
+            const Conic2 C = plane_conic(Mt, ex, ey, iAc, iEc, rp.dilation);
+            const Conic2 I = plane_conic(Mt, ex, ez, iA, iR, rp.dilation);
+            ok = C.ok && I.ok;
+            if (ok) {
+                const float xr = ex[0] * m0 + ex[1] * m1 + ex[2] * m2;
+                const float yr = ey[0] * m0 + ey[1] * m1 + ey[2] * m2;
+                const double zr = range_coordinate(V.ez, m0, m1, m2);
+                const float cCx = xr * iAc + (float)V.hWc, cCy = yr * iEc + (float)V.hHc;
+                const float cIx = xr * iA + (float)V.hW, cIy = (float)zr * iR + (float)V.hH;
+                nc = tile_rect(cCx, cCy, C.sxx, C.syy, rp.q_max, V.Wc, V.Hc, &rc);
+                ni = tile_rect(cIx, cIy, I.sxx, I.syy, rp.q_max, V.W, V.H, &ri);
+                zbits = __float_as_uint(__double2float_rn(zr));
+                if (zbits == 0x80000000u) zbits = 0u;   // -0 -> +0
+                vc_q = make_float4(cCx, cCy, C.a, C.b);
+                vc_w = make_float2(C.c, S.ext[i]);
+                vi_q = make_float4(cIx, cIy, I.a, I.b);
+                vi_w = make_float2(I.c, 0.0f);
+            }
         }
-        float zkey = 0.0f;
-        if (ok) {
-            cCx = g.x / V.dAc + V.hWc; cCy = g.y / V.dEc + V.hHc;
-            cIx = g.x / V.dA + V.hW;   cIy = g.z / V.dR + V.hH;
-            nc = tile_rect(cCx, cCy, covC, rp.q_max, V.Wc, V.Hc, &rc);
-            ni = tile_rect(cIx, cIy, covI, rp.q_max, V.W, V.H, &ri);
-            zkey = __double2float_rn(g.z);
-        }
-        uint32_t zbits = __float_as_uint(zkey);
-        if (zbits == 0x80000000u) zbits = 0u;   // -0 -> +0
         if (write_records) {
-            float kappa = ok ? S.ext[i] : 0.0f;
-            cq[r] = make_float4((float)cCx, (float)cCy, ok ? (float)QC[0] : 0.f, ok ? (float)QC[1] : 0.f);
-            cw[r] = make_float2(ok ? (float)QC[2] : 0.f, kappa);
-            iq[r] = make_float4((float)cIx, (float)cIy, ok ? (float)QI[0] : 0.f, ok ? (float)QI[1] : 0.f);
-            iw[r] = make_float2(ok ? (float)QI[2] : 0.f, 0.0f);
+            cq[r] = vc_q;
+            cw[r] = vc_w;
+            iq[r] = vi_q;
+            iw[r] = vi_w;
             rect_c[r] = rc;
             rect_i[r] = ri;
             cnt_c[r] = nc;
@@ -169,8 +243,8 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
             dval[r] = (uint32_t)r;
         }
     }
-    atomicAdd(&part[0], (unsigned long long)nc);
-    atomicAdd(&part[1], (unsigned long long)ni);
+    if (nc) atomicAdd(&part[0], (unsigned long long)nc);
+    if (ni) atomicAdd(&part[1], (unsigned long long)ni);
     __syncthreads();
     if (threadIdx.x == 0) {
         atomicAdd(&totals[0], part[0]);

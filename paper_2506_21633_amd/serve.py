@@ -97,6 +97,8 @@ class GpuExecutor:
         k = self.free_streams.pop()
         stream = self.streams[k]
         try:
+            # inputs (resident scenes, targets) were made on the default stream
+            stream.wait_stream(torch.cuda.default_stream(self.device))
             with torch.cuda.stream(stream):
                 scenes = [self.scenes[r.scene_id] for r in reqs]
                 views, ids = [], []
@@ -137,7 +139,8 @@ class GpuExecutor:
         out, v0 = [], 0
         for i, r in enumerate(launch.requests):
             imgs = [res.image(v0 + j) for j in range(r.nviews)]
-            out.append(Result(r.id, imgs, grads[i] if grads is not None else None))
+            out.append(Result(r.id, imgs, grads[i] if (grads is not None and r.want_grad)
+                              else None))
             v0 += r.nviews
         return out
 
