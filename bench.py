@@ -49,6 +49,11 @@ def parse():
                     help="skip the per-stage HIP event timing")
     ap.add_argument("--serving-requests", type=int, default=160,
                     help="requests of the served-vs-plain stream (0 skips it)")
+    ap.add_argument("--no-work-count", action="store_true",
+                    help="skip the untimed step that counts footprint hits (profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of MIB MiB (the reference "
+                         "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     return ap.parse_args()
 
 
@@ -196,6 +201,14 @@ def main():
     from paper_2506_21633_amd import _capi, api
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        nf = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(nf, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize(dev)
+        dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        del src, dst
     sc, views, target, cfg = workload(args.workload)
     g = api.GaussianTensors.from_numpy(sc, dev)
     tgt = api.GaussianTensors.from_numpy(target, dev)
@@ -222,20 +235,22 @@ def main():
         step()
     torch.cuda.synchronize(dev)
     res = step()
-    plan = res.plan
+    exact = r._last_exact          # the exact pair counts (capacities add 10 %)
     torch.cuda.synchronize(dev)
 
     lib = _capi.lib()
-    # one untimed step with the work counters on (they add atomics)
-    lib.sdgr_profile_count(1)
-    res = step()
-    torch.cuda.synchronize(dev)
-    lib.sdgr_profile_count(0)
-    work = (ctypes.c_uint64 * 8)()
-    _capi.check(lib.sdgr_read_work(ctypes.byref(res.plan), res.state.data_ptr(), work, 8,
-                                   torch.cuda.current_stream(dev).cuda_stream))
-    work = list(work)
-    del res
+    work = [0] * 8
+    if not args.no_work_count:
+        # one untimed step with the work counters on
+        lib.sdgr_profile_count(1)
+        res = step()
+        torch.cuda.synchronize(dev)
+        lib.sdgr_profile_count(0)
+        wk = (ctypes.c_uint64 * 8)()
+        _capi.check(lib.sdgr_read_work(ctypes.byref(res.plan), res.state.data_ptr(), wk, 8,
+                                       torch.cuda.current_stream(dev).cuda_stream))
+        work = list(wk)
+        del res
     if not args.no_profile:
         _capi.profile_read()
         lib.sdgr_profile_enable(1)
@@ -263,13 +278,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": dict(cfg, parallelism="single GPU", pairs_c=plan.pairs_c,
-                       pairs_i=plan.pairs_i, tiles_c=plan.tiles_c, tiles_i=plan.tiles_i),
+        "config": dict(cfg, parallelism="single GPU", pairs_c=exact.pairs_c,
+                       pairs_i=exact.pairs_i, tiles_c=exact.tiles_c, tiles_i=exact.tiles_i),
     }
     out["work"] = {"hits_a_fwd": work[0], "hits_a_bwd": work[1], "hits_b_fwd": work[2],
                    "hits_b_bwd": work[3], "entries_a_fwd": work[4], "entries_a_bwd": work[5],
                    "entries_b_fwd": work[6]}
-    out["path_hbm"] = path_hbm(plan, sc.n, views, ms_step)
+    out["path_hbm"] = path_hbm(exact, sc.n, views, ms_step)
     if stages:
         per = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}
         out["stages_ms"] = {k: round(v, 4) for k, v in per.items()}

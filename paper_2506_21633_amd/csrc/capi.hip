@@ -247,6 +247,7 @@ struct Bufs {
     uint32_t* pval[2] = {nullptr, nullptr};
     uint64_t* pmask = nullptr;      // footprint cells per computation-plane pair
     uint2* ranges = nullptr;
+    uint32_t* worklist = nullptr;   // non-empty computation-plane tiles, longest first
     // transient: projection counts and sort buffers
     uint2* rect_c = nullptr;
     uint2* rect_i = nullptr;
@@ -260,6 +261,7 @@ struct Bufs {
     uint32_t* pkey[2] = {nullptr, nullptr};
     uint32_t* hist = nullptr;
     uint32_t* scan_tmp = nullptr;
+    unsigned long long* slots = nullptr;   // spread pair-total accumulators
     // backward accumulators, 8 floats per record
     float* grad_c = nullptr;
     float* grad_i = nullptr;
@@ -302,6 +304,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.pval[1] = a.take<uint32_t>(K);
         b.pmask = a.take<uint64_t>(cap_c);
         b.ranges = a.take<uint2>(P.tiles_c + P.tiles_i);
+        b.worklist = a.take<uint32_t>(P.tiles_c);
     };
     auto transient = [&](Arena& a) {
         b.rect_c = a.take<uint2>(R);
@@ -321,6 +324,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.hist = a.take<uint32_t>(hw);
         int64_t sw = (int64_t)std::max(scan_tmp_words(R), scan_tmp_words(hw));
         b.scan_tmp = a.take<uint32_t>(sw);
+        b.slots = a.take<unsigned long long>(2 * TOTAL_SLOTS);
     };
     if (!P.recompute) geo(st);
     if (ph == FWD) {
@@ -358,12 +362,7 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
 
 int passes_bits_depth(const Problem& P) { return 32 + bits_for(P.nv - 1); }
 int passes_bits_pairs(const Problem& P) { return bits_for(P.tiles_c + P.tiles_i - 1); }
-int final_pair_buffer(const Problem& P)
-{
-    int bits = passes_bits_pairs(P);
-    int passes = (bits + 7) / 8;
-    return passes & 1;
-}
+int final_pair_buffer(const Problem& P) { return radix_passes_for(passes_bits_pairs(P)) & 1; }
 
 // Projection, binning, sorting and tile ranges (shared by the forward and
 // the recomputing backward).
@@ -376,7 +375,7 @@ int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStrea
         StageTimer t(SG_PREPROCESS, s);
         SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, R, P.rp, true, b.cq, b.cw, b.iq,
                                    b.iw, b.rect_c, b.rect_i, b.cnt_c, b.cnt_i, b.dkey[0],
-                                   b.dval[0],
+                                   b.dval[0], b.slots,
                                    reinterpret_cast<unsigned long long*>(b.status + ST_COUNT),
                                    s));
     }
@@ -415,6 +414,7 @@ int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStrea
                                 b.ranges, s));
     SDGR_HIP(launch_pair_masks(b.views, P.nv, plan->pairs_c, P.rp, b.status, pk[pw], pv[pw],
                                b.cq, b.cw, b.pmask, s));
+    SDGR_HIP(launch_tile_worklist(b.ranges, P.tiles_c, b.worklist, b.status, s));
     return SDGR_OK;
 }
 
@@ -443,7 +443,8 @@ void sdgr_default_options(sdgr_options* opt)
 size_t sdgr_query_bytes(int32_t nscenes, int32_t nv)
 {
     if (nscenes < 0 || nv < 0) return 0;
-    return 4096 + ((sizeof(DevView) * (size_t)nv + 255) & ~size_t(255)) +
+    return 4096 + 16 * (size_t)TOTAL_SLOTS + 256 +
+           ((sizeof(DevView) * (size_t)nv + 255) & ~size_t(255)) +
            ((sizeof(DevScene) * (size_t)nscenes + 255) & ~size_t(255));
 }
 
@@ -462,6 +463,7 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
     hipStream_t s = (hipStream_t)stream;
     Arena a{(char*)query_scratch};
     unsigned long long* totals = a.take<unsigned long long>(8);
+    unsigned long long* slots = a.take<unsigned long long>(2 * TOTAL_SLOTS);
     DevView* dviews = a.take<DevView>(nv);
     DevScene* dscenes = a.take<DevScene>(nscenes);
     SDGR_HIP(launch_upload(dviews, P.views.data(), sizeof(DevView) * nv, s));
@@ -471,7 +473,7 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
         StageTimer t(SG_QUERY, s);
         SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.records, P.rp, false, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   nullptr, nullptr, nullptr, totals, s));
+                                   nullptr, nullptr, nullptr, slots, totals, s));
     }
     unsigned long long host_tot[2] = {0, 0};
     SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));
@@ -543,10 +545,13 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     if ((rc = build_lists(P, plan, b, s))) return rc;
     const int pw = final_pair_buffer(P);
     SDGR_HIP(launch_fill_u32((uint32_t*)b.A, 0u, P.records, s));
+    SDGR_HIP(launch_fill_u32((uint32_t*)b.tau, 0u, P.rays, s));   // rays of empty tiles
+    SDGR_HIP(launch_fill_u32(b.nlast, 0u, P.rays, s));
     {
         StageTimer t(SG_RASTER_A_FWD, s);
-        SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, P.rp, b.ranges, b.pval[pw],
-                                     b.pmask, b.cq, b.cw, b.A, b.tau, b.nlast, s));
+        SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, P.rp, b.status, b.worklist,
+                                     b.ranges, b.pval[pw], b.pmask, b.cq, b.cw, b.A, b.tau,
+                                     b.nlast, s));
     }
     {
         StageTimer t(SG_INTENSITY, s);
@@ -607,9 +612,9 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     }
     {
         StageTimer t(SG_RASTER_A_BWD, s);
-        SDGR_HIP(launch_raster_a_bwd(b.views, b.scenes, P.nv, P.tiles_c, P.rp, b.ranges,
-                                     b.pval[pw], b.pmask, b.cq, b.cw, b.tau, b.nlast,
-                                     b.grad_i, b.grad_c, P.records, s));
+        SDGR_HIP(launch_raster_a_bwd(b.views, b.scenes, P.nv, P.tiles_c, P.rp, b.status,
+                                     b.worklist, b.ranges, b.pval[pw], b.pmask, b.cq, b.cw,
+                                     b.tau, b.nlast, b.grad_i, b.grad_c, P.records, s));
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,

@@ -66,7 +66,8 @@ enum StatusSlot : int {
     ST_PAIRS_C = 1,    // actual pair counts of the last projection
     ST_PAIRS_I = 2,
     ST_PAIRS_ALL = 3,  // min(pairs_c + pairs_i, capacity), sort length
-    ST_COUNT = 8
+    ST_WORK_TILES = 4, // non-empty computation-plane tiles in the worklist
+    ST_COUNT = 8       // u64 pair totals of the projection at status + 8
 };
 
 // Index of the view a global record / bucket belongs to: the last v with
@@ -117,12 +118,16 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 namespace sdgr {
 
 
+// Pair totals of the projection are accumulated in 2 x TOTAL_SLOTS u64
+// slots (spread atomics) and summed into totals[0..1].
+constexpr int TOTAL_SLOTS = 1024;
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
                              int64_t records, const RasterParams& rp,
                              bool write_records, float4* cq, float2* cw, float4* iq,
                              float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* cnt_c,
                              uint32_t* cnt_i, uint64_t* dkey, uint32_t* dval,
-                             unsigned long long* totals, hipStream_t s);
+                             unsigned long long* slots, unsigned long long* totals,
+                             hipStream_t s);
 
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
                                 int64_t records, const float* A, float2* iw,
@@ -146,6 +151,7 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
 // n_dev points at the device-side element count (<= cap). Buffers [0] hold
 // the input; returns in *which the index of the buffer holding the output.
 size_t radix_hist_words(int64_t cap);
+int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
 hipError_t launch_radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, uint32_t* hist,
                                  uint32_t* scan_tmp, int* which, hipStream_t s);
@@ -172,8 +178,11 @@ hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const 
                              const uint32_t* status, const uint32_t* pkey,
                              const uint32_t* pvals, const float4* cq, const float2* cw,
                              uint64_t* pmask, hipStream_t s);
+hipError_t launch_tile_worklist(const uint2* ranges, int64_t tiles_c, uint32_t* worklist,
+                                uint32_t* status, hipStream_t s);
 hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
-                               const RasterParams& rp, const uint2* ranges,
+                               const RasterParams& rp, const uint32_t* status,
+                               const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
                                const float2* cw, float* A, float* tau, uint32_t* nlast,
                                hipStream_t s);
@@ -185,7 +194,8 @@ hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
                             const RasterParams& rp, const float4* iq, const float2* iw,
                             const float* dimg, float* grad_i, hipStream_t s);
 hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
-                               int64_t tiles_c, const RasterParams& rp, const uint2* ranges,
+                               int64_t tiles_c, const RasterParams& rp, const uint32_t* status,
+                               const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
                                const float2* cw, const float* tau, const uint32_t* nlast,
                                const float* grad_i, float* grad_c, int64_t stride,

@@ -246,10 +246,22 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
     if (nc) atomicAdd(&part[0], (unsigned long long)nc);
     if (ni) atomicAdd(&part[1], (unsigned long long)ni);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        atomicAdd(&totals[0], part[0]);
-        atomicAdd(&totals[1], part[1]);
-    }
+    // spread over TOTAL_SLOTS addresses; k_sum_slots adds them up
+    if (threadIdx.x < 2 && part[threadIdx.x])
+        atomicAdd(&totals[2 * (blockIdx.x % TOTAL_SLOTS) + threadIdx.x], part[threadIdx.x]);
+}
+
+__global__ void __launch_bounds__(1024)
+k_sum_slots(const unsigned long long* __restrict__ slots, unsigned long long* __restrict__ out)
+{
+    __shared__ unsigned long long acc[2];
+    if (threadIdx.x < 2) acc[threadIdx.x] = 0;
+    __syncthreads();
+    const unsigned long long c = slots[2 * threadIdx.x], i = slots[2 * threadIdx.x + 1];
+    if (c) atomicAdd(&acc[0], c);
+    if (i) atomicAdd(&acc[1], i);
+    __syncthreads();
+    if (threadIdx.x < 2) out[threadIdx.x] = acc[threadIdx.x];
 }
 
 __global__ void __launch_bounds__(256)
@@ -374,18 +386,28 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+__global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 }  // namespace
 
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
                              int64_t records, const RasterParams& rp, bool write_records,
                              float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
                              uint2* rect_i, uint32_t* cnt_c, uint32_t* cnt_i, uint64_t* dkey,
-                             uint32_t* dval, unsigned long long* totals, hipStream_t s)
+                             uint32_t* dval, unsigned long long* slots,
+                             unsigned long long* totals, hipStream_t s)
 {
-    if (records <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
-                       scenes, nv, records, rp, write_records ? 1 : 0, cq, cw, iq, iw, rect_c,
-                       rect_i, cnt_c, cnt_i, dkey, dval, totals);
+    hipLaunchKernelGGL(k_fill_u64, dim3(2 * TOTAL_SLOTS / 256), dim3(256), 0, s, slots,
+                       2 * TOTAL_SLOTS);
+    if (records > 0)
+        hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
+                           scenes, nv, records, rp, write_records ? 1 : 0, cq, cw, iq, iw,
+                           rect_c, rect_i, cnt_c, cnt_i, dkey, dval, slots);
+    hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(TOTAL_SLOTS), 0, s, slots, totals);
     return hipGetLastError();
 }
 

@@ -2,7 +2,8 @@
 // scattering intensity and imaging; Sec. II-B, their gradients).
 //
 // Computation plane (order matters: front-to-back along each ray)
-//   One wave64 owns one 8x8 tile: lane l handles ray (l % 8, l / 8). Every
+//   One wave64 (a workgroup of its own) owns one 8x8 tile: lane l handles ray
+//   (l % 8, l / 8); only non-empty tiles run, longest lists first. Every
 //   (tile, Gaussian) pair carries a 64-bit mask of the tile cells inside the
 //   footprint ellipse (k_pair_masks). The tile's depth-sorted list is walked
 //   in batches of 64 entries: the masks are read coalesced, entries whose mask
@@ -145,23 +146,25 @@ k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParam
     pmask[p] = footprint_mask(g.x, g.y, g.z, g.w, g2.x, rp.q_max, local % V.txc, local / V.txc);
 }
 
-__global__ void __launch_bounds__(RASTER_THREADS)
-k_raster_a_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, RasterParams rp,
+__global__ void __launch_bounds__(WAVE)
+k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
+               const uint32_t* __restrict__ status, const uint32_t* __restrict__ worklist,
                const uint2* __restrict__ ranges, const uint32_t* __restrict__ pvals,
                const uint64_t* __restrict__ pmask, const float4* __restrict__ cq,
                const float2* __restrict__ cw, float* __restrict__ A, float* __restrict__ tau,
                uint32_t* __restrict__ nlast)
 {
-    __shared__ float4 s_q[RASTER_WAVES][WAVE];
-    __shared__ float2 s_w[RASTER_WAVES][WAVE];
-    __shared__ uint64_t s_m[RASTER_WAVES][WAVE];
-    __shared__ uint32_t s_r[RASTER_WAVES][WAVE];
-    __shared__ uint32_t s_e[RASTER_WAVES][WAVE];
+    constexpr int w = 0;   // one wave per workgroup: heavy tiles schedule one by one
+    __shared__ float4 s_q[1][WAVE];
+    __shared__ float2 s_w[1][WAVE];
+    __shared__ uint64_t s_m[1][WAVE];
+    __shared__ uint32_t s_r[1][WAVE];
+    __shared__ uint32_t s_e[1][WAVE];
     constexpr int GA = 32;
-    __shared__ GroupReduce<1, GA> s_red[RASTER_WAVES];
-    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int64_t bucket = (int64_t)blockIdx.x * RASTER_WAVES + w;
-    if (bucket >= tiles_c) return;
+    __shared__ GroupReduce<1, GA> s_red[1];
+    const int lane = threadIdx.x;
+    if (blockIdx.x >= status[ST_WORK_TILES]) return;
+    const int64_t bucket = worklist[blockIdx.x];
     const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
     const float px = tc.col + 0.5f, py = tc.row + 0.5f;
@@ -171,9 +174,15 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, Raste
     auto flush = [&]() {
         wave_lds_sync();
         if (lane < group) {
-            float sum = 0.0f;
-#pragma unroll 8
-            for (int k = 0; k < WAVE; ++k) sum += red.row[k][lane];
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+#pragma unroll 4
+            for (int k = 0; k < WAVE; k += 4) {
+                s0 += red.row[k][lane];
+                s1 += red.row[k + 1][lane];
+                s2 += red.row[k + 2][lane];
+                s3 += red.row[k + 3][lane];
+            }
+            const float sum = (s0 + s1) + (s2 + s3);
             if (sum != 0.0f) unsafeAtomicAdd(&A[red.rec[lane]], sum);
         }
         wave_lds_sync();
@@ -182,6 +191,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, Raste
     float T = 1.0f, t = 0.0f;
     bool alive = tc.inside;
     uint32_t last = 0;
+    unsigned long long n_entries = 0, n_hits = 0;   // work counters (wave-uniform)
     uint64_t live = __ballot(alive);
     for (uint32_t b0 = rg.x; b0 < rg.y && live != 0ull; b0 += WAVE) {
         const uint32_t e = b0 + lane;
@@ -209,10 +219,8 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, Raste
             const float q = quadform(g, g2.x, dx, dy);
             const bool hit = alive && ((mj >> lane) & 1ull) && q < rp.q_max;
             const uint64_t hb = __ballot(hit);
-            if (rp.work && lane == 0) {
-                atomicAdd(&rp.work[4], 1ull);
-                atomicAdd(&rp.work[0], (unsigned long long)__popcll(hb));
-            }
+            n_entries += 1;
+            n_hits += (unsigned long long)__popcll(hb);
             if (hb == 0ull) continue;
             float contrib = 0.0f, x = 0.0f, E = 1.0f;
             if (hit) {
@@ -235,6 +243,10 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, int64_t tiles_c, Raste
         wave_lds_sync();
     }
     if (group > 0) flush();
+    if (rp.work && lane == 0) {
+        atomicAdd(&rp.work[4], n_entries);
+        atomicAdd(&rp.work[0], n_hits);
+    }
     if (tc.inside) {
         const int64_t ray = V.ray_off + (int64_t)tc.row * V.Wc + tc.col;
         tau[ray] = t;
@@ -271,6 +283,7 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     uint32_t cur = 0xFFFFFFFFu;
     float acc = 0.0f, px = 0.0f, py = 0.0f;
     int64_t pix = -1;
+    unsigned long long n_entries = 0, n_hits = 0;   // work counters (wave-uniform)
     for (uint32_t b0 = (uint32_t)p0; b0 < p1; b0 += WAVE) {
         const uint32_t cnt = min((uint32_t)WAVE, p1 - b0);
         if (lane < cnt) {
@@ -298,16 +311,17 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
             const float q = quadform(g, g2.x, dx, dy);
             if (q < rp.q_max) acc += (__expf(-0.5f * q) - rp.eps) * rp.inv1meps * g2.y;
             if (rp.work) {
-                const uint64_t hb = __ballot(q < rp.q_max && pix >= 0);
-                if (lane == 0) {
-                    atomicAdd(&rp.work[6], 1ull);
-                    atomicAdd(&rp.work[2], (unsigned long long)__popcll(hb));
-                }
+                n_entries += 1;
+                n_hits += (unsigned long long)__popcll(__ballot(q < rp.q_max && pix >= 0));
             }
         }
         wave_lds_sync();
     }
     if (pix >= 0) unsafeAtomicAdd(&images[pix], acc);
+    if (rp.work && lane == 0) {
+        atomicAdd(&rp.work[6], n_entries);
+        atomicAdd(&rp.work[2], n_hits);
+    }
 }
 
 // Imaging-plane backward, one thread per record (view, Gaussian): the
@@ -320,8 +334,10 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
             const float4* __restrict__ iq, const float2* __restrict__ iw,
             const float* __restrict__ dimg, float* __restrict__ grad_i)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= records) return;
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long hits = 0;
+    if (r0 < records) {
+    const int64_t r = r0;
     const int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
     const DevView& V = views[v];
     const float4 g = iq[r];
@@ -329,7 +345,6 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
     const float a = g.z, b = g.w, c = g2.x, I = g2.y;
     const float det = a * c - b * b;
     float dI = 0.f, dcx = 0.f, dcy = 0.f, da = 0.f, db = 0.f, dc = 0.f;
-    unsigned long long hits = 0;
     if (det > 0.0f && a > 0.0f) {
         const float qm = rp.q_max;
         const float ry = sqrtf(qm * a / det);
@@ -362,34 +377,42 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
             }
         }
     }
-    if (rp.work && hits) atomicAdd(&rp.work[3], hits);
     grad_i[r] = dcx;
     grad_i[records + r] = dcy;
     grad_i[2 * records + r] = da;
     grad_i[3 * records + r] = db;
     grad_i[4 * records + r] = dc;
     grad_i[5 * records + r] = dI;
+    }
+    if (rp.work) {   // one atomic per wave
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1)
+            hits += (unsigned long long)__shfl_xor((long long)hits, d, WAVE);
+        if (lane_id() == 0 && hits) atomicAdd(&rp.work[3], hits);
+    }
 }
 
-__global__ void __launch_bounds__(RASTER_THREADS)
+__global__ void __launch_bounds__(WAVE)
 k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
-               int64_t tiles_c, RasterParams rp, const uint2* __restrict__ ranges,
+               RasterParams rp, const uint32_t* __restrict__ status,
+               const uint32_t* __restrict__ worklist, const uint2* __restrict__ ranges,
                const uint32_t* __restrict__ pvals, const uint64_t* __restrict__ pmask,
                const float4* __restrict__ cq, const float2* __restrict__ cw,
                const float* __restrict__ tau, const uint32_t* __restrict__ nlast,
                const float* __restrict__ grad_i, float* __restrict__ grad_c, int64_t stride)
 {
-    __shared__ float4 s_q[RASTER_WAVES][WAVE];
-    __shared__ float2 s_w[RASTER_WAVES][WAVE];
-    __shared__ uint64_t s_m[RASTER_WAVES][WAVE];
-    __shared__ float s_c[RASTER_WAVES][WAVE];
-    __shared__ uint32_t s_r[RASTER_WAVES][WAVE];
-    __shared__ uint32_t s_e[RASTER_WAVES][WAVE];
+    constexpr int w = 0;   // one wave per workgroup: heavy tiles schedule one by one
+    __shared__ float4 s_q[1][WAVE];
+    __shared__ float2 s_w[1][WAVE];
+    __shared__ uint64_t s_m[1][WAVE];
+    __shared__ float s_c[1][WAVE];
+    __shared__ uint32_t s_r[1][WAVE];
+    __shared__ uint32_t s_e[1][WAVE];
     constexpr int GB = 8;
-    __shared__ GroupReduce<6, GB> s_red[RASTER_WAVES];
-    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int64_t bucket = (int64_t)blockIdx.x * RASTER_WAVES + w;
-    if (bucket >= tiles_c) return;
+    __shared__ GroupReduce<6, GB> s_red[1];
+    const int lane = threadIdx.x;
+    if (blockIdx.x >= status[ST_WORK_TILES]) return;
+    const int64_t bucket = worklist[blockIdx.x];
     const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
     const float* amp = scenes[V.scene].amp;
@@ -398,9 +421,15 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
     auto flush = [&]() {
         wave_lds_sync();
         if (lane < 6 * group) {
-            float sum = 0.0f;
-#pragma unroll 8
-            for (int k = 0; k < WAVE; ++k) sum += red.row[k][lane];
+            float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+#pragma unroll 4
+            for (int k = 0; k < WAVE; k += 4) {
+                s0 += red.row[k][lane];
+                s1 += red.row[k + 1][lane];
+                s2 += red.row[k + 2][lane];
+                s3 += red.row[k + 3][lane];
+            }
+            const float sum = (s0 + s1) + (s2 + s3);
             const int slot = lane / 6, comp = lane - 6 * slot;
             if (sum != 0.0f) unsafeAtomicAdd(&grad_c[comp * stride + red.rec[slot]], sum);
         }
@@ -413,6 +442,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
     const uint32_t n_mine = tc.inside ? nlast[ray] : 0u;
     float t = tc.inside ? tau[ray] : 0.0f;
     float U = 0.0f;
+    unsigned long long n_entries = 0, n_hits = 0;   // work counters (wave-uniform)
     const uint32_t n_max = wave_max_u32(n_mine);
     // batches back to front over list entries [0, n_max)
     for (int64_t be = n_max; be > 0; be -= WAVE) {
@@ -445,10 +475,8 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
             const float q = quadform(g, g2.x, dx, dy);
             const bool hit = ej < n_mine && ((mj >> lane) & 1ull) && q < rp.q_max;
             const uint64_t hb = __ballot(hit);
-            if (rp.work && lane == 0) {
-                atomicAdd(&rp.work[5], 1ull);
-                atomicAdd(&rp.work[1], (unsigned long long)__popcll(hb));
-            }
+            n_entries += 1;
+            n_hits += (unsigned long long)__popcll(hb);
             if (hb == 0ull) continue;
             float dcx = 0.f, dcy = 0.f, da = 0.f, db = 0.f, dc = 0.f, dk = 0.f;
             if (hit) {
@@ -486,6 +514,43 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
         wave_lds_sync();
     }
     if (group > 0) flush();
+    if (rp.work && lane == 0) {
+        atomicAdd(&rp.work[5], n_entries);
+        atomicAdd(&rp.work[1], n_hits);
+    }
+}
+
+// Non-empty computation-plane tiles, longest lists first (binned by the
+// bit length of the list size), so the heaviest tiles start earliest. One
+// workgroup; the count goes to status[ST_WORK_TILES].
+__global__ void __launch_bounds__(1024)
+k_tile_worklist(const uint2* __restrict__ ranges, int64_t tiles_c, uint32_t* __restrict__ worklist,
+                uint32_t* __restrict__ status)
+{
+    __shared__ uint32_t cnt[33], base[33];
+    const int tid = threadIdx.x;
+    if (tid < 33) cnt[tid] = 0;
+    __syncthreads();
+    for (int64_t t = tid; t < tiles_c; t += blockDim.x) {
+        const uint2 rg = ranges[t];
+        const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;
+        if (len) atomicAdd(&cnt[32 - __clz(len)], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (int lvl = 32; lvl >= 1; --lvl) {
+            base[lvl] = acc;
+            acc += cnt[lvl];
+        }
+        status[ST_WORK_TILES] = acc;
+    }
+    __syncthreads();
+    for (int64_t t = tid; t < tiles_c; t += blockDim.x) {
+        const uint2 rg = ranges[t];
+        const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;
+        if (len) worklist[atomicAdd(&base[32 - __clz(len)], 1u)] = (uint32_t)t;
+    }
 }
 
 inline unsigned raster_grid(int64_t waves)
@@ -508,15 +573,24 @@ hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const 
     return hipGetLastError();
 }
 
+hipError_t launch_tile_worklist(const uint2* ranges, int64_t tiles_c, uint32_t* worklist,
+                                uint32_t* status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_tile_worklist, dim3(1), dim3(1024), 0, s, ranges, tiles_c, worklist,
+                       status);
+    return hipGetLastError();
+}
+
 hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
-                               const RasterParams& rp, const uint2* ranges,
+                               const RasterParams& rp, const uint32_t* status,
+                               const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
                                const float2* cw, float* A, float* tau, uint32_t* nlast,
                                hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_a_fwd, dim3(raster_grid(tiles_c)), dim3(RASTER_THREADS), 0, s,
-                       views, nv, tiles_c, rp, ranges, pvals, pmask, cq, cw, A, tau, nlast);
+    hipLaunchKernelGGL(k_raster_a_fwd, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views, nv, rp,
+                       status, worklist, ranges, pvals, pmask, cq, cw, A, tau, nlast);
     return hipGetLastError();
 }
 
@@ -546,15 +620,16 @@ hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
 }
 
 hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
-                               int64_t tiles_c, const RasterParams& rp, const uint2* ranges,
+                               int64_t tiles_c, const RasterParams& rp, const uint32_t* status,
+                               const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
                                const float2* cw, const float* tau, const uint32_t* nlast,
                                const float* grad_i, float* grad_c, int64_t stride,
                                hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_a_bwd, dim3(raster_grid(tiles_c)), dim3(RASTER_THREADS), 0, s,
-                       views, scenes, nv, tiles_c, rp, ranges, pvals, pmask, cq, cw, tau, nlast,
+    hipLaunchKernelGGL(k_raster_a_bwd, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views, scenes,
+                       nv, rp, status, worklist, ranges, pvals, pmask, cq, cw, tau, nlast,
                        grad_i, grad_c, stride);
     return hipGetLastError();
 }

@@ -26,8 +26,7 @@ namespace {
 constexpr int SB = 256;          // threads per sort/scan block
 constexpr int SI = 16;           // items per thread
 constexpr int SN = SB * SI;      // items per block
-constexpr int RADIX_BITS = 8;
-constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int MAX_RADIX = 1 << 10;
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + SN - 1) / SN); }
 
@@ -96,45 +95,61 @@ __global__ void __launch_bounds__(256) k_scan_add(uint32_t* out, int64_t n, cons
     if (i < n) out[i] += sums[i / SN];
 }
 
-template <class K>
+// Digit width of a sort: the fewest passes of at most 10 bits, then the
+// narrowest digit (8 to 10 bits) that covers the key in that many passes.
+inline int digit_bits(int bits)
+{
+    const int passes = (bits + 9) / 10;
+    const int d = (bits + passes - 1) / passes;
+    return d < 8 ? 8 : d;
+}
+
+template <class K, int BITS>
 __global__ void __launch_bounds__(SB)
 k_radix_hist(const K* __restrict__ keys, const uint32_t* __restrict__ n_dev, int shift,
              uint32_t* __restrict__ hist, unsigned nb)
 {
-    __shared__ uint32_t h[RADIX];
+    constexpr int R = 1 << BITS;
+    __shared__ uint32_t h[R];
     const int tid = threadIdx.x;
-    h[tid] = 0;
+#pragma unroll
+    for (int d = tid; d < R; d += SB) h[d] = 0;
     __syncthreads();
     const int64_t n = *n_dev;
     const int64_t base = (int64_t)blockIdx.x * SN;
 #pragma unroll 4
     for (int k = 0; k < SI; ++k) {
         int64_t idx = base + k * SB + tid;
-        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & (RADIX - 1)], 1u);
+        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & (R - 1)], 1u);
     }
     __syncthreads();
-    hist[(int64_t)tid * nb + blockIdx.x] = h[tid];
+#pragma unroll
+    for (int d = tid; d < R; d += SB) hist[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
 // Stable scatter: items are taken in index order in rounds of 256; within a
 // round the rank of an item among equal digits is its lane order inside the
-// wave plus the counts of the lower waves.
-template <class K>
+// wave (ballot match over the digit bits) plus the counts of the lower waves.
+template <class K, int BITS>
 __global__ void __launch_bounds__(SB)
 k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                 K* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int shift,
                 const uint32_t* __restrict__ offs, unsigned nb)
 {
-    __shared__ uint32_t base[RADIX];
-    __shared__ uint32_t wc[SB / WAVE][RADIX];
+    constexpr int R = 1 << BITS;
+    __shared__ uint32_t base[R];
+    __shared__ uint32_t wc[SB / WAVE][R];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int64_t n = *n_dev;
     const int64_t blk = (int64_t)blockIdx.x * SN;
     if (blk >= n) return;
-    base[tid] = offs[(int64_t)tid * nb + blockIdx.x];
 #pragma unroll
-    for (int k = 0; k < SB / WAVE; ++k) wc[k][tid] = 0;
+    for (int d = tid; d < R; d += SB) {
+        base[d] = offs[(int64_t)d * nb + blockIdx.x];
+#pragma unroll
+        for (int k = 0; k < SB / WAVE; ++k) wc[k][d] = 0;
+    }
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     for (int round = 0; round < SI; ++round) {
@@ -142,24 +157,25 @@ k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
         const bool valid = idx < n;
         K key = valid ? kin[idx] : (K)0;
         uint32_t val = valid ? vin[idx] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & (RADIX - 1);
+        uint32_t d = (uint32_t)(key >> shift) & (R - 1);
         uint64_t m = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < RADIX_BITS; ++b) {
+        for (int b = 0; b < BITS; ++b) {
             uint64_t bb = __ballot((d >> b) & 1u);
             m &= ((d >> b) & 1u) ? bb : ~bb;
         }
         uint32_t rank = (uint32_t)__popcll(m & below);
         if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(m);
         __syncthreads();
-        {
-            uint32_t b0 = base[tid];
-            uint32_t c0 = wc[0][tid], c1 = wc[1][tid], c2 = wc[2][tid], c3 = wc[3][tid];
-            wc[0][tid] = b0;
-            wc[1][tid] = b0 + c0;
-            wc[2][tid] = b0 + c0 + c1;
-            wc[3][tid] = b0 + c0 + c1 + c2;
-            base[tid] = b0 + c0 + c1 + c2 + c3;
+#pragma unroll
+        for (int dd = tid; dd < R; dd += SB) {
+            uint32_t b0 = base[dd];
+            uint32_t c0 = wc[0][dd], c1 = wc[1][dd], c2 = wc[2][dd], c3 = wc[3][dd];
+            wc[0][dd] = b0;
+            wc[1][dd] = b0 + c0;
+            wc[2][dd] = b0 + c0 + c1;
+            wc[3][dd] = b0 + c0 + c1 + c2;
+            base[dd] = b0 + c0 + c1 + c2 + c3;
         }
         __syncthreads();
         if (valid) {
@@ -169,9 +185,31 @@ k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
         }
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < SB / WAVE; ++k) wc[k][tid] = 0;
+        for (int dd = tid; dd < R; dd += SB) {
+#pragma unroll
+            for (int k = 0; k < SB / WAVE; ++k) wc[k][dd] = 0;
+        }
         __syncthreads();
     }
+}
+
+template <class K, int BITS>
+hipError_t radix_passes(K* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
+                        int bits, uint32_t* hist, uint32_t* scan_tmp, int* cur, hipStream_t s)
+{
+    constexpr int R = 1 << BITS;
+    const unsigned nb = nblocks(cap);
+    const int64_t hn = (int64_t)R * nb;
+    for (int shift = 0; shift < bits; shift += BITS) {
+        hipLaunchKernelGGL((k_radix_hist<K, BITS>), dim3(nb), dim3(SB), 0, s, keys[*cur], n_dev,
+                           shift, hist, nb);
+        hipError_t e = launch_exclusive_scan(hist, hist, hn, scan_tmp, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_radix_scatter<K, BITS>), dim3(nb), dim3(SB), 0, s, keys[*cur],
+                           vals[*cur], keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist, nb);
+        *cur ^= 1;
+    }
+    return hipGetLastError();
 }
 
 template <class K>
@@ -181,19 +219,14 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t
     int cur = 0;
     *which = 0;
     if (cap <= 0 || bits <= 0) return hipSuccess;
-    const unsigned nb = nblocks(cap);
-    const int64_t hn = (int64_t)RADIX * nb;
-    for (int shift = 0; shift < bits; shift += RADIX_BITS) {
-        hipLaunchKernelGGL(k_radix_hist<K>, dim3(nb), dim3(SB), 0, s, keys[cur], n_dev, shift,
-                           hist, nb);
-        hipError_t e = launch_exclusive_scan(hist, hist, hn, scan_tmp, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter<K>, dim3(nb), dim3(SB), 0, s, keys[cur], vals[cur],
-                           keys[cur ^ 1], vals[cur ^ 1], n_dev, shift, hist, nb);
-        cur ^= 1;
+    hipError_t e;
+    switch (digit_bits(bits)) {
+    case 8: e = radix_passes<K, 8>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
+    case 9: e = radix_passes<K, 9>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
+    default: e = radix_passes<K, 10>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
     }
     *which = cur;
-    return hipGetLastError();
+    return e;
 }
 
 __global__ void __launch_bounds__(256)
@@ -329,7 +362,14 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, u
     return hipGetLastError();
 }
 
-size_t radix_hist_words(int64_t cap) { return (size_t)RADIX * nblocks(cap > 0 ? cap : 1); }
+size_t radix_hist_words(int64_t cap) { return (size_t)MAX_RADIX * nblocks(cap > 0 ? cap : 1); }
+
+int radix_passes_for(int bits)
+{
+    if (bits <= 0) return 0;
+    const int d = digit_bits(bits);
+    return (bits + d - 1) / d;
+}
 
 hipError_t launch_radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, uint32_t* hist,
