@@ -246,6 +246,7 @@ struct Bufs {
     float2* iw = nullptr;
     uint32_t* pval[2] = {nullptr, nullptr};
     uint64_t* pmask = nullptr;      // footprint cells per computation-plane pair
+    uint64_t* psum = nullptr;       // OR of the masks of every 64 consecutive pairs
     uint2* ranges = nullptr;
     uint32_t* worklist = nullptr;   // non-empty computation-plane tiles, longest first
     // transient: projection counts and sort buffers
@@ -256,7 +257,7 @@ struct Bufs {
     uint32_t* cnt_c_sorted = nullptr;
     uint32_t* off_c = nullptr;
     uint32_t* off_i = nullptr;
-    uint64_t* dkey[2] = {nullptr, nullptr};
+    uint32_t* dkey[2] = {nullptr, nullptr};
     uint32_t* dval[2] = {nullptr, nullptr};
     uint32_t* pkey[2] = {nullptr, nullptr};
     uint32_t* hist = nullptr;
@@ -303,6 +304,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.pval[0] = a.take<uint32_t>(K);
         b.pval[1] = a.take<uint32_t>(K);
         b.pmask = a.take<uint64_t>(cap_c);
+        b.psum = a.take<uint64_t>(cap_c / WAVE + 1);
         b.ranges = a.take<uint2>(P.tiles_c + P.tiles_i);
         b.worklist = a.take<uint32_t>(P.tiles_c);
     };
@@ -314,8 +316,8 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.cnt_c_sorted = a.take<uint32_t>(R);
         b.off_c = a.take<uint32_t>(R);
         b.off_i = a.take<uint32_t>(R);
-        b.dkey[0] = a.take<uint64_t>(R);
-        b.dkey[1] = a.take<uint64_t>(R);
+        b.dkey[0] = a.take<uint32_t>(R);
+        b.dkey[1] = a.take<uint32_t>(R);
         b.dval[0] = a.take<uint32_t>(R);
         b.dval[1] = a.take<uint32_t>(R);
         b.pkey[0] = a.take<uint32_t>(K);
@@ -360,7 +362,10 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
     return SDGR_OK;
 }
 
-int passes_bits_depth(const Problem& P) { return 32 + bits_for(P.nv - 1); }
+// The depth sort orders all records by depth alone: the views need not be
+// separated, since the stable bucket sort of the pairs groups them by tile
+// (and so by view) afterwards and keeps the depth order within each tile.
+int passes_bits_depth(const Problem&) { return 32; }
 int passes_bits_pairs(const Problem& P) { return bits_for(P.tiles_c + P.tiles_i - 1); }
 int final_pair_buffer(const Problem& P) { return radix_passes_for(passes_bits_pairs(P)) & 1; }
 
@@ -380,12 +385,12 @@ int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStrea
                                    s));
     }
     // depth order of the records of every view
-    uint64_t* dk[2] = {b.dkey[0], b.dkey[1]};
+    uint32_t* dk[2] = {b.dkey[0], b.dkey[1]};
     uint32_t* dv[2] = {b.dval[0], b.dval[1]};
     int which = 0;
     {
         StageTimer t(SG_DEPTH_SORT, s);
-        SDGR_HIP(launch_radix_sort_u64(dk, dv, R, b.status + ST_RECORDS, passes_bits_depth(P),
+        SDGR_HIP(launch_radix_sort_u32(dk, dv, R, b.status + ST_RECORDS, passes_bits_depth(P),
                                        b.hist, b.scan_tmp, &which, s));
     }
     uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
@@ -396,7 +401,7 @@ int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStrea
         SDGR_HIP(launch_exclusive_scan(b.cnt_c_sorted, b.off_c, R, b.scan_tmp, s));
         SDGR_HIP(launch_exclusive_scan(b.cnt_i, b.off_i, R, b.scan_tmp, s));
         SDGR_HIP(launch_pair_totals(plan->pairs_c, plan->pairs_i, b.status, s));
-        SDGR_HIP(launch_emit_pairs(b.views, P.nv, R, dk[which], dv[which], b.rect_c, b.rect_i,
+        SDGR_HIP(launch_emit_pairs(b.views, P.nv, R, dv[which], b.rect_c, b.rect_i,
                                    b.off_c, b.off_i, plan->pairs_c, plan->pairs_i, b.status,
                                    pk[0], pv[0], s));
     }
@@ -413,7 +418,7 @@ int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStrea
     SDGR_HIP(launch_tile_ranges(pk[pw], K, b.status + ST_PAIRS_ALL, P.tiles_c + P.tiles_i,
                                 b.ranges, s));
     SDGR_HIP(launch_pair_masks(b.views, P.nv, plan->pairs_c, P.rp, b.status, pk[pw], pv[pw],
-                               b.cq, b.cw, b.pmask, s));
+                               b.cq, b.cw, b.pmask, b.psum, s));
     SDGR_HIP(launch_tile_worklist(b.ranges, P.tiles_c, b.worklist, b.status, s));
     return SDGR_OK;
 }
@@ -550,8 +555,8 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     {
         StageTimer t(SG_RASTER_A_FWD, s);
         SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, P.rp, b.status, b.worklist,
-                                     b.ranges, b.pval[pw], b.pmask, b.cq, b.cw, b.A, b.tau,
-                                     b.nlast, s));
+                                     b.ranges, b.pval[pw], b.pmask, b.psum, b.cq, b.cw, b.A,
+                                     b.tau, b.nlast, s));
     }
     {
         StageTimer t(SG_INTENSITY, s);
@@ -613,8 +618,8 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     {
         StageTimer t(SG_RASTER_A_BWD, s);
         SDGR_HIP(launch_raster_a_bwd(b.views, b.scenes, P.nv, P.tiles_c, P.rp, b.status,
-                                     b.worklist, b.ranges, b.pval[pw], b.pmask, b.cq, b.cw,
-                                     b.tau, b.nlast, b.grad_i, b.grad_c, P.records, s));
+                                     b.worklist, b.ranges, b.pval[pw], b.pmask, b.psum, b.cq,
+                                     b.cw, b.tau, b.nlast, b.grad_i, b.grad_c, P.records, s));
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,

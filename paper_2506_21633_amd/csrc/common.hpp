@@ -71,11 +71,24 @@ enum StatusSlot : int {
 };
 
 // Index of the view a global record / bucket belongs to: the last v with
-// off(v) <= x, for offsets non-decreasing in v.
+// off(v) <= x, for offsets non-decreasing in v. The lanes of a wave almost
+// always fall in one view, so the search runs once for the first active
+// lane on wave-uniform values (scalar loads); only lanes outside that view
+// search on their own.
 template <class F>
 __device__ __forceinline__ int find_view(int nv, int64_t x, F off)
 {
+    const uint32_t xlo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    const uint32_t xhi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+    const int64_t x0 = (int64_t)(((uint64_t)xhi << 32) | xlo);
     int lo = 0, hi = nv - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off(mid) <= x0) lo = mid; else hi = mid - 1;
+    }
+    if (off(lo) <= x && (lo + 1 >= nv || x < off(lo + 1))) return lo;
+    lo = 0;
+    hi = nv - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (off(mid) <= x) lo = mid; else hi = mid - 1;
@@ -125,7 +138,7 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
                              int64_t records, const RasterParams& rp,
                              bool write_records, float4* cq, float2* cw, float4* iq,
                              float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* cnt_c,
-                             uint32_t* cnt_i, uint64_t* dkey, uint32_t* dval,
+                             uint32_t* cnt_i, uint32_t* dkey, uint32_t* dval,
                              unsigned long long* slots, unsigned long long* totals,
                              hipStream_t s);
 
@@ -152,9 +165,6 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
 // the input; returns in *which the index of the buffer holding the output.
 size_t radix_hist_words(int64_t cap);
 int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
-hipError_t launch_radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], int64_t cap,
-                                 const uint32_t* n_dev, int bits, uint32_t* hist,
-                                 uint32_t* scan_tmp, int* which, hipStream_t s);
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, uint32_t* hist,
                                  uint32_t* scan_tmp, int* which, hipStream_t s);
@@ -164,7 +174,7 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* cnt, int6
 // overflow check and actual pair counts from the projection's u64 totals
 hipError_t launch_pair_totals(int64_t cap_c, int64_t cap_i, uint32_t* status, hipStream_t s);
 hipError_t launch_emit_pairs(const DevView* views, int nv, int64_t records,
-                             const uint64_t* dkey_sorted, const uint32_t* dval_sorted,
+                             const uint32_t* dval_sorted,
                              const uint2* rect_c, const uint2* rect_i,
                              const uint32_t* off_c, const uint32_t* off_i,
                              int64_t cap_c, int64_t cap_i, const uint32_t* status,
@@ -177,15 +187,15 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
 hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const RasterParams& rp,
                              const uint32_t* status, const uint32_t* pkey,
                              const uint32_t* pvals, const float4* cq, const float2* cw,
-                             uint64_t* pmask, hipStream_t s);
+                             uint64_t* pmask, uint64_t* psum, hipStream_t s);
 hipError_t launch_tile_worklist(const uint2* ranges, int64_t tiles_c, uint32_t* worklist,
                                 uint32_t* status, hipStream_t s);
 hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
-                               const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
-                               const float2* cw, float* A, float* tau, uint32_t* nlast,
-                               hipStream_t s);
+                               const uint32_t* pvals, const uint64_t* pmask,
+                               const uint64_t* psum, const float4* cq, const float2* cw,
+                               float* A, float* tau, uint32_t* nlast, hipStream_t s);
 hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_i,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
@@ -196,9 +206,9 @@ hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
 hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
                                int64_t tiles_c, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
-                               const uint32_t* pvals, const uint64_t* pmask, const float4* cq,
-                               const float2* cw, const float* tau, const uint32_t* nlast,
-                               const float* grad_i, float* grad_c, int64_t stride,
-                               hipStream_t s);
+                               const uint32_t* pvals, const uint64_t* pmask,
+                               const uint64_t* psum, const float4* cq, const float2* cw,
+                               const float* tau, const uint32_t* nlast, const float* grad_i,
+                               float* grad_c, int64_t stride, hipStream_t s);
 
 }  // namespace sdgr

@@ -167,7 +167,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
              float2* __restrict__ cw, float4* __restrict__ iq, float2* __restrict__ iw,
              uint2* __restrict__ rect_c, uint2* __restrict__ rect_i,
              uint32_t* __restrict__ cnt_c, uint32_t* __restrict__ cnt_i,
-             uint64_t* __restrict__ dkey, uint32_t* __restrict__ dval,
+             uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
              unsigned long long* __restrict__ totals)
 {
     __shared__ unsigned long long part[2];
@@ -239,7 +239,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
             rect_i[r] = ri;
             cnt_c[r] = nc;
             cnt_i[r] = ni;
-            dkey[r] = ((uint64_t)(uint32_t)v << 32) | float_order_bits(__uint_as_float(zbits));
+            dkey[r] = float_order_bits(__uint_as_float(zbits));
             dval[r] = (uint32_t)r;
         }
     }
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int n)
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
                              int64_t records, const RasterParams& rp, bool write_records,
                              float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
-                             uint2* rect_i, uint32_t* cnt_c, uint32_t* cnt_i, uint64_t* dkey,
+                             uint2* rect_i, uint32_t* cnt_c, uint32_t* cnt_i, uint32_t* dkey,
                              uint32_t* dval, unsigned long long* slots,
                              unsigned long long* totals, hipStream_t s)
 {

@@ -3,8 +3,9 @@
 // intensity is computed along depth-indexed Gaussian lists; the third radar
 // coordinate serves as the sorting depth).
 //
-//   1. records are sorted by (view, fl32 depth, index) with a stable LSD
-//      radix sort of 64-bit keys (index order is the initial order);
+//   1. records of all views are sorted by (fl32 depth, index) with a stable
+//      LSD radix sort of 32-bit keys (index order is the initial order);
+//      the views stay interleaved, which step 3 undoes;
 //   2. their pair counts are scanned in that order and every record emits
 //      (tile bucket, record) pairs -- computation-plane pairs in depth order,
 //      imaging-plane pairs in index order;
@@ -104,116 +105,184 @@ inline int digit_bits(int bits)
     return d < 8 ? 8 : d;
 }
 
-template <class K, int BITS>
+// Block digit histogram. Keys are often long runs of one digit (pair keys
+// are tile ids of a few busy tiles), so each wave first groups its lanes by
+// digit (ballot match over the digit bits) and only one lane per digit adds
+// the group's count: same-address LDS atomics would serialise 64-fold.
+template <int BITS>
 __global__ void __launch_bounds__(SB)
-k_radix_hist(const K* __restrict__ keys, const uint32_t* __restrict__ n_dev, int shift,
+k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int shift,
              uint32_t* __restrict__ hist, unsigned nb)
 {
     constexpr int R = 1 << BITS;
     __shared__ uint32_t h[R];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
 #pragma unroll
     for (int d = tid; d < R; d += SB) h[d] = 0;
     __syncthreads();
     const int64_t n = *n_dev;
     const int64_t base = (int64_t)blockIdx.x * SN;
-#pragma unroll 4
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    uint32_t key[SI];
+#pragma unroll
     for (int k = 0; k < SI; ++k) {
-        int64_t idx = base + k * SB + tid;
-        if (idx < n) atomicAdd(&h[(uint32_t)(keys[idx] >> shift) & (R - 1)], 1u);
+        const int64_t idx = base + k * SB + tid;
+        key[k] = idx < n ? keys[idx] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < SI; ++k) {
+        const int64_t idx = base + k * SB + tid;
+        const bool valid = idx < n;
+        const uint32_t d = (key[k] >> shift) & (R - 1);
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < BITS; ++b) {
+            const uint64_t bb = __ballot((d >> b) & 1u);
+            m &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        if (valid && (m & below) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(m));
     }
     __syncthreads();
 #pragma unroll
     for (int d = tid; d < R; d += SB) hist[(int64_t)d * nb + blockIdx.x] = h[d];
 }
 
-// Stable scatter: items are taken in index order in rounds of 256; within a
-// round the rank of an item among equal digits is its lane order inside the
-// wave (ballot match over the digit bits) plus the counts of the lower waves.
-template <class K, int BITS>
+// Stable scatter of one 4096-item block. Each wave ranks its own 1024
+// consecutive items in 16 rounds of 64 (ballot match over the digit bits,
+// per-wave digit counters in LDS, no block barrier); the block then turns
+// the per-wave counts into digit-major local offsets, places the items in
+// LDS in digit order and writes them out so that the items of one digit
+// leave as a contiguous run.
+template <int BITS>
 __global__ void __launch_bounds__(SB)
-k_radix_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                K* __restrict__ kout, uint32_t* __restrict__ vout,
+k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int shift,
                 const uint32_t* __restrict__ offs, unsigned nb)
 {
     constexpr int R = 1 << BITS;
-    __shared__ uint32_t base[R];
-    __shared__ uint32_t wc[SB / WAVE][R];
+    constexpr int NW = SB / WAVE;
+    constexpr int DPT = R / SB;                  // digits per thread
+    __shared__ uint32_t wc[NW][R];              // per-wave digit counters, then offsets
+    __shared__ uint32_t gbase[R];               // global position minus local offset
+    __shared__ uint32_t wsum[NW];
+    __shared__ uint32_t s_key[SN];
+    __shared__ uint32_t s_val[SN];
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     const int64_t n = *n_dev;
     const int64_t blk = (int64_t)blockIdx.x * SN;
     if (blk >= n) return;
+    const uint32_t cnt_blk = (uint32_t)min((int64_t)SN, n - blk);
 #pragma unroll
-    for (int d = tid; d < R; d += SB) {
-        base[d] = offs[(int64_t)d * nb + blockIdx.x];
+    for (int k = 0; k < DPT; ++k)
 #pragma unroll
-        for (int k = 0; k < SB / WAVE; ++k) wc[k][d] = 0;
-    }
+        for (int ww = 0; ww < NW; ++ww) wc[ww][tid * DPT + k] = 0u;
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    for (int round = 0; round < SI; ++round) {
-        const int64_t idx = blk + round * SB + tid;
+    uint32_t key[SI], val[SI], rank[SI];
+#pragma unroll
+    for (int k = 0; k < SI; ++k) {
+        const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
         const bool valid = idx < n;
-        K key = valid ? kin[idx] : (K)0;
-        uint32_t val = valid ? vin[idx] : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & (R - 1);
+        key[k] = valid ? kin[idx] : 0u;
+        val[k] = valid ? vin[idx] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < SI; ++k) {
+        const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
+        const bool valid = idx < n;
+        const uint32_t d = (key[k] >> shift) & (R - 1);
         uint64_t m = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < BITS; ++b) {
-            uint64_t bb = __ballot((d >> b) & 1u);
+            const uint64_t bb = __ballot((d >> b) & 1u);
             m &= ((d >> b) & 1u) ? bb : ~bb;
         }
-        uint32_t rank = (uint32_t)__popcll(m & below);
-        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(m);
-        __syncthreads();
+        const uint32_t before = valid ? wc[w][d] : 0u;
+        rank[k] = before + (uint32_t)__popcll(m & below);
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (m & below) == 0ull) wc[w][d] = before + (uint32_t)__popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    __syncthreads();
+    // digit totals of the block, exclusive scan over digits (digit-major)
+    uint32_t tot[DPT], run = 0u;
 #pragma unroll
-        for (int dd = tid; dd < R; dd += SB) {
-            uint32_t b0 = base[dd];
-            uint32_t c0 = wc[0][dd], c1 = wc[1][dd], c2 = wc[2][dd], c3 = wc[3][dd];
-            wc[0][dd] = b0;
-            wc[1][dd] = b0 + c0;
-            wc[2][dd] = b0 + c0 + c1;
-            wc[3][dd] = b0 + c0 + c1 + c2;
-            base[dd] = b0 + c0 + c1 + c2 + c3;
-        }
-        __syncthreads();
-        if (valid) {
-            uint32_t pos = wc[w][d] + rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
+    for (int k = 0; k < DPT; ++k) {
+        uint32_t t = 0u;
 #pragma unroll
-        for (int dd = tid; dd < R; dd += SB) {
+        for (int ww = 0; ww < NW; ++ww) t += wc[ww][tid * DPT + k];
+        tot[k] = t;
+        run += t;
+    }
+    uint32_t inc = run;
 #pragma unroll
-            for (int k = 0; k < SB / WAVE; ++k) wc[k][dd] = 0;
+    for (int dd = 1; dd < WAVE; dd <<= 1) {
+        const uint32_t t = __shfl_up(inc, dd, WAVE);
+        if (lane >= dd) inc += t;
+    }
+    if (lane == WAVE - 1) wsum[w] = inc;
+    __syncthreads();
+    uint32_t lofs = inc - run;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww)
+        if (ww < w) lofs += wsum[ww];
+#pragma unroll
+    for (int k = 0; k < DPT; ++k) {
+        const int d = tid * DPT + k;
+        gbase[d] = offs[(int64_t)d * nb + blockIdx.x] - lofs;
+        uint32_t o = lofs;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t c = wc[ww][d];
+            wc[ww][d] = o;
+            o += c;
         }
-        __syncthreads();
+        lofs += tot[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < SI; ++k) {
+        const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
+        if (idx < n) {
+            const uint32_t d = (key[k] >> shift) & (R - 1);
+            const uint32_t pos = wc[w][d] + rank[k];
+            s_key[pos] = key[k];
+            s_val[pos] = val[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (uint32_t i = tid; i < cnt_blk; i += SB) {
+        const uint32_t k = s_key[i];
+        const uint32_t g = gbase[(k >> shift) & (R - 1)] + i;
+        kout[g] = k;
+        vout[g] = s_val[i];
     }
 }
 
-template <class K, int BITS>
-hipError_t radix_passes(K* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
+template <int BITS>
+hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, uint32_t* hist, uint32_t* scan_tmp, int* cur, hipStream_t s)
 {
     constexpr int R = 1 << BITS;
     const unsigned nb = nblocks(cap);
     const int64_t hn = (int64_t)R * nb;
     for (int shift = 0; shift < bits; shift += BITS) {
-        hipLaunchKernelGGL((k_radix_hist<K, BITS>), dim3(nb), dim3(SB), 0, s, keys[*cur], n_dev,
+        hipLaunchKernelGGL((k_radix_hist<BITS>), dim3(nb), dim3(SB), 0, s, keys[*cur], n_dev,
                            shift, hist, nb);
         hipError_t e = launch_exclusive_scan(hist, hist, hn, scan_tmp, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_radix_scatter<K, BITS>), dim3(nb), dim3(SB), 0, s, keys[*cur],
+        hipLaunchKernelGGL((k_radix_scatter<BITS>), dim3(nb), dim3(SB), 0, s, keys[*cur],
                            vals[*cur], keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist, nb);
         *cur ^= 1;
     }
     return hipGetLastError();
 }
 
-template <class K>
-hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
+hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                       int bits, uint32_t* hist, uint32_t* scan_tmp, int* which, hipStream_t s)
 {
     int cur = 0;
@@ -221,9 +290,9 @@ hipError_t radix_sort(K* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t
     if (cap <= 0 || bits <= 0) return hipSuccess;
     hipError_t e;
     switch (digit_bits(bits)) {
-    case 8: e = radix_passes<K, 8>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
-    case 9: e = radix_passes<K, 9>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
-    default: e = radix_passes<K, 10>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
+    case 8: e = radix_passes<8>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
+    case 9: e = radix_passes<9>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
+    default: e = radix_passes<10>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
     }
     *which = cur;
     return e;
@@ -252,7 +321,7 @@ __global__ void k_pair_totals(int64_t cap_c, int64_t cap_i, uint32_t* status)
 
 __global__ void __launch_bounds__(256)
 k_emit(const DevView* __restrict__ views, int nv, int64_t records,
-       const uint64_t* __restrict__ dkey, const uint32_t* __restrict__ dval,
+       const uint32_t* __restrict__ dval,
        const uint2* __restrict__ rect_c, const uint2* __restrict__ rect_i,
        const uint32_t* __restrict__ off_c, const uint32_t* __restrict__ off_i,
        int64_t cap_c, int64_t cap_i, const uint32_t* __restrict__ status,
@@ -264,7 +333,7 @@ k_emit(const DevView* __restrict__ views, int nv, int64_t records,
     if (status[ST_OVERFLOW]) return;
     {   // computation plane, depth-sorted position p
         const uint32_t r = dval[p];
-        const int v = (int)(dkey[p] >> 32);
+        const int v = find_view(nv, (int64_t)r, [&](int k) { return views[k].rec_off; });
         const DevView& V = views[v];
         const uint2 rc = rect_c[r];
         const uint32_t tx0 = rc.x & 0xFFFF, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFF,
@@ -371,18 +440,11 @@ int radix_passes_for(int bits)
     return (bits + d - 1) / d;
 }
 
-hipError_t launch_radix_sort_u64(uint64_t* keys[2], uint32_t* vals[2], int64_t cap,
-                                 const uint32_t* n_dev, int bits, uint32_t* hist,
-                                 uint32_t* scan_tmp, int* which, hipStream_t s)
-{
-    return radix_sort<uint64_t>(keys, vals, cap, n_dev, bits, hist, scan_tmp, which, s);
-}
-
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, uint32_t* hist,
                                  uint32_t* scan_tmp, int* which, hipStream_t s)
 {
-    return radix_sort<uint32_t>(keys, vals, cap, n_dev, bits, hist, scan_tmp, which, s);
+    return radix_sort(keys, vals, cap, n_dev, bits, hist, scan_tmp, which, s);
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
@@ -407,7 +469,7 @@ hipError_t launch_pair_totals(int64_t cap_c, int64_t cap_i, uint32_t* status, hi
 }
 
 hipError_t launch_emit_pairs(const DevView* views, int nv, int64_t records,
-                             const uint64_t* dkey_sorted, const uint32_t* dval_sorted,
+                             const uint32_t* dval_sorted,
                              const uint2* rect_c, const uint2* rect_i, const uint32_t* off_c,
                              const uint32_t* off_i, int64_t cap_c, int64_t cap_i,
                              const uint32_t* status, uint32_t* pkey, uint32_t* pval,
@@ -415,7 +477,7 @@ hipError_t launch_emit_pairs(const DevView* views, int nv, int64_t records,
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
-                       dkey_sorted, dval_sorted, rect_c, rect_i, off_c, off_i, cap_c, cap_i,
+                       dval_sorted, rect_c, rect_i, off_c, off_i, cap_c, cap_i,
                        status, pkey, pval);
     return hipGetLastError();
 }
