@@ -129,7 +129,9 @@ typedef struct sdgr_plan {
     size_t image_floats;       /* minimum length of images / dL_dimages */
     int64_t records;           /* sum over views of the scene's n */
     int64_t pairs_c;           /* (Gaussian, tile) pairs, computation plane */
-    int64_t pairs_i;           /* (Gaussian, tile) pairs, imaging plane */
+    int64_t pairs_i;           /* (Gaussian, tile) pairs, imaging plane, of
+                                  all Gaussians: a capacity, since only those
+                                  with a nonzero intensity emit pairs */
     int64_t tiles_c, tiles_i;  /* tiles over all views */
     int64_t rays;              /* computation-plane cells over all views */
     int32_t nviews, nscenes;

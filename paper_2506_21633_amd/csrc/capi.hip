@@ -38,12 +38,12 @@ int hip_fail(hipError_t e, const char* where)
 enum Stage {
     SG_QUERY, SG_PREPROCESS, SG_DEPTH_SORT, SG_BIN, SG_PAIR_SORT, SG_RANGES,
     SG_RASTER_A_FWD, SG_INTENSITY, SG_RASTER_B_FWD, SG_ZERO, SG_RASTER_B_BWD,
-    SG_RASTER_A_BWD, SG_PARAMS_BWD, SG_COUNT
+    SG_RASTER_A_BWD, SG_PARAMS_BWD, SG_BIN_I, SG_PAIR_SORT_I, SG_COUNT
 };
 const char* const kStageNames[SG_COUNT] = {
     "plan_query", "preprocess", "depth_sort", "bin_pairs", "pair_sort", "tile_ranges",
     "raster_a_fwd", "set_intensity", "raster_b_fwd", "zero_grads", "raster_b_bwd",
-    "raster_a_bwd", "params_bwd"};
+    "raster_a_bwd", "params_bwd", "bin_pairs_i", "pair_sort_i"};
 
 struct Profiler {
     std::mutex mu;
@@ -255,6 +255,7 @@ struct Bufs {
     uint32_t* cnt_c = nullptr;
     uint32_t* cnt_i = nullptr;
     uint32_t* cnt_c_sorted = nullptr;
+    uint2* rect_c_sorted = nullptr;
     uint32_t* off_c = nullptr;
     uint32_t* off_i = nullptr;
     uint32_t* dkey[2] = {nullptr, nullptr};
@@ -305,7 +306,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.pval[1] = a.take<uint32_t>(K);
         b.pmask = a.take<uint64_t>(cap_c);
         b.psum = a.take<uint64_t>(cap_c / WAVE + 1);
-        b.ranges = a.take<uint2>(P.tiles_c + P.tiles_i);
+        b.ranges = a.take<uint2>(P.tiles_c);
         b.worklist = a.take<uint32_t>(P.tiles_c);
     };
     auto transient = [&](Arena& a) {
@@ -314,6 +315,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.cnt_c = a.take<uint32_t>(R);
         b.cnt_i = a.take<uint32_t>(R);
         b.cnt_c_sorted = a.take<uint32_t>(R);
+        b.rect_c_sorted = a.take<uint2>(R);
         b.off_c = a.take<uint32_t>(R);
         b.off_i = a.take<uint32_t>(R);
         b.dkey[0] = a.take<uint32_t>(R);
@@ -366,12 +368,16 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
 // separated, since the stable bucket sort of the pairs groups them by tile
 // (and so by view) afterwards and keeps the depth order within each tile.
 int passes_bits_depth(const Problem&) { return 32; }
-int passes_bits_pairs(const Problem& P) { return bits_for(P.tiles_c + P.tiles_i - 1); }
-int final_pair_buffer(const Problem& P) { return radix_passes_for(passes_bits_pairs(P)) & 1; }
+// Computation-plane buckets are [0, tiles_c); imaging-plane buckets follow.
+int bits_pairs_c(const Problem& P) { return bits_for(P.tiles_c - 1); }
+int bits_pairs_i(const Problem& P) { return bits_for(P.tiles_c + P.tiles_i - 1); }
+int final_buffer_c(const Problem& P) { return radix_passes_for(bits_pairs_c(P)) & 1; }
+int final_buffer_i(const Problem& P) { return radix_passes_for(bits_pairs_i(P)) & 1; }
 
-// Projection, binning, sorting and tile ranges (shared by the forward and
-// the recomputing backward).
-int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStream_t s)
+// Projection, depth sort and the computation-plane lists: binning, the
+// stable bucket sort, tile ranges, footprint masks and the tile worklist
+// (shared by the forward and the recomputing backward).
+int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStream_t s)
 {
     const int64_t R = P.records;
     SDGR_HIP(launch_fill_u32(b.status, 0u, STATUS_WORDS, s));
@@ -397,29 +403,50 @@ int build_lists(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStrea
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};
     {
         StageTimer t(SG_BIN, s);
-        SDGR_HIP(launch_gather_counts(dv[which], b.cnt_c, R, b.cnt_c_sorted, s));
+        SDGR_HIP(launch_gather_rects(dv[which], b.rect_c, R, b.rect_c_sorted, b.cnt_c_sorted, s));
         SDGR_HIP(launch_exclusive_scan(b.cnt_c_sorted, b.off_c, R, b.scan_tmp, s));
-        SDGR_HIP(launch_exclusive_scan(b.cnt_i, b.off_i, R, b.scan_tmp, s));
-        SDGR_HIP(launch_pair_totals(plan->pairs_c, plan->pairs_i, b.status, s));
-        SDGR_HIP(launch_emit_pairs(b.views, P.nv, R, dv[which], b.rect_c, b.rect_i,
-                                   b.off_c, b.off_i, plan->pairs_c, plan->pairs_i, b.status,
-                                   pk[0], pv[0], s));
+        SDGR_HIP(launch_pair_total_c(plan->pairs_c, b.status, s));
+        SDGR_HIP(launch_emit_pairs_c(b.views, P.nv, R, dv[which], b.rect_c_sorted, b.off_c,
+                                     plan->pairs_c, b.status, pk[0], pv[0], s));
     }
     int pw = 0;
-    const int64_t K = plan->pairs_c + plan->pairs_i;
     {
         StageTimer t(SG_PAIR_SORT, s);
-        SDGR_HIP(launch_radix_sort_u32(pk, pv, K, b.status + ST_PAIRS_ALL,
-                                       passes_bits_pairs(P), b.hist, b.scan_tmp, &pw, s));
+        SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_c, b.status + ST_PAIRS_C,
+                                       bits_pairs_c(P), b.hist, b.scan_tmp, &pw, s));
     }
-    if (K > 0 && pw != final_pair_buffer(P))
+    if (plan->pairs_c > 0 && pw != final_buffer_c(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
     StageTimer t(SG_RANGES, s);
-    SDGR_HIP(launch_tile_ranges(pk[pw], K, b.status + ST_PAIRS_ALL, P.tiles_c + P.tiles_i,
+    SDGR_HIP(launch_tile_ranges(pk[pw], plan->pairs_c, b.status + ST_PAIRS_C, P.tiles_c,
                                 b.ranges, s));
     SDGR_HIP(launch_pair_masks(b.views, P.nv, plan->pairs_c, P.rp, b.status, pk[pw], pv[pw],
                                b.cq, b.cw, b.pmask, b.psum, s));
     SDGR_HIP(launch_tile_worklist(b.ranges, P.tiles_c, b.worklist, b.status, s));
+    return SDGR_OK;
+}
+
+// Imaging-plane lists, after pass A: only records with nonzero intensity
+// emit pairs (counted by the intensity kernel), which a stable bucket sort
+// groups by tile behind the computation-plane part of the pair arrays.
+int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStream_t s)
+{
+    const int64_t R = P.records;
+    uint32_t* pk[2] = {b.pkey[0] + plan->pairs_c, b.pkey[1] + plan->pairs_c};
+    uint32_t* pv[2] = {b.pval[0] + plan->pairs_c, b.pval[1] + plan->pairs_c};
+    {
+        StageTimer t(SG_BIN_I, s);
+        SDGR_HIP(launch_exclusive_scan(b.cnt_i, b.off_i, R, b.scan_tmp, s));
+        SDGR_HIP(launch_pair_total_i(b.off_i, b.cnt_i, R, plan->pairs_i, b.status, s));
+        SDGR_HIP(launch_emit_pairs_i(b.views, P.nv, R, b.rect_i, b.cnt_i, b.off_i, plan->pairs_c,
+                                     plan->pairs_i, b.status, b.pkey[0], b.pval[0], s));
+    }
+    int pw = 0;
+    StageTimer t(SG_PAIR_SORT_I, s);
+    SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_i, b.status + ST_PAIRS_I, bits_pairs_i(P),
+                                   b.hist, b.scan_tmp, &pw, s));
+    if (plan->pairs_i > 0 && pw != final_buffer_i(P))
+        return fail(SDGR_EHIP, "internal: pair buffer parity");
     return SDGR_OK;
 }
 
@@ -547,8 +574,8 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
            nullptr);
     if (g_count_work) P.rp.work = reinterpret_cast<unsigned long long*>(b.status + WORK_WORD);
     if ((rc = upload_tables(P, b, s))) return rc;
-    if ((rc = build_lists(P, plan, b, s))) return rc;
-    const int pw = final_pair_buffer(P);
+    if ((rc = build_lists_c(P, plan, b, s))) return rc;
+    const int pw = final_buffer_c(P);
     SDGR_HIP(launch_fill_u32((uint32_t*)b.A, 0u, P.records, s));
     SDGR_HIP(launch_fill_u32((uint32_t*)b.tau, 0u, P.rays, s));   // rays of empty tiles
     SDGR_HIP(launch_fill_u32(b.nlast, 0u, P.rays, s));
@@ -560,11 +587,14 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     }
     {
         StageTimer t(SG_INTENSITY, s);
-        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, s));
+        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, b.rect_i,
+                                      b.cnt_i, s));
     }
+    if ((rc = build_lists_i(P, plan, b, s))) return rc;
+    const int pwi = final_buffer_i(P);
     StageTimer t(SG_RASTER_B_FWD, s);
-    SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.pixels, plan->pairs_i, P.rp, b.status,
-                                 b.pkey[pw], b.pval[pw], b.iq, b.iw, images, s));
+    SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.pixels, plan->pairs_c, plan->pairs_i, P.rp,
+                                 b.status, b.pkey[pwi], b.pval[pwi], b.iq, b.iw, images, s));
     return SDGR_OK;
 }
 
@@ -602,10 +632,11 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     if (P.recompute) {
         // the forward's lists are gone: rebuild them (identical, the sorts
         // are deterministic) and refill the intensities from the kept A
-        if ((rc = build_lists(P, plan, b, s))) return rc;
-        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, s));
+        if ((rc = build_lists_c(P, plan, b, s))) return rc;
+        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, nullptr,
+                                      nullptr, s));
     }
-    const int pw = final_pair_buffer(P);
+    const int pw = final_buffer_c(P);
     {
         StageTimer t(SG_ZERO, s);
         SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_c, 0u, 6 * P.records, s));

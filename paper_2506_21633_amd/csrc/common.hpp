@@ -63,9 +63,8 @@ constexpr int WORK_WORD = 16;   // work counters live at status + 16 (8 x u64)
 // Device-side scalars kept at the start of the state buffer.
 enum StatusSlot : int {
     ST_OVERFLOW = 0,   // nonzero if pairs exceeded the planned capacity
-    ST_PAIRS_C = 1,    // actual pair counts of the last projection
-    ST_PAIRS_I = 2,
-    ST_PAIRS_ALL = 3,  // min(pairs_c + pairs_i, capacity), sort length
+    ST_PAIRS_C = 1,    // computation-plane pairs of the last projection (sort length)
+    ST_PAIRS_I = 2,    // imaging-plane pairs of records with nonzero intensity
     ST_WORK_TILES = 4, // non-empty computation-plane tiles in the worklist
     ST_COUNT = 8       // u64 pair totals of the projection at status + 8
 };
@@ -125,6 +124,41 @@ __device__ __forceinline__ float wave_sum(float v)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+__device__ __forceinline__ float quadform(float4 g, float c, float dx, float dy)
+{
+    return g.z * dx * dx + 2.0f * g.w * dx * dy + c * dy * dy;
+}
+
+// Cells of tile (tx, ty) inside the ellipse q < q_max of a Gaussian with
+// centre (cx, cy) and conic (a, b, c): per row the exact column span from
+// the quadratic, widened by a small slack. Bit 8 * row + col.
+__device__ inline uint64_t footprint_mask(float cx, float cy, float a, float b, float c, float qm,
+                                   int tx, int ty)
+{
+    const float det = a * c - b * b;
+    if (!(det > 0.0f) || !(a > 0.0f)) return 0ull;
+    const float slack = 1e-3f;
+    uint64_t m = 0ull;
+    const float x0 = (float)(tx * TILE);
+#pragma unroll
+    for (int k = 0; k < TILE; ++k) {
+        const float dy = (float)(ty * TILE + k) + 0.5f - cy;
+        const float D = a * qm - det * dy * dy;
+        if (D < 0.0f) continue;
+        const float half = sqrtf(D) / a + slack;
+        const float xc = cx - b * dy / a;
+        // local columns j with |x0 + j + 1/2 - xc| <= half
+        const float lo = fmaxf(ceilf(xc - half - 0.5f - x0), 0.0f);
+        const float hi = fminf(floorf(xc + half - 0.5f - x0), (float)(TILE - 1));
+        if (lo > hi) continue;
+        const uint32_t j0 = (uint32_t)lo, j1 = (uint32_t)hi;
+        const uint64_t row_bits = ((1ull << (j1 - j0 + 1)) - 1ull) << j0;
+        m |= row_bits << (TILE * k);
+    }
+    return m;
+}
+
+
 }  // namespace sdgr
 
 // ---- host-side launchers (defined in the .hip files) ----------------------
@@ -144,7 +178,7 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
 
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
                                 int64_t records, const float* A, float2* iw,
-                                hipStream_t s);
+                                const uint2* rect_i, uint32_t* cnt_i, hipStream_t s);
 
 // Per-record gradient buffers are plane-major: component k of record r at
 // [k * records + r]; grad_c = (dcx, dcy, da, db, dc, dkappa) on the
@@ -169,16 +203,21 @@ hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t c
                                  const uint32_t* n_dev, int bits, uint32_t* hist,
                                  uint32_t* scan_tmp, int* which, hipStream_t s);
 
-hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* cnt, int64_t n,
-                                uint32_t* out, hipStream_t s);
+hipError_t launch_gather_rects(const uint32_t* order, const uint2* rect, int64_t n,
+                               uint2* rect_sorted, uint32_t* cnt_sorted, hipStream_t s);
 // overflow check and actual pair counts from the projection's u64 totals
-hipError_t launch_pair_totals(int64_t cap_c, int64_t cap_i, uint32_t* status, hipStream_t s);
-hipError_t launch_emit_pairs(const DevView* views, int nv, int64_t records,
-                             const uint32_t* dval_sorted,
-                             const uint2* rect_c, const uint2* rect_i,
-                             const uint32_t* off_c, const uint32_t* off_i,
-                             int64_t cap_c, int64_t cap_i, const uint32_t* status,
-                             uint32_t* pkey, uint32_t* pval, hipStream_t s);
+hipError_t launch_pair_total_c(int64_t cap_c, uint32_t* status, hipStream_t s);
+hipError_t launch_pair_total_i(const uint32_t* off_i, const uint32_t* cnt_i, int64_t records,
+                               int64_t cap_i, uint32_t* status, hipStream_t s);
+hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
+                               const uint32_t* dval_sorted, const uint2* rect_sorted,
+                               const uint32_t* off_c, int64_t cap_c, const uint32_t* status,
+                               uint32_t* pkey, uint32_t* pval, hipStream_t s);
+hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
+                               const uint2* rect_i, const uint32_t* cnt_i,
+                               const uint32_t* off_i, int64_t cap_c, int64_t cap_i,
+                               const uint32_t* status, uint32_t* pkey, uint32_t* pval,
+                               hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, int64_t cap, const uint32_t* n_dev,
                               int64_t buckets, uint2* ranges, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
@@ -196,8 +235,8 @@ hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
                                const uint32_t* pvals, const uint64_t* pmask,
                                const uint64_t* psum, const float4* cq, const float2* cw,
                                float* A, float* tau, uint32_t* nlast, hipStream_t s);
-hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_i,
-                               const RasterParams& rp, const uint32_t* status,
+hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_c,
+                               int64_t cap_i, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
                                const float2* iw, float* images, hipStream_t s);
 hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,

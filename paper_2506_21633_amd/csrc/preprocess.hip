@@ -264,16 +264,27 @@ k_sum_slots(const unsigned long long* __restrict__ slots, unsigned long long* __
     if (threadIdx.x < 2) out[threadIdx.x] = acc[threadIdx.x];
 }
 
+// I = P A into the imaging record (incident intensity 1, Sec. II-A); with
+// rect_i given, also the imaging-plane pair count of the record: the tiles
+// of its rectangle if I is nonzero, none otherwise (a zero intensity adds
+// nothing to any pixel).
 __global__ void __launch_bounds__(256)
 k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
-                int64_t records, const float* __restrict__ A, float2* __restrict__ iw)
+                int64_t records, const float* __restrict__ A, float2* __restrict__ iw,
+                const uint2* __restrict__ rect_i, uint32_t* __restrict__ cnt_i)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= records) return;
     int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
     const DevView& V = views[v];
-    float p = scenes[V.scene].amp[r - V.rec_off];
-    iw[r].y = p * A[r];
+    const float p = scenes[V.scene].amp[r - V.rec_off];
+    const float I = p * A[r];
+    iw[r].y = I;
+    if (cnt_i) {
+        const uint2 ri = rect_i[r];
+        const uint32_t area = ((ri.x >> 16) - (ri.x & 0xFFFF)) * ((ri.y >> 16) - (ri.y & 0xFFFF));
+        cnt_i[r] = I != 0.0f ? area : 0u;
+    }
 }
 
 // Adjoint of one plane: conic gradient (a, b, c with q = a dx^2 + 2 b dx dy
@@ -412,11 +423,12 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
 }
 
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
-                                int64_t records, const float* A, float2* iw, hipStream_t s)
+                                int64_t records, const float* A, float2* iw, const uint2* rect_i,
+                                uint32_t* cnt_i, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_set_intensity, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
-                       scenes, nv, records, A, iw);
+                       scenes, nv, records, A, iw, rect_i, cnt_i);
     return hipGetLastError();
 }
 

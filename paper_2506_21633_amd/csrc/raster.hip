@@ -64,7 +64,8 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int d)
 
 // 64x64 bit-matrix transpose across the wave: on return, bit j of lane i is
 // bit i of lane j's input. Recursive block swap: at step s, lanes i and
-// i ^ s exchange the s-wide bit blocks that sit off the diagonal.
+// i ^ s exchange the s-wide bit blocks that sit off the diagonal (written
+// with selects, no divergent branches).
 __device__ __forceinline__ uint64_t transpose64(uint64_t v)
 {
     const int lane = lane_id();
@@ -76,7 +77,10 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t v)
         const int s = 32 >> k;
         const uint64_t lo = LO[k];
         const uint64_t p = shfl_xor_u64(v, s);
-        v = (lane & s) ? ((v & ~lo) | ((p & ~lo) >> s)) : ((v & lo) | ((p & lo) << s));
+        const bool up = (lane & s) != 0;
+        const uint64_t keep = up ? ~lo : lo;
+        const uint64_t moved = up ? ((p & ~lo) >> s) : ((p & lo) << s);
+        v = (v & keep) | moved;
     }
     return v;
 }
@@ -93,6 +97,70 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t v)
 #pragma unroll
     for (int d = 1; d < WAVE; d <<= 1) v |= shfl_xor_u64(v, d);
     return v;
+}
+
+// Segmented inclusive prefix sum over lanes: lane l adds the lanes
+// [seg0, l] of its segment (seg0 <= l is the first lane of the segment).
+__device__ __forceinline__ float seg_incl_scan(float x, int seg0)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const float y = __shfl_up(x, d, WAVE);
+        if (lane - d >= seg0) x += y;
+    }
+    return x;
+}
+
+// Segmented inclusive composition of the affine maps U -> a U + b held by
+// the lanes, earlier lanes applied first: lane l gets f_l o ... o f_seg0.
+__device__ __forceinline__ void seg_incl_affine(float& a, float& b, int seg0)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const float ae = __shfl_up(a, d, WAVE);
+        const float be = __shfl_up(b, d, WAVE);
+        if (lane - d >= seg0) {
+            b = a * be + b;
+            a = a * ae;
+        }
+    }
+}
+
+// Exclusive prefix sum of small unsigned counts over the 64 lanes.
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v)
+{
+    const int lane = lane_id();
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)x, d, WAVE);
+        if (lane >= d) x += y;
+    }
+    return x - v;
+}
+
+// Direct global-to-LDS loads (gfx950): every lane's 16 (or 4) bytes land
+// at dst + lane * 16 (or 4) without passing through registers, so a batch's
+// gathers all stay in flight until one wait.
+__device__ __forceinline__ void load16_to_lds(const void* src, void* dst_wave_base)
+{
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                     (void __attribute__((address_space(3)))*)dst_wave_base,
+                                     16, 0, 0);
+}
+
+__device__ __forceinline__ void load4_to_lds(const void* src, void* dst_wave_base)
+{
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)src,
+                                     (void __attribute__((address_space(3)))*)dst_wave_base,
+                                     4, 0, 0);
+}
+
+__device__ __forceinline__ void wait_all_memory()
+{
+    __builtin_amdgcn_s_waitcnt(0);
 }
 
 struct TileCell {
@@ -124,41 +192,8 @@ __device__ __forceinline__ TileCell tile_cell(const DevView* views, int nv, int6
     return t;
 }
 
-__device__ __forceinline__ float quadform(float4 g, float c, float dx, float dy)
-{
-    return g.z * dx * dx + 2.0f * g.w * dx * dy + c * dy * dy;
-}
-
-// Cells of tile (tx, ty) inside the ellipse q < q_max of a Gaussian with
-// centre (cx, cy) and conic (a, b, c): per row the exact column span from
-// the quadratic, widened by a small slack. Bit 8 * row + col.
-__device__ uint64_t footprint_mask(float cx, float cy, float a, float b, float c, float qm,
-                                   int tx, int ty)
-{
-    const float det = a * c - b * b;
-    if (!(det > 0.0f) || !(a > 0.0f)) return 0ull;
-    const float slack = 1e-3f;
-    uint64_t m = 0ull;
-    const float x0 = (float)(tx * TILE);
-#pragma unroll
-    for (int k = 0; k < TILE; ++k) {
-        const float dy = (float)(ty * TILE + k) + 0.5f - cy;
-        const float D = a * qm - det * dy * dy;
-        if (D < 0.0f) continue;
-        const float half = sqrtf(D) / a + slack;
-        const float xc = cx - b * dy / a;
-        // local columns j with |x0 + j + 1/2 - xc| <= half
-        const float lo = fmaxf(ceilf(xc - half - 0.5f - x0), 0.0f);
-        const float hi = fminf(floorf(xc + half - 0.5f - x0), (float)(TILE - 1));
-        if (lo > hi) continue;
-        const uint32_t j0 = (uint32_t)lo, j1 = (uint32_t)hi;
-        const uint64_t row_bits = ((1ull << (j1 - j0 + 1)) - 1ull) << j0;
-        m |= row_bits << (TILE * k);
-    }
-    return m;
-}
-
-// Footprint mask of every computation-plane pair, and per 64-pair chunk of
+// Footprint mask of every computation-plane pair (bit 8 * row + col for
+// the tile cells inside the ellipse q < q_max), and per 64-pair chunk of
 // the sorted array (aligned to the array, so a chunk may span two tiles)
 // the OR of its masks. Blocks are whole waves, so a wave is a chunk.
 __global__ void __launch_bounds__(256)
@@ -188,20 +223,22 @@ k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParam
     if (lane_id() == 0) psum[p / WAVE] = m;
 }
 
-// Pass A forward, one wave per non-empty 8x8 tile, lane = ray. The list
-// is walked in 64-entry chunks aligned to the global pair array; a chunk
-// whose footprint summary misses every ray still in play is skipped
-// without reading its entries (rays at a silhouette rarely saturate, and
-// the lists run to ~5e4 entries). Chunks that are read are taken AF_BATCH
-// at a time: their masks are loaded together, then the records of the
-// entries any live ray needs are gathered together, so one batch pays two
-// memory latencies. In each chunk the 64x64 bit matrix of footprint masks
-// is transposed so that each lane walks only the entries covering its own
-// cell, front to back; per-entry sums go into LDS with float atomics and
-// leave with one global atomic per (tile, entry).
-constexpr int AF_BATCH = 8;
+// Pass A forward, one wave per non-empty 8x8 tile; the wave's rays are the
+// tile's 64 cells. The list is walked in 64-entry chunks aligned to the
+// global pair array; a chunk whose footprint summary misses every ray still
+// in play is skipped without reading its entries. Chunks that are read are
+// taken A_BATCH at a time: their masks are loaded together, then the
+// records of the entries any live ray needs are gathered together, so a
+// batch pays two memory latencies. Inside a chunk the 64x64 bit matrix of
+// footprint masks is transposed (lane = ray: which entries cover my cell),
+// the (ray, entry) hits are compacted ray-major into LDS, and the wave
+// takes them 64 at a time, lane = hit: each ray's optical depth in front of
+// each of its hits is a segmented prefix sum, so a round costs the same
+// however the hits are spread over the rays. Per-entry sums collect in LDS
+// and leave with one global atomic per (tile, entry).
+constexpr int A_BATCH = 4;
 
-__global__ void __launch_bounds__(WAVE)
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                const uint32_t* __restrict__ status, const uint32_t* __restrict__ worklist,
                const uint2* __restrict__ ranges, const uint32_t* __restrict__ pvals,
@@ -209,16 +246,23 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                const float4* __restrict__ cq, const float2* __restrict__ cw,
                float* __restrict__ A, float* __restrict__ tau, uint32_t* __restrict__ nlast)
 {
-    constexpr int NB = AF_BATCH;
+    constexpr int NB = A_BATCH;
     __shared__ float4 s_q[NB][WAVE];
-    __shared__ float2 s_w[NB][WAVE];
+    __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
     __shared__ float s_A[NB][WAVE];
+    __shared__ uint64_t s_m[NB][WAVE];
+    __shared__ uint32_t s_r[NB][WAVE];
+    __shared__ uint32_t s_chk[NB];
+    __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray << 8 | entry), ray-major
+    __shared__ uint32_t s_o[WAVE];            // first hit of each ray in s_hit
+    __shared__ float s_t[WAVE], s_T[WAVE];    // ray state during a chunk
+    __shared__ uint32_t s_last[WAVE];
     const int lane = threadIdx.x;
     if (blockIdx.x >= status[ST_WORK_TILES]) return;
     const int64_t bucket = worklist[blockIdx.x];
     const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
-    const float px = tc.col + 0.5f, py = tc.row + 0.5f;
+    const float x0 = (float)(tc.tx * TILE) + 0.5f, y0 = (float)(tc.ty * TILE) + 0.5f;
     const uint2 rg = ranges[bucket];
 #pragma unroll
     for (int k = 0; k < NB; ++k) s_A[k][lane] = 0.0f;
@@ -232,75 +276,136 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
         const uint64_t sm = g0 + lane < c_end ? psum[g0 + lane] : 0ull;
         uint64_t todo = __ballot((sm & live) != 0ull);   // chunks to read, in order
         while (todo != 0ull && live != 0ull) {
-            uint32_t chk[NB];
-            uint64_t m[NB];
-            uint32_t r[NB];
-            int nb = 0;
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                chk[k] = 0u;
-                if (todo != 0ull) {
-                    chk[k] = g0 + (uint32_t)__builtin_ctzll(todo);
-                    todo &= todo - 1ull;
-                    nb = k + 1;
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                const uint32_t e = chk[k] * WAVE + lane;
-                const bool in = k < nb && e >= rg.x && e < rg.y;
-                m[k] = in ? pmask[e] : 0ull;
-                r[k] = in ? pvals[e] : 0u;
-            }
+            // up to NB chunks: masks and values, then the needed records
             uint32_t got = 0u;   // bit k: this lane's entry of chunk k was gathered
+            int nb = 0;
+            {
+                uint32_t chk[NB];
+                uint64_t m[NB];
+                uint32_t r[NB];
 #pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                if ((m[k] & live) != 0ull) {
-                    s_q[k][lane] = cq[r[k]];
-                    s_w[k][lane] = cw[r[k]];
-                    got |= 1u << k;
-                }
-            }
-            wave_lds_sync();
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                if (k >= nb || live == 0ull) break;
-                if (__ballot((m[k] & live) != 0ull) == 0ull) continue;
-                uint64_t col = transpose64(m[k]);   // entries covering my cell (all lanes)
-                if (!alive) col = 0ull;
-                const uint32_t pos0 = chk[k] * WAVE - rg.x;   // list position of entry 0
-                for (;;) {
-                    const bool act = alive && col != 0ull;
-                    if (__ballot(act) == 0ull) break;
-                    ++n_iter;
-                    if (act) {
-                        const int j = __builtin_ctzll(col);
-                        col &= col - 1ull;
-                        const float4 g = s_q[k][j];
-                        const float2 g2 = s_w[k][j];
-                        const float dx = px - g.x, dy = py - g.y;
-                        const float q = quadform(g, g2.x, dx, dy);
-                        if (q < rp.q_max) {
-                            ++n_hits;
-                            const float f = (__expf(-0.5f * q) - rp.eps) * rp.inv1meps;
-                            const float x = g2.y * f;
-                            const float E = __expf(-x);
-                            atomicAdd(&s_A[k][j], (1.0f - E) * T);
-                            if (rp.shadowing) T *= E;
-                            t += x;
-                            last = pos0 + (uint32_t)j + 1u;
-                            if (rp.shadowing && t >= rp.tau_max) alive = false;
-                        }
+                for (int k = 0; k < NB; ++k) {
+                    chk[k] = 0u;
+                    if (todo != 0ull) {
+                        chk[k] = g0 + (uint32_t)__builtin_ctzll(todo);
+                        todo &= todo - 1ull;
+                        nb = k + 1;
                     }
                 }
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const uint32_t e = chk[k] * WAVE + lane;
+                    const bool in = k < nb && e >= rg.x && e < rg.y;
+                    m[k] = in ? pmask[e] : 0ull;
+                    r[k] = in ? pvals[e] : 0u;
+                }
+                // records straight into LDS, all in flight together (entries
+                // no live ray needs read record 0, one shared line)
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const bool need = (m[k] & live) != 0ull;
+                    got |= need ? 1u << k : 0u;
+                    const uint32_t rk = need ? r[k] : 0u;
+                    const float* w = reinterpret_cast<const float*>(cw + rk);
+                    load16_to_lds(cq + rk, &s_q[k][0]);
+                    load4_to_lds(w, &s_wc[k][0]);
+                    load4_to_lds(w + 1, &s_wk[k][0]);
+                }
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    s_m[k][lane] = m[k];
+                    s_r[k][lane] = r[k];
+                    if (lane == k) s_chk[k] = chk[k];
+                }
+            }
+            wait_all_memory();
+            wave_lds_sync();
+#pragma unroll 1
+            for (int k = 0; k < nb && live != 0ull; ++k) {
+                const uint64_t m = s_m[k][lane];
+                uint64_t col = transpose64(m);   // entries covering my cell (all lanes)
+                if (!alive) col = 0ull;
+                const uint32_t nr = (uint32_t)__popcll(col);
+                const uint32_t o = wave_excl_scan_u32(nr);
+                const uint32_t H = (uint32_t)__builtin_amdgcn_readlane((int)(o + nr), WAVE - 1);
+                if (H == 0u) continue;
+                const uint32_t pos0 = s_chk[k] * WAVE - rg.x;   // list position of entry 0
+                {   // compact my hits, front to back
+                    uint32_t w = o;
+                    uint64_t c = col;
+                    while (c != 0ull) {
+                        const int j = __builtin_ctzll(c);
+                        c &= c - 1ull;
+                        s_hit[w++] = (uint16_t)((lane << 8) | j);
+                    }
+                }
+                s_o[lane] = o;
+                s_t[lane] = t;
+                s_T[lane] = T;
+                s_last[lane] = last;
+                wave_lds_sync();
+                for (uint32_t base = 0; base < H; base += WAVE) {
+                    ++n_iter;
+                    const uint32_t L = base + lane;
+                    const bool valid = L < H;
+                    const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
+                    const int rr = (int)(hv >> 8), j = (int)(hv & 63u);
+                    const int seg0 = valid ? max((int)s_o[rr] - (int)base, 0) : lane;
+                    bool real = false;
+                    float x = 0.0f, E = 1.0f;
+                    if (valid) {
+                        const float4 g = s_q[k][j];
+                        const float2 g2 = make_float2(s_wc[k][j], s_wk[k][j]);
+                        const float dx = x0 + (float)(rr & (TILE - 1)) - g.x;
+                        const float dy = y0 + (float)(rr / TILE) - g.y;
+                        const float q = quadform(g, g2.x, dx, dy);
+                        if (q < rp.q_max) {
+                            real = true;
+                            x = g2.y * ((__expf(-0.5f * q) - rp.eps) * rp.inv1meps);
+                            E = __expf(-x);
+                        }
+                    }
+                    const float incl = seg_incl_scan(x, seg0);
+                    const float excl = incl - x;
+                    const float tr = valid ? s_t[rr] : 0.0f;
+                    const float Tr = valid ? s_T[rr] : 1.0f;
+                    // a ray's hits are processed up to the first one reached
+                    // with an optical depth of tau_max (a prefix of its segment)
+                    const uint64_t stop =
+                        __ballot(valid && rp.shadowing && !(tr + excl < rp.tau_max));
+                    const uint64_t after = stop & (~0ull << seg0);
+                    const bool proc = valid && (after == 0ull || lane < __builtin_ctzll(after));
+                    if (proc && real) {
+                        const float a = (1.0f - E) * (rp.shadowing ? Tr * __expf(-excl) : 1.0f);
+                        atomicAdd(&s_A[k][j], a);
+                    }
+                    const uint64_t hb = __ballot(proc && real);
+                    if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
+                    // the last processed hit of each ray in this round updates the ray
+                    const int nxt = __shfl_down((int)(proc ? hv : 0xFFFFu), 1, WAVE);
+                    const bool endseg = proc && (lane == WAVE - 1 || (nxt >> 8) != rr || nxt == 0xFFFF);
+                    wave_lds_sync();
+                    if (endseg) {
+                        const float tn = tr + incl;
+                        s_t[rr] = tn;
+                        if (rp.shadowing) s_T[rr] = Tr * __expf(-incl);
+                        s_last[rr] = pos0 + (uint32_t)j + 1u;
+                    }
+                    wave_lds_sync();
+                }
+                t = s_t[lane];
+                T = s_T[lane];
+                last = s_last[lane];
+                if (rp.shadowing && t >= rp.tau_max) alive = false;
                 live = __ballot(alive);
+                wave_lds_sync();
             }
             wave_lds_sync();
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 if (got & (1u << k)) {
                     const float a = s_A[k][lane];
-                    if (a != 0.0f) unsafeAtomicAdd(&A[r[k]], a);
+                    if (a != 0.0f) unsafeAtomicAdd(&A[s_r[k][lane]], a);
                     s_A[k][lane] = 0.0f;
                 }
             }
@@ -338,7 +443,7 @@ k_zero_images(const DevView* __restrict__ views, int nv, int64_t pixels, float* 
 // bit-transposed and lane = pixel sums only the entries covering it. The
 // partial pixel sums are added to the image when the tile changes.
 __global__ void __launch_bounds__(RASTER_THREADS)
-k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
+k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64_t cap_c,
                const uint32_t* __restrict__ status, const uint32_t* __restrict__ pkey,
                const uint32_t* __restrict__ pvals, const float4* __restrict__ iq,
                const float2* __restrict__ iw, float* __restrict__ images)
@@ -346,10 +451,10 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     __shared__ float4 s_q[RASTER_WAVES][WAVE];
     __shared__ float2 s_w[RASTER_WAVES][WAVE];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const uint32_t kc = status[ST_PAIRS_C], ki = status[ST_PAIRS_I];
+    const uint32_t ki = status[ST_PAIRS_I];
     const uint64_t seg = (uint64_t)blockIdx.x * RASTER_WAVES + w;
-    const uint64_t p0 = (uint64_t)kc + seg * B_SEGMENT;
-    const uint64_t pend = (uint64_t)kc + ki;
+    const uint64_t p0 = (uint64_t)cap_c + seg * B_SEGMENT;
+    const uint64_t pend = (uint64_t)cap_c + ki;
     if (p0 >= pend) return;
     const uint32_t p1 = (uint32_t)min(pend, p0 + B_SEGMENT);
     uint32_t cur = 0xFFFFFFFFu;
@@ -491,17 +596,17 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
     }
 }
 
-// Pass A backward, same tiling and batched chunk walk as the forward but
-// back to front from each ray's last contributing entry: tau -= kappa f,
-// dL/dalpha = exp(-tau) (c - U), U <- c alpha + (1 - alpha) U, with
-// c = P dL/dI. A ray takes part in a chunk only if it used an entry at or
-// past the chunk's start in the forward, so the chunks behind the point
-// where most rays saturated are skipped as in the forward. The six
-// per-entry gradient sums go into LDS with float atomics and leave with one
-// global atomic each per (tile, entry).
-constexpr int AB_BATCH = 4;
-
-__global__ void __launch_bounds__(WAVE)
+// Pass A backward, same tiling, chunk batches and hit compaction as the
+// forward, but back to front from each ray's last contributing entry:
+// tau -= kappa f, dL/dalpha = exp(-tau) (c - U), U <- c alpha + (1 - alpha) U,
+// with c = P dL/dI. A ray takes part in a chunk only if it used an entry at
+// or past the chunk's start in the forward, so the chunks behind the point
+// where most rays saturated are skipped as in the forward. Within a round
+// (lane = hit, hits of a ray back to front) the optical depth is a
+// segmented prefix sum and U a segmented prefix composition of the affine
+// maps U -> (1 - alpha) U + c alpha. The six per-entry gradient sums collect
+// in LDS and leave with one global atomic each per (tile, entry).
+__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
                RasterParams rp, const uint32_t* __restrict__ status,
                const uint32_t* __restrict__ worklist, const uint2* __restrict__ ranges,
@@ -511,18 +616,24 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                const uint32_t* __restrict__ nlast, const float* __restrict__ grad_i,
                float* __restrict__ grad_c, int64_t stride)
 {
-    constexpr int NB = AB_BATCH;
+    constexpr int NB = A_BATCH;
     __shared__ float4 s_q[NB][WAVE];
-    __shared__ float2 s_w[NB][WAVE];
-    __shared__ float s_c[NB][WAVE];
+    __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
+    __shared__ float s_amp[NB][WAVE], s_dI[NB][WAVE];  // P and dL/dI of the entry
     __shared__ float s_G[NB][6][WAVE];
+    __shared__ uint64_t s_m[NB][WAVE];
+    __shared__ uint32_t s_r[NB][WAVE];
+    __shared__ uint32_t s_chk[NB];
+    __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray << 8 | entry), ray-major, back to front
+    __shared__ uint32_t s_o[WAVE];
+    __shared__ float s_t[WAVE], s_U[WAVE];
     const int lane = threadIdx.x;
     if (blockIdx.x >= status[ST_WORK_TILES]) return;
     const int64_t bucket = worklist[blockIdx.x];
     const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
     const float* amp = scenes[V.scene].amp;
-    const float px = tc.col + 0.5f, py = tc.row + 0.5f;
+    const float x0 = (float)(tc.tx * TILE) + 0.5f, y0 = (float)(tc.ty * TILE) + 0.5f;
     const uint2 rg = ranges[bucket];
     const int64_t ray = V.ray_off + (int64_t)tc.row * V.Wc + tc.col;
     const uint32_t n_mine = tc.inside ? nlast[ray] : 0u;   // entries [0, n_mine) were used
@@ -548,100 +659,163 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
         const uint64_t sm = g0 + lane < g1 ? psum[g0 + lane] : 0ull;
         uint64_t todo = __ballot((sm & live_c) != 0ull);   // chunks to read, back to front
         while (todo != 0ull) {
-            uint32_t chk[NB];
-            uint64_t lv[NB];
-            int nb = 0;
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                chk[k] = 0u;
-                lv[k] = 0ull;
-                if (todo != 0ull) {
-                    const int hi = 63 - __builtin_clzll(todo);
-                    todo &= ~(1ull << hi);
-                    chk[k] = (uint32_t)g0 + (uint32_t)hi;
-                    const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)live_c, hi);
-                    const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(live_c >> 32), hi);
-                    lv[k] = ((uint64_t)l1 << 32) | l0;
-                    nb = k + 1;
-                }
-            }
-            uint64_t m[NB];
-            uint32_t r[NB];
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                const uint32_t e = chk[k] * WAVE + lane;
-                const bool in = k < nb && e >= rg.x && e < e_end;
-                m[k] = in ? pmask[e] : 0ull;
-                r[k] = in ? pvals[e] : 0u;
-            }
             uint32_t got = 0u;
+            int nb = 0;
+            {
+                uint32_t chk[NB];
+                uint64_t lv[NB];
+                uint64_t m[NB];
+                uint32_t r[NB];
 #pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                if ((m[k] & lv[k]) != 0ull) {
-                    s_q[k][lane] = cq[r[k]];
-                    s_w[k][lane] = cw[r[k]];
-                    s_c[k][lane] = amp[r[k] - V.rec_off] * grad_i[5 * stride + r[k]];
-                    got |= 1u << k;
+                for (int k = 0; k < NB; ++k) {
+                    chk[k] = 0u;
+                    lv[k] = 0ull;
+                    if (todo != 0ull) {
+                        const int hi = 63 - __builtin_clzll(todo);
+                        todo &= ~(1ull << hi);
+                        chk[k] = (uint32_t)g0 + (uint32_t)hi;
+                        const uint32_t l0 =
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)live_c, hi);
+                        const uint32_t l1 =
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(live_c >> 32), hi);
+                        lv[k] = ((uint64_t)l1 << 32) | l0;
+                        nb = k + 1;
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const uint32_t e = chk[k] * WAVE + lane;
+                    const bool in = k < nb && e >= rg.x && e < e_end;
+                    m[k] = in ? pmask[e] : 0ull;
+                    r[k] = in ? pvals[e] : 0u;
+                }
+                // records straight into LDS, all in flight together (entries
+                // no ray needs read the view's first record, one shared line)
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    const bool need = (m[k] & lv[k]) != 0ull;
+                    got |= need ? 1u << k : 0u;
+                    const uint32_t rk = need ? r[k] : (uint32_t)V.rec_off;
+                    const float* w = reinterpret_cast<const float*>(cw + rk);
+                    load16_to_lds(cq + rk, &s_q[k][0]);
+                    load4_to_lds(w, &s_wc[k][0]);
+                    load4_to_lds(w + 1, &s_wk[k][0]);
+                    load4_to_lds(amp + (rk - V.rec_off), &s_amp[k][0]);
+                    load4_to_lds(grad_i + 5 * stride + rk, &s_dI[k][0]);
+                }
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    s_m[k][lane] = m[k];
+                    s_r[k][lane] = r[k];
+                    if (lane == k) s_chk[k] = chk[k];
                 }
             }
+            wait_all_memory();
             wave_lds_sync();
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                if (k >= nb) break;
+#pragma unroll 1
+            for (int k = 0; k < nb; ++k) {
+                const uint64_t m = s_m[k][lane];
+                const int64_t pos0 = (int64_t)s_chk[k] * WAVE - rg.x;
                 // entries of this chunk my ray used in the forward: positions < n_mine
-                const int64_t pos0 = (int64_t)chk[k] * WAVE - rg.x;
                 const int64_t nu = (int64_t)n_mine - pos0;
                 const uint64_t used =
                     nu >= WAVE ? ~0ull : (nu <= 0 ? 0ull : ((1ull << nu) - 1ull));
-                uint64_t col = transpose64(m[k]) & used;
-                for (;;) {
-                    const bool act = col != 0ull;
-                    if (__ballot(act) == 0ull) break;
-                    ++n_iter;
-                    if (act) {
-                        const int j = 63 - __builtin_clzll(col);
-                        col &= ~(1ull << j);
-                        const float4 g = s_q[k][j];
-                        const float2 g2 = s_w[k][j];
-                        const float dx = px - g.x, dy = py - g.y;
-                        const float q = quadform(g, g2.x, dx, dy);
-                        if (q < rp.q_max) {
-                            ++n_hits;
-                            const float ex = __expf(-0.5f * q);
-                            const float f = (ex - rp.eps) * rp.inv1meps;
-                            const float kappa = g2.y;
-                            const float x = kappa * f;
-                            const float E = __expf(-x);
-                            const float c = s_c[k][j];
-                            float dalpha;
-                            if (rp.shadowing) {
-                                t -= x;
-                                const float Tn = __expf(-fmaxf(t, 0.0f));
-                                dalpha = Tn * (c - U);
-                                U = c * (1.0f - E) + E * U;
-                            } else {
-                                dalpha = c;
-                            }
-                            const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
-                            const float dq = dxx * kappa * (-0.5f * ex * rp.inv1meps);
-                            atomicAdd(&s_G[k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
-                            atomicAdd(&s_G[k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
-                            atomicAdd(&s_G[k][2][j], dq * dx * dx);
-                            atomicAdd(&s_G[k][3][j], 2.0f * dq * dx * dy);
-                            atomicAdd(&s_G[k][4][j], dq * dy * dy);
-                            atomicAdd(&s_G[k][5][j], dxx * f);
-                        }
+                const uint64_t col = transpose64(m) & used;
+                const uint32_t nr = (uint32_t)__popcll(col);
+                const uint32_t o = wave_excl_scan_u32(nr);
+                const uint32_t H = (uint32_t)__builtin_amdgcn_readlane((int)(o + nr), WAVE - 1);
+                if (H == 0u) continue;
+                {   // compact my hits, back to front
+                    uint32_t w = o;
+                    uint64_t c = col;
+                    while (c != 0ull) {
+                        const int j = 63 - __builtin_clzll(c);
+                        c &= ~(1ull << j);
+                        s_hit[w++] = (uint16_t)((lane << 8) | j);
                     }
                 }
+                s_o[lane] = o;
+                s_t[lane] = t;
+                s_U[lane] = U;
+                wave_lds_sync();
+                for (uint32_t base = 0; base < H; base += WAVE) {
+                    ++n_iter;
+                    const uint32_t L = base + lane;
+                    const bool valid = L < H;
+                    const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
+                    const int rr = (int)(hv >> 8), j = (int)(hv & 63u);
+                    const int seg0 = valid ? max((int)s_o[rr] - (int)base, 0) : lane;
+                    bool real = false;
+                    float x = 0.0f, E = 1.0f, ex = 0.0f, f = 0.0f, dx = 0.0f, dy = 0.0f;
+                    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+                    float2 g2 = make_float2(0.f, 0.f);
+                    float c = 0.0f;
+                    if (valid) {
+                        g = s_q[k][j];
+                        g2 = make_float2(s_wc[k][j], s_wk[k][j]);
+                        dx = x0 + (float)(rr & (TILE - 1)) - g.x;
+                        dy = y0 + (float)(rr / TILE) - g.y;
+                        const float q = quadform(g, g2.x, dx, dy);
+                        if (q < rp.q_max) {
+                            real = true;
+                            c = s_amp[k][j] * s_dI[k][j];
+                            ex = __expf(-0.5f * q);
+                            f = (ex - rp.eps) * rp.inv1meps;
+                            x = g2.y * f;
+                            E = __expf(-x);
+                        }
+                    }
+                    const float sx = seg_incl_scan(x, seg0);   // this and the later hits
+                    float sa = E, sb = real ? c * (1.0f - E) : 0.0f;
+                    seg_incl_affine(sa, sb, seg0);
+                    float ea = __shfl_up(sa, 1, WAVE), eb = __shfl_up(sb, 1, WAVE);
+                    if (lane == seg0) {
+                        ea = 1.0f;
+                        eb = 0.0f;
+                    }
+                    const float tr = valid ? s_t[rr] : 0.0f;
+                    const float Ur = valid ? s_U[rr] : 0.0f;
+                    if (real) {
+                        float dalpha;
+                        if (rp.shadowing) {
+                            const float Tn = __expf(-fmaxf(tr - sx, 0.0f));
+                            dalpha = Tn * (c - (ea * Ur + eb));
+                        } else {
+                            dalpha = c;
+                        }
+                        const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
+                        const float dq = dxx * g2.y * (-0.5f * ex * rp.inv1meps);
+                        atomicAdd(&s_G[k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
+                        atomicAdd(&s_G[k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
+                        atomicAdd(&s_G[k][2][j], dq * dx * dx);
+                        atomicAdd(&s_G[k][3][j], 2.0f * dq * dx * dy);
+                        atomicAdd(&s_G[k][4][j], dq * dy * dy);
+                        atomicAdd(&s_G[k][5][j], dxx * f);
+                    }
+                    const uint64_t hb = __ballot(real);
+                    if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
+                    const int nxt = __shfl_down((int)(valid ? hv : 0xFFFFu), 1, WAVE);
+                    const bool endseg = valid && (lane == WAVE - 1 || (nxt >> 8) != rr || nxt == 0xFFFF);
+                    wave_lds_sync();
+                    if (endseg && rp.shadowing) {
+                        s_t[rr] = tr - sx;
+                        s_U[rr] = sa * Ur + sb;
+                    }
+                    wave_lds_sync();
+                }
+                t = s_t[lane];
+                U = s_U[lane];
+                wave_lds_sync();
             }
             wave_lds_sync();
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 if (got & (1u << k)) {
+                    const uint32_t rk = s_r[k][lane];
 #pragma unroll
                     for (int c = 0; c < 6; ++c) {
                         const float v = s_G[k][c][lane];
-                        if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + r[k]], v);
+                        if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + rk], v);
                         s_G[k][c][lane] = 0.0f;
                     }
                 }
@@ -732,8 +906,8 @@ hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
     return hipGetLastError();
 }
 
-hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_i,
-                               const RasterParams& rp, const uint32_t* status,
+hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_c,
+                               int64_t cap_i, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
                                const float2* iw, float* images, hipStream_t s)
 {
@@ -743,7 +917,7 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
     if (cap_i <= 0) return hipGetLastError();
     const int64_t segs = (cap_i + B_SEGMENT - 1) / B_SEGMENT;
     hipLaunchKernelGGL(k_raster_b_fwd, dim3(raster_grid(segs)), dim3(RASTER_THREADS), 0, s, views,
-                       nv, rp, status, pkey, pvals, iq, iw, images);
+                       nv, rp, cap_c, status, pkey, pvals, iq, iw, images);
     return hipGetLastError();
 }
 

@@ -298,68 +298,121 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
     return e;
 }
 
+// Tile rectangles of the records in depth order, and their pair counts.
 __global__ void __launch_bounds__(256)
-k_gather(const uint32_t* __restrict__ order, const uint32_t* __restrict__ cnt, int64_t n,
-         uint32_t* __restrict__ out)
+k_gather_rects(const uint32_t* __restrict__ order, const uint2* __restrict__ rect, int64_t n,
+               uint2* __restrict__ rect_sorted, uint32_t* __restrict__ cnt_sorted)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = cnt[order[i]];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint2 rc = rect[order[i]];
+    rect_sorted[i] = rc;
+    cnt_sorted[i] = ((rc.x >> 16) - (rc.x & 0xFFFF)) * ((rc.y >> 16) - (rc.y & 0xFFFF));
 }
 
-// status[ST_PAIRS_*] from the u64 totals of the projection (kept in
-// status[8..11] as two u64); flags overflow against the capacities.
-__global__ void k_pair_totals(int64_t cap_c, int64_t cap_i, uint32_t* status)
+// status[ST_PAIRS_C] from the u64 total of the projection (status + 8);
+// flags overflow against the capacity.
+__global__ void k_pair_total_c(int64_t cap_c, uint32_t* status)
 {
     const unsigned long long* tot = (const unsigned long long*)(status + ST_COUNT);
-    unsigned long long kc = tot[0], ki = tot[1];
-    bool over = kc > (unsigned long long)cap_c || ki > (unsigned long long)cap_i;
+    const unsigned long long kc = tot[0];
+    const bool over = kc > (unsigned long long)cap_c;
     status[ST_OVERFLOW] |= over ? 1u : 0u;
     status[ST_PAIRS_C] = over ? 0u : (uint32_t)kc;
-    status[ST_PAIRS_I] = over ? 0u : (uint32_t)ki;
-    status[ST_PAIRS_ALL] = over ? 0u : (uint32_t)(kc + ki);
 }
 
+// status[ST_PAIRS_I] from the exclusive scan of the imaging-plane counts
+// (total = last offset + last count); flags overflow against the capacity.
+__global__ void k_pair_total_i(const uint32_t* __restrict__ off, const uint32_t* __restrict__ cnt,
+                               int64_t n, int64_t cap_i, uint32_t* status)
+{
+    const unsigned long long ki =
+        n > 0 ? (unsigned long long)off[n - 1] + (unsigned long long)cnt[n - 1] : 0ull;
+    const bool over = ki > (unsigned long long)cap_i;
+    status[ST_OVERFLOW] |= over ? 1u : 0u;
+    status[ST_PAIRS_I] = over ? 0u : (uint32_t)ki;
+}
+
+// View of a record through a copy of the view offsets in LDS (records in
+// depth order come from all views at random).
+constexpr int LDS_VIEWS = 512;
+
+// Computation-plane pairs, one thread per record in depth order: the
+// record emits (tile bucket, record) for every tile of its rectangle at its
+// scanned offset, so each tile's pairs leave in depth order.
 __global__ void __launch_bounds__(256)
-k_emit(const DevView* __restrict__ views, int nv, int64_t records,
-       const uint32_t* __restrict__ dval,
-       const uint2* __restrict__ rect_c, const uint2* __restrict__ rect_i,
-       const uint32_t* __restrict__ off_c, const uint32_t* __restrict__ off_i,
-       int64_t cap_c, int64_t cap_i, const uint32_t* __restrict__ status,
-       uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval)
+k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
+         const uint32_t* __restrict__ dval, const uint2* __restrict__ rect_sorted,
+         const uint32_t* __restrict__ off_c, int64_t cap_c, const uint32_t* __restrict__ status,
+         uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval)
+{
+    __shared__ int64_t s_off[LDS_VIEWS];
+    __shared__ int32_t s_tile[LDS_VIEWS], s_tx[LDS_VIEWS];
+    const bool cached = nv <= LDS_VIEWS;
+    if (cached)
+        for (int k = threadIdx.x; k < nv; k += blockDim.x) {
+            s_off[k] = views[k].rec_off;
+            s_tile[k] = views[k].tile_c;
+            s_tx[k] = views[k].txc;
+        }
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= records) return;
+    const uint32_t kc = status[ST_PAIRS_C];
+    if (status[ST_OVERFLOW]) return;
+    const uint2 rc = rect_sorted[p];
+    const uint32_t tx0 = rc.x & 0xFFFF, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
+    if (tx0 >= tx1 || ty0 >= ty1) return;
+    const uint32_t r = dval[p];
+    uint32_t tile0, txc;
+    if (cached) {
+        int lo = 0, hi = nv - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= (int64_t)r) lo = mid; else hi = mid - 1;
+        }
+        tile0 = (uint32_t)s_tile[lo];
+        txc = (uint32_t)s_tx[lo];
+    } else {
+        const int v = find_view(nv, (int64_t)r, [&](int k) { return views[k].rec_off; });
+        tile0 = (uint32_t)views[v].tile_c;
+        txc = (uint32_t)views[v].txc;
+    }
+    uint64_t o = off_c[p];
+    for (uint32_t ty = ty0; ty < ty1; ++ty)
+        for (uint32_t tx = tx0; tx < tx1; ++tx, ++o)
+            if (o < kc && o < (uint64_t)cap_c) {
+                pkey[o] = tile0 + ty * txc + tx;
+                pval[o] = r;
+            }
+}
+
+// Imaging-plane pairs, one thread per record in index order, only for the
+// records whose intensity is nonzero (cnt_i = 0 otherwise); written after
+// the first cap_c entries of the pair arrays.
+__global__ void __launch_bounds__(256)
+k_emit_i(const DevView* __restrict__ views, int nv, int64_t records,
+         const uint2* __restrict__ rect_i, const uint32_t* __restrict__ cnt_i,
+         const uint32_t* __restrict__ off_i, int64_t cap_c, int64_t cap_i,
+         const uint32_t* __restrict__ status, uint32_t* __restrict__ pkey,
+         uint32_t* __restrict__ pval)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= records) return;
-    const uint32_t kc = status[ST_PAIRS_C], ki = status[ST_PAIRS_I];
+    const uint32_t ki = status[ST_PAIRS_I];
     if (status[ST_OVERFLOW]) return;
-    {   // computation plane, depth-sorted position p
-        const uint32_t r = dval[p];
-        const int v = find_view(nv, (int64_t)r, [&](int k) { return views[k].rec_off; });
-        const DevView& V = views[v];
-        const uint2 rc = rect_c[r];
-        const uint32_t tx0 = rc.x & 0xFFFF, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFF,
-                       ty1 = rc.y >> 16;
-        uint64_t o = off_c[p];
-        for (uint32_t ty = ty0; ty < ty1; ++ty)
-            for (uint32_t tx = tx0; tx < tx1; ++tx, ++o)
-                if (o < kc && o < (uint64_t)cap_c) {
-                    pkey[o] = (uint32_t)V.tile_c + ty * (uint32_t)V.txc + tx;
-                    pval[o] = r;
-                }
-    }
-    {   // imaging plane, record p
-        const int v = find_view(nv, p, [&](int k) { return views[k].rec_off; });
-        const DevView& V = views[v];
-        const uint2 ri = rect_i[p];
-        const uint32_t tx0 = ri.x & 0xFFFF, tx1 = ri.x >> 16, ty0 = ri.y & 0xFFFF,
-                       ty1 = ri.y >> 16;
-        uint64_t o = off_i[p];
-        for (uint32_t ty = ty0; ty < ty1; ++ty)
-            for (uint32_t tx = tx0; tx < tx1; ++tx, ++o)
-                if (o < ki && o < (uint64_t)cap_i) {
-                    pkey[kc + o] = (uint32_t)V.tile_i + ty * (uint32_t)V.txi + tx;
-                    pval[kc + o] = (uint32_t)p;
-                }
-    }
+    const int v = find_view(nv, p, [&](int k) { return views[k].rec_off; });
+    if (cnt_i[p] == 0u) return;
+    const DevView& V = views[v];
+    const uint2 ri = rect_i[p];
+    const uint32_t tx0 = ri.x & 0xFFFF, tx1 = ri.x >> 16, ty0 = ri.y & 0xFFFF, ty1 = ri.y >> 16;
+    uint64_t o = off_i[p];
+    for (uint32_t ty = ty0; ty < ty1; ++ty)
+        for (uint32_t tx = tx0; tx < tx1; ++tx, ++o)
+            if (o < ki && o < (uint64_t)cap_i) {
+                pkey[cap_c + o] = (uint32_t)V.tile_i + ty * (uint32_t)V.txi + tx;
+                pval[cap_c + o] = (uint32_t)p;
+            }
 }
 
 __global__ void __launch_bounds__(256)
@@ -454,31 +507,49 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* cnt, int64_t n,
-                                uint32_t* out, hipStream_t s)
+hipError_t launch_gather_rects(const uint32_t* order, const uint2* rect, int64_t n,
+                               uint2* rect_sorted, uint32_t* cnt_sorted, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(grid256(n)), dim3(256), 0, s, order, cnt, n, out);
+    hipLaunchKernelGGL(k_gather_rects, dim3(grid256(n)), dim3(256), 0, s, order, rect, n,
+                       rect_sorted, cnt_sorted);
     return hipGetLastError();
 }
 
-hipError_t launch_pair_totals(int64_t cap_c, int64_t cap_i, uint32_t* status, hipStream_t s)
+hipError_t launch_pair_total_c(int64_t cap_c, uint32_t* status, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_pair_totals, dim3(1), dim3(1), 0, s, cap_c, cap_i, status);
+    hipLaunchKernelGGL(k_pair_total_c, dim3(1), dim3(1), 0, s, cap_c, status);
     return hipGetLastError();
 }
 
-hipError_t launch_emit_pairs(const DevView* views, int nv, int64_t records,
-                             const uint32_t* dval_sorted,
-                             const uint2* rect_c, const uint2* rect_i, const uint32_t* off_c,
-                             const uint32_t* off_i, int64_t cap_c, int64_t cap_i,
-                             const uint32_t* status, uint32_t* pkey, uint32_t* pval,
-                             hipStream_t s)
+hipError_t launch_pair_total_i(const uint32_t* off_i, const uint32_t* cnt_i, int64_t records,
+                               int64_t cap_i, uint32_t* status, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pair_total_i, dim3(1), dim3(1), 0, s, off_i, cnt_i, records, cap_i,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
+                               const uint32_t* dval_sorted, const uint2* rect_sorted,
+                               const uint32_t* off_c, int64_t cap_c, const uint32_t* status,
+                               uint32_t* pkey, uint32_t* pval, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
-                       dval_sorted, rect_c, rect_i, off_c, off_i, cap_c, cap_i,
-                       status, pkey, pval);
+    hipLaunchKernelGGL(k_emit_c, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
+                       dval_sorted, rect_sorted, off_c, cap_c, status, pkey, pval);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
+                               const uint2* rect_i, const uint32_t* cnt_i,
+                               const uint32_t* off_i, int64_t cap_c, int64_t cap_i,
+                               const uint32_t* status, uint32_t* pkey, uint32_t* pval,
+                               hipStream_t s)
+{
+    if (records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit_i, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
+                       rect_i, cnt_i, off_i, cap_c, cap_i, status, pkey, pval);
     return hipGetLastError();
 }
 
