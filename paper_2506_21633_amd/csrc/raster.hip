@@ -55,89 +55,166 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int d)
+// ---- wave64 data movement without the LDS crossbar --------------------
+// Lane i reads lane i ^ S: S = 32 and 16 through the gfx950 permlane swaps,
+// S = 8 by a DPP row rotation, S = 4 by DPP row shifts, S = 2 and 1 by DPP
+// quad permutes.
+template <int S>
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v)
 {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d, WAVE);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d, WAVE);
-    return ((uint64_t)hi << 32) | lo;
+    const int lane = lane_id();
+    if constexpr (S == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return lane < 32 ? r[1] : r[0];
+    } else if constexpr (S == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16) ? r[0] : r[1];
+    } else if constexpr (S == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);
+    } else if constexpr (S == 4) {
+        const uint32_t from_below = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+        const uint32_t from_above = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x104, 0xF, 0xF, false);
+        return (lane & 4) ? from_below : from_above;
+    } else if constexpr (S == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);
+    } else {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v)
+{
+    return ((uint64_t)xor_lane<S>((uint32_t)(v >> 32)) << 32) | xor_lane<S>((uint32_t)v);
+}
+
+template <int S, uint64_t LO>
+__device__ __forceinline__ uint64_t transpose_step(uint64_t v)
+{
+    const uint64_t p = xor_lane64<S>(v);
+    const bool up = (lane_id() & S) != 0;
+    const uint64_t keep = up ? ~LO : LO;
+    const uint64_t moved = up ? ((p & ~LO) >> S) : ((p & LO) << S);
+    return (v & keep) | moved;
 }
 
 // 64x64 bit-matrix transpose across the wave: on return, bit j of lane i is
 // bit i of lane j's input. Recursive block swap: at step s, lanes i and
-// i ^ s exchange the s-wide bit blocks that sit off the diagonal (written
-// with selects, no divergent branches).
+// i ^ s exchange the s-wide bit blocks that sit off the diagonal.
 __device__ __forceinline__ uint64_t transpose64(uint64_t v)
 {
-    const int lane = lane_id();
-    constexpr uint64_t LO[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull,
-                                0x00FF00FF00FF00FFull, 0x0F0F0F0F0F0F0F0Full,
-                                0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int s = 32 >> k;
-        const uint64_t lo = LO[k];
-        const uint64_t p = shfl_xor_u64(v, s);
-        const bool up = (lane & s) != 0;
-        const uint64_t keep = up ? ~lo : lo;
-        const uint64_t moved = up ? ((p & ~lo) >> s) : ((p & lo) << s);
-        v = (v & keep) | moved;
-    }
+    v = transpose_step<32, 0x00000000FFFFFFFFull>(v);
+    v = transpose_step<16, 0x0000FFFF0000FFFFull>(v);
+    v = transpose_step<8, 0x00FF00FF00FF00FFull>(v);
+    v = transpose_step<4, 0x0F0F0F0F0F0F0F0Full>(v);
+    v = transpose_step<2, 0x3333333333333333ull>(v);
+    v = transpose_step<1, 0x5555555555555555ull>(v);
     return v;
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 {
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) v += shfl_xor_u64(v, d);
+    v += xor_lane64<1>(v);
+    v += xor_lane64<2>(v);
+    v += xor_lane64<4>(v);
+    v += xor_lane64<8>(v);
+    v += xor_lane64<16>(v);
+    v += xor_lane64<32>(v);
     return v;
 }
 
 __device__ __forceinline__ uint64_t wave_or_u64(uint64_t v)
 {
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) v |= shfl_xor_u64(v, d);
+    v |= xor_lane64<1>(v);
+    v |= xor_lane64<2>(v);
+    v |= xor_lane64<4>(v);
+    v |= xor_lane64<8>(v);
+    v |= xor_lane64<16>(v);
+    v |= xor_lane64<32>(v);
     return v;
 }
 
-// Segmented inclusive prefix sum over lanes: lane l adds the lanes
-// [seg0, l] of its segment (seg0 <= l is the first lane of the segment).
-__device__ __forceinline__ float seg_incl_scan(float x, int seg0)
+// Value of the lane a DPP row shift or row broadcast names, 0 where there
+// is none (bound control) or the row is masked off.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_from(int v)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const float y = __shfl_up(x, d, WAVE);
-        if (lane - d >= seg0) x += y;
-    }
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+
+__device__ __forceinline__ int from_lane_below(int v) { return dpp_from<0x138, 0xF>(v); }  // lane - 1
+__device__ __forceinline__ int from_lane_above(int v) { return dpp_from<0x130, 0xF>(v); }  // lane + 1
+
+// Scans over the 64 lanes in lane order: shifts by 1, 2, 4, 8 within rows
+// of 16 lanes, then the last lane of a row into the next row (row_bcast 15)
+// and of the first two rows into the last two (row_bcast 31).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_sum_step(float& x, int& f)
+{
+    const float xl = __int_as_float(dpp_from<CTRL, ROWS>(__float_as_int(x)));
+    const int fl = dpp_from<CTRL, ROWS>(f);
+    x = f ? x : xl + x;
+    f |= fl;
+}
+
+// Segmented inclusive prefix sum: `head` marks the first lane of a segment
+// (lane 0 must be one); each lane gets the sum over its segment up to itself.
+__device__ __forceinline__ float seg_incl_scan(float x, bool head)
+{
+    int f = head ? 1 : 0;
+    seg_sum_step<0x111, 0xF>(x, f);
+    seg_sum_step<0x112, 0xF>(x, f);
+    seg_sum_step<0x114, 0xF>(x, f);
+    seg_sum_step<0x118, 0xF>(x, f);
+    seg_sum_step<0x142, 0xA>(x, f);
+    seg_sum_step<0x143, 0xC>(x, f);
     return x;
 }
 
-// Segmented inclusive composition of the affine maps U -> a U + b held by
-// the lanes, earlier lanes applied first: lane l gets f_l o ... o f_seg0.
-__device__ __forceinline__ void seg_incl_affine(float& a, float& b, int seg0)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_affine_step(float& a, float& b, int& f)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const float ae = __shfl_up(a, d, WAVE);
-        const float be = __shfl_up(b, d, WAVE);
-        if (lane - d >= seg0) {
-            b = a * be + b;
-            a = a * ae;
-        }
+    // lanes without a source see the identity map (a = 1, b = 0)
+    const float al = __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(1.0f), __float_as_int(a), CTRL, ROWS, 0xF, false));
+    const float bl = __int_as_float(dpp_from<CTRL, ROWS>(__float_as_int(b)));
+    const int fl = dpp_from<CTRL, ROWS>(f);
+    if (!f) {
+        b = a * bl + b;
+        a = a * al;
     }
+    f |= fl;
+}
+
+// Segmented inclusive composition of the affine maps U -> a U + b held by
+// the lanes, earlier lanes applied first: lane l gets f_l o ... o f_head.
+__device__ __forceinline__ void seg_incl_affine(float& a, float& b, bool head)
+{
+    int f = head ? 1 : 0;
+    seg_affine_step<0x111, 0xF>(a, b, f);
+    seg_affine_step<0x112, 0xF>(a, b, f);
+    seg_affine_step<0x114, 0xF>(a, b, f);
+    seg_affine_step<0x118, 0xF>(a, b, f);
+    seg_affine_step<0x142, 0xA>(a, b, f);
+    seg_affine_step<0x143, 0xC>(a, b, f);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void sum_step_u32(uint32_t& x)
+{
+    x += (uint32_t)dpp_from<CTRL, ROWS>((int)x);
 }
 
 // Exclusive prefix sum of small unsigned counts over the 64 lanes.
 __device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v)
 {
-    const int lane = lane_id();
     uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)x, d, WAVE);
-        if (lane >= d) x += y;
-    }
+    sum_step_u32<0x111, 0xF>(x);
+    sum_step_u32<0x112, 0xF>(x);
+    sum_step_u32<0x114, 0xF>(x);
+    sum_step_u32<0x118, 0xF>(x);
+    sum_step_u32<0x142, 0xA>(x);
+    sum_step_u32<0x143, 0xC>(x);
     return x - v;
 }
 
@@ -365,7 +442,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                             E = __expf(-x);
                         }
                     }
-                    const float incl = seg_incl_scan(x, seg0);
+                    const float incl = seg_incl_scan(x, lane == seg0);
                     const float excl = incl - x;
                     const float tr = valid ? s_t[rr] : 0.0f;
                     const float Tr = valid ? s_T[rr] : 1.0f;
@@ -382,7 +459,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     const uint64_t hb = __ballot(proc && real);
                     if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
                     // the last processed hit of each ray in this round updates the ray
-                    const int nxt = __shfl_down((int)(proc ? hv : 0xFFFFu), 1, WAVE);
+                    const int nxt = from_lane_above((int)(proc ? hv : 0xFFFFu));
                     const bool endseg = proc && (lane == WAVE - 1 || (nxt >> 8) != rr || nxt == 0xFFFF);
                     wave_lds_sync();
                     if (endseg) {
@@ -765,10 +842,11 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                             E = __expf(-x);
                         }
                     }
-                    const float sx = seg_incl_scan(x, seg0);   // this and the later hits
+                    const float sx = seg_incl_scan(x, lane == seg0);   // this and the later hits
                     float sa = E, sb = real ? c * (1.0f - E) : 0.0f;
-                    seg_incl_affine(sa, sb, seg0);
-                    float ea = __shfl_up(sa, 1, WAVE), eb = __shfl_up(sb, 1, WAVE);
+                    seg_incl_affine(sa, sb, lane == seg0);
+                    float ea = __int_as_float(from_lane_below(__float_as_int(sa)));
+                float eb = __int_as_float(from_lane_below(__float_as_int(sb)));
                     if (lane == seg0) {
                         ea = 1.0f;
                         eb = 0.0f;
@@ -794,7 +872,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                     }
                     const uint64_t hb = __ballot(real);
                     if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
-                    const int nxt = __shfl_down((int)(valid ? hv : 0xFFFFu), 1, WAVE);
+                    const int nxt = from_lane_above((int)(valid ? hv : 0xFFFFu));
                     const bool endseg = valid && (lane == WAVE - 1 || (nxt >> 8) != rr || nxt == 0xFFFF);
                     wave_lds_sync();
                     if (endseg && rp.shadowing) {
