@@ -331,9 +331,10 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     __shared__ uint32_t s_r[NB][WAVE];
     __shared__ uint32_t s_chk[NB];
     __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray << 8 | entry), ray-major
-    __shared__ uint32_t s_o[WAVE];            // first hit of each ray in s_hit
-    __shared__ float s_t[WAVE], s_T[WAVE];    // ray state during a chunk
-    __shared__ uint32_t s_last[WAVE];
+    // per ray during a chunk: first hit in s_hit, optical depth, transmittance,
+    // last list position used (one 16-byte read per hit)
+    struct alignas(16) RayF { uint32_t o; float t, T; uint32_t last; };
+    __shared__ RayF s_ray[WAVE];
     const int lane = threadIdx.x;
     if (blockIdx.x >= status[ST_WORK_TILES]) return;
     const int64_t bucket = worklist[blockIdx.x];
@@ -416,10 +417,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                         s_hit[w++] = (uint16_t)((lane << 8) | j);
                     }
                 }
-                s_o[lane] = o;
-                s_t[lane] = t;
-                s_T[lane] = T;
-                s_last[lane] = last;
+                s_ray[lane] = RayF{o, t, T, last};
                 wave_lds_sync();
                 for (uint32_t base = 0; base < H; base += WAVE) {
                     ++n_iter;
@@ -427,25 +425,28 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     const bool valid = L < H;
                     const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
                     const int rr = (int)(hv >> 8), j = (int)(hv & 63u);
-                    const int seg0 = valid ? max((int)s_o[rr] - (int)base, 0) : lane;
+                    // ray state and entry record, read together (lanes past the last hit
+                    // read entry 0 of ray 0 and ignore it)
+                    const RayF rs = s_ray[rr];
+                    const float4 g = s_q[k][j];
+                    const float gc = s_wc[k][j], gk = s_wk[k][j];
+                    const int seg0 = valid ? max((int)rs.o - (int)base, 0) : lane;
                     bool real = false;
                     float x = 0.0f, E = 1.0f;
                     if (valid) {
-                        const float4 g = s_q[k][j];
-                        const float2 g2 = make_float2(s_wc[k][j], s_wk[k][j]);
                         const float dx = x0 + (float)(rr & (TILE - 1)) - g.x;
                         const float dy = y0 + (float)(rr / TILE) - g.y;
-                        const float q = quadform(g, g2.x, dx, dy);
+                        const float q = quadform(g, gc, dx, dy);
                         if (q < rp.q_max) {
                             real = true;
-                            x = g2.y * ((__expf(-0.5f * q) - rp.eps) * rp.inv1meps);
+                            x = gk * ((__expf(-0.5f * q) - rp.eps) * rp.inv1meps);
                             E = __expf(-x);
                         }
                     }
                     const float incl = seg_incl_scan(x, lane == seg0);
                     const float excl = incl - x;
-                    const float tr = valid ? s_t[rr] : 0.0f;
-                    const float Tr = valid ? s_T[rr] : 1.0f;
+                    const float tr = valid ? rs.t : 0.0f;
+                    const float Tr = valid ? rs.T : 1.0f;
                     // a ray's hits are processed up to the first one reached
                     // with an optical depth of tau_max (a prefix of its segment)
                     const uint64_t stop =
@@ -462,17 +463,17 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     const int nxt = from_lane_above((int)(proc ? hv : 0xFFFFu));
                     const bool endseg = proc && (lane == WAVE - 1 || (nxt >> 8) != rr || nxt == 0xFFFF);
                     wave_lds_sync();
-                    if (endseg) {
-                        const float tn = tr + incl;
-                        s_t[rr] = tn;
-                        if (rp.shadowing) s_T[rr] = Tr * __expf(-incl);
-                        s_last[rr] = pos0 + (uint32_t)j + 1u;
-                    }
+                    if (endseg)
+                        s_ray[rr] = RayF{rs.o, tr + incl, rp.shadowing ? Tr * __expf(-incl) : Tr,
+                                         pos0 + (uint32_t)j + 1u};
                     wave_lds_sync();
                 }
-                t = s_t[lane];
-                T = s_T[lane];
-                last = s_last[lane];
+                {
+                    const RayF rs = s_ray[lane];
+                    t = rs.t;
+                    T = rs.T;
+                    last = rs.last;
+                }
                 if (rp.shadowing && t >= rp.tau_max) alive = false;
                 live = __ballot(alive);
                 wave_lds_sync();
@@ -702,8 +703,9 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
     __shared__ uint32_t s_r[NB][WAVE];
     __shared__ uint32_t s_chk[NB];
     __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray << 8 | entry), ray-major, back to front
-    __shared__ uint32_t s_o[WAVE];
-    __shared__ float s_t[WAVE], s_U[WAVE];
+    // per ray during a chunk: first hit in s_hit, optical depth, U
+    struct alignas(16) RayB { uint32_t o; float t, U, pad; };
+    __shared__ RayB s_ray[WAVE];
     const int lane = threadIdx.x;
     if (blockIdx.x >= status[ST_WORK_TILES]) return;
     const int64_t bucket = worklist[blockIdx.x];
@@ -811,9 +813,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                         s_hit[w++] = (uint16_t)((lane << 8) | j);
                     }
                 }
-                s_o[lane] = o;
-                s_t[lane] = t;
-                s_U[lane] = U;
+                s_ray[lane] = RayB{o, t, U, 0.0f};
                 wave_lds_sync();
                 for (uint32_t base = 0; base < H; base += WAVE) {
                     ++n_iter;
@@ -821,21 +821,23 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                     const bool valid = L < H;
                     const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
                     const int rr = (int)(hv >> 8), j = (int)(hv & 63u);
-                    const int seg0 = valid ? max((int)s_o[rr] - (int)base, 0) : lane;
+                    // ray state and entry record, read together (lanes past the last hit
+                    // read entry 0 of ray 0 and ignore it)
+                    const RayB rs = s_ray[rr];
+                    const float4 g = s_q[k][j];
+                    const float2 g2 = make_float2(s_wc[k][j], s_wk[k][j]);
+                    const float cj = s_amp[k][j] * s_dI[k][j];
+                    const int seg0 = valid ? max((int)rs.o - (int)base, 0) : lane;
                     bool real = false;
                     float x = 0.0f, E = 1.0f, ex = 0.0f, f = 0.0f, dx = 0.0f, dy = 0.0f;
-                    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-                    float2 g2 = make_float2(0.f, 0.f);
                     float c = 0.0f;
                     if (valid) {
-                        g = s_q[k][j];
-                        g2 = make_float2(s_wc[k][j], s_wk[k][j]);
                         dx = x0 + (float)(rr & (TILE - 1)) - g.x;
                         dy = y0 + (float)(rr / TILE) - g.y;
                         const float q = quadform(g, g2.x, dx, dy);
                         if (q < rp.q_max) {
                             real = true;
-                            c = s_amp[k][j] * s_dI[k][j];
+                            c = cj;
                             ex = __expf(-0.5f * q);
                             f = (ex - rp.eps) * rp.inv1meps;
                             x = g2.y * f;
@@ -846,13 +848,13 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                     float sa = E, sb = real ? c * (1.0f - E) : 0.0f;
                     seg_incl_affine(sa, sb, lane == seg0);
                     float ea = __int_as_float(from_lane_below(__float_as_int(sa)));
-                float eb = __int_as_float(from_lane_below(__float_as_int(sb)));
+                    float eb = __int_as_float(from_lane_below(__float_as_int(sb)));
                     if (lane == seg0) {
                         ea = 1.0f;
                         eb = 0.0f;
                     }
-                    const float tr = valid ? s_t[rr] : 0.0f;
-                    const float Ur = valid ? s_U[rr] : 0.0f;
+                    const float tr = valid ? rs.t : 0.0f;
+                    const float Ur = valid ? rs.U : 0.0f;
                     if (real) {
                         float dalpha;
                         if (rp.shadowing) {
@@ -875,14 +877,14 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                     const int nxt = from_lane_above((int)(valid ? hv : 0xFFFFu));
                     const bool endseg = valid && (lane == WAVE - 1 || (nxt >> 8) != rr || nxt == 0xFFFF);
                     wave_lds_sync();
-                    if (endseg && rp.shadowing) {
-                        s_t[rr] = tr - sx;
-                        s_U[rr] = sa * Ur + sb;
-                    }
+                    if (endseg && rp.shadowing) s_ray[rr] = RayB{rs.o, tr - sx, sa * Ur + sb, 0.0f};
                     wave_lds_sync();
                 }
-                t = s_t[lane];
-                U = s_U[lane];
+                {
+                    const RayB rs = s_ray[lane];
+                    t = rs.t;
+                    U = rs.U;
+                }
                 wave_lds_sync();
             }
             wave_lds_sync();
