@@ -323,7 +323,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                const float4* __restrict__ cq, const float2* __restrict__ cw,
                float* __restrict__ A, float* __restrict__ tau, uint32_t* __restrict__ nlast)
 {
-    constexpr int NB = A_BATCH;
+    constexpr int NB = 2 * A_BATCH;   // the forward keeps less per chunk in LDS
     __shared__ float4 s_q[NB][WAVE];
     __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
     __shared__ float s_A[NB][WAVE];
