@@ -398,85 +398,117 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
             }
             wait_all_memory();
             wave_lds_sync();
-#pragma unroll 1
-            for (int k = 0; k < nb && live != 0ull; ++k) {
-                const uint64_t m = s_m[k][lane];
-                uint64_t col = transpose64(m);   // entries covering my cell (all lanes)
-                if (!alive) col = 0ull;
-                const uint32_t nr = (uint32_t)__popcll(col);
-                const uint32_t o = wave_excl_scan_u32(nr);
-                const uint32_t H = (uint32_t)__builtin_amdgcn_readlane((int)(o + nr), WAVE - 1);
-                if (H == 0u) continue;
-                const uint32_t pos0 = s_chk[k] * WAVE - rg.x;   // list position of entry 0
-                {   // compact my hits, front to back
-                    uint32_t w = o;
-                    uint64_t c = col;
-                    while (c != 0ull) {
-                        const int j = __builtin_ctzll(c);
-                        c &= c - 1ull;
-                        s_hit[w++] = (uint16_t)((lane << 8) | j);
+            // the batch's chunks, transposed: bit j of col[k] is entry j of
+            // chunk k covering my cell (rays already out of play keep none)
+            uint64_t col[NB];
+            uint32_t hk[NB];   // hits of each chunk over the wave
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                col[k] = 0ull;
+                if (k < nb) col[k] = transpose64(s_m[k][lane]);
+                if (!alive) col[k] = 0ull;
+                hk[k] = (uint32_t)__builtin_amdgcn_readlane(
+                    (int)(wave_excl_scan_u32((uint32_t)__popcll(col[k])) + (uint32_t)__popcll(col[k])),
+                    WAVE - 1);
+            }
+            // groups of consecutive chunks whose hits fit s_hit; each group's
+            // hits are compacted ray-major (chunk by chunk, front to back) and
+            // taken 64 per round
+            for (int g0 = 0; g0 < nb && live != 0ull;) {
+                int g1 = g0;
+                uint32_t H = 0;
+                bool open = true;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    if (k < g0 || k >= nb || !open) continue;
+                    if (H + hk[k] <= (uint32_t)(WAVE * WAVE)) {
+                        H += hk[k];
+                        g1 = k + 1;
+                    } else {
+                        open = false;
                     }
                 }
-                s_ray[lane] = RayF{o, t, T, last};
-                wave_lds_sync();
-                for (uint32_t base = 0; base < H; base += WAVE) {
-                    ++n_iter;
-                    const uint32_t L = base + lane;
-                    const bool valid = L < H;
-                    const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
-                    const int rr = (int)(hv >> 8), j = (int)(hv & 63u);
-                    // ray state and entry record, read together (lanes past the last hit
-                    // read entry 0 of ray 0 and ignore it)
-                    const RayF rs = s_ray[rr];
-                    const float4 g = s_q[k][j];
-                    const float gc = s_wc[k][j], gk = s_wk[k][j];
-                    const int seg0 = valid ? max((int)rs.o - (int)base, 0) : lane;
-                    bool real = false;
-                    float x = 0.0f, E = 1.0f;
-                    if (valid) {
-                        const float dx = x0 + (float)(rr & (TILE - 1)) - g.x;
-                        const float dy = y0 + (float)(rr / TILE) - g.y;
-                        const float q = quadform(g, gc, dx, dy);
-                        if (q < rp.q_max) {
-                            real = true;
-                            x = gk * ((__expf(-0.5f * q) - rp.eps) * rp.inv1meps);
-                            E = __expf(-x);
+                uint32_t nr = 0;
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+                    if (k >= g0 && k < g1) nr += (uint32_t)__popcll(col[k]);
+                const uint32_t o = wave_excl_scan_u32(nr);
+                if (H > 0u) {
+                    uint32_t w = o;
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        if (k < g0 || k >= g1) continue;
+                        uint64_t c = col[k];
+                        while (c != 0ull) {
+                            const int j = __builtin_ctzll(c);
+                            c &= c - 1ull;
+                            s_hit[w++] = (uint16_t)((lane << 9) | (k << 6) | j);
                         }
                     }
-                    const float incl = seg_incl_scan(x, lane == seg0);
-                    const float excl = incl - x;
-                    const float tr = valid ? rs.t : 0.0f;
-                    const float Tr = valid ? rs.T : 1.0f;
-                    // a ray's hits are processed up to the first one reached
-                    // with an optical depth of tau_max (a prefix of its segment)
-                    const uint64_t stop =
-                        __ballot(valid && rp.shadowing && !(tr + excl < rp.tau_max));
-                    const uint64_t after = stop & (~0ull << seg0);
-                    const bool proc = valid && (after == 0ull || lane < __builtin_ctzll(after));
-                    if (proc && real) {
-                        const float a = (1.0f - E) * (rp.shadowing ? Tr * __expf(-excl) : 1.0f);
-                        atomicAdd(&s_A[k][j], a);
+                    s_ray[lane] = RayF{o, t, T, last};
+                    wave_lds_sync();
+                    for (uint32_t base = 0; base < H; base += WAVE) {
+                        ++n_iter;
+                        const uint32_t L = base + lane;
+                        const bool valid = L < H;
+                        const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
+                        const int rr = (int)(hv >> 9), k = (int)((hv >> 6) & 7u), j = (int)(hv & 63u);
+                        // ray state and entry record, read together (lanes past
+                        // the last hit read entry 0 of ray 0 and ignore it)
+                        const RayF rs = s_ray[rr];
+                        const float4 g = s_q[k][j];
+                        const float gc = s_wc[k][j], gk = s_wk[k][j];
+                        const uint32_t pos = s_chk[k] * WAVE + (uint32_t)j - rg.x;   // list position
+                        const int seg0 = valid ? max((int)rs.o - (int)base, 0) : lane;
+                        bool real = false;
+                        float x = 0.0f, E = 1.0f;
+                        if (valid) {
+                            const float dx = x0 + (float)(rr & (TILE - 1)) - g.x;
+                            const float dy = y0 + (float)(rr / TILE) - g.y;
+                            const float q = quadform(g, gc, dx, dy);
+                            if (q < rp.q_max) {
+                                real = true;
+                                x = gk * ((__expf(-0.5f * q) - rp.eps) * rp.inv1meps);
+                                E = __expf(-x);
+                            }
+                        }
+                        const float incl = seg_incl_scan(x, lane == seg0);
+                        const float excl = incl - x;
+                        const float tr = valid ? rs.t : 0.0f;
+                        const float Tr = valid ? rs.T : 1.0f;
+                        // a ray's hits are processed up to the first one reached
+                        // with an optical depth of tau_max (a prefix of its segment)
+                        const uint64_t stop =
+                            __ballot(valid && rp.shadowing && !(tr + excl < rp.tau_max));
+                        const uint64_t after = stop & (~0ull << seg0);
+                        const bool proc = valid && (after == 0ull || lane < __builtin_ctzll(after));
+                        if (proc && real) {
+                            const float a = (1.0f - E) * (rp.shadowing ? Tr * __expf(-excl) : 1.0f);
+                            atomicAdd(&s_A[k][j], a);
+                        }
+                        const uint64_t hb = __ballot(proc && real);
+                        if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
+                        // the last processed hit of each ray in this round updates the ray
+                        const int nxt = from_lane_above((int)(proc ? hv : 0xFFFFu));
+                        const bool endseg =
+                            proc && (lane == WAVE - 1 || (nxt >> 9) != rr || nxt == 0xFFFF);
+                        wave_lds_sync();
+                        if (endseg)
+                            s_ray[rr] = RayF{rs.o, tr + incl, rp.shadowing ? Tr * __expf(-incl) : Tr,
+                                             pos + 1u};
+                        wave_lds_sync();
                     }
-                    const uint64_t hb = __ballot(proc && real);
-                    if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
-                    // the last processed hit of each ray in this round updates the ray
-                    const int nxt = from_lane_above((int)(proc ? hv : 0xFFFFu));
-                    const bool endseg = proc && (lane == WAVE - 1 || (nxt >> 8) != rr || nxt == 0xFFFF);
-                    wave_lds_sync();
-                    if (endseg)
-                        s_ray[rr] = RayF{rs.o, tr + incl, rp.shadowing ? Tr * __expf(-incl) : Tr,
-                                         pos0 + (uint32_t)j + 1u};
+                    {
+                        const RayF rs = s_ray[lane];
+                        t = rs.t;
+                        T = rs.T;
+                        last = rs.last;
+                    }
+                    if (rp.shadowing && t >= rp.tau_max) alive = false;
+                    live = __ballot(alive);
                     wave_lds_sync();
                 }
-                {
-                    const RayF rs = s_ray[lane];
-                    t = rs.t;
-                    T = rs.T;
-                    last = rs.last;
-                }
-                if (rp.shadowing && t >= rp.tau_max) alive = false;
-                live = __ballot(alive);
-                wave_lds_sync();
+                g0 = g1;
             }
             wave_lds_sync();
 #pragma unroll
@@ -791,101 +823,134 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
             }
             wait_all_memory();
             wave_lds_sync();
-#pragma unroll 1
-            for (int k = 0; k < nb; ++k) {
-                const uint64_t m = s_m[k][lane];
-                const int64_t pos0 = (int64_t)s_chk[k] * WAVE - rg.x;
-                // entries of this chunk my ray used in the forward: positions < n_mine
-                const int64_t nu = (int64_t)n_mine - pos0;
-                const uint64_t used =
-                    nu >= WAVE ? ~0ull : (nu <= 0 ? 0ull : ((1ull << nu) - 1ull));
-                const uint64_t col = transpose64(m) & used;
-                const uint32_t nr = (uint32_t)__popcll(col);
+            // the batch's chunks, transposed: bit j of col[k] is entry j of
+            // chunk k covering my cell that my ray used in the forward
+            uint64_t col[NB];
+            uint32_t hk[NB];   // hits of each chunk over the wave
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                col[k] = 0ull;
+                if (k < nb) {
+                    const int64_t pos0 = (int64_t)s_chk[k] * WAVE - rg.x;
+                    const int64_t nu = (int64_t)n_mine - pos0;   // used: positions < n_mine
+                    const uint64_t used =
+                        nu >= WAVE ? ~0ull : (nu <= 0 ? 0ull : ((1ull << nu) - 1ull));
+                    col[k] = transpose64(s_m[k][lane]) & used;
+                }
+                hk[k] = (uint32_t)__builtin_amdgcn_readlane(
+                    (int)(wave_excl_scan_u32((uint32_t)__popcll(col[k])) + (uint32_t)__popcll(col[k])),
+                    WAVE - 1);
+            }
+            // groups of consecutive chunks whose hits fit s_hit; each group's
+            // hits are compacted ray-major, back to front (the batch's chunks
+            // come back to front), and taken 64 per round
+            for (int g0 = 0; g0 < nb;) {
+                int g1 = g0;
+                uint32_t H = 0;
+                bool open = true;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) {
+                    if (k < g0 || k >= nb || !open) continue;
+                    if (H + hk[k] <= (uint32_t)(WAVE * WAVE)) {
+                        H += hk[k];
+                        g1 = k + 1;
+                    } else {
+                        open = false;
+                    }
+                }
+                uint32_t nr = 0;
+#pragma unroll
+                for (int k = 0; k < NB; ++k)
+                    if (k >= g0 && k < g1) nr += (uint32_t)__popcll(col[k]);
                 const uint32_t o = wave_excl_scan_u32(nr);
-                const uint32_t H = (uint32_t)__builtin_amdgcn_readlane((int)(o + nr), WAVE - 1);
-                if (H == 0u) continue;
-                {   // compact my hits, back to front
+                if (H > 0u) {
                     uint32_t w = o;
-                    uint64_t c = col;
-                    while (c != 0ull) {
-                        const int j = 63 - __builtin_clzll(c);
-                        c &= ~(1ull << j);
-                        s_hit[w++] = (uint16_t)((lane << 8) | j);
-                    }
-                }
-                s_ray[lane] = RayB{o, t, U, 0.0f};
-                wave_lds_sync();
-                for (uint32_t base = 0; base < H; base += WAVE) {
-                    ++n_iter;
-                    const uint32_t L = base + lane;
-                    const bool valid = L < H;
-                    const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
-                    const int rr = (int)(hv >> 8), j = (int)(hv & 63u);
-                    // ray state and entry record, read together (lanes past the last hit
-                    // read entry 0 of ray 0 and ignore it)
-                    const RayB rs = s_ray[rr];
-                    const float4 g = s_q[k][j];
-                    const float2 g2 = make_float2(s_wc[k][j], s_wk[k][j]);
-                    const float cj = s_amp[k][j] * s_dI[k][j];
-                    const int seg0 = valid ? max((int)rs.o - (int)base, 0) : lane;
-                    bool real = false;
-                    float x = 0.0f, E = 1.0f, ex = 0.0f, f = 0.0f, dx = 0.0f, dy = 0.0f;
-                    float c = 0.0f;
-                    if (valid) {
-                        dx = x0 + (float)(rr & (TILE - 1)) - g.x;
-                        dy = y0 + (float)(rr / TILE) - g.y;
-                        const float q = quadform(g, g2.x, dx, dy);
-                        if (q < rp.q_max) {
-                            real = true;
-                            c = cj;
-                            ex = __expf(-0.5f * q);
-                            f = (ex - rp.eps) * rp.inv1meps;
-                            x = g2.y * f;
-                            E = __expf(-x);
+#pragma unroll
+                    for (int k = 0; k < NB; ++k) {
+                        if (k < g0 || k >= g1) continue;
+                        uint64_t c = col[k];
+                        while (c != 0ull) {
+                            const int j = 63 - __builtin_clzll(c);
+                            c &= ~(1ull << j);
+                            s_hit[w++] = (uint16_t)((lane << 9) | (k << 6) | j);
                         }
                     }
-                    const float sx = seg_incl_scan(x, lane == seg0);   // this and the later hits
-                    float sa = E, sb = real ? c * (1.0f - E) : 0.0f;
-                    seg_incl_affine(sa, sb, lane == seg0);
-                    float ea = __int_as_float(from_lane_below(__float_as_int(sa)));
-                    float eb = __int_as_float(from_lane_below(__float_as_int(sb)));
-                    if (lane == seg0) {
-                        ea = 1.0f;
-                        eb = 0.0f;
-                    }
-                    const float tr = valid ? rs.t : 0.0f;
-                    const float Ur = valid ? rs.U : 0.0f;
-                    if (real) {
-                        float dalpha;
-                        if (rp.shadowing) {
-                            const float Tn = __expf(-fmaxf(tr - sx, 0.0f));
-                            dalpha = Tn * (c - (ea * Ur + eb));
-                        } else {
-                            dalpha = c;
+                    s_ray[lane] = RayB{o, t, U, 0.0f};
+                    wave_lds_sync();
+                    for (uint32_t base = 0; base < H; base += WAVE) {
+                        ++n_iter;
+                        const uint32_t L = base + lane;
+                        const bool valid = L < H;
+                        const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
+                        const int rr = (int)(hv >> 9), k = (int)((hv >> 6) & 7u), j = (int)(hv & 63u);
+                        // ray state and entry record, read together (lanes past
+                        // the last hit read entry 0 of ray 0 and ignore it)
+                        const RayB rs = s_ray[rr];
+                        const float4 g = s_q[k][j];
+                        const float2 g2 = make_float2(s_wc[k][j], s_wk[k][j]);
+                        const float cj = s_amp[k][j] * s_dI[k][j];
+                        const int seg0 = valid ? max((int)rs.o - (int)base, 0) : lane;
+                        bool real = false;
+                        float x = 0.0f, E = 1.0f, ex = 0.0f, f = 0.0f, dx = 0.0f, dy = 0.0f;
+                        float c = 0.0f;
+                        if (valid) {
+                            dx = x0 + (float)(rr & (TILE - 1)) - g.x;
+                            dy = y0 + (float)(rr / TILE) - g.y;
+                            const float q = quadform(g, g2.x, dx, dy);
+                            if (q < rp.q_max) {
+                                real = true;
+                                c = cj;
+                                ex = __expf(-0.5f * q);
+                                f = (ex - rp.eps) * rp.inv1meps;
+                                x = g2.y * f;
+                                E = __expf(-x);
+                            }
                         }
-                        const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
-                        const float dq = dxx * g2.y * (-0.5f * ex * rp.inv1meps);
-                        atomicAdd(&s_G[k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
-                        atomicAdd(&s_G[k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
-                        atomicAdd(&s_G[k][2][j], dq * dx * dx);
-                        atomicAdd(&s_G[k][3][j], 2.0f * dq * dx * dy);
-                        atomicAdd(&s_G[k][4][j], dq * dy * dy);
-                        atomicAdd(&s_G[k][5][j], dxx * f);
+                        const float sx = seg_incl_scan(x, lane == seg0);   // this and the later hits
+                        float sa = E, sb = real ? c * (1.0f - E) : 0.0f;
+                        seg_incl_affine(sa, sb, lane == seg0);
+                        float ea = __int_as_float(from_lane_below(__float_as_int(sa)));
+                        float eb = __int_as_float(from_lane_below(__float_as_int(sb)));
+                        if (lane == seg0) {
+                            ea = 1.0f;
+                            eb = 0.0f;
+                        }
+                        const float tr = valid ? rs.t : 0.0f;
+                        const float Ur = valid ? rs.U : 0.0f;
+                        if (real) {
+                            float dalpha;
+                            if (rp.shadowing) {
+                                const float Tn = __expf(-fmaxf(tr - sx, 0.0f));
+                                dalpha = Tn * (c - (ea * Ur + eb));
+                            } else {
+                                dalpha = c;
+                            }
+                            const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
+                            const float dq = dxx * g2.y * (-0.5f * ex * rp.inv1meps);
+                            atomicAdd(&s_G[k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
+                            atomicAdd(&s_G[k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
+                            atomicAdd(&s_G[k][2][j], dq * dx * dx);
+                            atomicAdd(&s_G[k][3][j], 2.0f * dq * dx * dy);
+                            atomicAdd(&s_G[k][4][j], dq * dy * dy);
+                            atomicAdd(&s_G[k][5][j], dxx * f);
+                        }
+                        const uint64_t hb = __ballot(real);
+                        if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
+                        const int nxt = from_lane_above((int)(valid ? hv : 0xFFFFu));
+                        const bool endseg =
+                            valid && (lane == WAVE - 1 || (nxt >> 9) != rr || nxt == 0xFFFF);
+                        wave_lds_sync();
+                        if (endseg && rp.shadowing) s_ray[rr] = RayB{rs.o, tr - sx, sa * Ur + sb, 0.0f};
+                        wave_lds_sync();
                     }
-                    const uint64_t hb = __ballot(real);
-                    if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
-                    const int nxt = from_lane_above((int)(valid ? hv : 0xFFFFu));
-                    const bool endseg = valid && (lane == WAVE - 1 || (nxt >> 8) != rr || nxt == 0xFFFF);
-                    wave_lds_sync();
-                    if (endseg && rp.shadowing) s_ray[rr] = RayB{rs.o, tr - sx, sa * Ur + sb, 0.0f};
+                    {
+                        const RayB rs = s_ray[lane];
+                        t = rs.t;
+                        U = rs.U;
+                    }
                     wave_lds_sync();
                 }
-                {
-                    const RayB rs = s_ray[lane];
-                    t = rs.t;
-                    U = rs.U;
-                }
-                wave_lds_sync();
+                g0 = g1;
             }
             wave_lds_sync();
 #pragma unroll
