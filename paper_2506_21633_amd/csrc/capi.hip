@@ -267,6 +267,7 @@ struct Bufs {
     // backward accumulators, 8 floats per record
     float* grad_c = nullptr;
     float* grad_i = nullptr;
+    float* cbwd = nullptr;          // c = P dL/dI per record (pass A backward)
 };
 
 struct Arena {
@@ -341,6 +342,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         }
         b.grad_c = sc.take<float>(6 * R);   // plane-major, see launch_params_backward
         b.grad_i = sc.take<float>(6 * R);
+        b.cbwd = sc.take<float>(R);
     }
     if (state_bytes) *state_bytes = st.off;
     if (scratch_bytes) *scratch_bytes = sc.off;
@@ -643,14 +645,14 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     }
     {
         StageTimer t(SG_RASTER_B_BWD, s);
-        SDGR_HIP(launch_image_bwd(b.views, P.nv, P.records, P.rp, b.iq, b.iw, dL_dimages,
-                                  b.grad_i, s));
+        SDGR_HIP(launch_image_bwd(b.views, b.scenes, P.nv, P.records, P.rp, b.iq, b.iw,
+                                  dL_dimages, b.grad_i, b.cbwd, s));
     }
     {
         StageTimer t(SG_RASTER_A_BWD, s);
-        SDGR_HIP(launch_raster_a_bwd(b.views, b.scenes, P.nv, P.tiles_c, P.rp, b.status,
-                                     b.worklist, b.ranges, b.pval[pw], b.pmask, b.psum, b.cq,
-                                     b.cw, b.tau, b.nlast, b.grad_i, b.grad_c, P.records, s));
+        SDGR_HIP(launch_raster_a_bwd(b.views, P.nv, P.tiles_c, P.rp, b.status, b.worklist,
+                                     b.ranges, b.pval[pw], b.pmask, b.psum, b.cq, b.cw, b.tau,
+                                     b.nlast, b.cbwd, b.grad_c, P.records, s));
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,

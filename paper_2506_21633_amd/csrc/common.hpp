@@ -239,15 +239,16 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
                                int64_t cap_i, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
                                const float2* iw, float* images, hipStream_t s);
-hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
-                            const RasterParams& rp, const float4* iq, const float2* iw,
-                            const float* dimg, float* grad_i, hipStream_t s);
-hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
-                               int64_t tiles_c, const RasterParams& rp, const uint32_t* status,
+hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
+                            int64_t records, const RasterParams& rp, const float4* iq,
+                            const float2* iw, const float* dimg, float* grad_i, float* cbwd,
+                            hipStream_t s);
+hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
+                               const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask,
                                const uint64_t* psum, const float4* cq, const float2* cw,
-                               const float* tau, const uint32_t* nlast, const float* grad_i,
+                               const float* tau, const uint32_t* nlast, const float* cbwd,
                                float* grad_c, int64_t stride, hipStream_t s);
 
 }  // namespace sdgr

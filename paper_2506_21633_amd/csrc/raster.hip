@@ -349,6 +349,20 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     uint32_t last = 0;
     unsigned long long n_iter = 0, n_hits = 0;   // work counters
     uint64_t live = __ballot(alive);
+    // per-entry sums of the last processed batch leave with one atomic each;
+    // they are sent while the next batch's loads are in flight
+    uint32_t got_prev = 0u;
+    auto flush = [&]() {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (got_prev & (1u << k)) {
+                const float a = s_A[k][lane];
+                if (a != 0.0f) unsafeAtomicAdd(&A[s_r[k][lane]], a);
+                s_A[k][lane] = 0.0f;
+            }
+        }
+        got_prev = 0u;
+    };
     const uint32_t c_first = rg.x / WAVE, c_end = (rg.y + WAVE - 1) / WAVE;
     for (uint32_t g0 = c_first; g0 < c_end && live != 0ull; g0 += WAVE) {
         const uint64_t sm = g0 + lane < c_end ? psum[g0 + lane] : 0ull;
@@ -377,6 +391,8 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     m[k] = in ? pmask[e] : 0ull;
                     r[k] = in ? pvals[e] : 0u;
                 }
+                // the previous batch's sums leave while these loads are in flight
+                flush();
                 // records straight into LDS, all in flight together (entries
                 // no live ray needs read record 0, one shared line)
 #pragma unroll
@@ -396,6 +412,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     if (lane == k) s_chk[k] = chk[k];
                 }
             }
+            got_prev = got;
             wait_all_memory();
             wave_lds_sync();
             // the batch's chunks, transposed: bit j of col[k] is entry j of
@@ -511,17 +528,9 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                 g0 = g1;
             }
             wave_lds_sync();
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                if (got & (1u << k)) {
-                    const float a = s_A[k][lane];
-                    if (a != 0.0f) unsafeAtomicAdd(&A[s_r[k][lane]], a);
-                    s_A[k][lane] = 0.0f;
-                }
-            }
-            wave_lds_sync();
         }
     }
+    flush();
     if (rp.work) {
         n_hits = wave_sum_u64(n_hits);
         if (lane == 0) {
@@ -644,9 +653,10 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64
 // widened by one pixel), gathers dL/dS there and keeps dL/dI and the centre
 // and conic gradients in registers -- no atomics, no tile list.
 __global__ void __launch_bounds__(256)
-k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterParams rp,
-            const float4* __restrict__ iq, const float2* __restrict__ iw,
-            const float* __restrict__ dimg, float* __restrict__ grad_i)
+k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
+            int64_t records, RasterParams rp, const float4* __restrict__ iq,
+            const float2* __restrict__ iw, const float* __restrict__ dimg,
+            float* __restrict__ grad_i, float* __restrict__ cbwd)
 {
     const int64_t r0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     unsigned long long hits = 0;
@@ -697,6 +707,7 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
     grad_i[3 * records + r] = db;
     grad_i[4 * records + r] = dc;
     grad_i[5 * records + r] = dI;
+    cbwd[r] = scenes[V.scene].amp[r - V.rec_off] * dI;   // c = P dL/dI for pass A
     }
     if (rp.work) {   // one atomic per wave
 #pragma unroll
@@ -717,19 +728,19 @@ k_image_bwd(const DevView* __restrict__ views, int nv, int64_t records, RasterPa
 // maps U -> (1 - alpha) U + c alpha. The six per-entry gradient sums collect
 // in LDS and leave with one global atomic each per (tile, entry).
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
-k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
+k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                RasterParams rp, const uint32_t* __restrict__ status,
                const uint32_t* __restrict__ worklist, const uint2* __restrict__ ranges,
                const uint32_t* __restrict__ pvals, const uint64_t* __restrict__ pmask,
                const uint64_t* __restrict__ psum, const float4* __restrict__ cq,
                const float2* __restrict__ cw, const float* __restrict__ tau,
-               const uint32_t* __restrict__ nlast, const float* __restrict__ grad_i,
+               const uint32_t* __restrict__ nlast, const float* __restrict__ cbwd,
                float* __restrict__ grad_c, int64_t stride)
 {
     constexpr int NB = A_BATCH;
     __shared__ float4 s_q[NB][WAVE];
     __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
-    __shared__ float s_amp[NB][WAVE], s_dI[NB][WAVE];  // P and dL/dI of the entry
+    __shared__ float s_c[NB][WAVE];                    // c = P dL/dI of the entry
     __shared__ float s_G[NB][6][WAVE];
     __shared__ uint64_t s_m[NB][WAVE];
     __shared__ uint32_t s_r[NB][WAVE];
@@ -743,7 +754,6 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
     const int64_t bucket = worklist[blockIdx.x];
     const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
-    const float* amp = scenes[V.scene].amp;
     const float x0 = (float)(tc.tx * TILE) + 0.5f, y0 = (float)(tc.ty * TILE) + 0.5f;
     const uint2 rg = ranges[bucket];
     const int64_t ray = V.ray_off + (int64_t)tc.row * V.Wc + tc.col;
@@ -757,6 +767,24 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
     unsigned long long n_iter = 0, n_hits = 0;   // work counters
     const uint32_t n_max = wave_max_u32(n_mine);
     const uint32_t e_end = rg.x + n_max;           // exclusive end of the used entries
+    // the six per-entry sums of the last processed batch leave with atomics;
+    // they are sent while the next batch's loads are in flight
+    uint32_t got_prev = 0u;
+    auto flush = [&]() {
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (got_prev & (1u << k)) {
+                const uint32_t rk = s_r[k][lane];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const float v = s_G[k][c][lane];
+                    if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + rk], v);
+                    s_G[k][c][lane] = 0.0f;
+                }
+            }
+        }
+        got_prev = 0u;
+    };
     const int64_t c_first = rg.x / WAVE, c_end = (int64_t)(e_end + WAVE - 1) / WAVE;
     for (int64_t g1 = c_end; g1 > c_first && n_max > 0u; g1 -= WAVE) {
         const int64_t g0 = max(c_first, g1 - (int64_t)WAVE);
@@ -800,8 +828,10 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                     m[k] = in ? pmask[e] : 0ull;
                     r[k] = in ? pvals[e] : 0u;
                 }
+                // the previous batch's sums leave while these loads are in flight
+                flush();
                 // records straight into LDS, all in flight together (entries
-                // no ray needs read the view's first record, one shared line)
+                // no ray needs read record 0 of the view, one shared line)
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     const bool need = (m[k] & lv[k]) != 0ull;
@@ -811,8 +841,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                     load16_to_lds(cq + rk, &s_q[k][0]);
                     load4_to_lds(w, &s_wc[k][0]);
                     load4_to_lds(w + 1, &s_wk[k][0]);
-                    load4_to_lds(amp + (rk - V.rec_off), &s_amp[k][0]);
-                    load4_to_lds(grad_i + 5 * stride + rk, &s_dI[k][0]);
+                    load4_to_lds(cbwd + rk, &s_c[k][0]);
                 }
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
@@ -821,6 +850,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                     if (lane == k) s_chk[k] = chk[k];
                 }
             }
+            got_prev = got;
             wait_all_memory();
             wave_lds_sync();
             // the batch's chunks, transposed: bit j of col[k] is entry j of
@@ -888,7 +918,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                         const RayB rs = s_ray[rr];
                         const float4 g = s_q[k][j];
                         const float2 g2 = make_float2(s_wc[k][j], s_wk[k][j]);
-                        const float cj = s_amp[k][j] * s_dI[k][j];
+                        const float cj = s_c[k][j];
                         const int seg0 = valid ? max((int)rs.o - (int)base, 0) : lane;
                         bool real = false;
                         float x = 0.0f, E = 1.0f, ex = 0.0f, f = 0.0f, dx = 0.0f, dy = 0.0f;
@@ -953,21 +983,9 @@ k_raster_a_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ s
                 g0 = g1;
             }
             wave_lds_sync();
-#pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                if (got & (1u << k)) {
-                    const uint32_t rk = s_r[k][lane];
-#pragma unroll
-                    for (int c = 0; c < 6; ++c) {
-                        const float v = s_G[k][c][lane];
-                        if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + rk], v);
-                        s_G[k][c][lane] = 0.0f;
-                    }
-                }
-            }
-            wave_lds_sync();
         }
     }
+    flush();
     if (rp.work) {
         n_hits = wave_sum_u64(n_hits);
         if (lane == 0) {
@@ -1066,28 +1084,29 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
     return hipGetLastError();
 }
 
-hipError_t launch_image_bwd(const DevView* views, int nv, int64_t records,
-                            const RasterParams& rp, const float4* iq, const float2* iw,
-                            const float* dimg, float* grad_i, hipStream_t s)
+hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
+                            int64_t records, const RasterParams& rp, const float4* iq,
+                            const float2* iw, const float* dimg, float* grad_i, float* cbwd,
+                            hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_image_bwd, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
-                       rp, iq, iw, dimg, grad_i);
+    hipLaunchKernelGGL(k_image_bwd, dim3(grid256(records)), dim3(256), 0, s, views, scenes, nv,
+                       records, rp, iq, iw, dimg, grad_i, cbwd);
     return hipGetLastError();
 }
 
-hipError_t launch_raster_a_bwd(const DevView* views, const DevScene* scenes, int nv,
-                               int64_t tiles_c, const RasterParams& rp, const uint32_t* status,
+hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
+                               const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask,
                                const uint64_t* psum, const float4* cq, const float2* cw,
-                               const float* tau, const uint32_t* nlast, const float* grad_i,
+                               const float* tau, const uint32_t* nlast, const float* cbwd,
                                float* grad_c, int64_t stride, hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_a_bwd, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views, scenes,
-                       nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, tau, nlast,
-                       grad_i, grad_c, stride);
+    hipLaunchKernelGGL(k_raster_a_bwd, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views, nv, rp,
+                       status, worklist, ranges, pvals, pmask, psum, cq, cw, tau, nlast, cbwd,
+                       grad_c, stride);
     return hipGetLastError();
 }
 
