@@ -21,6 +21,7 @@ import math
 import os
 import sys
 import time
+import types
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -237,6 +238,11 @@ def main():
     res = step()
     exact = r._last_exact          # the exact pair counts (capacities add 10 %)
     torch.cuda.synchronize(dev)
+    # pairs the step actually sorted and rasterized: all computation-plane
+    # pairs, and imaging-plane pairs of the Gaussians with nonzero intensity
+    st = res.state[:64].view(torch.int32).cpu()
+    used = types.SimpleNamespace(records=exact.records, rays=exact.rays,
+                                 pairs_c=int(st[1]), pairs_i=int(st[2]))
 
     lib = _capi.lib()
     work = [0] * 8
@@ -278,13 +284,14 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": dict(cfg, parallelism="single GPU", pairs_c=exact.pairs_c,
-                       pairs_i=exact.pairs_i, tiles_c=exact.tiles_c, tiles_i=exact.tiles_i),
+        "config": dict(cfg, parallelism="single GPU", pairs_c=used.pairs_c,
+                       pairs_i=used.pairs_i, pairs_i_all=exact.pairs_i, tiles_c=exact.tiles_c,
+                       tiles_i=exact.tiles_i),
     }
     out["work"] = {"hits_a_fwd": work[0], "hits_a_bwd": work[1], "hits_b_fwd": work[2],
                    "hits_b_bwd": work[3], "entries_a_fwd": work[4], "entries_a_bwd": work[5],
                    "entries_b_fwd": work[6]}
-    out["path_hbm"] = path_hbm(exact, sc.n, views, ms_step)
+    out["path_hbm"] = path_hbm(used, sc.n, views, ms_step)
     if stages:
         per = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}
         out["stages_ms"] = {k: round(v, 4) for k, v in per.items()}
