@@ -37,12 +37,12 @@ int hip_fail(hipError_t e, const char* where)
 // ---- optional per-stage timing with HIP events on the caller's stream ----
 enum Stage {
     SG_QUERY, SG_PREPROCESS, SG_DEPTH_SORT, SG_BIN, SG_PAIR_SORT, SG_RANGES,
-    SG_RASTER_A_FWD, SG_INTENSITY, SG_RASTER_B_FWD, SG_ZERO, SG_RASTER_B_BWD,
+    SG_RASTER_A_FWD, SG_INTENSITY, SG_RASTER_B_FWD, SG_ACTIVE, SG_RASTER_B_BWD,
     SG_RASTER_A_BWD, SG_PARAMS_BWD, SG_BIN_I, SG_PAIR_SORT_I, SG_COUNT
 };
 const char* const kStageNames[SG_COUNT] = {
     "plan_query", "preprocess", "depth_sort", "bin_pairs", "pair_sort", "tile_ranges",
-    "raster_a_fwd", "set_intensity", "raster_b_fwd", "zero_grads", "raster_b_bwd",
+    "raster_a_fwd", "set_intensity", "raster_b_fwd", "active_records", "raster_b_bwd",
     "raster_a_bwd", "params_bwd", "bin_pairs_i", "pair_sort_i"};
 
 struct Profiler {
@@ -193,6 +193,7 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         d.dA = in.d_az; d.dR = in.d_rg;
         d.dAc = in.comp_d_az > 0.0 ? in.comp_d_az : in.d_az;
         d.dEc = in.comp_d_el > 0.0 ? in.comp_d_el : in.d_rg * tan(in.grazing);
+        d.iA = 1.0 / d.dA; d.iR = 1.0 / d.dR; d.iAc = 1.0 / d.dAc; d.iEc = 1.0 / d.dEc;
         d.hW = 0.5 * (double)d.W; d.hH = 0.5 * (double)d.H;
         d.hWc = 0.5 * (double)d.Wc; d.hHc = 0.5 * (double)d.Hc;
         d.txc = (d.Wc + TILE - 1) / TILE; d.tyc = (d.Hc + TILE - 1) / TILE;
@@ -264,10 +265,11 @@ struct Bufs {
     uint32_t* hist = nullptr;
     uint32_t* scan_tmp = nullptr;
     unsigned long long* slots = nullptr;   // spread pair-total accumulators
-    // backward accumulators, 8 floats per record
+    // backward accumulators: 13 floats and one list slot per record
     float* grad_c = nullptr;
     float* grad_i = nullptr;
     float* cbwd = nullptr;          // c = P dL/dI per record (pass A backward)
+    uint32_t* active = nullptr;     // records with A > 0 (backward)
 };
 
 struct Arena {
@@ -343,6 +345,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.grad_c = sc.take<float>(6 * R);   // plane-major, see launch_params_backward
         b.grad_i = sc.take<float>(6 * R);
         b.cbwd = sc.take<float>(R);
+        b.active = sc.take<uint32_t>(R);
     }
     if (state_bytes) *state_bytes = st.off;
     if (scratch_bytes) *scratch_bytes = sc.off;
@@ -640,13 +643,16 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     }
     const int pw = final_buffer_c(P);
     {
-        StageTimer t(SG_ZERO, s);
-        SDGR_HIP(launch_fill_u32((uint32_t*)b.grad_c, 0u, 6 * P.records, s));
+        // only the records pass A used carry gradients; their sums are
+        // cleared here and nothing else is read by the passes below
+        StageTimer t(SG_ACTIVE, s);
+        SDGR_HIP(launch_fill_u32(b.status + ST_ACTIVE, 0u, 1, s));
+        SDGR_HIP(launch_active_records(P.records, b.A, b.status, b.active, b.grad_c, s));
     }
     {
         StageTimer t(SG_RASTER_B_BWD, s);
-        SDGR_HIP(launch_image_bwd(b.views, b.scenes, P.nv, P.records, P.rp, b.iq, b.iw,
-                                  dL_dimages, b.grad_i, b.cbwd, s));
+        SDGR_HIP(launch_image_bwd(b.views, b.scenes, P.nv, P.records, P.rp, b.status, b.active,
+                                  b.iq, b.iw, dL_dimages, b.grad_i, b.cbwd, s));
     }
     {
         StageTimer t(SG_RASTER_A_BWD, s);

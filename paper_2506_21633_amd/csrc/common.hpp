@@ -18,6 +18,7 @@ constexpr int RASTER_THREADS = RASTER_WAVES * WAVE;
 struct DevView {
     double ex[3], ey[3], ez[3];   // rows of the world-to-radar rotation
     double dA, dR, dAc, dEc;      // image and computation-plane spacings
+    double iA, iR, iAc, iEc;      // their reciprocals
     double hW, hH, hWc, hHc;      // half sizes (centre of each grid)
     int64_t rec_off;              // first record (view, Gaussian) of the view
     int64_t img_off;              // float offset of the image
@@ -66,6 +67,7 @@ enum StatusSlot : int {
     ST_PAIRS_C = 1,    // computation-plane pairs of the last projection (sort length)
     ST_PAIRS_I = 2,    // imaging-plane pairs of records with nonzero intensity
     ST_WORK_TILES = 4, // non-empty computation-plane tiles in the worklist
+    ST_ACTIVE = 5,     // records pass A used (backward list length)
     ST_COUNT = 8       // u64 pair totals of the projection at status + 8
 };
 
@@ -239,10 +241,12 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
                                int64_t cap_i, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
                                const float2* iw, float* images, hipStream_t s);
+hipError_t launch_active_records(int64_t records, const float* A, uint32_t* status,
+                                 uint32_t* active, float* grad_c, hipStream_t s);
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
-                            int64_t records, const RasterParams& rp, const float4* iq,
-                            const float2* iw, const float* dimg, float* grad_i, float* cbwd,
-                            hipStream_t s);
+                            int64_t records, const RasterParams& rp, const uint32_t* status,
+                            const uint32_t* active, const float4* iq, const float2* iw,
+                            const float* dimg, float* grad_i, float* cbwd, hipStream_t s);
 hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,

@@ -16,7 +16,6 @@ struct Geo {
     bool valid;
     double qn[4], qnorm, s[3], R[9], M[9];
     double S[6];        // 3D covariance xx, xy, xz, yy, yz, zz
-    double x, y, z;     // radar coordinates
 };
 
 __device__ __forceinline__ bool finite(double a) { return isfinite(a); }
@@ -34,7 +33,9 @@ __device__ __attribute__((noinline)) double range_coordinate(const double* ez, d
     return (a + b) + c;
 }
 
-__device__ void geometry(const DevView& V, const DevScene& S, int64_t i, Geo& g)
+// View-independent frame of Gaussian i: unit quaternion, rotation R,
+// M = R diag(s) and Sigma = M M^T.
+__device__ void gaussian_frame(const DevScene& S, int64_t i, Geo& g)
 {
     const float* mu = S.means + 3 * i;
     const float* sc = S.scales + 3 * i;
@@ -65,9 +66,6 @@ __device__ void geometry(const DevView& V, const DevScene& S, int64_t i, Geo& g)
     };
     g.S[0] = row(0, 0); g.S[1] = row(0, 1); g.S[2] = row(0, 2);
     g.S[3] = row(1, 1); g.S[4] = row(1, 2); g.S[5] = row(2, 2);
-    g.x = V.ex[0] * m0 + V.ex[1] * m1 + V.ex[2] * m2;
-    g.y = V.ey[0] * m0 + V.ey[1] * m1 + V.ey[2] * m2;
-    g.z = range_coordinate(V.ez, m0, m1, m2);
 }
 
 // u^T Sigma w with Sigma given by its 6 unique entries
@@ -80,19 +78,21 @@ __device__ __forceinline__ double quad(const double* u, const double* S, const d
 }
 
 // 2D covariance of one plane spanned by radar axes u, w with spacings su, sw.
+// iu, iw: reciprocal spacings along u and w
 __device__ __forceinline__ void plane_cov(const Geo& g, const double* u, const double* w,
-                                          double su, double sw, double dil, double* cov)
+                                          double iu, double iw, double dil, double* cov)
 {
-    cov[0] = quad(u, g.S, u) / (su * su) + dil;
-    cov[1] = quad(u, g.S, w) / (su * sw);
-    cov[2] = quad(w, g.S, w) / (sw * sw) + dil;
+    cov[0] = quad(u, g.S, u) * (iu * iu) + dil;
+    cov[1] = quad(u, g.S, w) * (iu * iw);
+    cov[2] = quad(w, g.S, w) * (iw * iw) + dil;
 }
 
 __device__ __forceinline__ bool conic(const double* cov, double* Q)
 {
     double det = cov[0] * cov[2] - cov[1] * cov[1];
     if (!(det > 0.0) || !isfinite(det)) return false;
-    Q[0] = cov[2] / det; Q[1] = -cov[1] / det; Q[2] = cov[0] / det;
+    const double id = 1.0 / det;
+    Q[0] = cov[2] * id; Q[1] = -cov[1] * id; Q[2] = cov[0] * id;
     return true;
 }
 
@@ -291,7 +291,7 @@ k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ 
 // + c dy^2) and centre gradient -> dSigma (6 unique, symmetric full-matrix
 // convention) and dmu.
 __device__ void plane_adjoint(const double* Q, const float* gq, const double* u,
-                              const double* w, double su, double sw, double* dS, double* dmu)
+                              const double* w, double a, double b, double* dS, double* dmu)
 {
     // symmetric gradient of the conic matrix, then dSigma2 = -Q G Q
     double g00 = gq[2], g01 = 0.5 * (double)gq[3], g11 = gq[4];
@@ -301,7 +301,6 @@ __device__ void plane_adjoint(const double* Q, const float* gq, const double* u,
     double h00 = -(t00 * q00 + t01 * q01);
     double h01 = -(t00 * q01 + t01 * q11);
     double h11 = -(t10 * q01 + t11 * q11);
-    double a = 1.0 / su, b = 1.0 / sw;
     h00 *= a * a; h01 *= a * b; h11 *= b * b;
     // dSigma += h00 u u^T + h01 (u w^T + w u^T) + h11 w w^T
     int idx[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
@@ -328,16 +327,17 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
     double dmu[3] = {0, 0, 0}, dS[6] = {0, 0, 0, 0, 0, 0};
     double dk = 0.0, dp = 0.0;
     Geo g;
-    g.valid = false;
+    gaussian_frame(S, i, g);
     bool any = false;
-    for (int v = 0; v < nv; ++v) {
+    for (int v = 0; v < nv && g.valid; ++v) {
         const DevView& V = views[v];
         if (V.scene != s) continue;
-        geometry(V, S, i, g);
-        if (!g.valid) break;
+        // a record pass A never used (A = 0) has zero gradients in this view,
+        // and its gradient sums were never written
+        if (A[V.rec_off + i] == 0.0f) continue;
         double covC[3], covI[3], QC[3], QI[3];
-        plane_cov(g, V.ex, V.ey, V.dAc, V.dEc, rp.dilation, covC);
-        plane_cov(g, V.ex, V.ez, V.dA, V.dR, rp.dilation, covI);
+        plane_cov(g, V.ex, V.ey, V.iAc, V.iEc, rp.dilation, covC);
+        plane_cov(g, V.ex, V.ez, V.iA, V.iR, rp.dilation, covI);
         if (!conic(covC, QC) || !conic(covI, QI)) continue;  // no pairs in this view
         any = true;
         int64_t r = V.rec_off + i;
@@ -346,8 +346,8 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
             gc[k] = grad_c[k * records + r];
             gi[k] = grad_i[k * records + r];
         }
-        plane_adjoint(QC, gc, V.ex, V.ey, V.dAc, V.dEc, dS, dmu);
-        plane_adjoint(QI, gi, V.ex, V.ez, V.dA, V.dR, dS, dmu);
+        plane_adjoint(QC, gc, V.ex, V.ey, V.iAc, V.iEc, dS, dmu);
+        plane_adjoint(QI, gi, V.ex, V.ez, V.iA, V.iR, dS, dmu);
         dk += gc[5];
         dp += (double)A[r] * gi[5];
     }
