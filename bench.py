@@ -289,8 +289,8 @@ def main():
                        tiles_i=exact.tiles_i),
     }
     out["work"] = {"hits_a_fwd": work[0], "hits_a_bwd": work[1], "hits_b_fwd": work[2],
-                   "hits_b_bwd": work[3], "entries_a_fwd": work[4], "entries_a_bwd": work[5],
-                   "entries_b_fwd": work[6]}
+                   "hits_b_bwd": work[3], "rounds_a_fwd": work[4], "rounds_a_bwd": work[5],
+                   "rounds_b_fwd": work[6], "list_prefix_a": work[7]}
     out["path_hbm"] = path_hbm(used, sc.n, views, ms_step)
     if stages:
         per = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}

@@ -228,9 +228,11 @@ const char* sdgr_profile_stage(int32_t i);
 /* Work counters. While sdgr_profile_count(1) is in effect, forward and
  * backward calls count, in `state`, the (cell, Gaussian) evaluations inside
  * the footprint (q < q_max) of pass A forward, pass A backward, pass B
- * forward and pass B backward (out[0..3]) and the list entries evaluated by
- * a whole tile in pass A forward, pass A backward and pass B forward
- * (out[4..6]); the counting adds atomics, so timed runs leave it off.
+ * forward and pass B backward (out[0..3]), the rounds of 64 evaluations
+ * (pass A forward and backward) or 64 list entries (pass B forward) a wave
+ * ran (out[4..6]), and the summed length of the tile-list prefixes some ray
+ * of pass A used (out[7]); the counting adds atomics, so timed runs leave it
+ * off.
  * sdgr_read_work synchronises `stream` and copies min(n, 8) counters of the
  * last forward (and backward) that used `state`. */
 int sdgr_profile_count(int32_t on);

@@ -391,7 +391,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
         StageTimer t(SG_PREPROCESS, s);
         SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, R, P.rp, true, b.cq, b.cw, b.iq,
                                    b.iw, b.rect_c, b.rect_i, b.cnt_c, b.cnt_i, b.dkey[0],
-                                   b.dval[0], b.slots,
+                                   b.slots,
                                    reinterpret_cast<unsigned long long*>(b.status + ST_COUNT),
                                    s));
     }
@@ -402,7 +402,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     {
         StageTimer t(SG_DEPTH_SORT, s);
         SDGR_HIP(launch_radix_sort_u32(dk, dv, R, b.status + ST_RECORDS, passes_bits_depth(P),
-                                       b.hist, b.scan_tmp, &which, s));
+                                       true, b.hist, b.scan_tmp, &which, s));
     }
     uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};
@@ -418,7 +418,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     {
         StageTimer t(SG_PAIR_SORT, s);
         SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_c, b.status + ST_PAIRS_C,
-                                       bits_pairs_c(P), b.hist, b.scan_tmp, &pw, s));
+                                       bits_pairs_c(P), false, b.hist, b.scan_tmp, &pw, s));
     }
     if (plan->pairs_c > 0 && pw != final_buffer_c(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
@@ -449,7 +449,7 @@ int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     int pw = 0;
     StageTimer t(SG_PAIR_SORT_I, s);
     SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_i, b.status + ST_PAIRS_I, bits_pairs_i(P),
-                                   b.hist, b.scan_tmp, &pw, s));
+                                   false, b.hist, b.scan_tmp, &pw, s));
     if (plan->pairs_i > 0 && pw != final_buffer_i(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
     return SDGR_OK;
@@ -510,7 +510,7 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
         StageTimer t(SG_QUERY, s);
         SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.records, P.rp, false, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   nullptr, nullptr, nullptr, slots, totals, s));
+                                   nullptr, nullptr, slots, totals, s));
     }
     unsigned long long host_tot[2] = {0, 0};
     SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));

@@ -126,33 +126,48 @@ __device__ __forceinline__ float wave_sum(float v)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Workgroups go to the eight XCDs (each with its own L2) round-robin by id.
+// For a grid whose first n workgroups have work, this renumbering hands each
+// XCD one contiguous range of [0, n), so workgroups that read the same
+// records (neighbouring list entries) share an L2; ids >= n stay as they are.
+constexpr uint32_t XCDS = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t pid, uint32_t n)
+{
+    if (pid >= n) return pid;
+    const uint32_t x = pid % XCDS, q = n / XCDS, r = n % XCDS;
+    return x * q + min(x, r) + pid / XCDS;
+}
+
 __device__ __forceinline__ float quadform(float4 g, float c, float dx, float dy)
 {
     return g.z * dx * dx + 2.0f * g.w * dx * dy + c * dy * dy;
 }
 
 // Cells of tile (tx, ty) inside the ellipse q < q_max of a Gaussian with
-// centre (cx, cy) and conic (a, b, c): per row the exact column span from
-// the quadratic, widened by a small slack. Bit 8 * row + col.
+// centre (cx, cy) and conic (a, b, c): per row the column span from the
+// quadratic, widened by a slack that covers the rounding of the hardware
+// reciprocal and square root, so the mask holds every cell whose FP32 q is
+// below q_max (callers test q itself). Bit 8 * row + col.
 __device__ inline uint64_t footprint_mask(float cx, float cy, float a, float b, float c, float qm,
                                    int tx, int ty)
 {
     const float det = a * c - b * b;
     if (!(det > 0.0f) || !(a > 0.0f)) return 0ull;
     const float slack = 1e-3f;
+    const float ia = __builtin_amdgcn_rcpf(a);
+    const float aq = a * qm, dmin = -1e-4f * aq;
     uint64_t m = 0ull;
-    const float x0 = (float)(tx * TILE);
+    const float x0 = (float)(tx * TILE) + 0.5f;
 #pragma unroll
     for (int k = 0; k < TILE; ++k) {
         const float dy = (float)(ty * TILE + k) + 0.5f - cy;
-        const float D = a * qm - det * dy * dy;
-        if (D < 0.0f) continue;
-        const float half = sqrtf(D) / a + slack;
-        const float xc = cx - b * dy / a;
-        // local columns j with |x0 + j + 1/2 - xc| <= half
-        const float lo = fmaxf(ceilf(xc - half - 0.5f - x0), 0.0f);
-        const float hi = fminf(floorf(xc + half - 0.5f - x0), (float)(TILE - 1));
-        if (lo > hi) continue;
+        const float D = aq - det * dy * dy;
+        const float half = __builtin_amdgcn_sqrtf(fmaxf(D, 0.0f)) * ia + slack;
+        const float xc = cx - b * ia * dy;
+        // local columns j with |x0 + j - xc| <= half
+        const float lo = fmaxf(ceilf(xc - half - x0), 0.0f);
+        const float hi = fminf(floorf(xc + half - x0), (float)(TILE - 1));
+        if (D < dmin || lo > hi) continue;
         const uint32_t j0 = (uint32_t)lo, j1 = (uint32_t)hi;
         const uint64_t row_bits = ((1ull << (j1 - j0 + 1)) - 1ull) << j0;
         m |= row_bits << (TILE * k);
@@ -174,7 +189,7 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
                              int64_t records, const RasterParams& rp,
                              bool write_records, float4* cq, float2* cw, float4* iq,
                              float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* cnt_c,
-                             uint32_t* cnt_i, uint32_t* dkey, uint32_t* dval,
+                             uint32_t* cnt_i, uint32_t* dkey,
                              unsigned long long* slots, unsigned long long* totals,
                              hipStream_t s);
 
@@ -201,8 +216,11 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
 // the input; returns in *which the index of the buffer holding the output.
 size_t radix_hist_words(int64_t cap);
 int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
+// Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
+// n_dev items (at most cap); iota_vals: the input values are the positions
+// 0..n-1 and vals[0] is not read. *which: the buffer holding the result.
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
-                                 const uint32_t* n_dev, int bits, uint32_t* hist,
+                                 const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  uint32_t* scan_tmp, int* which, hipStream_t s);
 
 hipError_t launch_gather_rects(const uint32_t* order, const uint2* rect, int64_t n,

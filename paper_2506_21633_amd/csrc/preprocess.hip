@@ -167,8 +167,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
              float2* __restrict__ cw, float4* __restrict__ iq, float2* __restrict__ iw,
              uint2* __restrict__ rect_c, uint2* __restrict__ rect_i,
              uint32_t* __restrict__ cnt_c, uint32_t* __restrict__ cnt_i,
-             uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval,
-             unsigned long long* __restrict__ totals)
+             uint32_t* __restrict__ dkey, unsigned long long* __restrict__ totals)
 {
     __shared__ unsigned long long part[2];
     if (threadIdx.x < 2) part[threadIdx.x] = 0;
@@ -209,8 +208,8 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
             const float ex[3] = {(float)V.ex[0], (float)V.ex[1], (float)V.ex[2]};
             const float ey[3] = {(float)V.ey[0], (float)V.ey[1], (float)V.ey[2]};
             const float ez[3] = {(float)V.ez[0], (float)V.ez[1], (float)V.ez[2]};
-            const float iA = (float)(1.0 / V.dA), iR = (float)(1.0 / V.dR);
-            const float iAc = (float)(1.0 / V.dAc), iEc = (float)(1.0 / V.dEc);
+            const float iA = (float)V.iA, iR = (float)V.iR;
+            const float iAc = (float)V.iAc, iEc = (float)V.iEc;
             const Conic2 C = plane_conic(Mt, ex, ey, iAc, iEc, rp.dilation);
             const Conic2 I = plane_conic(Mt, ex, ez, iA, iR, rp.dilation);
             ok = C.ok && I.ok;
@@ -240,11 +239,19 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
             cnt_c[r] = nc;
             cnt_i[r] = ni;
             dkey[r] = float_order_bits(__uint_as_float(zbits));
-            dval[r] = (uint32_t)r;
         }
     }
-    if (nc) atomicAdd(&part[0], (unsigned long long)nc);
-    if (ni) atomicAdd(&part[1], (unsigned long long)ni);
+    // wave sums first: 256 same-address LDS atomics would serialise
+    unsigned long long wc = nc, wi = ni;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        wc += (unsigned long long)__shfl_xor((long long)wc, d, WAVE);
+        wi += (unsigned long long)__shfl_xor((long long)wi, d, WAVE);
+    }
+    if (lane_id() == 0) {
+        if (wc) atomicAdd(&part[0], wc);
+        if (wi) atomicAdd(&part[1], wi);
+    }
     __syncthreads();
     // spread over TOTAL_SLOTS addresses; k_sum_slots adds them up
     if (threadIdx.x < 2 && part[threadIdx.x])
@@ -409,7 +416,7 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
                              int64_t records, const RasterParams& rp, bool write_records,
                              float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
                              uint2* rect_i, uint32_t* cnt_c, uint32_t* cnt_i, uint32_t* dkey,
-                             uint32_t* dval, unsigned long long* slots,
+                             unsigned long long* slots,
                              unsigned long long* totals, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(2 * TOTAL_SLOTS / 256), dim3(256), 0, s, slots,
@@ -417,7 +424,7 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
     if (records > 0)
         hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
                            scenes, nv, records, rp, write_records ? 1 : 0, cq, cw, iq, iw,
-                           rect_c, rect_i, cnt_c, cnt_i, dkey, dval, slots);
+                           rect_c, rect_i, cnt_c, cnt_i, dkey, slots);
     hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(TOTAL_SLOTS), 0, s, slots, totals);
     return hipGetLastError();
 }

@@ -282,8 +282,9 @@ k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParam
              const float2* __restrict__ cw, uint64_t* __restrict__ pmask,
              uint64_t* __restrict__ psum)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t kc = min(cap, (int64_t)status[ST_PAIRS_C]);
+    const uint32_t nblk = (uint32_t)((kc + blockDim.x - 1) / blockDim.x);
+    const int64_t p = (int64_t)xcd_block(blockIdx.x, nblk) * blockDim.x + threadIdx.x;
     if (p - lane_id() >= kc) return;   // whole wave past the end
     uint64_t m = 0ull;
     if (p < kc) {
@@ -539,9 +540,11 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     flush();
     if (rp.work) {
         n_hits = wave_sum_u64(n_hits);
+        const uint32_t used = wave_max_u32(last);   // list prefix any ray used
         if (lane == 0) {
             atomicAdd(&rp.work[4], n_iter);
             atomicAdd(&rp.work[0], n_hits);
+            atomicAdd(&rp.work[7], (unsigned long long)used);
         }
     }
     if (tc.inside) {
@@ -577,7 +580,9 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64
     __shared__ float2 s_w[RASTER_WAVES][WAVE];
     const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const uint32_t ki = status[ST_PAIRS_I];
-    const uint64_t seg = (uint64_t)blockIdx.x * RASTER_WAVES + w;
+    const uint32_t nblk = (uint32_t)(((uint64_t)ki + (uint64_t)B_SEGMENT * RASTER_WAVES - 1) /
+                                     ((uint64_t)B_SEGMENT * RASTER_WAVES));
+    const uint64_t seg = (uint64_t)xcd_block(blockIdx.x, nblk) * RASTER_WAVES + w;
     const uint64_t p0 = (uint64_t)cap_c + seg * B_SEGMENT;
     const uint64_t pend = (uint64_t)cap_c + ki;
     if (p0 >= pend) return;
@@ -734,8 +739,8 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
         for (int row = row0; row <= row1; ++row) {
             const float dy = row + 0.5f - g.y;
             const float D = a * qm - det * dy * dy;
-            if (D < 0.0f) continue;
-            const float half = sqrtf(D) / a;
+            if (D < -1e-4f * a * qm) continue;   // rows an FP32 q < q_max can still reach
+            const float half = sqrtf(fmaxf(D, 0.0f)) / a;
             const float xc = g.x - b * dy / a;
             const int col0 = (int)fmaxf(0.0f, ceilf(xc - half - 0.5f) - 1.0f);
             const int col1 = (int)fminf((float)(V.W - 1), floorf(xc + half - 0.5f) + 1.0f);

@@ -105,60 +105,133 @@ inline int digit_bits(int bits)
     return d < 8 ? 8 : d;
 }
 
-// Block digit histogram. Keys are often long runs of one digit (pair keys
-// are tile ids of a few busy tiles), so each wave first groups its lanes by
-// digit (ballot match over the digit bits) and only one lane per digit adds
-// the group's count: same-address LDS atomics would serialise 64-fold.
+// Sort grids have at most MAX_SORT_BLOCKS blocks; each takes a contiguous
+// run of 4096-item tiles of the actual item count, so the per-block digit
+// counts (digit-major, R x nb words) and their scan stay small however long
+// the array is.
+constexpr unsigned MAX_SORT_BLOCKS = 2048;
+inline unsigned sort_grid(int64_t cap) { return std::min(nblocks(cap), MAX_SORT_BLOCKS); }
+
+struct SortSpan {
+    int64_t n;      // items
+    uint32_t nb;    // blocks with items
+    uint32_t tpb;   // tiles per block
+};
+
+__device__ __forceinline__ SortSpan sort_span(const uint32_t* n_dev, uint32_t grid)
+{
+    SortSpan sp;
+    sp.n = *n_dev;
+    const uint32_t tiles = (uint32_t)((sp.n + SN - 1) / SN);
+    sp.tpb = max(1u, (tiles + grid - 1) / grid);
+    sp.nb = (tiles + sp.tpb - 1) / sp.tpb;
+    return sp;
+}
+
+// Block digit histogram over the block's tiles. Keys are often long runs of
+// one digit (pair keys are tile ids of a few busy tiles), so each wave first
+// groups its lanes by digit (ballot match over the digit bits) and only one
+// lane per digit adds the group's count: same-address LDS atomics would
+// serialise 64-fold.
 template <int BITS>
 __global__ void __launch_bounds__(SB)
 k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int shift,
-             uint32_t* __restrict__ hist, unsigned nb)
+             uint32_t* __restrict__ hist)
 {
     constexpr int R = 1 << BITS;
     __shared__ uint32_t h[R];
+    const SortSpan sp = sort_span(n_dev, gridDim.x);
+    if (blockIdx.x >= sp.nb) return;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
 #pragma unroll
     for (int d = tid; d < R; d += SB) h[d] = 0;
     __syncthreads();
-    const int64_t n = *n_dev;
-    const int64_t base = (int64_t)blockIdx.x * SN;
+    const int64_t n = sp.n;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    uint32_t key[SI];
+    for (uint32_t t = 0; t < sp.tpb; ++t) {
+        const int64_t base = ((int64_t)blockIdx.x * sp.tpb + t) * SN;
+        if (base >= n) break;
+        uint32_t key[SI];
 #pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        const int64_t idx = base + k * SB + tid;
-        key[k] = idx < n ? keys[idx] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        const int64_t idx = base + k * SB + tid;
-        const bool valid = idx < n;
-        const uint32_t d = (key[k] >> shift) & (R - 1);
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < BITS; ++b) {
-            const uint64_t bb = __ballot((d >> b) & 1u);
-            m &= ((d >> b) & 1u) ? bb : ~bb;
+        for (int k = 0; k < SI; ++k) {
+            const int64_t idx = base + k * SB + tid;
+            key[k] = idx < n ? keys[idx] : 0u;
         }
-        if (valid && (m & below) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(m));
+#pragma unroll
+        for (int k = 0; k < SI; ++k) {
+            const int64_t idx = base + k * SB + tid;
+            const bool valid = idx < n;
+            const uint32_t d = (key[k] >> shift) & (R - 1);
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < BITS; ++b) {
+                const uint64_t bb = __ballot((d >> b) & 1u);
+                m &= ((d >> b) & 1u) ? bb : ~bb;
+            }
+            if (valid && (m & below) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(m));
+        }
     }
     __syncthreads();
 #pragma unroll
-    for (int d = tid; d < R; d += SB) hist[(int64_t)d * nb + blockIdx.x] = h[d];
+    for (int d = tid; d < R; d += SB) hist[(int64_t)d * sp.nb + blockIdx.x] = h[d];
 }
 
-// Stable scatter of one 4096-item block. Each wave ranks its own 1024
-// consecutive items in 16 rounds of 64 (ballot match over the digit bits,
-// per-wave digit counters in LDS, no block barrier); the block then turns
-// the per-wave counts into digit-major local offsets, places the items in
-// LDS in digit order and writes them out so that the items of one digit
-// leave as a contiguous run.
+// Spine of one pass: block d turns row d of the digit-major block counts
+// into its exclusive prefix over blocks, in place, and writes the digit's
+// total to tot[d] (the scatter adds the prefix over digits).
+__global__ void __launch_bounds__(SB)
+k_radix_spine(uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
+              const uint32_t* __restrict__ n_dev, unsigned grid)
+{
+    constexpr int PER = MAX_SORT_BLOCKS / SB;
+    __shared__ uint32_t wtot[SB / WAVE];
+    const SortSpan sp = sort_span(n_dev, grid);
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    uint32_t* row = hist + (int64_t)blockIdx.x * sp.nb;
+    uint32_t v[PER], sum = 0u;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t b = (uint32_t)(tid * PER + k);
+        v[k] = b < sp.nb ? row[b] : 0u;
+        sum += v[k];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int dd = 1; dd < WAVE; dd <<= 1) {
+        const uint32_t c = __shfl_up(inc, dd, WAVE);
+        if (lane >= dd) inc += c;
+    }
+    if (lane == WAVE - 1) wtot[w] = inc;
+    __syncthreads();
+    uint32_t run = inc - sum, all = 0u;
+#pragma unroll
+    for (int ww = 0; ww < SB / WAVE; ++ww) {
+        if (ww < w) run += wtot[ww];
+        all += wtot[ww];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t b = (uint32_t)(tid * PER + k);
+        if (b < sp.nb) row[b] = run;
+        run += v[k];
+    }
+    if (tid == 0) tot[blockIdx.x] = all;
+}
+
+// Stable scatter, one 4096-item tile at a time over the block's tiles. Each
+// wave ranks its own 1024 consecutive items in 16 rounds of 64 (ballot
+// match over the digit bits, per-wave digit counters in LDS, no block
+// barrier); the block then turns the per-wave counts into digit-major local
+// offsets, places the items in LDS in digit order and writes them out so
+// that the items of one digit leave as a contiguous run. The block's next
+// position per digit carries over from tile to tile. With vin null the
+// values are the items' input positions.
 template <int BITS>
 __global__ void __launch_bounds__(SB)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int shift,
-                const uint32_t* __restrict__ offs, unsigned nb)
+                const uint32_t* __restrict__ offs, const uint32_t* __restrict__ tot)
 {
     constexpr int R = 1 << BITS;
     constexpr int NW = SB / WAVE;
@@ -168,131 +241,179 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t s_key[SN];
     __shared__ uint32_t s_val[SN];
+    const SortSpan sp = sort_span(n_dev, gridDim.x);
+    if (blockIdx.x >= sp.nb) return;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-    const int64_t n = *n_dev;
-    const int64_t blk = (int64_t)blockIdx.x * SN;
-    if (blk >= n) return;
-    const uint32_t cnt_blk = (uint32_t)min((int64_t)SN, n - blk);
+    const int64_t n = sp.n;
+    uint32_t run[DPT];   // next output position of my digits
+    {
+        // items of all smaller digits (exclusive scan of the digit totals)
+        uint32_t t[DPT], sum = 0u;
 #pragma unroll
-    for (int k = 0; k < DPT; ++k)
+        for (int k = 0; k < DPT; ++k) {
+            t[k] = tot[tid * DPT + k];
+            sum += t[k];
+        }
+        uint32_t inc = sum;
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) wc[ww][tid * DPT + k] = 0u;
-    __syncthreads();
+        for (int dd = 1; dd < WAVE; dd <<= 1) {
+            const uint32_t c = __shfl_up(inc, dd, WAVE);
+            if (lane >= dd) inc += c;
+        }
+        if (lane == WAVE - 1) wsum[w] = inc;
+        __syncthreads();
+        uint32_t base = inc - sum;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww)
+            if (ww < w) base += wsum[ww];
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            run[k] = base + offs[(int64_t)(tid * DPT + k) * sp.nb + blockIdx.x];
+            base += t[k];
+        }
+        __syncthreads();   // wsum is reused per tile
+    }
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     uint32_t key[SI], val[SI], rank[SI];
+    auto load_tile = [&](int64_t blk) {
 #pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
-        const bool valid = idx < n;
-        key[k] = valid ? kin[idx] : 0u;
-        val[k] = valid ? vin[idx] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
-        const bool valid = idx < n;
-        const uint32_t d = (key[k] >> shift) & (R - 1);
-        uint64_t m = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < BITS; ++b) {
-            const uint64_t bb = __ballot((d >> b) & 1u);
-            m &= ((d >> b) & 1u) ? bb : ~bb;
+        for (int k = 0; k < SI; ++k) {
+            const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
+            const bool valid = idx < n;
+            key[k] = valid ? kin[idx] : 0u;
+            val[k] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
         }
-        const uint32_t before = valid ? wc[w][d] : 0u;
-        rank[k] = before + (uint32_t)__popcll(m & below);
-        __builtin_amdgcn_wave_barrier();
-        if (valid && (m & below) == 0ull) wc[w][d] = before + (uint32_t)__popcll(m);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    __syncthreads();
-    // digit totals of the block, exclusive scan over digits (digit-major)
-    uint32_t tot[DPT], run = 0u;
+    };
+    const int64_t first = (int64_t)blockIdx.x * sp.tpb * SN;
+    load_tile(first);
+    for (uint32_t t = 0; t < sp.tpb; ++t) {
+        const int64_t blk = first + (int64_t)t * SN;
+        if (blk >= n) break;
+        const uint32_t cnt_blk = (uint32_t)min((int64_t)SN, n - blk);
 #pragma unroll
-    for (int k = 0; k < DPT; ++k) {
-        uint32_t t = 0u;
+        for (int k = 0; k < DPT; ++k)
 #pragma unroll
-        for (int ww = 0; ww < NW; ++ww) t += wc[ww][tid * DPT + k];
-        tot[k] = t;
-        run += t;
-    }
-    uint32_t inc = run;
+            for (int ww = 0; ww < NW; ++ww) wc[ww][tid * DPT + k] = 0u;
+        __syncthreads();
 #pragma unroll
-    for (int dd = 1; dd < WAVE; dd <<= 1) {
-        const uint32_t t = __shfl_up(inc, dd, WAVE);
-        if (lane >= dd) inc += t;
-    }
-    if (lane == WAVE - 1) wsum[w] = inc;
-    __syncthreads();
-    uint32_t lofs = inc - run;
-#pragma unroll
-    for (int ww = 0; ww < NW; ++ww)
-        if (ww < w) lofs += wsum[ww];
-#pragma unroll
-    for (int k = 0; k < DPT; ++k) {
-        const int d = tid * DPT + k;
-        gbase[d] = offs[(int64_t)d * nb + blockIdx.x] - lofs;
-        uint32_t o = lofs;
-#pragma unroll
-        for (int ww = 0; ww < NW; ++ww) {
-            const uint32_t c = wc[ww][d];
-            wc[ww][d] = o;
-            o += c;
-        }
-        lofs += tot[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
-        if (idx < n) {
+        for (int k = 0; k < SI; ++k) {
+            const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
+            const bool valid = idx < n;
             const uint32_t d = (key[k] >> shift) & (R - 1);
-            const uint32_t pos = wc[w][d] + rank[k];
-            s_key[pos] = key[k];
-            s_val[pos] = val[k];
+            uint64_t m = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < BITS; ++b) {
+                const uint64_t bb = __ballot((d >> b) & 1u);
+                m &= ((d >> b) & 1u) ? bb : ~bb;
+            }
+            const uint32_t before = valid ? wc[w][d] : 0u;
+            rank[k] = before + (uint32_t)__popcll(m & below);
+            __builtin_amdgcn_wave_barrier();
+            if (valid && (m & below) == 0ull) wc[w][d] = before + (uint32_t)__popcll(m);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
-    }
-    __syncthreads();
+        __syncthreads();
+        // digit totals of the tile, exclusive scan over digits (digit-major)
+        uint32_t tot[DPT], sum = 0u;
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            uint32_t c = 0u;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) c += wc[ww][tid * DPT + k];
+            tot[k] = c;
+            sum += c;
+        }
+        uint32_t inc = sum;
+#pragma unroll
+        for (int dd = 1; dd < WAVE; dd <<= 1) {
+            const uint32_t c = __shfl_up(inc, dd, WAVE);
+            if (lane >= dd) inc += c;
+        }
+        if (lane == WAVE - 1) wsum[w] = inc;
+        __syncthreads();
+        uint32_t lofs = inc - sum;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww)
+            if (ww < w) lofs += wsum[ww];
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            const int d = tid * DPT + k;
+            gbase[d] = run[k] - lofs;
+            run[k] += tot[k];
+            uint32_t o = lofs;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                const uint32_t c = wc[ww][d];
+                wc[ww][d] = o;
+                o += c;
+            }
+            lofs += tot[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < SI; ++k) {
+            const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
+            if (idx < n) {
+                const uint32_t d = (key[k] >> shift) & (R - 1);
+                const uint32_t pos = wc[w][d] + rank[k];
+                s_key[pos] = key[k];
+                s_val[pos] = val[k];
+            }
+        }
+        // the next tile's items load while this one is written out
+        if (t + 1 < sp.tpb && blk + SN < n) load_tile(blk + SN);
+        __syncthreads();
 #pragma unroll 4
-    for (uint32_t i = tid; i < cnt_blk; i += SB) {
-        const uint32_t k = s_key[i];
-        const uint32_t g = gbase[(k >> shift) & (R - 1)] + i;
-        kout[g] = k;
-        vout[g] = s_val[i];
+        for (uint32_t i = tid; i < cnt_blk; i += SB) {
+            const uint32_t k = s_key[i];
+            const uint32_t g = gbase[(k >> shift) & (R - 1)] + i;
+            kout[g] = k;
+            vout[g] = s_val[i];
+        }
     }
 }
 
 template <int BITS>
 hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
-                        int bits, uint32_t* hist, uint32_t* scan_tmp, int* cur, hipStream_t s)
+                        int bits, bool iota_vals, uint32_t* hist, uint32_t* scan_tmp, int* cur,
+                        hipStream_t s)
 {
     constexpr int R = 1 << BITS;
-    const unsigned nb = nblocks(cap);
-    const int64_t hn = (int64_t)R * nb;
+    const unsigned grid = sort_grid(cap);
+    uint32_t* tot = hist + (int64_t)MAX_RADIX * grid;   // digit totals after the counts
     for (int shift = 0; shift < bits; shift += BITS) {
-        hipLaunchKernelGGL((k_radix_hist<BITS>), dim3(nb), dim3(SB), 0, s, keys[*cur], n_dev,
-                           shift, hist, nb);
-        hipError_t e = launch_exclusive_scan(hist, hist, hn, scan_tmp, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_radix_scatter<BITS>), dim3(nb), dim3(SB), 0, s, keys[*cur],
-                           vals[*cur], keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist, nb);
+        hipLaunchKernelGGL((k_radix_hist<BITS>), dim3(grid), dim3(SB), 0, s, keys[*cur], n_dev,
+                           shift, hist);
+        hipLaunchKernelGGL(k_radix_spine, dim3(R), dim3(SB), 0, s, hist, tot, n_dev, grid);
+        const uint32_t* vin = (iota_vals && shift == 0) ? nullptr : vals[*cur];
+        hipLaunchKernelGGL((k_radix_scatter<BITS>), dim3(grid), dim3(SB), 0, s, keys[*cur], vin,
+                           keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist, tot);
         *cur ^= 1;
     }
+    (void)scan_tmp;
     return hipGetLastError();
 }
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
-                      int bits, uint32_t* hist, uint32_t* scan_tmp, int* which, hipStream_t s)
+                      int bits, bool iota_vals, uint32_t* hist, uint32_t* scan_tmp, int* which,
+                      hipStream_t s)
 {
     int cur = 0;
     *which = 0;
     if (cap <= 0 || bits <= 0) return hipSuccess;
     hipError_t e;
     switch (digit_bits(bits)) {
-    case 8: e = radix_passes<8>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
-    case 9: e = radix_passes<9>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
-    default: e = radix_passes<10>(keys, vals, cap, n_dev, bits, hist, scan_tmp, &cur, s); break;
+    case 8:
+        e = radix_passes<8>(keys, vals, cap, n_dev, bits, iota_vals, hist, scan_tmp, &cur, s);
+        break;
+    case 9:
+        e = radix_passes<9>(keys, vals, cap, n_dev, bits, iota_vals, hist, scan_tmp, &cur, s);
+        break;
+    default:
+        e = radix_passes<10>(keys, vals, cap, n_dev, bits, iota_vals, hist, scan_tmp, &cur, s);
+        break;
     }
     *which = cur;
     return e;
@@ -484,7 +605,10 @@ hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, u
     return hipGetLastError();
 }
 
-size_t radix_hist_words(int64_t cap) { return (size_t)MAX_RADIX * nblocks(cap > 0 ? cap : 1); }
+size_t radix_hist_words(int64_t cap)
+{
+    return (size_t)MAX_RADIX * (sort_grid(cap > 0 ? cap : 1) + 1);   // counts, digit totals
+}
 
 int radix_passes_for(int bits)
 {
@@ -494,10 +618,10 @@ int radix_passes_for(int bits)
 }
 
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
-                                 const uint32_t* n_dev, int bits, uint32_t* hist,
+                                 const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  uint32_t* scan_tmp, int* which, hipStream_t s)
 {
-    return radix_sort(keys, vals, cap, n_dev, bits, hist, scan_tmp, which, s);
+    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, scan_tmp, which, s);
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
