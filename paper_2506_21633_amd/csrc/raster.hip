@@ -329,7 +329,10 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     constexpr int NB = 2 * A_BATCH;   // the forward keeps less per chunk in LDS
     __shared__ float4 s_q[NB][WAVE];
     __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
-    __shared__ float s_A[NB][WAVE];
+    // per-entry sums in GC copies picked by ray (as in the backward; one
+    // atomic per hit conflicts little enough that one copy is fastest here)
+    constexpr int GC = 1;
+    __shared__ float s_A[GC][NB][WAVE + 1];
     __shared__ uint64_t s_m[NB][WAVE];
     __shared__ uint32_t s_r[NB][WAVE];
     __shared__ uint32_t s_chk[NB];
@@ -346,7 +349,9 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     const float x0 = (float)(tc.tx * TILE) + 0.5f, y0 = (float)(tc.ty * TILE) + 0.5f;
     const uint2 rg = ranges[bucket];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) s_A[k][lane] = 0.0f;
+    for (int g = 0; g < GC; ++g)
+#pragma unroll
+        for (int k = 0; k < NB; ++k) s_A[g][k][lane] = 0.0f;
     float T = 1.0f, t = 0.0f;
     bool alive = tc.inside;
     uint32_t last = 0;
@@ -359,9 +364,13 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             if (got_prev & (1u << k)) {
-                const float a = s_A[k][lane];
+                float a = 0.0f;
+#pragma unroll
+                for (int g = 0; g < GC; ++g) {
+                    a += s_A[g][k][lane];
+                    s_A[g][k][lane] = 0.0f;
+                }
                 if (a != 0.0f) unsafeAtomicAdd(&A[s_r[k][lane]], a);
-                s_A[k][lane] = 0.0f;
             }
         }
         got_prev = 0u;
@@ -508,7 +517,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                             // for every footprint hit)
                             const float a = fmaxf(
                                 (1.0f - E) * (rp.shadowing ? Tr * __expf(-excl) : 1.0f), FLT_MIN);
-                            atomicAdd(&s_A[k][j], a);
+                            atomicAdd(&s_A[(rr + (rr >> 3)) & (GC - 1)][k][j], a);
                         }
                         const uint64_t hb = __ballot(proc && real);
                         if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
@@ -801,7 +810,11 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     __shared__ float4 s_q[NB][WAVE];
     __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
     __shared__ float s_c[NB][WAVE];                    // c = P dL/dI of the entry
-    __shared__ float s_G[NB][6][WAVE];
+    // per-entry gradient sums in GC copies, picked by ray so that the hits
+    // of one entry from neighbouring rays in a round add to different
+    // addresses (rows padded by one word: copies and rows differ in bank)
+    constexpr int GC = 4;
+    __shared__ float s_G[GC][NB][6][WAVE + 1];
     __shared__ uint64_t s_m[NB][WAVE];
     __shared__ uint32_t s_r[NB][WAVE];
     __shared__ uint32_t s_chk[NB];
@@ -821,9 +834,11 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     float t = tc.inside ? tau[ray] : 0.0f;
     float U = 0.0f;
 #pragma unroll
-    for (int k = 0; k < NB; ++k)
+    for (int g = 0; g < GC; ++g)
 #pragma unroll
-        for (int c = 0; c < 6; ++c) s_G[k][c][lane] = 0.0f;
+        for (int k = 0; k < NB; ++k)
+#pragma unroll
+            for (int c = 0; c < 6; ++c) s_G[g][k][c][lane] = 0.0f;
     unsigned long long n_iter = 0, n_hits = 0;   // work counters
     const uint32_t n_max = wave_max_u32(n_mine);
     const uint32_t e_end = rg.x + n_max;           // exclusive end of the used entries
@@ -837,9 +852,13 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                 const uint32_t rk = s_r[k][lane];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
-                    const float v = s_G[k][c][lane];
+                    float v = 0.0f;
+#pragma unroll
+                    for (int g = 0; g < GC; ++g) {
+                        v += s_G[g][k][c][lane];
+                        s_G[g][k][c][lane] = 0.0f;
+                    }
                     if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + rk], v);
-                    s_G[k][c][lane] = 0.0f;
                 }
             }
         }
@@ -1017,12 +1036,13 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                             }
                             const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
                             const float dq = dxx * g2.y * (-0.5f * ex * rp.inv1meps);
-                            atomicAdd(&s_G[k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
-                            atomicAdd(&s_G[k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
-                            atomicAdd(&s_G[k][2][j], dq * dx * dx);
-                            atomicAdd(&s_G[k][3][j], 2.0f * dq * dx * dy);
-                            atomicAdd(&s_G[k][4][j], dq * dy * dy);
-                            atomicAdd(&s_G[k][5][j], dxx * f);
+                            const int gc = (rr + (rr >> 3)) & (GC - 1);
+                            atomicAdd(&s_G[gc][k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
+                            atomicAdd(&s_G[gc][k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
+                            atomicAdd(&s_G[gc][k][2][j], dq * dx * dx);
+                            atomicAdd(&s_G[gc][k][3][j], 2.0f * dq * dx * dy);
+                            atomicAdd(&s_G[gc][k][4][j], dq * dy * dy);
+                            atomicAdd(&s_G[gc][k][5][j], dxx * f);
                         }
                         const uint64_t hb = __ballot(real);
                         if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
