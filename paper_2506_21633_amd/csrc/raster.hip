@@ -327,6 +327,9 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                float* __restrict__ A, float* __restrict__ tau, uint32_t* __restrict__ nlast)
 {
     constexpr int NB = 2 * A_BATCH;   // the forward keeps less per chunk in LDS
+    constexpr int HKB = NB <= 8 ? 3 : 4;   // bits of a hit's chunk index
+    constexpr int HRS = 6 + HKB;           // shift of a hit's ray index
+    static_assert(NB <= 16, "hits are packed in 16 bits");
     __shared__ float4 s_q[NB][WAVE];
     __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
     // per-entry sums in GC copies picked by ray (as in the backward; one
@@ -334,9 +337,8 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     constexpr int GC = 1;
     __shared__ float s_A[GC][NB][WAVE + 1];
     __shared__ uint64_t s_m[NB][WAVE];
-    __shared__ uint32_t s_r[NB][WAVE];
     __shared__ uint32_t s_chk[NB];
-    __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray << 8 | entry), ray-major
+    __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray, chunk, entry) packed, ray-major
     // per ray during a chunk: first hit in s_hit, optical depth, transmittance,
     // last list position used (one 16-byte read per hit)
     struct alignas(16) RayF { uint32_t o; float t, T; uint32_t last; };
@@ -358,8 +360,10 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     unsigned long long n_iter = 0, n_hits = 0;   // work counters
     uint64_t live = __ballot(alive);
     // per-entry sums of the last processed batch leave with one atomic each;
-    // they are sent while the next batch's loads are in flight
+    // they are sent once the next batch's loads have landed, so the wait for
+    // those loads never waits for the atomics
     uint32_t got_prev = 0u;
+    uint32_t r_prev[NB], r_cur[NB];   // record of my entry in each chunk
     auto flush = [&]() {
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -370,7 +374,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     a += s_A[g][k][lane];
                     s_A[g][k][lane] = 0.0f;
                 }
-                if (a != 0.0f) unsafeAtomicAdd(&A[s_r[k][lane]], a);
+                if (a != 0.0f) unsafeAtomicAdd(&A[r_prev[k]], a);
             }
         }
         got_prev = 0u;
@@ -386,7 +390,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
             {
                 uint32_t chk[NB];
                 uint64_t m[NB];
-                uint32_t r[NB];
+                uint32_t* r = r_cur;
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     chk[k] = 0u;
@@ -403,8 +407,6 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     m[k] = in ? pmask[e] : 0ull;
                     r[k] = in ? pvals[e] : 0u;
                 }
-                // the previous batch's sums leave while these loads are in flight
-                flush();
                 // records straight into LDS, all in flight together (entries
                 // no live ray needs read record 0, one shared line)
 #pragma unroll
@@ -420,13 +422,15 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     s_m[k][lane] = m[k];
-                    s_r[k][lane] = r[k];
                     if (lane == k) s_chk[k] = chk[k];
                 }
             }
-            got_prev = got;
             wait_all_memory();
             wave_lds_sync();
+            flush();
+            got_prev = got;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) r_prev[k] = r_cur[k];
             // the batch's chunks, transposed: bit j of col[k] is entry j of
             // chunk k covering my cell (rays already out of play keep none)
             uint64_t col[NB];
@@ -471,7 +475,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                         while (c != 0ull) {
                             const int j = __builtin_ctzll(c);
                             c &= c - 1ull;
-                            s_hit[w++] = (uint16_t)((lane << 9) | (k << 6) | j);
+                            s_hit[w++] = (uint16_t)((lane << HRS) | (k << 6) | j);
                         }
                     }
                     s_ray[lane] = RayF{o, t, T, last};
@@ -481,7 +485,8 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                         const uint32_t L = base + lane;
                         const bool valid = L < H;
                         const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
-                        const int rr = (int)(hv >> 9), k = (int)((hv >> 6) & 7u), j = (int)(hv & 63u);
+                        const int rr = (int)(hv >> HRS), k = (int)((hv >> 6) & ((1u << HKB) - 1u)),
+                                  j = (int)(hv & 63u);
                         // ray state and entry record, read together (lanes past
                         // the last hit read entry 0 of ray 0 and ignore it)
                         const RayF rs = s_ray[rr];
@@ -522,9 +527,8 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                         const uint64_t hb = __ballot(proc && real);
                         if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
                         // the last processed hit of each ray in this round updates the ray
-                        const int nxt = from_lane_above((int)(proc ? hv : 0xFFFFu));
-                        const bool endseg =
-                            proc && (lane == WAVE - 1 || (nxt >> 9) != rr || nxt == 0xFFFF);
+                        const int nxt = from_lane_above(proc ? (int)hv : -1);
+                        const bool endseg = proc && (lane == WAVE - 1 || (nxt >> HRS) != rr);
                         wave_lds_sync();
                         if (endseg)
                             s_ray[rr] = RayF{rs.o, tr + incl, rp.shadowing ? Tr * __expf(-incl) : Tr,
@@ -807,6 +811,9 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                float* __restrict__ grad_c, int64_t stride)
 {
     constexpr int NB = A_BATCH;
+    constexpr int HKB = NB <= 8 ? 3 : 4;   // bits of a hit's chunk index
+    constexpr int HRS = 6 + HKB;           // shift of a hit's ray index
+    static_assert(NB <= 16, "hits are packed in 16 bits");
     __shared__ float4 s_q[NB][WAVE];
     __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
     __shared__ float s_c[NB][WAVE];                    // c = P dL/dI of the entry
@@ -816,9 +823,8 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     constexpr int GC = 4;
     __shared__ float s_G[GC][NB][6][WAVE + 1];
     __shared__ uint64_t s_m[NB][WAVE];
-    __shared__ uint32_t s_r[NB][WAVE];
     __shared__ uint32_t s_chk[NB];
-    __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray << 8 | entry), ray-major, back to front
+    __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray, chunk, entry) packed, ray-major, back to front
     // per ray during a chunk: first hit in s_hit, optical depth, U
     struct alignas(16) RayB { uint32_t o; float t, U, pad; };
     __shared__ RayB s_ray[WAVE];
@@ -843,13 +849,15 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     const uint32_t n_max = wave_max_u32(n_mine);
     const uint32_t e_end = rg.x + n_max;           // exclusive end of the used entries
     // the six per-entry sums of the last processed batch leave with atomics;
-    // they are sent while the next batch's loads are in flight
+    // they are sent once the next batch's loads have landed, so the wait for
+    // those loads never waits for the atomics
     uint32_t got_prev = 0u;
+    uint32_t r_prev[NB], r_cur[NB];   // record of my entry in each chunk
     auto flush = [&]() {
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
             if (got_prev & (1u << k)) {
-                const uint32_t rk = s_r[k][lane];
+                const uint32_t rk = r_prev[k];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
                     float v = 0.0f;
@@ -883,7 +891,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                 uint32_t chk[NB];
                 uint64_t lv[NB];
                 uint64_t m[NB];
-                uint32_t r[NB];
+                uint32_t* r = r_cur;
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     chk[k] = 0u;
@@ -907,8 +915,6 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                     m[k] = in ? pmask[e] : 0ull;
                     r[k] = in ? pvals[e] : 0u;
                 }
-                // the previous batch's sums leave while these loads are in flight
-                flush();
                 // records straight into LDS, all in flight together (entries
                 // no ray needs read record 0 of the view, one shared line)
 #pragma unroll
@@ -925,13 +931,15 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     s_m[k][lane] = m[k];
-                    s_r[k][lane] = r[k];
                     if (lane == k) s_chk[k] = chk[k];
                 }
             }
-            got_prev = got;
             wait_all_memory();
             wave_lds_sync();
+            flush();
+            got_prev = got;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) r_prev[k] = r_cur[k];
             // the batch's chunks, transposed: bit j of col[k] is entry j of
             // chunk k covering my cell that my ray used in the forward
             uint64_t col[NB];
@@ -981,7 +989,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                         while (c != 0ull) {
                             const int j = 63 - __builtin_clzll(c);
                             c &= ~(1ull << j);
-                            s_hit[w++] = (uint16_t)((lane << 9) | (k << 6) | j);
+                            s_hit[w++] = (uint16_t)((lane << HRS) | (k << 6) | j);
                         }
                     }
                     s_ray[lane] = RayB{o, t, U, 0.0f};
@@ -991,7 +999,8 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                         const uint32_t L = base + lane;
                         const bool valid = L < H;
                         const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
-                        const int rr = (int)(hv >> 9), k = (int)((hv >> 6) & 7u), j = (int)(hv & 63u);
+                        const int rr = (int)(hv >> HRS), k = (int)((hv >> 6) & ((1u << HKB) - 1u)),
+                                  j = (int)(hv & 63u);
                         // ray state and entry record, read together (lanes past
                         // the last hit read entry 0 of ray 0 and ignore it)
                         const RayB rs = s_ray[rr];
@@ -1046,9 +1055,8 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                         }
                         const uint64_t hb = __ballot(real);
                         if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
-                        const int nxt = from_lane_above((int)(valid ? hv : 0xFFFFu));
-                        const bool endseg =
-                            valid && (lane == WAVE - 1 || (nxt >> 9) != rr || nxt == 0xFFFF);
+                        const int nxt = from_lane_above(valid ? (int)hv : -1);
+                        const bool endseg = valid && (lane == WAVE - 1 || (nxt >> HRS) != rr);
                         wave_lds_sync();
                         if (endseg && rp.shadowing) s_ray[rr] = RayB{rs.o, tr - sx, sa * Ur + sb, 0.0f};
                         wave_lds_sync();
