@@ -810,7 +810,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                const uint32_t* __restrict__ nlast, const float* __restrict__ cbwd,
                float* __restrict__ grad_c, int64_t stride)
 {
-    constexpr int NB = A_BATCH;
+    constexpr int NB = 2 * A_BATCH;
     constexpr int HKB = NB <= 8 ? 3 : 4;   // bits of a hit's chunk index
     constexpr int HRS = 6 + HKB;           // shift of a hit's ray index
     static_assert(NB <= 16, "hits are packed in 16 bits");
@@ -820,7 +820,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     // per-entry gradient sums in GC copies, picked by ray so that the hits
     // of one entry from neighbouring rays in a round add to different
     // addresses (rows padded by one word: copies and rows differ in bank)
-    constexpr int GC = 4;
+    constexpr int GC = 2;
     __shared__ float s_G[GC][NB][6][WAVE + 1];
     __shared__ uint64_t s_m[NB][WAVE];
     __shared__ uint32_t s_chk[NB];
