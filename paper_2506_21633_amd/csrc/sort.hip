@@ -4,18 +4,19 @@
 // coordinate serves as the sorting depth).
 //
 //   1. records of all views are sorted by (fl32 depth, index) with a stable
-//      LSD radix sort of 32-bit keys (index order is the initial order);
-//      the views stay interleaved, which step 3 undoes;
-//   2. their pair counts are scanned in that order and every record emits
-//      (tile bucket, record) pairs -- computation-plane pairs in depth order,
-//      imaging-plane pairs in index order;
+//      LSD radix sort of 32-bit keys (index order is the initial order, the
+//      first pass generates the indices); the views stay interleaved;
+//   2. their computation-plane pair counts are scanned in that order and
+//      every record emits (tile bucket, record) pairs in depth order;
 //   3. a stable LSD radix sort of the pairs on the bucket id yields, per
-//      tile, the Gaussians in depth order (computation plane) or in index
-//      order (imaging plane, where the order only fixes the FP32 summation
-//      order);
-//   4. tile ranges [start, end) are read off the sorted bucket ids.
+//      tile, the Gaussians in depth order;
+//   4. tile ranges [start, end) are read off the sorted bucket ids;
+//   5. after pass A, records with a nonzero intensity emit their
+//      imaging-plane pairs in index order (after the computation-plane
+//      ones) and the same sort groups them by tile, the order only fixing
+//      the FP32 summation order of pass B.
 //
-// All kernels work on 4096-element blocks (256 threads x 16 items).
+// Sort blocks work on runs of 4096-element tiles (256 threads x 16 items).
 #include "common.hpp"
 
 #include <algorithm>
