@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="vehicle_200k", choices=WORKLOADS)
-    ap.add_argument("--cpu-rows", type=int, default=32,
+    ap.add_argument("--cpu-rows", type=int, default=64,
                     help="range rows of one view the CPU oracle baseline times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",

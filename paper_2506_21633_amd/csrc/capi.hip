@@ -253,7 +253,6 @@ struct Bufs {
     // transient: projection counts and sort buffers
     uint2* rect_c = nullptr;
     uint2* rect_i = nullptr;
-    uint32_t* cnt_c = nullptr;
     uint32_t* cnt_i = nullptr;
     uint32_t* cnt_c_sorted = nullptr;
     uint2* rect_c_sorted = nullptr;
@@ -315,7 +314,6 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
     auto transient = [&](Arena& a) {
         b.rect_c = a.take<uint2>(R);
         b.rect_i = a.take<uint2>(R);
-        b.cnt_c = a.take<uint32_t>(R);
         b.cnt_i = a.take<uint32_t>(R);
         b.cnt_c_sorted = a.take<uint32_t>(R);
         b.rect_c_sorted = a.take<uint2>(R);
@@ -372,7 +370,6 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
 // The depth sort orders all records by depth alone: the views need not be
 // separated, since the stable bucket sort of the pairs groups them by tile
 // (and so by view) afterwards and keeps the depth order within each tile.
-int passes_bits_depth(const Problem&) { return 32; }
 // Computation-plane buckets are [0, tiles_c); imaging-plane buckets follow.
 int bits_pairs_c(const Problem& P) { return bits_for(P.tiles_c - 1); }
 int bits_pairs_i(const Problem& P) { return bits_for(P.tiles_c + P.tiles_i - 1); }
@@ -390,7 +387,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     {
         StageTimer t(SG_PREPROCESS, s);
         SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, R, P.rp, true, b.cq, b.cw, b.iq,
-                                   b.iw, b.rect_c, b.rect_i, b.cnt_c, b.cnt_i, b.dkey[0],
+                                   b.iw, b.rect_c, b.rect_i, b.dkey[0],
                                    b.slots,
                                    reinterpret_cast<unsigned long long*>(b.status + ST_COUNT),
                                    s));
@@ -401,8 +398,8 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     int which = 0;
     {
         StageTimer t(SG_DEPTH_SORT, s);
-        SDGR_HIP(launch_radix_sort_u32(dk, dv, R, b.status + ST_RECORDS, passes_bits_depth(P),
-                                       true, b.hist, b.scan_tmp, &which, s));
+        SDGR_HIP(launch_radix_sort_u32(dk, dv, R, b.status + ST_RECORDS, 32, true, b.hist,
+                                       b.scan_tmp, &which, s));
     }
     uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};
@@ -509,8 +506,8 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
     {
         StageTimer t(SG_QUERY, s);
         SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.records, P.rp, false, nullptr,
-                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   nullptr, nullptr, slots, totals, s));
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, slots,
+                                   totals, s));
     }
     unsigned long long host_tot[2] = {0, 0};
     SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));

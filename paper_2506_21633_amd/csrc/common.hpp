@@ -188,8 +188,7 @@ constexpr int TOTAL_SLOTS = 1024;
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
                              int64_t records, const RasterParams& rp,
                              bool write_records, float4* cq, float2* cw, float4* iq,
-                             float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* cnt_c,
-                             uint32_t* cnt_i, uint32_t* dkey,
+                             float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* dkey,
                              unsigned long long* slots, unsigned long long* totals,
                              hipStream_t s);
 

@@ -165,9 +165,8 @@ __global__ void __launch_bounds__(256)
 k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
              int64_t records, RasterParams rp, int write_records, float4* __restrict__ cq,
              float2* __restrict__ cw, float4* __restrict__ iq, float2* __restrict__ iw,
-             uint2* __restrict__ rect_c, uint2* __restrict__ rect_i,
-             uint32_t* __restrict__ cnt_c, uint32_t* __restrict__ cnt_i,
-             uint32_t* __restrict__ dkey, unsigned long long* __restrict__ totals)
+             uint2* __restrict__ rect_c, uint2* __restrict__ rect_i, uint32_t* __restrict__ dkey,
+             unsigned long long* __restrict__ totals)
 {
     __shared__ unsigned long long part[2];
     if (threadIdx.x < 2) part[threadIdx.x] = 0;
@@ -236,8 +235,6 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
             iw[r] = vi_w;
             rect_c[r] = rc;
             rect_i[r] = ri;
-            cnt_c[r] = nc;
-            cnt_i[r] = ni;
             dkey[r] = float_order_bits(__uint_as_float(zbits));
         }
     }
@@ -415,7 +412,7 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int n)
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
                              int64_t records, const RasterParams& rp, bool write_records,
                              float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
-                             uint2* rect_i, uint32_t* cnt_c, uint32_t* cnt_i, uint32_t* dkey,
+                             uint2* rect_i, uint32_t* dkey,
                              unsigned long long* slots,
                              unsigned long long* totals, hipStream_t s)
 {
@@ -424,7 +421,7 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
     if (records > 0)
         hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
                            scenes, nv, records, rp, write_records ? 1 : 0, cq, cw, iq, iw,
-                           rect_c, rect_i, cnt_c, cnt_i, dkey, slots);
+                           rect_c, rect_i, dkey, slots);
     hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(TOTAL_SLOTS), 0, s, slots, totals);
     return hipGetLastError();
 }
