@@ -604,15 +604,28 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64
     float acc = 0.0f, px = 0.0f, py = 0.0f;
     int64_t pix = -1;
     unsigned long long n_iter = 0, n_hits = 0;   // work counters
+    // software pipeline over the 64-entry steps: the records of step s + 1
+    // and the keys and record ids of step s + 2 load while step s runs
+    const uint32_t e0 = (uint32_t)p0 + lane;
+    uint32_t key_n = e0 < p1 ? pkey[e0] : 0xFFFFFFFFu;
+    uint32_t r_n = e0 < p1 ? pvals[e0] : 0u;
+    float4 g_n = iq[r_n];
+    float2 g2_n = iw[r_n];
+    uint32_t key_nn = e0 + WAVE < p1 ? pkey[e0 + WAVE] : 0xFFFFFFFFu;
+    uint32_t r_nn = e0 + WAVE < p1 ? pvals[e0 + WAVE] : 0u;
     for (uint32_t b0 = (uint32_t)p0; b0 < p1; b0 += WAVE) {
         const uint32_t e = b0 + lane;
         const bool in = e < p1;
-        const uint32_t key = in ? pkey[e] : 0xFFFFFFFFu;
+        const uint32_t key = key_n;
+        const float4 g = g_n;
+        const float2 g2 = g2_n;
+        key_n = key_nn;
+        g_n = iq[r_nn];
+        g2_n = iw[r_nn];
+        key_nn = e + 2 * WAVE < p1 ? pkey[e + 2 * WAVE] : 0xFFFFFFFFu;
+        r_nn = e + 2 * WAVE < p1 ? pvals[e + 2 * WAVE] : 0u;
         uint64_t m = 0ull;
         if (in) {
-            const uint32_t r = pvals[e];
-            const float4 g = iq[r];
-            const float2 g2 = iw[r];
             s_q[w][lane] = g;
             s_w[w][lane] = g2;
             const int v = find_view(nv, (int64_t)key,
