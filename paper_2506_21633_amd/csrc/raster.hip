@@ -812,8 +812,9 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
 // (lane = hit, hits of a ray back to front) the optical depth is a
 // segmented prefix sum and U a segmented prefix composition of the affine
 // maps U -> (1 - alpha) U + c alpha. The six per-entry gradient sums collect
-// in LDS and leave with one global atomic each per (tile, entry).
-__global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
+// in LDS and leave with one global atomic each per (tile, entry), sent by a
+// second wave of the workgroup so the first never waits on them.
+__global__ void __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                RasterParams rp, const uint32_t* __restrict__ status,
                const uint32_t* __restrict__ worklist, const uint2* __restrict__ ranges,
@@ -833,16 +834,45 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     // per-entry gradient sums in GC copies, picked by ray so that the hits
     // of one entry from neighbouring rays in a round add to different
     // addresses (rows padded by one word: copies and rows differ in bank)
-    constexpr int GC = 2;
-    __shared__ float s_G[GC][NB][6][WAVE + 1];
-    __shared__ uint64_t s_m[NB][WAVE];
+    constexpr int GC = 1;
+    // two buffers: the second wave of the workgroup sends one batch's sums
+    // with atomics while the first accumulates the next batch in the other
+    __shared__ float s_G[2][GC][NB][6][WAVE + 1];
+    __shared__ uint32_t s_rf[2][NB][WAVE];   // records of the handed-off entries
+    __shared__ uint32_t s_cmd[2][WAVE];      // per entry lane: chunks gathered (bits), last flag
     __shared__ uint32_t s_chk[NB];
     __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray, chunk, entry) packed, ray-major, back to front
     // per ray during a chunk: first hit in s_hit, optical depth, U
     struct alignas(16) RayB { uint32_t o; float t, U, pad; };
     __shared__ RayB s_ray[WAVE];
-    const int lane = threadIdx.x;
     if (blockIdx.x >= status[ST_WORK_TILES]) return;
+    constexpr uint32_t LAST = 1u << 31;
+    if (threadIdx.x >= WAVE) {
+        // the flusher: per hand-off, the six sums of every handed-off entry
+        // leave with one atomic each, and the buffer is cleared for reuse
+        const int fl = threadIdx.x - WAVE;
+        for (int hb = 0;; hb ^= 1) {
+            __syncthreads();
+            const uint32_t cmd = s_cmd[hb][fl];
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                if (!(cmd & (1u << k))) continue;
+                const uint32_t rk = s_rf[hb][k][fl];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    float v = 0.0f;
+#pragma unroll
+                    for (int g = 0; g < GC; ++g) {
+                        v += s_G[hb][g][k][c][fl];
+                        s_G[hb][g][k][c][fl] = 0.0f;
+                    }
+                    if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + rk], v);
+                }
+            }
+            if (cmd & LAST) return;
+        }
+    }
+    const int lane = threadIdx.x;
     const int64_t bucket = worklist[blockIdx.x];
     const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
@@ -853,36 +883,28 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     float t = tc.inside ? tau[ray] : 0.0f;
     float U = 0.0f;
 #pragma unroll
-    for (int g = 0; g < GC; ++g)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
+        for (int g = 0; g < GC; ++g)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) s_G[g][k][c][lane] = 0.0f;
+            for (int k = 0; k < NB; ++k)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) s_G[b][g][k][c][lane] = 0.0f;
     unsigned long long n_iter = 0, n_hits = 0;   // work counters
     const uint32_t n_max = wave_max_u32(n_mine);
     const uint32_t e_end = rg.x + n_max;           // exclusive end of the used entries
-    // the six per-entry sums of the last processed batch leave with atomics;
-    // they are sent once the next batch's loads have landed, so the wait for
-    // those loads never waits for the atomics
+    // the six per-entry sums of the last processed batch go to the flusher
+    // wave once the next batch's loads have landed; the barrier also returns
+    // the buffer the flusher emptied last
     uint32_t got_prev = 0u;
     uint32_t r_prev[NB], r_cur[NB];   // record of my entry in each chunk
-    auto flush = [&]() {
+    int hb = 0;                        // buffer the current batch accumulates in
+    auto flush = [&](bool last) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            if (got_prev & (1u << k)) {
-                const uint32_t rk = r_prev[k];
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    float v = 0.0f;
-#pragma unroll
-                    for (int g = 0; g < GC; ++g) {
-                        v += s_G[g][k][c][lane];
-                        s_G[g][k][c][lane] = 0.0f;
-                    }
-                    if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + rk], v);
-                }
-            }
-        }
+        for (int k = 0; k < NB; ++k) s_rf[hb][k][lane] = r_prev[k];
+        s_cmd[hb][lane] = got_prev | (last ? LAST : 0u);
+        __syncthreads();
+        hb ^= 1;
         got_prev = 0u;
     };
     const int64_t c_first = rg.x / WAVE, c_end = (int64_t)(e_end + WAVE - 1) / WAVE;
@@ -900,10 +922,10 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
         while (todo != 0ull) {
             uint32_t got = 0u;
             int nb = 0;
+            uint64_t m[NB];   // lane = entry: the cells it covers
             {
                 uint32_t chk[NB];
                 uint64_t lv[NB];
-                uint64_t m[NB];
                 uint32_t* r = r_cur;
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
@@ -942,14 +964,12 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                     load4_to_lds(cbwd + rk, &s_c[k][0]);
                 }
 #pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    s_m[k][lane] = m[k];
+                for (int k = 0; k < NB; ++k)
                     if (lane == k) s_chk[k] = chk[k];
-                }
             }
             wait_all_memory();
             wave_lds_sync();
-            flush();
+            flush(false);
             got_prev = got;
 #pragma unroll
             for (int k = 0; k < NB; ++k) r_prev[k] = r_cur[k];
@@ -965,7 +985,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                     const int64_t nu = (int64_t)n_mine - pos0;   // used: positions < n_mine
                     const uint64_t used =
                         nu >= WAVE ? ~0ull : (nu <= 0 ? 0ull : ((1ull << nu) - 1ull));
-                    col[k] = transpose64(s_m[k][lane]) & used;
+                    col[k] = transpose64(m[k]) & used;
                 }
                 hk[k] = (uint32_t)__builtin_amdgcn_readlane(
                     (int)(wave_excl_scan_u32((uint32_t)__popcll(col[k])) + (uint32_t)__popcll(col[k])),
@@ -1059,12 +1079,12 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                             const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
                             const float dq = dxx * g2.y * (-0.5f * ex * rp.inv1meps);
                             const int gc = (rr + (rr >> 3)) & (GC - 1);
-                            atomicAdd(&s_G[gc][k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
-                            atomicAdd(&s_G[gc][k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
-                            atomicAdd(&s_G[gc][k][2][j], dq * dx * dx);
-                            atomicAdd(&s_G[gc][k][3][j], 2.0f * dq * dx * dy);
-                            atomicAdd(&s_G[gc][k][4][j], dq * dy * dy);
-                            atomicAdd(&s_G[gc][k][5][j], dxx * f);
+                            atomicAdd(&s_G[hb][gc][k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
+                            atomicAdd(&s_G[hb][gc][k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
+                            atomicAdd(&s_G[hb][gc][k][2][j], dq * dx * dx);
+                            atomicAdd(&s_G[hb][gc][k][3][j], 2.0f * dq * dx * dy);
+                            atomicAdd(&s_G[hb][gc][k][4][j], dq * dy * dy);
+                            atomicAdd(&s_G[hb][gc][k][5][j], dxx * f);
                         }
                         const uint64_t hb = __ballot(real);
                         if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
@@ -1086,7 +1106,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
             wave_lds_sync();
         }
     }
-    flush();
+    flush(true);
     if (rp.work) {
         n_hits = wave_sum_u64(n_hits);
         if (lane == 0) {
@@ -1215,7 +1235,7 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                float* grad_c, int64_t stride, hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_a_bwd, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views, nv, rp,
+    hipLaunchKernelGGL(k_raster_a_bwd, dim3((unsigned)tiles_c), dim3(2 * WAVE), 0, s, views, nv, rp,
                        status, worklist, ranges, pvals, pmask, psum, cq, cw, tau, nlast, cbwd,
                        grad_c, stride);
     return hipGetLastError();
