@@ -834,7 +834,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     // per-entry gradient sums in GC copies, picked by ray so that the hits
     // of one entry from neighbouring rays in a round add to different
     // addresses (rows padded by one word: copies and rows differ in bank)
-    constexpr int GC = 1;
+    constexpr int GC = 2;
     // two buffers: the second wave of the workgroup sends one batch's sums
     // with atomics while the first accumulates the next batch in the other
     __shared__ float s_G[2][GC][NB][6][WAVE + 1];
