@@ -34,7 +34,7 @@
 namespace sdgr {
 namespace {
 
-constexpr uint32_t B_SEGMENT = 2048;   // pair entries per pass-B forward wave
+constexpr uint32_t B_SEGMENT = 128;    // pair entries per pass-B forward wave
 
 __device__ __forceinline__ void wave_lds_sync()
 {
