@@ -382,7 +382,10 @@ int final_buffer_i(const Problem& P) { return radix_passes_for(bits_pairs_i(P)) 
 int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStream_t s)
 {
     const int64_t R = P.records;
-    SDGR_HIP(launch_fill_u32(b.status, 0u, STATUS_WORDS, s));
+    // list-building words only: the work counters and the imaging-plane pair
+    // count of the forward survive a recomputing backward
+    SDGR_HIP(launch_fill_u32(b.status, 0u, ST_PAIRS_I, s));
+    SDGR_HIP(launch_fill_u32(b.status + ST_PAIRS_I + 1, 0u, WORK_WORD - ST_PAIRS_I - 1, s));
     SDGR_HIP(launch_fill_u32(b.status + ST_RECORDS, (uint32_t)R, 1, s));
     {
         StageTimer t(SG_PREPROCESS, s);
@@ -576,6 +579,8 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
            nullptr);
     if (g_count_work) P.rp.work = reinterpret_cast<unsigned long long*>(b.status + WORK_WORD);
     if ((rc = upload_tables(P, b, s))) return rc;
+    SDGR_HIP(launch_fill_u32(b.status + ST_PAIRS_I, 0u, 1, s));
+    SDGR_HIP(launch_fill_u32(b.status + WORK_WORD, 0u, STATUS_WORDS - WORK_WORD, s));
     if ((rc = build_lists_c(P, plan, b, s))) return rc;
     const int pw = final_buffer_c(P);
     SDGR_HIP(launch_fill_u32((uint32_t*)b.A, 0u, P.records, s));
