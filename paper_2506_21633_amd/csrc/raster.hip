@@ -1127,6 +1127,7 @@ k_tile_worklist(const uint2* __restrict__ ranges, int64_t tiles_c, uint32_t* __r
     const int tid = threadIdx.x;
     if (tid < 33) cnt[tid] = 0;
     __syncthreads();
+#pragma unroll 8
     for (int64_t t = tid; t < tiles_c; t += blockDim.x) {
         const uint2 rg = ranges[t];
         const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;
@@ -1142,6 +1143,7 @@ k_tile_worklist(const uint2* __restrict__ ranges, int64_t tiles_c, uint32_t* __r
         status[ST_WORK_TILES] = acc;
     }
     __syncthreads();
+#pragma unroll 8
     for (int64_t t = tid; t < tiles_c; t += blockDim.x) {
         const uint2 rg = ranges[t];
         const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;

@@ -537,17 +537,34 @@ k_emit_i(const DevView* __restrict__ views, int nv, int64_t records,
             }
 }
 
+// Tile ranges from the sorted bucket ids, four keys per thread (one 16-byte
+// load when the four are in range) and the neighbours of the first and last.
 __global__ void __launch_bounds__(256)
 k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int64_t buckets,
          uint2* __restrict__ ranges)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t p0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     const int64_t n = *n_dev;
-    if (p >= n) return;
-    const uint32_t k = keys[p];
-    if (k >= buckets) return;
-    if (p == 0 || keys[p - 1] != k) ranges[k].x = (uint32_t)p;
-    if (p == n - 1 || keys[p + 1] != k) ranges[k].y = (uint32_t)(p + 1);
+    if (p0 >= n) return;
+    uint32_t k[4];
+    if (p0 + 4 <= n) {
+        const uint4 q = *reinterpret_cast<const uint4*>(keys + p0);
+        k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) k[i] = p0 + i < n ? keys[p0 + i] : 0xFFFFFFFFu;
+    }
+    const uint32_t before = p0 > 0 ? keys[p0 - 1] : 0xFFFFFFFFu;
+    const uint32_t after = p0 + 4 < n ? keys[p0 + 4] : 0xFFFFFFFFu;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t p = p0 + i;
+        if (p >= n || k[i] >= buckets) continue;
+        const uint32_t prev = i == 0 ? before : k[i - 1];
+        const uint32_t next = i == 3 ? after : k[i + 1];
+        if (p == 0 || prev != k[i]) ranges[k[i]].x = (uint32_t)p;
+        if (p == n - 1 || next != k[i]) ranges[k[i]].y = (uint32_t)(p + 1);
+    }
 }
 
 inline unsigned grid256(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -683,8 +700,8 @@ hipError_t launch_tile_ranges(const uint32_t* keys, int64_t cap, const uint32_t*
 {
     hipError_t e = launch_fill_u32((uint32_t*)ranges, 0u, 2 * buckets, s);
     if (e != hipSuccess || cap <= 0) return e;
-    hipLaunchKernelGGL(k_ranges, dim3(grid256(cap)), dim3(256), 0, s, keys, n_dev, buckets,
-                       ranges);
+    hipLaunchKernelGGL(k_ranges, dim3(grid256((cap + 3) / 4)), dim3(256), 0, s, keys, n_dev,
+                       buckets, ranges);
     return hipGetLastError();
 }
 
