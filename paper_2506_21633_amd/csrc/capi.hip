@@ -254,10 +254,9 @@ struct Bufs {
     uint2* rect_c = nullptr;
     uint2* rect_i = nullptr;
     uint32_t* cnt_i = nullptr;
-    uint32_t* cnt_c_sorted = nullptr;
     uint2* rect_c_sorted = nullptr;
-    uint32_t* off_c = nullptr;
-    uint32_t* off_i = nullptr;
+    uint32_t* bsum_c = nullptr;     // pair counts per 256 records, then their scan
+    uint32_t* bsum_i = nullptr;
     uint32_t* dkey[2] = {nullptr, nullptr};
     uint32_t* dval[2] = {nullptr, nullptr};
     uint32_t* pkey[2] = {nullptr, nullptr};
@@ -315,10 +314,9 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.rect_c = a.take<uint2>(R);
         b.rect_i = a.take<uint2>(R);
         b.cnt_i = a.take<uint32_t>(R);
-        b.cnt_c_sorted = a.take<uint32_t>(R);
         b.rect_c_sorted = a.take<uint2>(R);
-        b.off_c = a.take<uint32_t>(R);
-        b.off_i = a.take<uint32_t>(R);
+        b.bsum_c = a.take<uint32_t>(R / 256 + 1);
+        b.bsum_i = a.take<uint32_t>(R / 256 + 1);
         b.dkey[0] = a.take<uint32_t>(R);
         b.dkey[1] = a.take<uint32_t>(R);
         b.dval[0] = a.take<uint32_t>(R);
@@ -408,10 +406,10 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};
     {
         StageTimer t(SG_BIN, s);
-        SDGR_HIP(launch_gather_rects(dv[which], b.rect_c, R, b.rect_c_sorted, b.cnt_c_sorted, s));
-        SDGR_HIP(launch_exclusive_scan(b.cnt_c_sorted, b.off_c, R, b.scan_tmp, s));
+        SDGR_HIP(launch_gather_rects(dv[which], b.rect_c, R, b.rect_c_sorted, b.bsum_c, s));
+        SDGR_HIP(launch_scan_blocks(b.bsum_c, (R + 255) / 256, plan->pairs_c, b.status, -1, s));
         SDGR_HIP(launch_pair_total_c(plan->pairs_c, b.status, s));
-        SDGR_HIP(launch_emit_pairs_c(b.views, P.nv, R, dv[which], b.rect_c_sorted, b.off_c,
+        SDGR_HIP(launch_emit_pairs_c(b.views, P.nv, R, dv[which], b.rect_c_sorted, b.bsum_c,
                                      plan->pairs_c, b.status, pk[0], pv[0], s));
     }
     int pw = 0;
@@ -441,9 +439,9 @@ int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     uint32_t* pv[2] = {b.pval[0] + plan->pairs_c, b.pval[1] + plan->pairs_c};
     {
         StageTimer t(SG_BIN_I, s);
-        SDGR_HIP(launch_exclusive_scan(b.cnt_i, b.off_i, R, b.scan_tmp, s));
-        SDGR_HIP(launch_pair_total_i(b.off_i, b.cnt_i, R, plan->pairs_i, b.status, s));
-        SDGR_HIP(launch_emit_pairs_i(b.views, P.nv, R, b.rect_i, b.cnt_i, b.off_i, plan->pairs_c,
+        SDGR_HIP(launch_scan_blocks(b.bsum_i, (R + 255) / 256, plan->pairs_i, b.status, ST_PAIRS_I,
+                                    s));
+        SDGR_HIP(launch_emit_pairs_i(b.views, P.nv, R, b.rect_i, b.cnt_i, b.bsum_i, plan->pairs_c,
                                      plan->pairs_i, b.status, b.pkey[0], b.pval[0], s));
     }
     int pw = 0;
@@ -595,7 +593,7 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     {
         StageTimer t(SG_INTENSITY, s);
         SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, b.rect_i,
-                                      b.cnt_i, s));
+                                      b.cnt_i, b.bsum_i, s));
     }
     if ((rc = build_lists_i(P, plan, b, s))) return rc;
     const int pwi = final_buffer_i(P);
@@ -641,7 +639,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         // are deterministic) and refill the intensities from the kept A
         if ((rc = build_lists_c(P, plan, b, s))) return rc;
         SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, nullptr,
-                                      nullptr, s));
+                                      nullptr, nullptr, s));
     }
     const int pw = final_buffer_c(P);
     {

@@ -143,6 +143,29 @@ __device__ __forceinline__ float quadform(float4 g, float c, float dx, float dy)
     return g.z * dx * dx + 2.0f * g.w * dx * dy + c * dy * dy;
 }
 
+// Exclusive prefix of one value per thread over a 256-thread block, and the
+// block total (s_w: four LDS words; every thread of the block must call).
+__device__ inline uint32_t block_excl_scan_256(uint32_t v, uint32_t* s_w, uint32_t& total)
+{
+    const int lane = lane_id(), w = (int)threadIdx.x / WAVE;
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t t = __shfl_up(inc, d, WAVE);
+        if (lane >= d) inc += t;
+    }
+    if (lane == WAVE - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t off = 0u;
+    total = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k < w) off += s_w[k];
+        total += s_w[k];
+    }
+    return off + inc - v;
+}
+
 // Cells of tile (tx, ty) inside the ellipse q < q_max of a Gaussian with
 // centre (cx, cy) and conic (a, b, c): per row the column span from the
 // quadratic, widened by a slack that covers the rounding of the hardware
@@ -194,7 +217,8 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
 
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
                                 int64_t records, const float* A, float2* iw,
-                                const uint2* rect_i, uint32_t* cnt_i, hipStream_t s);
+                                const uint2* rect_i, uint32_t* cnt_i, uint32_t* bsum_i,
+                                hipStream_t s);
 
 // Per-record gradient buffers are plane-major: component k of record r at
 // [k * records + r]; grad_c = (dcx, dcy, da, db, dc, dkappa) on the
@@ -222,19 +246,24 @@ hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t c
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  uint32_t* scan_tmp, int* which, hipStream_t s);
 
+// Tile rectangles of the records in depth order, and the computation-plane
+// pair count of every 256 of them (bsum).
 hipError_t launch_gather_rects(const uint32_t* order, const uint2* rect, int64_t n,
-                               uint2* rect_sorted, uint32_t* cnt_sorted, hipStream_t s);
+                               uint2* rect_sorted, uint32_t* bsum, hipStream_t s);
+// Exclusive scan in place of n per-block counts (one workgroup); with
+// status_slot >= 0 the total goes to status[status_slot], flagged against
+// cap as an overflow.
+hipError_t launch_scan_blocks(uint32_t* bsum, int64_t n, int64_t cap, uint32_t* status,
+                              int status_slot, hipStream_t s);
 // overflow check and actual pair counts from the projection's u64 totals
 hipError_t launch_pair_total_c(int64_t cap_c, uint32_t* status, hipStream_t s);
-hipError_t launch_pair_total_i(const uint32_t* off_i, const uint32_t* cnt_i, int64_t records,
-                               int64_t cap_i, uint32_t* status, hipStream_t s);
 hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
                                const uint32_t* dval_sorted, const uint2* rect_sorted,
-                               const uint32_t* off_c, int64_t cap_c, const uint32_t* status,
+                               const uint32_t* bscan_c, int64_t cap_c, const uint32_t* status,
                                uint32_t* pkey, uint32_t* pval, hipStream_t s);
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
                                const uint2* rect_i, const uint32_t* cnt_i,
-                               const uint32_t* off_i, int64_t cap_c, int64_t cap_i,
+                               const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i,
                                const uint32_t* status, uint32_t* pkey, uint32_t* pval,
                                hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, int64_t cap, const uint32_t* n_dev,

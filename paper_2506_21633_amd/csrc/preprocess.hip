@@ -271,23 +271,34 @@ k_sum_slots(const unsigned long long* __restrict__ slots, unsigned long long* __
 // I = P A into the imaging record (incident intensity 1, Sec. II-A); with
 // rect_i given, also the imaging-plane pair count of the record: the tiles
 // of its rectangle if I is nonzero, none otherwise (a zero intensity adds
-// nothing to any pixel).
+// nothing to any pixel), and their sum over each block of 256 records.
 __global__ void __launch_bounds__(256)
 k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
                 int64_t records, const float* __restrict__ A, float2* __restrict__ iw,
-                const uint2* __restrict__ rect_i, uint32_t* __restrict__ cnt_i)
+                const uint2* __restrict__ rect_i, uint32_t* __restrict__ cnt_i,
+                uint32_t* __restrict__ bsum_i)
 {
+    __shared__ uint32_t s_w[4];
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= records) return;
-    int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
-    const DevView& V = views[v];
-    const float p = scenes[V.scene].amp[r - V.rec_off];
-    const float I = p * A[r];
-    iw[r].y = I;
-    if (cnt_i) {
-        const uint2 ri = rect_i[r];
-        const uint32_t area = ((ri.x >> 16) - (ri.x & 0xFFFF)) * ((ri.y >> 16) - (ri.y & 0xFFFF));
-        cnt_i[r] = I != 0.0f ? area : 0u;
+    uint32_t cnt = 0u;
+    if (r < records) {
+        int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
+        const DevView& V = views[v];
+        const float p = scenes[V.scene].amp[r - V.rec_off];
+        const float I = p * A[r];
+        iw[r].y = I;
+        if (cnt_i) {
+            const uint2 ri = rect_i[r];
+            const uint32_t area =
+                ((ri.x >> 16) - (ri.x & 0xFFFF)) * ((ri.y >> 16) - (ri.y & 0xFFFF));
+            cnt = I != 0.0f ? area : 0u;
+            cnt_i[r] = cnt;
+        }
+    }
+    if (cnt_i) {   // the block's imaging-plane pair count (the emission scans within)
+        uint32_t tot;
+        (void)block_excl_scan_256(cnt, s_w, tot);
+        if (threadIdx.x == 0) bsum_i[blockIdx.x] = tot;
     }
 }
 
@@ -427,12 +438,13 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
 }
 
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
-                                int64_t records, const float* A, float2* iw, const uint2* rect_i,
-                                uint32_t* cnt_i, hipStream_t s)
+                                int64_t records, const float* A, float2* iw,
+                                const uint2* rect_i, uint32_t* cnt_i, uint32_t* bsum_i,
+                                hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_set_intensity, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
-                       scenes, nv, records, A, iw, rect_i, cnt_i);
+                       scenes, nv, records, A, iw, rect_i, cnt_i, bsum_i);
     return hipGetLastError();
 }
 

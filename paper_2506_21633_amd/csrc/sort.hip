@@ -420,16 +420,77 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
     return e;
 }
 
-// Tile rectangles of the records in depth order, and their pair counts.
+// Tile rectangles of the records in depth order, and the computation-plane
+// pair count of each block of 256 (the emission scans within the block).
 __global__ void __launch_bounds__(256)
 k_gather_rects(const uint32_t* __restrict__ order, const uint2* __restrict__ rect, int64_t n,
-               uint2* __restrict__ rect_sorted, uint32_t* __restrict__ cnt_sorted)
+               uint2* __restrict__ rect_sorted, uint32_t* __restrict__ bsum)
 {
+    __shared__ uint32_t s_w[4];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const uint2 rc = rect[order[i]];
-    rect_sorted[i] = rc;
-    cnt_sorted[i] = ((rc.x >> 16) - (rc.x & 0xFFFF)) * ((rc.y >> 16) - (rc.y & 0xFFFF));
+    uint32_t c = 0u;
+    if (i < n) {
+        const uint2 rc = rect[order[i]];
+        rect_sorted[i] = rc;
+        c = ((rc.x >> 16) - (rc.x & 0xFFFF)) * ((rc.y >> 16) - (rc.y & 0xFFFF));
+    }
+    uint32_t tot;
+    (void)block_excl_scan_256(c, s_w, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Exclusive scan in place of the per-block counts, one workgroup walking
+// them 16384 at a time with a running carry; the total optionally becomes a
+// pair count in status (0 and the overflow flag when above the capacity).
+__global__ void __launch_bounds__(1024)
+k_scan_blocks(uint32_t* __restrict__ a, int64_t n, int64_t cap, uint32_t* __restrict__ status,
+              int slot)
+{
+    constexpr int ITEMS = 16, NT = 1024, NWV = NT / WAVE;
+    __shared__ uint32_t s_w[NWV];
+    __shared__ unsigned long long s_carry;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    if (tid == 0) s_carry = 0ull;
+    __syncthreads();
+    for (int64_t base = 0; base < n; base += (int64_t)NT * ITEMS) {
+        uint32_t v[ITEMS], sum = 0u;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int64_t idx = base + (int64_t)tid * ITEMS + k;
+            v[k] = idx < n ? a[idx] : 0u;
+            sum += v[k];
+        }
+        uint32_t inc = sum;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const uint32_t t = __shfl_up(inc, d, WAVE);
+            if (lane >= d) inc += t;
+        }
+        if (lane == WAVE - 1) s_w[w] = inc;
+        __syncthreads();
+        uint32_t off = 0u, total = 0u;
+#pragma unroll
+        for (int k = 0; k < NWV; ++k) {
+            if (k < w) off += s_w[k];
+            total += s_w[k];
+        }
+        uint32_t run = (uint32_t)s_carry + off + inc - sum;
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int64_t idx = base + (int64_t)tid * ITEMS + k;
+            if (idx < n) a[idx] = run;
+            run += v[k];
+        }
+        __syncthreads();   // everyone has read s_carry and s_w
+        if (tid == 0) s_carry += total;
+        __syncthreads();
+    }
+    if (tid == 0 && slot >= 0) {
+        const unsigned long long tot = s_carry;
+        const bool over = tot > (unsigned long long)cap;
+        status[ST_OVERFLOW] |= over ? 1u : 0u;
+        status[slot] = over ? 0u : (uint32_t)tot;
+    }
 }
 
 // status[ST_PAIRS_C] from the u64 total of the projection (status + 8);
@@ -443,17 +504,6 @@ __global__ void k_pair_total_c(int64_t cap_c, uint32_t* status)
     status[ST_PAIRS_C] = over ? 0u : (uint32_t)kc;
 }
 
-// status[ST_PAIRS_I] from the exclusive scan of the imaging-plane counts
-// (total = last offset + last count); flags overflow against the capacity.
-__global__ void k_pair_total_i(const uint32_t* __restrict__ off, const uint32_t* __restrict__ cnt,
-                               int64_t n, int64_t cap_i, uint32_t* status)
-{
-    const unsigned long long ki =
-        n > 0 ? (unsigned long long)off[n - 1] + (unsigned long long)cnt[n - 1] : 0ull;
-    const bool over = ki > (unsigned long long)cap_i;
-    status[ST_OVERFLOW] |= over ? 1u : 0u;
-    status[ST_PAIRS_I] = over ? 0u : (uint32_t)ki;
-}
 
 // View of a record through a copy of the view offsets in LDS (records in
 // depth order come from all views at random).
@@ -465,9 +515,10 @@ constexpr int LDS_VIEWS = 512;
 __global__ void __launch_bounds__(256)
 k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
          const uint32_t* __restrict__ dval, const uint2* __restrict__ rect_sorted,
-         const uint32_t* __restrict__ off_c, int64_t cap_c, const uint32_t* __restrict__ status,
+         const uint32_t* __restrict__ bscan, int64_t cap_c, const uint32_t* __restrict__ status,
          uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval)
 {
+    __shared__ uint32_t s_w[4];
     __shared__ int64_t s_off[LDS_VIEWS];
     __shared__ int32_t s_tile[LDS_VIEWS], s_tx[LDS_VIEWS];
     const bool cached = nv <= LDS_VIEWS;
@@ -479,11 +530,14 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
         }
     __syncthreads();
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint2 rc = p < records ? rect_sorted[p] : make_uint2(0u, 0u);
+    const uint32_t tx0 = rc.x & 0xFFFF, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
+    // offset: the block's prefix plus the counts of the block's records before
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan_256((tx1 - tx0) * (ty1 - ty0), s_w, tot);
     if (p >= records) return;
     const uint32_t kc = status[ST_PAIRS_C];
     if (status[ST_OVERFLOW]) return;
-    const uint2 rc = rect_sorted[p];
-    const uint32_t tx0 = rc.x & 0xFFFF, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
     if (tx0 >= tx1 || ty0 >= ty1) return;
     const uint32_t r = dval[p];
     uint32_t tile0, txc;
@@ -500,7 +554,7 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
         tile0 = (uint32_t)views[v].tile_c;
         txc = (uint32_t)views[v].txc;
     }
-    uint64_t o = off_c[p];
+    uint64_t o = (uint64_t)bscan[blockIdx.x] + ex;
     for (uint32_t ty = ty0; ty < ty1; ++ty)
         for (uint32_t tx = tx0; tx < tx1; ++tx, ++o)
             if (o < kc && o < (uint64_t)cap_c) {
@@ -515,20 +569,25 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
 __global__ void __launch_bounds__(256)
 k_emit_i(const DevView* __restrict__ views, int nv, int64_t records,
          const uint2* __restrict__ rect_i, const uint32_t* __restrict__ cnt_i,
-         const uint32_t* __restrict__ off_i, int64_t cap_c, int64_t cap_i,
+         const uint32_t* __restrict__ bscan, int64_t cap_c, int64_t cap_i,
          const uint32_t* __restrict__ status, uint32_t* __restrict__ pkey,
          uint32_t* __restrict__ pval)
 {
+    __shared__ uint32_t s_w[4];
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t cnt = p < records ? cnt_i[p] : 0u;
+    // offset: the block's prefix plus the counts of the block's records before
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan_256(cnt, s_w, tot);
     if (p >= records) return;
     const uint32_t ki = status[ST_PAIRS_I];
     if (status[ST_OVERFLOW]) return;
+    if (cnt == 0u) return;
     const int v = find_view(nv, p, [&](int k) { return views[k].rec_off; });
-    if (cnt_i[p] == 0u) return;
     const DevView& V = views[v];
     const uint2 ri = rect_i[p];
     const uint32_t tx0 = ri.x & 0xFFFF, tx1 = ri.x >> 16, ty0 = ri.y & 0xFFFF, ty1 = ri.y >> 16;
-    uint64_t o = off_i[p];
+    uint64_t o = (uint64_t)bscan[blockIdx.x] + ex;
     for (uint32_t ty = ty0; ty < ty1; ++ty)
         for (uint32_t tx = tx0; tx < tx1; ++tx, ++o)
             if (o < ki && o < (uint64_t)cap_i) {
@@ -650,11 +709,19 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
 }
 
 hipError_t launch_gather_rects(const uint32_t* order, const uint2* rect, int64_t n,
-                               uint2* rect_sorted, uint32_t* cnt_sorted, hipStream_t s)
+                               uint2* rect_sorted, uint32_t* bsum, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_rects, dim3(grid256(n)), dim3(256), 0, s, order, rect, n,
-                       rect_sorted, cnt_sorted);
+                       rect_sorted, bsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_blocks(uint32_t* bsum, int64_t n, int64_t cap, uint32_t* status,
+                              int status_slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, s, bsum, n, cap, status,
+                       status_slot);
     return hipGetLastError();
 }
 
@@ -664,34 +731,26 @@ hipError_t launch_pair_total_c(int64_t cap_c, uint32_t* status, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_pair_total_i(const uint32_t* off_i, const uint32_t* cnt_i, int64_t records,
-                               int64_t cap_i, uint32_t* status, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_pair_total_i, dim3(1), dim3(1), 0, s, off_i, cnt_i, records, cap_i,
-                       status);
-    return hipGetLastError();
-}
-
 hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
                                const uint32_t* dval_sorted, const uint2* rect_sorted,
-                               const uint32_t* off_c, int64_t cap_c, const uint32_t* status,
+                               const uint32_t* bscan_c, int64_t cap_c, const uint32_t* status,
                                uint32_t* pkey, uint32_t* pval, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit_c, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
-                       dval_sorted, rect_sorted, off_c, cap_c, status, pkey, pval);
+                       dval_sorted, rect_sorted, bscan_c, cap_c, status, pkey, pval);
     return hipGetLastError();
 }
 
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
                                const uint2* rect_i, const uint32_t* cnt_i,
-                               const uint32_t* off_i, int64_t cap_c, int64_t cap_i,
+                               const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i,
                                const uint32_t* status, uint32_t* pkey, uint32_t* pval,
                                hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit_i, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
-                       rect_i, cnt_i, off_i, cap_c, cap_i, status, pkey, pval);
+                       rect_i, cnt_i, bscan_i, cap_c, cap_i, status, pkey, pval);
     return hipGetLastError();
 }
 
