@@ -261,7 +261,6 @@ struct Bufs {
     uint32_t* dval[2] = {nullptr, nullptr};
     uint32_t* pkey[2] = {nullptr, nullptr};
     uint32_t* hist = nullptr;
-    uint32_t* scan_tmp = nullptr;
     unsigned long long* slots = nullptr;   // spread pair-total accumulators
     // backward accumulators: 13 floats and one list slot per record
     float* grad_c = nullptr;
@@ -325,8 +324,6 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.pkey[1] = a.take<uint32_t>(K);
         int64_t hw = (int64_t)std::max(radix_hist_words(R), radix_hist_words(K));
         b.hist = a.take<uint32_t>(hw);
-        int64_t sw = (int64_t)std::max(scan_tmp_words(R), scan_tmp_words(hw));
-        b.scan_tmp = a.take<uint32_t>(sw);
         b.slots = a.take<unsigned long long>(2 * TOTAL_SLOTS);
     };
     if (!P.recompute) geo(st);
@@ -400,7 +397,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     {
         StageTimer t(SG_DEPTH_SORT, s);
         SDGR_HIP(launch_radix_sort_u32(dk, dv, R, b.status + ST_RECORDS, 32, true, b.hist,
-                                       b.scan_tmp, &which, s));
+                                       &which, s));
     }
     uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};
@@ -416,7 +413,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     {
         StageTimer t(SG_PAIR_SORT, s);
         SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_c, b.status + ST_PAIRS_C,
-                                       bits_pairs_c(P), false, b.hist, b.scan_tmp, &pw, s));
+                                       bits_pairs_c(P), false, b.hist, &pw, s));
     }
     if (plan->pairs_c > 0 && pw != final_buffer_c(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
@@ -447,7 +444,7 @@ int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     int pw = 0;
     StageTimer t(SG_PAIR_SORT_I, s);
     SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_i, b.status + ST_PAIRS_I, bits_pairs_i(P),
-                                   false, b.hist, b.scan_tmp, &pw, s));
+                                   false, b.hist, &pw, s));
     if (plan->pairs_i > 0 && pw != final_buffer_i(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
     return SDGR_OK;

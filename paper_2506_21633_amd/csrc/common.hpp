@@ -229,11 +229,6 @@ hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, 
                                   const float* grad_c, const float* grad_i,
                                   int64_t records, hipStream_t s);
 
-// exclusive scan of n uint32 (n <= 2^31); tmp must hold scan_tmp_words(n)
-size_t scan_tmp_words(int64_t n);
-hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n,
-                                 uint32_t* tmp, hipStream_t s);
-
 // stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
 // n_dev points at the device-side element count (<= cap). Buffers [0] hold
 // the input; returns in *which the index of the buffer holding the output.
@@ -244,7 +239,7 @@ int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
 // 0..n-1 and vals[0] is not read. *which: the buffer holding the result.
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
-                                 uint32_t* scan_tmp, int* which, hipStream_t s);
+                                 int* which, hipStream_t s);
 
 // Tile rectangles of the records in depth order, and the computation-plane
 // pair count of every 256 of them (bsum).

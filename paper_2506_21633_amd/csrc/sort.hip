@@ -38,64 +38,6 @@ __global__ void __launch_bounds__(256) k_fill(uint32_t* p, uint32_t v, int64_t n
     if (i < n) p[i] = v;
 }
 
-// Exclusive scan of one 4096-element block; the block total goes to sums.
-__global__ void __launch_bounds__(SB)
-k_scan_block(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* sums)
-{
-    __shared__ uint32_t buf[SN + SN / 32];   // padded: index k -> k + k/32
-    __shared__ uint32_t wtot[SB / WAVE];
-    const int tid = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * SN;
-    auto pad = [](int k) { return k + (k >> 5); };
-#pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        int64_t idx = base + k * SB + tid;
-        buf[pad(k * SB + tid)] = idx < n ? in[idx] : 0u;
-    }
-    __syncthreads();
-    uint32_t v[SI];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        v[k] = buf[pad(tid * SI + k)];
-        sum += v[k];
-    }
-    // inclusive wave scan of the per-thread sums
-    const int lane = tid & (WAVE - 1), w = tid / WAVE;
-    uint32_t inc = sum;
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        uint32_t t = __shfl_up(inc, d, WAVE);
-        if (lane >= d) inc += t;
-    }
-    if (lane == WAVE - 1) wtot[w] = inc;
-    __syncthreads();
-    uint32_t woff = 0, total = 0;
-#pragma unroll
-    for (int k = 0; k < SB / WAVE; ++k) {
-        if (k < w) woff += wtot[k];
-        total += wtot[k];
-    }
-    uint32_t run = woff + inc - sum;
-#pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        buf[pad(tid * SI + k)] = run;
-        run += v[k];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < SI; ++k) {
-        int64_t idx = base + k * SB + tid;
-        if (idx < n) out[idx] = buf[pad(k * SB + tid)];
-    }
-    if (tid == 0) sums[blockIdx.x] = total;
-}
-
-__global__ void __launch_bounds__(256) k_scan_add(uint32_t* out, int64_t n, const uint32_t* sums)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] += sums[i / SN];
-}
 
 // Digit width of a sort: the fewest passes of at most 10 bits, then the
 // narrowest digit (8 to 10 bits) that covers the key in that many passes.
@@ -378,8 +320,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
 
 template <int BITS>
 hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
-                        int bits, bool iota_vals, uint32_t* hist, uint32_t* scan_tmp, int* cur,
-                        hipStream_t s)
+                        int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s)
 {
     constexpr int R = 1 << BITS;
     const unsigned grid = sort_grid(cap);
@@ -393,13 +334,11 @@ hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const
                            keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist, tot);
         *cur ^= 1;
     }
-    (void)scan_tmp;
     return hipGetLastError();
 }
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
-                      int bits, bool iota_vals, uint32_t* hist, uint32_t* scan_tmp, int* which,
-                      hipStream_t s)
+                      int bits, bool iota_vals, uint32_t* hist, int* which, hipStream_t s)
 {
     int cur = 0;
     *which = 0;
@@ -407,13 +346,13 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
     hipError_t e;
     switch (digit_bits(bits)) {
     case 8:
-        e = radix_passes<8>(keys, vals, cap, n_dev, bits, iota_vals, hist, scan_tmp, &cur, s);
+        e = radix_passes<8>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s);
         break;
     case 9:
-        e = radix_passes<9>(keys, vals, cap, n_dev, bits, iota_vals, hist, scan_tmp, &cur, s);
+        e = radix_passes<9>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s);
         break;
     default:
-        e = radix_passes<10>(keys, vals, cap, n_dev, bits, iota_vals, hist, scan_tmp, &cur, s);
+        e = radix_passes<10>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s);
         break;
     }
     *which = cur;
@@ -656,31 +595,7 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
     return hipGetLastError();
 }
 
-size_t scan_tmp_words(int64_t n)
-{
-    size_t words = 0;
-    while (n > 1) {
-        int64_t nb = (n + SN - 1) / SN;
-        words += (size_t)((nb + 63) / 64 * 64);
-        n = nb;
-    }
-    return words + 64;
-}
 
-hipError_t launch_exclusive_scan(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* tmp,
-                                 hipStream_t s)
-{
-    if (n <= 0) return hipSuccess;
-    const int64_t nb = (n + SN - 1) / SN;
-    hipLaunchKernelGGL(k_scan_block, dim3((unsigned)nb), dim3(SB), 0, s, in, out, n, tmp);
-    if (nb > 1) {
-        uint32_t* next = tmp + (nb + 63) / 64 * 64;
-        hipError_t e = launch_exclusive_scan(tmp, tmp, nb, next, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_scan_add, dim3(grid256(n)), dim3(256), 0, s, out, n, tmp);
-    }
-    return hipGetLastError();
-}
 
 size_t radix_hist_words(int64_t cap)
 {
@@ -696,9 +611,9 @@ int radix_passes_for(int bits)
 
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
-                                 uint32_t* scan_tmp, int* which, hipStream_t s)
+                                 int* which, hipStream_t s)
 {
-    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, scan_tmp, which, s);
+    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s);
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
