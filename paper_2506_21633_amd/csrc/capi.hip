@@ -113,6 +113,8 @@ struct Problem {
     int64_t records = 0, rays = 0, tiles_c = 0, tiles_i = 0, items = 0, pixels = 0;
     int64_t image_floats = 0;
     bool recompute = false;
+    bool ikey_vm = false;   // imaging keys (tile within the view << 8) | view
+    int ikey_bits = 0;      // bits of the tile within a view
 };
 
 // Rows of the world-to-radar rotation R_r(phi, theta) (Sec. II-A).
@@ -227,6 +229,11 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     P.rays = rays;
     P.tiles_c = tc;
     P.tiles_i = ti;
+    int64_t max_ti = 1;
+    for (int v = 0; v < nv; ++v)
+        max_ti = std::max<int64_t>(max_ti, (int64_t)P.views[v].txi * P.views[v].tyi);
+    P.ikey_bits = bits_for(max_ti - 1);
+    P.ikey_vm = nv <= IKEY_VIEWS && P.ikey_bits <= 24;
     P.image_floats = img;
     P.pixels = pix;
     return SDGR_OK;
@@ -367,7 +374,10 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
 // (and so by view) afterwards and keeps the depth order within each tile.
 // Computation-plane buckets are [0, tiles_c); imaging-plane buckets follow.
 int bits_pairs_c(const Problem& P) { return bits_for(P.tiles_c - 1); }
-int bits_pairs_i(const Problem& P) { return bits_for(P.tiles_c + P.tiles_i - 1); }
+int bits_pairs_i(const Problem& P)
+{
+    return P.ikey_vm ? P.ikey_bits : bits_for(P.tiles_c + P.tiles_i - 1);
+}
 int final_buffer_c(const Problem& P) { return radix_passes_for(bits_pairs_c(P)) & 1; }
 int final_buffer_i(const Problem& P) { return radix_passes_for(bits_pairs_i(P)) & 1; }
 
@@ -439,12 +449,12 @@ int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
         SDGR_HIP(launch_scan_blocks(b.bsum_i, (R + 255) / 256, plan->pairs_i, b.status, ST_PAIRS_I,
                                     s));
         SDGR_HIP(launch_emit_pairs_i(b.views, P.nv, R, b.rect_i, b.cnt_i, b.bsum_i, plan->pairs_c,
-                                     plan->pairs_i, b.status, b.pkey[0], b.pval[0], s));
+                                     plan->pairs_i, P.ikey_vm, b.status, b.pkey[0], b.pval[0], s));
     }
     int pw = 0;
     StageTimer t(SG_PAIR_SORT_I, s);
     SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_i, b.status + ST_PAIRS_I, bits_pairs_i(P),
-                                   false, b.hist, &pw, s));
+                                   false, b.hist, &pw, s, P.ikey_vm ? 8 : 0));
     if (plan->pairs_i > 0 && pw != final_buffer_i(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
     return SDGR_OK;
@@ -596,7 +606,7 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     const int pwi = final_buffer_i(P);
     StageTimer t(SG_RASTER_B_FWD, s);
     SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.pixels, plan->pairs_c, plan->pairs_i, P.rp,
-                                 b.status, b.pkey[pwi], b.pval[pwi], b.iq, b.iw, images, s));
+                                 b.status, b.pkey[pwi], b.pval[pwi], b.iq, b.iw, images, P.ikey_vm, s));
     return SDGR_OK;
 }
 

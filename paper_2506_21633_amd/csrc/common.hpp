@@ -143,6 +143,17 @@ __device__ __forceinline__ float quadform(float4 g, float c, float dx, float dy)
     return g.z * dx * dx + 2.0f * g.w * dx * dy + c * dy * dy;
 }
 
+// Imaging-plane bucket keys. With at most IKEY_VIEWS views a key is
+// (tile within the view << 8) | view: pairs are emitted view by view, so a
+// stable sort on the tile bits alone groups every (view, tile); otherwise
+// the key is the global bucket id (views' imaging tiles after all
+// computation-plane ones).
+constexpr int IKEY_VIEWS = 256;
+__device__ __forceinline__ uint32_t ikey_encode(bool vm, int v, uint32_t tile_i, uint32_t local)
+{
+    return vm ? ((local << 8) | (uint32_t)v) : tile_i + local;
+}
+
 // Exclusive prefix of one value per thread over a 256-thread block, and the
 // block total (s_w: four LDS words; every thread of the block must call).
 __device__ inline uint32_t block_excl_scan_256(uint32_t v, uint32_t* s_w, uint32_t& total)
@@ -239,7 +250,7 @@ int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
 // 0..n-1 and vals[0] is not read. *which: the buffer holding the result.
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
-                                 int* which, hipStream_t s);
+                                 int* which, hipStream_t s, int shift0 = 0);
 
 // Tile rectangles of the records in depth order, and the computation-plane
 // pair count of every 256 of them (bsum).
@@ -258,7 +269,7 @@ hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
                                uint32_t* pkey, uint32_t* pval, hipStream_t s);
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
                                const uint2* rect_i, const uint32_t* cnt_i,
-                               const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i,
+                               const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i, bool vm,
                                const uint32_t* status, uint32_t* pkey, uint32_t* pval,
                                hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, int64_t cap, const uint32_t* n_dev,
@@ -281,7 +292,7 @@ hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
 hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_c,
                                int64_t cap_i, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
-                               const float2* iw, float* images, hipStream_t s);
+                               const float2* iw, float* images, bool vm, hipStream_t s);
 hipError_t launch_active_records(int64_t records, const float* A, uint32_t* status,
                                  uint32_t* active, float* grad_c, hipStream_t s);
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,

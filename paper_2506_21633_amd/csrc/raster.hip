@@ -271,6 +271,24 @@ __device__ __forceinline__ TileCell tile_cell(const DevView* views, int nv, int6
     return t;
 }
 
+// Tile coordinates and this lane's pixel of an imaging-plane key (view-major
+// when vm, else a global bucket id).
+__device__ __forceinline__ TileCell tile_cell_i(const DevView* views, int nv, uint32_t key, bool vm)
+{
+    if (!vm) return tile_cell(views, nv, (int64_t)key, false);
+    TileCell t;
+    t.v = (int)(key & 0xFFu);
+    const DevView& V = views[t.v];
+    const uint32_t local = key >> 8;
+    t.tx = (int)(local % (uint32_t)V.txi);
+    t.ty = (int)(local / (uint32_t)V.txi);
+    const int lane = lane_id();
+    t.col = t.tx * TILE + (lane & (TILE - 1));
+    t.row = t.ty * TILE + (lane / TILE);
+    t.inside = t.col < V.W && t.row < V.H;
+    return t;
+}
+
 // Footprint mask of every computation-plane pair (bit 8 * row + col for
 // the tile cells inside the ellipse q < q_max), and per 64-pair chunk of
 // the sorted array (aligned to the array, so a chunk may span two tiles)
@@ -587,7 +605,7 @@ __global__ void __launch_bounds__(RASTER_THREADS)
 k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64_t cap_c,
                const uint32_t* __restrict__ status, const uint32_t* __restrict__ pkey,
                const uint32_t* __restrict__ pvals, const float4* __restrict__ iq,
-               const float2* __restrict__ iw, float* __restrict__ images)
+               const float2* __restrict__ iw, float* __restrict__ images, int vm)
 {
     __shared__ float4 s_q[RASTER_WAVES][WAVE];
     __shared__ float2 s_w[RASTER_WAVES][WAVE];
@@ -628,12 +646,9 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64
         if (in) {
             s_q[w][lane] = g;
             s_w[w][lane] = g2;
-            const int v = find_view(nv, (int64_t)key,
-                                    [&](int k) { return (int64_t)views[k].tile_i; });
-            const int local = (int)(key - (uint32_t)views[v].tile_i);
-            const int txi = views[v].txi;
+            const TileCell tk = tile_cell_i(views, nv, key, vm != 0);
             if (g2.y != 0.0f)   // zero intensity adds nothing
-                m = footprint_mask(g.x, g.y, g.z, g.w, g2.x, rp.q_max, local % txi, local / txi);
+                m = footprint_mask(g.x, g.y, g.z, g.w, g2.x, rp.q_max, tk.tx, tk.ty);
         }
         wave_lds_sync();
         uint64_t rest = __ballot(in);
@@ -645,7 +660,7 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64
             rest &= ~sel;
             if (k != cur) {   // tile change: flush the partial sums
                 if (pix >= 0 && acc != 0.0f) unsafeAtomicAdd(&images[pix], acc);
-                const TileCell tc = tile_cell(views, nv, (int64_t)k, false);
+                const TileCell tc = tile_cell_i(views, nv, k, vm != 0);
                 const DevView& V = views[tc.v];
                 px = tc.col + 0.5f;
                 py = tc.row + 0.5f;
@@ -1195,7 +1210,7 @@ hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
 hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_c,
                                int64_t cap_i, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
-                               const float2* iw, float* images, hipStream_t s)
+                               const float2* iw, float* images, bool vm, hipStream_t s)
 {
     if (pixels <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_images, dim3(grid256(pixels)), dim3(256), 0, s, views, nv, pixels,
@@ -1203,7 +1218,7 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
     if (cap_i <= 0) return hipGetLastError();
     const int64_t segs = (cap_i + B_SEGMENT - 1) / B_SEGMENT;
     hipLaunchKernelGGL(k_raster_b_fwd, dim3(raster_grid(segs)), dim3(RASTER_THREADS), 0, s, views,
-                       nv, rp, cap_c, status, pkey, pvals, iq, iw, images);
+                       nv, rp, cap_c, status, pkey, pvals, iq, iw, images, vm ? 1 : 0);
     return hipGetLastError();
 }
 

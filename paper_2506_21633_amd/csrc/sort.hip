@@ -320,16 +320,17 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
 
 template <int BITS>
 hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
-                        int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s)
+                        int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
+                        int shift0)
 {
     constexpr int R = 1 << BITS;
     const unsigned grid = sort_grid(cap);
     uint32_t* tot = hist + (int64_t)MAX_RADIX * grid;   // digit totals after the counts
-    for (int shift = 0; shift < bits; shift += BITS) {
+    for (int shift = shift0; shift < shift0 + bits; shift += BITS) {
         hipLaunchKernelGGL((k_radix_hist<BITS>), dim3(grid), dim3(SB), 0, s, keys[*cur], n_dev,
                            shift, hist);
         hipLaunchKernelGGL(k_radix_spine, dim3(R), dim3(SB), 0, s, hist, tot, n_dev, grid);
-        const uint32_t* vin = (iota_vals && shift == 0) ? nullptr : vals[*cur];
+        const uint32_t* vin = (iota_vals && shift == shift0) ? nullptr : vals[*cur];
         hipLaunchKernelGGL((k_radix_scatter<BITS>), dim3(grid), dim3(SB), 0, s, keys[*cur], vin,
                            keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist, tot);
         *cur ^= 1;
@@ -338,7 +339,8 @@ hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const
 }
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
-                      int bits, bool iota_vals, uint32_t* hist, int* which, hipStream_t s)
+                      int bits, bool iota_vals, uint32_t* hist, int* which, hipStream_t s,
+                      int shift0)
 {
     int cur = 0;
     *which = 0;
@@ -346,13 +348,13 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
     hipError_t e;
     switch (digit_bits(bits)) {
     case 8:
-        e = radix_passes<8>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s);
+        e = radix_passes<8>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0);
         break;
     case 9:
-        e = radix_passes<9>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s);
+        e = radix_passes<9>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0);
         break;
     default:
-        e = radix_passes<10>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s);
+        e = radix_passes<10>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0);
         break;
     }
     *which = cur;
@@ -508,7 +510,7 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
 __global__ void __launch_bounds__(256)
 k_emit_i(const DevView* __restrict__ views, int nv, int64_t records,
          const uint2* __restrict__ rect_i, const uint32_t* __restrict__ cnt_i,
-         const uint32_t* __restrict__ bscan, int64_t cap_c, int64_t cap_i,
+         const uint32_t* __restrict__ bscan, int64_t cap_c, int64_t cap_i, int vm,
          const uint32_t* __restrict__ status, uint32_t* __restrict__ pkey,
          uint32_t* __restrict__ pval)
 {
@@ -530,7 +532,7 @@ k_emit_i(const DevView* __restrict__ views, int nv, int64_t records,
     for (uint32_t ty = ty0; ty < ty1; ++ty)
         for (uint32_t tx = tx0; tx < tx1; ++tx, ++o)
             if (o < ki && o < (uint64_t)cap_i) {
-                pkey[cap_c + o] = (uint32_t)V.tile_i + ty * (uint32_t)V.txi + tx;
+                pkey[cap_c + o] = ikey_encode(vm != 0, v, (uint32_t)V.tile_i, ty * (uint32_t)V.txi + tx);
                 pval[cap_c + o] = (uint32_t)p;
             }
 }
@@ -611,9 +613,9 @@ int radix_passes_for(int bits)
 
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
-                                 int* which, hipStream_t s)
+                                 int* which, hipStream_t s, int shift0)
 {
-    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s);
+    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s, shift0);
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
@@ -659,13 +661,13 @@ hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
 
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
                                const uint2* rect_i, const uint32_t* cnt_i,
-                               const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i,
+                               const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i, bool vm,
                                const uint32_t* status, uint32_t* pkey, uint32_t* pval,
                                hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_emit_i, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
-                       rect_i, cnt_i, bscan_i, cap_c, cap_i, status, pkey, pval);
+                       rect_i, cnt_i, bscan_i, cap_c, cap_i, vm ? 1 : 0, status, pkey, pval);
     return hipGetLastError();
 }
 
