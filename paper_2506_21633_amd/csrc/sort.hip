@@ -381,24 +381,32 @@ k_gather_rects(const uint32_t* __restrict__ order, const uint2* __restrict__ rec
 }
 
 // Exclusive scan in place of the per-block counts, one workgroup walking
-// them 16384 at a time with a running carry; the total optionally becomes a
-// pair count in status (0 and the overflow flag when above the capacity).
+// them 8192 at a time with a running carry (coalesced loads and stores
+// through LDS, each thread scanning 8 consecutive counts); the total
+// optionally becomes a pair count in status (0 and the overflow flag when
+// above the capacity).
 __global__ void __launch_bounds__(1024)
 k_scan_blocks(uint32_t* __restrict__ a, int64_t n, int64_t cap, uint32_t* __restrict__ status,
               int slot)
 {
-    constexpr int ITEMS = 16, NT = 1024, NWV = NT / WAVE;
+    constexpr int ITEMS = 8, NT = 1024, NWV = NT / WAVE, CH = NT * ITEMS;
+    __shared__ uint32_t s_v[CH + CH / 32];   // padded: index k -> k + k / 32
     __shared__ uint32_t s_w[NWV];
     __shared__ unsigned long long s_carry;
+    auto pad = [](int k) { return k + (k >> 5); };
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     if (tid == 0) s_carry = 0ull;
-    __syncthreads();
-    for (int64_t base = 0; base < n; base += (int64_t)NT * ITEMS) {
+    for (int64_t base = 0; base < n; base += CH) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int64_t idx = base + k * NT + tid;
+            s_v[pad(k * NT + tid)] = idx < n ? a[idx] : 0u;
+        }
+        __syncthreads();
         uint32_t v[ITEMS], sum = 0u;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const int64_t idx = base + (int64_t)tid * ITEMS + k;
-            v[k] = idx < n ? a[idx] : 0u;
+            v[k] = s_v[pad(tid * ITEMS + k)];
             sum += v[k];
         }
         uint32_t inc = sum;
@@ -418,11 +426,15 @@ k_scan_blocks(uint32_t* __restrict__ a, int64_t n, int64_t cap, uint32_t* __rest
         uint32_t run = (uint32_t)s_carry + off + inc - sum;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
-            const int64_t idx = base + (int64_t)tid * ITEMS + k;
-            if (idx < n) a[idx] = run;
+            s_v[pad(tid * ITEMS + k)] = run;
             run += v[k];
         }
-        __syncthreads();   // everyone has read s_carry and s_w
+        __syncthreads();   // everyone has read s_carry and s_w; s_v holds the prefixes
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) {
+            const int64_t idx = base + k * NT + tid;
+            if (idx < n) a[idx] = s_v[pad(k * NT + tid)];
+        }
         if (tid == 0) s_carry += total;
         __syncthreads();
     }
