@@ -290,8 +290,9 @@ struct Arena {
 };
 
 enum Phase { FWD, BWD };
-constexpr int STATUS_WORDS = 64;
+constexpr int STATUS_WORDS = 64 + 66;   // status words, then the worklist bins
 constexpr int ST_RECORDS = 12;   // device copy of the record count (sort length)
+constexpr int WL_BINS = 64;      // 66 words of worklist bins after the status words
 
 void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* state,
             char* scratch, Bufs& b, size_t* state_bytes, size_t* scratch_bytes)
@@ -432,7 +433,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
                                 b.ranges, s));
     SDGR_HIP(launch_pair_masks(b.views, P.nv, plan->pairs_c, P.rp, b.status, pk[pw], pv[pw],
                                b.cq, b.cw, b.pmask, b.psum, s));
-    SDGR_HIP(launch_tile_worklist(b.ranges, P.tiles_c, b.worklist, b.status, s));
+    SDGR_HIP(launch_tile_worklist(b.ranges, P.tiles_c, b.worklist, b.status + WL_BINS, b.status, s));
     return SDGR_OK;
 }
 

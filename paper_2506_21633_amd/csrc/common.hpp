@@ -282,7 +282,7 @@ hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const 
                              const uint32_t* pvals, const float4* cq, const float2* cw,
                              uint64_t* pmask, uint64_t* psum, hipStream_t s);
 hipError_t launch_tile_worklist(const uint2* ranges, int64_t tiles_c, uint32_t* worklist,
-                                uint32_t* status, hipStream_t s);
+                                uint32_t* bins, uint32_t* status, hipStream_t s);
 hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,

@@ -1132,38 +1132,40 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
 }
 
 // Non-empty computation-plane tiles, longest lists first (binned by the
-// bit length of the list size), so the heaviest tiles start earliest. One
-// workgroup; the count goes to status[ST_WORK_TILES].
-__global__ void __launch_bounds__(1024)
-k_tile_worklist(const uint2* __restrict__ ranges, int64_t tiles_c, uint32_t* __restrict__ worklist,
-                uint32_t* __restrict__ status)
+// bit length of the list size), so the heaviest tiles start earliest. Three
+// steps over global bins (bins[0..32] counts, bins[33..65] cursors): count
+// per bin, turn the counts into starts (one workgroup; the tile count goes
+// to status[ST_WORK_TILES]), place each tile at its bin's cursor.
+__global__ void __launch_bounds__(256)
+k_worklist_count(const uint2* __restrict__ ranges, int64_t tiles_c, uint32_t* __restrict__ bins)
 {
-    __shared__ uint32_t cnt[33], base[33];
-    const int tid = threadIdx.x;
-    if (tid < 33) cnt[tid] = 0;
-    __syncthreads();
-#pragma unroll 8
-    for (int64_t t = tid; t < tiles_c; t += blockDim.x) {
-        const uint2 rg = ranges[t];
-        const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;
-        if (len) atomicAdd(&cnt[32 - __clz(len)], 1u);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles_c) return;
+    const uint2 rg = ranges[t];
+    const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;
+    if (len) atomicAdd(&bins[32 - __clz(len)], 1u);
+}
+
+__global__ void k_worklist_starts(uint32_t* __restrict__ bins, uint32_t* __restrict__ status)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int lvl = 32; lvl >= 1; --lvl) {
+        bins[33 + lvl] = acc;
+        acc += bins[lvl];
     }
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        for (int lvl = 32; lvl >= 1; --lvl) {
-            base[lvl] = acc;
-            acc += cnt[lvl];
-        }
-        status[ST_WORK_TILES] = acc;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int64_t t = tid; t < tiles_c; t += blockDim.x) {
-        const uint2 rg = ranges[t];
-        const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;
-        if (len) worklist[atomicAdd(&base[32 - __clz(len)], 1u)] = (uint32_t)t;
-    }
+    status[ST_WORK_TILES] = acc;
+}
+
+__global__ void __launch_bounds__(256)
+k_worklist_place(const uint2* __restrict__ ranges, int64_t tiles_c, uint32_t* __restrict__ bins,
+                 uint32_t* __restrict__ worklist)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tiles_c) return;
+    const uint2 rg = ranges[t];
+    const uint32_t len = rg.y > rg.x ? rg.y - rg.x : 0u;
+    if (len) worklist[atomicAdd(&bins[33 + 32 - __clz(len)], 1u)] = (uint32_t)t;
 }
 
 inline unsigned raster_grid(int64_t waves)
@@ -1187,10 +1189,17 @@ hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const 
 }
 
 hipError_t launch_tile_worklist(const uint2* ranges, int64_t tiles_c, uint32_t* worklist,
-                                uint32_t* status, hipStream_t s)
+                                uint32_t* bins, uint32_t* status, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_tile_worklist, dim3(1), dim3(1024), 0, s, ranges, tiles_c, worklist,
-                       status);
+    hipError_t e = launch_fill_u32(bins, 0u, 66, s);
+    if (e != hipSuccess) return e;
+    if (tiles_c > 0)
+        hipLaunchKernelGGL(k_worklist_count, dim3(grid256(tiles_c)), dim3(256), 0, s, ranges,
+                           tiles_c, bins);
+    hipLaunchKernelGGL(k_worklist_starts, dim3(1), dim3(64), 0, s, bins, status);
+    if (tiles_c > 0)
+        hipLaunchKernelGGL(k_worklist_place, dim3(grid256(tiles_c)), dim3(256), 0, s, ranges,
+                           tiles_c, bins, worklist);
     return hipGetLastError();
 }
 
