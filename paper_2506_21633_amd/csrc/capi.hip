@@ -114,6 +114,8 @@ struct Problem {
     int64_t image_floats = 0;
     bool recompute = false;
     bool ikey_vm = false;   // imaging keys (tile within the view << 8) | view
+    bool seg = false;       // depth and pair sorts segmented by view
+    int cbits = 0;          // bits of the computation-plane tile within a view
     int ikey_bits = 0;      // bits of the tile within a view
 };
 
@@ -234,6 +236,11 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         max_ti = std::max<int64_t>(max_ti, (int64_t)P.views[v].txi * P.views[v].tyi);
     P.ikey_bits = bits_for(max_ti - 1);
     P.ikey_vm = nv <= IKEY_VIEWS && P.ikey_bits <= 24;
+    int64_t max_tc = 1;
+    for (int v = 0; v < nv; ++v)
+        max_tc = std::max<int64_t>(max_tc, (int64_t)P.views[v].txc * P.views[v].tyc);
+    P.cbits = bits_for(max_tc - 1);
+    P.seg = nv <= SEG_MAX;
     P.image_floats = img;
     P.pixels = pix;
     return SDGR_OK;
@@ -268,6 +275,7 @@ struct Bufs {
     uint32_t* dval[2] = {nullptr, nullptr};
     uint32_t* pkey[2] = {nullptr, nullptr};
     uint32_t* hist = nullptr;
+    SegTable* segt = nullptr;       // [0] records, [1] computation-plane pairs
     unsigned long long* slots = nullptr;   // spread pair-total accumulators
     // backward accumulators: 13 floats and one list slot per record
     float* grad_c = nullptr;
@@ -322,6 +330,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.rect_i = a.take<uint2>(R);
         b.cnt_i = a.take<uint32_t>(R);
         b.rect_c_sorted = a.take<uint2>(R);
+        b.segt = a.take<SegTable>(2);
         b.bsum_c = a.take<uint32_t>(R / 256 + 1);
         b.bsum_i = a.take<uint32_t>(R / 256 + 1);
         b.dkey[0] = a.take<uint32_t>(R);
@@ -374,7 +383,7 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
 // separated, since the stable bucket sort of the pairs groups them by tile
 // (and so by view) afterwards and keeps the depth order within each tile.
 // Computation-plane buckets are [0, tiles_c); imaging-plane buckets follow.
-int bits_pairs_c(const Problem& P) { return bits_for(P.tiles_c - 1); }
+int bits_pairs_c(const Problem& P) { return P.seg ? P.cbits : bits_for(P.tiles_c - 1); }
 int bits_pairs_i(const Problem& P)
 {
     return P.ikey_vm ? P.ikey_bits : bits_for(P.tiles_c + P.tiles_i - 1);
@@ -407,8 +416,14 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     int which = 0;
     {
         StageTimer t(SG_DEPTH_SORT, s);
+        // segmented by view: view-major depth order, so the rectangle gather
+        // below reads one view's records at a time (the per-tile lists are
+        // the same either way)
+        if (P.seg)
+            SDGR_HIP(launch_seg_setup(b.views, P.nv, R, b.status + ST_RECORDS, false, &b.segt[0],
+                                      s));
         SDGR_HIP(launch_radix_sort_u32(dk, dv, R, b.status + ST_RECORDS, 32, true, b.hist,
-                                       &which, s));
+                                       &which, s, 0, P.seg ? &b.segt[0] : nullptr, P.nv));
     }
     uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};
@@ -418,13 +433,18 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
         SDGR_HIP(launch_scan_blocks(b.bsum_c, (R + 255) / 256, plan->pairs_c, b.status, -1, s));
         SDGR_HIP(launch_pair_total_c(plan->pairs_c, b.status, s));
         SDGR_HIP(launch_emit_pairs_c(b.views, P.nv, R, dv[which], b.rect_c_sorted, b.bsum_c,
-                                     plan->pairs_c, b.status, pk[0], pv[0], s));
+                                     plan->pairs_c, b.status, pk[0], pv[0],
+                                     P.seg ? b.segt[1].seg : nullptr, s));
     }
     int pw = 0;
     {
         StageTimer t(SG_PAIR_SORT, s);
+        if (P.seg)
+            SDGR_HIP(launch_seg_setup(b.views, P.nv, R, b.status + ST_PAIRS_C, true, &b.segt[1],
+                                      s));
         SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_c, b.status + ST_PAIRS_C,
-                                       bits_pairs_c(P), false, b.hist, &pw, s));
+                                       bits_pairs_c(P), false, b.hist, &pw, s, 0,
+                                       P.seg ? &b.segt[1] : nullptr, P.nv));
     }
     if (plan->pairs_c > 0 && pw != final_buffer_c(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");

@@ -149,6 +149,16 @@ __device__ __forceinline__ float quadform(float4 g, float c, float dx, float dy)
 // the key is the global bucket id (views' imaging tiles after all
 // computation-plane ones).
 constexpr int IKEY_VIEWS = 256;
+
+// Segmented sorts (at most SEG_MAX segments, one per view): segment s holds
+// items [seg[s], seg[s+1]), its keys minus kb[s] are sorted, and it owns the
+// 4096-item sort tiles tp[s] .. tp[s+1] - 1 (tp[S] = all tiles).
+constexpr int SEG_MAX = 256;
+struct SegTable {
+    uint32_t seg[SEG_MAX + 1];
+    uint32_t kb[SEG_MAX];
+    uint32_t tp[SEG_MAX + 1];
+};
 __device__ __forceinline__ uint32_t ikey_encode(bool vm, int v, uint32_t tile_i, uint32_t local)
 {
     return vm ? ((local << 8) | (uint32_t)v) : tile_i + local;
@@ -250,7 +260,13 @@ int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
 // 0..n-1 and vals[0] is not read. *which: the buffer holding the result.
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
-                                 int* which, hipStream_t s, int shift0 = 0);
+                                 int* which, hipStream_t s, int shift0 = 0,
+                                 const SegTable* segt = nullptr, int S = 0);
+// Segment table of a segmented sort over the views: records (pairs = false)
+// or computation-plane pairs (pairs = true; seg[] as the emission wrote it),
+// n_dev items in all.
+hipError_t launch_seg_setup(const DevView* views, int nv, int64_t records, const uint32_t* n_dev,
+                            bool pairs, SegTable* segt, hipStream_t s);
 
 // Tile rectangles of the records in depth order, and the computation-plane
 // pair count of every 256 of them (bsum).
@@ -266,7 +282,7 @@ hipError_t launch_pair_total_c(int64_t cap_c, uint32_t* status, hipStream_t s);
 hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
                                const uint32_t* dval_sorted, const uint2* rect_sorted,
                                const uint32_t* bscan_c, int64_t cap_c, const uint32_t* status,
-                               uint32_t* pkey, uint32_t* pval, hipStream_t s);
+                               uint32_t* pkey, uint32_t* pval, uint32_t* seg, hipStream_t s);
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
                                const uint2* rect_i, const uint32_t* cnt_i,
                                const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i, bool vm,

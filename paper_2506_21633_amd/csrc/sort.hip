@@ -3,13 +3,17 @@
 // intensity is computed along depth-indexed Gaussian lists; the third radar
 // coordinate serves as the sorting depth).
 //
-//   1. records of all views are sorted by (fl32 depth, index) with a stable
-//      LSD radix sort of 32-bit keys (index order is the initial order, the
-//      first pass generates the indices); the views stay interleaved;
+//   1. records are sorted by (fl32 depth, index) with a stable LSD radix
+//      sort of 32-bit keys (index order is the initial order, the first
+//      pass generates the indices); with up to SEG_MAX views each view's
+//      records are sorted among themselves (a segmented sort), so the order
+//      is view-major and the reads by record index that follow stay inside
+//      one view at a time; with more views they are sorted together;
 //   2. their computation-plane pair counts are scanned in that order and
 //      every record emits (tile bucket, record) pairs in depth order;
 //   3. a stable LSD radix sort of the pairs on the bucket id yields, per
-//      tile, the Gaussians in depth order;
+//      tile, the Gaussians in depth order (segmented by view when the
+//      records were: only the tile bits within a view are sorted);
 //   4. tile ranges [start, end) are read off the sorted bucket ids;
 //   5. after pass A, records with a nonzero intensity emit their
 //      imaging-plane pairs in index order (after the computation-plane
@@ -71,28 +75,122 @@ __device__ __forceinline__ SortSpan sort_span(const uint32_t* n_dev, uint32_t gr
     return sp;
 }
 
+// Items of one sort block: a run of tiles of the whole array, or (segmented
+// sorts) one tile of one segment. Digits are taken from key - kb; slot is
+// the block's column in the digit-major count matrix of stride columns.
+struct BlockItems {
+    int64_t first, end;
+    uint32_t tiles, stride, kb;
+    int s;
+};
+
+__device__ __forceinline__ bool span_items(const uint32_t* n_dev, BlockItems& bi)
+{
+    const SortSpan sp = sort_span(n_dev, gridDim.x);
+    if (blockIdx.x >= sp.nb) return false;
+    bi.first = (int64_t)blockIdx.x * sp.tpb * SN;
+    bi.end = sp.n;
+    bi.tiles = sp.tpb;
+    bi.stride = sp.nb;
+    bi.kb = 0u;
+    bi.s = 0;
+    return true;
+}
+
+// Segment of block b: the last s with tp[s] <= b (empty segments own no
+// tile, so the block lands in the non-empty one that follows them).
+__device__ __forceinline__ bool seg_items(const SegTable* t, int S, uint32_t* s_tp, BlockItems& bi)
+{
+    for (int k = threadIdx.x; k <= S; k += blockDim.x) s_tp[k] = t->tp[k];
+    __syncthreads();
+    const uint32_t T = s_tp[S], b = blockIdx.x;
+    if (b >= T) return false;
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_tp[mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    bi.s = lo;
+    bi.first = (int64_t)t->seg[lo] + (int64_t)(b - s_tp[lo]) * SN;
+    bi.end = min(bi.first + SN, (int64_t)t->seg[lo + 1]);
+    bi.tiles = 1u;
+    bi.stride = T;
+    bi.kb = t->kb[lo];
+    return true;
+}
+
+// Segment table of a segmented sort: item offsets (views' records, or the
+// computation-plane pair offsets the emission wrote for the first record of
+// each view), key bases, and the tile offsets of every segment.
+__global__ void __launch_bounds__(SEG_MAX)
+k_seg_setup(const DevView* __restrict__ views, int nv, int64_t records,
+            const uint32_t* __restrict__ n_dev, int pairs, SegTable* __restrict__ t)
+{
+    __shared__ uint32_t s_seg[SEG_MAX + 1];
+    __shared__ uint8_t s_empty[SEG_MAX];
+    __shared__ uint32_t s_w[SEG_MAX / WAVE];
+    const int tid = threadIdx.x;
+    const uint32_t n = *n_dev;
+    if (tid < nv) {
+        const int64_t r0 = views[tid].rec_off;
+        const int64_t r1 = tid + 1 < nv ? views[tid + 1].rec_off : records;
+        s_empty[tid] = r1 <= r0;
+        s_seg[tid] = pairs ? t->seg[tid] : (uint32_t)r0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        // empty segments start where the next one does; all clamped to n
+        // (0 after a pair overflow)
+        uint32_t next = n;
+        for (int v = nv - 1; v >= 0; --v) {
+            const uint32_t o = s_empty[v] ? next : min(s_seg[v], next);
+            s_seg[v] = o;
+            next = o;
+        }
+        s_seg[nv] = n;
+    }
+    __syncthreads();
+    const uint32_t len = tid < nv ? s_seg[tid + 1] - s_seg[tid] : 0u;
+    uint32_t total;
+    const uint32_t tp = block_excl_scan_256((len + SN - 1) / SN, s_w, total);
+    if (tid < nv) {
+        t->seg[tid] = s_seg[tid];
+        t->tp[tid] = tp;
+        t->kb[tid] = pairs ? (uint32_t)views[tid].tile_c : 0u;
+    }
+    if (tid == 0) {
+        t->seg[nv] = n;
+        t->tp[nv] = total;
+    }
+}
+
 // Block digit histogram over the block's tiles. Keys are often long runs of
 // one digit (pair keys are tile ids of a few busy tiles), so each wave first
 // groups its lanes by digit (ballot match over the digit bits) and only one
 // lane per digit adds the group's count: same-address LDS atomics would
 // serialise 64-fold.
-template <int BITS>
+template <int BITS, bool SEG>
 __global__ void __launch_bounds__(SB)
 k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int shift,
-             uint32_t* __restrict__ hist)
+             uint32_t* __restrict__ hist, const SegTable* __restrict__ segt, int S)
 {
     constexpr int R = 1 << BITS;
     __shared__ uint32_t h[R];
-    const SortSpan sp = sort_span(n_dev, gridDim.x);
-    if (blockIdx.x >= sp.nb) return;
+    __shared__ uint32_t s_tp[SEG ? SEG_MAX + 1 : 1];
+    BlockItems bi;
+    if constexpr (SEG) {
+        if (!seg_items(segt, S, s_tp, bi)) return;
+    } else {
+        if (!span_items(n_dev, bi)) return;
+    }
     const int tid = threadIdx.x, lane = tid & (WAVE - 1);
 #pragma unroll
     for (int d = tid; d < R; d += SB) h[d] = 0;
     __syncthreads();
-    const int64_t n = sp.n;
+    const int64_t n = bi.end;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    for (uint32_t t = 0; t < sp.tpb; ++t) {
-        const int64_t base = ((int64_t)blockIdx.x * sp.tpb + t) * SN;
+    for (uint32_t t = 0; t < bi.tiles; ++t) {
+        const int64_t base = bi.first + (int64_t)t * SN;
         if (base >= n) break;
         uint32_t key[SI];
 #pragma unroll
@@ -104,7 +202,7 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
         for (int k = 0; k < SI; ++k) {
             const int64_t idx = base + k * SB + tid;
             const bool valid = idx < n;
-            const uint32_t d = (key[k] >> shift) & (R - 1);
+            const uint32_t d = ((key[k] - bi.kb) >> shift) & (R - 1);
             uint64_t m = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < BITS; ++b) {
@@ -116,7 +214,7 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
     }
     __syncthreads();
 #pragma unroll
-    for (int d = tid; d < R; d += SB) hist[(int64_t)d * sp.nb + blockIdx.x] = h[d];
+    for (int d = tid; d < R; d += SB) hist[(int64_t)d * bi.stride + blockIdx.x] = h[d];
 }
 
 // Spine of one pass: block d turns row d of the digit-major block counts
@@ -124,41 +222,49 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
 // total to tot[d] (the scatter adds the prefix over digits).
 __global__ void __launch_bounds__(SB)
 k_radix_spine(uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
-              const uint32_t* __restrict__ n_dev, unsigned grid)
+              const uint32_t* __restrict__ n_dev, unsigned grid, const SegTable* __restrict__ segt,
+              int S)
 {
     constexpr int PER = MAX_SORT_BLOCKS / SB;
     __shared__ uint32_t wtot[SB / WAVE];
-    const SortSpan sp = sort_span(n_dev, grid);
+    // a segmented sort's blocks (one tile each) may exceed MAX_SORT_BLOCKS:
+    // the row is taken MAX_SORT_BLOCKS at a time with a running carry
+    const uint32_t nb = segt ? segt->tp[S] : sort_span(n_dev, grid).nb;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-    uint32_t* row = hist + (int64_t)blockIdx.x * sp.nb;
-    uint32_t v[PER], sum = 0u;
+    uint32_t* row = hist + (int64_t)blockIdx.x * nb;
+    uint32_t carry = 0u;
+    for (uint32_t base = 0; base < nb; base += MAX_SORT_BLOCKS) {
+        uint32_t v[PER], sum = 0u;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const uint32_t b = (uint32_t)(tid * PER + k);
-        v[k] = b < sp.nb ? row[b] : 0u;
-        sum += v[k];
-    }
-    uint32_t inc = sum;
+        for (int k = 0; k < PER; ++k) {
+            const uint32_t b = base + (uint32_t)(tid * PER + k);
+            v[k] = b < nb ? row[b] : 0u;
+            sum += v[k];
+        }
+        uint32_t inc = sum;
 #pragma unroll
-    for (int dd = 1; dd < WAVE; dd <<= 1) {
-        const uint32_t c = __shfl_up(inc, dd, WAVE);
-        if (lane >= dd) inc += c;
-    }
-    if (lane == WAVE - 1) wtot[w] = inc;
-    __syncthreads();
-    uint32_t run = inc - sum, all = 0u;
+        for (int dd = 1; dd < WAVE; dd <<= 1) {
+            const uint32_t c = __shfl_up(inc, dd, WAVE);
+            if (lane >= dd) inc += c;
+        }
+        if (lane == WAVE - 1) wtot[w] = inc;
+        __syncthreads();
+        uint32_t run = carry + inc - sum, all = 0u;
 #pragma unroll
-    for (int ww = 0; ww < SB / WAVE; ++ww) {
-        if (ww < w) run += wtot[ww];
-        all += wtot[ww];
-    }
+        for (int ww = 0; ww < SB / WAVE; ++ww) {
+            if (ww < w) run += wtot[ww];
+            all += wtot[ww];
+        }
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const uint32_t b = (uint32_t)(tid * PER + k);
-        if (b < sp.nb) row[b] = run;
-        run += v[k];
+        for (int k = 0; k < PER; ++k) {
+            const uint32_t b = base + (uint32_t)(tid * PER + k);
+            if (b < nb) row[b] = run;
+            run += v[k];
+        }
+        carry += all;
+        __syncthreads();   // wtot is rewritten by the next chunk
     }
-    if (tid == 0) tot[blockIdx.x] = all;
+    if (tid == 0) tot[blockIdx.x] = carry;
 }
 
 // Stable scatter, one 4096-item tile at a time over the block's tiles. Each
@@ -169,12 +275,13 @@ k_radix_spine(uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
 // that the items of one digit leave as a contiguous run. The block's next
 // position per digit carries over from tile to tile. With vin null the
 // values are the items' input positions.
-template <int BITS>
+template <int BITS, bool SEG>
 __global__ void __launch_bounds__(SB)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int shift,
-                const uint32_t* __restrict__ offs, const uint32_t* __restrict__ tot)
+                const uint32_t* __restrict__ offs, const uint32_t* __restrict__ tot,
+                const SegTable* __restrict__ segt, int S)
 {
     constexpr int R = 1 << BITS;
     constexpr int NW = SB / WAVE;
@@ -184,19 +291,37 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t s_key[SN];
     __shared__ uint32_t s_val[SN];
-    const SortSpan sp = sort_span(n_dev, gridDim.x);
-    if (blockIdx.x >= sp.nb) return;
+    __shared__ uint32_t s_tp[SEG ? SEG_MAX + 1 : 1];
+    BlockItems bi;
+    if constexpr (SEG) {
+        if (!seg_items(segt, S, s_tp, bi)) return;
+    } else {
+        if (!span_items(n_dev, bi)) return;
+    }
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
-    const int64_t n = sp.n;
+    const int64_t n = bi.end;
     uint32_t run[DPT];   // next output position of my digits
     {
-        // items of all smaller digits (exclusive scan of the digit totals)
-        uint32_t t[DPT], sum = 0u;
+        // items of all smaller digits (exclusive scan of the digit totals;
+        // segmented: of the segment's digit totals, from the segment start)
+        uint32_t t[DPT], pb[DPT], sum = 0u, seg0 = 0u;
+        const int64_t col = blockIdx.x;
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
-            t[k] = tot[tid * DPT + k];
+            const int64_t row = (int64_t)(tid * DPT + k) * bi.stride;
+            if constexpr (SEG) {
+                const uint32_t b0 = s_tp[bi.s], b1 = s_tp[bi.s + 1];
+                const uint32_t p0 = offs[row + b0];
+                const uint32_t p1 = b1 < bi.stride ? offs[row + b1] : tot[tid * DPT + k];
+                t[k] = p1 - p0;
+                pb[k] = offs[row + col] - p0;
+            } else {
+                t[k] = tot[tid * DPT + k];
+                pb[k] = offs[row + col];
+            }
             sum += t[k];
         }
+        if constexpr (SEG) seg0 = segt->seg[bi.s];
         uint32_t inc = sum;
 #pragma unroll
         for (int dd = 1; dd < WAVE; dd <<= 1) {
@@ -211,7 +336,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
             if (ww < w) base += wsum[ww];
 #pragma unroll
         for (int k = 0; k < DPT; ++k) {
-            run[k] = base + offs[(int64_t)(tid * DPT + k) * sp.nb + blockIdx.x];
+            run[k] = seg0 + base + pb[k];
             base += t[k];
         }
         __syncthreads();   // wsum is reused per tile
@@ -227,9 +352,9 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
             val[k] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
         }
     };
-    const int64_t first = (int64_t)blockIdx.x * sp.tpb * SN;
+    const int64_t first = bi.first;
     load_tile(first);
-    for (uint32_t t = 0; t < sp.tpb; ++t) {
+    for (uint32_t t = 0; t < bi.tiles; ++t) {
         const int64_t blk = first + (int64_t)t * SN;
         if (blk >= n) break;
         const uint32_t cnt_blk = (uint32_t)min((int64_t)SN, n - blk);
@@ -242,7 +367,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
         for (int k = 0; k < SI; ++k) {
             const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
             const bool valid = idx < n;
-            const uint32_t d = (key[k] >> shift) & (R - 1);
+            const uint32_t d = ((key[k] - bi.kb) >> shift) & (R - 1);
             uint64_t m = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < BITS; ++b) {
@@ -299,64 +424,85 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
         for (int k = 0; k < SI; ++k) {
             const int64_t idx = blk + (int64_t)w * (SI * WAVE) + k * WAVE + lane;
             if (idx < n) {
-                const uint32_t d = (key[k] >> shift) & (R - 1);
+                const uint32_t d = ((key[k] - bi.kb) >> shift) & (R - 1);
                 const uint32_t pos = wc[w][d] + rank[k];
                 s_key[pos] = key[k];
                 s_val[pos] = val[k];
             }
         }
         // the next tile's items load while this one is written out
-        if (t + 1 < sp.tpb && blk + SN < n) load_tile(blk + SN);
+        if (t + 1 < bi.tiles && blk + SN < n) load_tile(blk + SN);
         __syncthreads();
 #pragma unroll 4
         for (uint32_t i = tid; i < cnt_blk; i += SB) {
             const uint32_t k = s_key[i];
-            const uint32_t g = gbase[(k >> shift) & (R - 1)] + i;
+            const uint32_t g = gbase[((k - bi.kb) >> shift) & (R - 1)] + i;
             kout[g] = k;
             vout[g] = s_val[i];
         }
     }
 }
 
-template <int BITS>
+// Grid of a sort pass: a segmented sort has one block per tile, and every
+// segment may end in a partial tile.
+inline unsigned pass_grid(int64_t cap, int S, bool seg)
+{
+    return seg ? nblocks(cap) + (unsigned)S : sort_grid(cap);
+}
+
+template <int BITS, bool SEG>
 hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
-                        int shift0)
+                        int shift0, const SegTable* segt, int S)
 {
     constexpr int R = 1 << BITS;
-    const unsigned grid = sort_grid(cap);
+    const unsigned grid = pass_grid(cap, S, SEG);
     uint32_t* tot = hist + (int64_t)MAX_RADIX * grid;   // digit totals after the counts
     for (int shift = shift0; shift < shift0 + bits; shift += BITS) {
-        hipLaunchKernelGGL((k_radix_hist<BITS>), dim3(grid), dim3(SB), 0, s, keys[*cur], n_dev,
-                           shift, hist);
-        hipLaunchKernelGGL(k_radix_spine, dim3(R), dim3(SB), 0, s, hist, tot, n_dev, grid);
+        hipLaunchKernelGGL((k_radix_hist<BITS, SEG>), dim3(grid), dim3(SB), 0, s, keys[*cur],
+                           n_dev, shift, hist, segt, S);
+        hipLaunchKernelGGL(k_radix_spine, dim3(R), dim3(SB), 0, s, hist, tot, n_dev, grid,
+                           SEG ? segt : nullptr, S);
         const uint32_t* vin = (iota_vals && shift == shift0) ? nullptr : vals[*cur];
-        hipLaunchKernelGGL((k_radix_scatter<BITS>), dim3(grid), dim3(SB), 0, s, keys[*cur], vin,
-                           keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist, tot);
+        hipLaunchKernelGGL((k_radix_scatter<BITS, SEG>), dim3(grid), dim3(SB), 0, s,
+                           keys[*cur], vin, keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist,
+                           tot, segt, S);
         *cur ^= 1;
     }
     return hipGetLastError();
 }
 
+template <bool SEG>
+hipError_t radix_sort_t(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
+                        int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
+                        int shift0, const SegTable* segt, int S)
+{
+    switch (digit_bits(bits)) {
+    case 8:
+        return radix_passes<8, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
+                                    segt, S);
+    case 9:
+        return radix_passes<9, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
+                                    segt, S);
+    default:
+        return radix_passes<10, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s,
+                                     shift0, segt, S);
+    }
+}
+
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                       int bits, bool iota_vals, uint32_t* hist, int* which, hipStream_t s,
-                      int shift0)
+                      int shift0, const SegTable* segt, int S)
 {
     int cur = 0;
     *which = 0;
     if (cap <= 0 || bits <= 0) return hipSuccess;
-    hipError_t e;
-    switch (digit_bits(bits)) {
-    case 8:
-        e = radix_passes<8>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0);
-        break;
-    case 9:
-        e = radix_passes<9>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0);
-        break;
-    default:
-        e = radix_passes<10>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0);
-        break;
-    }
+    if (segt && (S < 1 || S > SEG_MAX)) return hipErrorInvalidValue;
+    const hipError_t e =
+        segt ? radix_sort_t<true>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
+                                  segt, S)
+             : radix_sort_t<false>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
+                                   nullptr, 0);
     *which = cur;
     return e;
 }
@@ -368,7 +514,10 @@ k_gather_rects(const uint32_t* __restrict__ order, const uint2* __restrict__ rec
                uint2* __restrict__ rect_sorted, uint32_t* __restrict__ bsum)
 {
     __shared__ uint32_t s_w[4];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // each XCD walks a contiguous part of the order: in view-major order its
+    // reads stay inside a view or two, which its L2 holds
+    const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
     uint32_t c = 0u;
     if (i < n) {
         const uint2 rc = rect[order[i]];
@@ -377,7 +526,7 @@ k_gather_rects(const uint32_t* __restrict__ order, const uint2* __restrict__ rec
     }
     uint32_t tot;
     (void)block_excl_scan_256(c, s_w, tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    if (threadIdx.x == 0) bsum[blk] = tot;
 }
 
 // Exclusive scan in place of the per-block counts, one workgroup walking
@@ -469,7 +618,7 @@ __global__ void __launch_bounds__(256)
 k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
          const uint32_t* __restrict__ dval, const uint2* __restrict__ rect_sorted,
          const uint32_t* __restrict__ bscan, int64_t cap_c, const uint32_t* __restrict__ status,
-         uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval)
+         uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t* __restrict__ seg)
 {
     __shared__ uint32_t s_w[4];
     __shared__ int64_t s_off[LDS_VIEWS];
@@ -489,6 +638,16 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
     uint32_t tot;
     const uint32_t ex = block_excl_scan_256((tx1 - tx0) * (ty1 - ty0), s_w, tot);
     if (p >= records) return;
+    if (seg && cached) {
+        // view-major order (segmented depth sort): the first record of each
+        // view marks where the view's pairs start
+        int lo = 0, hi = nv - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        if (s_off[lo] == p) seg[lo] = bscan[blockIdx.x] + ex;
+    }
     const uint32_t kc = status[ST_PAIRS_C];
     if (status[ST_OVERFLOW]) return;
     if (tx0 >= tx1 || ty0 >= ty1) return;
@@ -613,7 +772,9 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
 
 size_t radix_hist_words(int64_t cap)
 {
-    return (size_t)MAX_RADIX * (sort_grid(cap > 0 ? cap : 1) + 1);   // counts, digit totals
+    // counts (up to one block per tile and a partial tile per segment),
+    // digit totals
+    return (size_t)MAX_RADIX * (pass_grid(cap > 0 ? cap : 1, SEG_MAX, true) + 1);
 }
 
 int radix_passes_for(int bits)
@@ -625,9 +786,19 @@ int radix_passes_for(int bits)
 
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
-                                 int* which, hipStream_t s, int shift0)
+                                 int* which, hipStream_t s, int shift0, const SegTable* segt,
+                                 int S)
 {
-    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s, shift0);
+    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s, shift0, segt, S);
+}
+
+hipError_t launch_seg_setup(const DevView* views, int nv, int64_t records, const uint32_t* n_dev,
+                            bool pairs, SegTable* segt, hipStream_t s)
+{
+    if (nv < 1 || nv > SEG_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_seg_setup, dim3(1), dim3(SEG_MAX), 0, s, views, nv, records, n_dev,
+                       pairs ? 1 : 0, segt);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
@@ -663,11 +834,12 @@ hipError_t launch_pair_total_c(int64_t cap_c, uint32_t* status, hipStream_t s)
 hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
                                const uint32_t* dval_sorted, const uint2* rect_sorted,
                                const uint32_t* bscan_c, int64_t cap_c, const uint32_t* status,
-                               uint32_t* pkey, uint32_t* pval, hipStream_t s)
+                               uint32_t* pkey, uint32_t* pval, uint32_t* seg, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
+    if (seg && nv > LDS_VIEWS) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_emit_c, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
-                       dval_sorted, rect_sorted, bscan_c, cap_c, status, pkey, pval);
+                       dval_sorted, rect_sorted, bscan_c, cap_c, status, pkey, pval, seg);
     return hipGetLastError();
 }
 

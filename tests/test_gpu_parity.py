@@ -148,6 +148,19 @@ def test_empty_outside_and_degenerate_gaussians(cuda):
     assert np.all(out_b["A"][0, -3:] == 0)
 
 
+def test_more_views_than_view_major_keys(cuda):
+    """Above 256 views the imaging-plane bucket keys are global tile ids
+    (two sort passes) instead of (tile within the view, view)."""
+    sc = _small_scene(18, n=60, half=0.6)
+    views = [scenes.View.from_degrees(1.5 * k, 30.0 + (k % 7), 16 + (k % 3) * 4, 0.1)
+             for k in range(260)]
+    rng = scenes.make_rng(19)
+    G = [rng.standard_normal((v.img_h, v.img_w)) for v in views]
+    out = gpu_run(sc, views, G=G)
+    check_forward(sc, views, out)
+    check_grads(sc, views, G, out)
+
+
 def test_permutation_invariance(cuda):
     sc = _small_scene(11, n=400)
     views = scenes.vehicle_views(48, 0.1, count=3, step=40.0)
