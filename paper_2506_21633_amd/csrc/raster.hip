@@ -292,7 +292,11 @@ __device__ __forceinline__ TileCell tile_cell_i(const DevView* views, int nv, ui
 // Footprint mask of every computation-plane pair (bit 8 * row + col for
 // the tile cells inside the ellipse q < q_max), and per 64-pair chunk of
 // the sorted array (aligned to the array, so a chunk may span two tiles)
-// the OR of its masks. Blocks are whole waves, so a wave is a chunk.
+// the OR of its masks. A block takes PM_ITEMS runs of 256 pairs, each wave
+// one chunk of every run, so that each lane has PM_ITEMS independent record
+// reads in flight.
+constexpr int PM_ITEMS = 4;
+
 __global__ void __launch_bounds__(256)
 k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParams rp,
              const uint32_t* __restrict__ status, const uint32_t* __restrict__ pkey,
@@ -300,25 +304,44 @@ k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParam
              const float2* __restrict__ cw, uint64_t* __restrict__ pmask,
              uint64_t* __restrict__ psum)
 {
+    constexpr int BP = 256 * PM_ITEMS;
     const int64_t kc = min(cap, (int64_t)status[ST_PAIRS_C]);
-    const uint32_t nblk = (uint32_t)((kc + blockDim.x - 1) / blockDim.x);
-    const int64_t p = (int64_t)xcd_block(blockIdx.x, nblk) * blockDim.x + threadIdx.x;
-    if (p - lane_id() >= kc) return;   // whole wave past the end
-    uint64_t m = 0ull;
-    if (p < kc) {
-        const uint32_t bucket = pkey[p];
-        const int v = find_view(nv, (int64_t)bucket,
-                                [&](int k) { return (int64_t)views[k].tile_c; });
-        const DevView& V = views[v];
-        const int local = (int)(bucket - (uint32_t)V.tile_c);
-        const uint32_t r = pvals[p];
-        const float4 g = cq[r];
-        const float2 g2 = cw[r];
-        m = footprint_mask(g.x, g.y, g.z, g.w, g2.x, rp.q_max, local % V.txc, local / V.txc);
-        pmask[p] = m;
+    const uint32_t nblk = (uint32_t)((kc + BP - 1) / BP);
+    const int64_t base = (int64_t)xcd_block(blockIdx.x, nblk) * BP + threadIdx.x;
+    if (base - lane_id() >= kc) return;   // whole wave past the end
+    uint32_t bucket[PM_ITEMS], r[PM_ITEMS];
+#pragma unroll
+    for (int k = 0; k < PM_ITEMS; ++k) {
+        const int64_t p = base + k * 256;
+        bucket[k] = p < kc ? pkey[p] : 0u;
+        r[k] = p < kc ? pvals[p] : 0u;
     }
-    m = wave_or_u64(m);
-    if (lane_id() == 0) psum[p / WAVE] = m;
+    float4 g[PM_ITEMS];
+    float2 g2[PM_ITEMS];
+#pragma unroll
+    for (int k = 0; k < PM_ITEMS; ++k) {
+        if (base + k * 256 < kc) {
+            g[k] = cq[r[k]];
+            g2[k] = cw[r[k]];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PM_ITEMS; ++k) {
+        const int64_t p = base + k * 256;
+        if (p - lane_id() >= kc) break;   // this and later chunks of the wave are past the end
+        uint64_t m = 0ull;
+        if (p < kc) {
+            const int v = find_view(nv, (int64_t)bucket[k],
+                                    [&](int j) { return (int64_t)views[j].tile_c; });
+            const DevView& V = views[v];
+            const int local = (int)(bucket[k] - (uint32_t)V.tile_c);
+            m = footprint_mask(g[k].x, g[k].y, g[k].z, g[k].w, g2[k].x, rp.q_max, local % V.txc,
+                               local / V.txc);
+            pmask[p] = m;
+        }
+        m = wave_or_u64(m);
+        if (lane_id() == 0) psum[p / WAVE] = m;
+    }
 }
 
 // Pass A forward, one wave per non-empty 8x8 tile; the wave's rays are the
@@ -1183,8 +1206,9 @@ hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const 
                              uint64_t* pmask, uint64_t* psum, hipStream_t s)
 {
     if (cap_c <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pair_masks, dim3(grid256(cap_c)), dim3(256), 0, s, views, nv, cap_c, rp,
-                       status, pkey, pvals, cq, cw, pmask, psum);
+    const unsigned grid = (unsigned)((cap_c + 256 * PM_ITEMS - 1) / (256 * PM_ITEMS));
+    hipLaunchKernelGGL(k_pair_masks, dim3(grid), dim3(256), 0, s, views, nv, cap_c, rp, status,
+                       pkey, pvals, cq, cw, pmask, psum);
     return hipGetLastError();
 }
 
