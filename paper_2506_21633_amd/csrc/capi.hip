@@ -404,7 +404,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     SDGR_HIP(launch_fill_u32(b.status + ST_RECORDS, (uint32_t)R, 1, s));
     {
         StageTimer t(SG_PREPROCESS, s);
-        SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, R, P.rp, true, b.cq, b.cw, b.iq,
+        SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, true, b.cq, b.cw, b.iq,
                                    b.iw, b.rect_c, b.rect_i, b.dkey[0],
                                    b.slots,
                                    reinterpret_cast<unsigned long long*>(b.status + ST_COUNT),
@@ -534,7 +534,7 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
     SDGR_HIP(launch_fill_u32((uint32_t*)totals, 0u, 16, s));
     {
         StageTimer t(SG_QUERY, s);
-        SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.records, P.rp, false, nullptr,
+        SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.ns, P.items, P.rp, false, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, slots,
                                    totals, s));
     }

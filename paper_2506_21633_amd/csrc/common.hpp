@@ -149,6 +149,10 @@ __device__ __forceinline__ float quadform(float4 g, float c, float dx, float dy)
 // the key is the global bucket id (views' imaging tiles after all
 // computation-plane ones).
 constexpr int IKEY_VIEWS = 256;
+__device__ __forceinline__ uint32_t ikey_encode(bool vm, int v, uint32_t tile_i, uint32_t local)
+{
+    return vm ? ((local << 8) | (uint32_t)v) : tile_i + local;
+}
 
 // Segmented sorts (at most SEG_MAX segments, one per view): segment s holds
 // items [seg[s], seg[s+1]), its keys minus kb[s] are sorted, and it owns the
@@ -159,10 +163,6 @@ struct SegTable {
     uint32_t kb[SEG_MAX];
     uint32_t tp[SEG_MAX + 1];
 };
-__device__ __forceinline__ uint32_t ikey_encode(bool vm, int v, uint32_t tile_i, uint32_t local)
-{
-    return vm ? ((local << 8) | (uint32_t)v) : tile_i + local;
-}
 
 // Exclusive prefix of one value per thread over a 256-thread block, and the
 // block total (s_w: four LDS words; every thread of the block must call).
@@ -229,8 +229,8 @@ namespace sdgr {
 // Pair totals of the projection are accumulated in 2 x TOTAL_SLOTS u64
 // slots (spread atomics) and summed into totals[0..1].
 constexpr int TOTAL_SLOTS = 1024;
-hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
-                             int64_t records, const RasterParams& rp,
+hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv, int nscenes,
+                             int64_t items, const RasterParams& rp,
                              bool write_records, float4* cq, float2* cw, float4* iq,
                              float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* dkey,
                              unsigned long long* slots, unsigned long long* totals,

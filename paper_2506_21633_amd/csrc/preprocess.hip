@@ -159,42 +159,44 @@ __device__ __forceinline__ Conic2 plane_conic(const float* Mt, const float* e1, 
     return r;
 }
 
-// FP32 projection of one record; the range coordinate that orders the depth
-// lists is evaluated in FP64 (range_coordinate) for a reproducible key.
+// FP32 projection of the records; the range coordinate that orders the
+// depth lists is evaluated in FP64 (range_coordinate) for a reproducible
+// key. A thread takes one Gaussian and up to PRE_VIEWS views of its scene
+// (grid y: the group of views), so the Gaussian's parameters are read and
+// its rotation built once per group instead of once per record; writes of
+// one view are coalesced across the block's Gaussians.
+constexpr int PRE_VIEWS = 8;
+
 __global__ void __launch_bounds__(256)
 k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
-             int64_t records, RasterParams rp, int write_records, float4* __restrict__ cq,
-             float2* __restrict__ cw, float4* __restrict__ iq, float2* __restrict__ iw,
-             uint2* __restrict__ rect_c, uint2* __restrict__ rect_i, uint32_t* __restrict__ dkey,
-             unsigned long long* __restrict__ totals)
+             int nscenes, int64_t items, RasterParams rp, int write_records,
+             float4* __restrict__ cq, float2* __restrict__ cw, float4* __restrict__ iq,
+             float2* __restrict__ iw, uint2* __restrict__ rect_c, uint2* __restrict__ rect_i,
+             uint32_t* __restrict__ dkey, unsigned long long* __restrict__ totals)
 {
     __shared__ unsigned long long part[2];
     if (threadIdx.x < 2) part[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t nc = 0, ni = 0;
-    if (r < records) {
-        const int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
-        const DevView& V = views[v];
-        const DevScene& S = scenes[V.scene];
-        const int64_t i = r - V.rec_off;
+    if (t < items) {
+        const int sc = find_view(nscenes, t, [&](int k) { return scenes[k].item_off; });
+        const DevScene& S = scenes[sc];
+        const int64_t i = t - S.item_off;
         const float m0 = S.means[3 * i], m1 = S.means[3 * i + 1], m2 = S.means[3 * i + 2];
         const float s0 = S.scales[3 * i], s1 = S.scales[3 * i + 1], s2 = S.scales[3 * i + 2];
         const float* qp = S.quats + 4 * i;
         const float4 q = make_float4(qp[0], qp[1], qp[2], qp[3]);
+        const float ext = S.ext[i];
         const float n2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
-        bool ok = isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(s0) &&
-                  isfinite(s1) && isfinite(s2) && s0 > 0.0f && s1 > 0.0f && s2 > 0.0f &&
-                  isfinite(n2) && n2 > 0.0f;
-        float4 vc_q = make_float4(0.f, 0.f, 0.f, 0.f), vi_q = vc_q;
-        float2 vc_w = make_float2(0.f, 0.f), vi_w = vc_w;
-        uint2 rc = make_uint2(0, 0), ri = make_uint2(0, 0);
-        uint32_t zbits = 0u;
-        if (ok) {
-            const float inv_n = rsqrtf(n2);
+        const bool valid = isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(s0) &&
+                           isfinite(s1) && isfinite(s2) && s0 > 0.0f && s1 > 0.0f &&
+                           s2 > 0.0f && isfinite(n2) && n2 > 0.0f;
+        // rows of M^T: column k of R scaled by s_k
+        float Mt[9];
+        {
+            const float inv_n = valid ? rsqrtf(n2) : 0.0f;
             const float w = q.x * inv_n, x = q.y * inv_n, y = q.z * inv_n, z = q.w * inv_n;
-            // rows of M^T: column k of R scaled by s_k
-            float Mt[9];
             Mt[0] = (1.f - 2.f * (y * y + z * z)) * s0;
             Mt[1] = 2.f * (x * y + w * z) * s0;
             Mt[2] = 2.f * (x * z - w * y) * s0;
@@ -204,38 +206,49 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
             Mt[6] = 2.f * (x * z + w * y) * s2;
             Mt[7] = 2.f * (y * z - w * x) * s2;
             Mt[8] = (1.f - 2.f * (x * x + y * y)) * s2;
-            const float ex[3] = {(float)V.ex[0], (float)V.ex[1], (float)V.ex[2]};
-            const float ey[3] = {(float)V.ey[0], (float)V.ey[1], (float)V.ey[2]};
-            const float ez[3] = {(float)V.ez[0], (float)V.ez[1], (float)V.ez[2]};
-            const float iA = (float)V.iA, iR = (float)V.iR;
-            const float iAc = (float)V.iAc, iEc = (float)V.iEc;
-            const Conic2 C = plane_conic(Mt, ex, ey, iAc, iEc, rp.dilation);
-            const Conic2 I = plane_conic(Mt, ex, ez, iA, iR, rp.dilation);
-            ok = C.ok && I.ok;
-            if (ok) {
-                const float xr = ex[0] * m0 + ex[1] * m1 + ex[2] * m2;
-                const float yr = ey[0] * m0 + ey[1] * m1 + ey[2] * m2;
-                const double zr = range_coordinate(V.ez, m0, m1, m2);
-                const float cCx = xr * iAc + (float)V.hWc, cCy = yr * iEc + (float)V.hHc;
-                const float cIx = xr * iA + (float)V.hW, cIy = (float)zr * iR + (float)V.hH;
-                nc = tile_rect(cCx, cCy, C.sxx, C.syy, rp.q_max, V.Wc, V.Hc, &rc);
-                ni = tile_rect(cIx, cIy, I.sxx, I.syy, rp.q_max, V.W, V.H, &ri);
-                zbits = __float_as_uint(__double2float_rn(zr));
-                if (zbits == 0x80000000u) zbits = 0u;   // -0 -> +0
-                vc_q = make_float4(cCx, cCy, C.a, C.b);
-                vc_w = make_float2(C.c, S.ext[i]);
-                vi_q = make_float4(cIx, cIy, I.a, I.b);
-                vi_w = make_float2(I.c, 0.0f);
-            }
         }
-        if (write_records) {
-            cq[r] = vc_q;
-            cw[r] = vc_w;
-            iq[r] = vi_q;
-            iw[r] = vi_w;
-            rect_c[r] = rc;
-            rect_i[r] = ri;
-            dkey[r] = float_order_bits(__uint_as_float(zbits));
+        const int v_end = min(nv, (int)(blockIdx.y + 1) * PRE_VIEWS);
+        for (int v = (int)blockIdx.y * PRE_VIEWS; v < v_end; ++v) {
+            const DevView& V = views[v];
+            if (V.scene != sc) continue;
+            const int64_t r = V.rec_off + i;
+            float4 vc_q = make_float4(0.f, 0.f, 0.f, 0.f), vi_q = vc_q;
+            float2 vc_w = make_float2(0.f, 0.f), vi_w = vc_w;
+            uint2 rc = make_uint2(0, 0), ri = make_uint2(0, 0);
+            uint32_t zbits = 0u;
+            if (valid) {
+                const float ex[3] = {(float)V.ex[0], (float)V.ex[1], (float)V.ex[2]};
+                const float ey[3] = {(float)V.ey[0], (float)V.ey[1], (float)V.ey[2]};
+                const float ez[3] = {(float)V.ez[0], (float)V.ez[1], (float)V.ez[2]};
+                const float iA = (float)V.iA, iR = (float)V.iR;
+                const float iAc = (float)V.iAc, iEc = (float)V.iEc;
+                const Conic2 C = plane_conic(Mt, ex, ey, iAc, iEc, rp.dilation);
+                const Conic2 I = plane_conic(Mt, ex, ez, iA, iR, rp.dilation);
+                if (C.ok && I.ok) {
+                    const float xr = ex[0] * m0 + ex[1] * m1 + ex[2] * m2;
+                    const float yr = ey[0] * m0 + ey[1] * m1 + ey[2] * m2;
+                    const double zr = range_coordinate(V.ez, m0, m1, m2);
+                    const float cCx = xr * iAc + (float)V.hWc, cCy = yr * iEc + (float)V.hHc;
+                    const float cIx = xr * iA + (float)V.hW, cIy = (float)zr * iR + (float)V.hH;
+                    nc += tile_rect(cCx, cCy, C.sxx, C.syy, rp.q_max, V.Wc, V.Hc, &rc);
+                    ni += tile_rect(cIx, cIy, I.sxx, I.syy, rp.q_max, V.W, V.H, &ri);
+                    zbits = __float_as_uint(__double2float_rn(zr));
+                    if (zbits == 0x80000000u) zbits = 0u;   // -0 -> +0
+                    vc_q = make_float4(cCx, cCy, C.a, C.b);
+                    vc_w = make_float2(C.c, ext);
+                    vi_q = make_float4(cIx, cIy, I.a, I.b);
+                    vi_w = make_float2(I.c, 0.0f);
+                }
+            }
+            if (write_records) {
+                cq[r] = vc_q;
+                cw[r] = vc_w;
+                iq[r] = vi_q;
+                iw[r] = vi_w;
+                rect_c[r] = rc;
+                rect_i[r] = ri;
+                dkey[r] = float_order_bits(__uint_as_float(zbits));
+            }
         }
     }
     // wave sums first: 256 same-address LDS atomics would serialise
@@ -251,8 +264,9 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
     }
     __syncthreads();
     // spread over TOTAL_SLOTS addresses; k_sum_slots adds them up
+    const uint32_t bid = blockIdx.y * gridDim.x + blockIdx.x;
     if (threadIdx.x < 2 && part[threadIdx.x])
-        atomicAdd(&totals[2 * (blockIdx.x % TOTAL_SLOTS) + threadIdx.x], part[threadIdx.x]);
+        atomicAdd(&totals[2 * (bid % TOTAL_SLOTS) + threadIdx.x], part[threadIdx.x]);
 }
 
 __global__ void __launch_bounds__(1024)
@@ -420,8 +434,8 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int n)
 
 }  // namespace
 
-hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv,
-                             int64_t records, const RasterParams& rp, bool write_records,
+hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv, int nscenes,
+                             int64_t items, const RasterParams& rp, bool write_records,
                              float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
                              uint2* rect_i, uint32_t* dkey,
                              unsigned long long* slots,
@@ -429,10 +443,11 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(2 * TOTAL_SLOTS / 256), dim3(256), 0, s, slots,
                        2 * TOTAL_SLOTS);
-    if (records > 0)
-        hipLaunchKernelGGL(k_preprocess, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
-                           scenes, nv, records, rp, write_records ? 1 : 0, cq, cw, iq, iw,
-                           rect_c, rect_i, dkey, slots);
+    if (items > 0 && nv > 0)
+        hipLaunchKernelGGL(k_preprocess,
+                           dim3(blocks_for(items, 256), (unsigned)((nv + PRE_VIEWS - 1) / PRE_VIEWS)),
+                           dim3(256), 0, s, views, scenes, nv, nscenes, items, rp,
+                           write_records ? 1 : 0, cq, cw, iq, iw, rect_c, rect_i, dkey, slots);
     hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(TOTAL_SLOTS), 0, s, slots, totals);
     return hipGetLastError();
 }

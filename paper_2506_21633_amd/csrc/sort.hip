@@ -611,6 +611,66 @@ __global__ void k_pair_total_c(int64_t cap_c, uint32_t* status)
 // depth order come from all views at random).
 constexpr int LDS_VIEWS = 512;
 
+// Pair writes of one wave's records (imaging plane: few records have pairs,
+// and a loop per record would leave most lanes idle). Record (lane) l
+// owns the wave's pairs [ex[l], ex[l] + cnt_l) in row-major order over its
+// tile rectangle (width w, first tile local0, tile row stride txn); the key
+// is kadd + local, or (local << 8) | kadd for view-major imaging keys. The
+// lanes take the wave's pairs 64 at a time, each finding its pair's record
+// by binary search over the offsets (the largest l with ex[l] <= j owns j:
+// records without pairs share their offset with the next record), so each
+// store writes 64 consecutive entries whatever the spread of the counts.
+struct EmitWaves {
+    uint32_t ex[4][WAVE];
+    uint32_t local0[4][WAVE];
+    uint32_t w[4][WAVE];
+    uint32_t txn[4][WAVE];
+    uint32_t kadd[4][WAVE];
+    uint32_t val[4][WAVE];
+};
+
+__device__ __forceinline__ void emit_wave_pairs(const EmitWaves& L, int w, uint32_t lane,
+                                                uint64_t o0, uint32_t total, uint64_t lim,
+                                                bool vm, uint32_t* __restrict__ pkey,
+                                                uint32_t* __restrict__ pval)
+{
+    for (uint32_t j = lane; j < total; j += WAVE) {
+        uint32_t l = 0;
+#pragma unroll
+        for (uint32_t step = WAVE / 2; step > 0; step >>= 1)
+            if (L.ex[w][l + step] <= j) l += step;
+        const uint32_t t = j - L.ex[w][l], rw = L.w[w][l];
+        const uint32_t row = t / rw, col = t - row * rw;
+        const uint32_t local = L.local0[w][l] + row * L.txn[w][l] + col;
+        const uint64_t o = o0 + j;
+        if (o < lim) {
+            pkey[o] = ikey_encode(vm, (int)L.kadd[w][l], L.kadd[w][l], local);
+            pval[o] = L.val[w][l];
+        }
+    }
+}
+
+// Offsets of a wave's records relative to the wave (ex: block-relative
+// exclusive offsets), stored with the records' emission data; returns the
+// wave's pair count and its first offset in *ex0.
+__device__ __forceinline__ uint32_t stage_wave_records(EmitWaves& L, int w, uint32_t lane,
+                                                       uint32_t ex, uint32_t cnt, uint2 rc,
+                                                       uint32_t txn, uint32_t kadd, uint32_t val,
+                                                       uint32_t* ex0)
+{
+    const uint32_t first = __shfl(ex, 0, WAVE);
+    const uint32_t total = __shfl(ex + cnt, WAVE - 1, WAVE) - first;
+    const uint32_t tx0 = rc.x & 0xFFFF, tx1 = rc.x >> 16, ty0 = rc.y & 0xFFFF;
+    L.ex[w][lane] = ex - first;
+    L.local0[w][lane] = ty0 * txn + tx0;
+    L.w[w][lane] = tx1 - tx0;
+    L.txn[w][lane] = txn;
+    L.kadd[w][lane] = kadd;
+    L.val[w][lane] = val;
+    *ex0 = first;
+    return total;
+}
+
 // Computation-plane pairs, one thread per record in depth order: the
 // record emits (tile bucket, record) for every tile of its rectangle at its
 // scanned offset, so each tile's pairs leave in depth order.
@@ -675,9 +735,9 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
             }
 }
 
-// Imaging-plane pairs, one thread per record in index order, only for the
-// records whose intensity is nonzero (cnt_i = 0 otherwise); written after
-// the first cap_c entries of the pair arrays.
+// Imaging-plane pairs of the records in index order, only for the records
+// whose intensity is nonzero (cnt_i = 0 otherwise); written after the
+// first cap_c entries of the pair arrays.
 __global__ void __launch_bounds__(256)
 k_emit_i(const DevView* __restrict__ views, int nv, int64_t records,
          const uint2* __restrict__ rect_i, const uint32_t* __restrict__ cnt_i,
@@ -686,26 +746,31 @@ k_emit_i(const DevView* __restrict__ views, int nv, int64_t records,
          uint32_t* __restrict__ pval)
 {
     __shared__ uint32_t s_w[4];
+    __shared__ EmitWaves L;
+    const uint32_t lane = lane_id();
+    const int w = threadIdx.x / WAVE;
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t cnt = p < records ? cnt_i[p] : 0u;
     // offset: the block's prefix plus the counts of the block's records before
     uint32_t tot;
     const uint32_t ex = block_excl_scan_256(cnt, s_w, tot);
-    if (p >= records) return;
-    const uint32_t ki = status[ST_PAIRS_I];
     if (status[ST_OVERFLOW]) return;
-    if (cnt == 0u) return;
-    const int v = find_view(nv, p, [&](int k) { return views[k].rec_off; });
-    const DevView& V = views[v];
-    const uint2 ri = rect_i[p];
-    const uint32_t tx0 = ri.x & 0xFFFF, tx1 = ri.x >> 16, ty0 = ri.y & 0xFFFF, ty1 = ri.y >> 16;
-    uint64_t o = (uint64_t)bscan[blockIdx.x] + ex;
-    for (uint32_t ty = ty0; ty < ty1; ++ty)
-        for (uint32_t tx = tx0; tx < tx1; ++tx, ++o)
-            if (o < ki && o < (uint64_t)cap_i) {
-                pkey[cap_c + o] = ikey_encode(vm != 0, v, (uint32_t)V.tile_i, ty * (uint32_t)V.txi + tx);
-                pval[cap_c + o] = (uint32_t)p;
-            }
+    const uint64_t lim = min((uint64_t)status[ST_PAIRS_I], (uint64_t)cap_i);
+    uint2 ri = make_uint2(0u, 0u);
+    uint32_t kadd = 0u, txi = 1u;
+    if (cnt) {
+        const int v = find_view(nv, p, [&](int k) { return views[k].rec_off; });
+        const DevView& V = views[v];
+        ri = rect_i[p];
+        txi = (uint32_t)V.txi;
+        kadd = vm ? (uint32_t)v : (uint32_t)V.tile_i;
+    }
+    uint32_t ex0;
+    const uint32_t total =
+        stage_wave_records(L, w, lane, ex, cnt, ri, txi, kadd, (uint32_t)p, &ex0);
+    __syncthreads();
+    emit_wave_pairs(L, w, lane, (uint64_t)bscan[blockIdx.x] + ex0, total, lim, vm != 0,
+                    pkey + cap_c, pval + cap_c);
 }
 
 // Tile ranges from the sorted bucket ids, four keys per thread (one 16-byte
