@@ -280,6 +280,7 @@ struct Bufs {
     // backward accumulators: 13 floats and one list slot per record
     float* grad_c = nullptr;
     float* grad_i = nullptr;
+    float* pgrad = nullptr;         // per-view-group parts of the parameter gradients
     float* cbwd = nullptr;          // c = P dL/dI per record (pass A backward)
     uint32_t* active = nullptr;     // records with A > 0 (backward)
 };
@@ -356,6 +357,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.grad_i = sc.take<float>(6 * R);
         b.cbwd = sc.take<float>(R);
         b.active = sc.take<uint32_t>(R);
+        b.pgrad = sc.take<float>((int64_t)params_part_floats(P.nv, P.items));
     }
     if (state_bytes) *state_bytes = st.off;
     if (scratch_bytes) *scratch_bytes = sc.off;
@@ -690,7 +692,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,
-                                    b.grad_c, b.grad_i, P.records, s));
+                                    b.grad_c, b.grad_i, P.records, b.pgrad, s));
     return SDGR_OK;
 }
 

@@ -248,7 +248,9 @@ hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, 
                                   int nscenes, int64_t scene_items,
                                   const RasterParams& rp, const float* A,
                                   const float* grad_c, const float* grad_i,
-                                  int64_t records, hipStream_t s);
+                                  int64_t records, float* part, hipStream_t s);
+// Scratch floats of the per-view-group gradient parts (0: one group).
+size_t params_part_floats(int nv, int64_t items);
 
 // stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
 // n_dev points at the device-side element count (<= cap). Buffers [0] hold

@@ -342,11 +342,28 @@ __device__ void plane_adjoint(const double* Q, const float* gq, const double* u,
     for (int k = 0; k < 3; ++k) dmu[k] += gx * u[k] + gy * w[k];
 }
 
+// Per-Gaussian gradient outputs: d_means (3), d_scales (3), d_quats (4),
+// d_amp, d_ext. The backward takes the views PB_VIEWS at a time (grid y).
+constexpr int PB_OUT = 12;
+constexpr int PB_VIEWS = 8;
+
+__device__ __forceinline__ void store_param_grads(const DevScene& S, int64_t i, const float* o)
+{
+    float* om = S.d_means + 3 * i;
+    float* os = S.d_scales + 3 * i;
+    float* oq = S.d_quats + 4 * i;
+    om[0] = o[0]; om[1] = o[1]; om[2] = o[2];
+    os[0] = o[3]; os[1] = o[4]; os[2] = o[5];
+    oq[0] = o[6]; oq[1] = o[7]; oq[2] = o[8]; oq[3] = o[9];
+    S.d_amp[i] = o[10];
+    S.d_ext[i] = o[11];
+}
+
 __global__ void __launch_bounds__(256)
 k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
                   int nscenes, int64_t items, RasterParams rp, const float* __restrict__ A,
                   const float* __restrict__ grad_c, const float* __restrict__ grad_i,
-                  int64_t records)
+                  int64_t records, float* __restrict__ part)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= items) return;
@@ -358,7 +375,8 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
     Geo g;
     gaussian_frame(S, i, g);
     bool any = false;
-    for (int v = 0; v < nv && g.valid; ++v) {
+    const int v_end = min(nv, (int)(blockIdx.y + 1) * PB_VIEWS);
+    for (int v = (int)blockIdx.y * PB_VIEWS; v < v_end && g.valid; ++v) {
         const DevView& V = views[v];
         if (V.scene != s) continue;
         // a record pass A never used (A = 0) has zero gradients in this view,
@@ -380,48 +398,67 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
         dk += gc[5];
         dp += (double)A[r] * gi[5];
     }
-    float* om = S.d_means + 3 * i;
-    float* os = S.d_scales + 3 * i;
-    float* oq = S.d_quats + 4 * i;
-    if (!any || !g.valid) {
-        om[0] = om[1] = om[2] = 0.f;
-        os[0] = os[1] = os[2] = 0.f;
-        oq[0] = oq[1] = oq[2] = oq[3] = 0.f;
-        S.d_amp[i] = 0.f;
-        S.d_ext[i] = 0.f;
-        return;
+    // the gradients are linear in (dSigma, dmu, dkappa, dP): a group of views
+    // contributes its own part, summed over the groups by k_params_reduce
+    float o[PB_OUT] = {};
+    if (any && g.valid) {
+        // Sigma = M M^T with M = R diag(s): dM = 2 dSigma M (dSigma symmetric)
+        double D[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
+        double dM[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c)
+                dM[3 * r + c] = 2.0 * (D[3 * r] * g.M[c] + D[3 * r + 1] * g.M[3 + c] +
+                                       D[3 * r + 2] * g.M[6 + c]);
+        double ds[3], G[9];
+        for (int c = 0; c < 3; ++c) {
+            ds[c] = g.R[c] * dM[c] + g.R[3 + c] * dM[3 + c] + g.R[6 + c] * dM[6 + c];
+            for (int r = 0; r < 3; ++r) G[3 * r + c] = dM[3 * r + c] * g.s[c];
+        }
+        double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
+        // derivative of the unit-quaternion rotation matrix entries
+        double gw = 2.0 * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+        double gx = 2.0 * (y * G[1] + z * G[2] + y * G[3] - 2.0 * x * G[4] - w * G[5] + z * G[6] +
+                           w * G[7] - 2.0 * x * G[8]);
+        double gy = 2.0 * (-2.0 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] +
+                           z * G[7] - 2.0 * y * G[8]);
+        double gz = 2.0 * (-2.0 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.0 * z * G[4] +
+                           y * G[5] + x * G[6] + y * G[7]);
+        double dot = w * gw + x * gx + y * gy + z * gz;
+        double inv = 1.0 / g.qnorm;
+        o[0] = (float)dmu[0]; o[1] = (float)dmu[1]; o[2] = (float)dmu[2];
+        o[3] = (float)ds[0]; o[4] = (float)ds[1]; o[5] = (float)ds[2];
+        o[6] = (float)((gw - w * dot) * inv);
+        o[7] = (float)((gx - x * dot) * inv);
+        o[8] = (float)((gy - y * dot) * inv);
+        o[9] = (float)((gz - z * dot) * inv);
+        o[10] = (float)dp;
+        o[11] = (float)dk;
     }
-    // Sigma = M M^T with M = R diag(s): dM = 2 dSigma M (dSigma symmetric)
-    double D[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
-    double dM[9];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c)
-            dM[3 * r + c] = 2.0 * (D[3 * r] * g.M[c] + D[3 * r + 1] * g.M[3 + c] +
-                                   D[3 * r + 2] * g.M[6 + c]);
-    double ds[3], G[9];
-    for (int c = 0; c < 3; ++c) {
-        ds[c] = g.R[c] * dM[c] + g.R[3 + c] * dM[3 + c] + g.R[6 + c] * dM[6 + c];
-        for (int r = 0; r < 3; ++r) G[3 * r + c] = dM[3 * r + c] * g.s[c];
+    if (gridDim.y == 1) {
+        store_param_grads(S, i, o);
+    } else {
+#pragma unroll
+        for (int k = 0; k < PB_OUT; ++k) part[((int64_t)blockIdx.y * PB_OUT + k) * items + t] = o[k];
     }
-    double w = g.qn[0], x = g.qn[1], y = g.qn[2], z = g.qn[3];
-    // derivative of the unit-quaternion rotation matrix entries
-    double gw = 2.0 * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
-    double gx = 2.0 * (y * G[1] + z * G[2] + y * G[3] - 2.0 * x * G[4] - w * G[5] + z * G[6] +
-                       w * G[7] - 2.0 * x * G[8]);
-    double gy = 2.0 * (-2.0 * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] +
-                       z * G[7] - 2.0 * y * G[8]);
-    double gz = 2.0 * (-2.0 * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.0 * z * G[4] +
-                       y * G[5] + x * G[6] + y * G[7]);
-    double dot = w * gw + x * gx + y * gy + z * gz;
-    double inv = 1.0 / g.qnorm;
-    oq[0] = (float)((gw - w * dot) * inv);
-    oq[1] = (float)((gx - x * dot) * inv);
-    oq[2] = (float)((gy - y * dot) * inv);
-    oq[3] = (float)((gz - z * dot) * inv);
-    om[0] = (float)dmu[0]; om[1] = (float)dmu[1]; om[2] = (float)dmu[2];
-    os[0] = (float)ds[0]; os[1] = (float)ds[1]; os[2] = (float)ds[2];
-    S.d_amp[i] = (float)dp;
-    S.d_ext[i] = (float)dk;
+}
+
+// Sum of the view groups' parts of every Gaussian's gradients.
+__global__ void __launch_bounds__(256)
+k_params_reduce(const DevScene* __restrict__ scenes, int nscenes, int64_t items, int groups,
+                const float* __restrict__ part)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= items) return;
+    const int s = find_view(nscenes, t, [&](int k) { return scenes[k].item_off; });
+    const DevScene& S = scenes[s];
+    double acc[PB_OUT] = {};
+    for (int gq = 0; gq < groups; ++gq)
+#pragma unroll
+        for (int k = 0; k < PB_OUT; ++k) acc[k] += part[((int64_t)gq * PB_OUT + k) * items + t];
+    float o[PB_OUT];
+#pragma unroll
+    for (int k = 0; k < PB_OUT; ++k) o[k] = (float)acc[k];
+    store_param_grads(S, t - S.item_off, o);
 }
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -463,15 +500,28 @@ hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, in
     return hipGetLastError();
 }
 
+int params_groups(int nv) { return nv > 0 ? (nv + PB_VIEWS - 1) / PB_VIEWS : 1; }
+
+size_t params_part_floats(int nv, int64_t items)
+{
+    const int g = params_groups(nv);
+    return g > 1 ? (size_t)PB_OUT * g * (size_t)items : 0;
+}
+
 hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, int nv,
                                   int nscenes, int64_t scene_items, const RasterParams& rp,
                                   const float* A, const float* grad_c, const float* grad_i,
-                                  int64_t records, hipStream_t s)
+                                  int64_t records, float* part, hipStream_t s)
 {
     if (scene_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_params_backward, dim3(blocks_for(scene_items, 256)), dim3(256), 0, s,
-                       views, scenes, nv, nscenes, scene_items, rp, A, grad_c, grad_i,
-                       records);
+    const int groups = params_groups(nv);
+    if (groups > 1 && !part) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_params_backward, dim3(blocks_for(scene_items, 256), groups), dim3(256),
+                       0, s, views, scenes, nv, nscenes, scene_items, rp, A, grad_c, grad_i,
+                       records, part);
+    if (groups > 1)
+        hipLaunchKernelGGL(k_params_reduce, dim3(blocks_for(scene_items, 256)), dim3(256), 0, s,
+                           scenes, nscenes, scene_items, groups, part);
     return hipGetLastError();
 }
 
