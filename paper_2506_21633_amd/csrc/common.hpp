@@ -156,12 +156,14 @@ __device__ __forceinline__ uint32_t ikey_encode(bool vm, int v, uint32_t tile_i,
 
 // Segmented sorts (at most SEG_MAX segments, one per view): segment s holds
 // items [seg[s], seg[s+1]), its keys minus kb[s] are sorted, and it owns the
-// 4096-item sort tiles tp[s] .. tp[s+1] - 1 (tp[S] = all tiles).
+// sort blocks tp[s] .. tp[s+1] - 1 (tp[S] = all blocks), each a run of tpb
+// 4096-item tiles of the segment (the last one shorter).
 constexpr int SEG_MAX = 256;
 struct SegTable {
     uint32_t seg[SEG_MAX + 1];
     uint32_t kb[SEG_MAX];
     uint32_t tp[SEG_MAX + 1];
+    uint32_t tpb;
 };
 
 // Exclusive prefix of one value per thread over a 256-thread block, and the

@@ -76,7 +76,7 @@ __device__ __forceinline__ SortSpan sort_span(const uint32_t* n_dev, uint32_t gr
 }
 
 // Items of one sort block: a run of tiles of the whole array, or (segmented
-// sorts) one tile of one segment. Digits are taken from key - kb; slot is
+// sorts) a run of tiles of one segment. Digits are taken from key - kb; slot is
 // the block's column in the digit-major count matrix of stride columns.
 struct BlockItems {
     int64_t first, end;
@@ -98,7 +98,7 @@ __device__ __forceinline__ bool span_items(const uint32_t* n_dev, BlockItems& bi
 }
 
 // Segment of block b: the last s with tp[s] <= b (empty segments own no
-// tile, so the block lands in the non-empty one that follows them).
+// block, so the block lands in the non-empty one that follows them).
 __device__ __forceinline__ bool seg_items(const SegTable* t, int S, uint32_t* s_tp, BlockItems& bi)
 {
     for (int k = threadIdx.x; k <= S; k += blockDim.x) s_tp[k] = t->tp[k];
@@ -110,10 +110,11 @@ __device__ __forceinline__ bool seg_items(const SegTable* t, int S, uint32_t* s_
         const int mid = (lo + hi + 1) >> 1;
         if (s_tp[mid] <= b) lo = mid; else hi = mid - 1;
     }
+    const uint32_t tpb = t->tpb;
     bi.s = lo;
-    bi.first = (int64_t)t->seg[lo] + (int64_t)(b - s_tp[lo]) * SN;
-    bi.end = min(bi.first + SN, (int64_t)t->seg[lo + 1]);
-    bi.tiles = 1u;
+    bi.first = (int64_t)t->seg[lo] + (int64_t)(b - s_tp[lo]) * tpb * SN;
+    bi.end = min(bi.first + (int64_t)tpb * SN, (int64_t)t->seg[lo + 1]);
+    bi.tiles = tpb;
     bi.stride = T;
     bi.kb = t->kb[lo];
     return true;
@@ -121,7 +122,8 @@ __device__ __forceinline__ bool seg_items(const SegTable* t, int S, uint32_t* s_
 
 // Segment table of a segmented sort: item offsets (views' records, or the
 // computation-plane pair offsets the emission wrote for the first record of
-// each view), key bases, and the tile offsets of every segment.
+// each view), key bases, and the block offsets of every segment, with as
+// many tiles per block as keep the blocks near MAX_SORT_BLOCKS.
 __global__ void __launch_bounds__(SEG_MAX)
 k_seg_setup(const DevView* __restrict__ views, int nv, int64_t records,
             const uint32_t* __restrict__ n_dev, int pairs, SegTable* __restrict__ t)
@@ -151,8 +153,12 @@ k_seg_setup(const DevView* __restrict__ views, int nv, int64_t records,
     }
     __syncthreads();
     const uint32_t len = tid < nv ? s_seg[tid + 1] - s_seg[tid] : 0u;
-    uint32_t total;
-    const uint32_t tp = block_excl_scan_256((len + SN - 1) / SN, s_w, total);
+    const uint32_t tiles = (len + SN - 1) / SN;
+    uint32_t all_tiles, total;
+    (void)block_excl_scan_256(tiles, s_w, all_tiles);
+    const uint32_t tpb = max(1u, (all_tiles + MAX_SORT_BLOCKS - 1) / MAX_SORT_BLOCKS);
+    __syncthreads();   // s_w is reused by the second scan
+    const uint32_t tp = block_excl_scan_256((tiles + tpb - 1) / tpb, s_w, total);
     if (tid < nv) {
         t->seg[tid] = s_seg[tid];
         t->tp[tid] = tp;
@@ -161,6 +167,7 @@ k_seg_setup(const DevView* __restrict__ views, int nv, int64_t records,
     if (tid == 0) {
         t->seg[nv] = n;
         t->tp[nv] = total;
+        t->tpb = tpb;
     }
 }
 
@@ -443,11 +450,11 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     }
 }
 
-// Grid of a sort pass: a segmented sort has one block per tile, and every
-// segment may end in a partial tile.
+// Grid of a sort pass: a segmented sort's blocks take a run of tiles of
+// their segment, and every segment may end in a shorter block.
 inline unsigned pass_grid(int64_t cap, int S, bool seg)
 {
-    return seg ? nblocks(cap) + (unsigned)S : sort_grid(cap);
+    return seg ? sort_grid(cap) + (unsigned)S : sort_grid(cap);
 }
 
 template <int BITS, bool SEG>
