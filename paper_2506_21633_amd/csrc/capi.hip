@@ -7,6 +7,8 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cstring>
+#include <unordered_map>
 #include <mutex>
 #include <cstdio>
 #include <string>
@@ -363,10 +365,38 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
     if (scratch_bytes) *scratch_bytes = sc.off;
 }
 
-int upload_tables(const Problem& P, const Bufs& b, hipStream_t s)
+// Host copies of the views table the last forward wrote into each state
+// workspace. The state must stay untouched between a forward and its
+// backward (the backward reads the forward's records and lists there), so a
+// backward given the same views finds an identical table on the device and
+// skips its upload (each upload launch reads its argument block from host
+// memory). A forward always uploads.
+struct ViewsCache {
+    std::mutex mu;
+    std::unordered_map<const void*, std::vector<char>> last;
+};
+ViewsCache g_views;
+constexpr size_t VIEWS_CACHE_STATES = 64;
+
+int upload_tables(const Problem& P, const Bufs& b, hipStream_t s, const void* state, bool forward)
 {
-    SDGR_HIP(launch_upload(b.views, P.views.data(), sizeof(DevView) * P.nv, s));
+    const size_t nb = sizeof(DevView) * (size_t)P.nv;
+    const char* bytes = reinterpret_cast<const char*>(P.views.data());
+    bool skip = false;
+    if (!forward) {
+        std::lock_guard<std::mutex> g(g_views.mu);
+        auto it = g_views.last.find(state);
+        skip = it != g_views.last.end() && it->second.size() == nb &&
+               std::memcmp(it->second.data(), bytes, nb) == 0;
+    }
+    if (!skip) SDGR_HIP(launch_upload(b.views, P.views.data(), nb, s));
     SDGR_HIP(launch_upload(b.scenes, P.scenes.data(), sizeof(DevScene) * P.ns, s));
+    if (forward) {
+        std::lock_guard<std::mutex> g(g_views.mu);
+        if (g_views.last.size() >= VIEWS_CACHE_STATES && !g_views.last.count(state))
+            g_views.last.clear();
+        g_views.last[state].assign(bytes, bytes + nb);
+    }
     return SDGR_OK;
 }
 
@@ -606,7 +636,7 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     layout(P, plan->pairs_c, plan->pairs_i, FWD, (char*)state, (char*)scratch, b, nullptr,
            nullptr);
     if (g_count_work) P.rp.work = reinterpret_cast<unsigned long long*>(b.status + WORK_WORD);
-    if ((rc = upload_tables(P, b, s))) return rc;
+    if ((rc = upload_tables(P, b, s, state, true))) return rc;
     SDGR_HIP(launch_fill_u32(b.status + ST_PAIRS_I, 0u, 1, s));
     SDGR_HIP(launch_fill_u32(b.status + WORK_WORD, 0u, STATUS_WORDS - WORK_WORD, s));
     if ((rc = build_lists_c(P, plan, b, s))) return rc;
@@ -663,7 +693,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     layout(P, plan->pairs_c, plan->pairs_i, BWD, (char*)state, (char*)scratch, b, nullptr,
            nullptr);
     if (g_count_work) P.rp.work = reinterpret_cast<unsigned long long*>(b.status + WORK_WORD);
-    if ((rc = upload_tables(P, b, s))) return rc;
+    if ((rc = upload_tables(P, b, s, state, false))) return rc;
     if (P.recompute) {
         // the forward's lists are gone: rebuild them (identical, the sorts
         // are deterministic) and refill the intensities from the kept A

@@ -515,25 +515,42 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
 }
 
 // Tile rectangles of the records in depth order, and the computation-plane
-// pair count of each block of 256 (the emission scans within the block).
+// pair count of each block of 256 (the emission scans within the block). A
+// workgroup takes four blocks of 256, so each lane has four gathers in
+// flight.
+constexpr int GATHER_BLOCKS = 4;
+
 __global__ void __launch_bounds__(256)
 k_gather_rects(const uint32_t* __restrict__ order, const uint2* __restrict__ rect, int64_t n,
                uint2* __restrict__ rect_sorted, uint32_t* __restrict__ bsum)
 {
-    __shared__ uint32_t s_w[4];
+    __shared__ uint32_t s_w[GATHER_BLOCKS][4];
     // each XCD walks a contiguous part of the order: in view-major order its
     // reads stay inside a view or two, which its L2 holds
     const uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t i = (int64_t)blk * blockDim.x + threadIdx.x;
-    uint32_t c = 0u;
-    if (i < n) {
-        const uint2 rc = rect[order[i]];
-        rect_sorted[i] = rc;
-        c = ((rc.x >> 16) - (rc.x & 0xFFFF)) * ((rc.y >> 16) - (rc.y & 0xFFFF));
+    uint32_t o[GATHER_BLOCKS];
+#pragma unroll
+    for (int k = 0; k < GATHER_BLOCKS; ++k) {
+        const int64_t i = ((int64_t)blk * GATHER_BLOCKS + k) * 256 + threadIdx.x;
+        o[k] = i < n ? order[i] : 0u;
     }
-    uint32_t tot;
-    (void)block_excl_scan_256(c, s_w, tot);
-    if (threadIdx.x == 0) bsum[blk] = tot;
+    uint2 rc[GATHER_BLOCKS];
+#pragma unroll
+    for (int k = 0; k < GATHER_BLOCKS; ++k) {
+        const int64_t i = ((int64_t)blk * GATHER_BLOCKS + k) * 256 + threadIdx.x;
+        rc[k] = i < n ? rect[o[k]] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int k = 0; k < GATHER_BLOCKS; ++k) {
+        const int64_t b0 = ((int64_t)blk * GATHER_BLOCKS + k) * 256;
+        const int64_t i = b0 + threadIdx.x;
+        if (i < n) rect_sorted[i] = rc[k];
+        const uint32_t c = ((rc[k].x >> 16) - (rc[k].x & 0xFFFF)) *
+                           ((rc[k].y >> 16) - (rc[k].y & 0xFFFF));
+        uint32_t tot;
+        (void)block_excl_scan_256(c, s_w[k], tot);
+        if (threadIdx.x == 0 && b0 < n) bsum[blk * GATHER_BLOCKS + k] = tot;
+    }
 }
 
 // Exclusive scan in place of the per-block counts, one workgroup walking
@@ -884,8 +901,9 @@ hipError_t launch_gather_rects(const uint32_t* order, const uint2* rect, int64_t
                                uint2* rect_sorted, uint32_t* bsum, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather_rects, dim3(grid256(n)), dim3(256), 0, s, order, rect, n,
-                       rect_sorted, bsum);
+    const unsigned grid = (unsigned)((n + 256 * GATHER_BLOCKS - 1) / (256 * GATHER_BLOCKS));
+    hipLaunchKernelGGL(k_gather_rects, dim3(grid), dim3(256), 0, s, order, rect, n, rect_sorted,
+                       bsum);
     return hipGetLastError();
 }
 
