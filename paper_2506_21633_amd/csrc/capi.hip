@@ -39,12 +39,12 @@ int hip_fail(hipError_t e, const char* where)
 // ---- optional per-stage timing with HIP events on the caller's stream ----
 enum Stage {
     SG_QUERY, SG_PREPROCESS, SG_DEPTH_SORT, SG_BIN, SG_PAIR_SORT, SG_RANGES,
-    SG_RASTER_A_FWD, SG_INTENSITY, SG_RASTER_B_FWD, SG_ACTIVE, SG_RASTER_B_BWD,
+    SG_RASTER_A_FWD, SG_INTENSITY, SG_RASTER_B_FWD, SG_RASTER_B_BWD,
     SG_RASTER_A_BWD, SG_PARAMS_BWD, SG_BIN_I, SG_PAIR_SORT_I, SG_COUNT
 };
 const char* const kStageNames[SG_COUNT] = {
     "plan_query", "preprocess", "depth_sort", "bin_pairs", "pair_sort", "tile_ranges",
-    "raster_a_fwd", "set_intensity", "raster_b_fwd", "active_records", "raster_b_bwd",
+    "raster_a_fwd", "set_intensity", "raster_b_fwd", "raster_b_bwd",
     "raster_a_bwd", "params_bwd", "bin_pairs_i", "pair_sort_i"};
 
 struct Profiler {
@@ -317,6 +317,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
     b.tau = st.take<float>(P.rays);
     b.nlast = st.take<uint32_t>(P.rays);
     auto geo = [&](Arena& a) {
+        b.active = a.take<uint32_t>(R);   // records pass A used
         b.cq = a.take<float4>(R);
         b.cw = a.take<float2>(R);
         b.iq = a.take<float4>(R);
@@ -358,7 +359,6 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.grad_c = sc.take<float>(6 * R);   // plane-major, see launch_params_backward
         b.grad_i = sc.take<float>(6 * R);
         b.cbwd = sc.take<float>(R);
-        b.active = sc.take<uint32_t>(R);
         b.pgrad = sc.take<float>((int64_t)params_part_floats(P.nv, P.items));
     }
     if (state_bytes) *state_bytes = st.off;
@@ -653,7 +653,7 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     {
         StageTimer t(SG_INTENSITY, s);
         SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, b.rect_i,
-                                      b.cnt_i, b.bsum_i, s));
+                                      b.cnt_i, b.bsum_i, b.status, b.active, s));
     }
     if ((rc = build_lists_i(P, plan, b, s))) return rc;
     const int pwi = final_buffer_i(P);
@@ -699,20 +699,15 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         // are deterministic) and refill the intensities from the kept A
         if ((rc = build_lists_c(P, plan, b, s))) return rc;
         SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, nullptr,
-                                      nullptr, nullptr, s));
+                                      nullptr, nullptr, b.status, b.active, s));
     }
     const int pw = final_buffer_c(P);
     {
-        // only the records pass A used carry gradients; their sums are
-        // cleared here and nothing else is read by the passes below
-        StageTimer t(SG_ACTIVE, s);
-        SDGR_HIP(launch_fill_u32(b.status + ST_ACTIVE, 0u, 1, s));
-        SDGR_HIP(launch_active_records(P.records, b.A, b.status, b.active, b.grad_c, s));
-    }
-    {
         StageTimer t(SG_RASTER_B_BWD, s);
+        // only the records pass A used (listed by the intensity pass) carry
+        // gradients; this pass also clears their computation-plane sums
         SDGR_HIP(launch_image_bwd(b.views, b.scenes, P.nv, P.records, P.rp, b.status, b.active,
-                                  b.iq, b.iw, dL_dimages, b.grad_i, b.cbwd, s));
+                                  b.iq, b.iw, dL_dimages, b.grad_i, b.cbwd, b.grad_c, s));
     }
     {
         StageTimer t(SG_RASTER_A_BWD, s);

@@ -241,7 +241,7 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
                                 int64_t records, const float* A, float2* iw,
                                 const uint2* rect_i, uint32_t* cnt_i, uint32_t* bsum_i,
-                                hipStream_t s);
+                                uint32_t* status, uint32_t* active, hipStream_t s);
 
 // Per-record gradient buffers are plane-major: component k of record r at
 // [k * records + r]; grad_c = (dcx, dcy, da, db, dc, dkappa) on the
@@ -313,12 +313,11 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
                                int64_t cap_i, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
                                const float2* iw, float* images, bool vm, hipStream_t s);
-hipError_t launch_active_records(int64_t records, const float* A, uint32_t* status,
-                                 uint32_t* active, float* grad_c, hipStream_t s);
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
                             int64_t records, const RasterParams& rp, const uint32_t* status,
                             const uint32_t* active, const float4* iq, const float2* iw,
-                            const float* dimg, float* grad_i, float* cbwd, hipStream_t s);
+                            const float* dimg, float* grad_i, float* cbwd, float* grad_c,
+                            hipStream_t s);
 hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,

@@ -283,36 +283,79 @@ k_sum_slots(const unsigned long long* __restrict__ slots, unsigned long long* __
 }
 
 // I = P A into the imaging record (incident intensity 1, Sec. II-A); with
-// rect_i given, also the imaging-plane pair count of the record: the tiles
-// of its rectangle if I is nonzero, none otherwise (a zero intensity adds
+// cnt_i given, also the imaging-plane pair count of the record: the tiles of
+// its rectangle if I is nonzero, none otherwise (a zero intensity adds
 // nothing to any pixel), and their sum over each block of 256 records.
+// Also the list of the records pass A used (A > 0; every used record gets at
+// least FLT_MIN), in index order within each block's 4096 records (blocks
+// in any order), its length in status[ST_ACTIVE]. A record with A = 0 has
+// I = P A = 0 and took part in no ray's compositing, so all of its
+// gradients are zero: the backward passes and the parameter adjoint visit
+// the listed records only. A wave takes 16 groups of 64 consecutive records.
+constexpr int INT_GROUPS = 16;
+
 __global__ void __launch_bounds__(256)
 k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
                 int64_t records, const float* __restrict__ A, float2* __restrict__ iw,
                 const uint2* __restrict__ rect_i, uint32_t* __restrict__ cnt_i,
-                uint32_t* __restrict__ bsum_i)
+                uint32_t* __restrict__ bsum_i, uint32_t* __restrict__ status,
+                uint32_t* __restrict__ active)
 {
-    __shared__ uint32_t s_w[4];
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t cnt = 0u;
-    if (r < records) {
-        int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
-        const DevView& V = views[v];
-        const float p = scenes[V.scene].amp[r - V.rec_off];
-        const float I = p * A[r];
-        iw[r].y = I;
+    __shared__ uint32_t s_cnt[4];
+    __shared__ uint32_t s_base;
+    const int lane = lane_id(), w = threadIdx.x / WAVE;
+    const int64_t wave0 = ((int64_t)blockIdx.x * 4 + w) * (INT_GROUPS * WAVE);
+    uint64_t m[INT_GROUPS];
+    uint32_t n = 0, quarter = 0;
+#pragma unroll
+    for (int g = 0; g < INT_GROUPS; ++g) {
+        const int64_t r = wave0 + g * WAVE + lane;
+        float a = 0.0f;
+        uint32_t cnt = 0u;
+        if (r < records) {
+            a = A[r];
+            const int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
+            const DevView& V = views[v];
+            const float I = scenes[V.scene].amp[r - V.rec_off] * a;
+            iw[r].y = I;
+            if (cnt_i) {
+                if (I != 0.0f) {
+                    const uint2 ri = rect_i[r];
+                    cnt = ((ri.x >> 16) - (ri.x & 0xFFFF)) * ((ri.y >> 16) - (ri.y & 0xFFFF));
+                }
+                cnt_i[r] = cnt;
+            }
+        }
+        m[g] = __ballot(a != 0.0f);
+        n += (uint32_t)__popcll(m[g]);
         if (cnt_i) {
-            const uint2 ri = rect_i[r];
-            const uint32_t area =
-                ((ri.x >> 16) - (ri.x & 0xFFFF)) * ((ri.y >> 16) - (ri.y & 0xFFFF));
-            cnt = I != 0.0f ? area : 0u;
-            cnt_i[r] = cnt;
+            // the imaging-plane pair count of each 256 records (four groups)
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1) cnt += __shfl_xor(cnt, d, WAVE);
+            quarter += cnt;
+            const int64_t b0 = wave0 + (g & ~3) * WAVE;
+            if ((g & 3) == 3) {
+                if (lane == 0 && b0 < records) bsum_i[b0 / 256] = quarter;
+                quarter = 0;
+            }
         }
     }
-    if (cnt_i) {   // the block's imaging-plane pair count (the emission scans within)
-        uint32_t tot;
-        (void)block_excl_scan_256(cnt, s_w, tot);
-        if (threadIdx.x == 0) bsum_i[blockIdx.x] = tot;
+    // one counter update per block: the list is filled in runs, not per wave
+    if (lane == 0) s_cnt[w] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        s_base = tot ? atomicAdd(&status[ST_ACTIVE], tot) : 0u;
+    }
+    __syncthreads();
+    uint32_t o = s_base;
+    for (int k = 0; k < w; ++k) o += s_cnt[k];
+    const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int g = 0; g < INT_GROUPS; ++g) {
+        if (m[g] >> lane & 1ull)
+            active[o + (uint32_t)__popcll(m[g] & below)] = (uint32_t)(wave0 + g * WAVE + lane);
+        o += (uint32_t)__popcll(m[g]);
     }
 }
 
@@ -492,11 +535,12 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
                                 int64_t records, const float* A, float2* iw,
                                 const uint2* rect_i, uint32_t* cnt_i, uint32_t* bsum_i,
-                                hipStream_t s)
+                                uint32_t* status, uint32_t* active, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_set_intensity, dim3(blocks_for(records, 256)), dim3(256), 0, s, views,
-                       scenes, nv, records, A, iw, rect_i, cnt_i, bsum_i);
+    hipLaunchKernelGGL(k_set_intensity, dim3(blocks_for(records, 4 * INT_GROUPS * WAVE)),
+                       dim3(256), 0, s, views, scenes, nv, records, A, iw, rect_i, cnt_i, bsum_i,
+                       status, active);
     return hipGetLastError();
 }
 

@@ -722,64 +722,18 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64
     }
 }
 
-// Records pass A used (A > 0; every used record gets at least FLT_MIN), in
-// index order within each block's 4096 records (blocks in any order), with
-// their computation-plane gradient sums cleared.
-// A record with A = 0 has I = P A = 0 and took part in no ray's
-// compositing, so all of its gradients are zero: the backward passes and
-// the parameter adjoint skip it. The count goes to status[ST_ACTIVE].
-constexpr int ACTIVE_GROUPS = 16;   // 64-record groups per wave: 4096 records per block
-
-__global__ void __launch_bounds__(256)
-k_active_records(int64_t records, const float* __restrict__ A, uint32_t* __restrict__ status,
-                 uint32_t* __restrict__ active, float* __restrict__ grad_c)
-{
-    __shared__ uint32_t s_cnt[4];
-    __shared__ uint32_t s_base;
-    const int lane = lane_id(), w = threadIdx.x / WAVE;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + w) * (ACTIVE_GROUPS * WAVE) + lane;
-    uint64_t m[ACTIVE_GROUPS];
-    uint32_t n = 0;
-#pragma unroll
-    for (int g = 0; g < ACTIVE_GROUPS; ++g) {
-        const int64_t r = r0 + g * WAVE;
-        m[g] = __ballot(r < records && A[r] != 0.0f);
-        n += (uint32_t)__popcll(m[g]);
-    }
-    // one counter update per block: the list is filled in runs, not per wave
-    if (lane == 0) s_cnt[w] = n;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t tot = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-        s_base = tot ? atomicAdd(&status[ST_ACTIVE], tot) : 0u;
-    }
-    __syncthreads();
-    uint32_t o = s_base;
-    for (int k = 0; k < w; ++k) o += s_cnt[k];
-    const uint64_t below = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int g = 0; g < ACTIVE_GROUPS; ++g) {
-        if (m[g] >> lane & 1ull) {
-            const int64_t r = r0 + g * WAVE;
-            active[o + (uint32_t)__popcll(m[g] & below)] = (uint32_t)r;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) grad_c[k * records + r] = 0.0f;
-        }
-        o += (uint32_t)__popcll(m[g]);
-    }
-}
-
 // Imaging-plane backward, one thread per used record (view, Gaussian): the
 // additive image formation has no order, so each thread walks its own
 // footprint ellipse q < q_max row by row (exact column span from the conic,
 // widened by one pixel), gathers dL/dS there and keeps dL/dI and the centre
-// and conic gradients in registers -- no atomics, no tile list.
+// and conic gradients in registers -- no atomics, no tile list. It also
+// clears the record's computation-plane gradient sums for pass A.
 __global__ void __launch_bounds__(256)
 k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
             int64_t records, RasterParams rp, const uint32_t* __restrict__ status,
             const uint32_t* __restrict__ active, const float4* __restrict__ iq,
             const float2* __restrict__ iw, const float* __restrict__ dimg,
-            float* __restrict__ grad_i, float* __restrict__ cbwd)
+            float* __restrict__ grad_i, float* __restrict__ cbwd, float* __restrict__ grad_c)
 {
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if ((int64_t)blockIdx.x * blockDim.x >= (int64_t)status[ST_ACTIVE]) return;
@@ -832,6 +786,9 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
     grad_i[4 * records + r] = dc;
     grad_i[5 * records + r] = dI;
     cbwd[r] = scenes[V.scene].amp[r - V.rec_off] * dI;   // c = P dL/dI for pass A
+    // pass A backward adds into the record's computation-plane sums
+#pragma unroll
+    for (int k = 0; k < 6; ++k) grad_c[k * records + r] = 0.0f;
     }
     if (rp.work) {   // one atomic per wave
 #pragma unroll
@@ -1255,24 +1212,15 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
     return hipGetLastError();
 }
 
-hipError_t launch_active_records(int64_t records, const float* A, uint32_t* status,
-                                 uint32_t* active, float* grad_c, hipStream_t s)
-{
-    if (records <= 0) return hipSuccess;
-    const int64_t blocks = (records + 4 * ACTIVE_GROUPS * WAVE - 1) / (4 * ACTIVE_GROUPS * WAVE);
-    hipLaunchKernelGGL(k_active_records, dim3((unsigned)blocks), dim3(256), 0, s, records, A,
-                       status, active, grad_c);
-    return hipGetLastError();
-}
-
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
                             int64_t records, const RasterParams& rp, const uint32_t* status,
                             const uint32_t* active, const float4* iq, const float2* iw,
-                            const float* dimg, float* grad_i, float* cbwd, hipStream_t s)
+                            const float* dimg, float* grad_i, float* cbwd, float* grad_c,
+                            hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_image_bwd, dim3(grid256(records)), dim3(256), 0, s, views, scenes, nv,
-                       records, rp, status, active, iq, iw, dimg, grad_i, cbwd);
+                       records, rp, status, active, iq, iw, dimg, grad_i, cbwd, grad_c);
     return hipGetLastError();
 }
 
