@@ -426,7 +426,8 @@ int final_buffer_i(const Problem& P) { return radix_passes_for(bits_pairs_i(P)) 
 // Projection, depth sort and the computation-plane lists: binning, the
 // stable bucket sort, tile ranges, footprint masks and the tile worklist
 // (shared by the forward and the recomputing backward).
-int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStream_t s)
+int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool zero_A,
+                  hipStream_t s)
 {
     const int64_t R = P.records;
     // list-building words only: the work counters and the imaging-plane pair
@@ -438,7 +439,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
         StageTimer t(SG_PREPROCESS, s);
         SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, true, b.cq, b.cw, b.iq,
                                    b.iw, b.rect_c, b.rect_i, b.dkey[0],
-                                   b.slots,
+                                   zero_A ? b.A : nullptr, b.slots,
                                    reinterpret_cast<unsigned long long*>(b.status + ST_COUNT),
                                    s));
     }
@@ -455,7 +456,8 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
             SDGR_HIP(launch_seg_setup(b.views, P.nv, R, b.status + ST_RECORDS, false, &b.segt[0],
                                       s));
         SDGR_HIP(launch_radix_sort_u32(dk, dv, R, b.status + ST_RECORDS, 32, true, b.hist,
-                                       &which, s, 0, P.seg ? &b.segt[0] : nullptr, P.nv));
+                                       &which, s, 0, P.seg ? &b.segt[0] : nullptr, P.nv,
+                                       false));
     }
     uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};
@@ -567,7 +569,8 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
     {
         StageTimer t(SG_QUERY, s);
         SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.ns, P.items, P.rp, false, nullptr,
-                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, slots,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   slots,
                                    totals, s));
     }
     unsigned long long host_tot[2] = {0, 0};
@@ -639,9 +642,9 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     if ((rc = upload_tables(P, b, s, state, true))) return rc;
     SDGR_HIP(launch_fill_u32(b.status + ST_PAIRS_I, 0u, 1, s));
     SDGR_HIP(launch_fill_u32(b.status + WORK_WORD, 0u, STATUS_WORDS - WORK_WORD, s));
-    if ((rc = build_lists_c(P, plan, b, s))) return rc;
+    // the projection also clears A for pass A's sums
+    if ((rc = build_lists_c(P, plan, b, true, s))) return rc;
     const int pw = final_buffer_c(P);
-    SDGR_HIP(launch_fill_u32((uint32_t*)b.A, 0u, P.records, s));
     SDGR_HIP(launch_fill_u32((uint32_t*)b.tau, 0u, P.rays, s));   // rays of empty tiles
     SDGR_HIP(launch_fill_u32(b.nlast, 0u, P.rays, s));
     {
@@ -697,7 +700,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     if (P.recompute) {
         // the forward's lists are gone: rebuild them (identical, the sorts
         // are deterministic) and refill the intensities from the kept A
-        if ((rc = build_lists_c(P, plan, b, s))) return rc;
+        if ((rc = build_lists_c(P, plan, b, false, s))) return rc;
         SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, nullptr,
                                       nullptr, nullptr, b.status, b.active, s));
     }

@@ -235,8 +235,8 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
                              int64_t items, const RasterParams& rp,
                              bool write_records, float4* cq, float2* cw, float4* iq,
                              float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* dkey,
-                             unsigned long long* slots, unsigned long long* totals,
-                             hipStream_t s);
+                             float* A_zero, unsigned long long* slots,
+                             unsigned long long* totals, hipStream_t s);
 
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
                                 int64_t records, const float* A, float2* iw,
@@ -261,11 +261,13 @@ size_t radix_hist_words(int64_t cap);
 int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
 // Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
 // n_dev items (at most cap); iota_vals: the input values are the positions
-// 0..n-1 and vals[0] is not read. *which: the buffer holding the result.
+// 0..n-1 and vals[0] is not read. *which: the buffer holding the result
+// (with keys_out false only the values are valid there).
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  int* which, hipStream_t s, int shift0 = 0,
-                                 const SegTable* segt = nullptr, int S = 0);
+                                 const SegTable* segt = nullptr, int S = 0,
+                                 bool keys_out = true);
 // Segment table of a segmented sort over the views: records (pairs = false)
 // or computation-plane pairs (pairs = true; seg[] as the emission wrote it),
 // n_dev items in all.

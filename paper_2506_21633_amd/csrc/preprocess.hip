@@ -172,7 +172,8 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
              int nscenes, int64_t items, RasterParams rp, int write_records,
              float4* __restrict__ cq, float2* __restrict__ cw, float4* __restrict__ iq,
              float2* __restrict__ iw, uint2* __restrict__ rect_c, uint2* __restrict__ rect_i,
-             uint32_t* __restrict__ dkey, unsigned long long* __restrict__ totals)
+             uint32_t* __restrict__ dkey, float* __restrict__ A_zero,
+             unsigned long long* __restrict__ totals)
 {
     __shared__ unsigned long long part[2];
     if (threadIdx.x < 2) part[threadIdx.x] = 0;
@@ -248,6 +249,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
                 rect_c[r] = rc;
                 rect_i[r] = ri;
                 dkey[r] = float_order_bits(__uint_as_float(zbits));
+                if (A_zero) A_zero[r] = 0.0f;   // pass A adds the shares
             }
         }
     }
@@ -517,9 +519,9 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int n)
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv, int nscenes,
                              int64_t items, const RasterParams& rp, bool write_records,
                              float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
-                             uint2* rect_i, uint32_t* dkey,
-                             unsigned long long* slots,
-                             unsigned long long* totals, hipStream_t s)
+                             uint2* rect_i, uint32_t* dkey, float* A_zero,
+                             unsigned long long* slots, unsigned long long* totals,
+                             hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(2 * TOTAL_SLOTS / 256), dim3(256), 0, s, slots,
                        2 * TOTAL_SLOTS);
@@ -527,7 +529,8 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
         hipLaunchKernelGGL(k_preprocess,
                            dim3(blocks_for(items, 256), (unsigned)((nv + PRE_VIEWS - 1) / PRE_VIEWS)),
                            dim3(256), 0, s, views, scenes, nv, nscenes, items, rp,
-                           write_records ? 1 : 0, cq, cw, iq, iw, rect_c, rect_i, dkey, slots);
+                           write_records ? 1 : 0, cq, cw, iq, iw, rect_c, rect_i, dkey,
+                           write_records ? A_zero : nullptr, slots);
     hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(TOTAL_SLOTS), 0, s, slots, totals);
     return hipGetLastError();
 }

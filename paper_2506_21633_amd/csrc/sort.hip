@@ -444,7 +444,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
         for (uint32_t i = tid; i < cnt_blk; i += SB) {
             const uint32_t k = s_key[i];
             const uint32_t g = gbase[((k - bi.kb) >> shift) & (R - 1)] + i;
-            kout[g] = k;
+            if (kout) kout[g] = k;
             vout[g] = s_val[i];
         }
     }
@@ -460,7 +460,7 @@ inline unsigned pass_grid(int64_t cap, int S, bool seg)
 template <int BITS, bool SEG>
 hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
-                        int shift0, const SegTable* segt, int S)
+                        int shift0, const SegTable* segt, int S, bool keys_out)
 {
     constexpr int R = 1 << BITS;
     const unsigned grid = pass_grid(cap, S, SEG);
@@ -471,9 +471,11 @@ hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const
         hipLaunchKernelGGL(k_radix_spine, dim3(R), dim3(SB), 0, s, hist, tot, n_dev, grid,
                            SEG ? segt : nullptr, S);
         const uint32_t* vin = (iota_vals && shift == shift0) ? nullptr : vals[*cur];
+        // the last pass writes no keys when the caller needs only the values
+        uint32_t* kout = (keys_out || shift + BITS < shift0 + bits) ? keys[*cur ^ 1] : nullptr;
         hipLaunchKernelGGL((k_radix_scatter<BITS, SEG>), dim3(grid), dim3(SB), 0, s,
-                           keys[*cur], vin, keys[*cur ^ 1], vals[*cur ^ 1], n_dev, shift, hist,
-                           tot, segt, S);
+                           keys[*cur], vin, kout, vals[*cur ^ 1], n_dev, shift, hist, tot, segt,
+                           S);
         *cur ^= 1;
     }
     return hipGetLastError();
@@ -482,24 +484,24 @@ hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const
 template <bool SEG>
 hipError_t radix_sort_t(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
-                        int shift0, const SegTable* segt, int S)
+                        int shift0, const SegTable* segt, int S, bool keys_out)
 {
     switch (digit_bits(bits)) {
     case 8:
         return radix_passes<8, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
-                                    segt, S);
+                                    segt, S, keys_out);
     case 9:
         return radix_passes<9, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
-                                    segt, S);
+                                    segt, S, keys_out);
     default:
         return radix_passes<10, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s,
-                                     shift0, segt, S);
+                                     shift0, segt, S, keys_out);
     }
 }
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                       int bits, bool iota_vals, uint32_t* hist, int* which, hipStream_t s,
-                      int shift0, const SegTable* segt, int S)
+                      int shift0, const SegTable* segt, int S, bool keys_out)
 {
     int cur = 0;
     *which = 0;
@@ -507,9 +509,9 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
     if (segt && (S < 1 || S > SEG_MAX)) return hipErrorInvalidValue;
     const hipError_t e =
         segt ? radix_sort_t<true>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
-                                  segt, S)
+                                  segt, S, keys_out)
              : radix_sort_t<false>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
-                                   nullptr, 0);
+                                   nullptr, 0, keys_out);
     *which = cur;
     return e;
 }
@@ -876,9 +878,10 @@ int radix_passes_for(int bits)
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  int* which, hipStream_t s, int shift0, const SegTable* segt,
-                                 int S)
+                                 int S, bool keys_out)
 {
-    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s, shift0, segt, S);
+    return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s, shift0, segt, S,
+                      keys_out);
 }
 
 hipError_t launch_seg_setup(const DevView* views, int nv, int64_t records, const uint32_t* n_dev,
