@@ -309,6 +309,10 @@ k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ 
     const int64_t wave0 = ((int64_t)blockIdx.x * 4 + w) * (INT_GROUPS * WAVE);
     uint64_t m[INT_GROUPS];
     uint32_t n = 0, quarter = 0;
+    // the wave's records mostly lie in one view: look it up once
+    const int v0 = wave0 < records ? find_view(nv, wave0, [&](int k) { return views[k].rec_off; })
+                                   : 0;
+    const int64_t v0_end = v0 + 1 < nv ? views[v0 + 1].rec_off : records;
 #pragma unroll
     for (int g = 0; g < INT_GROUPS; ++g) {
         const int64_t r = wave0 + g * WAVE + lane;
@@ -316,7 +320,8 @@ k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ 
         uint32_t cnt = 0u;
         if (r < records) {
             a = A[r];
-            const int v = find_view(nv, r, [&](int k) { return views[k].rec_off; });
+            const int v = r < v0_end ? v0
+                                     : find_view(nv, r, [&](int k) { return views[k].rec_off; });
             const DevView& V = views[v];
             const float I = scenes[V.scene].amp[r - V.rec_off] * a;
             iw[r].y = I;

@@ -557,7 +557,8 @@ k_gather_rects(const uint32_t* __restrict__ order, const uint2* __restrict__ rec
 
 // Exclusive scan in place of the per-block counts, one workgroup walking
 // them 8192 at a time with a running carry (coalesced loads and stores
-// through LDS, each thread scanning 8 consecutive counts); the total
+// through LDS, each thread scanning 8 consecutive counts, the next 8192
+// loading meanwhile); the total
 // optionally becomes a pair count in status (0 and the overflow flag when
 // above the capacity).
 __global__ void __launch_bounds__(1024)
@@ -571,13 +572,21 @@ k_scan_blocks(uint32_t* __restrict__ a, int64_t n, int64_t cap, uint32_t* __rest
     auto pad = [](int k) { return k + (k >> 5); };
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
     if (tid == 0) s_carry = 0ull;
-    for (int64_t base = 0; base < n; base += CH) {
+    // the next chunk's counts load while this one is scanned and written
+    uint32_t nx[ITEMS];
+    auto load = [&](int64_t base) {
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
             const int64_t idx = base + k * NT + tid;
-            s_v[pad(k * NT + tid)] = idx < n ? a[idx] : 0u;
+            nx[k] = idx < n ? a[idx] : 0u;
         }
+    };
+    load(0);
+    for (int64_t base = 0; base < n; base += CH) {
+#pragma unroll
+        for (int k = 0; k < ITEMS; ++k) s_v[pad(k * NT + tid)] = nx[k];
         __syncthreads();
+        if (base + CH < n) load(base + CH);
         uint32_t v[ITEMS], sum = 0u;
 #pragma unroll
         for (int k = 0; k < ITEMS; ++k) {
