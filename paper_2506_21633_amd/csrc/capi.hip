@@ -455,10 +455,9 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool z
         if (P.seg)
             SDGR_HIP(launch_seg_setup(b.views, P.nv, R, b.status + ST_RECORDS, false, &b.segt[0],
                                       s));
-        // (the three low bytes of fl32 depth keys are well spread digits)
         SDGR_HIP(launch_radix_sort_u32(dk, dv, R, b.status + ST_RECORDS, 32, true, b.hist,
                                        &which, s, 0, P.seg ? &b.segt[0] : nullptr, P.nv,
-                                       false, 24));
+                                       false));
     }
     uint32_t* pk[2] = {b.pkey[0], b.pkey[1]};
     uint32_t* pv[2] = {b.pval[0], b.pval[1]};

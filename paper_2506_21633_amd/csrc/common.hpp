@@ -262,13 +262,12 @@ int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
 // Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
 // n_dev items (at most cap); iota_vals: the input values are the positions
 // 0..n-1 and vals[0] is not read. *which: the buffer holding the result
-// (with keys_out false only the values are valid there). Digits entirely
-// below bit spread_bits are taken to be well spread over their range.
+// (with keys_out false only the values are valid there).
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  int* which, hipStream_t s, int shift0 = 0,
                                  const SegTable* segt = nullptr, int S = 0,
-                                 bool keys_out = true, int spread_bits = 0);
+                                 bool keys_out = true);
 // Segment table of a segmented sort over the views: records (pairs = false)
 // or computation-plane pairs (pairs = true; seg[] as the emission wrote it),
 // n_dev items in all.

@@ -171,16 +171,14 @@ k_seg_setup(const DevView* __restrict__ views, int nv, int64_t records,
     }
 }
 
-// Block digit histogram over the block's tiles. Keys are often long runs of
-// one digit (pair keys are tile ids of a few busy tiles), so each wave first
-// groups its lanes by digit (ballot match over the digit bits) and only one
-// lane per digit adds the group's count: same-address LDS atomics would
-// serialise 64-fold. Digits the caller knows to be well spread (the low
-// bytes of depth keys) are counted with one LDS atomic per item.
+// Block digit histogram over the block's tiles, one LDS atomic per item.
+// (Grouping a wave's lanes by digit first, with a ballot match over the
+// digit bits, was slower for every key set here, the pair keys of a few busy
+// tiles included.)
 template <int BITS, bool SEG>
 __global__ void __launch_bounds__(SB)
 k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev, int shift,
-             uint32_t* __restrict__ hist, const SegTable* __restrict__ segt, int S, int direct)
+             uint32_t* __restrict__ hist, const SegTable* __restrict__ segt, int S)
 {
     constexpr int R = 1 << BITS;
     __shared__ uint32_t h[R];
@@ -191,12 +189,11 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
     } else {
         if (!span_items(n_dev, bi)) return;
     }
-    const int tid = threadIdx.x, lane = tid & (WAVE - 1);
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int d = tid; d < R; d += SB) h[d] = 0;
     __syncthreads();
     const int64_t n = bi.end;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
     for (uint32_t t = 0; t < bi.tiles; ++t) {
         const int64_t base = bi.first + (int64_t)t * SN;
         if (base >= n) break;
@@ -209,19 +206,7 @@ k_radix_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_d
 #pragma unroll
         for (int k = 0; k < SI; ++k) {
             const int64_t idx = base + k * SB + tid;
-            const bool valid = idx < n;
-            const uint32_t d = ((key[k] - bi.kb) >> shift) & (R - 1);
-            if (direct) {   // well-spread digits: few lanes share an address
-                if (valid) atomicAdd(&h[d], 1u);
-                continue;
-            }
-            uint64_t m = __ballot(valid);
-#pragma unroll
-            for (int b = 0; b < BITS; ++b) {
-                const uint64_t bb = __ballot((d >> b) & 1u);
-                m &= ((d >> b) & 1u) ? bb : ~bb;
-            }
-            if (valid && (m & below) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(m));
+            if (idx < n) atomicAdd(&h[((key[k] - bi.kb) >> shift) & (R - 1)], 1u);
         }
     }
     __syncthreads();
@@ -465,14 +450,14 @@ inline unsigned pass_grid(int64_t cap, int S, bool seg)
 template <int BITS, bool SEG>
 hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
-                        int shift0, const SegTable* segt, int S, bool keys_out, int spread_bits)
+                        int shift0, const SegTable* segt, int S, bool keys_out)
 {
     constexpr int R = 1 << BITS;
     const unsigned grid = pass_grid(cap, S, SEG);
     uint32_t* tot = hist + (int64_t)MAX_RADIX * grid;   // digit totals after the counts
     for (int shift = shift0; shift < shift0 + bits; shift += BITS) {
         hipLaunchKernelGGL((k_radix_hist<BITS, SEG>), dim3(grid), dim3(SB), 0, s, keys[*cur],
-                           n_dev, shift, hist, segt, S, shift + BITS <= spread_bits ? 1 : 0);
+                           n_dev, shift, hist, segt, S);
         hipLaunchKernelGGL(k_radix_spine, dim3(R), dim3(SB), 0, s, hist, tot, n_dev, grid,
                            SEG ? segt : nullptr, S);
         const uint32_t* vin = (iota_vals && shift == shift0) ? nullptr : vals[*cur];
@@ -489,24 +474,24 @@ hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const
 template <bool SEG>
 hipError_t radix_sort_t(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
-                        int shift0, const SegTable* segt, int S, bool keys_out, int spread_bits)
+                        int shift0, const SegTable* segt, int S, bool keys_out)
 {
     switch (digit_bits(bits)) {
     case 8:
         return radix_passes<8, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
-                                    segt, S, keys_out, spread_bits);
+                                    segt, S, keys_out);
     case 9:
         return radix_passes<9, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
-                                    segt, S, keys_out, spread_bits);
+                                    segt, S, keys_out);
     default:
         return radix_passes<10, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s,
-                                     shift0, segt, S, keys_out, spread_bits);
+                                     shift0, segt, S, keys_out);
     }
 }
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                       int bits, bool iota_vals, uint32_t* hist, int* which, hipStream_t s,
-                      int shift0, const SegTable* segt, int S, bool keys_out, int spread_bits)
+                      int shift0, const SegTable* segt, int S, bool keys_out)
 {
     int cur = 0;
     *which = 0;
@@ -514,9 +499,9 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
     if (segt && (S < 1 || S > SEG_MAX)) return hipErrorInvalidValue;
     const hipError_t e =
         segt ? radix_sort_t<true>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
-                                  segt, S, keys_out, spread_bits)
+                                  segt, S, keys_out)
              : radix_sort_t<false>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
-                                   nullptr, 0, keys_out, spread_bits);
+                                   nullptr, 0, keys_out);
     *which = cur;
     return e;
 }
@@ -892,10 +877,10 @@ int radix_passes_for(int bits)
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  int* which, hipStream_t s, int shift0, const SegTable* segt,
-                                 int S, bool keys_out, int spread_bits)
+                                 int S, bool keys_out)
 {
     return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s, shift0, segt, S,
-                      keys_out, spread_bits);
+                      keys_out);
 }
 
 hipError_t launch_seg_setup(const DevView* views, int nv, int64_t records, const uint32_t* n_dev,
