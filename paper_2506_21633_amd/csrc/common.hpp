@@ -202,7 +202,9 @@ __device__ inline uint64_t footprint_mask(float cx, float cy, float a, float b, 
     const float slack = 1e-3f;
     const float ia = __builtin_amdgcn_rcpf(a);
     const float aq = a * qm, dmin = -1e-4f * aq;
-    uint64_t m = 0ull;
+    // rows 0-3 and 4-7 in two 32-bit words, each row's cells j0..j1 as 8
+    // bits without a branch (none when the row is out of reach)
+    uint32_t m[2] = {0u, 0u};
     const float x0 = (float)(tx * TILE) + 0.5f;
 #pragma unroll
     for (int k = 0; k < TILE; ++k) {
@@ -213,12 +215,12 @@ __device__ inline uint64_t footprint_mask(float cx, float cy, float a, float b, 
         // local columns j with |x0 + j - xc| <= half
         const float lo = fmaxf(ceilf(xc - half - x0), 0.0f);
         const float hi = fminf(floorf(xc + half - x0), (float)(TILE - 1));
-        if (D < dmin || lo > hi) continue;
-        const uint32_t j0 = (uint32_t)lo, j1 = (uint32_t)hi;
-        const uint64_t row_bits = ((1ull << (j1 - j0 + 1)) - 1ull) << j0;
-        m |= row_bits << (TILE * k);
+        const bool reach = !(D < dmin) && lo <= hi;
+        const uint32_t j0 = reach ? (uint32_t)lo : 8u, j1 = reach ? (uint32_t)hi : 0u;
+        const uint32_t row = (0xFFu << j0) & (0xFFu >> (7u - j1)) & 0xFFu;
+        m[k >> 2] |= row << (TILE * (k & 3));
     }
-    return m;
+    return ((uint64_t)m[1] << 32) | m[0];
 }
 
 
