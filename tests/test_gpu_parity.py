@@ -161,6 +161,41 @@ def test_more_views_than_view_major_keys(cuda):
     check_grads(sc, views, G, out)
 
 
+def test_views_of_an_empty_scene_between_others(cuda):
+    """Several scenes in one launch, with views of an empty scene between
+    views of non-empty ones: the per-view segments of the depth and pair
+    sorts include empty ones."""
+    A_ = api()
+    sc = [_small_scene(20, n=200),
+          scenes.Scene(*(np.zeros((0,) + s, np.float32) for s in ((3,), (3,), (4,), (), ()))),
+          _small_scene(21, n=150, half=1.0)]
+    which = [0, 1, 1, 2, 1, 0, 2]
+    views = [scenes.View.from_degrees(25.0 * k, 35.0 + 2 * k, 32 + 4 * (k % 2), 0.1, scene=s)
+             for k, s in enumerate(which)]
+    rng = scenes.make_rng(22)
+    G = [rng.standard_normal((v.img_h, v.img_w)) for v in views]
+    r = A_.Renderer([A_.GaussianTensors.from_numpy(x, cuda) for x in sc], views)
+    res = r.forward()
+    flat = np.concatenate([g.astype(np.float32).ravel() for g in G])
+    grads = r.backward(res, torch.as_tensor(flat, device=cuda))
+    torch.cuda.synchronize()
+    r.status(res)
+    for k, v in enumerate(views):
+        img = res.image(k).cpu().numpy()
+        if which[k] == 1:
+            assert np.all(img == 0)
+            continue
+        S_ref = oracle.forward_view(sc[which[k]], v)[2]
+        assert img_err(img, S_ref) <= IMG_TOL, k
+    for s in (0, 2):
+        vs = [v for v in views if v.scene == s]
+        gs = [G[k] for k, v in enumerate(views) if v.scene == s]
+        ref, _ = oracle.backward(sc[s], vs, gs)
+        for k in GROUPS:
+            g = grads[s][k].cpu().numpy()
+            assert cosine(g, ref[k]) >= GRAD_COS and rel_l2(g, ref[k]) <= GRAD_L2, (s, k)
+
+
 def test_permutation_invariance(cuda):
     sc = _small_scene(11, n=400)
     views = scenes.vehicle_views(48, 0.1, count=3, step=40.0)
