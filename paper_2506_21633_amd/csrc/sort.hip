@@ -723,6 +723,7 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
     uint32_t tot;
     const uint32_t ex = block_excl_scan_256((tx1 - tx0) * (ty1 - ty0), s_w, tot);
     if (p >= records) return;
+    int vp = -1;   // the view of position p, when the order is view-major
     if (seg && cached) {
         // view-major order (segmented depth sort): the first record of each
         // view marks where the view's pairs start
@@ -732,13 +733,17 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
             if (s_off[mid] <= p) lo = mid; else hi = mid - 1;
         }
         if (s_off[lo] == p) seg[lo] = bscan[blockIdx.x] + ex;
+        vp = lo;
     }
     const uint32_t kc = status[ST_PAIRS_C];
     if (status[ST_OVERFLOW]) return;
     if (tx0 >= tx1 || ty0 >= ty1) return;
     const uint32_t r = dval[p];
     uint32_t tile0, txc;
-    if (cached) {
+    if (vp >= 0) {   // the record at p is one of that view's
+        tile0 = (uint32_t)s_tile[vp];
+        txc = (uint32_t)s_tx[vp];
+    } else if (cached) {
         int lo = 0, hi = nv - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
