@@ -633,7 +633,8 @@ __global__ void k_pair_total_c(int64_t cap_c, uint32_t* status)
 
 
 // View of a record through a copy of the view offsets in LDS (records in
-// depth order come from all views at random).
+// depth order come from all views at random unless the depth sort was
+// segmented by view).
 constexpr int LDS_VIEWS = 512;
 
 // Pair writes of one wave's records (imaging plane: few records have pairs,
