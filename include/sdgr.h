@@ -230,11 +230,16 @@ const char* sdgr_profile_stage(int32_t i);
  * the footprint (q < q_max) of pass A forward, pass A backward, pass B
  * forward and pass B backward (out[0..3]), the rounds of 64 evaluations
  * (pass A forward and backward) or 64 list entries (pass B forward) a wave
- * ran (out[4..6]), and the summed length of the tile-list prefixes some ray
- * of pass A used (out[7]); the counting adds atomics, so timed runs leave it
- * off.
- * sdgr_read_work synchronises `stream` and copies min(n, 8) counters of the
- * last forward (and backward) that used `state`. */
+ * ran (out[4..6]), the summed length of the tile-list prefixes some ray
+ * of pass A used (out[7]), the most batches of list chunks one computation-
+ * plane tile read in pass A forward and backward (out[8], out[9]), the
+ * batches whose footprint hits did not fit one compaction round, counted
+ * once per extra group, in pass A forward and backward (out[10], out[11]),
+ * the rays stopped at tau_max (out[12]) and the longest list prefix one
+ * tile used (out[13]); out[14..15] are 0. The counting adds atomics, so
+ * timed runs leave it off.
+ * sdgr_read_work synchronises `stream` and copies min(n, 16) counters of
+ * the last forward (and backward) that used `state`. */
 int sdgr_profile_count(int32_t on);
 int sdgr_read_work(const sdgr_plan* plan, const void* state, uint64_t* out, int32_t n,
                    void* stream);

@@ -69,6 +69,10 @@ def lib():
                                          ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int, _i64, _ip, _dp, _i64,
                                          _ip, _dp]
+        L.orc_fd_linear.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, _dp,
+                                    ctypes.c_double, ctypes.c_double,
+                                    ctypes.c_int, _dp, _i64, ctypes.c_int,
+                                    ctypes.c_double, _dp]
         _lib = L
     return _lib
 
@@ -189,6 +193,30 @@ def sparse_forward(scene, view, pix_ids, gids, q_max=Q_MAX, dilation=0.0,
                                 gid.ctypes.data_as(_ip), _p(A)):
         raise ValueError("invalid arguments")
     return S, A
+
+
+# parameter components of one Gaussian, in the order orc_fd_linear numbers them
+FD_COMPONENTS = [("means", 0), ("means", 1), ("means", 2), ("scales", 0),
+                 ("scales", 1), ("scales", 2), ("quats", 0), ("quats", 1),
+                 ("quats", 2), ("quats", 3), ("amp", None), ("ext", None)]
+
+
+def fd_linear(scene, view, V, k, comp, h, q_max=Q_MAX, dilation=0.0,
+              shadowing=True):
+    """Central difference of L = <V, S> for one view when component `comp`
+    (see FD_COMPONENTS) of Gaussian k moves by +h and -h, recomputing exactly
+    only the rays and pixels the change reaches. Returns
+    (L(+h) - L(-h), order_changed)."""
+    m, s, q, a, e = _params(scene)
+    n = m.shape[0]
+    Vd = _d(V)
+    out = np.zeros(2)
+    if lib().orc_fd_linear(n, _p(m), _p(s), _p(q), _p(a), _p(e),
+                           _p(view_params(view)), q_max, dilation,
+                           int(bool(shadowing)), _p(Vd), int(k), int(comp),
+                           float(h), _p(out)):
+        raise ValueError("invalid arguments")
+    return float(out[0]), bool(out[1])
 
 
 def threads() -> int:

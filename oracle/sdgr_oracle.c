@@ -466,7 +466,10 @@ static void cov_to_params(const OG* g, const double* dSig, double* ds, double* d
  * aux (may be NULL) receives 16 doubles per Gaussian:
  *   [0] A  [1] dL/dI  [2..3] dL/dcI  [4..6] dL/dconic_I (a,b,c)
  *   [7..8] dL/dcC  [9..11] dL/dconic_C  [12] dL/dkappa  [13] dL/dA (= c)
- *   [14..15] unused */
+ *   [14], [15] the smallest |q - q_max| over the Gaussian's imaging-plane
+ *   pixels and computation-plane cells (how close a cell comes to the
+ *   footprint's cutoff, where the footprint is 0 but its derivative is not;
+ *   inf for an invalid Gaussian) */
 int orc_backward(int64_t n, const double* means, const double* scales,
                  const double* quats, const double* amp, const double* ext,
                  const double* view, double q_max, double dil, int shadowing,
@@ -491,9 +494,13 @@ int orc_backward(int64_t n, const double* means, const double* scales,
     double* gt = (double*)calloc((size_t)nt * (size_t)(n > 0 ? n : 1) * 6, sizeof(double));
     if (!G || !g2 || !gt) { free(A); free(G); free(g2); free(gt); return -2; }
 
+    /* distance of the nearest cell to the footprint cutoff, both planes */
+    double* edge = (double*)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
+    if (!edge) { free(A); free(G); free(g2); free(gt); return -2; }
     /* imaging plane: every Gaussian against every pixel */
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n; ++i) {
+        edge[2 * i] = edge[2 * i + 1] = INFINITY;
         if (!G[i].valid) continue;
         double I = amp[i] * A[i];
         double* o = g2 + 12 * i;
@@ -501,6 +508,7 @@ int orc_backward(int64_t n, const double* means, const double* scales,
             double dx = (double)(p % v.W) + 0.5 - G[i].cI[0];
             double dy = (double)(p / v.W) + 0.5 - G[i].cI[1];
             double q = quadform(G[i].QI, dx, dy);
+            if (fabs(q - q_max) < edge[2 * i]) edge[2 * i] = fabs(q - q_max);
             if (!(q < q_max)) continue;
             double Gp = Gimg[p];
             o[0] += Gp * foot(q, q_max);
@@ -557,6 +565,23 @@ int orc_backward(int64_t n, const double* means, const double* scales,
             for (int k = 0; k < 6; ++k)
                 g2[12 * i + 6 + k] += gt[((size_t)th * (size_t)n + (size_t)i) * 6 + k];
     free(gt);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!G[i].valid) continue;
+        const double* b = G[i].bxC;
+        int64_t c0 = (int64_t)floor(b[0] - 0.5) - 1, c1 = (int64_t)ceil(b[1] - 0.5) + 1;
+        int64_t r0 = (int64_t)floor(b[2] - 0.5) - 1, r1 = (int64_t)ceil(b[3] - 0.5) + 1;
+        if (c0 < 0) c0 = 0;
+        if (r0 < 0) r0 = 0;
+        if (c1 > v.Wc - 1) c1 = v.Wc - 1;
+        if (r1 > v.Hc - 1) r1 = v.Hc - 1;
+        for (int64_t r = r0; r <= r1; ++r)
+            for (int64_t c = c0; c <= c1; ++c) {
+                double q = quadform(G[i].QC, (double)c + 0.5 - G[i].cC[0],
+                                    (double)r + 0.5 - G[i].cC[1]);
+                if (fabs(q - q_max) < edge[2 * i + 1]) edge[2 * i + 1] = fabs(q - q_max);
+            }
+    }
 
     /* parameters */
 #pragma omp parallel for schedule(static)
@@ -573,7 +598,8 @@ int orc_backward(int64_t n, const double* means, const double* scales,
             a[0] = A[i]; a[1] = o[0];
             a[2] = o[1]; a[3] = o[2]; a[4] = o[3]; a[5] = o[4]; a[6] = o[5];
             a[7] = o[7]; a[8] = o[8]; a[9] = o[9]; a[10] = o[10]; a[11] = o[11];
-            a[12] = o[6]; a[13] = amp[i] * o[0]; a[14] = a[15] = 0.0;
+            a[12] = o[6]; a[13] = amp[i] * o[0];
+            a[14] = edge[2 * i]; a[15] = edge[2 * i + 1];
         }
         if (!G[i].valid) continue;
         damp[i] = A[i] * o[0];
@@ -583,7 +609,7 @@ int orc_backward(int64_t n, const double* means, const double* scales,
         plane_to_3d(G[i].QC, o + 9, o + 7, v.ex, v.ey, v.dAc, v.dEc, dSig, dm);
         cov_to_params(&G[i], dSig, dsc, dqu);
     }
-    free(g2); free(G); free(A);
+    free(g2); free(G); free(A); free(edge);
     return 0;
 }
 
@@ -680,4 +706,162 @@ int orc_sparse_forward(int64_t n, const double* means, const double* scales,
     }
     free(sel); free(G); free(needA); free(ray_on); free(A);
     return 0;
+}
+
+/* Marks the computation-plane rays on which Gaussian g has a footprint
+ * (q < q_max), searched inside its ellipse bounding box widened by one
+ * cell. */
+static void mark_rays(const OView* v, const OG* g, double q_max, char* on)
+{
+    if (!g->valid) return;
+    const double* b = g->bxC;
+    int64_t c0 = (int64_t)floor(b[0] - 0.5) - 1, c1 = (int64_t)ceil(b[1] - 0.5) + 1;
+    int64_t r0 = (int64_t)floor(b[2] - 0.5) - 1, r1 = (int64_t)ceil(b[3] - 0.5) + 1;
+    if (c0 < 0) c0 = 0;
+    if (r0 < 0) r0 = 0;
+    if (c1 > v->Wc - 1) c1 = v->Wc - 1;
+    if (r1 > v->Hc - 1) r1 = v->Hc - 1;
+    for (int64_t r = r0; r <= r1; ++r)
+        for (int64_t c = c0; c <= c1; ++c)
+            if (quadform(g->QC, (double)c + 0.5 - g->cC[0], (double)r + 0.5 - g->cC[1]) < q_max)
+                on[r * v->Wc + c] = 1;
+}
+
+/* w = sum_p V[p] f(q(p)) over the imaging plane, the pixels searched inside
+ * the footprint's bounding box widened by one pixel. */
+static double weighted_footprint(const OView* v, const OG* g, const double* V, double q_max)
+{
+    if (!g->valid) return 0.0;
+    const double* b = g->bxI;
+    int64_t c0 = (int64_t)floor(b[0] - 0.5) - 1, c1 = (int64_t)ceil(b[1] - 0.5) + 1;
+    int64_t r0 = (int64_t)floor(b[2] - 0.5) - 1, r1 = (int64_t)ceil(b[3] - 0.5) + 1;
+    if (c0 < 0) c0 = 0;
+    if (r0 < 0) r0 = 0;
+    if (c1 > v->W - 1) c1 = v->W - 1;
+    if (r1 > v->H - 1) r1 = v->H - 1;
+    double w = 0.0;
+    for (int64_t r = r0; r <= r1; ++r)
+        for (int64_t c = c0; c <= c1; ++c) {
+            double q = quadform(g->QI, (double)c + 0.5 - g->cI[0], (double)r + 0.5 - g->cI[1]);
+            if (q < q_max) w += V[r * v->W + c] * foot(q, q_max);
+        }
+    return w;
+}
+
+/* Central difference of the linear loss L = sum_p V[p] S[p] of one view when
+ * parameter `comp` of Gaussian k moves by +h and by -h.
+ *   comp: 0-2 mean, 3-5 scale, 6-9 quaternion (raw), 10 amplitude P,
+ *         11 extinction kappa.
+ *   out[0] = L(+h) - L(-h)
+ *   out[1] = 1 if, on a ray where Gaussian k has a footprint in both states,
+ *            the number of Gaussians in front of it differs between the
+ *            states (its depth key crossed another's: the loss jumps, and
+ *            the difference is no derivative), else 0.
+ * Exact, and cheap at full image sizes, because only what the perturbation
+ * changes is recomputed. Every ray on which Gaussian k has no footprint in
+ * either state composites identically in both states; the rays on which it
+ * has one are brute-forced against all n Gaussians in both states, giving
+ * the change dA_i of every share. Writing w_i = sum_p V[p] f_i(p) for the
+ * imaging footprint of Gaussian i (unchanged for i != k),
+ *   L(+) - L(-) = sum_{i != k} P_i w_i dA_i
+ *               + P_k(+) A_k(+) w_k(+) - P_k(-) A_k(-) w_k(-),
+ * where all of A_k's terms lie on those rays. */
+int orc_fd_linear(int64_t n, const double* means, const double* scales,
+                  const double* quats, const double* amp, const double* ext,
+                  const double* view, double q_max, double dil, int shadowing,
+                  const double* V, int64_t k, int comp, double h, double* out)
+{
+    OView v;
+    if (n <= 0 || k < 0 || k >= n || comp < 0 || comp > 11 || view_init(&v, view) ||
+        !(q_max > 0) || !(h > 0))
+        return -1;
+    OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
+    int64_t nrays = v.Wc * v.Hc;
+    char* on = (char*)calloc((size_t)nrays, 1);
+    double* dA = (double*)calloc((size_t)n, sizeof(double));
+    if (!G || !on || !dA) {
+        free(G); free(on); free(dA); return -2;
+    }
+    /* Gaussian k in the two states */
+    OG gs[2];
+    double Pk[2], Kk[2];
+    for (int st = 0; st < 2; ++st) {
+        double p[14];
+        for (int j = 0; j < 3; ++j) { p[j] = means[3 * k + j]; p[3 + j] = scales[3 * k + j]; }
+        for (int j = 0; j < 4; ++j) p[6 + j] = quats[4 * k + j];
+        p[10] = amp[k];
+        p[11] = ext[k];
+        p[comp] += st == 0 ? h : -h;
+        project(&v, p, p + 3, p + 6, dil, q_max, &gs[st]);
+        Pk[st] = p[10];
+        Kk[st] = p[11];
+        mark_rays(&v, &gs[st], q_max, on);
+    }
+    int64_t nsel = 0;
+    for (int64_t r = 0; r < nrays; ++r) nsel += on[r];
+    int64_t* sel = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nsel > 0 ? nsel : 1));
+    /* per ray and state: entries in front of k (-1: k not on the ray) */
+    int64_t* front = (int64_t*)malloc(sizeof(int64_t) * 2 * (size_t)(nsel > 0 ? nsel : 1));
+    nsel = 0;
+    for (int64_t r = 0; r < nrays; ++r) if (on[r]) sel[nsel++] = r;
+    int nt = nthreads();
+    double* At = (double*)calloc((size_t)nt * (size_t)n, sizeof(double));
+    double Ak[2] = {0.0, 0.0};
+    const OG base = G[k];
+    for (int st = 0; st < 2 && At && sel && front; ++st) {
+        G[k] = gs[st];
+        const double sign = st == 0 ? 1.0 : -1.0;
+        double akst = 0.0;
+#pragma omp parallel reduction(+ : akst)
+        {
+            Hit* list = (Hit*)malloc(sizeof(Hit) * (size_t)n);
+            double* mine = At + (size_t)thread_id() * (size_t)n;
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t s = 0; s < nsel; ++s) {
+                int64_t r = sel[s];
+                int64_t m = ray_list(G, n, r % v.Wc, r / v.Wc, q_max, list);
+                double t = 0.0;
+                front[2 * s + st] = -1;
+                for (int64_t j = 0; j < m; ++j) {
+                    int64_t i = list[j].idx;
+                    double kap = i == k ? Kk[st] : ext[i];
+                    double x = kap * list[j].g;
+                    double a = (1.0 - exp(-x)) * (shadowing ? exp(-t) : 1.0);
+                    if (i == k) {
+                        akst += a;
+                        front[2 * s + st] = j;
+                    } else {
+                        mine[i] += sign * a;
+                    }
+                    t += x;
+                }
+            }
+            free(list);
+        }
+        Ak[st] = akst;
+    }
+    G[k] = base;
+    int flag = 0;
+    for (int64_t s = 0; s < nsel && front; ++s)
+        if (front[2 * s] >= 0 && front[2 * s + 1] >= 0 && front[2 * s] != front[2 * s + 1])
+            flag = 1;
+    double diff = 0.0;
+    if (At) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int th = 0; th < nt; ++th) dA[i] += At[(size_t)th * (size_t)n + i];
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : diff)
+        for (int64_t i = 0; i < n; ++i) {
+            /* zero for every Gaussian the change does not reach, and for
+             * those in front of k (identical terms in both states) */
+            if (i == k || dA[i] == 0.0) continue;
+            diff += amp[i] * weighted_footprint(&v, &G[i], V, q_max) * dA[i];
+        }
+        diff += Pk[0] * Ak[0] * weighted_footprint(&v, &gs[0], V, q_max) -
+                Pk[1] * Ak[1] * weighted_footprint(&v, &gs[1], V, q_max);
+    }
+    int err = (At && sel && front) ? 0 : -2;
+    out[0] = diff;
+    out[1] = (double)flag;
+    free(At); free(sel); free(front); free(G); free(on); free(dA);
+    return err;
 }

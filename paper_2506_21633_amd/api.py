@@ -21,7 +21,7 @@ import torch
 from . import _capi as C
 
 __all__ = ["RenderOptions", "GaussianTensors", "Renderer", "ForwardResult",
-           "render", "SDGRFunction"]
+           "render", "SDGRFunction", "count_work", "WORK_NAMES"]
 
 
 @dataclass(frozen=True)
@@ -241,11 +241,30 @@ class Renderer:
                                              out.data_ptr(), _stream_ptr(self.device)))
         return out[:fwd.plan.records]
 
+    def work_counters(self, fwd: ForwardResult) -> dict:
+        """Work counters of the last forward (and backward) on `fwd`'s state;
+        filled only for calls made while count_work(True) was in effect."""
+        wk = (ctypes.c_uint64 * 16)()
+        C.check(self.lib.sdgr_read_work(ctypes.byref(fwd.plan), fwd.state.data_ptr(), wk, 16,
+                                        _stream_ptr(self.device)))
+        return dict(zip(WORK_NAMES, list(wk)))
+
     def optical_depth(self, fwd: ForwardResult) -> torch.Tensor:
         out = torch.empty(max(int(fwd.plan.rays), 1), dtype=torch.float32, device=self.device)
         C.check(self.lib.sdgr_read_optical_depth(ctypes.byref(fwd.plan), fwd.state.data_ptr(),
                                                  out.data_ptr(), _stream_ptr(self.device)))
         return out[:fwd.plan.rays]
+
+
+WORK_NAMES = ("hits_a_fwd", "hits_a_bwd", "hits_b_fwd", "hits_b_bwd", "rounds_a_fwd",
+              "rounds_a_bwd", "rounds_b_fwd", "list_prefix_a", "max_batches_a_fwd",
+              "max_batches_a_bwd", "extra_hit_groups_a_fwd", "extra_hit_groups_a_bwd",
+              "rays_stopped_tau_max", "max_list_prefix_a", "unused14", "unused15")
+
+
+def count_work(on: bool) -> None:
+    """Turn the library's work counters on or off for later calls."""
+    C.check(C.lib().sdgr_profile_count(int(bool(on))))
 
 
 class SDGRFunction(torch.autograd.Function):

@@ -302,6 +302,7 @@ struct Arena {
 
 enum Phase { FWD, BWD };
 constexpr int STATUS_WORDS = 64 + 66;   // status words, then the worklist bins
+static_assert(WORK_WORD + 2 * WORK_COUNTERS <= 64, "work counters overlap the worklist bins");
 constexpr int ST_RECORDS = 12;   // device copy of the record count (sort length)
 constexpr int WL_BINS = 64;      // 66 words of worklist bins after the status words
 
@@ -806,12 +807,12 @@ int sdgr_read_work(const sdgr_plan* plan, const void* state, uint64_t* out, int3
 {
     g_last_error.clear();
     if (!plan || !state || !out || n < 0) return fail(SDGR_EINVAL, "null argument");
-    uint64_t w[8] = {0};
+    uint64_t w[WORK_COUNTERS] = {0};
     hipStream_t s = (hipStream_t)stream;
     SDGR_HIP(hipMemcpyAsync(w, static_cast<const uint32_t*>(state) + WORK_WORD, sizeof(w),
                             hipMemcpyDeviceToHost, s));
     SDGR_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < n && i < 8; ++i) out[i] = w[i];
+    for (int i = 0; i < n && i < WORK_COUNTERS; ++i) out[i] = w[i];
     return SDGR_OK;
 }
 

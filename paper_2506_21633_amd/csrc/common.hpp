@@ -55,11 +55,16 @@ struct RasterParams {
     // work counters (null = off): [0..3] footprint hits of pass A forward,
     // pass A backward, pass B forward, pass B backward; [4..6] list entries
     // evaluated by all 64 lanes in pass A forward, pass A backward, pass B
-    // forward
+    // forward; [7] summed list prefix the tiles of pass A used; [8], [9]
+    // most chunk batches one tile read in pass A forward, backward; [10],
+    // [11] hit groups beyond the first of a batch (batches whose hits
+    // overflow the compaction buffer) in pass A forward, backward; [12] rays
+    // stopped at tau_max; [13] longest list prefix one tile used
     unsigned long long* work = nullptr;
 };
 
-constexpr int WORK_WORD = 16;   // work counters live at status + 16 (8 x u64)
+constexpr int WORK_WORD = 16;    // work counters live at status + 16
+constexpr int WORK_COUNTERS = 16;   // u64 each: status words 16 .. 47
 
 // Device-side scalars kept at the start of the state buffer.
 enum StatusSlot : int {

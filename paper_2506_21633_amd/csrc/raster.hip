@@ -399,6 +399,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     bool alive = tc.inside;
     uint32_t last = 0;
     unsigned long long n_iter = 0, n_hits = 0;   // work counters
+    unsigned long long n_batch = 0, n_group = 0;
     uint64_t live = __ballot(alive);
     // per-entry sums of the last processed batch leave with one atomic each;
     // they are sent once the next batch's loads have landed, so the wait for
@@ -425,6 +426,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
         const uint64_t sm = g0 + lane < c_end ? psum[g0 + lane] : 0ull;
         uint64_t todo = __ballot((sm & live) != 0ull);   // chunks to read, in order
         while (todo != 0ull && live != 0ull) {
+            ++n_batch;
             // up to NB chunks: masks and values, then the needed records
             uint32_t got = 0u;   // bit k: this lane's entry of chunk k was gathered
             int nb = 0;
@@ -489,6 +491,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
             // hits are compacted ray-major (chunk by chunk, front to back) and
             // taken 64 per round
             for (int g0 = 0; g0 < nb && live != 0ull;) {
+                ++n_group;
                 int g1 = g0;
                 uint32_t H = 0;
                 bool open = true;
@@ -595,10 +598,15 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     if (rp.work) {
         n_hits = wave_sum_u64(n_hits);
         const uint32_t used = wave_max_u32(last);   // list prefix any ray used
+        const uint64_t stopped = __ballot(tc.inside && rp.shadowing && t >= rp.tau_max);
         if (lane == 0) {
             atomicAdd(&rp.work[4], n_iter);
             atomicAdd(&rp.work[0], n_hits);
             atomicAdd(&rp.work[7], (unsigned long long)used);
+            atomicMax(&rp.work[8], n_batch);
+            atomicAdd(&rp.work[10], n_group - n_batch);
+            atomicAdd(&rp.work[12], (unsigned long long)__popcll(stopped));
+            atomicMax(&rp.work[13], (unsigned long long)used);
         }
     }
     if (tc.inside) {
@@ -886,6 +894,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
 #pragma unroll
                 for (int c = 0; c < 6; ++c) s_G[b][g][k][c][lane] = 0.0f;
     unsigned long long n_iter = 0, n_hits = 0;   // work counters
+    unsigned long long n_batch = 0, n_group = 0;
     const uint32_t n_max = wave_max_u32(n_mine);
     const uint32_t e_end = rg.x + n_max;           // exclusive end of the used entries
     // the six per-entry sums of the last processed batch go to the flusher
@@ -915,6 +924,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
         const uint64_t sm = g0 + lane < g1 ? psum[g0 + lane] : 0ull;
         uint64_t todo = __ballot((sm & live_c) != 0ull);   // chunks to read, back to front
         while (todo != 0ull) {
+            ++n_batch;
             uint32_t got = 0u;
             int nb = 0;
             uint64_t m[NB];   // lane = entry: the cells it covers
@@ -990,6 +1000,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
             // hits are compacted ray-major, back to front (the batch's chunks
             // come back to front), and taken 64 per round
             for (int g0 = 0; g0 < nb;) {
+                ++n_group;
                 int g1 = g0;
                 uint32_t H = 0;
                 bool open = true;
@@ -1107,6 +1118,8 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
         if (lane == 0) {
             atomicAdd(&rp.work[5], n_iter);
             atomicAdd(&rp.work[1], n_hits);
+            atomicMax(&rp.work[9], n_batch);
+            atomicAdd(&rp.work[11], n_group - n_batch);
         }
     }
 }

@@ -466,3 +466,50 @@ def test_sparse_forward_equals_full():
     Ss, As = oracle.sparse_forward(sc, v, pix, gid)
     assert np.allclose(Ss, S.reshape(-1)[pix], rtol=1e-12, atol=1e-14 * S.max())
     assert np.allclose(As, A[gid], rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("shadowing", [True, False])
+def test_restricted_central_difference_equals_full_forward(shadowing):
+    """The restricted difference recomputes only the rays and pixels a
+    perturbation reaches; it must equal the difference of two full brute-force
+    forwards, for every kind of parameter, and divided by 2h approach the
+    analytic gradient."""
+    sc = _small_dense(51)
+    v = scenes.View(azimuth=0.9, grazing=math.radians(50), img_w=24, img_h=20,
+                    d_az=0.08, d_rg=0.09)
+    rng = scenes.make_rng(52)
+    Vc = rng.standard_normal((20, 24))
+    g, _ = oracle.backward_view(sc, v, Vc, shadowing=shadowing)
+
+    def loss(s):
+        return float((oracle.forward_view(s, v, shadowing=shadowing)[2] * Vc).sum())
+
+    A, _, S = oracle.forward_view(sc, v, shadowing=shadowing)
+    # rounding of the two full forwards: ~1e-16 per term of the loss
+    Lscale = float(np.abs(S * Vc).sum())
+    ks = rng.choice(np.flatnonzero(A > 0), 6, replace=False)
+    for k in ks:
+        for comp, (name, j) in enumerate(oracle.FD_COMPONENTS):
+            arr = getattr(sc, name)
+            idx = (k,) if j is None else (k, j)
+            h = 1e-3 * max(1.0, abs(arr[idx]))   # large step: a real difference
+            d, flag = oracle.fd_linear(sc, v, Vc, k, comp, h, shadowing=shadowing)
+            sp, sm = sc.copy(), sc.copy()
+            getattr(sp, name)[idx] += h
+            getattr(sm, name)[idx] -= h
+            full = loss(sp) - loss(sm)
+            assert abs(d - full) <= 1e-13 * Lscale, (k, name, j, d, full)
+            h = 1e-6 * max(1.0, abs(arr[idx]))
+            d, flag = oracle.fd_linear(sc, v, Vc, k, comp, h, shadowing=shadowing)
+            if flag:
+                continue
+            gg = g[name][idx]
+            scale = np.abs(g[name]).max()
+            assert abs(d / (2 * h) - gg) <= 2e-6 * scale, (k, name, j, d / (2 * h), gg)
+
+
+def _small_dense(seed, n=120):
+    rng = scenes.make_rng(seed)
+    return mk_scene(rng.uniform(-0.5, 0.5, (n, 3)), rng.uniform(0.05, 0.2, (n, 3)),
+                    quats=rng.standard_normal((n, 4)), amp=rng.uniform(0.3, 1.0, n),
+                    ext=rng.uniform(0.5, 3, n))
