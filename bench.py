@@ -9,7 +9,11 @@ cotangent against a target rendered from a copy with means jittered by
 N(0, 0.1 m) + backward to all Gaussian parameters + the overflow check,
 everything resident in HBM. Pair capacities come from an exact count taken
 before the timed region plus 10 % headroom (an overflow would re-count and
-redo the step). Prints one JSON line.
+redo the step). Prints one JSON line, which also carries the roofline
+object of the dominant kernel (HBM bytes of the algorithm per launch over its
+measured launch time), the forward-only 1k-Gaussian and the 50k-Gaussian
+building workloads as sub-objects, the served-vs-plain stream and the FP64
+oracle timed on the host.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -53,8 +57,13 @@ def parse():
     ap.add_argument("--no-work-count", action="store_true",
                     help="skip the untimed step that counts footprint hits (profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="first run one device-to-device copy of MIB MiB (the reference "
-                         "kernel that scales rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
+                    help="first run one device-to-device copy of MIB MiB and one gather of "
+                         "MIB MiB in random 64-byte rows (the reference kernels that scale "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
+    ap.add_argument("--no-other-workloads", action="store_true",
+                    help="skip the short runs of the 1k-Gaussian and building workloads")
+    ap.add_argument("--with-large", action="store_true",
+                    help="also time the 2M-Gaussian recompute workload (a few seconds)")
     return ap.parse_args()
 
 
@@ -110,10 +119,23 @@ def stored_traffic(kernel, launches_per_step, src_hash):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sc, views, rows):
     """The FP64 oracle (untuned) on a bounded sample: the central `rows`
     range rows of view 0 (image and computation plane), all Gaussians,
-    forward + backward; scaled to whole images."""
+    forward + backward (the oracle's backward runs its forward first, so one
+    backward call is the whole step) with a fixed random cotangent; scaled
+    to whole images."""
     import numpy as np
     import oracle
     from paper_2506_21633_amd import scenes
@@ -121,13 +143,13 @@ def cpu_baseline(sc, views, rows):
     band = scenes.View(azimuth=v.azimuth, grazing=v.grazing, img_w=v.img_w, img_h=rows,
                        d_az=v.d_az, d_rg=v.d_rg, comp_w=v.img_w, comp_h=rows,
                        comp_d_az=v.d_az, comp_d_el=v.d_rg * math.tan(v.grazing))
+    G = np.random.default_rng(0).standard_normal((rows, v.img_w))
     t0 = time.perf_counter()
-    _, _, S = oracle.forward_view(sc, band)
-    oracle.backward_view(sc, band, np.sign(S) / S.size)
+    oracle.backward_view(sc, band, G)
     dt = time.perf_counter() - t0
     per_image = dt * (v.img_h / rows)
     return {"value": 1.0 / per_image, "unit": "images/s", "cores": oracle.threads(),
-            "kind": "oracle",
+            "cpu": cpu_model(), "kind": "oracle",
             "sample": f"forward+backward of the central {rows} of {v.img_h} range rows of "
                       f"view 0 ({v.img_w} columns, {sc.n} Gaussians), {dt:.1f} s, "
                       f"scaled x{v.img_h / rows:g} to one image"}
@@ -196,6 +218,75 @@ def serving_bench(dev, n_requests, seed=404):
                         "1-16 views of 64^2-512^2, half with L1 gradient"}
 
 
+def calibration_kernels(dev, mib):
+    """Reference kernels of known HBM bytes for scaling the rocprofv3
+    FETCH_SIZE / WRITE_SIZE counters: a device-to-device copy of `mib` MiB
+    (streaming) and a gather of `mib` MiB in random 64-byte rows (the access
+    shape of the record gathers); reads and writes `mib` MiB each, plus 8 B
+    of index per row for the gather."""
+    import torch
+    nf = mib * (1 << 20) // 4
+    src = torch.ones(nf, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize(dev)
+    dst.copy_(src)
+    rows = src.view(-1, 16)
+    perm = torch.randperm(rows.shape[0], device=dev)
+    torch.cuda.synchronize(dev)
+    torch.index_select(rows, 0, perm, out=dst.view(-1, 16))
+    torch.cuda.synchronize(dev)
+    del src, dst, perm
+
+
+def make_step(r, target_images, forward_only=False):
+    import torch
+    from paper_2506_21633_amd import _capi
+    numel = float(target_images.numel())
+
+    def step():
+        # pair capacities from the last exact count plus 10 % headroom; the
+        # status check at the end of the step catches an overflow
+        while True:
+            res = r.forward(r.planned(0.1))
+            if not forward_only:
+                G = torch.sign(res.images - target_images) / numel
+                r.backward(res, G)
+            try:
+                r.status(res)
+                return res
+            except _capi.SDGRError as exc:
+                if exc.code != _capi.SDGR_EOVERFLOW:
+                    raise
+                r.replan()
+    return step
+
+
+def time_workload(name, dev, steps, warmup, forward_only=False):
+    """Short timed run of one more workload: images/s and ms per step."""
+    import torch
+    from paper_2506_21633_amd import api
+    sc, views, target, cfg = workload(name)
+    opts = api.RenderOptions(recompute=bool(cfg.get("recompute", False)))
+    r = api.Renderer([api.GaussianTensors.from_numpy(sc, dev)], views, opts)
+    timg = api.Renderer([api.GaussianTensors.from_numpy(target, dev)], views,
+                        opts).forward().images.clone()
+    step = make_step(r, timg, forward_only)
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize(dev)
+    dt = time.perf_counter() - t0
+    cfg = dict(cfg, mode="forward only" if forward_only else "forward+backward",
+               steps=steps, warmup=warmup)
+    if forward_only:
+        cfg.pop("loss", None)
+    return {"value": len(views) * steps / dt, "unit": "images/s",
+            "ms_per_step": dt * 1e3 / steps, "config": cfg}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -210,35 +301,14 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.copy_calibration > 0:
-        nf = args.copy_calibration * (1 << 20) // 4
-        src = torch.ones(nf, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize(dev)
-        dst.copy_(src)
-        torch.cuda.synchronize(dev)
-        del src, dst
+        calibration_kernels(dev, args.copy_calibration)
     sc, views, target, cfg = workload(args.workload)
     g = api.GaussianTensors.from_numpy(sc, dev)
     tgt = api.GaussianTensors.from_numpy(target, dev)
     opts = api.RenderOptions(recompute=bool(cfg.get("recompute", False)))
     r = api.Renderer([g], views, opts)
     target_images = api.Renderer([tgt], views, opts).forward().images.clone()
-    numel = float(target_images.numel())
-
-    def step():
-        # pair capacities from the last exact count plus 10 % headroom; the
-        # status check at the end of the step catches an overflow
-        while True:
-            res = r.forward(r.planned(0.1))
-            G = torch.sign(res.images - target_images) / numel
-            r.backward(res, G)
-            try:
-                r.status(res)
-                return res
-            except _capi.SDGRError as exc:
-                if exc.code != _capi.SDGR_EOVERFLOW:
-                    raise
-                r.replan()
+    step = make_step(r, target_images)
 
     for _ in range(args.warmup):
         step()
@@ -247,23 +317,22 @@ def main():
     exact = r._last_exact          # the exact pair counts (capacities add 10 %)
     torch.cuda.synchronize(dev)
     # pairs the step actually sorted and rasterized: all computation-plane
-    # pairs, and imaging-plane pairs of the Gaussians with nonzero intensity
+    # pairs, and imaging-plane pairs of the Gaussians with nonzero intensity;
+    # records pass A used (the backward's work list)
     st = res.state[:64].view(torch.int32).cpu()
     used = types.SimpleNamespace(records=exact.records, rays=exact.rays,
-                                 pairs_c=int(st[1]), pairs_i=int(st[2]))
+                                 pairs_c=int(st[1]), pairs_i=int(st[2]), active=int(st[5]),
+                                 pixels=sum(v.img_w * v.img_h for v in views), n=sc.n)
 
     lib = _capi.lib()
-    work = [0] * 8
+    work = [0] * 16
     if not args.no_work_count:
         # one untimed step with the work counters on
-        lib.sdgr_profile_count(1)
+        api.count_work(True)
         res = step()
         torch.cuda.synchronize(dev)
-        lib.sdgr_profile_count(0)
-        wk = (ctypes.c_uint64 * 8)()
-        _capi.check(lib.sdgr_read_work(ctypes.byref(res.plan), res.state.data_ptr(), wk, 8,
-                                       torch.cuda.current_stream(dev).cuda_stream))
-        work = list(wk)
+        api.count_work(False)
+        work = list(r.work_counters(res).values())
         del res
     if not args.no_profile:
         _capi.profile_read()
@@ -295,17 +364,23 @@ def main():
         "data": "synthetic",
         "config": dict(cfg, parallelism="single GPU", pairs_c=used.pairs_c,
                        pairs_i=used.pairs_i, pairs_i_all=exact.pairs_i, tiles_c=exact.tiles_c,
-                       tiles_i=exact.tiles_i),
+                       tiles_i=exact.tiles_i, records=used.records, records_used=used.active),
     }
-    out["work"] = {"hits_a_fwd": work[0], "hits_a_bwd": work[1], "hits_b_fwd": work[2],
-                   "hits_b_bwd": work[3], "rounds_a_fwd": work[4], "rounds_a_bwd": work[5],
-                   "rounds_b_fwd": work[6], "list_prefix_a": work[7]}
-    out["path_hbm"] = path_hbm(used, sc.n, views, ms_step)
+    out["work"] = dict(zip(api.WORK_NAMES[:14], work[:14]))
+    out["path_hbm"] = path_hbm(used, ms_step)
     if stages:
         per = {k: v[0] / max(v[1], 1) for k, v in stages.items() if v[1]}
         out["stages_ms"] = {k: round(v, 4) for k, v in per.items()}
         dom = max(per, key=per.get)
-        out["roofline"] = roofline(dom, per[dom], work)
+        out["roofline"] = roofline(dom, per[dom], used, work)
+        out["kernels_hbm"] = {k: kernel_hbm(k, per[k], used) for k in ALGO_BYTES if k in per}
+    if not args.no_other_workloads:
+        out["workloads"] = {
+            "fwd_1k": time_workload("fwd_1k", dev, 50, 5, forward_only=True),
+            "building_50k": time_workload("building_50k", dev, 10, 3),
+        }
+        if args.with_large:
+            out["workloads"]["large_2m"] = time_workload("large_2m", dev, 3, 1)
     if args.serving_requests > 0:
         out["serving"] = serving_bench(dev, args.serving_requests)
     if not args.no_cpu_baseline:
@@ -334,37 +409,76 @@ SOURCES = {"raster_a_fwd": "raster.hip", "raster_b_fwd": "raster.hip",
 OPS_PER_HIT = {"raster_a_fwd": 26, "raster_b_fwd": 17, "raster_b_bwd": 37,
                "raster_a_bwd": 56}
 
+# Algorithmic HBM bytes per launch of each stage: the compulsory traffic of
+# the binned method, split from the per-unit figures of the whole step
+# (per pair 4 B read in each rasterizer pass, 12 B emitted, 24 B per sort
+# pass; per used record its 24 B plane record read in each pass that needs
+# it and 8 B per float accumulated read-modify-write; per ray and pixel 4 B
+# per array written or read). u: Kc, Ki (pairs of the two planes), R
+# (records), Nu (records pass A used), rays, pixels, N (Gaussians).
+ALGO_BYTES = {
+    # pass A forward: pair ids, plane-C records, A accumulated, tau written
+    "raster_a_fwd": lambda u: 4 * u.pairs_c + (24 + 8) * u.active + 4 * u.rays,
+    # pass A backward: pair ids, plane-C records, c = P dL/dI, six
+    # plane-C gradient sums accumulated, tau read
+    "raster_a_bwd": lambda u: 4 * u.pairs_c + (24 + 4 + 48) * u.active + 4 * u.rays,
+    # pass B forward: pair ids, plane-I records, image written
+    "raster_b_fwd": lambda u: 4 * u.pairs_i + 24 * u.active + 4 * u.pixels,
+    # pass B backward: plane-I records, dL/dS read once, six plane-I sums
+    # and c written, six plane-C sums cleared
+    "raster_b_bwd": lambda u: (24 + 28 + 24) * u.active + 4 * u.pixels,
+    # parameter adjoint: parameters read and gradients written per Gaussian,
+    # 12 plane gradients and A read per used record
+    "params_bwd": lambda u: 96 * u.n + 52 * u.active,
+    # projection: parameters read, 48 B record and 8 B pair count per record
+    "preprocess": lambda u: 48 * u.n + 56 * u.records,
+    # one 24 B pass over the computation-plane pairs
+    "pair_sort": lambda u: 24 * u.pairs_c,
+    # emission of the computation-plane pairs
+    "bin_pairs": lambda u: 12 * u.pairs_c,
+}
 
-def roofline(kernel, ms, work):
-    """Roofline object of the dominant stage. The rasterizers are bound by
-    VALU issue (alu); achieved = footprint hits x ops per hit / time."""
+
+def kernel_hbm(stage, ms, u):
+    byts = ALGO_BYTES[stage](u)
+    gbs = byts / (ms * 1e-3) / 1e9
+    return {"bytes": byts, "ms": round(ms, 4), "GBps": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def roofline(kernel, ms, u, work):
+    """Roofline object of the dominant stage against HBM: achieved = its
+    algorithmic bytes per launch (ALGO_BYTES) / its mean launch time from
+    HIP events on the launching stream. The lane-operation count of the
+    rasterizers against the VALU peak is a secondary figure."""
     src = SOURCES.get(kernel)
     traffic = stored_traffic(kernel, 1, source_hash(src)) if src else None
-    if kernel in HIT_KERNELS:
+    out = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": None, "traffic": traffic, "kernel": kernel, "ms": ms}
+    if kernel in ALGO_BYTES:
+        h = kernel_hbm(kernel, ms, u)
+        out.update(achieved=h["GBps"], frac=h["GBps"] / HBM_PEAK_GBS,
+                   algorithmic_bytes=h["bytes"])
+    if kernel in HIT_KERNELS and work[HIT_KERNELS[kernel]]:
         hits = work[HIT_KERNELS[kernel]]
-        ops = hits * OPS_PER_HIT[kernel]
-        achieved = ops / (ms * 1e-3) / 1e12
-        out = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-               "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-               "kernel": kernel, "ms": ms,
-               "work": f"{hits} footprint hits x {OPS_PER_HIT[kernel]} lane-ops"}
-        if kernel in ENTRY_KERNELS and hits:
-            out["evaluated_over_hits"] = work[ENTRY_KERNELS[kernel]] * 64 / hits
-        return out
-    return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": None, "traffic": traffic, "kernel": kernel, "ms": ms}
+        ops = hits * OPS_PER_HIT[kernel] / (ms * 1e-3) / 1e12
+        out["alu"] = {"achieved": ops, "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
+                      "frac": ops / VALU_PEAK_TOPS,
+                      "work": f"{hits} footprint hits x {OPS_PER_HIT[kernel]} lane-ops"}
+        if kernel in ENTRY_KERNELS:
+            out["alu"]["evaluated_over_hits"] = work[ENTRY_KERNELS[kernel]] * 64 / hits
+    return out
 
 
-def path_hbm(plan, n, views, ms_step):
+def path_hbm(u, ms_step):
     """Compulsory HBM bytes of one fwd+bwd step of the binned method (per
-    Gaussian: parameters read and gradients written, 96 B; per record: the
-    projected record written once and read in forward and backward plus the
-    per-record reductions, 256 B; per pair: emission, one sort pass, one read
-    in forward and one in backward, 44 B; per pixel and per ray: image and
-    dL/dS, optical depth written and read, 8 B each) against 8 TB/s."""
-    pixels = sum(v.img_w * v.img_h for v in views)
-    rays = plan.rays
-    byts = 96 * n + 256 * plan.records + 44 * (plan.pairs_c + plan.pairs_i) + 8 * pixels + 8 * rays
+    Gaussian: parameters read and gradients written, 96 B; per used record:
+    the projected record written once and read in forward and backward plus
+    the per-record reductions, 256 B; per pair: emission, one sort pass, one
+    read in forward and one in backward, 44 B; per pixel and per ray: image
+    and dL/dS, optical depth written and read, 8 B each) against 8 TB/s."""
+    byts = (96 * u.n + 256 * u.active + 44 * (u.pairs_c + u.pairs_i) + 8 * u.pixels
+            + 8 * u.rays)
     gbs = byts / (ms_step * 1e-3) / 1e9
     return {"bytes_per_step": byts, "achieved_GBps": gbs, "peak_GBps": HBM_PEAK_GBS,
             "frac": gbs / HBM_PEAK_GBS}

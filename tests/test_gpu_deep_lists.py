@@ -48,7 +48,7 @@ IMG_ELEM = 2e-5
 GRAD_ELEM = 1e-4
 GRAD_EDGE = 1e-2
 EDGE_BAND = 1e-5
-EDGE_FRACTION = 2e-3   # at most this share of the used Gaussians near the cutoff
+EDGE_FRACTION = 1e-2   # at most this share of the used Gaussians near the cutoff
 GRAD_COS = 0.9999
 FD_ORACLE_TOL = 1e-8
 GROUPS = ("means", "scales", "quats", "amp", "ext")
