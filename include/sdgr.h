@@ -134,6 +134,7 @@ typedef struct sdgr_plan {
                                   with a nonzero intensity emit pairs */
     int64_t tiles_c, tiles_i;  /* tiles over all views */
     int64_t rays;              /* computation-plane cells over all views */
+    int64_t gaussians;         /* sum over the scenes of n */
     int32_t nviews, nscenes;
     int32_t tile;              /* tile side in pixels (8) */
     int32_t recompute;         /* copy of options.recompute */
@@ -170,9 +171,14 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes,
 /* Re-sizes `plan` for pair capacities pairs_c, pairs_i (for instance the
  * counts of a previous query plus headroom, so that a training loop whose
  * Gaussians move a little need not query every step): recomputes the three
- * workspace sizes; host-only. A forward that finds more pairs than the
- * capacities reports SDGR_EOVERFLOW through sdgr_status. */
+ * workspace sizes from the plan's own counts; host-only. A forward that
+ * finds more pairs than the capacities reports SDGR_EOVERFLOW through
+ * sdgr_status. */
 int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i);
+
+/* Forward and backward return SDGR_EINVAL if `plan` does not belong to the
+ * scenes, views and options, and SDGR_EWORKSPACE if its workspace sizes are
+ * smaller than its capacities need (a plan edited by hand). */
 
 /* Forward render (Sec. II-A). Writes every view's H x W image at
  * images + view.img_offset (row-major [range row][azimuth column]); other

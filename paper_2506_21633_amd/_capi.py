@@ -61,7 +61,7 @@ class Plan(ctypes.Structure):
                 ("records", ctypes.c_int64), ("pairs_c", ctypes.c_int64),
                 ("pairs_i", ctypes.c_int64), ("tiles_c", ctypes.c_int64),
                 ("tiles_i", ctypes.c_int64), ("rays", ctypes.c_int64),
-                ("nviews", ctypes.c_int32), ("nscenes", ctypes.c_int32),
+                ("gaussians", ctypes.c_int64), ("nviews", ctypes.c_int32), ("nscenes", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("recompute", ctypes.c_int32)]
 
 

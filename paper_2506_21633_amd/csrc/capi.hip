@@ -405,10 +405,18 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
 {
     if (!plan) return fail(SDGR_EINVAL, "plan is null");
     if (plan->records != P.records || plan->rays != P.rays || plan->tiles_c != P.tiles_c ||
-        plan->tiles_i != P.tiles_i || plan->nviews != P.nv || plan->nscenes != P.ns ||
+        plan->tiles_i != P.tiles_i || plan->gaussians != P.items || plan->nviews != P.nv ||
+        plan->nscenes != P.ns ||
         plan->tile != TILE || plan->recompute != (P.recompute ? 1 : 0) ||
         plan->pairs_c < 0 || plan->pairs_i < 0 || plan->pairs_c + plan->pairs_i > INT32_MAX)
         return fail(SDGR_EINVAL, "plan does not match the scenes, views and options");
+    // the workspaces the plan promises must hold the layout of its capacities
+    Bufs b;
+    size_t st = 0, fs = 0, bs = 0;
+    layout(P, plan->pairs_c, plan->pairs_i, FWD, nullptr, nullptr, b, &st, &fs);
+    layout(P, plan->pairs_c, plan->pairs_i, BWD, nullptr, nullptr, b, nullptr, &bs);
+    if (plan->state_bytes < st || plan->fwd_scratch_bytes < fs || plan->bwd_scratch_bytes < bs)
+        return fail(SDGR_EWORKSPACE, "plan's workspace sizes are smaller than its capacities need");
     return SDGR_OK;
 }
 
@@ -516,6 +524,53 @@ int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     return SDGR_OK;
 }
 
+
+// Pair counts of the projection (count-only preprocess into `query`, which
+// holds sdgr_query_bytes(ns, nv)), read back with one stream
+// synchronisation, and the workspace sizes they imply.
+int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan)
+{
+    Arena a{query};
+    unsigned long long* totals = a.take<unsigned long long>(8);
+    unsigned long long* slots = a.take<unsigned long long>(2 * TOTAL_SLOTS);
+    DevView* dviews = a.take<DevView>(P.nv);
+    DevScene* dscenes = a.take<DevScene>(P.ns);
+    SDGR_HIP(launch_upload(dviews, P.views.data(), sizeof(DevView) * P.nv, s));
+    SDGR_HIP(launch_upload(dscenes, P.scenes.data(), sizeof(DevScene) * P.ns, s));
+    SDGR_HIP(launch_fill_u32((uint32_t*)totals, 0u, 16, s));
+    {
+        StageTimer t(SG_QUERY, s);
+        SDGR_HIP(launch_preprocess(dviews, dscenes, P.nv, P.ns, P.items, P.rp, false, nullptr,
+                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                   slots, totals, s));
+    }
+    unsigned long long host_tot[2] = {0, 0};
+    SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));
+    SDGR_HIP(hipStreamSynchronize(s));
+    if (host_tot[0] + host_tot[1] > (unsigned long long)INT32_MAX)
+        return fail(SDGR_EUNSUPPORTED, "more than 2^31 - 1 (Gaussian, tile) pairs");
+    sdgr_plan out{};
+    out.records = P.records;
+    out.pairs_c = (int64_t)host_tot[0];
+    out.pairs_i = (int64_t)host_tot[1];
+    out.tiles_c = P.tiles_c;
+    out.tiles_i = P.tiles_i;
+    out.rays = P.rays;
+    out.gaussians = P.items;
+    out.nviews = P.nv;
+    out.nscenes = P.ns;
+    out.tile = TILE;
+    out.recompute = P.recompute ? 1 : 0;
+    out.image_floats = (size_t)P.image_floats;
+    Bufs b;
+    layout(P, out.pairs_c, out.pairs_i, FWD, nullptr, nullptr, b, &out.state_bytes,
+           &out.fwd_scratch_bytes);
+    layout(P, out.pairs_c, out.pairs_i, BWD, nullptr, nullptr, b, nullptr,
+           &out.bwd_scratch_bytes);
+    *plan = out;
+    return SDGR_OK;
+}
+
 }  // namespace
 }  // namespace sdgr
 
@@ -558,46 +613,7 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
     if (!query_scratch || query_bytes < sdgr_query_bytes(nscenes, nv))
         return fail(SDGR_EWORKSPACE, "query scratch smaller than sdgr_query_bytes()");
     if ((uintptr_t)query_scratch & 255) return fail(SDGR_EINVAL, "scratch not 256-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
-    Arena a{(char*)query_scratch};
-    unsigned long long* totals = a.take<unsigned long long>(8);
-    unsigned long long* slots = a.take<unsigned long long>(2 * TOTAL_SLOTS);
-    DevView* dviews = a.take<DevView>(nv);
-    DevScene* dscenes = a.take<DevScene>(nscenes);
-    SDGR_HIP(launch_upload(dviews, P.views.data(), sizeof(DevView) * nv, s));
-    SDGR_HIP(launch_upload(dscenes, P.scenes.data(), sizeof(DevScene) * nscenes, s));
-    SDGR_HIP(launch_fill_u32((uint32_t*)totals, 0u, 16, s));
-    {
-        StageTimer t(SG_QUERY, s);
-        SDGR_HIP(launch_preprocess(dviews, dscenes, nv, P.ns, P.items, P.rp, false, nullptr,
-                                   nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   slots,
-                                   totals, s));
-    }
-    unsigned long long host_tot[2] = {0, 0};
-    SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));
-    SDGR_HIP(hipStreamSynchronize(s));
-    if (host_tot[0] + host_tot[1] > (unsigned long long)INT32_MAX)
-        return fail(SDGR_EUNSUPPORTED, "more than 2^31 - 1 (Gaussian, tile) pairs");
-    sdgr_plan out{};
-    out.records = P.records;
-    out.pairs_c = (int64_t)host_tot[0];
-    out.pairs_i = (int64_t)host_tot[1];
-    out.tiles_c = P.tiles_c;
-    out.tiles_i = P.tiles_i;
-    out.rays = P.rays;
-    out.nviews = nv;
-    out.nscenes = nscenes;
-    out.tile = TILE;
-    out.recompute = P.recompute ? 1 : 0;
-    out.image_floats = (size_t)P.image_floats;
-    Bufs b;
-    layout(P, out.pairs_c, out.pairs_i, FWD, nullptr, nullptr, b, &out.state_bytes,
-           &out.fwd_scratch_bytes);
-    layout(P, out.pairs_c, out.pairs_i, BWD, nullptr, nullptr, b, nullptr,
-           &out.bwd_scratch_bytes);
-    *plan = out;
-    return SDGR_OK;
+    return count_and_plan(P, (char*)query_scratch, (hipStream_t)stream, plan);
 }
 
 int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i)
@@ -613,6 +629,7 @@ int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i)
     P.rays = plan->rays;
     P.tiles_c = plan->tiles_c;
     P.tiles_i = plan->tiles_i;
+    P.items = plan->gaussians;   // sizes the parameter-gradient parts
     P.recompute = plan->recompute != 0;
     plan->pairs_c = pairs_c;
     plan->pairs_i = pairs_i;

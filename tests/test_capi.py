@@ -112,3 +112,48 @@ def test_query_bytes_small_and_monotone():
     L = C.lib()
     a, b = L.sdgr_query_bytes(1, 1), L.sdgr_query_bytes(8, 512)
     assert 0 < a <= b < 1 << 20
+
+
+def _host_plan(n, nv, size, recompute=0):
+    """A plan as sdgr_plan_query would fill it for one scene of n Gaussians
+    and nv views of size x size (counts only; host-side)."""
+    p = C.Plan()
+    tiles = ((size + 7) // 8) ** 2
+    p.records, p.gaussians, p.nviews, p.nscenes, p.tile = n * nv, n, nv, 1, 8
+    p.tiles_c = p.tiles_i = nv * tiles
+    p.rays = nv * size * size
+    p.recompute = recompute
+    p.image_floats = nv * size * size
+    return p
+
+
+@pytest.mark.parametrize("recompute", [0, 1])
+def test_plan_resize_keeps_parameter_gradient_scratch(recompute):
+    """A resized plan's backward scratch must hold the per-view-group parts
+    of the parameter gradients (they grow with the Gaussian count once there
+    is more than one group of views), as the query's own plan does."""
+    L = C.lib()
+    sizes = []
+    for n in (1000, 2_000_000):
+        p = _host_plan(n, 16, 1024, recompute)
+        p.records = 16 * 2_000_000   # same records: only the Gaussian count differs
+        C.check(L.sdgr_plan_resize(ctypes.byref(p), 5_000_000, 4_000_000))
+        sizes.append(p.bwd_scratch_bytes)
+        again = C.Plan()
+        ctypes.pointer(again)[0] = p
+        C.check(L.sdgr_plan_resize(ctypes.byref(again), 5_000_000, 4_000_000))
+        assert again.bwd_scratch_bytes == p.bwd_scratch_bytes
+    # two groups of 8 views: at least 2 x 12 floats per extra Gaussian
+    assert sizes[1] - sizes[0] >= 2 * 12 * 4 * (2_000_000 - 1000)
+
+
+def test_forward_rejects_plan_with_short_workspaces():
+    L = C.lib()
+    sc, views, o = _args()
+    p = _host_plan(10, 1, 64)
+    C.check(L.sdgr_plan_resize(ctypes.byref(p), 100, 100))
+    p.bwd_scratch_bytes -= 256
+    rc = L.sdgr_backward(sc, 1, views, 1, ctypes.byref(o), ctypes.byref(p), 0x1000, 0x1000,
+                         0x1000, (C.SceneGrad * 1)(C.SceneGrad(0x1000, 0x1000, 0x1000, 0x1000,
+                                                               0x1000)), None)
+    assert rc == C.SDGR_EWORKSPACE
