@@ -203,6 +203,25 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes,
                   void* scratch, const float* dL_dimages,
                   const sdgr_scene_grad* grads, void* stream);
 
+/* Forward render (Sec. II-A) that allocates nothing and takes no workspace:
+ * for callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc). Same arguments and
+ * result as sdgr_forward without the plan and workspaces: the pair counts,
+ * the kept state and the scratch live in one static device array of
+ * SDGR_STATIC_SCRATCH_BYTES per GPU, held from the first call on that GPU
+ * until the process ends. The call counts the (Gaussian, tile) pairs as
+ * sdgr_plan_query does (one synchronisation of `stream`), then enqueues the
+ * forward on `stream`. Returns SDGR_EUNSUPPORTED, before enqueuing the
+ * forward, when the problem needs more than the array holds (the message
+ * gives the size). Calls on one GPU share its array: a call's work must be
+ * complete before another call on that GPU starts (calls on one stream are
+ * ordered; calls on different streams or threads race). No state is kept
+ * for a backward. */
+#define SDGR_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int sdgr_forward_static(const sdgr_scene* scenes, int32_t nscenes,
+                        const sdgr_view* views, int32_t nv,
+                        const sdgr_options* opt, float* images, void* stream);
+
 /* Synchronises `stream` and returns SDGR_EOVERFLOW if a forward or backward
  * that used `state` found more pairs than planned, else SDGR_OK. */
 int sdgr_status(const sdgr_plan* plan, const void* state, void* stream);

@@ -21,7 +21,9 @@ EXPORTED = ("sdgr_version", "sdgr_last_error", "sdgr_default_options",
             "sdgr_backward", "sdgr_status", "sdgr_read_intensity",
             "sdgr_read_optical_depth", "sdgr_profile_enable", "sdgr_profile_read",
             "sdgr_profile_stage", "sdgr_profile_count", "sdgr_read_work",
-            "sdgr_plan_resize")
+            "sdgr_plan_resize", "sdgr_forward_static")
+
+STATIC_SCRATCH_BYTES = 64 << 20   # SDGR_STATIC_SCRATCH_BYTES
 
 
 class Scene(ctypes.Structure):
@@ -97,6 +99,8 @@ def lib():
                                P(Options), P(Plan), vp, vp, vp, vp]
     L.sdgr_backward.argtypes = [P(Scene), ctypes.c_int32, P(View), ctypes.c_int32,
                                 P(Options), P(Plan), vp, vp, vp, P(SceneGrad), vp]
+    L.sdgr_forward_static.argtypes = [P(Scene), ctypes.c_int32, P(View), ctypes.c_int32,
+                                      P(Options), vp, vp]
     L.sdgr_status.argtypes = [P(Plan), vp, vp]
     L.sdgr_read_intensity.argtypes = [P(Plan), vp, vp, vp]
     L.sdgr_read_optical_depth.argtypes = [P(Plan), vp, vp, vp]
@@ -109,7 +113,7 @@ def lib():
     L.sdgr_read_work.argtypes = [P(Plan), vp, P(ctypes.c_uint64), ctypes.c_int32, vp]
     for name in ("sdgr_plan_resize", "sdgr_profile_count", "sdgr_read_work",
                  "sdgr_profile_enable", "sdgr_profile_read", "sdgr_plan_query", "sdgr_forward", "sdgr_backward", "sdgr_status",
-                 "sdgr_read_intensity", "sdgr_read_optical_depth"):
+                 "sdgr_read_intensity", "sdgr_read_optical_depth", "sdgr_forward_static"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -571,6 +571,37 @@ int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan
     return SDGR_OK;
 }
 
+// ---- workspace for callers that cannot allocate device memory -----------
+// One fixed array per device, held until the process ends. Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// for the symbol): it takes each device's address once with
+// hipGetSymbolAddress and uses that.
+constexpr size_t STATIC_SCRATCH_BYTES = SDGR_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+struct StaticScratchPtrs {
+    std::mutex mu;
+    std::vector<char*> ptr;   // per device ordinal, null until first use
+};
+StaticScratchPtrs g_static;
+
+int static_scratch(char** out)
+{
+    int dev = -1;
+    SDGR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_static.mu);
+    if ((int)g_static.ptr.size() <= dev) g_static.ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_static.ptr[dev]) {
+        void* p = nullptr;
+        SDGR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || ((uintptr_t)p & 255))
+            return fail(SDGR_EHIP, "static scratch has no usable device address");
+        g_static.ptr[dev] = static_cast<char*>(p);
+    }
+    *out = g_static.ptr[dev];
+    return SDGR_OK;
+}
+
 }  // namespace
 }  // namespace sdgr
 
@@ -740,6 +771,32 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,
                                     b.grad_c, b.grad_i, P.records, b.pgrad, s));
     return SDGR_OK;
+}
+
+int sdgr_forward_static(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* views,
+                        int32_t nv, const sdgr_options* opt, float* images, void* stream)
+{
+    g_last_error.clear();
+    Problem P;
+    int rc = build_problem(scenes, nscenes, views, nv, opt, P);
+    if (rc) return rc;
+    if (!images) return fail(SDGR_EINVAL, "images is null");
+    char* base = nullptr;
+    if ((rc = static_scratch(&base))) return rc;
+    const size_t qb = (sdgr_query_bytes(nscenes, nv) + 255) & ~size_t(255);
+    if (qb > STATIC_SCRATCH_BYTES)
+        return fail(SDGR_EUNSUPPORTED, "too many views or scenes for the static workspace");
+    hipStream_t s = (hipStream_t)stream;
+    sdgr_plan plan{};
+    if ((rc = count_and_plan(P, base, s, &plan))) return rc;
+    const size_t sb = (plan.state_bytes + 255) & ~size_t(255);
+    const size_t need = qb + sb + plan.fwd_scratch_bytes;
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(SDGR_EUNSUPPORTED,
+                    "problem needs " + std::to_string(need) + " bytes of workspace; the static "
+                    "workspace holds " + std::to_string(STATIC_SCRATCH_BYTES));
+    return sdgr_forward(scenes, nscenes, views, nv, opt, &plan, base + qb, base + qb + sb,
+                        images, stream);
 }
 
 int sdgr_status(const sdgr_plan* plan, const void* state, void* stream)
