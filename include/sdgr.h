@@ -260,9 +260,10 @@ const char* sdgr_profile_stage(int32_t i);
  * plane tile read in pass A forward and backward (out[8], out[9]), the
  * batches whose footprint hits did not fit one compaction round, counted
  * once per extra group, in pass A forward and backward (out[10], out[11]),
- * the rays stopped at tau_max (out[12]) and the longest list prefix one
- * tile used (out[13]); out[14..15] are 0. The counting adds atomics, so
- * timed runs leave it off.
+ * the rays stopped at tau_max (out[12]), the longest list prefix one
+ * tile used (out[13]) and the tiles the pass A backward ran as long lists
+ * (at least 2048 entries) and as short ones (out[14], out[15]). The
+ * counting adds atomics, so timed runs leave it off.
  * sdgr_read_work synchronises `stream` and copies min(n, 16) counters of
  * the last forward (and backward) that used `state`. */
 int sdgr_profile_count(int32_t on);

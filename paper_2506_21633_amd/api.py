@@ -259,7 +259,7 @@ class Renderer:
 WORK_NAMES = ("hits_a_fwd", "hits_a_bwd", "hits_b_fwd", "hits_b_bwd", "rounds_a_fwd",
               "rounds_a_bwd", "rounds_b_fwd", "list_prefix_a", "max_batches_a_fwd",
               "max_batches_a_bwd", "extra_hit_groups_a_fwd", "extra_hit_groups_a_bwd",
-              "rays_stopped_tau_max", "max_list_prefix_a", "unused14", "unused15")
+              "rays_stopped_tau_max", "max_list_prefix_a", "tiles_a_bwd_long", "tiles_a_bwd_short")
 
 
 def count_work(on: bool) -> None:

@@ -304,7 +304,7 @@ enum Phase { FWD, BWD };
 constexpr int STATUS_WORDS = 64 + 66;   // status words, then the worklist bins
 static_assert(WORK_WORD + 2 * WORK_COUNTERS <= 64, "work counters overlap the worklist bins");
 constexpr int ST_RECORDS = 12;   // device copy of the record count (sort length)
-constexpr int WL_BINS = 64;      // 66 words of worklist bins after the status words
+constexpr int WL_BINS = WL_BINS_WORD;   // 66 words of worklist bins after the status words
 
 void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* state,
             char* scratch, Bufs& b, size_t* state_bytes, size_t* scratch_bytes)

@@ -59,11 +59,16 @@ struct RasterParams {
     // most chunk batches one tile read in pass A forward, backward; [10],
     // [11] hit groups beyond the first of a batch (batches whose hits
     // overflow the compaction buffer) in pass A forward, backward; [12] rays
-    // stopped at tau_max; [13] longest list prefix one tile used
+    // stopped at tau_max; [13] longest list prefix one tile used; [14], [15]
+    // tiles the pass A backward ran as long and as short lists
     unsigned long long* work = nullptr;
 };
 
 constexpr int WORK_WORD = 16;    // work counters live at status + 16
+// the tile worklist's bins follow the status words: bins[0..32] tile counts
+// by the bit length of the list length, bins[33..65] (after placement) the
+// number of tiles whose list has at least that bit length
+constexpr int WL_BINS_WORD = 64;
 constexpr int WORK_COUNTERS = 16;   // u64 each: status words 16 .. 47
 
 // Device-side scalars kept at the start of the state buffer.

@@ -815,9 +815,19 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
 // (lane = hit, hits of a ray back to front) the optical depth is a
 // segmented prefix sum and U a segmented prefix composition of the affine
 // maps U -> (1 - alpha) U + c alpha. The six per-entry gradient sums collect
-// in LDS and leave with one global atomic each per (tile, entry), sent by a
-// second wave of the workgroup so the first never waits on them.
-__global__ void __launch_bounds__(2 * WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
+// in LDS and leave with one global atomic each per (tile, entry).
+// Two variants, by list length (the worklist holds the long lists first;
+// when long lists are the majority the first variant runs every tile):
+//   FLUSHER (lists of at least 2^(LONG_LIST_BITS - 1) entries): a second wave
+//     of the workgroup sends each batch's atomics while the first goes on,
+//     so a long chain of batches never waits on them; two sum buffers and
+//     two copies picked by ray (fewer same-address LDS atomics);
+//   short lists: one wave sends its own atomics, one buffer and one copy:
+//     less than half the LDS, so more tiles run per CU.
+constexpr int LONG_LIST_BITS = 12;
+
+template <bool FLUSHER>
+__global__ void __launch_bounds__(FLUSHER ? 2 * WAVE : WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                RasterParams rp, const uint32_t* __restrict__ status,
                const uint32_t* __restrict__ worklist, const uint2* __restrict__ ranges,
@@ -837,20 +847,29 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     // per-entry gradient sums in GC copies, picked by ray so that the hits
     // of one entry from neighbouring rays in a round add to different
     // addresses (rows padded by one word: copies and rows differ in bank)
-    constexpr int GC = 2;
-    // two buffers: the second wave of the workgroup sends one batch's sums
-    // with atomics while the first accumulates the next batch in the other
-    __shared__ float s_G[2][GC][NB][6][WAVE + 1];
-    __shared__ uint32_t s_rf[2][NB][WAVE];   // records of the handed-off entries
-    __shared__ uint32_t s_cmd[2][WAVE];      // per entry lane: chunks gathered (bits), last flag
+    constexpr int GC = FLUSHER ? 2 : 1;
+    // two buffers with the flusher: the second wave of the workgroup sends
+    // one batch's sums with atomics while the first accumulates the next
+    // batch in the other
+    constexpr int GB = FLUSHER ? 2 : 1;
+    __shared__ float s_G[GB][GC][NB][6][WAVE + 1];
+    __shared__ uint32_t s_rf[GB][FLUSHER ? NB : 1][WAVE];   // records of the handed-off entries
+    __shared__ uint32_t s_cmd[GB][WAVE];      // per entry lane: chunks gathered (bits), last flag
     __shared__ uint32_t s_chk[NB];
     __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray, chunk, entry) packed, ray-major, back to front
     // per ray during a chunk: first hit in s_hit, optical depth, U
     struct alignas(16) RayB { uint32_t o; float t, U, pad; };
     __shared__ RayB s_ray[WAVE];
-    if (blockIdx.x >= status[ST_WORK_TILES]) return;
+    // worklist entries [0, nlong) hold the long lists; when they are the
+    // majority the run is bound by their chains and the flusher variant
+    // takes every tile (short ones then fill its gaps)
+    const uint32_t ntiles = status[ST_WORK_TILES];
+    uint32_t nlong = status[WL_BINS_WORD + 33 + LONG_LIST_BITS];
+    if (2u * nlong >= ntiles) nlong = ntiles;
+    const uint32_t wi = FLUSHER ? blockIdx.x : nlong + blockIdx.x;
+    if (wi >= (FLUSHER ? nlong : ntiles)) return;
     constexpr uint32_t LAST = 1u << 31;
-    if (threadIdx.x >= WAVE) {
+    if (FLUSHER && threadIdx.x >= WAVE) {
         // the flusher: per hand-off, the six sums of every handed-off entry
         // leave with one atomic each, and the buffer is cleared for reuse
         const int fl = threadIdx.x - WAVE;
@@ -876,7 +895,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
         }
     }
     const int lane = threadIdx.x;
-    const int64_t bucket = worklist[blockIdx.x];
+    const int64_t bucket = worklist[wi];
     const TileCell tc = tile_cell(views, nv, bucket, true);
     const DevView& V = views[tc.v];
     const float x0 = (float)(tc.tx * TILE) + 0.5f, y0 = (float)(tc.ty * TILE) + 0.5f;
@@ -886,7 +905,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     float t = tc.inside ? tau[ray] : 0.0f;
     float U = 0.0f;
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < GB; ++b)
 #pragma unroll
         for (int g = 0; g < GC; ++g)
 #pragma unroll
@@ -897,18 +916,33 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     unsigned long long n_batch = 0, n_group = 0;
     const uint32_t n_max = wave_max_u32(n_mine);
     const uint32_t e_end = rg.x + n_max;           // exclusive end of the used entries
-    // the six per-entry sums of the last processed batch go to the flusher
-    // wave once the next batch's loads have landed; the barrier also returns
-    // the buffer the flusher emptied last
+    // the six per-entry sums of the last processed batch leave once the next
+    // batch's loads have landed: handed to the flusher wave (the barrier also
+    // returns the buffer it emptied last), or sent by this wave before the
+    // next batch accumulates into the same buffer
     uint32_t got_prev = 0u;
     uint32_t r_prev[NB], r_cur[NB];   // record of my entry in each chunk
     int hb = 0;                        // buffer the current batch accumulates in
     auto flush = [&](bool last) {
+        if constexpr (FLUSHER) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) s_rf[hb][k][lane] = r_prev[k];
-        s_cmd[hb][lane] = got_prev | (last ? LAST : 0u);
-        __syncthreads();
-        hb ^= 1;
+            for (int k = 0; k < NB; ++k) s_rf[hb][k][lane] = r_prev[k];
+            s_cmd[hb][lane] = got_prev | (last ? LAST : 0u);
+            __syncthreads();
+            hb ^= 1;
+        } else {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                if (!(got_prev & (1u << k))) continue;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const float v = s_G[0][0][k][c][lane];
+                    s_G[0][0][k][c][lane] = 0.0f;
+                    if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + r_prev[k]], v);
+                }
+            }
+            wave_lds_sync();
+        }
         got_prev = 0u;
     };
     const int64_t c_first = rg.x / WAVE, c_end = (int64_t)(e_end + WAVE - 1) / WAVE;
@@ -1120,6 +1154,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
             atomicAdd(&rp.work[1], n_hits);
             atomicMax(&rp.work[9], n_batch);
             atomicAdd(&rp.work[11], n_group - n_batch);
+            atomicAdd(&rp.work[FLUSHER ? 14 : 15], 1ull);
         }
     }
 }
@@ -1246,8 +1281,12 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                float* grad_c, int64_t stride, hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_a_bwd, dim3((unsigned)tiles_c), dim3(2 * WAVE), 0, s, views, nv, rp,
-                       status, worklist, ranges, pvals, pmask, psum, cq, cw, tau, nlast, cbwd,
+    // long lists (the front of the worklist), then the short ones
+    hipLaunchKernelGGL(k_raster_a_bwd<true>, dim3((unsigned)tiles_c), dim3(2 * WAVE), 0, s, views,
+                       nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, tau, nlast,
+                       cbwd, grad_c, stride);
+    hipLaunchKernelGGL(k_raster_a_bwd<false>, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views, nv,
+                       rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, tau, nlast, cbwd,
                        grad_c, stride);
     return hipGetLastError();
 }

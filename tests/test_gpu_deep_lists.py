@@ -139,12 +139,14 @@ def check_report(report):
 
 def check_deep_paths(work, bwd_groups=True):
     # several batches of 8 list chunks in one tile, batches split into hit
-    # groups, rays stopped at the optical-depth cut-off
+    # groups, rays stopped at the optical-depth cut-off, the long-list
+    # backward kernel
     assert work["max_batches_a_fwd"] >= 2 and work["max_batches_a_bwd"] >= 2, work
     assert work["extra_hit_groups_a_fwd"] > 0, work
     assert work["extra_hit_groups_a_bwd"] > 0 or not bwd_groups, work
     assert work["rays_stopped_tau_max"] > 0, work
     assert work["max_list_prefix_a"] > 2048, work
+    assert work["tiles_a_bwd_long"] > 0, work
 
 
 # --------------------------------------------------------- dense small scenes
