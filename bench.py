@@ -62,6 +62,8 @@ def parse():
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE to bytes)")
     ap.add_argument("--no-other-workloads", action="store_true",
                     help="skip the short runs of the 1k-Gaussian and building workloads")
+    ap.add_argument("--no-deterministic", action="store_true",
+                    help="skip the short run of the same workload in the deterministic mode")
     ap.add_argument("--with-large", action="store_true",
                     help="also time the 2M-Gaussian recompute workload (a few seconds)")
     return ap.parse_args()
@@ -374,6 +376,22 @@ def main():
         dom = max(per, key=per.get)
         out["roofline"] = roofline(dom, per[dom], used, work)
         out["kernels_hbm"] = {k: kernel_hbm(k, per[k], used) for k in ALGO_BYTES if k in per}
+    if not args.no_deterministic:
+        # the same step with ordered sums instead of float atomics
+        rd = api.Renderer([g], views, api.RenderOptions(recompute=opts.recompute,
+                                                        deterministic=True))
+        dstep = make_step(rd, target_images)
+        for _ in range(2):
+            dstep()
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dstep()
+        torch.cuda.synchronize(dev)
+        ddt = (time.perf_counter() - t0) / 5
+        out["deterministic"] = {"value": nv / ddt, "unit": "images/s",
+                                "ms_per_step": ddt * 1e3, "steps": 5}
+        del rd, dstep
     if not args.no_other_workloads:
         out["workloads"] = {
             "fwd_1k": time_workload("fwd_1k", dev, 50, 5, forward_only=True),

@@ -117,6 +117,14 @@ typedef struct sdgr_options {
                             <= 0 disables early termination */
     float dilation;      /* added to the diagonal of every projected 2D
                             covariance, in pixels^2 (0 = none) */
+    int32_t deterministic;  /* 1: repeated calls on the same inputs give
+                            bitwise identical images and gradients: every
+                            sum over tiles or list segments runs in a fixed
+                            order (per-pair partials reduced per Gaussian in
+                            list order, one wave per image tile) instead of
+                            float atomics; costs extra memory and time */
+    int32_t tile;        /* tile side in cells: 0 (default) or 8, the one
+                            size built; other values give SDGR_EUNSUPPORTED */
     int32_t reserved;    /* must be 0 */
 } sdgr_options;
 
@@ -138,6 +146,8 @@ typedef struct sdgr_plan {
     int32_t nviews, nscenes;
     int32_t tile;              /* tile side in pixels (8) */
     int32_t recompute;         /* copy of options.recompute */
+    int32_t deterministic;     /* copy of options.deterministic */
+    int32_t reserved;
 } sdgr_plan;
 
 /* Library version (SDGR_VERSION). */
@@ -147,7 +157,7 @@ int sdgr_version(void);
 const char* sdgr_last_error(void);
 
 /* Fill `opt` with the defaults: shadowing 1, recompute 0, q_max 9,
- * tau_max 16, dilation 0. */
+ * tau_max 16, dilation 0, deterministic 0, tile 0 (8). */
 void sdgr_default_options(sdgr_options* opt);
 
 /* Bytes of device scratch that sdgr_plan_query needs for nscenes scenes

@@ -52,7 +52,8 @@ class View(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("shadowing", ctypes.c_int32), ("recompute", ctypes.c_int32),
                 ("q_max", ctypes.c_float), ("tau_max", ctypes.c_float),
-                ("dilation", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("dilation", ctypes.c_float), ("deterministic", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Plan(ctypes.Structure):
@@ -64,7 +65,8 @@ class Plan(ctypes.Structure):
                 ("pairs_i", ctypes.c_int64), ("tiles_c", ctypes.c_int64),
                 ("tiles_i", ctypes.c_int64), ("rays", ctypes.c_int64),
                 ("gaussians", ctypes.c_int64), ("nviews", ctypes.c_int32), ("nscenes", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("recompute", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("recompute", ctypes.c_int32),
+                ("deterministic", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SDGRError(RuntimeError):

@@ -31,6 +31,7 @@ class RenderOptions:
     q_max: float = 9.0
     tau_max: float = 16.0
     dilation: float = 0.0
+    deterministic: bool = False
 
     def to_c(self) -> C.Options:
         o = C.Options()
@@ -39,6 +40,8 @@ class RenderOptions:
         o.q_max = float(self.q_max)
         o.tau_max = float(self.tau_max)
         o.dilation = float(self.dilation)
+        o.deterministic = int(bool(self.deterministic))
+        o.tile = 0
         o.reserved = 0
         return o
 

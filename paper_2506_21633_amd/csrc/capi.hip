@@ -115,6 +115,7 @@ struct Problem {
     int64_t records = 0, rays = 0, tiles_c = 0, tiles_i = 0, items = 0, pixels = 0;
     int64_t image_floats = 0;
     bool recompute = false;
+    bool det = false;       // ordered sums instead of float atomics
     bool ikey_vm = false;   // imaging keys (tile within the view << 8) | view
     bool seg = false;       // depth and pair sorts segmented by view
     int cbits = 0;          // bits of the computation-plane tile within a view
@@ -146,9 +147,14 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         return fail(SDGR_EINVAL, "shadowing must be 0 or 1");
     if (opt->recompute != 0 && opt->recompute != 1)
         return fail(SDGR_EINVAL, "recompute must be 0 or 1");
+    if (opt->deterministic != 0 && opt->deterministic != 1)
+        return fail(SDGR_EINVAL, "deterministic must be 0 or 1");
+    if (opt->tile != 0 && opt->tile != TILE)
+        return fail(SDGR_EUNSUPPORTED, "tile side must be 0 or 8 (the one size built)");
     P.nv = nv;
     P.ns = nscenes;
     P.recompute = opt->recompute != 0;
+    P.det = opt->deterministic != 0;
     double eps = exp(-0.5 * (double)opt->q_max);
     P.rp.q_max = opt->q_max;
     P.rp.eps = (float)eps;
@@ -285,6 +291,17 @@ struct Bufs {
     float* pgrad = nullptr;         // per-view-group parts of the parameter gradients
     float* cbwd = nullptr;          // c = P dL/dI per record (pass A backward)
     uint32_t* active = nullptr;     // records with A > 0 (backward)
+    // deterministic mode: the computation-plane pairs' positions before the
+    // pair sort (where each (tile, record) partial lands, so that a record's
+    // partials are contiguous), the records in depth order and the first
+    // pair of each, the partials of A and of the six plane-C gradient sums,
+    // and the imaging-plane tile ranges
+    uint32_t* ppos[2] = {nullptr, nullptr};
+    uint32_t* dord = nullptr;
+    uint32_t* poff = nullptr;
+    float* part_a = nullptr;
+    float* part_g = nullptr;
+    uint2* ranges_i = nullptr;
 };
 
 struct Arena {
@@ -329,6 +346,12 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.psum = a.take<uint64_t>(cap_c / WAVE + 1);
         b.ranges = a.take<uint2>(P.tiles_c);
         b.worklist = a.take<uint32_t>(P.tiles_c);
+        if (P.det) {
+            b.ppos[0] = a.take<uint32_t>(cap_c);
+            b.ppos[1] = a.take<uint32_t>(cap_c);
+            b.dord = a.take<uint32_t>(R);
+            b.poff = a.take<uint32_t>(R);
+        }
     };
     auto transient = [&](Arena& a) {
         b.rect_c = a.take<uint2>(R);
@@ -347,6 +370,10 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         int64_t hw = (int64_t)std::max(radix_hist_words(R), radix_hist_words(K));
         b.hist = a.take<uint32_t>(hw);
         b.slots = a.take<unsigned long long>(2 * TOTAL_SLOTS);
+        if (P.det) {
+            b.part_a = a.take<float>(cap_c);
+            b.ranges_i = a.take<uint2>(P.tiles_i);
+        }
     };
     if (!P.recompute) geo(st);
     if (ph == FWD) {
@@ -361,6 +388,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.grad_i = sc.take<float>(6 * R);
         b.cbwd = sc.take<float>(R);
         b.pgrad = sc.take<float>((int64_t)params_part_floats(P.nv, P.items));
+        if (P.det) b.part_g = sc.take<float>(6 * cap_c);
     }
     if (state_bytes) *state_bytes = st.off;
     if (scratch_bytes) *scratch_bytes = sc.off;
@@ -408,6 +436,7 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
         plan->tiles_i != P.tiles_i || plan->gaussians != P.items || plan->nviews != P.nv ||
         plan->nscenes != P.ns ||
         plan->tile != TILE || plan->recompute != (P.recompute ? 1 : 0) ||
+        plan->deterministic != (P.det ? 1 : 0) ||
         plan->pairs_c < 0 || plan->pairs_i < 0 || plan->pairs_c + plan->pairs_i > INT32_MAX)
         return fail(SDGR_EINVAL, "plan does not match the scenes, views and options");
     // the workspaces the plan promises must hold the layout of its capacities
@@ -477,7 +506,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool z
         SDGR_HIP(launch_pair_total_c(plan->pairs_c, b.status, s));
         SDGR_HIP(launch_emit_pairs_c(b.views, P.nv, R, dv[which], b.rect_c_sorted, b.bsum_c,
                                      plan->pairs_c, b.status, pk[0], pv[0],
-                                     P.seg ? b.segt[1].seg : nullptr, s));
+                                     P.seg ? b.segt[1].seg : nullptr, b.dord, b.poff, s));
     }
     int pw = 0;
     {
@@ -485,9 +514,11 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool z
         if (P.seg)
             SDGR_HIP(launch_seg_setup(b.views, P.nv, R, b.status + ST_PAIRS_C, true, &b.segt[1],
                                       s));
+        uint32_t* pp[2] = {b.ppos[0], b.ppos[1]};
         SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_c, b.status + ST_PAIRS_C,
                                        bits_pairs_c(P), false, b.hist, &pw, s, 0,
-                                       P.seg ? &b.segt[1] : nullptr, P.nv));
+                                       P.seg ? &b.segt[1] : nullptr, P.nv, true,
+                                       P.det ? pp : nullptr));
     }
     if (plan->pairs_c > 0 && pw != final_buffer_c(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
@@ -561,6 +592,7 @@ int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan
     out.nscenes = P.ns;
     out.tile = TILE;
     out.recompute = P.recompute ? 1 : 0;
+    out.deterministic = P.det ? 1 : 0;
     out.image_floats = (size_t)P.image_floats;
     Bufs b;
     layout(P, out.pairs_c, out.pairs_i, FWD, nullptr, nullptr, b, &out.state_bytes,
@@ -621,6 +653,8 @@ void sdgr_default_options(sdgr_options* opt)
     opt->q_max = 9.0f;
     opt->tau_max = 16.0f;
     opt->dilation = 0.0f;
+    opt->deterministic = 0;
+    opt->tile = 0;
     opt->reserved = 0;
 }
 
@@ -662,6 +696,7 @@ int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i)
     P.tiles_i = plan->tiles_i;
     P.items = plan->gaussians;   // sizes the parameter-gradient parts
     P.recompute = plan->recompute != 0;
+    P.det = plan->deterministic != 0;
     plan->pairs_c = pairs_c;
     plan->pairs_i = pairs_i;
     Bufs b;
@@ -698,9 +733,19 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     SDGR_HIP(launch_fill_u32(b.nlast, 0u, P.rays, s));
     {
         StageTimer t(SG_RASTER_A_FWD, s);
-        SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, P.rp, b.status, b.worklist,
+        RasterParams rp = P.rp;
+        if (P.det) {
+            // one partial per (tile, record) pair, summed per record in list order
+            SDGR_HIP(launch_fill_u32((uint32_t*)b.part_a, 0u, plan->pairs_c, s));
+            rp.ppos = b.ppos[pw];
+            rp.part = b.part_a;
+        }
+        SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
                                      b.ranges, b.pval[pw], b.pmask, b.psum, b.cq, b.cw, b.A,
                                      b.tau, b.nlast, s));
+        if (P.det)
+            SDGR_HIP(launch_reduce_pairs(b.dord, b.poff, P.records, b.status, b.part_a, 1,
+                                         plan->pairs_c, b.A, P.records, s));
     }
     {
         StageTimer t(SG_INTENSITY, s);
@@ -710,8 +755,15 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     if ((rc = build_lists_i(P, plan, b, s))) return rc;
     const int pwi = final_buffer_i(P);
     StageTimer t(SG_RASTER_B_FWD, s);
-    SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.pixels, plan->pairs_c, plan->pairs_i, P.rp,
-                                 b.status, b.pkey[pwi], b.pval[pwi], b.iq, b.iw, images, P.ikey_vm, s));
+    if (P.det)
+        SDGR_HIP(launch_raster_b_tiles(b.views, P.nv, P.pixels, plan->pairs_c, plan->pairs_i,
+                                       P.tiles_c, P.tiles_i, P.rp, b.status, b.pkey[pwi],
+                                       b.pval[pwi], b.iq, b.iw, b.ranges_i, images, P.ikey_vm,
+                                       s));
+    else
+        SDGR_HIP(launch_raster_b_fwd(b.views, P.nv, P.pixels, plan->pairs_c, plan->pairs_i, P.rp,
+                                     b.status, b.pkey[pwi], b.pval[pwi], b.iq, b.iw, images,
+                                     P.ikey_vm, s));
     return SDGR_OK;
 }
 
@@ -763,9 +815,19 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     }
     {
         StageTimer t(SG_RASTER_A_BWD, s);
-        SDGR_HIP(launch_raster_a_bwd(b.views, P.nv, P.tiles_c, P.rp, b.status, b.worklist,
+        RasterParams rp = P.rp;
+        if (P.det) {
+            SDGR_HIP(launch_fill_u32((uint32_t*)b.part_g, 0u, 6 * plan->pairs_c, s));
+            rp.ppos = b.ppos[pw];
+            rp.part = b.part_g;
+            rp.part_stride = plan->pairs_c;
+        }
+        SDGR_HIP(launch_raster_a_bwd(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
                                      b.ranges, b.pval[pw], b.pmask, b.psum, b.cq, b.cw, b.tau,
                                      b.nlast, b.cbwd, b.grad_c, P.records, s));
+        if (P.det)
+            SDGR_HIP(launch_reduce_pairs(b.dord, b.poff, P.records, b.status, b.part_g, 6,
+                                         plan->pairs_c, b.grad_c, P.records, s));
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,
@@ -823,6 +885,8 @@ static int read_state_array(const sdgr_plan* plan, const void* state, float* out
     P.rays = plan->rays;
     P.tiles_c = plan->tiles_c;
     P.tiles_i = plan->tiles_i;
+    P.recompute = plan->recompute != 0;
+    P.det = plan->deterministic != 0;
     Bufs b;
     layout(P, plan->pairs_c, plan->pairs_i, FWD, (char*)state, nullptr, b, nullptr, nullptr);
     const float* src = which == 0 ? b.A : b.tau;

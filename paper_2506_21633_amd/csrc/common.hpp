@@ -62,6 +62,13 @@ struct RasterParams {
     // stopped at tau_max; [13] longest list prefix one tile used; [14], [15]
     // tiles the pass A backward ran as long and as short lists
     unsigned long long* work = nullptr;
+    // deterministic mode (null = off): every computation-plane pair's
+    // position before the pair sort; pass A writes its per-(tile, record)
+    // sums there, in `part` (component k at k * part_stride), instead of
+    // adding them into the records' sums with float atomics
+    const uint32_t* ppos = nullptr;
+    float* part = nullptr;
+    int64_t part_stride = 0;
 };
 
 constexpr int WORK_WORD = 16;    // work counters live at status + 16
@@ -274,12 +281,14 @@ int radix_passes_for(int bits);   // passes a sort of `bits` key bits takes
 // Stable LSD radix sort of (key, value) pairs on the low `bits` key bits,
 // n_dev items (at most cap); iota_vals: the input values are the positions
 // 0..n-1 and vals[0] is not read. *which: the buffer holding the result
-// (with keys_out false only the values are valid there).
+// (with keys_out false only the values are valid there). vals2 (optional,
+// two buffers): a second value array that ends up holding every item's
+// input position (vals2[*which] after the sort).
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  int* which, hipStream_t s, int shift0 = 0,
                                  const SegTable* segt = nullptr, int S = 0,
-                                 bool keys_out = true);
+                                 bool keys_out = true, uint32_t* const* vals2 = nullptr);
 // Segment table of a segmented sort over the views: records (pairs = false)
 // or computation-plane pairs (pairs = true; seg[] as the emission wrote it),
 // n_dev items in all.
@@ -297,10 +306,19 @@ hipError_t launch_scan_blocks(uint32_t* bsum, int64_t n, int64_t cap, uint32_t* 
                               int status_slot, hipStream_t s);
 // overflow check and actual pair counts from the projection's u64 totals
 hipError_t launch_pair_total_c(int64_t cap_c, uint32_t* status, hipStream_t s);
+// (dord, poff optional: the record at each depth rank and its first pair)
 hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
                                const uint32_t* dval_sorted, const uint2* rect_sorted,
                                const uint32_t* bscan_c, int64_t cap_c, const uint32_t* status,
-                               uint32_t* pkey, uint32_t* pval, uint32_t* seg, hipStream_t s);
+                               uint32_t* pkey, uint32_t* pval, uint32_t* seg, uint32_t* dord,
+                               uint32_t* poff, hipStream_t s);
+// out[k * out_stride + dord[p]] = sum of part[k * part_stride + i] over the
+// pairs i in [poff[p], poff[p + 1]) in order (the last record's end is
+// status[ST_PAIRS_C]), for every depth rank p < records and k < ncomp.
+hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64_t records,
+                               const uint32_t* status, const float* part, int ncomp,
+                               int64_t part_stride, float* out, int64_t out_stride,
+                               hipStream_t s);
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
                                const uint2* rect_i, const uint32_t* cnt_i,
                                const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i, bool vm,
@@ -327,6 +345,17 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
                                int64_t cap_i, const RasterParams& rp, const uint32_t* status,
                                const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
                                const float2* iw, float* images, bool vm, hipStream_t s);
+hipError_t launch_ranges_i(const DevView* views, const uint32_t* keys, const uint32_t* status,
+                           int64_t cap_i, int64_t tiles_c, int64_t tiles_i, bool vm,
+                           uint2* ranges, hipStream_t s);
+// Deterministic pass B: one wave per imaging tile over its whole list (in
+// list order per pixel), from the imaging-plane tile ranges it builds.
+hipError_t launch_raster_b_tiles(const DevView* views, int nv, int64_t pixels, int64_t cap_c,
+                                 int64_t cap_i, int64_t tiles_c, int64_t tiles_i,
+                                 const RasterParams& rp, const uint32_t* status,
+                                 const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
+                                 const float2* iw, uint2* ranges_i, float* images, bool vm,
+                                 hipStream_t s);
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
                             int64_t records, const RasterParams& rp, const uint32_t* status,
                             const uint32_t* active, const float4* iq, const float2* iw,

@@ -28,6 +28,7 @@
 //   pass B backward: one thread per record walks its footprint ellipse and
 //                    gathers dL/dS (no atomics).
 #include <cfloat>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -359,6 +360,8 @@ k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParam
 // and leave with one global atomic per (tile, entry).
 constexpr int A_BATCH = 4;
 
+// DET: deterministic mode (per-pair partials at their pre-sort positions)
+template <bool DET>
 __global__ void __launch_bounds__(WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                const uint32_t* __restrict__ status, const uint32_t* __restrict__ worklist,
@@ -406,6 +409,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     // those loads never waits for the atomics
     uint32_t got_prev = 0u;
     uint32_t r_prev[NB], r_cur[NB];   // record of my entry in each chunk
+    uint32_t d_prev[NB], d_cur[NB];   // deterministic mode: its pair's position before the sort
     auto flush = [&]() {
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -416,7 +420,10 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     a += s_A[g][k][lane];
                     s_A[g][k][lane] = 0.0f;
                 }
-                if (a != 0.0f) unsafeAtomicAdd(&A[r_prev[k]], a);
+                if (a != 0.0f) {
+                    if constexpr (DET) rp.part[d_prev[k]] = a;
+                    else unsafeAtomicAdd(&A[r_prev[k]], a);
+                }
             }
         }
         got_prev = 0u;
@@ -449,6 +456,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     const bool in = k < nb && e >= rg.x && e < rg.y;
                     m[k] = in ? pmask[e] : 0ull;
                     r[k] = in ? pvals[e] : 0u;
+                    if constexpr (DET) d_cur[k] = in ? rp.ppos[e] : 0u;
                 }
                 // records straight into LDS, all in flight together (entries
                 // no live ray needs read record 0, one shared line)
@@ -473,7 +481,10 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
             flush();
             got_prev = got;
 #pragma unroll
-            for (int k = 0; k < NB; ++k) r_prev[k] = r_cur[k];
+            for (int k = 0; k < NB; ++k) {
+                r_prev[k] = r_cur[k];
+                if constexpr (DET) d_prev[k] = d_cur[k];
+            }
             // the batch's chunks, transposed: bit j of col[k] is entry j of
             // chunk k covering my cell (rays already out of play keep none)
             uint64_t col[NB];
@@ -730,6 +741,55 @@ k_raster_b_fwd(const DevView* __restrict__ views, int nv, RasterParams rp, int64
     }
 }
 
+// Deterministic pass B: one wave per imaging tile (bucket tiles_c + t) walks
+// its whole list, 64 entries at a time: lane = entry while the records load
+// and the footprint masks form, then lane = pixel adding the entries that
+// cover it in list order. Every pixel is written once, by a plain store on
+// the zeroed image, so repeated runs agree bit for bit.
+__global__ void __launch_bounds__(RASTER_THREADS)
+k_raster_b_tile(const DevView* __restrict__ views, int nv, RasterParams rp, int64_t cap_c,
+                int64_t tiles_c, int64_t tiles_i, const uint2* __restrict__ ranges_i,
+                const uint32_t* __restrict__ pvals, const float4* __restrict__ iq,
+                const float2* __restrict__ iw, float* __restrict__ images)
+{
+    __shared__ float4 s_q[RASTER_WAVES][WAVE];
+    __shared__ float2 s_w[RASTER_WAVES][WAVE];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int64_t t = (int64_t)blockIdx.x * RASTER_WAVES + w;
+    if (t >= tiles_i) return;
+    const uint2 rg = ranges_i[t];
+    if (rg.y <= rg.x) return;
+    const TileCell tc = tile_cell(views, nv, tiles_c + t, false);
+    const DevView& V = views[tc.v];
+    const float px = tc.col + 0.5f, py = tc.row + 0.5f;
+    float acc = 0.0f;
+    for (uint32_t b0 = rg.x; b0 < rg.y; b0 += WAVE) {
+        const uint32_t e = b0 + lane;
+        uint64_t m = 0ull;
+        if (e < rg.y) {
+            const uint32_t r = pvals[cap_c + e];
+            const float4 g = iq[r];
+            const float2 g2 = iw[r];
+            s_q[w][lane] = g;
+            s_w[w][lane] = g2;
+            if (g2.y != 0.0f)   // zero intensity adds nothing
+                m = footprint_mask(g.x, g.y, g.z, g.w, g2.x, rp.q_max, tc.tx, tc.ty);
+        }
+        wave_lds_sync();
+        uint64_t col = tc.inside ? transpose64(m) : 0ull;
+        while (col != 0ull) {
+            const int j = __builtin_ctzll(col);
+            col &= col - 1ull;
+            const float4 g = s_q[w][j];
+            const float2 g2 = s_w[w][j];
+            const float q = quadform(g, g2.x, px - g.x, py - g.y);
+            if (q < rp.q_max) acc += (__expf(-0.5f * q) - rp.eps) * rp.inv1meps * g2.y;
+        }
+        wave_lds_sync();
+    }
+    if (tc.inside) images[V.img_off + (int64_t)tc.row * V.W + tc.col] = acc;
+}
+
 // Imaging-plane backward, one thread per used record (view, Gaussian): the
 // additive image formation has no order, so each thread walks its own
 // footprint ellipse q < q_max row by row (exact column span from the conic,
@@ -826,7 +886,7 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
 //     less than half the LDS, so more tiles run per CU.
 constexpr int LONG_LIST_BITS = 12;
 
-template <bool FLUSHER>
+template <bool FLUSHER, bool DET>
 __global__ void __launch_bounds__(FLUSHER ? 2 * WAVE : WAVE) __attribute__((amdgpu_waves_per_eu(1, 2)))
 k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                RasterParams rp, const uint32_t* __restrict__ status,
@@ -888,7 +948,9 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                         v += s_G[hb][g][k][c][fl];
                         s_G[hb][g][k][c][fl] = 0.0f;
                     }
-                    if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + rk], v);
+                    if (v == 0.0f) continue;
+                    if constexpr (DET) rp.part[c * rp.part_stride + rk] = v;
+                    else unsafeAtomicAdd(&grad_c[c * stride + rk], v);
                 }
             }
             if (cmd & LAST) return;
@@ -921,7 +983,9 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     // returns the buffer it emptied last), or sent by this wave before the
     // next batch accumulates into the same buffer
     uint32_t got_prev = 0u;
-    uint32_t r_prev[NB], r_cur[NB];   // record of my entry in each chunk
+    // where each entry's sums go: its record, or in deterministic mode its
+    // pair's position before the sort
+    uint32_t r_prev[NB], r_cur[NB];
     int hb = 0;                        // buffer the current batch accumulates in
     auto flush = [&](bool last) {
         if constexpr (FLUSHER) {
@@ -938,7 +1002,9 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                 for (int c = 0; c < 6; ++c) {
                     const float v = s_G[0][0][k][c][lane];
                     s_G[0][0][k][c][lane] = 0.0f;
-                    if (v != 0.0f) unsafeAtomicAdd(&grad_c[c * stride + r_prev[k]], v);
+                    if (v == 0.0f) continue;
+                    if constexpr (DET) rp.part[c * rp.part_stride + r_prev[k]] = v;
+                    else unsafeAtomicAdd(&grad_c[c * stride + r_prev[k]], v);
                 }
             }
             wave_lds_sync();
@@ -982,12 +1048,15 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                         nb = k + 1;
                     }
                 }
+                uint32_t rec[NB];
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     const uint32_t e = chk[k] * WAVE + lane;
                     const bool in = k < nb && e >= rg.x && e < e_end;
                     m[k] = in ? pmask[e] : 0ull;
-                    r[k] = in ? pvals[e] : 0u;
+                    rec[k] = in ? pvals[e] : 0u;
+                    if constexpr (DET) r[k] = in ? rp.ppos[e] : 0u;
+                    else r[k] = rec[k];
                 }
                 // records straight into LDS, all in flight together (entries
                 // no ray needs read record 0 of the view, one shared line)
@@ -995,7 +1064,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                 for (int k = 0; k < NB; ++k) {
                     const bool need = (m[k] & lv[k]) != 0ull;
                     got |= need ? 1u << k : 0u;
-                    const uint32_t rk = need ? r[k] : (uint32_t)V.rec_off;
+                    const uint32_t rk = need ? rec[k] : (uint32_t)V.rec_off;
                     const float* w = reinterpret_cast<const float*>(cw + rk);
                     load16_to_lds(cq + rk, &s_q[k][0]);
                     load4_to_lds(w, &s_wc[k][0]);
@@ -1240,8 +1309,14 @@ hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
                                float* A, float* tau, uint32_t* nlast, hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_raster_a_fwd, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views, nv, rp,
-                       status, worklist, ranges, pvals, pmask, psum, cq, cw, A, tau, nlast);
+    if (rp.ppos)
+        hipLaunchKernelGGL(k_raster_a_fwd<true>, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views,
+                           nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, A, tau,
+                           nlast);
+    else
+        hipLaunchKernelGGL(k_raster_a_fwd<false>, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views,
+                           nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, A, tau,
+                           nlast);
     return hipGetLastError();
 }
 
@@ -1257,6 +1332,25 @@ hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int
     const int64_t segs = (cap_i + B_SEGMENT - 1) / B_SEGMENT;
     hipLaunchKernelGGL(k_raster_b_fwd, dim3(raster_grid(segs)), dim3(RASTER_THREADS), 0, s, views,
                        nv, rp, cap_c, status, pkey, pvals, iq, iw, images, vm ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_raster_b_tiles(const DevView* views, int nv, int64_t pixels, int64_t cap_c,
+                                 int64_t cap_i, int64_t tiles_c, int64_t tiles_i,
+                                 const RasterParams& rp, const uint32_t* status,
+                                 const uint32_t* pkey, const uint32_t* pvals, const float4* iq,
+                                 const float2* iw, uint2* ranges_i, float* images, bool vm,
+                                 hipStream_t s)
+{
+    if (pixels <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_images, dim3(grid256(pixels)), dim3(256), 0, s, views, nv, pixels,
+                       images);
+    if (cap_i <= 0 || tiles_i <= 0) return hipGetLastError();
+    hipError_t e = launch_ranges_i(views, pkey + cap_c, status, cap_i, tiles_c, tiles_i, vm,
+                                   ranges_i, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_raster_b_tile, dim3(raster_grid(tiles_i)), dim3(RASTER_THREADS), 0, s,
+                       views, nv, rp, cap_c, tiles_c, tiles_i, ranges_i, pvals, iq, iw, images);
     return hipGetLastError();
 }
 
@@ -1282,12 +1376,19 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
 {
     if (tiles_c <= 0) return hipSuccess;
     // long lists (the front of the worklist), then the short ones
-    hipLaunchKernelGGL(k_raster_a_bwd<true>, dim3((unsigned)tiles_c), dim3(2 * WAVE), 0, s, views,
-                       nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, tau, nlast,
-                       cbwd, grad_c, stride);
-    hipLaunchKernelGGL(k_raster_a_bwd<false>, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views, nv,
-                       rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, tau, nlast, cbwd,
-                       grad_c, stride);
+    auto two = [&](auto det) {
+        constexpr bool D = decltype(det)::value;
+        hipLaunchKernelGGL((k_raster_a_bwd<true, D>), dim3((unsigned)tiles_c), dim3(2 * WAVE), 0,
+                           s, views, nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw,
+                           tau, nlast, cbwd, grad_c, stride);
+        hipLaunchKernelGGL((k_raster_a_bwd<false, D>), dim3((unsigned)tiles_c), dim3(WAVE), 0, s,
+                           views, nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw,
+                           tau, nlast, cbwd, grad_c, stride);
+    };
+    if (rp.ppos)
+        two(std::true_type{});
+    else
+        two(std::false_type{});
     return hipGetLastError();
 }
 

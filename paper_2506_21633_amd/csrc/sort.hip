@@ -271,14 +271,16 @@ k_radix_spine(uint32_t* __restrict__ hist, uint32_t* __restrict__ tot,
 // offsets, places the items in LDS in digit order and writes them out so
 // that the items of one digit leave as a contiguous run. The block's next
 // position per digit carries over from tile to tile. With vin null the
-// values are the items' input positions.
-template <int BITS, bool SEG>
+// values are the items' input positions. V2 moves a second value array
+// along (vin2 null: the input positions).
+template <int BITS, bool SEG, bool V2>
 __global__ void __launch_bounds__(SB)
 k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                 uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                 const uint32_t* __restrict__ n_dev, int shift,
                 const uint32_t* __restrict__ offs, const uint32_t* __restrict__ tot,
-                const SegTable* __restrict__ segt, int S)
+                const SegTable* __restrict__ segt, int S,
+                const uint32_t* __restrict__ vin2, uint32_t* __restrict__ vout2)
 {
     constexpr int R = 1 << BITS;
     constexpr int NW = SB / WAVE;
@@ -288,6 +290,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
     __shared__ uint32_t wsum[NW];
     __shared__ uint32_t s_key[SN];
     __shared__ uint32_t s_val[SN];
+    __shared__ uint32_t s_val2[V2 ? SN : 1];
     __shared__ uint32_t s_tp[SEG ? SEG_MAX + 1 : 1];
     BlockItems bi;
     if constexpr (SEG) {
@@ -339,7 +342,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
         __syncthreads();   // wsum is reused per tile
     }
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
-    uint32_t key[SI], val[SI], rank[SI];
+    uint32_t key[SI], val[SI], rank[SI], val2[V2 ? SI : 1];
     auto load_tile = [&](int64_t blk) {
 #pragma unroll
         for (int k = 0; k < SI; ++k) {
@@ -347,6 +350,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
             const bool valid = idx < n;
             key[k] = valid ? kin[idx] : 0u;
             val[k] = valid ? (vin ? vin[idx] : (uint32_t)idx) : 0u;
+            if constexpr (V2) val2[k] = valid ? (vin2 ? vin2[idx] : (uint32_t)idx) : 0u;
         }
     };
     const int64_t first = bi.first;
@@ -425,6 +429,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
                 const uint32_t pos = wc[w][d] + rank[k];
                 s_key[pos] = key[k];
                 s_val[pos] = val[k];
+                if constexpr (V2) s_val2[pos] = val2[k];
             }
         }
         // the next tile's items load while this one is written out
@@ -436,6 +441,7 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
             const uint32_t g = gbase[((k - bi.kb) >> shift) & (R - 1)] + i;
             if (kout) kout[g] = k;
             vout[g] = s_val[i];
+            if constexpr (V2) vout2[g] = s_val2[i];
         }
     }
 }
@@ -450,7 +456,8 @@ inline unsigned pass_grid(int64_t cap, int S, bool seg)
 template <int BITS, bool SEG>
 hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
-                        int shift0, const SegTable* segt, int S, bool keys_out)
+                        int shift0, const SegTable* segt, int S, bool keys_out,
+                        uint32_t* const* vals2)
 {
     constexpr int R = 1 << BITS;
     const unsigned grid = pass_grid(cap, S, SEG);
@@ -463,9 +470,16 @@ hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const
         const uint32_t* vin = (iota_vals && shift == shift0) ? nullptr : vals[*cur];
         // the last pass writes no keys when the caller needs only the values
         uint32_t* kout = (keys_out || shift + BITS < shift0 + bits) ? keys[*cur ^ 1] : nullptr;
-        hipLaunchKernelGGL((k_radix_scatter<BITS, SEG>), dim3(grid), dim3(SB), 0, s,
-                           keys[*cur], vin, kout, vals[*cur ^ 1], n_dev, shift, hist, tot, segt,
-                           S);
+        if (vals2) {
+            const uint32_t* vin2 = shift == shift0 ? nullptr : vals2[*cur];
+            hipLaunchKernelGGL((k_radix_scatter<BITS, SEG, true>), dim3(grid), dim3(SB), 0, s,
+                               keys[*cur], vin, kout, vals[*cur ^ 1], n_dev, shift, hist, tot,
+                               segt, S, vin2, vals2[*cur ^ 1]);
+        } else {
+            hipLaunchKernelGGL((k_radix_scatter<BITS, SEG, false>), dim3(grid), dim3(SB), 0, s,
+                               keys[*cur], vin, kout, vals[*cur ^ 1], n_dev, shift, hist, tot,
+                               segt, S, nullptr, nullptr);
+        }
         *cur ^= 1;
     }
     return hipGetLastError();
@@ -474,24 +488,26 @@ hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const
 template <bool SEG>
 hipError_t radix_sort_t(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
-                        int shift0, const SegTable* segt, int S, bool keys_out)
+                        int shift0, const SegTable* segt, int S, bool keys_out,
+                        uint32_t* const* vals2)
 {
     switch (digit_bits(bits)) {
     case 8:
         return radix_passes<8, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
-                                    segt, S, keys_out);
+                                    segt, S, keys_out, vals2);
     case 9:
         return radix_passes<9, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
-                                    segt, S, keys_out);
+                                    segt, S, keys_out, vals2);
     default:
         return radix_passes<10, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s,
-                                     shift0, segt, S, keys_out);
+                                     shift0, segt, S, keys_out, vals2);
     }
 }
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                       int bits, bool iota_vals, uint32_t* hist, int* which, hipStream_t s,
-                      int shift0, const SegTable* segt, int S, bool keys_out)
+                      int shift0, const SegTable* segt, int S, bool keys_out,
+                      uint32_t* const* vals2)
 {
     int cur = 0;
     *which = 0;
@@ -499,9 +515,9 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
     if (segt && (S < 1 || S > SEG_MAX)) return hipErrorInvalidValue;
     const hipError_t e =
         segt ? radix_sort_t<true>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
-                                  segt, S, keys_out)
+                                  segt, S, keys_out, vals2)
              : radix_sort_t<false>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
-                                   nullptr, 0, keys_out);
+                                   nullptr, 0, keys_out, vals2);
     *which = cur;
     return e;
 }
@@ -704,7 +720,8 @@ __global__ void __launch_bounds__(256)
 k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
          const uint32_t* __restrict__ dval, const uint2* __restrict__ rect_sorted,
          const uint32_t* __restrict__ bscan, int64_t cap_c, const uint32_t* __restrict__ status,
-         uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t* __restrict__ seg)
+         uint32_t* __restrict__ pkey, uint32_t* __restrict__ pval, uint32_t* __restrict__ seg,
+         uint32_t* __restrict__ dord, uint32_t* __restrict__ poff)
 {
     __shared__ uint32_t s_w[4];
     __shared__ int64_t s_off[LDS_VIEWS];
@@ -724,6 +741,10 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
     uint32_t tot;
     const uint32_t ex = block_excl_scan_256((tx1 - tx0) * (ty1 - ty0), s_w, tot);
     if (p >= records) return;
+    if (poff) {   // deterministic mode: the record at this depth rank and its first pair
+        poff[p] = bscan[blockIdx.x] + ex;
+        dord[p] = dval[p];
+    }
     int vp = -1;   // the view of position p, when the order is view-major
     if (seg && cached) {
         // view-major order (segmented depth sort): the first record of each
@@ -764,6 +785,48 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
                 pkey[o] = tile0 + ty * txc + tx;
                 pval[o] = r;
             }
+}
+
+// Deterministic sums over the computation-plane pairs: thread = depth rank
+// p, its record's pairs are [poff[p], next) before the pair sort (one
+// record's tiles, row by row); their partials are added in that order.
+__global__ void __launch_bounds__(256)
+k_reduce_pairs(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ poff,
+               int64_t records, const uint32_t* __restrict__ status,
+               const float* __restrict__ part, int ncomp, int64_t part_stride,
+               float* __restrict__ out, int64_t out_stride)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= records) return;
+    const uint32_t kc = status[ST_PAIRS_C];
+    const uint32_t lo = min(poff[p], kc);
+    const uint32_t hi = p + 1 < records ? min(poff[p + 1], kc) : kc;
+    const uint32_t r = dord[p];
+    for (int k = 0; k < ncomp; ++k) {
+        const float* src = part + (int64_t)k * part_stride;
+        float acc = 0.0f;
+        for (uint32_t i = lo; i < hi; ++i) acc += src[i];
+        out[(int64_t)k * out_stride + r] = acc;
+    }
+}
+
+// Imaging-plane tile ranges (deterministic pass B): runs of equal keys in
+// the sorted imaging-plane keys, indexed by the tile's imaging bucket minus
+// tiles_c (keys (tile within the view << 8) | view when vm).
+__global__ void __launch_bounds__(256)
+k_ranges_i(const DevView* __restrict__ views, const uint32_t* __restrict__ keys,
+           const uint32_t* __restrict__ status, int64_t cap_i, int64_t tiles_c, int64_t tiles_i,
+           int vm, uint2* __restrict__ ranges)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = min((int64_t)status[ST_PAIRS_I], cap_i);
+    if (p >= n) return;
+    const uint32_t k = keys[p];
+    const int64_t t = vm ? (int64_t)views[k & 0xFFu].tile_i - tiles_c + (k >> 8)
+                         : (int64_t)k - tiles_c;
+    if (t < 0 || t >= tiles_i) return;
+    if (p == 0 || keys[p - 1] != k) ranges[t].x = (uint32_t)p;
+    if (p == n - 1 || keys[p + 1] != k) ranges[t].y = (uint32_t)(p + 1);
 }
 
 // Imaging-plane pairs of the records in index order, only for the records
@@ -883,10 +946,10 @@ int radix_passes_for(int bits)
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  int* which, hipStream_t s, int shift0, const SegTable* segt,
-                                 int S, bool keys_out)
+                                 int S, bool keys_out, uint32_t* const* vals2)
 {
     return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s, shift0, segt, S,
-                      keys_out);
+                      keys_out, vals2);
 }
 
 hipError_t launch_seg_setup(const DevView* views, int nv, int64_t records, const uint32_t* n_dev,
@@ -932,12 +995,36 @@ hipError_t launch_pair_total_c(int64_t cap_c, uint32_t* status, hipStream_t s)
 hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
                                const uint32_t* dval_sorted, const uint2* rect_sorted,
                                const uint32_t* bscan_c, int64_t cap_c, const uint32_t* status,
-                               uint32_t* pkey, uint32_t* pval, uint32_t* seg, hipStream_t s)
+                               uint32_t* pkey, uint32_t* pval, uint32_t* seg, uint32_t* dord,
+                               uint32_t* poff, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     if (seg && nv > LDS_VIEWS) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_emit_c, dim3(grid256(records)), dim3(256), 0, s, views, nv, records,
-                       dval_sorted, rect_sorted, bscan_c, cap_c, status, pkey, pval, seg);
+                       dval_sorted, rect_sorted, bscan_c, cap_c, status, pkey, pval, seg, dord,
+                       poff);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64_t records,
+                               const uint32_t* status, const float* part, int ncomp,
+                               int64_t part_stride, float* out, int64_t out_stride,
+                               hipStream_t s)
+{
+    if (records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_pairs, dim3(grid256(records)), dim3(256), 0, s, dord, poff,
+                       records, status, part, ncomp, part_stride, out, out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges_i(const DevView* views, const uint32_t* keys, const uint32_t* status,
+                           int64_t cap_i, int64_t tiles_c, int64_t tiles_i, bool vm,
+                           uint2* ranges, hipStream_t s)
+{
+    hipError_t e = launch_fill_u32((uint32_t*)ranges, 0u, 2 * tiles_i, s);
+    if (e != hipSuccess || cap_i <= 0) return e;
+    hipLaunchKernelGGL(k_ranges_i, dim3(grid256(cap_i)), dim3(256), 0, s, views, keys, status,
+                       cap_i, tiles_c, tiles_i, vm ? 1 : 0, ranges);
     return hipGetLastError();
 }
 

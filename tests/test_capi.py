@@ -50,8 +50,8 @@ def test_struct_layout_matches_header(tmp_path):
 def test_default_options():
     o = C.Options()
     C.lib().sdgr_default_options(ctypes.byref(o))
-    assert (o.shadowing, o.recompute, o.q_max, o.tau_max, o.dilation, o.reserved) == \
-        (1, 0, 9.0, 16.0, 0.0, 0)
+    assert (o.shadowing, o.recompute, o.q_max, o.tau_max, o.dilation, o.deterministic, o.tile,
+            o.reserved) == (1, 0, 9.0, 16.0, 0.0, 0, 0, 0)
 
 
 def _args(grazing=math.radians(45), nv=1, n=10, q_max=9.0, scene=0, w=64):

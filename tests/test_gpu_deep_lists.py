@@ -155,16 +155,19 @@ DENSE_VIEWS = [scenes.View.from_degrees(20.0, 45.0, 64, 0.05),
                scenes.View.from_degrees(140.0, 30.0, 64, 0.05)]
 
 
-@pytest.mark.parametrize("recompute", [False, True])
+@pytest.mark.parametrize("recompute,deterministic", [(False, False), (True, False),
+                                                     (False, True)])
 @pytest.mark.parametrize("kappa", [(0.05, 0.3), (1.0, 4.0)])
-def test_dense_lists_elementwise(cuda, kappa, recompute):
+def test_dense_lists_elementwise(cuda, kappa, recompute, deterministic):
     """20k Gaussians in a 1.2 m cube at 5 cm cells: tile lists of thousands
     of entries. Thin extinction walks most of each list before the cut-off;
-    the workloads' extinction (1-4) stops the core rays early."""
+    the workloads' extinction (1-4) stops the core rays early. Also in the
+    deterministic mode (ordered sums instead of float atomics)."""
     sc = dense_scene(61, 20_000, 0.6, 0.02, 0.1, *kappa)
     rng = scenes.make_rng(62)
     G = [rng.standard_normal((64, 64)) for _ in DENSE_VIEWS]
-    out = gpu_run(sc, DENSE_VIEWS, G, api().RenderOptions(recompute=recompute), cuda)
+    out = gpu_run(sc, DENSE_VIEWS, G,
+                  api().RenderOptions(recompute=recompute, deterministic=deterministic), cuda)
     A_ref, _, S_ref = oracle.forward(sc, DENSE_VIEWS)
     report = {}
     for v in range(len(DENSE_VIEWS)):
@@ -172,7 +175,8 @@ def test_dense_lists_elementwise(cuda, kappa, recompute):
         report[f"S{v}"] = elem_err(out["images"][v], S_ref[v])
     ref, auxes = oracle.backward(sc, DENSE_VIEWS, G)
     grad_report(out, ref, *near_cutoff(auxes), report)
-    print(f"\ndense kappa={kappa} recompute={recompute}: {report} work={out['work']}")
+    print(f"\ndense kappa={kappa} recompute={recompute} deterministic={deterministic}: "
+          f"{report} work={out['work']}")
     check_report(report)
     # the backward's batches overflow the compaction buffer only where rays
     # walk deep (thin extinction)

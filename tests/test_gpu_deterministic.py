@@ -1,0 +1,64 @@
+"""The deterministic option: repeated calls on the same inputs give bitwise
+identical images, shares A and gradients (ordered per-Gaussian sums of the
+per-(tile, Gaussian) partials, one wave per image tile), with stored state
+and with recomputation, at the benchmark's 72-view vehicle launch and on a
+scene with several scenes and image sizes in one launch; and the option
+changes results only within FP32 rounding of the default mode."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2506_21633_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def run(scs, views, cuda, **opts):
+    from paper_2506_21633_amd import api
+    r = api.Renderer([api.GaussianTensors.from_numpy(x, cuda) for x in scs], views,
+                     api.RenderOptions(**opts))
+    res = r.forward()
+    G = torch.randn(int(res.plan.image_floats), device=cuda,
+                    generator=torch.Generator(cuda).manual_seed(11))
+    grads = r.backward(res, G)
+    torch.cuda.synchronize()
+    r.status(res)
+    out = {"images": res.images.cpu().numpy(), "A": r.intensity_shares(res).cpu().numpy()}
+    for s_, d in enumerate(grads):
+        for k, t in d.items():
+            out[f"{s_}.{k}"] = t.cpu().numpy()
+    return out
+
+
+def assert_bitwise(a, b):
+    for k in a:
+        assert a[k].tobytes() == b[k].tobytes(), k
+
+
+def mixed_scene():
+    rng = scenes.make_rng(81)
+    sc = [scenes.vehicle(82, 20_000), scenes.vehicle(83, 5_000)]
+    views = [scenes.View.from_degrees(float(rng.uniform(0, 360)), 30.0 + 15 * (k % 2),
+                                      [64, 128, 96][k % 3], 0.08, scene=k % 2)
+             for k in range(7)]
+    return sc, views
+
+
+@pytest.mark.parametrize("recompute", [False, True])
+def test_deterministic_repeats_bitwise_mixed_launch(cuda, recompute):
+    sc, views = mixed_scene()
+    a = run(sc, views, cuda, deterministic=True, recompute=recompute)
+    b = run(sc, views, cuda, deterministic=True, recompute=recompute)
+    assert_bitwise(a, b)
+    # same result as the default mode up to FP32 summation order
+    c = run(sc, views, cuda, deterministic=False, recompute=recompute)
+    for k in a:
+        scale = max(np.abs(c[k]).max(), 1e-30)
+        assert np.abs(a[k] - c[k]).max() <= 1e-4 * scale, k
+
+
+def test_deterministic_repeats_bitwise_vehicle_72_views(cuda):
+    sc, views = scenes.vehicle(303, 200_000), scenes.vehicle_views()
+    a = run([sc], views, cuda, deterministic=True)
+    b = run([sc], views, cuda, deterministic=True)
+    assert_bitwise(a, b)
