@@ -58,21 +58,23 @@ def lib():
         L.orc_view.argtypes = [_dp, _dp]
         L.orc_project.argtypes = [_i64, _dp, _dp, _dp, _dp, ctypes.c_double,
                                   ctypes.c_double, _dp]
-        L.orc_forward.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, _dp,
+        X = [_dp, _dp, _i64, _i64]   # ext_back, sh, sh_deg, cell_area
+        L.orc_forward.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, *X, _dp,
                                   ctypes.c_double, ctypes.c_double,
                                   ctypes.c_int, _dp, _dp, _dp]
-        L.orc_backward.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, _dp,
+        L.orc_backward.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, *X, _dp,
                                    ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int, _dp, _dp, _dp, _dp, _dp,
-                                   _dp, _dp]
-        L.orc_sparse_forward.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, _dp,
+                                   _dp, _dp, _dp, _dp]
+        L.orc_sparse_forward.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, *X, _dp,
                                          ctypes.c_double, ctypes.c_double,
                                          ctypes.c_int, _i64, _ip, _dp, _i64,
                                          _ip, _dp]
-        L.orc_fd_linear.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, _dp,
+        L.orc_fd_linear.argtypes = [_i64, _dp, _dp, _dp, _dp, _dp, *X, _dp,
                                     ctypes.c_double, ctypes.c_double,
                                     ctypes.c_int, _dp, _i64, ctypes.c_int,
                                     ctypes.c_double, _dp]
+        L.orc_sh_basis.argtypes = [_i64, _dp, _i64, _dp]
         _lib = L
     return _lib
 
@@ -89,7 +91,8 @@ def view_params(v) -> np.ndarray:
     return np.array([v.azimuth, v.grazing, v.img_w, v.img_h, v.d_az, v.d_rg,
                      getattr(v, "comp_w", 0), getattr(v, "comp_h", 0),
                      getattr(v, "comp_d_az", 0.0),
-                     getattr(v, "comp_d_el", 0.0)], dtype=np.float64)
+                     getattr(v, "comp_d_el", 0.0),
+                     getattr(v, "radar_range", 0.0)], dtype=np.float64)
 
 
 def resolved_view(v) -> dict:
@@ -98,7 +101,7 @@ def resolved_view(v) -> dict:
         raise ValueError("invalid view")
     return dict(W=int(out[0]), H=int(out[1]), dA=out[2], dR=out[3],
                 Wc=int(out[4]), Hc=int(out[5]), dAc=out[6], dEc=out[7],
-                ex=out[10:13].copy(), ey=out[13:16].copy(),
+                range=out[8], ex=out[10:13].copy(), ey=out[13:16].copy(),
                 ez=out[16:19].copy())
 
 
@@ -111,6 +114,23 @@ def axes(phi: float, theta: float):
 def _params(scene):
     return (_d(scene.means), _d(scene.scales), _d(scene.quats),
             _d(scene.amp), _d(scene.ext))
+
+
+def _extra(scene, cell_area):
+    """(ext_back, sh, sh_deg, cell_area) arguments and the arrays kept alive
+    behind them: the optional backward extinction and SH coefficients."""
+    eb = getattr(scene, "ext_back", None)
+    sh = getattr(scene, "sh", None)
+    eb = None if eb is None else _d(eb)
+    deg = 0
+    if sh is not None:
+        sh = _d(sh)
+        deg = int(round(np.sqrt(sh.shape[1]))) - 1
+        if (deg + 1) ** 2 != sh.shape[1] or not 0 <= deg <= 3:
+            raise ValueError("sh must hold (d+1)^2 coefficients per Gaussian, d <= 3")
+    args = (None if eb is None else _p(eb), None if sh is None else _p(sh), deg,
+            int(bool(cell_area)))
+    return args, (eb, sh)
 
 
 def project(scene, view, q_max: float = Q_MAX, dilation: float = 0.0) -> dict:
@@ -126,15 +146,17 @@ def project(scene, view, q_max: float = Q_MAX, dilation: float = 0.0) -> dict:
                 cI=out[:, 13:15], covI=out[:, 15:18], conI=out[:, 18:21])
 
 
-def forward_view(scene, view, q_max=Q_MAX, dilation=0.0, shadowing=True):
+def forward_view(scene, view, q_max=Q_MAX, dilation=0.0, shadowing=True,
+                 cell_area=False):
     """One view: returns (A[n], tau[Hc, Wc], S[H, W])."""
     m, s, q, a, e = _params(scene)
+    x, keep = _extra(scene, cell_area)
     n = m.shape[0]
     rv = resolved_view(view)
     A = np.zeros(n)
     tau = np.zeros((rv["Hc"], rv["Wc"]))
     S = np.zeros((rv["H"], rv["W"]))
-    if lib().orc_forward(n, _p(m), _p(s), _p(q), _p(a), _p(e),
+    if lib().orc_forward(n, _p(m), _p(s), _p(q), _p(a), _p(e), *x,
                          _p(view_params(view)), q_max, dilation,
                          int(bool(shadowing)), _p(A), _p(tau), _p(S)):
         raise ValueError("invalid arguments")
@@ -148,23 +170,32 @@ def forward(scene, views: Sequence, **kw):
             [o[2] for o in outs])
 
 
-def backward_view(scene, view, G, q_max=Q_MAX, dilation=0.0, shadowing=True):
+def backward_view(scene, view, G, q_max=Q_MAX, dilation=0.0, shadowing=True,
+                  cell_area=False):
     """Gradients of L with dL/dS = G for one view.
 
     Returns (grads dict, aux[n, 16]) where aux holds the per-Gaussian
-    intermediate quantities documented in the C source."""
+    intermediate quantities documented in the C source. The dict has
+    ext_back and sh entries when the scene has those inputs."""
     m, s, q, a, e = _params(scene)
+    x, keep = _extra(scene, cell_area)
     n = m.shape[0]
     G = _d(G)
     dm, ds = np.zeros((n, 3)), np.zeros((n, 3))
-    dq, da, de = np.zeros((n, 4)), np.zeros(n), np.zeros(n)
+    dq, da, de, deb = np.zeros((n, 4)), np.zeros(n), np.zeros(n), np.zeros(n)
+    dsh = np.zeros((n, 16 if keep[1] is None else keep[1].shape[1]))
     aux = np.zeros((n, 16))
-    if lib().orc_backward(n, _p(m), _p(s), _p(q), _p(a), _p(e),
+    if lib().orc_backward(n, _p(m), _p(s), _p(q), _p(a), _p(e), *x,
                           _p(view_params(view)), q_max, dilation,
                           int(bool(shadowing)), _p(G), _p(dm), _p(ds),
-                          _p(dq), _p(da), _p(de), _p(aux)):
+                          _p(dq), _p(da), _p(de), _p(deb), _p(dsh), _p(aux)):
         raise ValueError("invalid arguments")
-    return dict(means=dm, scales=ds, quats=dq, amp=da, ext=de), aux
+    out = dict(means=dm, scales=ds, quats=dq, amp=da, ext=de)
+    if keep[0] is not None:
+        out["ext_back"] = deb
+    if keep[1] is not None:
+        out["sh"] = dsh
+    return out, aux
 
 
 def backward(scene, views: Sequence, Gs: Sequence, **kw):
@@ -178,15 +209,16 @@ def backward(scene, views: Sequence, Gs: Sequence, **kw):
 
 
 def sparse_forward(scene, view, pix_ids, gids, q_max=Q_MAX, dilation=0.0,
-                   shadowing=True):
+                   shadowing=True, cell_area=False):
     """S at flat pixel ids (row * W + col) and A of Gaussians `gids`."""
     m, s, q, a, e = _params(scene)
+    x, keep = _extra(scene, cell_area)
     n = m.shape[0]
     pix = np.ascontiguousarray(pix_ids, dtype=np.int64)
     gid = np.ascontiguousarray(gids, dtype=np.int64)
     S = np.zeros(pix.shape[0])
     A = np.zeros(gid.shape[0])
-    if lib().orc_sparse_forward(n, _p(m), _p(s), _p(q), _p(a), _p(e),
+    if lib().orc_sparse_forward(n, _p(m), _p(s), _p(q), _p(a), _p(e), *x,
                                 _p(view_params(view)), q_max, dilation,
                                 int(bool(shadowing)), pix.shape[0],
                                 pix.ctypes.data_as(_ip), _p(S), gid.shape[0],
@@ -198,25 +230,52 @@ def sparse_forward(scene, view, pix_ids, gids, q_max=Q_MAX, dilation=0.0,
 # parameter components of one Gaussian, in the order orc_fd_linear numbers them
 FD_COMPONENTS = [("means", 0), ("means", 1), ("means", 2), ("scales", 0),
                  ("scales", 1), ("scales", 2), ("quats", 0), ("quats", 1),
-                 ("quats", 2), ("quats", 3), ("amp", None), ("ext", None)]
+                 ("quats", 2), ("quats", 3), ("amp", None), ("ext", None),
+                 ("ext_back", None)] + [("sh", k) for k in range(16)]
+
+
+def fd_components(scene):
+    """(comp, name, index) of the parameter components `scene` has."""
+    out = []
+    nsh = 0 if getattr(scene, "sh", None) is None else scene.sh.shape[1]
+    for c, (name, j) in enumerate(FD_COMPONENTS):
+        if name == "ext_back" and getattr(scene, "ext_back", None) is None:
+            continue
+        if name == "sh" and j >= nsh:
+            continue
+        if name == "amp" and nsh:
+            continue
+        out.append((c, name, j))
+    return out
 
 
 def fd_linear(scene, view, V, k, comp, h, q_max=Q_MAX, dilation=0.0,
-              shadowing=True):
+              shadowing=True, cell_area=False):
     """Central difference of L = <V, S> for one view when component `comp`
-    (see FD_COMPONENTS) of Gaussian k moves by +h and -h, recomputing exactly
-    only the rays and pixels the change reaches. Returns
-    (L(+h) - L(-h), order_changed)."""
+    (see FD_COMPONENTS; 12 needs ext_back, 13 + j the SH coefficients) of
+    Gaussian k moves by +h and -h, recomputing exactly only the rays and
+    pixels the change reaches. Returns (L(+h) - L(-h), order_changed)."""
     m, s, q, a, e = _params(scene)
+    x, keep = _extra(scene, cell_area)
     n = m.shape[0]
     Vd = _d(V)
     out = np.zeros(2)
-    if lib().orc_fd_linear(n, _p(m), _p(s), _p(q), _p(a), _p(e),
+    if lib().orc_fd_linear(n, _p(m), _p(s), _p(q), _p(a), _p(e), *x,
                            _p(view_params(view)), q_max, dilation,
                            int(bool(shadowing)), _p(Vd), int(k), int(comp),
                            float(h), _p(out)):
         raise ValueError("invalid arguments")
     return float(out[0]), bool(out[1])
+
+
+def sh_basis(dirs, deg: int) -> np.ndarray:
+    """Real spherical harmonics of degree <= deg at unit vectors dirs [m, 3]:
+    [m, (deg + 1)^2], index l*l + l + m."""
+    d = _d(np.atleast_2d(dirs))
+    Y = np.zeros((d.shape[0], (deg + 1) ** 2))
+    if lib().orc_sh_basis(d.shape[0], _p(d), deg, _p(Y)):
+        raise ValueError("invalid arguments")
+    return Y
 
 
 def threads() -> int:

@@ -46,7 +46,13 @@
  *     eps = exp(-q_max/2): continuous, peak 1, zero beyond the cutoff.
  *   - alpha_i = 1 - exp(-kappa_i g_i) with kappa = k_e+ + k_e-; transmittance
  *     over the Gaussians strictly in front; incident intensity 1; no
- *     cell-area factor.
+ *     cell-area factor unless asked for (then I = P A dAc dEc, the share
+ *     in m^2 of the plane perpendicular to the line of sight).
+ *   - the phase function's direction (Sec. II-B, SH coefficients per
+ *     Gaussian): from the Gaussian's centre to the radar, which sits on the
+ *     line of sight through the origin at the view's slant distance; a view
+ *     without one is a plane wave, the direction then -e_z everywhere and
+ *     the same for every Gaussian. Real SH to degree 3, orthonormal.
  *   - depth order: key fl32_rn(z computed in FP64), ties by ascending index.
  *   - computation plane spacing (d_az, d_rg tan(theta)) and size of the
  *     image by default (Eq. for P_C); imaging plane rows = slant range at
@@ -73,8 +79,25 @@ typedef struct {
     double dA, dR;          /* image spacings [m] */
     int64_t Wc, Hc;         /* computation-plane cells */
     double dAc, dEc;        /* computation-plane spacings [m] */
+    double range;           /* slant distance of the radar from the scene
+                               origin along the line of sight; 0: so far
+                               that the incident wave is plane */
     double ex[3], ey[3], ez[3];  /* rows of R_r */
 } OView;
+
+/* Per-Gaussian inputs beyond position, shape, the scalar amplitude P and the
+ * extinction: the paper's two extinction coefficients (forward and backward
+ * along the line of sight) enter only through their sum kappa = ext +
+ * ext_back; the phase function P may be a spherical-harmonics expansion in
+ * the direction from the Gaussian's centre to the radar; the intensity may
+ * be normalised by the computation-plane cell area. */
+typedef struct {
+    const double* ext_back;   /* [n] backward extinction, or NULL (ext is kappa) */
+    const double* sh;         /* [n, (sh_deg + 1)^2] SH coefficients of P, or
+                                 NULL (P = amp) */
+    int64_t sh_deg;           /* 0 .. 3 */
+    int64_t cell_area;        /* 1: I = P A times the cell area [m^2] */
+} OExtra;
 
 typedef struct {
     int valid;
@@ -99,9 +122,9 @@ void orc_axes(double phi, double theta, double* ex, double* ey, double* ez)
 }
 
 /* p = [azimuth, grazing, img_w, img_h, d_az, d_rg, comp_w, comp_h,
- *      comp_d_az, comp_d_el]; zeros in the comp_* slots take the defaults
- * of the computation-plane projection (same grid, elevation spacing
- * d_rg * tan(theta)). */
+ *      comp_d_az, comp_d_el, radar_range]; zeros in the comp_* slots take
+ * the defaults of the computation-plane projection (same grid, elevation
+ * spacing d_rg * tan(theta)); radar_range 0 is a plane incident wave. */
 static int view_init(OView* v, const double* p)
 {
     v->az = p[0]; v->gr = p[1];
@@ -111,9 +134,10 @@ static int view_init(OView* v, const double* p)
     v->Hc = p[7] > 0 ? (int64_t)p[7] : v->H;
     v->dAc = p[8] > 0 ? p[8] : v->dA;
     v->dEc = p[9] > 0 ? p[9] : v->dR * tan(v->gr);
+    v->range = p[10];
     if (!(v->gr > 0.0 && v->gr < M_PI / 2) || v->W <= 0 || v->H <= 0 ||
         v->Wc <= 0 || v->Hc <= 0 || !(v->dA > 0) || !(v->dR > 0) ||
-        !(v->dAc > 0) || !(v->dEc > 0))
+        !(v->dAc > 0) || !(v->dEc > 0) || !(v->range >= 0.0))
         return -1;
     orc_axes(v->az, v->gr, v->ex, v->ey, v->ez);
     return 0;
@@ -199,6 +223,116 @@ static void project(const OView* v, const double* mu, const double* s,
         bbox_of(g->cC, g->SC, q_max, g->bxC);
         bbox_of(g->cI, g->SI, q_max, g->bxI);
     }
+}
+
+/* ------------------------------------------------ phase and extinction */
+
+/* Real spherical harmonics of degree <= deg at the unit vector d = (x, y, z)
+ * (orthonormal on the sphere, no Condon-Shortley phase), index l*l + l + m
+ * for m = -l..l, written as polynomials in x, y, z; dY[3 k + j] (if not NULL)
+ * is the derivative of polynomial k with respect to component j. */
+static void sh_basis(const double* d, int64_t deg, double* Y, double* dY)
+{
+    const double x = d[0], y = d[1], z = d[2], pi = M_PI;
+    const double c0 = 0.5 * sqrt(1.0 / pi);
+    const double c1 = sqrt(3.0 / (4.0 * pi));
+    const double c2a = 0.5 * sqrt(15.0 / pi), c2b = 0.25 * sqrt(5.0 / pi),
+                 c2c = 0.25 * sqrt(15.0 / pi);
+    const double c3a = 0.25 * sqrt(35.0 / (2.0 * pi)), c3b = 0.5 * sqrt(105.0 / pi),
+                 c3c = 0.25 * sqrt(21.0 / (2.0 * pi)), c3d = 0.25 * sqrt(7.0 / pi),
+                 c3e = 0.25 * sqrt(105.0 / pi);
+    double v[16], g[16][3];
+    memset(g, 0, sizeof(g));
+    v[0] = c0;
+    v[1] = c1 * y;  g[1][1] = c1;
+    v[2] = c1 * z;  g[2][2] = c1;
+    v[3] = c1 * x;  g[3][0] = c1;
+    v[4] = c2a * x * y;  g[4][0] = c2a * y; g[4][1] = c2a * x;
+    v[5] = c2a * y * z;  g[5][1] = c2a * z; g[5][2] = c2a * y;
+    v[6] = c2b * (3.0 * z * z - 1.0);  g[6][2] = c2b * 6.0 * z;
+    v[7] = c2a * x * z;  g[7][0] = c2a * z; g[7][2] = c2a * x;
+    v[8] = c2c * (x * x - y * y);  g[8][0] = c2c * 2.0 * x; g[8][1] = -c2c * 2.0 * y;
+    v[9] = c3a * y * (3.0 * x * x - y * y);
+    g[9][0] = c3a * 6.0 * x * y; g[9][1] = c3a * (3.0 * x * x - 3.0 * y * y);
+    v[10] = c3b * x * y * z;
+    g[10][0] = c3b * y * z; g[10][1] = c3b * x * z; g[10][2] = c3b * x * y;
+    v[11] = c3c * y * (5.0 * z * z - 1.0);
+    g[11][1] = c3c * (5.0 * z * z - 1.0); g[11][2] = c3c * 10.0 * y * z;
+    v[12] = c3d * z * (5.0 * z * z - 3.0);  g[12][2] = c3d * (15.0 * z * z - 3.0);
+    v[13] = c3c * x * (5.0 * z * z - 1.0);
+    g[13][0] = c3c * (5.0 * z * z - 1.0); g[13][2] = c3c * 10.0 * x * z;
+    v[14] = c3e * z * (x * x - y * y);
+    g[14][0] = c3e * 2.0 * x * z; g[14][1] = -c3e * 2.0 * y * z; g[14][2] = c3e * (x * x - y * y);
+    v[15] = c3a * x * (x * x - 3.0 * y * y);
+    g[15][0] = c3a * (3.0 * x * x - 3.0 * y * y); g[15][1] = -c3a * 6.0 * x * y;
+    const int64_t ns = (deg + 1) * (deg + 1);
+    for (int64_t k = 0; k < ns; ++k) {
+        Y[k] = v[k];
+        if (dY)
+            for (int j = 0; j < 3; ++j) dY[3 * k + j] = g[k][j];
+    }
+}
+
+/* Unit vector from the centre mu to the radar, which sits on the line of
+ * sight through the origin at slant distance range on the near side
+ * (-range e_z); a plane wave (range 0) comes from -e_z everywhere. J (if
+ * not NULL) receives the 3x3 Jacobian dd/dmu, row-major. */
+static void radar_dir(const OView* v, const double* mu, double* d, double* J)
+{
+    if (!(v->range > 0.0)) {
+        for (int k = 0; k < 3; ++k) d[k] = -v->ez[k];
+        if (J) memset(J, 0, 9 * sizeof(double));
+        return;
+    }
+    double w[3], r2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        w[k] = -v->range * v->ez[k] - mu[k];
+        r2 += w[k] * w[k];
+    }
+    const double r = sqrt(r2);
+    for (int k = 0; k < 3; ++k) d[k] = w[k] / r;
+    if (J)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) J[3 * a + b] = -((a == b ? 1.0 : 0.0) - d[a] * d[b]) / r;
+}
+
+static int64_t sh_count(const OExtra* ex) { return (ex->sh_deg + 1) * (ex->sh_deg + 1); }
+
+/* The intensity factor of Gaussian i in this view: its phase function P
+ * (the scalar amp, or the SH expansion at the direction to the radar)
+ * times the cell area when normalised. */
+static double phase_of(const OView* v, const OExtra* ex, const double* amp,
+                       const double* mu, int64_t i)
+{
+    double P = amp ? amp[i] : 0.0;
+    if (ex->sh) {
+        double d[3], Y[16];
+        radar_dir(v, mu, d, NULL);
+        sh_basis(d, ex->sh_deg, Y, NULL);
+        const int64_t ns = sh_count(ex);
+        P = 0.0;
+        for (int64_t k = 0; k < ns; ++k) P += ex->sh[i * ns + k] * Y[k];
+    }
+    return ex->cell_area ? P * v->dAc * v->dEc : P;
+}
+
+static double kappa_of(const OExtra* ex, const double* ext, int64_t i)
+{
+    return ex->ext_back ? ext[i] + ex->ext_back[i] : ext[i];
+}
+
+/* Per-Gaussian phase factors and extinctions of one view. */
+static int prepare(const OView* v, const OExtra* ex, int64_t n, const double* means,
+                   const double* amp, const double* ext, double** peff, double** kap)
+{
+    *peff = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    *kap = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!*peff || !*kap) { free(*peff); free(*kap); *peff = *kap = NULL; return -2; }
+    for (int64_t i = 0; i < n; ++i) {
+        (*peff)[i] = phase_of(v, ex, amp, means + 3 * i, i);
+        (*kap)[i] = kappa_of(ex, ext, i);
+    }
+    return 0;
 }
 
 static OG* project_all(const OView* v, int64_t n, const double* means,
@@ -292,7 +426,7 @@ static int thread_id(void)
 int orc_version(void) { return ORC_VERSION; }
 int orc_threads(void) { return nthreads(); }
 
-/* Resolved view: out[0..9] = W, H, dA, dR, Wc, Hc, dAc, dEc, 0, 0;
+/* Resolved view: out[0..9] = W, H, dA, dR, Wc, Hc, dAc, dEc, range, 0;
  * out[10..18] = ex, ey, ez. */
 int orc_view(const double* p, double* out)
 {
@@ -300,7 +434,8 @@ int orc_view(const double* p, double* out)
     if (view_init(&v, p)) return -1;
     out[0] = (double)v.W; out[1] = (double)v.H; out[2] = v.dA; out[3] = v.dR;
     out[4] = (double)v.Wc; out[5] = (double)v.Hc; out[6] = v.dAc; out[7] = v.dEc;
-    out[8] = out[9] = 0.0;
+    out[8] = v.range;
+    out[9] = 0.0;
     for (int k = 0; k < 3; ++k) {
         out[10 + k] = v.ex[k]; out[13 + k] = v.ey[k]; out[16 + k] = v.ez[k];
     }
@@ -333,19 +468,25 @@ int orc_project(int64_t n, const double* means, const double* scales,
 }
 
 /* Forward of one view.
- * A[n]          scattering share of every Gaussian (I_i = amp_i * A_i)
+ * ext_back, sh, sh_deg, cell_area: see OExtra (NULL, NULL, 0, 0 for the
+ * scalar-amplitude model with kappa = ext).
+ * A[n]          scattering share of every Gaussian (I_i = P_i * A_i)
  * tau[Hc*Wc]    total optical depth of every ray (row-major [row][col])
  * S[H*W]        SAR image (row-major [range row][azimuth column])
  * shadowing=0 drops the transmittance (every Gaussian sees the full wave). */
 int orc_forward(int64_t n, const double* means, const double* scales,
                 const double* quats, const double* amp, const double* ext,
-                const double* view, double q_max, double dil, int shadowing,
-                double* A, double* tau, double* S)
+                const double* ext_back, const double* sh, int64_t sh_deg,
+                int64_t cell_area, const double* view, double q_max, double dil,
+                int shadowing, double* A, double* tau, double* S)
 {
     OView v;
-    if (n < 0 || view_init(&v, view) || !(q_max > 0)) return -1;
+    if (n < 0 || view_init(&v, view) || !(q_max > 0) || sh_deg < 0 || sh_deg > 3) return -1;
+    const OExtra ex = {ext_back, sh, sh_deg, cell_area};
     OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
     if (!G) return -2;
+    double *peff = NULL, *kap = NULL;
+    if (prepare(&v, &ex, n, means, amp, ext, &peff, &kap)) { free(G); return -2; }
     int nt = nthreads();
     double* At = (double*)calloc((size_t)nt * (size_t)(n > 0 ? n : 1), sizeof(double));
     int err = At ? 0 : -2;
@@ -361,7 +502,7 @@ int orc_forward(int64_t n, const double* means, const double* scales,
                 double t = 0.0;
                 for (int64_t k = 0; k < m; ++k) {
                     int64_t i = list[k].idx;
-                    double x = ext[i] * list[k].g;
+                    double x = kap[i] * list[k].g;
                     double alpha = 1.0 - exp(-x);
                     Amine[i] += shadowing ? alpha * exp(-t) : alpha;
                     t += x;
@@ -382,13 +523,15 @@ int orc_forward(int64_t n, const double* means, const double* scales,
             for (int64_t i = 0; i < n; ++i) {
                 if (!G[i].valid) continue;
                 double q = quadform(G[i].QI, px - G[i].cI[0], py - G[i].cI[1]);
-                if (q < q_max) acc += foot(q, q_max) * amp[i] * A[i];
+                if (q < q_max) acc += foot(q, q_max) * peff[i] * A[i];
             }
             S[p] = acc;
         }
     }
     free(At);
     free(G);
+    free(peff);
+    free(kap);
     return err;
 }
 
@@ -462,7 +605,10 @@ static void cov_to_params(const OG* g, const double* dSig, double* ds, double* d
 }
 
 /* Backward of one view for a cotangent Gimg = dL/dS [H*W].
- * Overwrites dmeans[3n], dscales[3n], dquats[4n], damp[n], dext[n].
+ * Overwrites dmeans[3n], dscales[3n], dquats[4n], damp[n] (0 with SH),
+ * dext[n], dext_back[n] (if not NULL; equal to dext: only the sum of the two
+ * extinctions enters) and dsh[n, (sh_deg + 1)^2] (if not NULL and sh is
+ * given).
  * aux (may be NULL) receives 16 doubles per Gaussian:
  *   [0] A  [1] dL/dI  [2..3] dL/dcI  [4..6] dL/dconic_I (a,b,c)
  *   [7..8] dL/dcC  [9..11] dL/dconic_C  [12] dL/dkappa  [13] dL/dA (= c)
@@ -472,37 +618,44 @@ static void cov_to_params(const OG* g, const double* dSig, double* ds, double* d
  *   inf for an invalid Gaussian) */
 int orc_backward(int64_t n, const double* means, const double* scales,
                  const double* quats, const double* amp, const double* ext,
-                 const double* view, double q_max, double dil, int shadowing,
-                 const double* Gimg, double* dmeans, double* dscales,
-                 double* dquats, double* damp, double* dext, double* aux)
+                 const double* ext_back, const double* sh, int64_t sh_deg,
+                 int64_t cell_area, const double* view, double q_max, double dil,
+                 int shadowing, const double* Gimg, double* dmeans, double* dscales,
+                 double* dquats, double* damp, double* dext, double* dext_back,
+                 double* dsh, double* aux)
 {
     OView v;
-    if (n < 0 || view_init(&v, view) || !(q_max > 0)) return -1;
+    if (n < 0 || view_init(&v, view) || !(q_max > 0) || sh_deg < 0 || sh_deg > 3) return -1;
+    const OExtra ex = {ext_back, sh, sh_deg, cell_area};
     int64_t nrays = v.Wc * v.Hc, npix = v.W * v.H;
     double* A = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double* tau = (double*)malloc(sizeof(double) * (size_t)nrays);
     double* S = (double*)malloc(sizeof(double) * (size_t)npix);
     if (!A || !tau || !S) { free(A); free(tau); free(S); return -2; }
-    int err = orc_forward(n, means, scales, quats, amp, ext, view, q_max, dil,
-                          shadowing, A, tau, S);
+    int err = orc_forward(n, means, scales, quats, amp, ext, ext_back, sh, sh_deg, cell_area,
+                          view, q_max, dil, shadowing, A, tau, S);
     free(tau); free(S);
     if (err) { free(A); return err; }
     OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
+    double *peff = NULL, *kap = NULL;
+    if (!G || prepare(&v, &ex, n, means, amp, ext, &peff, &kap)) {
+        free(A); free(G); return -2;
+    }
     /* per-Gaussian 2D gradients: dI, dcI(2), dQI(3), dcC(2), dQC(3), dk */
     double* g2 = (double*)calloc((size_t)(n > 0 ? n : 1) * 12, sizeof(double));
     int nt = nthreads();
     double* gt = (double*)calloc((size_t)nt * (size_t)(n > 0 ? n : 1) * 6, sizeof(double));
-    if (!G || !g2 || !gt) { free(A); free(G); free(g2); free(gt); return -2; }
+    if (!g2 || !gt) { free(A); free(G); free(g2); free(gt); free(peff); free(kap); return -2; }
 
     /* distance of the nearest cell to the footprint cutoff, both planes */
     double* edge = (double*)malloc(sizeof(double) * 2 * (size_t)(n > 0 ? n : 1));
-    if (!edge) { free(A); free(G); free(g2); free(gt); return -2; }
+    if (!edge) { free(A); free(G); free(g2); free(gt); free(peff); free(kap); return -2; }
     /* imaging plane: every Gaussian against every pixel */
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t i = 0; i < n; ++i) {
         edge[2 * i] = edge[2 * i + 1] = INFINITY;
         if (!G[i].valid) continue;
-        double I = amp[i] * A[i];
+        double I = peff[i] * A[i];
         double* o = g2 + 12 * i;
         for (int64_t p = 0; p < npix; ++p) {
             double dx = (double)(p % v.W) + 0.5 - G[i].cI[0];
@@ -534,7 +687,7 @@ int orc_backward(int64_t n, const double* means, const double* scales,
             int64_t m = ray_list(G, n, r % v.Wc, r / v.Wc, q_max, list);
             double t = 0.0;
             for (int64_t k = 0; k < m; ++k) {
-                double x = ext[list[k].idx] * list[k].g;
+                double x = kap[list[k].idx] * list[k].g;
                 T[k] = shadowing ? exp(-t) : 1.0;
                 al[k] = 1.0 - exp(-x);
                 t += x;
@@ -542,13 +695,13 @@ int orc_backward(int64_t n, const double* means, const double* scales,
             double suffix = 0.0;  /* sum_{j>k} c_j alpha_j T_j */
             for (int64_t k = m - 1; k >= 0; --k) {
                 int64_t i = list[k].idx;
-                double c = amp[i] * g2[12 * i];
+                double c = peff[i] * g2[12 * i];
                 double dx_ = c * (1.0 - al[k]) * T[k] - (shadowing ? suffix : 0.0);
                 suffix += c * al[k] * T[k];
                 double g = list[k].g;
                 double* o = mine + 6 * i;
                 o[0] += dx_ * g;                       /* dL/dkappa */
-                double dq = dx_ * ext[i] * dfoot(list[k].q, q_max);
+                double dq = dx_ * kap[i] * dfoot(list[k].q, q_max);
                 const double* Q = G[i].QC;
                 double ddx = list[k].dx, ddy = list[k].dy;
                 o[1] += dq * (-2.0 * (Q[0] * ddx + Q[1] * ddy));
@@ -592,24 +745,45 @@ int orc_backward(int64_t n, const double* means, const double* scales,
         for (int k = 0; k < 3; ++k) dm[k] = dsc[k] = 0.0;
         for (int k = 0; k < 4; ++k) dqu[k] = 0.0;
         damp[i] = dext[i] = 0.0;
+        if (dext_back) dext_back[i] = 0.0;
+        const int64_t ns = sh_count(&ex);
+        if (sh && dsh)
+            for (int64_t k = 0; k < ns; ++k) dsh[i * ns + k] = 0.0;
         const double* o = g2 + 12 * i;
         if (aux) {
             double* a = aux + 16 * i;
             a[0] = A[i]; a[1] = o[0];
             a[2] = o[1]; a[3] = o[2]; a[4] = o[3]; a[5] = o[4]; a[6] = o[5];
             a[7] = o[7]; a[8] = o[8]; a[9] = o[9]; a[10] = o[10]; a[11] = o[11];
-            a[12] = o[6]; a[13] = amp[i] * o[0];
+            a[12] = o[6]; a[13] = peff[i] * o[0];
             a[14] = edge[2 * i]; a[15] = edge[2 * i + 1];
         }
         if (!G[i].valid) continue;
-        damp[i] = A[i] * o[0];
+        /* dL/dP_eff = A dL/dI, with P_eff = P (times the cell area) */
+        const double scale = cell_area ? v.dAc * v.dEc : 1.0;
+        const double dP = A[i] * o[0] * scale;
+        if (sh) {
+            double d[3], J[9], Y[16], dY[48];
+            radar_dir(&v, means + 3 * i, d, J);
+            sh_basis(d, sh_deg, Y, dY);
+            double gd[3] = {0.0, 0.0, 0.0};   /* dP/dd */
+            for (int64_t k = 0; k < ns; ++k) {
+                if (dsh) dsh[i * ns + k] = dP * Y[k];
+                for (int j = 0; j < 3; ++j) gd[j] += sh[i * ns + k] * dY[3 * k + j];
+            }
+            for (int j = 0; j < 3; ++j)
+                for (int a2 = 0; a2 < 3; ++a2) dm[j] += dP * gd[a2] * J[3 * a2 + j];
+        } else {
+            damp[i] = dP;
+        }
         dext[i] = o[6];
+        if (dext_back) dext_back[i] = o[6];
         double dSig[9] = {0};
         plane_to_3d(G[i].QI, o + 3, o + 1, v.ex, v.ez, v.dA, v.dR, dSig, dm);
         plane_to_3d(G[i].QC, o + 9, o + 7, v.ex, v.ey, v.dAc, v.dEc, dSig, dm);
         cov_to_params(&G[i], dSig, dsc, dqu);
     }
-    free(g2); free(G); free(A); free(edge);
+    free(g2); free(G); free(A); free(edge); free(peff); free(kap);
     return 0;
 }
 
@@ -621,20 +795,24 @@ int orc_backward(int64_t n, const double* means, const double* scales,
  * are searched inside its exact ellipse bounding box widened by one cell. */
 int orc_sparse_forward(int64_t n, const double* means, const double* scales,
                        const double* quats, const double* amp,
-                       const double* ext, const double* view, double q_max,
-                       double dil, int shadowing, int64_t npix,
+                       const double* ext, const double* ext_back, const double* sh,
+                       int64_t sh_deg, int64_t cell_area, const double* view,
+                       double q_max, double dil, int shadowing, int64_t npix,
                        const int64_t* pix, double* S, int64_t ng,
                        const int64_t* gids, double* Aout)
 {
     OView v;
-    if (n < 0 || view_init(&v, view) || !(q_max > 0)) return -1;
+    if (n < 0 || view_init(&v, view) || !(q_max > 0) || sh_deg < 0 || sh_deg > 3) return -1;
+    const OExtra ex = {ext_back, sh, sh_deg, cell_area};
+    double *peff = NULL, *kap = NULL;
+    if (prepare(&v, &ex, n, means, amp, ext, &peff, &kap)) return -2;
     OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
     int64_t nrays = v.Wc * v.Hc;
     char* needA = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
     char* ray_on = (char*)calloc((size_t)nrays, 1);
     double* A = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
     if (!G || !needA || !ray_on || !A) {
-        free(G); free(needA); free(ray_on); free(A); return -2;
+        free(G); free(needA); free(ray_on); free(A); free(peff); free(kap); return -2;
     }
     for (int64_t k = 0; k < ng; ++k) needA[gids[k]] = 1;
 #pragma omp parallel for schedule(static)
@@ -681,7 +859,7 @@ int orc_sparse_forward(int64_t n, const double* means, const double* scales,
             double t = 0.0;
             for (int64_t k = 0; k < m; ++k) {
                 int64_t i = list[k].idx;
-                double x = ext[i] * list[k].g;
+                double x = kap[i] * list[k].g;
                 double alpha = 1.0 - exp(-x);
                 if (needA[i]) mine[i] += shadowing ? alpha * exp(-t) : alpha;
                 t += x;
@@ -700,11 +878,11 @@ int orc_sparse_forward(int64_t n, const double* means, const double* scales,
         for (int64_t i = 0; i < n; ++i) {
             if (!G[i].valid) continue;
             double q = quadform(G[i].QI, px - G[i].cI[0], py - G[i].cI[1]);
-            if (q < q_max) acc += foot(q, q_max) * amp[i] * A[i];
+            if (q < q_max) acc += foot(q, q_max) * peff[i] * A[i];
         }
         S[k] = acc;
     }
-    free(sel); free(G); free(needA); free(ray_on); free(A);
+    free(sel); free(G); free(needA); free(ray_on); free(A); free(peff); free(kap);
     return 0;
 }
 
@@ -751,7 +929,8 @@ static double weighted_footprint(const OView* v, const OG* g, const double* V, d
 /* Central difference of the linear loss L = sum_p V[p] S[p] of one view when
  * parameter `comp` of Gaussian k moves by +h and by -h.
  *   comp: 0-2 mean, 3-5 scale, 6-9 quaternion (raw), 10 amplitude P,
- *         11 extinction kappa.
+ *         11 extinction ext, 12 backward extinction ext_back (when given),
+ *         13 + k SH coefficient k (when sh is given).
  *   out[0] = L(+h) - L(-h)
  *   out[1] = 1 if, on a ray where Gaussian k has a footprint in both states,
  *            the number of Gaussians in front of it differs between the
@@ -768,33 +947,45 @@ static double weighted_footprint(const OView* v, const OG* g, const double* V, d
  * where all of A_k's terms lie on those rays. */
 int orc_fd_linear(int64_t n, const double* means, const double* scales,
                   const double* quats, const double* amp, const double* ext,
-                  const double* view, double q_max, double dil, int shadowing,
-                  const double* V, int64_t k, int comp, double h, double* out)
+                  const double* ext_back, const double* sh, int64_t sh_deg,
+                  int64_t cell_area, const double* view, double q_max, double dil,
+                  int shadowing, const double* V, int64_t k, int comp, double h, double* out)
 {
     OView v;
-    if (n <= 0 || k < 0 || k >= n || comp < 0 || comp > 11 || view_init(&v, view) ||
-        !(q_max > 0) || !(h > 0))
+    const int64_t ns = (sh_deg + 1) * (sh_deg + 1);
+    if (n <= 0 || k < 0 || k >= n || comp < 0 || sh_deg < 0 || sh_deg > 3 ||
+        comp > (sh ? 12 + (int)ns : 12) || (comp == 12 && !ext_back) ||
+        view_init(&v, view) || !(q_max > 0) || !(h > 0))
         return -1;
+    const OExtra ex = {ext_back, sh, sh_deg, cell_area};
+    double *peff = NULL, *kap = NULL;
+    if (prepare(&v, &ex, n, means, amp, ext, &peff, &kap)) return -2;
     OG* G = project_all(&v, n, means, scales, quats, dil, q_max);
     int64_t nrays = v.Wc * v.Hc;
     char* on = (char*)calloc((size_t)nrays, 1);
     double* dA = (double*)calloc((size_t)n, sizeof(double));
     if (!G || !on || !dA) {
-        free(G); free(on); free(dA); return -2;
+        free(G); free(on); free(dA); free(peff); free(kap); return -2;
     }
     /* Gaussian k in the two states */
     OG gs[2];
     double Pk[2], Kk[2];
     for (int st = 0; st < 2; ++st) {
-        double p[14];
+        /* Gaussian k's parameters in this state: mean, scale, quaternion,
+         * amp, ext, ext_back, SH coefficients */
+        double p[13 + 16];
         for (int j = 0; j < 3; ++j) { p[j] = means[3 * k + j]; p[3 + j] = scales[3 * k + j]; }
         for (int j = 0; j < 4; ++j) p[6 + j] = quats[4 * k + j];
-        p[10] = amp[k];
+        p[10] = amp ? amp[k] : 0.0;
         p[11] = ext[k];
+        p[12] = ext_back ? ext_back[k] : 0.0;
+        for (int64_t j = 0; j < ns; ++j) p[13 + j] = sh ? sh[k * ns + j] : 0.0;
         p[comp] += st == 0 ? h : -h;
         project(&v, p, p + 3, p + 6, dil, q_max, &gs[st]);
-        Pk[st] = p[10];
-        Kk[st] = p[11];
+        /* phase of Gaussian k alone, from its own perturbed values */
+        const OExtra exk = {NULL, sh ? p + 13 : NULL, sh_deg, cell_area};
+        Pk[st] = phase_of(&v, &exk, p + 10, p, 0);
+        Kk[st] = p[11] + p[12];
         mark_rays(&v, &gs[st], q_max, on);
     }
     int64_t nsel = 0;
@@ -824,8 +1015,8 @@ int orc_fd_linear(int64_t n, const double* means, const double* scales,
                 front[2 * s + st] = -1;
                 for (int64_t j = 0; j < m; ++j) {
                     int64_t i = list[j].idx;
-                    double kap = i == k ? Kk[st] : ext[i];
-                    double x = kap * list[j].g;
+                    double kp = i == k ? Kk[st] : kap[i];
+                    double x = kp * list[j].g;
                     double a = (1.0 - exp(-x)) * (shadowing ? exp(-t) : 1.0);
                     if (i == k) {
                         akst += a;
@@ -854,7 +1045,7 @@ int orc_fd_linear(int64_t n, const double* means, const double* scales,
             /* zero for every Gaussian the change does not reach, and for
              * those in front of k (identical terms in both states) */
             if (i == k || dA[i] == 0.0) continue;
-            diff += amp[i] * weighted_footprint(&v, &G[i], V, q_max) * dA[i];
+            diff += peff[i] * weighted_footprint(&v, &G[i], V, q_max) * dA[i];
         }
         diff += Pk[0] * Ak[0] * weighted_footprint(&v, &gs[0], V, q_max) -
                 Pk[1] * Ak[1] * weighted_footprint(&v, &gs[1], V, q_max);
@@ -862,6 +1053,16 @@ int orc_fd_linear(int64_t n, const double* means, const double* scales,
     int err = (At && sel && front) ? 0 : -2;
     out[0] = diff;
     out[1] = (double)flag;
-    free(At); free(sel); free(front); free(G); free(on); free(dA);
+    free(At); free(sel); free(front); free(G); free(on); free(dA); free(peff); free(kap);
     return err;
+}
+
+/* The real spherical-harmonics basis of degree <= deg at m unit vectors
+ * dirs[3m]: Y[m, (deg + 1)^2] (exported for the tests that check it). */
+int orc_sh_basis(int64_t m, const double* dirs, int64_t deg, double* Y)
+{
+    if (m < 0 || deg < 0 || deg > 3) return -1;
+    const int64_t ns = (deg + 1) * (deg + 1);
+    for (int64_t j = 0; j < m; ++j) sh_basis(dirs + 3 * j, deg, Y + ns * j, NULL);
+    return 0;
 }

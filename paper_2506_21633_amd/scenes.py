@@ -39,30 +39,46 @@ class Scene:
     scales (N,3) per-axis standard deviation [m], > 0 (not log)
     quats  (N,4) rotation quaternion (w, x, y, z), any nonzero norm
     amp    (N,)  scattering amplitude P >= 0 (phase function, scalar form)
-    ext    (N,)  extinction kappa = k_e+ + k_e- >= 0
+    ext    (N,)  extinction kappa = k_e+ + k_e- >= 0, or k_e+ alone when
+                 ext_back is given
+    ext_back (N,) optional backward extinction k_e- (kappa = ext + ext_back)
+    sh     (N,(d+1)^2) optional spherical-harmonics coefficients of the phase
+                 function, degree d <= 3 (then amp is not used)
     """
     means: np.ndarray
     scales: np.ndarray
     quats: np.ndarray
     amp: np.ndarray
     ext: np.ndarray
+    ext_back: Optional[np.ndarray] = None
+    sh: Optional[np.ndarray] = None
 
     @property
     def n(self) -> int:
         return int(self.means.shape[0])
 
+    @property
+    def sh_degree(self) -> int:
+        return -1 if self.sh is None else int(round(math.sqrt(self.sh.shape[1]))) - 1
+
     def subset(self, idx) -> "Scene":
+        opt = lambda a: None if a is None else a[idx].copy()
         return Scene(self.means[idx].copy(), self.scales[idx].copy(),
                      self.quats[idx].copy(), self.amp[idx].copy(),
-                     self.ext[idx].copy())
+                     self.ext[idx].copy(), opt(self.ext_back), opt(self.sh))
 
     def copy(self) -> "Scene":
         return self.subset(slice(None))
 
     def concat(self, other: "Scene") -> "Scene":
+        if (self.ext_back is None) != (other.ext_back is None) or \
+                (self.sh is None) != (other.sh is None):
+            raise ValueError("scenes differ in their optional inputs")
+        opt = lambda a, b: None if a is None else np.concatenate([a, b])
         return Scene(*(np.concatenate([a, b]) for a, b in zip(
             (self.means, self.scales, self.quats, self.amp, self.ext),
-            (other.means, other.scales, other.quats, other.amp, other.ext))))
+            (other.means, other.scales, other.quats, other.amp, other.ext))),
+            ext_back=opt(self.ext_back, other.ext_back), sh=opt(self.sh, other.sh))
 
 
 @dataclass
@@ -86,6 +102,7 @@ class View:
     comp_d_az: float = 0.0
     comp_d_el: float = 0.0
     scene: int = 0
+    radar_range: float = 0.0   # slant distance of the radar from the origin [m]; 0: plane wave
 
     @staticmethod
     def from_degrees(azimuth_deg: float, incidence_deg: float, size: int,

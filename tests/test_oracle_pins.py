@@ -489,7 +489,7 @@ def test_restricted_central_difference_equals_full_forward(shadowing):
     Lscale = float(np.abs(S * Vc).sum())
     ks = rng.choice(np.flatnonzero(A > 0), 6, replace=False)
     for k in ks:
-        for comp, (name, j) in enumerate(oracle.FD_COMPONENTS):
+        for comp, name, j in oracle.fd_components(sc):
             arr = getattr(sc, name)
             idx = (k,) if j is None else (k, j)
             h = 1e-3 * max(1.0, abs(arr[idx]))   # large step: a real difference
@@ -513,3 +513,201 @@ def _small_dense(seed, n=120):
     return mk_scene(rng.uniform(-0.5, 0.5, (n, 3)), rng.uniform(0.05, 0.2, (n, 3)),
                     quats=rng.standard_normal((n, 4)), amp=rng.uniform(0.3, 1.0, n),
                     ext=rng.uniform(0.5, 3, n))
+
+
+# ------------------------------------------- phase function and extinctions
+
+def _unit_dirs(rng, m):
+    d = rng.standard_normal((m, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+def test_sh_basis_matches_library_real_harmonics():
+    """The real basis against scipy's complex spherical harmonics (with the
+    Condon-Shortley phase): Y_{l,m} = sqrt(2) (-1)^m Re / Im of Y_l^{|m|},
+    Y_{l,0} = Y_l^0."""
+    import scipy.special as sp
+    rng = scenes.make_rng(91)
+    d = _unit_dirs(rng, 200)
+    Y = oracle.sh_basis(d, 3)
+    polar = np.arccos(np.clip(d[:, 2], -1, 1))
+    azim = np.arctan2(d[:, 1], d[:, 0])
+    for l in range(4):
+        for m in range(-l, l + 1):
+            c = sp.sph_harm_y(l, abs(m), polar, azim)
+            if m > 0:
+                ref = np.sqrt(2) * (-1) ** m * c.real
+            elif m < 0:
+                ref = np.sqrt(2) * (-1) ** m * c.imag
+            else:
+                ref = c.real
+            assert np.allclose(Y[:, l * l + l + m], ref, atol=1e-13), (l, m)
+
+
+def test_sh_basis_orthonormal():
+    """Gauss-Legendre in cos(polar) x uniform azimuth integrates products of
+    degree <= 6 exactly: the Gram matrix is the identity."""
+    x, w = np.polynomial.legendre.leggauss(12)
+    az = np.arange(24) * (2 * np.pi / 24)
+    ct, ph = np.meshgrid(x, az, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    d = np.stack([st * np.cos(ph), st * np.sin(ph), ct], -1).reshape(-1, 3)
+    wt = (w[:, None] * np.full(az.size, 2 * np.pi / az.size)[None, :]).ravel()
+    Y = oracle.sh_basis(d, 3)
+    gram = (Y * wt[:, None]).T @ Y
+    assert np.allclose(gram, np.eye(16), atol=1e-12)
+
+
+def _phase_scene(seed, n=40, deg=3):
+    sc = _small_dense(seed, n)
+    rng = scenes.make_rng(seed + 1)
+    sc.sh = rng.normal(0.0, 0.3, (n, (deg + 1) ** 2))
+    sc.sh[:, 0] += 2.0      # mostly positive phase functions
+    sc.ext_back = rng.uniform(0.2, 1.5, n)
+    return sc
+
+
+PH_VIEW = scenes.View(azimuth=0.9, grazing=math.radians(50), img_w=24, img_h=20,
+                      d_az=0.08, d_rg=0.09, radar_range=40.0)
+
+
+def test_sh_degree0_is_the_scalar_amplitude():
+    """A degree-0 expansion with c_00 = P / Y_00 renders and differentiates
+    exactly like the scalar amplitude P; the direction to the radar then
+    carries no gradient."""
+    sc = _small_dense(95, 60)
+    y00 = oracle.sh_basis([[0.0, 0.0, 1.0]], 0)[0, 0]
+    sh = sc.copy()
+    sh.sh = (sc.amp / y00)[:, None]
+    rng = scenes.make_rng(96)
+    Vc = rng.standard_normal((20, 24))
+    A1, _, S1 = oracle.forward_view(sc, PH_VIEW)
+    A2, _, S2 = oracle.forward_view(sh, PH_VIEW)
+    assert np.allclose(S2, S1, rtol=1e-13, atol=1e-15) and np.allclose(A2, A1, rtol=1e-14)
+    g1, _ = oracle.backward_view(sc, PH_VIEW, Vc)
+    g2, _ = oracle.backward_view(sh, PH_VIEW, Vc)
+    for k in ("means", "scales", "quats", "ext"):
+        assert np.allclose(g2[k], g1[k], rtol=1e-11, atol=1e-13 * np.abs(g1[k]).max()), k
+    assert np.allclose(g2["sh"][:, 0], g1["amp"] * y00, rtol=1e-11)
+    assert np.all(g2["amp"] == 0.0)
+
+
+def test_extinction_split_enters_as_its_sum():
+    """With separate forward and backward extinctions the result equals the
+    single-extinction model at kappa = ext + ext_back, and both receive the
+    same gradient dL/dkappa."""
+    sc = _small_dense(97, 60)
+    rng = scenes.make_rng(98)
+    split = sc.copy()
+    split.ext_back = rng.uniform(0.1, 1.0, sc.n)
+    split.ext = sc.ext - 0.5 * split.ext_back
+    summed = sc.copy()
+    summed.ext = split.ext + split.ext_back
+    Vc = rng.standard_normal((20, 24))
+    _, _, S1 = oracle.forward_view(split, PH_VIEW)
+    _, _, S2 = oracle.forward_view(summed, PH_VIEW)
+    assert np.allclose(S1, S2, rtol=1e-13, atol=1e-15)
+    g1, _ = oracle.backward_view(split, PH_VIEW, Vc)
+    g2, _ = oracle.backward_view(summed, PH_VIEW, Vc)
+    assert np.array_equal(g1["ext"], g1["ext_back"])
+    assert np.allclose(g1["ext"], g2["ext"], rtol=1e-11, atol=1e-13 * np.abs(g2["ext"]).max())
+
+
+def test_cell_area_normalisation_is_grid_independent():
+    """Normalised by the computation-plane cell area, an isolated Gaussian's
+    intensity approaches its absorbing cross-section in m^2, the integral of
+    alpha = 1 - exp(-kappa f(q)) over the plane perpendicular to the line of
+    sight, pi sqrt(det C) int_0^q_max alpha dq with C the projected covariance
+    in m^2, whatever the cell size; the unnormalised share counts cells (x4
+    when the cells halve). The normalised image is the plain one times the
+    cell area."""
+    import scipy.integrate as si
+    kappa = 60.0
+    sc = mk_scene([[0.0, 0.0, 0.0]], [[0.3, 0.2, 0.25]], ext=[kappa])
+    eps = math.exp(-0.5 * oracle.Q_MAX)
+    f = lambda q: (math.exp(-0.5 * q) - eps) / (1.0 - eps)
+    cross_q = si.quad(lambda q: 1.0 - math.exp(-kappa * f(q)), 0.0, oracle.Q_MAX,
+                      limit=200, epsabs=1e-13)[0]
+    got = []
+    for fine in (1, 2, 4):
+        v = scenes.View(azimuth=0.4, grazing=math.radians(45), img_w=64, img_h=64,
+                        d_az=0.05, d_rg=0.05, comp_w=64 * fine, comp_h=64 * fine,
+                        comp_d_az=0.05 / fine, comp_d_el=0.05 / fine)
+        A, _, S = oracle.forward_view(sc, v)
+        An, _, Sn = oracle.forward_view(sc, v, cell_area=True)
+        cell = v.comp_d_az * v.comp_d_el
+        assert np.allclose(Sn, S * cell, rtol=1e-14, atol=0)
+        assert np.allclose(An, A, rtol=1e-13, atol=0)
+        c = oracle.project(sc, v)["covC"][0] * cell      # cells^2 -> m^2
+        cross = math.pi * math.sqrt(c[0] * c[2] - c[1] ** 2) * cross_q
+        assert abs(A[0] * cell - cross) <= 2e-3 * cross, fine
+        got.append(A[0])
+    assert abs(got[1] / got[0] - 4.0) <= 8e-3 and abs(got[2] / got[1] - 4.0) <= 8e-3
+
+
+@pytest.mark.parametrize("shadowing", [True, False])
+def test_phase_and_split_extinction_central_differences(shadowing):
+    """SH coefficients, the backward extinction and the means (through the
+    direction to a radar 40 m away) against the restricted FP64 central
+    difference, itself equal to the difference of two full forwards."""
+    sc = _phase_scene(99)
+    rng = scenes.make_rng(100)
+    Vc = rng.standard_normal((20, 24))
+    g, _ = oracle.backward_view(sc, PH_VIEW, Vc, shadowing=shadowing)
+    A, _, S = oracle.forward_view(sc, PH_VIEW, shadowing=shadowing)
+    Lscale = float(np.abs(S * Vc).sum())
+
+    def loss(s):
+        return float((oracle.forward_view(s, PH_VIEW, shadowing=shadowing)[2] * Vc).sum())
+
+    comps = [c for c in oracle.fd_components(sc) if c[1] in ("means", "ext", "ext_back", "sh")]
+    for k in rng.choice(np.flatnonzero(A > 0), 4, replace=False):
+        for comp, name, j in comps:
+            arr = getattr(sc, name)
+            idx = (k,) if j is None else (k, j)
+            h = 1e-3 * max(1.0, abs(arr[idx]))
+            d, _ = oracle.fd_linear(sc, PH_VIEW, Vc, k, comp, h, shadowing=shadowing)
+            sp_, sm_ = sc.copy(), sc.copy()
+            getattr(sp_, name)[idx] += h
+            getattr(sm_, name)[idx] -= h
+            assert abs(d - (loss(sp_) - loss(sm_))) <= 1e-13 * Lscale, (k, name, j)
+            h = 1e-6 * max(1.0, abs(arr[idx]))
+            d, flag = oracle.fd_linear(sc, PH_VIEW, Vc, k, comp, h, shadowing=shadowing)
+            if flag:
+                continue
+            scale = np.abs(g[name]).max()
+            assert abs(d / (2 * h) - g[name][idx]) <= 2e-6 * scale, (k, name, j)
+
+
+def _rot_z(psi):
+    c, s = math.cos(psi), math.sin(psi)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+def test_rotation_about_the_vertical_with_the_view():
+    """Turning the scene about the vertical by psi, its orientations and its
+    phase functions with it (SH coefficients refitted in the rotated frame),
+    and the radar azimuth by -psi leaves the images unchanged."""
+    sc = _phase_scene(101, n=50)
+    psi = 0.7
+    R = _rot_z(psi)
+    rot = sc.copy()
+    rot.means = sc.means @ R.T
+    qz = np.array([math.cos(psi / 2), 0.0, 0.0, math.sin(psi / 2)])
+    w1, v1 = qz[0], qz[1:]
+    w2, v2 = sc.quats[:, :1], sc.quats[:, 1:]
+    rot.quats = np.concatenate([w1 * w2 - (v2 @ v1)[:, None],
+                                w1 * v2 + w2 * v1 + np.cross(v1, v2)], axis=1)
+    # P'(R d) = P(d) for all d: least-squares refit on many directions
+    dirs = _unit_dirs(scenes.make_rng(102), 400)
+    Y = oracle.sh_basis(dirs, 3)
+    Yr = oracle.sh_basis(dirs @ R.T, 3)
+    rot.sh = np.linalg.lstsq(Yr, Y @ sc.sh.T, rcond=None)[0].T
+    assert np.allclose(Yr @ rot.sh.T, Y @ sc.sh.T, atol=1e-12)
+    v = PH_VIEW
+    v_rot = scenes.View(azimuth=v.azimuth - psi, grazing=v.grazing, img_w=v.img_w,
+                        img_h=v.img_h, d_az=v.d_az, d_rg=v.d_rg, radar_range=v.radar_range)
+    A1, _, S1 = oracle.forward_view(sc, v)
+    A2, _, S2 = oracle.forward_view(rot, v_rot)
+    assert np.allclose(S2, S1, rtol=1e-9, atol=1e-12 * S1.max())
+    assert np.allclose(A2, A1, rtol=1e-9, atol=1e-12)
