@@ -776,7 +776,10 @@ k_raster_b_tile(const DevView* __restrict__ views, int nv, RasterParams rp, int6
                 m = footprint_mask(g.x, g.y, g.z, g.w, g2.x, rp.q_max, tc.tx, tc.ty);
         }
         wave_lds_sync();
-        uint64_t col = tc.inside ? transpose64(m) : 0ull;
+        // the transpose exchanges bits between lanes: every lane takes part,
+        // pixels outside the image drop their column afterwards
+        uint64_t col = transpose64(m);
+        if (!tc.inside) col = 0ull;
         while (col != 0ull) {
             const int j = __builtin_ctzll(col);
             col &= col - 1ull;
