@@ -68,24 +68,47 @@ extern "C" {
 #define SDGR_EOVERFLOW (-4)    /* pair count exceeds the plan's capacity */
 #define SDGR_EUNSUPPORTED (-5) /* option or size outside what is built */
 
-/* One scene of n Gaussians (device pointers, float32). */
+/* One scene of n Gaussians (device pointers, float32).
+ *
+ * Extinction (Sec. II-A): the forward and backward coefficients k_e+ and
+ * k_e- enter the model only through their sum kappa. Give ext = kappa and
+ * ext_back = NULL, or the two coefficients separately (ext = k_e+,
+ * ext_back = k_e-); both then receive the same gradient dL/dkappa.
+ *
+ * Phase function (Sec. II-B): the scalar amp, or (sh not NULL) a real
+ * spherical-harmonics expansion of degree sh_degree (0..3, orthonormal,
+ * without the Condon-Shortley phase, coefficient index l*l + l + m for
+ * m = -l..l) evaluated at the unit direction from the Gaussian's centre to
+ * the radar (see sdgr_view.radar_range). With sh given, amp is ignored and
+ * may be NULL, and the means also receive the gradient through that
+ * direction. */
 typedef struct sdgr_scene {
     int64_t n;
     const float* means;   /* [n,3] world position, metres */
     const float* scales;  /* [n,3] per-axis standard deviation, metres */
     const float* quats;   /* [n,4] rotation (w,x,y,z) */
     const float* amp;     /* [n]   scattering amplitude P (phase function) */
-    const float* ext;     /* [n]   extinction kappa = k_e+ + k_e- */
+    const float* ext;     /* [n]   extinction kappa, or k_e+ with ext_back */
+    const float* ext_back;   /* [n] backward extinction k_e-, or NULL */
+    const float* sh;         /* [n, (sh_degree + 1)^2] SH coefficients of
+                                the phase function, or NULL */
+    int32_t sh_degree;       /* 0..3 when sh is given, else ignored */
+    int32_t reserved;        /* must be 0 */
 } sdgr_scene;
 
 /* Gradient outputs of one scene (device pointers, same shapes as the
- * inputs). They are OVERWRITTEN with the sum over all views of the scene. */
+ * inputs). They are OVERWRITTEN with the sum over all views of the scene.
+ * d_ext_back is required when the scene has ext_back (it receives the same
+ * values as d_ext), d_sh when it has sh; with sh, d_amp may be NULL (if
+ * given it is filled with zeros: amp takes no part). */
 typedef struct sdgr_scene_grad {
     float* d_means;
     float* d_scales;
     float* d_quats;
     float* d_amp;
     float* d_ext;
+    float* d_ext_back;
+    float* d_sh;
 } sdgr_scene_grad;
 
 /* One radar view (host struct). Zero in comp_* takes the default. */
@@ -102,6 +125,12 @@ typedef struct sdgr_view {
     int32_t comp_w, comp_h;  /* computation-plane cells, 0 = image size */
     int32_t scene;           /* index into the scenes array */
     int32_t reserved;        /* must be 0 */
+    double radar_range;      /* slant distance [m] of the radar from the
+                                scene origin, on the line of sight on the
+                                near side; it sets the direction at which a
+                                phase-function expansion is evaluated for
+                                each Gaussian. 0: a plane wave, the
+                                direction the same (-e_z) for all. >= 0 */
 } sdgr_view;
 
 typedef struct sdgr_options {
@@ -125,6 +154,10 @@ typedef struct sdgr_options {
                             float atomics; costs extra memory and time */
     int32_t tile;        /* tile side in cells: 0 (default) or 8, the one
                             size built; other values give SDGR_EUNSUPPORTED */
+    int32_t cell_area;   /* 1: I = P A times the computation-plane cell area
+                            comp_d_az * comp_d_el [m^2], so that intensities
+                            measure the absorbing cross-section and do not
+                            depend on the cell size; 0: I = P A */
     int32_t reserved;    /* must be 0 */
 } sdgr_options;
 
@@ -147,7 +180,8 @@ typedef struct sdgr_plan {
     int32_t tile;              /* tile side in pixels (8) */
     int32_t recompute;         /* copy of options.recompute */
     int32_t deterministic;     /* copy of options.deterministic */
-    int32_t reserved;
+    int32_t sh_coeffs;         /* most SH coefficients of any scene (0: no
+                                  scene has sh); sizes the backward scratch */
 } sdgr_plan;
 
 /* Library version (SDGR_VERSION). */

@@ -30,13 +30,16 @@ class Scene(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64),
                 ("means", ctypes.c_void_p), ("scales", ctypes.c_void_p),
                 ("quats", ctypes.c_void_p), ("amp", ctypes.c_void_p),
-                ("ext", ctypes.c_void_p)]
+                ("ext", ctypes.c_void_p), ("ext_back", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p), ("sh_degree", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class SceneGrad(ctypes.Structure):
     _fields_ = [("d_means", ctypes.c_void_p), ("d_scales", ctypes.c_void_p),
                 ("d_quats", ctypes.c_void_p), ("d_amp", ctypes.c_void_p),
-                ("d_ext", ctypes.c_void_p)]
+                ("d_ext", ctypes.c_void_p), ("d_ext_back", ctypes.c_void_p),
+                ("d_sh", ctypes.c_void_p)]
 
 
 class View(ctypes.Structure):
@@ -46,14 +49,16 @@ class View(ctypes.Structure):
                 ("img_offset", ctypes.c_int64),
                 ("img_w", ctypes.c_int32), ("img_h", ctypes.c_int32),
                 ("comp_w", ctypes.c_int32), ("comp_h", ctypes.c_int32),
-                ("scene", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("scene", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("radar_range", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("shadowing", ctypes.c_int32), ("recompute", ctypes.c_int32),
                 ("q_max", ctypes.c_float), ("tau_max", ctypes.c_float),
                 ("dilation", ctypes.c_float), ("deterministic", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("cell_area", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Plan(ctypes.Structure):
@@ -66,7 +71,7 @@ class Plan(ctypes.Structure):
                 ("tiles_i", ctypes.c_int64), ("rays", ctypes.c_int64),
                 ("gaussians", ctypes.c_int64), ("nviews", ctypes.c_int32), ("nscenes", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("recompute", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32), ("sh_coeffs", ctypes.c_int32)]
 
 
 class SDGRError(RuntimeError):

@@ -7,6 +7,13 @@ tensors) and the stream (the current stream of the tensors' device).
     scene = GaussianTensors.from_numpy(scenes.vehicle(), device="cuda")
     images = render(scene.means, scene.scales, scene.quats, scene.amp,
                     scene.ext, views)            # [V, H, W], differentiable
+
+Optional per-Gaussian inputs: ``ext_back`` (the backward extinction; only
+ext + ext_back enters the model) and ``sh`` ([n, (deg + 1)^2] coefficients
+of a real spherical-harmonics phase function evaluated at the direction to
+the radar, replacing amp; a view's ``radar_range`` places the radar, 0 is a
+plane wave). ``RenderOptions.cell_area`` scales intensities by the
+computation-plane cell area.
 """
 from __future__ import annotations
 
@@ -32,6 +39,7 @@ class RenderOptions:
     tau_max: float = 16.0
     dilation: float = 0.0
     deterministic: bool = False
+    cell_area: bool = False
 
     def to_c(self) -> C.Options:
         o = C.Options()
@@ -42,6 +50,7 @@ class RenderOptions:
         o.dilation = float(self.dilation)
         o.deterministic = int(bool(self.deterministic))
         o.tile = 0
+        o.cell_area = int(bool(self.cell_area))
         o.reserved = 0
         return o
 
@@ -51,22 +60,37 @@ class GaussianTensors:
     means: torch.Tensor
     scales: torch.Tensor
     quats: torch.Tensor
-    amp: torch.Tensor
+    amp: Optional[torch.Tensor]            # None only with sh
     ext: torch.Tensor
+    ext_back: Optional[torch.Tensor] = None
+    sh: Optional[torch.Tensor] = None      # [n, (deg + 1)^2]
 
     @property
     def n(self) -> int:
         return int(self.means.shape[0])
 
+    @property
+    def sh_degree(self) -> int:
+        if self.sh is None:
+            return -1
+        deg = int(round(math.sqrt(self.sh.shape[1]))) - 1
+        if deg < 0 or deg > 3 or (deg + 1) ** 2 != self.sh.shape[1]:
+            raise ValueError("sh must have 1, 4, 9 or 16 coefficients per Gaussian")
+        return deg
+
     @staticmethod
     def from_numpy(scene, device="cuda") -> "GaussianTensors":
-        f = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32),
-                                      device=device)
+        f = lambda a: None if a is None else torch.as_tensor(
+            np.ascontiguousarray(a, dtype=np.float32), device=device)
         return GaussianTensors(f(scene.means), f(scene.scales), f(scene.quats),
-                               f(scene.amp), f(scene.ext))
+                               f(scene.amp), f(scene.ext), f(getattr(scene, "ext_back", None)),
+                               f(getattr(scene, "sh", None)))
 
-    def tensors(self):
-        return (self.means, self.scales, self.quats, self.amp, self.ext)
+    def named(self) -> dict:
+        """The parameter tensors that are present, by gradient name."""
+        d = {"means": self.means, "scales": self.scales, "quats": self.quats,
+             "amp": self.amp, "ext": self.ext, "ext_back": self.ext_back, "sh": self.sh}
+        return {k: v for k, v in d.items() if v is not None}
 
 
 def _dev_f32(t: torch.Tensor, shape, name) -> torch.Tensor:
@@ -84,10 +108,17 @@ def _scene_struct(g: GaussianTensors) -> C.Scene:
     m = _dev_f32(g.means, (n, 3), "means")
     s = _dev_f32(g.scales, (n, 3), "scales")
     q = _dev_f32(g.quats, (n, 4), "quats")
-    a = _dev_f32(g.amp, (n,), "amp")
     e = _dev_f32(g.ext, (n,), "ext")
-    st = C.Scene(n, m.data_ptr(), s.data_ptr(), q.data_ptr(), a.data_ptr(), e.data_ptr())
-    st._keep = (m, s, q, a, e)
+    if g.amp is None and g.sh is None:
+        raise ValueError("a scene needs amp or sh")
+    a = None if g.amp is None else _dev_f32(g.amp, (n,), "amp")
+    eb = None if g.ext_back is None else _dev_f32(g.ext_back, (n,), "ext_back")
+    deg = g.sh_degree
+    sh = None if g.sh is None else _dev_f32(g.sh, (n, (deg + 1) ** 2), "sh")
+    ptr = lambda t: 0 if t is None else t.data_ptr()
+    st = C.Scene(n, m.data_ptr(), s.data_ptr(), q.data_ptr(), ptr(a), e.data_ptr(), ptr(eb),
+                 ptr(sh), max(deg, 0), 0)
+    st._keep = (m, s, q, a, e, eb, sh)
     return st
 
 
@@ -110,6 +141,7 @@ def _view_structs(views, scene_ids=None):
         c.comp_h = int(getattr(v, "comp_h", 0))
         c.scene = int(scene_ids[k] if scene_ids is not None else getattr(v, "scene", 0))
         c.reserved = 0
+        c.radar_range = float(getattr(v, "radar_range", 0.0))
         shapes.append((off, int(v.img_h), int(v.img_w)))
         off += int(v.img_h) * int(v.img_w)
     return arr, shapes, off
@@ -212,7 +244,8 @@ class Renderer:
         return ForwardResult(images, self.shapes, plan, state)
 
     def backward(self, fwd: ForwardResult, grad_images: torch.Tensor):
-        """Gradients for every scene: list of dicts of tensors."""
+        """Gradients for every scene: list of dicts of tensors, one entry per
+        parameter tensor the scene has (amp's is zero with sh)."""
         g = grad_images.contiguous().view(-1)
         if g.dtype != torch.float32 or g.numel() < fwd.plan.image_floats:
             raise ValueError("grad_images must be float32 and cover every image")
@@ -220,11 +253,11 @@ class Renderer:
         outs = []
         grads_c = (C.SceneGrad * len(self.scenes))()
         for k, sc in enumerate(self.scenes):
-            d = {name: torch.empty_like(t) for name, t in
-                 zip(("means", "scales", "quats", "amp", "ext"), sc.tensors())}
-            grads_c[k] = C.SceneGrad(d["means"].data_ptr(), d["scales"].data_ptr(),
-                                     d["quats"].data_ptr(), d["amp"].data_ptr(),
-                                     d["ext"].data_ptr())
+            d = {name: torch.empty(t.shape, dtype=torch.float32, device=self.device)
+                 for name, t in sc.named().items()}
+            ptr = lambda name: d[name].data_ptr() if name in d else 0
+            grads_c[k] = C.SceneGrad(ptr("means"), ptr("scales"), ptr("quats"), ptr("amp"),
+                                     ptr("ext"), ptr("ext_back"), ptr("sh"))
             outs.append(d)
         C.check(self.lib.sdgr_backward(self.scenes_c, len(self.scenes), self.views_c, self.nv,
                                        ctypes.byref(self.opts_c), ctypes.byref(fwd.plan),
@@ -272,12 +305,14 @@ def count_work(on: bool) -> None:
 
 class SDGRFunction(torch.autograd.Function):
     """Differentiable SAR rendering of one scene over a batch of views of
-    equal image size; the backward is the library's hand-written one."""
+    equal image size; the backward is the library's hand-written one.
+    ext_back and sh may be None (and amp None when sh is given)."""
 
     @staticmethod
-    def forward(ctx, views, options, means, scales, quats, amp, ext):
-        g = GaussianTensors(means.detach(), scales.detach(), quats.detach(), amp.detach(),
-                            ext.detach())
+    def forward(ctx, views, options, means, scales, quats, amp, ext, ext_back=None, sh=None):
+        det = lambda t: None if t is None else t.detach()
+        g = GaussianTensors(det(means), det(scales), det(quats), det(amp), det(ext),
+                            det(ext_back), det(sh))
         r = Renderer([g], views, options)
         res = r.forward()
         ctx.renderer = r
@@ -292,11 +327,13 @@ class SDGRFunction(torch.autograd.Function):
         full[:n] = grad_images.reshape(-1)
         d = r.backward(res, full)[0]
         ctx.renderer = ctx.result = None
-        return None, None, d["means"], d["scales"], d["quats"], d["amp"], d["ext"]
+        return (None, None, d["means"], d["scales"], d["quats"], d.get("amp"), d["ext"],
+                d.get("ext_back"), d.get("sh"))
 
 
-def render(means, scales, quats, amp, ext, views, options: Optional[RenderOptions] = None):
-    """SAR images [V, H, W] of one scene; differentiable w.r.t. all five
-    parameter tensors."""
+def render(means, scales, quats, amp, ext, views, options: Optional[RenderOptions] = None,
+           ext_back=None, sh=None):
+    """SAR images [V, H, W] of one scene; differentiable w.r.t. every
+    parameter tensor given (amp may be None when sh is given)."""
     return SDGRFunction.apply(list(views), options or RenderOptions(), means, scales, quats,
-                              amp, ext)
+                              amp, ext, ext_back, sh)

@@ -116,6 +116,7 @@ struct Problem {
     int64_t image_floats = 0;
     bool recompute = false;
     bool det = false;       // ordered sums instead of float atomics
+    int shc = 0;            // most SH coefficients of any scene (0: none has sh)
     bool ikey_vm = false;   // imaging keys (tile within the view << 8) | view
     bool seg = false;       // depth and pair sorts segmented by view
     int cbits = 0;          // bits of the computation-plane tile within a view
@@ -151,6 +152,8 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         return fail(SDGR_EINVAL, "deterministic must be 0 or 1");
     if (opt->tile != 0 && opt->tile != TILE)
         return fail(SDGR_EUNSUPPORTED, "tile side must be 0 or 8 (the one size built)");
+    if (opt->cell_area != 0 && opt->cell_area != 1)
+        return fail(SDGR_EINVAL, "cell_area must be 0 or 1");
     P.nv = nv;
     P.ns = nscenes;
     P.recompute = opt->recompute != 0;
@@ -169,10 +172,18 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     for (int s = 0; s < nscenes; ++s) {
         const sdgr_scene& S = scenes[s];
         if (S.n < 0) return fail(SDGR_EINVAL, "scene " + std::to_string(s) + ": n < 0");
-        if (S.n > 0 && (!S.means || !S.scales || !S.quats || !S.amp || !S.ext))
-            return fail(SDGR_EINVAL, "scene " + std::to_string(s) + ": null parameter array");
+        const std::string tag = "scene " + std::to_string(s) + ": ";
+        if (S.reserved != 0) return fail(SDGR_EINVAL, tag + "reserved must be 0");
+        if (S.sh && (S.sh_degree < 0 || S.sh_degree > 3))
+            return fail(SDGR_EUNSUPPORTED, tag + "sh_degree outside 0..3");
+        if (S.n > 0 && (!S.means || !S.scales || !S.quats || !S.ext || (!S.amp && !S.sh)))
+            return fail(SDGR_EINVAL, tag + "null parameter array");
         DevScene d{};
         d.means = S.means; d.scales = S.scales; d.quats = S.quats; d.amp = S.amp; d.ext = S.ext;
+        d.ext_back = S.ext_back;
+        d.sh = S.sh;
+        d.shc = S.sh ? (S.sh_degree + 1) * (S.sh_degree + 1) : 0;
+        P.shc = std::max(P.shc, (int)d.shc);
         d.n = S.n;
         d.item_off = items;
         items += S.n;
@@ -197,6 +208,8 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         if (in.scene < 0 || in.scene >= nscenes)
             return fail(SDGR_EINVAL, tag + "scene index out of range");
         if (in.img_offset < 0) return fail(SDGR_EINVAL, tag + "negative image offset");
+        if (!(in.radar_range >= 0.0) || !std::isfinite(in.radar_range))
+            return fail(SDGR_EINVAL, tag + "radar_range must be finite and >= 0");
         DevView d{};
         radar_axes(in.azimuth, in.grazing, d.ex, d.ey, d.ez);
         d.W = in.img_w; d.H = in.img_h;
@@ -205,6 +218,8 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         d.dA = in.d_az; d.dR = in.d_rg;
         d.dAc = in.comp_d_az > 0.0 ? in.comp_d_az : in.d_az;
         d.dEc = in.comp_d_el > 0.0 ? in.comp_d_el : in.d_rg * tan(in.grazing);
+        d.range = in.radar_range;
+        d.pscale = opt->cell_area ? d.dAc * d.dEc : 1.0;
         d.iA = 1.0 / d.dA; d.iR = 1.0 / d.dR; d.iAc = 1.0 / d.dAc; d.iEc = 1.0 / d.dEc;
         d.hW = 0.5 * (double)d.W; d.hH = 0.5 * (double)d.H;
         d.hWc = 0.5 * (double)d.Wc; d.hHc = 0.5 * (double)d.Hc;
@@ -290,6 +305,7 @@ struct Bufs {
     float* grad_i = nullptr;
     float* pgrad = nullptr;         // per-view-group parts of the parameter gradients
     float* cbwd = nullptr;          // c = P dL/dI per record (pass A backward)
+    float* prec = nullptr;          // phase factor per record (scenes with SH)
     uint32_t* active = nullptr;     // records with A > 0 (backward)
     // deterministic mode: the computation-plane pairs' positions before the
     // pair sort (where each (tile, record) partial lands, so that a record's
@@ -346,6 +362,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.psum = a.take<uint64_t>(cap_c / WAVE + 1);
         b.ranges = a.take<uint2>(P.tiles_c);
         b.worklist = a.take<uint32_t>(P.tiles_c);
+        if (P.shc > 0) b.prec = a.take<float>(R);
         if (P.det) {
             b.ppos[0] = a.take<uint32_t>(cap_c);
             b.ppos[1] = a.take<uint32_t>(cap_c);
@@ -387,7 +404,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.grad_c = sc.take<float>(6 * R);   // plane-major, see launch_params_backward
         b.grad_i = sc.take<float>(6 * R);
         b.cbwd = sc.take<float>(R);
-        b.pgrad = sc.take<float>((int64_t)params_part_floats(P.nv, P.items));
+        b.pgrad = sc.take<float>((int64_t)params_part_floats(P.nv, P.items, P.shc));
         if (P.det) b.part_g = sc.take<float>(6 * cap_c);
     }
     if (state_bytes) *state_bytes = st.off;
@@ -436,7 +453,7 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
         plan->tiles_i != P.tiles_i || plan->gaussians != P.items || plan->nviews != P.nv ||
         plan->nscenes != P.ns ||
         plan->tile != TILE || plan->recompute != (P.recompute ? 1 : 0) ||
-        plan->deterministic != (P.det ? 1 : 0) ||
+        plan->deterministic != (P.det ? 1 : 0) || plan->sh_coeffs != P.shc ||
         plan->pairs_c < 0 || plan->pairs_i < 0 || plan->pairs_c + plan->pairs_i > INT32_MAX)
         return fail(SDGR_EINVAL, "plan does not match the scenes, views and options");
     // the workspaces the plan promises must hold the layout of its capacities
@@ -477,7 +494,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool z
         StageTimer t(SG_PREPROCESS, s);
         SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, true, b.cq, b.cw, b.iq,
                                    b.iw, b.rect_c, b.rect_i, b.dkey[0],
-                                   zero_A ? b.A : nullptr, b.slots,
+                                   zero_A ? b.A : nullptr, b.prec, b.slots,
                                    reinterpret_cast<unsigned long long*>(b.status + ST_COUNT),
                                    s));
     }
@@ -573,7 +590,7 @@ int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan
         StageTimer t(SG_QUERY, s);
         SDGR_HIP(launch_preprocess(dviews, dscenes, P.nv, P.ns, P.items, P.rp, false, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   slots, totals, s));
+                                   nullptr, slots, totals, s));
     }
     unsigned long long host_tot[2] = {0, 0};
     SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));
@@ -593,6 +610,7 @@ int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan
     out.tile = TILE;
     out.recompute = P.recompute ? 1 : 0;
     out.deterministic = P.det ? 1 : 0;
+    out.sh_coeffs = P.shc;
     out.image_floats = (size_t)P.image_floats;
     Bufs b;
     layout(P, out.pairs_c, out.pairs_i, FWD, nullptr, nullptr, b, &out.state_bytes,
@@ -655,6 +673,7 @@ void sdgr_default_options(sdgr_options* opt)
     opt->dilation = 0.0f;
     opt->deterministic = 0;
     opt->tile = 0;
+    opt->cell_area = 0;
     opt->reserved = 0;
 }
 
@@ -697,6 +716,8 @@ int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i)
     P.items = plan->gaussians;   // sizes the parameter-gradient parts
     P.recompute = plan->recompute != 0;
     P.det = plan->deterministic != 0;
+    P.shc = plan->sh_coeffs;
+    if (P.shc < 0 || P.shc > 16) return fail(SDGR_EINVAL, "plan's sh_coeffs outside 0..16");
     plan->pairs_c = pairs_c;
     plan->pairs_i = pairs_i;
     Bufs b;
@@ -749,8 +770,8 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     }
     {
         StageTimer t(SG_INTENSITY, s);
-        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, b.rect_i,
-                                      b.cnt_i, b.bsum_i, b.status, b.active, s));
+        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.prec, b.iw,
+                                      b.rect_i, b.cnt_i, b.bsum_i, b.status, b.active, s));
     }
     if ((rc = build_lists_i(P, plan, b, s))) return rc;
     const int pwi = final_buffer_i(P);
@@ -783,14 +804,18 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         return fail(SDGR_EINVAL, "workspaces must be 256-byte aligned");
     for (int sidx = 0; sidx < nscenes; ++sidx) {
         const sdgr_scene_grad& g = grads[sidx];
-        if (scenes[sidx].n > 0 &&
-            (!g.d_means || !g.d_scales || !g.d_quats || !g.d_amp || !g.d_ext))
+        const sdgr_scene& S = scenes[sidx];
+        if (S.n > 0 && (!g.d_means || !g.d_scales || !g.d_quats || !g.d_ext ||
+                        (!g.d_amp && !S.sh) || (!g.d_ext_back && S.ext_back) ||
+                        (!g.d_sh && S.sh)))
             return fail(SDGR_EINVAL, "scene " + std::to_string(sidx) + ": null gradient array");
         P.scenes[sidx].d_means = g.d_means;
         P.scenes[sidx].d_scales = g.d_scales;
         P.scenes[sidx].d_quats = g.d_quats;
         P.scenes[sidx].d_amp = g.d_amp;
         P.scenes[sidx].d_ext = g.d_ext;
+        P.scenes[sidx].d_ext_back = S.ext_back ? g.d_ext_back : nullptr;
+        P.scenes[sidx].d_sh = S.sh ? g.d_sh : nullptr;
     }
     hipStream_t s = (hipStream_t)stream;
     Bufs b;
@@ -802,8 +827,8 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         // the forward's lists are gone: rebuild them (identical, the sorts
         // are deterministic) and refill the intensities from the kept A
         if ((rc = build_lists_c(P, plan, b, false, s))) return rc;
-        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.iw, nullptr,
-                                      nullptr, nullptr, b.status, b.active, s));
+        SDGR_HIP(launch_set_intensity(b.views, b.scenes, P.nv, P.records, b.A, b.prec, b.iw,
+                                      nullptr, nullptr, nullptr, b.status, b.active, s));
     }
     const int pw = final_buffer_c(P);
     {
@@ -811,7 +836,8 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         // only the records pass A used (listed by the intensity pass) carry
         // gradients; this pass also clears their computation-plane sums
         SDGR_HIP(launch_image_bwd(b.views, b.scenes, P.nv, P.records, P.rp, b.status, b.active,
-                                  b.iq, b.iw, dL_dimages, b.grad_i, b.cbwd, b.grad_c, s));
+                                  b.iq, b.iw, b.prec, dL_dimages, b.grad_i, b.cbwd, b.grad_c,
+                                  s));
     }
     {
         StageTimer t(SG_RASTER_A_BWD, s);
@@ -831,7 +857,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,
-                                    b.grad_c, b.grad_i, P.records, b.pgrad, s));
+                                    b.grad_c, b.grad_i, P.records, P.shc, b.pgrad, s));
     return SDGR_OK;
 }
 

@@ -24,6 +24,8 @@ struct DevView {
     int64_t img_off;              // float offset of the image
     int64_t ray_off;              // first computation-plane cell
     int64_t pix_off;              // first pixel in the concatenation of all images
+    double range;                 // radar's slant distance from the origin (0: plane wave)
+    double pscale;                // factor on P: the cell area dAc dEc, or 1
     int32_t W, H, Wc, Hc;
     int32_t txc, tyc, txi, tyi;   // tiles per axis on each plane
     int32_t tile_c, tile_i;       // first bucket id on each plane
@@ -36,13 +38,19 @@ struct DevScene {
     const float* quats;
     const float* amp;
     const float* ext;
+    const float* ext_back;   // or null: ext is the total extinction
+    const float* sh;         // [n, shc] phase-function SH coefficients, or null
     float* d_means;
     float* d_scales;
     float* d_quats;
-    float* d_amp;
+    float* d_amp;            // may be null with sh
     float* d_ext;
+    float* d_ext_back;
+    float* d_sh;
     int64_t n;
     int64_t item_off;   // first Gaussian of this scene in the flat item space
+    int32_t shc;        // SH coefficients per Gaussian, (degree + 1)^2, 0 without sh
+    int32_t pad;
 };
 
 struct RasterParams {
@@ -254,13 +262,14 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
                              int64_t items, const RasterParams& rp,
                              bool write_records, float4* cq, float2* cw, float4* iq,
                              float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* dkey,
-                             float* A_zero, unsigned long long* slots,
+                             float* A_zero, float* prec, unsigned long long* slots,
                              unsigned long long* totals, hipStream_t s);
 
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
-                                int64_t records, const float* A, float2* iw,
-                                const uint2* rect_i, uint32_t* cnt_i, uint32_t* bsum_i,
-                                uint32_t* status, uint32_t* active, hipStream_t s);
+                                int64_t records, const float* A, const float* prec,
+                                float2* iw, const uint2* rect_i, uint32_t* cnt_i,
+                                uint32_t* bsum_i, uint32_t* status, uint32_t* active,
+                                hipStream_t s);
 
 // Per-record gradient buffers are plane-major: component k of record r at
 // [k * records + r]; grad_c = (dcx, dcy, da, db, dc, dkappa) on the
@@ -269,9 +278,11 @@ hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, 
                                   int nscenes, int64_t scene_items,
                                   const RasterParams& rp, const float* A,
                                   const float* grad_c, const float* grad_i,
-                                  int64_t records, float* part, hipStream_t s);
-// Scratch floats of the per-view-group gradient parts (0: one group).
-size_t params_part_floats(int nv, int64_t items);
+                                  int64_t records, int sh_coeffs, float* part,
+                                  hipStream_t s);
+// Scratch floats of the per-view-group gradient parts (0: one group);
+// sh_coeffs: the most SH coefficients of any scene.
+size_t params_part_floats(int nv, int64_t items, int sh_coeffs);
 
 // stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
 // n_dev points at the device-side element count (<= cap). Buffers [0] hold
@@ -359,8 +370,8 @@ hipError_t launch_raster_b_tiles(const DevView* views, int nv, int64_t pixels, i
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
                             int64_t records, const RasterParams& rp, const uint32_t* status,
                             const uint32_t* active, const float4* iq, const float2* iw,
-                            const float* dimg, float* grad_i, float* cbwd, float* grad_c,
-                            hipStream_t s);
+                            const float* prec, const float* dimg, float* grad_i, float* cbwd,
+                            float* grad_c, hipStream_t s);
 hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,

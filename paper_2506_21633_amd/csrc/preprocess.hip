@@ -6,6 +6,7 @@
 // One thread per record r = (view v, Gaussian i). Geometry in FP64 (the
 // O(views x Gaussians) part is cheap), records stored in FP32.
 #include "common.hpp"
+#include "sh.hpp"
 
 #include <math.h>
 
@@ -14,6 +15,7 @@ namespace {
 
 struct Geo {
     bool valid;
+    double mu[3];
     double qn[4], qnorm, s[3], R[9], M[9];
     double S[6];        // 3D covariance xx, xy, xz, yy, yz, zz
 };
@@ -41,6 +43,7 @@ __device__ void gaussian_frame(const DevScene& S, int64_t i, Geo& g)
     const float* sc = S.scales + 3 * i;
     const float* qq = S.quats + 4 * i;
     double m0 = mu[0], m1 = mu[1], m2 = mu[2];
+    g.mu[0] = m0; g.mu[1] = m1; g.mu[2] = m2;
     double s0 = sc[0], s1 = sc[1], s2 = sc[2];
     double q0 = qq[0], q1 = qq[1], q2 = qq[2], q3 = qq[3];
     double n2 = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
@@ -159,12 +162,35 @@ __device__ __forceinline__ Conic2 plane_conic(const float* Mt, const float* e1, 
     return r;
 }
 
+// Unit direction from the centre (m0, m1, m2) to the radar, which sits on
+// the line of sight through the origin at slant distance V.range on the near
+// side; a plane wave (range 0) arrives from -e_z everywhere.
+__device__ __forceinline__ void radar_direction_f(const DevView& V, float m0, float m1, float m2,
+                                                  float* d)
+{
+    const float ez0 = (float)V.ez[0], ez1 = (float)V.ez[1], ez2 = (float)V.ez[2];
+    if (V.range > 0.0) {
+        const float rr = (float)V.range;
+        const float w0 = -rr * ez0 - m0, w1 = -rr * ez1 - m1, w2 = -rr * ez2 - m2;
+        const float n2 = w0 * w0 + w1 * w1 + w2 * w2;
+        if (n2 > 0.0f) {
+            const float inv = rsqrtf(n2);
+            d[0] = w0 * inv; d[1] = w1 * inv; d[2] = w2 * inv;
+            return;
+        }
+    }
+    d[0] = -ez0; d[1] = -ez1; d[2] = -ez2;
+}
+
 // FP32 projection of the records; the range coordinate that orders the
 // depth lists is evaluated in FP64 (range_coordinate) for a reproducible
 // key. A thread takes one Gaussian and up to PRE_VIEWS views of its scene
 // (grid y: the group of views), so the Gaussian's parameters are read and
 // its rotation built once per group instead of once per record; writes of
-// one view are coalesced across the block's Gaussians.
+// one view are coalesced across the block's Gaussians. With prec given, it
+// also writes each record's phase factor: P (the scalar amplitude or the SH
+// expansion at the direction to the radar) times the view's cell-area
+// factor.
 constexpr int PRE_VIEWS = 8;
 
 __global__ void __launch_bounds__(256)
@@ -173,7 +199,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
              float4* __restrict__ cq, float2* __restrict__ cw, float4* __restrict__ iq,
              float2* __restrict__ iw, uint2* __restrict__ rect_c, uint2* __restrict__ rect_i,
              uint32_t* __restrict__ dkey, float* __restrict__ A_zero,
-             unsigned long long* __restrict__ totals)
+             float* __restrict__ prec, unsigned long long* __restrict__ totals)
 {
     __shared__ unsigned long long part[2];
     if (threadIdx.x < 2) part[threadIdx.x] = 0;
@@ -188,7 +214,8 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
         const float s0 = S.scales[3 * i], s1 = S.scales[3 * i + 1], s2 = S.scales[3 * i + 2];
         const float* qp = S.quats + 4 * i;
         const float4 q = make_float4(qp[0], qp[1], qp[2], qp[3]);
-        const float ext = S.ext[i];
+        // only the sum of the forward and backward extinctions enters
+        const float ext = S.ext_back ? S.ext[i] + S.ext_back[i] : S.ext[i];
         const float n2 = q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w;
         const bool valid = isfinite(m0) && isfinite(m1) && isfinite(m2) && isfinite(s0) &&
                            isfinite(s1) && isfinite(s2) && s0 > 0.0f && s1 > 0.0f &&
@@ -241,6 +268,21 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
                     vi_w = make_float2(I.c, 0.0f);
                 }
             }
+            if (write_records && prec) {
+                float P = 0.0f;
+                if (valid) {
+                    if (S.shc > 0) {
+                        float d[3], Y[SH_MAX];
+                        radar_direction_f(V, m0, m1, m2, d);
+                        sh_basis(d[0], d[1], d[2], S.shc, Y);
+                        const float* c = S.sh + (int64_t)S.shc * i;
+                        for (int k = 0; k < S.shc; ++k) P += c[k] * Y[k];
+                    } else {
+                        P = S.amp[i];
+                    }
+                }
+                prec[r] = P * (float)V.pscale;
+            }
             if (write_records) {
                 cq[r] = vc_q;
                 cw[r] = vc_w;
@@ -284,7 +326,9 @@ k_sum_slots(const unsigned long long* __restrict__ slots, unsigned long long* __
     if (threadIdx.x < 2) out[threadIdx.x] = acc[threadIdx.x];
 }
 
-// I = P A into the imaging record (incident intensity 1, Sec. II-A); with
+// I = P A into the imaging record (incident intensity 1, Sec. II-A; P the
+// record's phase factor from prec when given, else the scalar amplitude
+// times the view's cell-area factor); with
 // cnt_i given, also the imaging-plane pair count of the record: the tiles of
 // its rectangle if I is nonzero, none otherwise (a zero intensity adds
 // nothing to any pixel), and their sum over each block of 256 records.
@@ -298,7 +342,8 @@ constexpr int INT_GROUPS = 16;
 
 __global__ void __launch_bounds__(256)
 k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
-                int64_t records, const float* __restrict__ A, float2* __restrict__ iw,
+                int64_t records, const float* __restrict__ A,
+                const float* __restrict__ prec, float2* __restrict__ iw,
                 const uint2* __restrict__ rect_i, uint32_t* __restrict__ cnt_i,
                 uint32_t* __restrict__ bsum_i, uint32_t* __restrict__ status,
                 uint32_t* __restrict__ active)
@@ -323,7 +368,9 @@ k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ 
             const int v = r < v0_end ? v0
                                      : find_view(nv, r, [&](int k) { return views[k].rec_off; });
             const DevView& V = views[v];
-            const float I = scenes[V.scene].amp[r - V.rec_off] * a;
+            const float P = prec ? prec[r]
+                                 : scenes[V.scene].amp[r - V.rec_off] * (float)V.pscale;
+            const float I = P * a;
             iw[r].y = I;
             if (cnt_i) {
                 if (I != 0.0f) {
@@ -393,10 +440,13 @@ __device__ void plane_adjoint(const double* Q, const float* gq, const double* u,
 }
 
 // Per-Gaussian gradient outputs: d_means (3), d_scales (3), d_quats (4),
-// d_amp, d_ext. The backward takes the views PB_VIEWS at a time (grid y).
+// d_amp, d_ext (d_ext_back is the same), then the SH coefficients' (up to
+// SH_MAX) for scenes with a phase-function expansion. The backward takes the
+// views PB_VIEWS at a time (grid y).
 constexpr int PB_OUT = 12;
 constexpr int PB_VIEWS = 8;
 
+template <bool SH>
 __device__ __forceinline__ void store_param_grads(const DevScene& S, int64_t i, const float* o)
 {
     float* om = S.d_means + 3 * i;
@@ -405,15 +455,23 @@ __device__ __forceinline__ void store_param_grads(const DevScene& S, int64_t i, 
     om[0] = o[0]; om[1] = o[1]; om[2] = o[2];
     os[0] = o[3]; os[1] = o[4]; os[2] = o[5];
     oq[0] = o[6]; oq[1] = o[7]; oq[2] = o[8]; oq[3] = o[9];
-    S.d_amp[i] = o[10];
+    if (S.d_amp) S.d_amp[i] = o[10];
     S.d_ext[i] = o[11];
+    if (S.d_ext_back) S.d_ext_back[i] = o[11];
+    if (SH)
+        for (int k = 0; k < S.shc; ++k) S.d_sh[(int64_t)S.shc * i + k] = o[PB_OUT + k];
 }
 
+// dL/dP per view is A dL/dI times the view's cell-area factor. With an SH
+// phase function P = sum_k c_k Y_k(d), d = (x_radar - mu) / |x_radar - mu|:
+// dL/dc_k = dL/dP Y_k(d), and the means gain dL/dP (dd/dmu)^T grad_d P with
+// dd/dmu = -(I - d d^T) / |x_radar - mu| (zero for a plane wave).
+template <bool SH>
 __global__ void __launch_bounds__(256)
 k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
                   int nscenes, int64_t items, RasterParams rp, const float* __restrict__ A,
                   const float* __restrict__ grad_c, const float* __restrict__ grad_i,
-                  int64_t records, float* __restrict__ part)
+                  int64_t records, int nout, float* __restrict__ part)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= items) return;
@@ -422,6 +480,15 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
     int64_t i = t - S.item_off;
     double dmu[3] = {0, 0, 0}, dS[6] = {0, 0, 0, 0, 0, 0};
     double dk = 0.0, dp = 0.0;
+    constexpr int NSH = SH ? SH_MAX : 1;
+    double csh[NSH], dsh[NSH];
+    const int nsh = SH ? S.shc : 0;
+    if (SH) {
+        for (int k = 0; k < NSH; ++k) {
+            csh[k] = k < nsh ? (double)S.sh[(int64_t)nsh * i + k] : 0.0;
+            dsh[k] = 0.0;
+        }
+    }
     Geo g;
     gaussian_frame(S, i, g);
     bool any = false;
@@ -446,11 +513,35 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
         plane_adjoint(QC, gc, V.ex, V.ey, V.iAc, V.iEc, dS, dmu);
         plane_adjoint(QI, gi, V.ex, V.ez, V.iA, V.iR, dS, dmu);
         dk += gc[5];
-        dp += (double)A[r] * gi[5];
+        const double dP = (double)A[r] * gi[5] * V.pscale;
+        if (SH && nsh > 0) {
+            double d[3], inv_r = 0.0;
+            double w[3] = {-V.range * V.ez[0] - g.mu[0], -V.range * V.ez[1] - g.mu[1],
+                           -V.range * V.ez[2] - g.mu[2]};
+            const double n2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+            if (V.range > 0.0 && n2 > 0.0) {
+                inv_r = 1.0 / sqrt(n2);
+                for (int k = 0; k < 3; ++k) d[k] = w[k] * inv_r;
+            } else {
+                for (int k = 0; k < 3; ++k) d[k] = -V.ez[k];
+            }
+            double Y[SH_MAX];
+            sh_basis(d[0], d[1], d[2], nsh, Y);
+            for (int k = 0; k < NSH; ++k)
+                if (k < nsh) dsh[k] += dP * Y[k];
+            if (inv_r > 0.0) {
+                double gd[3];
+                sh_expansion_grad(csh, nsh, d[0], d[1], d[2], gd);
+                const double along = gd[0] * d[0] + gd[1] * d[1] + gd[2] * d[2];
+                for (int k = 0; k < 3; ++k) dmu[k] -= dP * (gd[k] - along * d[k]) * inv_r;
+            }
+        } else {
+            dp += dP;
+        }
     }
     // the gradients are linear in (dSigma, dmu, dkappa, dP): a group of views
     // contributes its own part, summed over the groups by k_params_reduce
-    float o[PB_OUT] = {};
+    float o[PB_OUT + (SH ? SH_MAX : 0)] = {};
     if (any && g.valid) {
         // Sigma = M M^T with M = R diag(s): dM = 2 dSigma M (dSigma symmetric)
         double D[9] = {dS[0], dS[1], dS[2], dS[1], dS[3], dS[4], dS[2], dS[4], dS[5]};
@@ -483,32 +574,41 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
         o[9] = (float)((gz - z * dot) * inv);
         o[10] = (float)dp;
         o[11] = (float)dk;
+        if (SH)
+            for (int k = 0; k < NSH; ++k) o[PB_OUT + k] = (float)dsh[k];
     }
     if (gridDim.y == 1) {
-        store_param_grads(S, i, o);
+        store_param_grads<SH>(S, i, o);
     } else {
+        const int nw = PB_OUT + nsh;
 #pragma unroll
-        for (int k = 0; k < PB_OUT; ++k) part[((int64_t)blockIdx.y * PB_OUT + k) * items + t] = o[k];
+        for (int k = 0; k < PB_OUT + (SH ? SH_MAX : 0); ++k)
+            if (k < nw) part[((int64_t)blockIdx.y * nout + k) * items + t] = o[k];
     }
 }
 
-// Sum of the view groups' parts of every Gaussian's gradients.
+// Sum of the view groups' parts of every Gaussian's gradients (nout floats
+// per group and Gaussian; a scene's Gaussians use PB_OUT + its SH count).
+template <bool SH>
 __global__ void __launch_bounds__(256)
 k_params_reduce(const DevScene* __restrict__ scenes, int nscenes, int64_t items, int groups,
-                const float* __restrict__ part)
+                int nout, const float* __restrict__ part)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= items) return;
     const int s = find_view(nscenes, t, [&](int k) { return scenes[k].item_off; });
     const DevScene& S = scenes[s];
-    double acc[PB_OUT] = {};
+    constexpr int NO = PB_OUT + (SH ? SH_MAX : 0);
+    const int nw = PB_OUT + (SH ? S.shc : 0);
+    double acc[NO] = {};
     for (int gq = 0; gq < groups; ++gq)
 #pragma unroll
-        for (int k = 0; k < PB_OUT; ++k) acc[k] += part[((int64_t)gq * PB_OUT + k) * items + t];
-    float o[PB_OUT];
+        for (int k = 0; k < NO; ++k)
+            if (k < nw) acc[k] += part[((int64_t)gq * nout + k) * items + t];
+    float o[NO];
 #pragma unroll
-    for (int k = 0; k < PB_OUT; ++k) o[k] = (float)acc[k];
-    store_param_grads(S, t - S.item_off, o);
+    for (int k = 0; k < NO; ++k) o[k] = (float)acc[k];
+    store_param_grads<SH>(S, t - S.item_off, o);
 }
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -524,7 +624,7 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int n)
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv, int nscenes,
                              int64_t items, const RasterParams& rp, bool write_records,
                              float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
-                             uint2* rect_i, uint32_t* dkey, float* A_zero,
+                             uint2* rect_i, uint32_t* dkey, float* A_zero, float* prec,
                              unsigned long long* slots, unsigned long long* totals,
                              hipStream_t s)
 {
@@ -535,45 +635,59 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
                            dim3(blocks_for(items, 256), (unsigned)((nv + PRE_VIEWS - 1) / PRE_VIEWS)),
                            dim3(256), 0, s, views, scenes, nv, nscenes, items, rp,
                            write_records ? 1 : 0, cq, cw, iq, iw, rect_c, rect_i, dkey,
-                           write_records ? A_zero : nullptr, slots);
+                           write_records ? A_zero : nullptr, write_records ? prec : nullptr,
+                           slots);
     hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(TOTAL_SLOTS), 0, s, slots, totals);
     return hipGetLastError();
 }
 
 hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, int nv,
-                                int64_t records, const float* A, float2* iw,
-                                const uint2* rect_i, uint32_t* cnt_i, uint32_t* bsum_i,
-                                uint32_t* status, uint32_t* active, hipStream_t s)
+                                int64_t records, const float* A, const float* prec,
+                                float2* iw, const uint2* rect_i, uint32_t* cnt_i,
+                                uint32_t* bsum_i, uint32_t* status, uint32_t* active,
+                                hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_set_intensity, dim3(blocks_for(records, 4 * INT_GROUPS * WAVE)),
-                       dim3(256), 0, s, views, scenes, nv, records, A, iw, rect_i, cnt_i, bsum_i,
-                       status, active);
+                       dim3(256), 0, s, views, scenes, nv, records, A, prec, iw, rect_i, cnt_i,
+                       bsum_i, status, active);
     return hipGetLastError();
 }
 
 int params_groups(int nv) { return nv > 0 ? (nv + PB_VIEWS - 1) / PB_VIEWS : 1; }
 
-size_t params_part_floats(int nv, int64_t items)
+size_t params_part_floats(int nv, int64_t items, int sh_coeffs)
 {
     const int g = params_groups(nv);
-    return g > 1 ? (size_t)PB_OUT * g * (size_t)items : 0;
+    return g > 1 ? (size_t)(PB_OUT + sh_coeffs) * g * (size_t)items : 0;
 }
 
 hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, int nv,
                                   int nscenes, int64_t scene_items, const RasterParams& rp,
                                   const float* A, const float* grad_c, const float* grad_i,
-                                  int64_t records, float* part, hipStream_t s)
+                                  int64_t records, int sh_coeffs, float* part, hipStream_t s)
 {
     if (scene_items <= 0) return hipSuccess;
+    if (sh_coeffs < 0 || sh_coeffs > SH_MAX) return hipErrorInvalidValue;
     const int groups = params_groups(nv);
     if (groups > 1 && !part) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_params_backward, dim3(blocks_for(scene_items, 256), groups), dim3(256),
-                       0, s, views, scenes, nv, nscenes, scene_items, rp, A, grad_c, grad_i,
-                       records, part);
-    if (groups > 1)
-        hipLaunchKernelGGL(k_params_reduce, dim3(blocks_for(scene_items, 256)), dim3(256), 0, s,
-                           scenes, nscenes, scene_items, groups, part);
+    const int nout = PB_OUT + sh_coeffs;
+    const dim3 grid(blocks_for(scene_items, 256), groups);
+    if (sh_coeffs > 0)
+        hipLaunchKernelGGL(k_params_backward<true>, grid, dim3(256), 0, s, views, scenes, nv,
+                           nscenes, scene_items, rp, A, grad_c, grad_i, records, nout, part);
+    else
+        hipLaunchKernelGGL(k_params_backward<false>, grid, dim3(256), 0, s, views, scenes, nv,
+                           nscenes, scene_items, rp, A, grad_c, grad_i, records, nout, part);
+    if (groups > 1) {
+        const dim3 g1(blocks_for(scene_items, 256));
+        if (sh_coeffs > 0)
+            hipLaunchKernelGGL(k_params_reduce<true>, g1, dim3(256), 0, s, scenes, nscenes,
+                               scene_items, groups, nout, part);
+        else
+            hipLaunchKernelGGL(k_params_reduce<false>, g1, dim3(256), 0, s, scenes, nscenes,
+                               scene_items, groups, nout, part);
+    }
     return hipGetLastError();
 }
 

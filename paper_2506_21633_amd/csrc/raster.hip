@@ -803,8 +803,9 @@ __global__ void __launch_bounds__(256)
 k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
             int64_t records, RasterParams rp, const uint32_t* __restrict__ status,
             const uint32_t* __restrict__ active, const float4* __restrict__ iq,
-            const float2* __restrict__ iw, const float* __restrict__ dimg,
-            float* __restrict__ grad_i, float* __restrict__ cbwd, float* __restrict__ grad_c)
+            const float2* __restrict__ iw, const float* __restrict__ prec,
+            const float* __restrict__ dimg, float* __restrict__ grad_i,
+            float* __restrict__ cbwd, float* __restrict__ grad_c)
 {
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if ((int64_t)blockIdx.x * blockDim.x >= (int64_t)status[ST_ACTIVE]) return;
@@ -856,7 +857,8 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
     grad_i[3 * records + r] = db;
     grad_i[4 * records + r] = dc;
     grad_i[5 * records + r] = dI;
-    cbwd[r] = scenes[V.scene].amp[r - V.rec_off] * dI;   // c = P dL/dI for pass A
+    // c = P dL/dI for pass A (P the record's phase factor)
+    cbwd[r] = (prec ? prec[r] : scenes[V.scene].amp[r - V.rec_off] * (float)V.pscale) * dI;
     // pass A backward adds into the record's computation-plane sums
 #pragma unroll
     for (int k = 0; k < 6; ++k) grad_c[k * records + r] = 0.0f;
@@ -1360,12 +1362,12 @@ hipError_t launch_raster_b_tiles(const DevView* views, int nv, int64_t pixels, i
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
                             int64_t records, const RasterParams& rp, const uint32_t* status,
                             const uint32_t* active, const float4* iq, const float2* iw,
-                            const float* dimg, float* grad_i, float* cbwd, float* grad_c,
-                            hipStream_t s)
+                            const float* prec, const float* dimg, float* grad_i, float* cbwd,
+                            float* grad_c, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_image_bwd, dim3(grid256(records)), dim3(256), 0, s, views, scenes, nv,
-                       records, rp, status, active, iq, iw, dimg, grad_i, cbwd, grad_c);
+                       records, rp, status, active, iq, iw, prec, dimg, grad_i, cbwd, grad_c);
     return hipGetLastError();
 }
 

@@ -51,18 +51,24 @@ def test_default_options():
     o = C.Options()
     C.lib().sdgr_default_options(ctypes.byref(o))
     assert (o.shadowing, o.recompute, o.q_max, o.tau_max, o.dilation, o.deterministic, o.tile,
-            o.reserved) == (1, 0, 9.0, 16.0, 0.0, 0, 0, 0)
+            o.cell_area, o.reserved) == (1, 0, 9.0, 16.0, 0.0, 0, 0, 0, 0)
 
 
-def _args(grazing=math.radians(45), nv=1, n=10, q_max=9.0, scene=0, w=64):
-    sc = (C.Scene * 1)(C.Scene(n, 0x1000, 0x1000, 0x1000, 0x1000, 0x1000))
+def _args(grazing=math.radians(45), nv=1, n=10, q_max=9.0, scene=0, w=64, sh_degree=None,
+          amp=0x1000, radar_range=0.0, cell_area=0, scene_reserved=0):
+    sc = (C.Scene * 1)(C.Scene(n, 0x1000, 0x1000, 0x1000, amp, 0x1000))
+    if sh_degree is not None:
+        sc[0].sh, sc[0].sh_degree = 0x1000, sh_degree
+    sc[0].reserved = scene_reserved
     views = (C.View * max(nv, 1))()
     for v in views:
         v.azimuth, v.grazing, v.d_az, v.d_rg = 0.0, grazing, 0.1, 0.1
         v.img_w, v.img_h, v.scene = w, 64, scene
+        v.radar_range = radar_range
     o = C.Options()
     C.lib().sdgr_default_options(ctypes.byref(o))
     o.q_max = q_max
+    o.cell_area = cell_area
     return sc, views, o
 
 
@@ -76,6 +82,13 @@ def _args(grazing=math.radians(45), nv=1, n=10, q_max=9.0, scene=0, w=64):
     (dict(scene=3), C.SDGR_EINVAL),
     (dict(w=0), C.SDGR_EINVAL),
     (dict(w=8 * 70000), C.SDGR_EUNSUPPORTED),
+    (dict(sh_degree=4), C.SDGR_EUNSUPPORTED),
+    (dict(sh_degree=-1), C.SDGR_EUNSUPPORTED),
+    (dict(amp=0), C.SDGR_EINVAL),
+    (dict(radar_range=-1.0), C.SDGR_EINVAL),
+    (dict(radar_range=float("inf")), C.SDGR_EINVAL),
+    (dict(cell_area=2), C.SDGR_EINVAL),
+    (dict(scene_reserved=1), C.SDGR_EINVAL),
 ])
 def test_plan_query_rejects_bad_arguments(kw, code):
     L = C.lib()
@@ -86,6 +99,54 @@ def test_plan_query_rejects_bad_arguments(kw, code):
                            ctypes.byref(plan))
     assert rc == code
     assert L.sdgr_last_error()
+
+
+def test_sh_scene_needs_no_amplitude():
+    """With an SH phase function amp may be NULL: validation passes and the
+    query stops only at its missing scratch."""
+    L = C.lib()
+    sc, views, o = _args(sh_degree=3, amp=0, radar_range=50.0, cell_area=1)
+    plan = C.Plan()
+    rc = L.sdgr_plan_query(sc, 1, views, 1, ctypes.byref(o), None, 0, None, ctypes.byref(plan))
+    assert rc == C.SDGR_EWORKSPACE
+
+
+@pytest.mark.parametrize("missing", ["d_sh", "d_ext_back"])
+def test_backward_needs_gradients_of_the_optional_inputs(missing):
+    L = C.lib()
+    sc, views, o = _args(sh_degree=2, amp=0)
+    sc[0].ext_back = 0x1000
+    p = _host_plan(10, 1, 64)
+    p.sh_coeffs = 9
+    C.check(L.sdgr_plan_resize(ctypes.byref(p), 100, 100))
+    g = C.SceneGrad(0x1000, 0x1000, 0x1000, 0, 0x1000, 0x1000, 0x1000)
+    setattr(g, missing, 0)
+    rc = L.sdgr_backward(sc, 1, views, 1, ctypes.byref(o), ctypes.byref(p), 0x1000, 0x1000,
+                         0x1000, (C.SceneGrad * 1)(g), None)
+    assert rc == C.SDGR_EINVAL and b"gradient" in L.sdgr_last_error()
+
+
+def test_plan_must_carry_the_sh_coefficient_count():
+    L = C.lib()
+    sc, views, o = _args(sh_degree=1)
+    p = _host_plan(10, 1, 64)
+    C.check(L.sdgr_plan_resize(ctypes.byref(p), 100, 100))   # sh_coeffs 0: no SH scene
+    rc = L.sdgr_forward(sc, 1, views, 1, ctypes.byref(o), ctypes.byref(p), 0x1000, 0x1000,
+                        0x1000, None)
+    assert rc == C.SDGR_EINVAL and b"plan" in L.sdgr_last_error()
+
+
+def test_sh_plans_hold_the_coefficient_parts():
+    """More than one group of views: the parameter-gradient parts grow by
+    the coefficient count per Gaussian and group."""
+    L = C.lib()
+    got = []
+    for shc in (0, 16):
+        p = _host_plan(100_000, 16, 256)
+        p.sh_coeffs = shc
+        C.check(L.sdgr_plan_resize(ctypes.byref(p), 1_000_000, 1_000_000))
+        got.append(p.bwd_scratch_bytes)
+    assert got[1] - got[0] >= 2 * 16 * 4 * 100_000
 
 
 def test_plan_query_needs_scratch():
