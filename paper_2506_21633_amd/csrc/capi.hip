@@ -466,10 +466,13 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
     return SDGR_OK;
 }
 
-// The depth sort orders all records by depth alone: the views need not be
-// separated, since the stable bucket sort of the pairs groups them by tile
-// (and so by view) afterwards and keeps the depth order within each tile.
-// Computation-plane buckets are [0, tiles_c); imaging-plane buckets follow.
+// Up to SEG_MAX views the depth sort and the pair sort are segmented by
+// view (each view's records sorted by depth within the view, the pairs by
+// the tile within the view); beyond that the depth sort orders all records
+// by depth alone, which is enough since the stable bucket sort of the pairs
+// groups them by global tile (and so by view) and keeps the depth order
+// within each tile. Computation-plane buckets are [0, tiles_c);
+// imaging-plane buckets follow.
 int bits_pairs_c(const Problem& P) { return P.seg ? P.cbits : bits_for(P.tiles_c - 1); }
 int bits_pairs_i(const Problem& P)
 {

@@ -3,8 +3,10 @@
 // projections P_C and P_I) and its adjoint (Sec. II-B, gradient of the
 // Gaussian parameters, both planes contributing to dL/dSigma).
 //
-// One thread per record r = (view v, Gaussian i). Geometry in FP64 (the
-// O(views x Gaussians) part is cheap), records stored in FP32.
+// Forward: a thread per Gaussian and group of views; the projection runs
+// in FP32 except the range coordinate that orders the depth lists, which is
+// FP64 for a reproducible key; records are stored in FP32. The parameter
+// adjoint runs in FP64 (O(views x Gaussians), cheap).
 #include "common.hpp"
 #include "sh.hpp"
 

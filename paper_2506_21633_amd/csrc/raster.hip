@@ -19,7 +19,7 @@
 //                    tau -= kappa f, T = exp(-tau), dL/dalpha = T (c - U),
 //                    U <- c alpha + (1 - alpha) U (division-free), c = P dL/dI.
 // Imaging plane (order-free additive layover)
-//   pass B forward : fixed 2048-entry segments of the sorted (tile, Gaussian)
+//   pass B forward : fixed 128-entry segments of the sorted (tile, Gaussian)
 //                    pair array, one wave each (balanced however long a
 //                    tile's list is); footprint masks computed on the fly
 //                    and bit-transposed, so lane = pixel sums only the
@@ -637,7 +637,7 @@ k_zero_images(const DevView* __restrict__ views, int nv, int64_t pixels, float* 
     images[views[v].img_off + (p - views[v].pix_off)] = 0.0f;
 }
 
-// Pass B forward over fixed 2048-entry segments of the sorted imaging-plane
+// Pass B forward over fixed B_SEGMENT-entry segments of the sorted imaging-plane
 // pair array (one wave each, balanced however long a tile's list is).
 // Lane = entry: gather the record, compute its footprint mask on the
 // entry's tile; then, per run of entries of one tile, the masks are
