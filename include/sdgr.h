@@ -90,17 +90,23 @@ typedef struct sdgr_scene {
     const float* amp;     /* [n]   scattering amplitude P (phase function) */
     const float* ext;     /* [n]   extinction kappa, or k_e+ with ext_back */
     const float* ext_back;   /* [n] backward extinction k_e-, or NULL */
-    const float* sh;         /* [n, (sh_degree + 1)^2] SH coefficients of
-                                the phase function, or NULL */
+    const float* sh;         /* [n, sh_stride] SH coefficients of the phase
+                                function (the first (sh_degree + 1)^2 of
+                                each row are used), or NULL */
     int32_t sh_degree;       /* 0..3 when sh is given, else ignored */
-    int32_t reserved;        /* must be 0 */
+    int32_t sh_stride;       /* floats from one Gaussian's row of sh (and
+                                of d_sh) to the next: 0 means (sh_degree +
+                                1)^2, else at least that (a degree below the
+                                array's, e.g. while training raises it) */
 } sdgr_scene;
 
 /* Gradient outputs of one scene (device pointers, same shapes as the
  * inputs). They are OVERWRITTEN with the sum over all views of the scene.
  * d_ext_back is required when the scene has ext_back (it receives the same
- * values as d_ext), d_sh when it has sh; with sh, d_amp may be NULL (if
- * given it is filled with zeros: amp takes no part). */
+ * values as d_ext), d_sh when it has sh (rows of sh_stride floats, of which
+ * the used (sh_degree + 1)^2 are written and the rest left untouched); with
+ * sh, d_amp may be NULL (if given it is filled with zeros: amp takes no
+ * part). */
 typedef struct sdgr_scene_grad {
     float* d_means;
     float* d_scales;

@@ -52,12 +52,12 @@ class AdamConfig:
     eps: float = 1e-15
 
 
-def adam_step(x, g, m, v, t, lr, log_space=False, cfg=AdamConfig()):
+def adam_step(x, g, m, v, t, lr, log_space=False, cfg=AdamConfig(), lo=0.0, hi=0.0):
     """One Adam step at iteration t (1-based) on a parameter array x with
     gradient g and moments m, v (all float64 copies are returned).
 
     log_space: x > 0 is stepped as u = log x, whose gradient is g x, and
-    updated as x exp(-step)."""
+    updated as x exp(-step). lo < hi: the result is clamped to [lo, hi]."""
     x = np.asarray(x, np.float64)
     g = np.asarray(g, np.float64)
     m = np.asarray(m, np.float64)
@@ -70,6 +70,8 @@ def adam_step(x, g, m, v, t, lr, log_space=False, cfg=AdamConfig()):
     vhat = v / (1.0 - cfg.beta2 ** t)
     step = lr * mhat / (np.sqrt(vhat) + cfg.eps)
     x = x * np.exp(-step) if log_space else x - step
+    if lo < hi:
+        x = np.clip(x, lo, hi)
     return x, m, v
 
 

@@ -6,6 +6,7 @@ Submodules:
   scenes  seeded synthetic scenes and radar views (inputs only)
   api     Renderer / render / SDGRFunction (loads libsdgr.so on first use)
   serve   continuous-batching render server
+  train   reconstruction loop (Adam, densify/prune) and evaluation metrics
   build   compiles libsdgr.so for gfx950
 """
 __version__ = "0.1.0"

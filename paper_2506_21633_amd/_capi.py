@@ -1,4 +1,5 @@
-"""ctypes mirror of include/sdgr.h (argument marshalling only).
+"""ctypes mirror of include/sdgr.h and include/sdgr_train.h (argument
+marshalling only).
 
 Loading fails loudly when libsdgr.so has not been built: there is no
 fallback implementation anywhere in the package.
@@ -21,7 +22,10 @@ EXPORTED = ("sdgr_version", "sdgr_last_error", "sdgr_default_options",
             "sdgr_backward", "sdgr_status", "sdgr_read_intensity",
             "sdgr_read_optical_depth", "sdgr_profile_enable", "sdgr_profile_read",
             "sdgr_profile_stage", "sdgr_profile_count", "sdgr_read_work",
-            "sdgr_plan_resize", "sdgr_forward_static")
+            "sdgr_plan_resize", "sdgr_forward_static",
+            # reconstruction loop and metrics
+            "sdgr_adam_step", "sdgr_densify_stats", "sdgr_densify_workspace_bytes",
+            "sdgr_densify", "sdgr_nearest_sq", "sdgr_image_metrics")
 
 STATIC_SCRATCH_BYTES = 64 << 20   # SDGR_STATIC_SCRATCH_BYTES
 
@@ -32,7 +36,7 @@ class Scene(ctypes.Structure):
                 ("quats", ctypes.c_void_p), ("amp", ctypes.c_void_p),
                 ("ext", ctypes.c_void_p), ("ext_back", ctypes.c_void_p),
                 ("sh", ctypes.c_void_p), ("sh_degree", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("sh_stride", ctypes.c_int32)]
 
 
 class SceneGrad(ctypes.Structure):
@@ -72,6 +76,38 @@ class Plan(ctypes.Structure):
                 ("gaussians", ctypes.c_int64), ("nviews", ctypes.c_int32), ("nscenes", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("recompute", ctypes.c_int32),
                 ("deterministic", ctypes.c_int32), ("sh_coeffs", ctypes.c_int32)]
+
+
+ADAM_MAX_GROUPS = 16   # SDGR_ADAM_MAX_GROUPS
+
+
+class ParamGroup(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p),
+                ("m", ctypes.c_void_p), ("v", ctypes.c_void_p),
+                ("count", ctypes.c_int64), ("lr", ctypes.c_float),
+                ("log_space", ctypes.c_int32), ("lo", ctypes.c_float), ("hi", ctypes.c_float),
+                ("reserved", ctypes.c_int32)]
+
+
+class AdamConfig(ctypes.Structure):
+    _fields_ = [("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class DensifyConfig(ctypes.Structure):
+    _fields_ = [("grad_threshold", ctypes.c_float), ("split_scale", ctypes.c_float),
+                ("max_radius", ctypes.c_float), ("kappa_min", ctypes.c_float),
+                ("split_factor", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+SET_GROUPS = ("means", "scales", "quats", "amp", "ext", "sh")
+
+
+class GaussianSet(ctypes.Structure):
+    _fields_ = [f for g in SET_GROUPS
+                for f in ((g, ctypes.c_void_p), ("m_" + g, ctypes.c_void_p),
+                          ("v_" + g, ctypes.c_void_p))] + \
+               [("sh_coeffs", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class SDGRError(RuntimeError):
@@ -118,6 +154,19 @@ def lib():
     L.sdgr_profile_count.argtypes = [ctypes.c_int32]
     L.sdgr_plan_resize.argtypes = [P(Plan), ctypes.c_int64, ctypes.c_int64]
     L.sdgr_read_work.argtypes = [P(Plan), vp, P(ctypes.c_uint64), ctypes.c_int32, vp]
+    L.sdgr_adam_step.argtypes = [P(ParamGroup), ctypes.c_int32, ctypes.c_int64, P(AdamConfig),
+                                 vp]
+    L.sdgr_densify_stats.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp]
+    L.sdgr_densify_workspace_bytes.argtypes = [ctypes.c_int64]
+    L.sdgr_densify_workspace_bytes.restype = ctypes.c_size_t
+    L.sdgr_densify.argtypes = [P(GaussianSet), ctypes.c_int64, vp, vp, vp, P(DensifyConfig),
+                               P(GaussianSet), ctypes.c_int64, vp, vp, ctypes.c_size_t, vp]
+    L.sdgr_nearest_sq.argtypes = [vp, ctypes.c_int64, vp, ctypes.c_int64, vp, vp]
+    L.sdgr_image_metrics.argtypes = [vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_float, vp, vp, vp, vp]
+    for name in ("sdgr_adam_step", "sdgr_densify_stats", "sdgr_densify", "sdgr_nearest_sq",
+                 "sdgr_image_metrics"):
+        getattr(L, name).restype = ctypes.c_int
     for name in ("sdgr_plan_resize", "sdgr_profile_count", "sdgr_read_work",
                  "sdgr_profile_enable", "sdgr_profile_read", "sdgr_plan_query", "sdgr_forward", "sdgr_backward", "sdgr_status",
                  "sdgr_read_intensity", "sdgr_read_optical_depth", "sdgr_forward_static"):

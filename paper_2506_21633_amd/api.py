@@ -64,6 +64,7 @@ class GaussianTensors:
     ext: torch.Tensor
     ext_back: Optional[torch.Tensor] = None
     sh: Optional[torch.Tensor] = None      # [n, (deg + 1)^2]
+    sh_active: Optional[int] = None        # degree in use (<= the array's); None: all
 
     @property
     def n(self) -> int:
@@ -71,11 +72,16 @@ class GaussianTensors:
 
     @property
     def sh_degree(self) -> int:
+        """Degree the renderer evaluates (-1 without sh)."""
         if self.sh is None:
             return -1
         deg = int(round(math.sqrt(self.sh.shape[1]))) - 1
         if deg < 0 or deg > 3 or (deg + 1) ** 2 != self.sh.shape[1]:
             raise ValueError("sh must have 1, 4, 9 or 16 coefficients per Gaussian")
+        if self.sh_active is not None:
+            if not 0 <= self.sh_active <= deg:
+                raise ValueError("sh_active outside 0..the array's degree")
+            return int(self.sh_active)
         return deg
 
     @staticmethod
@@ -114,10 +120,10 @@ def _scene_struct(g: GaussianTensors) -> C.Scene:
     a = None if g.amp is None else _dev_f32(g.amp, (n,), "amp")
     eb = None if g.ext_back is None else _dev_f32(g.ext_back, (n,), "ext_back")
     deg = g.sh_degree
-    sh = None if g.sh is None else _dev_f32(g.sh, (n, (deg + 1) ** 2), "sh")
+    sh = None if g.sh is None else _dev_f32(g.sh, (n, g.sh.shape[1]), "sh")
     ptr = lambda t: 0 if t is None else t.data_ptr()
     st = C.Scene(n, m.data_ptr(), s.data_ptr(), q.data_ptr(), ptr(a), e.data_ptr(), ptr(eb),
-                 ptr(sh), max(deg, 0), 0)
+                 ptr(sh), max(deg, 0), 0 if sh is None else int(sh.shape[1]))
     st._keep = (m, s, q, a, e, eb, sh)
     return st
 
@@ -255,6 +261,8 @@ class Renderer:
         for k, sc in enumerate(self.scenes):
             d = {name: torch.empty(t.shape, dtype=torch.float32, device=self.device)
                  for name, t in sc.named().items()}
+            if "sh" in d and sc.sh_degree + 1 < round(math.sqrt(sc.sh.shape[1])):
+                d["sh"].zero_()   # the coefficients above the active degree get none
             ptr = lambda name: d[name].data_ptr() if name in d else 0
             grads_c[k] = C.SceneGrad(ptr("means"), ptr("scales"), ptr("quats"), ptr("amp"),
                                      ptr("ext"), ptr("ext_back"), ptr("sh"))

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsdgr.so")
-SOURCES = ["capi.hip", "preprocess.hip", "sort.hip", "raster.hip"]
+SOURCES = ["capi.hip", "preprocess.hip", "sort.hip", "raster.hip", "train.hip"]
 ARCH = os.environ.get("SDGR_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -173,16 +173,19 @@ int build_problem(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         const sdgr_scene& S = scenes[s];
         if (S.n < 0) return fail(SDGR_EINVAL, "scene " + std::to_string(s) + ": n < 0");
         const std::string tag = "scene " + std::to_string(s) + ": ";
-        if (S.reserved != 0) return fail(SDGR_EINVAL, tag + "reserved must be 0");
         if (S.sh && (S.sh_degree < 0 || S.sh_degree > 3))
             return fail(SDGR_EUNSUPPORTED, tag + "sh_degree outside 0..3");
+        const int shc = S.sh ? (S.sh_degree + 1) * (S.sh_degree + 1) : 0;
+        if (S.sh && S.sh_stride != 0 && S.sh_stride < shc)
+            return fail(SDGR_EINVAL, tag + "sh_stride below the coefficient count");
         if (S.n > 0 && (!S.means || !S.scales || !S.quats || !S.ext || (!S.amp && !S.sh)))
             return fail(SDGR_EINVAL, tag + "null parameter array");
         DevScene d{};
         d.means = S.means; d.scales = S.scales; d.quats = S.quats; d.amp = S.amp; d.ext = S.ext;
         d.ext_back = S.ext_back;
         d.sh = S.sh;
-        d.shc = S.sh ? (S.sh_degree + 1) * (S.sh_degree + 1) : 0;
+        d.shc = shc;
+        d.sh_stride = S.sh ? (S.sh_stride > 0 ? S.sh_stride : shc) : 0;
         P.shc = std::max(P.shc, (int)d.shc);
         d.n = S.n;
         d.item_off = items;
@@ -656,6 +659,12 @@ int static_scratch(char** out)
 }
 
 }  // namespace
+}  // namespace sdgr
+
+namespace sdgr {
+// error reporting for the library's other translation units
+int report_error(int code, const char* msg) { return fail(code, msg); }
+void clear_error() { g_last_error.clear(); }
 }  // namespace sdgr
 
 using namespace sdgr;

@@ -50,7 +50,7 @@ struct DevScene {
     int64_t n;
     int64_t item_off;   // first Gaussian of this scene in the flat item space
     int32_t shc;        // SH coefficients per Gaussian, (degree + 1)^2, 0 without sh
-    int32_t pad;
+    int32_t sh_stride;  // floats between consecutive rows of sh and d_sh
 };
 
 struct RasterParams {
@@ -78,6 +78,11 @@ struct RasterParams {
     float* part = nullptr;
     int64_t part_stride = 0;
 };
+
+// The calling thread's error message of the C ABI (sdgr_last_error): set
+// with a code to return, or cleared at the start of a call.
+int report_error(int code, const char* msg);
+void clear_error();
 
 constexpr int WORK_WORD = 16;    // work counters live at status + 16
 // the tile worklist's bins follow the status words: bins[0..32] tile counts

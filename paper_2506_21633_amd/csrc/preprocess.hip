@@ -277,7 +277,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
                         float d[3], Y[SH_MAX];
                         radar_direction_f(V, m0, m1, m2, d);
                         sh_basis(d[0], d[1], d[2], S.shc, Y);
-                        const float* c = S.sh + (int64_t)S.shc * i;
+                        const float* c = S.sh + (int64_t)S.sh_stride * i;
                         for (int k = 0; k < S.shc; ++k) P += c[k] * Y[k];
                     } else {
                         P = S.amp[i];
@@ -461,7 +461,7 @@ __device__ __forceinline__ void store_param_grads(const DevScene& S, int64_t i, 
     S.d_ext[i] = o[11];
     if (S.d_ext_back) S.d_ext_back[i] = o[11];
     if (SH)
-        for (int k = 0; k < S.shc; ++k) S.d_sh[(int64_t)S.shc * i + k] = o[PB_OUT + k];
+        for (int k = 0; k < S.shc; ++k) S.d_sh[(int64_t)S.sh_stride * i + k] = o[PB_OUT + k];
 }
 
 // dL/dP per view is A dL/dI times the view's cell-area factor. With an SH
@@ -487,7 +487,7 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
     const int nsh = SH ? S.shc : 0;
     if (SH) {
         for (int k = 0; k < NSH; ++k) {
-            csh[k] = k < nsh ? (double)S.sh[(int64_t)nsh * i + k] : 0.0;
+            csh[k] = k < nsh ? (double)S.sh[(int64_t)S.sh_stride * i + k] : 0.0;
             dsh[k] = 0.0;
         }
     }

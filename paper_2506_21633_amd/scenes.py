@@ -28,6 +28,7 @@ __all__ = [
     "Scene", "View", "make_rng", "random_quats", "fwd_1k", "building",
     "vehicle", "large_block", "serving_scenes", "vehicle_views",
     "building_views", "large_views", "jitter", "WORKLOADS",
+    "reconstruction_views", "reconstruction_test_views", "hemisphere_init",
 ]
 
 
@@ -324,6 +325,44 @@ def vehicle_views(size: int = 256, spacing: float = 0.1, count: int = 72,
     """Azimuth k*step deg; incidence 30 deg for even k, 45 deg for odd k."""
     return [View.from_degrees(k * step, 30.0 if k % 2 == 0 else 45.0, size,
                               spacing) for k in range(count)]
+
+
+def reconstruction_views(size: int = 64, spacing: float = 0.2):
+    """Training views of the synthetic reconstruction (Sec. III-B): incidence
+    15, 45 and 75 deg, azimuth every 15 deg (72 views)."""
+    return [View.from_degrees(15.0 * k, inc, size, spacing)
+            for inc in (15.0, 45.0, 75.0) for k in range(24)]
+
+
+def reconstruction_test_views(size: int = 64, spacing: float = 0.2):
+    """Held-out views between the training ones: azimuth 7.5 + 15 k deg,
+    incidence 30 and 60 deg alternating (24 views)."""
+    return [View.from_degrees(7.5 + 15.0 * k, 30.0 if k % 2 == 0 else 60.0, size, spacing)
+            for k in range(24)]
+
+
+def hemisphere_init(n: int, radius: float, seed: int = 404, sh_coeffs: int = 16,
+                    p0: float = 0.5, kappa0: float = 0.5, center=(0.0, 0.0, 0.0)):
+    """Initial point cloud of the reconstruction: n Gaussians on the upper
+    hemispherical shell of the given radius about `center` (uniform in
+    area), isotropic with the shell's mean point spacing as standard
+    deviation, identity rotations, extinction kappa0, and a constant phase
+    function p0 (degree-0 SH coefficient p0 / Y00, higher ones zero)."""
+    rng = make_rng(seed)
+    z = rng.uniform(0.0, 1.0, n)             # uniform in area on the hemisphere
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    rxy = np.sqrt(1.0 - z * z)
+    pts = radius * np.stack([rxy * np.cos(phi), rxy * np.sin(phi), z], axis=1) + \
+        np.asarray(center, np.float64)
+    spacing = math.sqrt(2.0 * math.pi * radius * radius / max(n, 1))
+    scales = np.full((n, 3), 0.5 * spacing, np.float32)
+    quats = np.tile(np.array([1.0, 0.0, 0.0, 0.0], np.float32), (n, 1))
+    sh = np.zeros((n, sh_coeffs), np.float32)
+    sh[:, 0] = p0 / (0.5 / math.sqrt(math.pi))
+    sc = Scene(pts.astype(np.float32), scales, quats, np.full(n, p0, np.float32),
+               np.full(n, kappa0, np.float32))
+    sc.sh = sh
+    return sc
 
 
 def large_block(seed: int = 505, n: int = 2_000_000):

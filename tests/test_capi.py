@@ -1,5 +1,5 @@
 """Host-side checks of the C ABI (no GPU compute): the library loads, exports
-every function include/sdgr.h declares, its structs match the header's
+every function include/*.h declares, its structs match the headers'
 layout, and argument validation rejects bad input before any device work."""
 import ctypes
 import math
@@ -13,12 +13,16 @@ from paper_2506_21633_amd import _capi as C
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "sdgr.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(sdgr_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(sdgr_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function():
@@ -32,18 +36,24 @@ def test_library_exports_every_declared_function():
 
 
 def test_struct_layout_matches_header(tmp_path):
+    layouts = [("sdgr_view", C.View), ("sdgr_plan", C.Plan), ("sdgr_options", C.Options),
+               ("sdgr_scene", C.Scene), ("sdgr_scene_grad", C.SceneGrad),
+               ("sdgr_param_group", C.ParamGroup), ("sdgr_adam_config", C.AdamConfig),
+               ("sdgr_densify_config", C.DensifyConfig), ("sdgr_gaussian_set", C.GaussianSet)]
+    fields = [("sdgr_view", "img_w", C.View), ("sdgr_view", "radar_range", C.View),
+              ("sdgr_plan", "records", C.Plan), ("sdgr_plan", "sh_coeffs", C.Plan),
+              ("sdgr_scene", "sh_stride", C.Scene), ("sdgr_param_group", "lr", C.ParamGroup),
+              ("sdgr_gaussian_set", "sh_coeffs", C.GaussianSet)]
+    exprs = [f"sizeof({n})" for n, _ in layouts] + [f"offsetof({n}, {f})" for n, f, _ in fields]
     src = tmp_path / "sizes.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "sdgr.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n",'
-                   'sizeof(sdgr_view), sizeof(sdgr_plan), sizeof(sdgr_options),'
-                   'sizeof(sdgr_scene), sizeof(sdgr_scene_grad),'
-                   'offsetof(sdgr_view, img_w), offsetof(sdgr_plan, records));}\n')
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "sdgr_train.h"\n'
+                   'int main(void){' +
+                   "".join(f'printf("%zu\\n", (size_t){e});' for e in exprs) + '}\n')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
-    want = [ctypes.sizeof(C.View), ctypes.sizeof(C.Plan), ctypes.sizeof(C.Options),
-            ctypes.sizeof(C.Scene), ctypes.sizeof(C.SceneGrad), C.View.img_w.offset,
-            C.Plan.records.offset]
+    want = [ctypes.sizeof(t) for _, t in layouts] + \
+        [getattr(t, f).offset for _, f, t in fields]
     assert got == want
 
 
@@ -55,11 +65,11 @@ def test_default_options():
 
 
 def _args(grazing=math.radians(45), nv=1, n=10, q_max=9.0, scene=0, w=64, sh_degree=None,
-          amp=0x1000, radar_range=0.0, cell_area=0, scene_reserved=0):
+          amp=0x1000, radar_range=0.0, cell_area=0, sh_stride=0):
     sc = (C.Scene * 1)(C.Scene(n, 0x1000, 0x1000, 0x1000, amp, 0x1000))
     if sh_degree is not None:
         sc[0].sh, sc[0].sh_degree = 0x1000, sh_degree
-    sc[0].reserved = scene_reserved
+    sc[0].sh_stride = sh_stride
     views = (C.View * max(nv, 1))()
     for v in views:
         v.azimuth, v.grazing, v.d_az, v.d_rg = 0.0, grazing, 0.1, 0.1
@@ -88,7 +98,7 @@ def _args(grazing=math.radians(45), nv=1, n=10, q_max=9.0, scene=0, w=64, sh_deg
     (dict(radar_range=-1.0), C.SDGR_EINVAL),
     (dict(radar_range=float("inf")), C.SDGR_EINVAL),
     (dict(cell_area=2), C.SDGR_EINVAL),
-    (dict(scene_reserved=1), C.SDGR_EINVAL),
+    (dict(sh_degree=2, sh_stride=8), C.SDGR_EINVAL),
 ])
 def test_plan_query_rejects_bad_arguments(kw, code):
     L = C.lib()
@@ -218,3 +228,64 @@ def test_forward_rejects_plan_with_short_workspaces():
                          0x1000, (C.SceneGrad * 1)(C.SceneGrad(0x1000, 0x1000, 0x1000, 0x1000,
                                                                0x1000)), None)
     assert rc == C.SDGR_EWORKSPACE
+
+
+# ---------------------------------------------------- reconstruction loop
+
+def test_adam_rejects_bad_arguments():
+    L = C.lib()
+    cfg = C.AdamConfig(0.9, 0.999, 1e-15, 0)
+    g = (C.ParamGroup * 1)(C.ParamGroup(0x1000, 0x1000, 0x1000, 0x1000, 10, 0.1, 0, 0.0, 0.0, 0))
+    assert L.sdgr_adam_step(g, 1, 0, ctypes.byref(cfg), None) == C.SDGR_EINVAL
+    bad = C.AdamConfig(1.0, 0.999, 1e-15, 0)
+    assert L.sdgr_adam_step(g, 1, 1, ctypes.byref(bad), None) == C.SDGR_EINVAL
+    assert L.sdgr_adam_step(g, C.ADAM_MAX_GROUPS + 1, 1, ctypes.byref(cfg), None) == C.SDGR_EINVAL
+    nul = (C.ParamGroup * 1)(C.ParamGroup(0x1000, 0, 0x1000, 0x1000, 10, 0.1, 0, 0.0, 0.0, 0))
+    assert L.sdgr_adam_step(nul, 1, 1, ctypes.byref(cfg), None) == C.SDGR_EINVAL
+    nan = (C.ParamGroup * 1)(C.ParamGroup(0x1000, 0x1000, 0x1000, 0x1000, 10, 0.1, 0,
+                                          float("nan"), 1.0, 0))
+    assert L.sdgr_adam_step(nan, 1, 1, ctypes.byref(cfg), None) == C.SDGR_EINVAL
+    res = (C.ParamGroup * 1)(C.ParamGroup(0x1000, 0x1000, 0x1000, 0x1000, 10, 0.1, 0, 0, 0, 1))
+    assert L.sdgr_adam_step(res, 1, 1, ctypes.byref(cfg), None) == C.SDGR_EINVAL
+    empty = (C.ParamGroup * 1)(C.ParamGroup(0, 0, 0, 0, 0, 0.1, 0))
+    assert L.sdgr_adam_step(empty, 1, 1, ctypes.byref(cfg), None) == C.SDGR_OK
+
+
+def _set(**kw):
+    s = C.GaussianSet()
+    for g in ("means", "scales", "quats", "ext"):
+        for pre in ("", "m_", "v_"):
+            setattr(s, pre + g, 0x1000)
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+def test_densify_rejects_bad_arguments():
+    L = C.lib()
+    cfg = C.DensifyConfig(0.003, 0.1, 1.0, 0.005, 1.6, 0)
+    n = 1000
+    ws = L.sdgr_densify_workspace_bytes(n)
+    assert ws >= n
+    a, b = _set(), _set()
+    def call(inp=a, out=b, cap=2 * n, c=cfg, wsb=ws, work=0x1000):
+        return L.sdgr_densify(ctypes.byref(inp), n, 0x1000, 0x1000, 0x1000, ctypes.byref(c),
+                              ctypes.byref(out), cap, 0x1000, work, wsb, None)
+    assert call(cap=2 * n - 1) == C.SDGR_EINVAL
+    assert call(wsb=ws - 1) == C.SDGR_EWORKSPACE
+    assert call(work=0x1010) == C.SDGR_EINVAL
+    assert call(c=C.DensifyConfig(0.003, 0.1, 1.0, 0.005, 1.0, 0)) == C.SDGR_EINVAL
+    assert call(out=_set(amp=0x1000, m_amp=0x1000, v_amp=0x1000)) == C.SDGR_EINVAL
+    assert call(inp=_set(m_means=0)) == C.SDGR_EINVAL
+    assert call(inp=_set(sh=0x1000, m_sh=0x1000, v_sh=0x1000, sh_coeffs=16),
+                out=_set(sh=0x1000, m_sh=0x1000, v_sh=0x1000, sh_coeffs=9)) == C.SDGR_EINVAL
+
+
+def test_metrics_reject_bad_arguments():
+    L = C.lib()
+    assert L.sdgr_image_metrics(0x1000, 0x1000, 1, 10, 64, 1.0, 0x1000, 0x1000, 0x1000,
+                                None) == C.SDGR_EINVAL
+    assert L.sdgr_image_metrics(0x1000, 0x1000, 1, 64, 64, 0.0, 0x1000, 0x1000, 0x1000,
+                                None) == C.SDGR_EINVAL
+    assert L.sdgr_nearest_sq(0x1000, -1, 0x1000, 5, 0x1000, None) == C.SDGR_EINVAL
+    assert L.sdgr_nearest_sq(0, 0, 0, 0, 0, None) == C.SDGR_OK

@@ -38,6 +38,18 @@ def test_adam_log_space_is_adam_on_the_logarithm():
     assert np.all(x > 0)
 
 
+def test_adam_clamp_bounds_the_result():
+    x, m, v = np.array([1.0, 5.0, 49.9]), np.zeros(3), np.zeros(3)
+    for t in range(1, 200):
+        x, m, v = T.adam_step(x, -np.ones(3), m, v, t, lr=0.1, log_space=True, lo=1e-6, hi=50.0)
+    assert np.all(x == 50.0)
+    y, _, _ = T.adam_step(np.array([2.0]), np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr=0.5,
+                          lo=1.8, hi=3.0)
+    assert y[0] == 1.8
+    z, _, _ = T.adam_step(np.array([2.0]), np.array([1.0]), np.zeros(1), np.zeros(1), 1, lr=0.5)
+    assert math.isclose(z[0], 1.5)
+
+
 def test_adam_converges_on_a_quadratic():
     x, m, v = np.array([3.0, -1.5]), np.zeros(2), np.zeros(2)
     a = np.array([2.0, 0.5])
