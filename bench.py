@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-stage HIP event timing")
-    ap.add_argument("--serving-requests", type=int, default=160,
+    ap.add_argument("--serving-requests", type=int, default=1000,
                     help="requests of the served-vs-plain stream (0 skips it)")
     ap.add_argument("--no-work-count", action="store_true",
                     help="skip the untimed step that counts footprint hits (profiler runs)")
@@ -161,13 +161,14 @@ def cpu_baseline(sc, views, rows):
                       f"scaled x{v.img_h / rows:g} to one image"}
 
 
-def serving_bench(dev, n_requests, seed=404):
-    """Served (continuous batching, 2 launch slots, HBM-budget admission) vs
-    plain (one request per launch, FIFO) on the same Poisson arrival stream
-    over 8 resident scenes of 1e4-5e5 Gaussians. Requests: 1-16 views of
+def serving_bench(dev, n_requests, seed=404, loads=(0.5, 0.8, 1.2, 2.0)):
+    """Served (continuous batching, 2 launch slots, admission by exact
+    workspace bytes, plans counted on planner threads) vs plain (one request
+    per launch, FIFO) on the same Poisson arrival stream over 8 resident
+    scenes of 1e4-5e5 Gaussians, at arrival rates of `loads` times the plain
+    form's measured capacity, n_requests per point. Requests: 1-16 views of
     64^2-512^2 at 0.1 m, azimuth U[0, 360), incidence 30 or 45 deg; half ask
-    for the L1 gradient against a zero target as well. The arrival rate is
-    80 % of the plain form's measured capacity."""
+    for the L1 gradient against a zero target as well."""
     import numpy as np
     import torch
     from paper_2506_21633_amd import api, scenes
@@ -184,6 +185,7 @@ def serving_bench(dev, n_requests, seed=404):
         want = bool(rng.integers(0, 2))
         tgt = torch.zeros(size * size * len(vs), device=dev) if want else None
         reqs.append((sid, vs, want, tgt))
+    images = sum(len(r[1]) for r in reqs)
 
     def run(batching, rate):
         ex = GpuExecutor(resident, dev)
@@ -199,27 +201,31 @@ def serving_bench(dev, n_requests, seed=404):
         dt = time.perf_counter() - t0
         st = srv.stats()
         srv.close()
-        images = sum(len(r[1]) for r in reqs)
-        return {"p50_ms": percentile(lat, 50) * 1e3, "p99_ms": percentile(lat, 99) * 1e3,
-                "images_per_s": images / dt, "requests": len(reqs),
-                "mean_batch_requests": st["mean_batch_requests"]}
+        return {"p50_ms": round(percentile(lat, 50) * 1e3, 3),
+                "p99_ms": round(percentile(lat, 99) * 1e3, 3),
+                "images_per_s": round(images / dt, 1),
+                "launches": len(srv.batch_sizes),
+                "mean_batch_requests": round(st["mean_batch_requests"], 3)}
 
     # capacity of the plain form: back-to-back requests
     ex = GpuExecutor(resident, dev)
     warm = Server(ex, hbm_budget=96 << 30, batching=False)
-    for sid, vs, want, tgt in reqs[:4]:
+    for sid, vs, want, tgt in reqs[:8]:
         warm.submit(Request(sid, vs, want, tgt)).result(600)
+    k = min(64, len(reqs))
     t0 = time.perf_counter()
-    k = min(24, len(reqs))
     futs = [warm.submit(Request(sid, vs, want, tgt)) for sid, vs, want, tgt in reqs[:k]]
     for f in futs:
         f.result(600)
     service = (time.perf_counter() - t0) / k
     warm.close()
-    rate = 0.8 / service
-    served = run(True, rate)
-    plain = run(False, rate)
-    return {"qps": rate, "served": served, "plain": plain,
+    points = []
+    for load in loads:
+        rate = load / service
+        points.append({"load": load, "qps": round(rate, 1), "served": run(True, rate),
+                       "plain": run(False, rate)})
+    return {"plain_capacity_qps": round(1.0 / service, 1), "requests_per_point": len(reqs),
+            "points": points,
             "workload": "8 resident vehicle scenes (1e4-5e5 Gaussians), Poisson arrivals, "
                         "1-16 views of 64^2-512^2, half with L1 gradient"}
 

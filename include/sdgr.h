@@ -226,6 +226,17 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes,
  * sdgr_status. */
 int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i);
 
+/* The plan sdgr_plan_query would return had it counted pairs_c and pairs_i
+ * pairs, built from host data alone (no device work, no synchronisation).
+ * For callers that know the counts already: the pair counts of a launch
+ * that fuses several problems' views are the sums of theirs, so a server
+ * can query each request once and plan any batch of them on the host.
+ * Same argument checks as sdgr_plan_query; SDGR_EUNSUPPORTED for capacities
+ * outside [0, 2^31 - 1]. */
+int sdgr_plan_host(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* views,
+                   int32_t nv, const sdgr_options* opt, int64_t pairs_c, int64_t pairs_i,
+                   sdgr_plan* plan);
+
 /* Forward and backward return SDGR_EINVAL if `plan` does not belong to the
  * scenes, views and options, and SDGR_EWORKSPACE if its workspace sizes are
  * smaller than its capacities need (a plan edited by hand). */

@@ -22,7 +22,7 @@ EXPORTED = ("sdgr_version", "sdgr_last_error", "sdgr_default_options",
             "sdgr_backward", "sdgr_status", "sdgr_read_intensity",
             "sdgr_read_optical_depth", "sdgr_profile_enable", "sdgr_profile_read",
             "sdgr_profile_stage", "sdgr_profile_count", "sdgr_read_work",
-            "sdgr_plan_resize", "sdgr_forward_static",
+            "sdgr_plan_resize", "sdgr_forward_static", "sdgr_plan_host",
             # reconstruction loop and metrics
             "sdgr_adam_step", "sdgr_densify_stats", "sdgr_densify_workspace_bytes",
             "sdgr_densify", "sdgr_nearest_sq", "sdgr_image_metrics")
@@ -153,6 +153,9 @@ def lib():
     L.sdgr_profile_stage.restype = ctypes.c_char_p
     L.sdgr_profile_count.argtypes = [ctypes.c_int32]
     L.sdgr_plan_resize.argtypes = [P(Plan), ctypes.c_int64, ctypes.c_int64]
+    L.sdgr_plan_host.argtypes = [P(Scene), ctypes.c_int32, P(View), ctypes.c_int32, P(Options),
+                                 ctypes.c_int64, ctypes.c_int64, P(Plan)]
+    L.sdgr_plan_host.restype = ctypes.c_int
     L.sdgr_read_work.argtypes = [P(Plan), vp, P(ctypes.c_uint64), ctypes.c_int32, vp]
     L.sdgr_adam_step.argtypes = [P(ParamGroup), ctypes.c_int32, ctypes.c_int64, P(AdamConfig),
                                  vp]

@@ -233,6 +233,16 @@ class Renderer:
                                           int(math.ceil(base.pairs_i * (1 + headroom))) + 64))
         return p
 
+    def plan_for(self, pairs_c: int, pairs_i: int) -> C.Plan:
+        """The plan at given pair capacities, from host data only (no
+        device work): e.g. the summed exact counts of the problems a fused
+        launch joins."""
+        p = C.Plan()
+        C.check(self.lib.sdgr_plan_host(self.scenes_c, len(self.scenes), self.views_c, self.nv,
+                                        ctypes.byref(self.opts_c), int(pairs_c), int(pairs_i),
+                                        ctypes.byref(p)))
+        return p
+
     def replan(self):
         """Forget the cached pair counts (after an overflow)."""
         self._last_exact = None

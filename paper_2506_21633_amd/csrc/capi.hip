@@ -582,6 +582,8 @@ int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
 // Pair counts of the projection (count-only preprocess into `query`, which
 // holds sdgr_query_bytes(ns, nv)), read back with one stream
 // synchronisation, and the workspace sizes they imply.
+void fill_plan(const Problem& P, int64_t pairs_c, int64_t pairs_i, sdgr_plan* plan);
+
 int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan)
 {
     Arena a{query};
@@ -603,10 +605,17 @@ int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan
     SDGR_HIP(hipStreamSynchronize(s));
     if (host_tot[0] + host_tot[1] > (unsigned long long)INT32_MAX)
         return fail(SDGR_EUNSUPPORTED, "more than 2^31 - 1 (Gaussian, tile) pairs");
+    fill_plan(P, (int64_t)host_tot[0], (int64_t)host_tot[1], plan);
+    return SDGR_OK;
+}
+
+// The plan of a problem at given pair capacities (host data only).
+void fill_plan(const Problem& P, int64_t pairs_c, int64_t pairs_i, sdgr_plan* plan)
+{
     sdgr_plan out{};
     out.records = P.records;
-    out.pairs_c = (int64_t)host_tot[0];
-    out.pairs_i = (int64_t)host_tot[1];
+    out.pairs_c = pairs_c;
+    out.pairs_i = pairs_i;
     out.tiles_c = P.tiles_c;
     out.tiles_i = P.tiles_i;
     out.rays = P.rays;
@@ -624,7 +633,6 @@ int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan
     layout(P, out.pairs_c, out.pairs_i, BWD, nullptr, nullptr, b, nullptr,
            &out.bwd_scratch_bytes);
     *plan = out;
-    return SDGR_OK;
 }
 
 // ---- workspace for callers that cannot allocate device memory -----------
@@ -710,6 +718,21 @@ int sdgr_plan_query(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* 
         return fail(SDGR_EWORKSPACE, "query scratch smaller than sdgr_query_bytes()");
     if ((uintptr_t)query_scratch & 255) return fail(SDGR_EINVAL, "scratch not 256-byte aligned");
     return count_and_plan(P, (char*)query_scratch, (hipStream_t)stream, plan);
+}
+
+int sdgr_plan_host(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* views,
+                   int32_t nv, const sdgr_options* opt, int64_t pairs_c, int64_t pairs_i,
+                   sdgr_plan* plan)
+{
+    g_last_error.clear();
+    if (!plan) return fail(SDGR_EINVAL, "plan is null");
+    if (pairs_c < 0 || pairs_i < 0 || pairs_c + pairs_i > INT32_MAX)
+        return fail(SDGR_EUNSUPPORTED, "pair capacities outside [0, 2^31 - 1]");
+    Problem P;
+    int rc = build_problem(scenes, nscenes, views, nv, opt, P);
+    if (rc) return rc;
+    fill_plan(P, pairs_c, pairs_i, plan);
+    return SDGR_OK;
 }
 
 int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i)

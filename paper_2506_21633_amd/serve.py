@@ -1,12 +1,17 @@
 """Continuous-batching render server for the SAR rasterizer.
 
 Scenes stay resident on the device. Requests (render, or render + L1
-gradient against a target) arrive at any time; a scheduler thread admits them
-into fused launches as launch slots and device memory free up, so requests
+gradient against a target) arrive at any time. Planner threads count each
+request's pairs exactly (one device query on a stream of their own, off the
+scheduler thread) and price it in bytes. The scheduler admits planned
+requests into fused launches as launch slots and device memory free up,
+checking each candidate batch's exact workspace bytes against the budget. A
+fused launch's pair counts are the sums of its requests', so its plan is
+built on the host (sdgr_plan_host) without another device query. Requests
 that arrive while others run are picked up without waiting for a queue to
-drain, and two launches overlap on the device (one plans while the other
-runs). Each request is its own scene entry in the fused launch (aliasing the
-resident tensors), so its gradient is never mixed with another request's.
+drain, and two launches overlap on the device. Each request is its own
+scene entry in the fused launch (aliasing the resident tensors), so its
+gradient is never mixed with another request's.
 
 The GPU executor calls the library through ``api.Renderer``; a fake executor
 with simulated memory and latency drives the same scheduler on the CPU for
@@ -15,7 +20,9 @@ tests.
 from __future__ import annotations
 
 import collections
+import ctypes
 import itertools
+import queue
 import threading
 import time
 from concurrent.futures import Future
@@ -34,6 +41,8 @@ class Request:
     deadline_s: Optional[float] = None   # fail if not admitted within this time
     id: int = -1
     arrival: float = 0.0
+    cost: int = 0              # exact workspace bytes alone (set by the planner)
+    plan_info: object = None   # executor's planning result (e.g. pair counts)
 
     @property
     def nviews(self) -> int:
@@ -73,25 +82,76 @@ class _Launch:
         self.payload = payload
 
 
+def _plan_bytes(plan, want_grad: bool) -> int:
+    return int(plan.state_bytes + plan.fwd_scratch_bytes +
+               (plan.bwd_scratch_bytes if want_grad else 0)) + 3 * 256
+
+
 class GpuExecutor:
-    """Fused launches on the device; one HIP stream per launch slot."""
+    """Fused launches on the device; one HIP stream per launch slot and one
+    per planner thread."""
 
     def __init__(self, scenes: Dict[str, object], device="cuda", options=None, slots=2):
         import torch
         from . import api
+        from . import _capi
         self.torch = torch
         self.api = api
+        self.C = _capi
+        self.lib = _capi.lib()
         self.device = torch.device(device)
         self.scenes = dict(scenes)
         self.options = options or api.RenderOptions()
+        self.opts_c = self.options.to_c()
         self.streams = [torch.cuda.Stream(self.device) for _ in range(slots)]
         self.free_streams = list(range(slots))
+        self._plan_streams = threading.local()
+        # one scene struct per resident scene, reused by every plan
+        self._scene_c = {k: api._scene_struct(g) for k, g in self.scenes.items()}
 
-    def estimate_bytes(self, req: Request) -> int:
-        # records, per-record projection/sort state and two lists of ~2 pairs
-        n = self.scenes[req.scene_id].n
-        return req.nviews * n * 420 + req.pixels * 16 + (1 << 20)
+    # -- planning (planner threads) -----------------------------------------
+    def prepare(self, req: Request) -> None:
+        """Exact pair counts and workspace bytes of the request alone: one
+        device query on this thread's own stream."""
+        torch = self.torch
+        st = getattr(self._plan_streams, "s", None)
+        if st is None:
+            st = self._plan_streams.s = torch.cuda.Stream(self.device)
+        with torch.cuda.stream(st):
+            rend = self.api.Renderer([self.scenes[req.scene_id]], list(req.views), self.options)
+            plan = rend.plan()
+        views_c, _, _ = self.api._view_structs(list(req.views), [0] * req.nviews)
+        req.plan_info = (int(plan.pairs_c), int(plan.pairs_i), views_c)
+        req.cost = _plan_bytes(plan, req.want_grad)
 
+    def _fused_plan(self, reqs: List[Request]):
+        """Plan of a fused launch from the parts' counts (host only)."""
+        C = self.C
+        nv = sum(r.nviews for r in reqs)
+        scenes = (C.Scene * len(reqs))(*[self._scene_c[r.scene_id] for r in reqs])
+        views = (C.View * nv)()
+        k, off = 0, 0
+        for i, r in enumerate(reqs):
+            for j in range(r.nviews):
+                views[k] = r.plan_info[2][j]
+                views[k].scene = i
+                views[k].img_offset = off
+                off += views[k].img_w * views[k].img_h
+                k += 1
+        pc = sum(r.plan_info[0] for r in reqs)
+        pi = sum(r.plan_info[1] for r in reqs)
+        plan = C.Plan()
+        C.check(self.lib.sdgr_plan_host(scenes, len(reqs), views, nv, ctypes.byref(self.opts_c),
+                                        pc, pi, ctypes.byref(plan)))
+        return plan
+
+    def batch_bytes(self, reqs: List[Request]) -> int:
+        """Exact workspace bytes of the fused launch of `reqs`."""
+        if len(reqs) == 1:
+            return reqs[0].cost
+        return _plan_bytes(self._fused_plan(reqs), any(r.want_grad for r in reqs))
+
+    # -- launches (scheduler thread) ----------------------------------------
     def launch(self, batch_id: int, reqs: List[Request]) -> _Launch:
         torch = self.torch
         k = self.free_streams.pop()
@@ -106,7 +166,8 @@ class GpuExecutor:
                     views.extend(r.views)
                     ids.extend([i] * r.nviews)
                 rend = self.api.Renderer(scenes, views, self.options, scene_ids=ids)
-                plan = rend.plan()
+                plan = rend.plan_for(sum(r.plan_info[0] for r in reqs),
+                                     sum(r.plan_info[1] for r in reqs))
                 res = rend.forward(plan)
                 grads = None
                 if any(r.want_grad for r in reqs):
@@ -122,9 +183,8 @@ class GpuExecutor:
                     grads = rend.backward(res, G)
                 done = torch.cuda.Event()
                 done.record(stream)
-            nbytes = plan.state_bytes + plan.fwd_scratch_bytes + \
-                (plan.bwd_scratch_bytes if grads is not None else 0)
-            return _Launch(batch_id, reqs, nbytes, (k, rend, res, grads, done))
+            return _Launch(batch_id, reqs, _plan_bytes(plan, grads is not None),
+                           (k, rend, res, grads, done))
         except Exception:
             self.free_streams.append(k)
             raise
@@ -136,6 +196,7 @@ class GpuExecutor:
         k, rend, res, grads, done = launch.payload
         done.synchronize()
         self.free_streams.append(k)
+        rend.status(res)     # a pair overflow would mean the counts were not additive
         out, v0 = [], 0
         for i, r in enumerate(launch.requests):
             imgs = [res.image(v0 + j) for j in range(r.nviews)]
@@ -151,23 +212,35 @@ class GpuExecutor:
 
 
 class FakeExecutor:
-    """CPU stand-in: simulated memory and latency, deterministic results.
+    """CPU stand-in: simulated memory, planning time and latency,
+    deterministic results.
 
+    cost(req) = bytes_per_view * views; a fused launch costs the sum plus
+    batch_overhead per extra request; planning takes plan_s(req) seconds;
     latency_s(batch) = base_s + per_view_s * views; `fail_on(req)` may raise
     to simulate a failing launch."""
 
     def __init__(self, bytes_per_view=1 << 20, base_s=0.002, per_view_s=0.0005,
-                 fail_on=None, slots=2):
+                 fail_on=None, slots=2, plan_s=None, batch_overhead=0):
         self.bytes_per_view = bytes_per_view
         self.base_s = base_s
         self.per_view_s = per_view_s
         self.fail_on = fail_on
         self.slots = slots
         self.free = slots
+        self.plan_s = plan_s
+        self.batch_overhead = batch_overhead
         self.launched: List[List[int]] = []
+        self.planned: List[int] = []
 
-    def estimate_bytes(self, req: Request) -> int:
-        return req.nviews * self.bytes_per_view
+    def prepare(self, req: Request) -> None:
+        if self.plan_s is not None:
+            time.sleep(self.plan_s(req))
+        req.cost = req.nviews * self.bytes_per_view
+        self.planned.append(req.id)
+
+    def batch_bytes(self, reqs) -> int:
+        return sum(r.cost for r in reqs) + self.batch_overhead * (len(reqs) - 1)
 
     def launch(self, batch_id, reqs):
         if self.fail_on is not None:
@@ -178,7 +251,7 @@ class FakeExecutor:
         self.launched.append([r.id for r in reqs])
         views = sum(r.nviews for r in reqs)
         t_done = time.perf_counter() + self.base_s + self.per_view_s * views
-        return _Launch(batch_id, reqs, sum(self.estimate_bytes(r) for r in reqs), t_done)
+        return _Launch(batch_id, reqs, self.batch_bytes(reqs), t_done)
 
     def done(self, launch):
         return time.perf_counter() >= launch.payload
@@ -204,7 +277,7 @@ class Server:
     launch in flight."""
 
     def __init__(self, executor, hbm_budget: int, max_views: int = 64, slots: int = 2,
-                 batching: bool = True):
+                 batching: bool = True, planners: int = 2):
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_views = max_views if batching else 1 << 30
@@ -223,31 +296,64 @@ class Server:
         self.failed = 0
         self.images_done = 0
         self.batch_sizes: List[int] = []
+        self._plan_q: queue.Queue = queue.Queue()
+        self._planning = 0
+        self._planners = [threading.Thread(target=self._plan_loop, name=f"sdgr-planner-{k}",
+                                           daemon=True) for k in range(max(1, planners))]
+        for t in self._planners:
+            t.start()
         self._thread = threading.Thread(target=self._loop, name="sdgr-server", daemon=True)
         self._thread.start()
 
     # ------------------------------------------------------------ client side
     def submit(self, req: Request) -> Future:
+        """Queue a request; it is planned off the scheduler thread, then
+        admitted. Returns a future of its Result."""
         fut: Future = Future()
         with self._cv:
             req.id = next(self._ids)
             req.arrival = time.perf_counter()
-            if self.ex.estimate_bytes(req) > self.budget:
-                fut.set_exception(MemoryError(
-                    f"request {req.id} needs more than the HBM budget of {self.budget} bytes"))
-                self.failed += 1
-                return fut
             self._futures[req.id] = fut
-            self._pending.append(req)
-            self._cv.notify()
+            self._planning += 1
+        self._plan_q.put(req)
         return fut
 
     def close(self, wait=True):
         with self._cv:
             self._stop = True
             self._cv.notify()
+        for _ in self._planners:
+            self._plan_q.put(None)
         if wait:
+            for t in self._planners:
+                t.join()
             self._thread.join()
+
+    # ------------------------------------------------------------- planners
+    def _plan_loop(self):
+        while True:
+            req = self._plan_q.get()
+            if req is None:
+                return
+            fut = self._futures.get(req.id)
+            err = None
+            if fut is not None and not fut.cancelled():
+                try:
+                    self.ex.prepare(req)
+                    if req.cost > self.budget:
+                        err = MemoryError(f"request {req.id} needs {req.cost} bytes, more "
+                                          f"than the HBM budget of {self.budget}")
+                except Exception as exc:   # a request that cannot be planned fails alone
+                    err = exc
+            with self._cv:
+                self._planning -= 1
+                if fut is None or fut.cancelled():
+                    self._futures.pop(req.id, None)
+                elif err is not None:
+                    self._fail([req], err)
+                else:
+                    self._pending.append(req)
+                self._cv.notify()
 
     def stats(self) -> dict:
         return {"completed": self.completed, "failed": self.failed,
@@ -274,15 +380,15 @@ class Server:
                 self._fail([r], TimeoutError(f"request {r.id} not admitted within "
                                              f"{r.deadline_s} s"))
                 continue
-            est = self.ex.estimate_bytes(r)
-            if batch and (views + r.nviews > self.max_views or
-                          self._used + nbytes + est > self.budget):
+            if batch and views + r.nviews > self.max_views:
                 break
-            if not batch and self._used + est > self.budget:
+            # the candidate batch's exact workspace bytes (a fused launch's
+            # parameter-gradient parts grow with all of its Gaussians)
+            need = self.ex.batch_bytes(batch + [r]) if batch else r.cost
+            if self._used + need > self.budget:
                 break                      # wait for memory to free up
             batch.append(self._pending.popleft())
             views += r.nviews
-            nbytes += est
             if not self.batching:
                 break
         return batch
@@ -337,7 +443,8 @@ class Server:
                     self._inflight.remove(launch)
                     self._retire(launch)
             with self._cv:
-                if self._stop and not self._pending and not self._inflight:
+                if self._stop and not self._pending and not self._inflight and \
+                        not self._planning:
                     return
                 batch = []
                 if len(self._inflight) < self.slots and self._pending:

@@ -289,3 +289,20 @@ def test_metrics_reject_bad_arguments():
                                 None) == C.SDGR_EINVAL
     assert L.sdgr_nearest_sq(0x1000, -1, 0x1000, 5, 0x1000, None) == C.SDGR_EINVAL
     assert L.sdgr_nearest_sq(0, 0, 0, 0, 0, None) == C.SDGR_OK
+
+
+def test_plan_host_matches_the_problem_without_device_work():
+    """sdgr_plan_host fills a plan from host data alone (the pointers here
+    are never dereferenced); forward accepts it as matching the problem and
+    then stops only at its null workspaces."""
+    L = C.lib()
+    sc, views, o = _args(nv=3)
+    p = C.Plan()
+    C.check(L.sdgr_plan_host(sc, 1, views, 3, ctypes.byref(o), 5000, 700, ctypes.byref(p)))
+    assert (p.records, p.pairs_c, p.pairs_i, p.nviews, p.tile) == (30, 5000, 700, 3, 8)
+    assert p.tiles_c == p.tiles_i == 3 * 64 and p.rays == 3 * 64 * 64
+    assert p.state_bytes > 0 and p.bwd_scratch_bytes > 0
+    rc = L.sdgr_forward(sc, 1, views, 3, ctypes.byref(o), ctypes.byref(p), None, None, None, None)
+    assert rc == C.SDGR_EINVAL and b"workspace" in L.sdgr_last_error()
+    assert L.sdgr_plan_host(sc, 1, views, 3, ctypes.byref(o), -1, 0,
+                            ctypes.byref(p)) == C.SDGR_EUNSUPPORTED

@@ -108,6 +108,41 @@ def test_cancel_and_deadline():
     assert not any(1 in b for b in ex.launched)
 
 
+def test_slow_planning_does_not_hold_up_planned_requests():
+    """Requests are planned on planner threads: a request whose plan takes
+    long is overtaken by later ones, and launches keep flowing meanwhile."""
+    ex = FakeExecutor(base_s=0.005, per_view_s=0.0,
+                      plan_s=lambda r: 0.3 if r.scene_id == "slow" else 0.0)
+    srv = Server(ex, hbm_budget=1 << 40, slots=1, planners=2)
+    slow = srv.submit(Request("slow", views(1)))
+    time.sleep(0.01)
+    fast = [srv.submit(Request("fast", views(1))) for _ in range(3)]
+    t_fast = []
+    for f in fast:
+        f.result(5)
+        t_fast.append(time.perf_counter())
+    slow.result(5)
+    t_slow = time.perf_counter()
+    srv.close()
+    assert max(t_fast) < t_slow
+    assert ex.launched[-1] == [0]          # the slow request launched last
+
+
+def test_admission_uses_the_batch_bytes():
+    """The fused launch may cost more than the sum of its parts (here 100
+    bytes per extra request): admission checks the batch's own bytes."""
+    ex = FakeExecutor(bytes_per_view=100, base_s=0.05, per_view_s=0.0, batch_overhead=100)
+    srv = Server(ex, hbm_budget=500, max_views=64, slots=1)
+    blocker = srv.submit(Request("a", views(1)))
+    time.sleep(0.01)                       # the blocker runs; the rest queue up
+    futs = [srv.submit(Request("b", views(1))) for _ in range(6)]
+    for f in [blocker] + futs:
+        f.result(5)
+    srv.close()
+    # 3 requests cost 300 + 200 = 500 (fits), 4 would cost 400 + 300 = 700
+    assert max(len(b) for b in ex.launched) == 3
+
+
 def test_poisson_stream_served_vs_plain():
     """Under load, batching amortises the per-launch cost: fewer launches and
     lower tail latency than one request per launch."""
@@ -156,6 +191,17 @@ def test_served_results_equal_plain_results(cuda):
         tgt = torch.rand(sum(v.img_w * v.img_h for v in vs), device=cuda) if want else None
         reqs.append((sid, vs, want, tgt))
     ex = GpuExecutor(dev_scenes, cuda)
+    # a fused launch's plan built on the host from its parts' exact counts
+    # equals the plan the device query gives for the fused problem
+    parts = [Request(sid, vs, want, tgt) for sid, vs, want, tgt in reqs[:5]]
+    for r in parts:
+        ex.prepare(r)
+    fused = api.Renderer([dev_scenes[r.scene_id] for r in parts],
+                         [v for r in parts for v in r.views],
+                         scene_ids=[i for i, r in enumerate(parts) for _ in r.views])
+    queried, host = fused.plan(), ex._fused_plan(parts)
+    for name, _ in type(host)._fields_:
+        assert getattr(host, name) == getattr(queried, name), name
     srv = Server(ex, hbm_budget=8 << 30, max_views=64, slots=2)
     futs = [srv.submit(Request(sid, vs, want, tgt)) for sid, vs, want, tgt in reqs]
     served = [f.result(120) for f in futs]
