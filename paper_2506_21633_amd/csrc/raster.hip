@@ -432,31 +432,47 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     for (uint32_t g0 = c_first; g0 < c_end && live != 0ull; g0 += WAVE) {
         const uint64_t sm = g0 + lane < c_end ? psum[g0 + lane] : 0ull;
         uint64_t todo = __ballot((sm & live) != 0ull);   // chunks to read, in order
-        while (todo != 0ull && live != 0ull) {
+        // up to NB chunks per batch: their masks and values are fetched one
+        // batch ahead (in flight while the current batch's hits are
+        // processed), then the records the live rays need
+        uint32_t chk_n[NB], r_n[NB], d_n[NB];
+        uint64_t m_n[NB];
+        int nb_n = 0;
+        auto fetch = [&]() {
+            nb_n = 0;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                chk_n[k] = 0u;
+                if (todo != 0ull) {
+                    chk_n[k] = g0 + (uint32_t)__builtin_ctzll(todo);
+                    todo &= todo - 1ull;
+                    nb_n = k + 1;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const uint32_t e = chk_n[k] * WAVE + lane;
+                const bool in = k < nb_n && e >= rg.x && e < rg.y;
+                m_n[k] = in ? pmask[e] : 0ull;
+                r_n[k] = in ? pvals[e] : 0u;
+                if constexpr (DET) d_n[k] = in ? rp.ppos[e] : 0u;
+            }
+        };
+        fetch();
+        while (nb_n > 0 && live != 0ull) {
             ++n_batch;
-            // up to NB chunks: masks and values, then the needed records
             uint32_t got = 0u;   // bit k: this lane's entry of chunk k was gathered
-            int nb = 0;
+            const int nb = nb_n;
             {
                 uint32_t chk[NB];
                 uint64_t m[NB];
                 uint32_t* r = r_cur;
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
-                    chk[k] = 0u;
-                    if (todo != 0ull) {
-                        chk[k] = g0 + (uint32_t)__builtin_ctzll(todo);
-                        todo &= todo - 1ull;
-                        nb = k + 1;
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    const uint32_t e = chk[k] * WAVE + lane;
-                    const bool in = k < nb && e >= rg.x && e < rg.y;
-                    m[k] = in ? pmask[e] : 0ull;
-                    r[k] = in ? pvals[e] : 0u;
-                    if constexpr (DET) d_cur[k] = in ? rp.ppos[e] : 0u;
+                    chk[k] = chk_n[k];
+                    m[k] = m_n[k];
+                    r[k] = r_n[k];
+                    if constexpr (DET) d_cur[k] = d_n[k];
                 }
                 // records straight into LDS, all in flight together (entries
                 // no live ray needs read record 0, one shared line)
@@ -478,6 +494,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
             }
             wait_all_memory();
             wave_lds_sync();
+            fetch();   // the next batch's masks and values
             flush();
             got_prev = got;
 #pragma unroll
@@ -1028,40 +1045,58 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
         }
         const uint64_t sm = g0 + lane < g1 ? psum[g0 + lane] : 0ull;
         uint64_t todo = __ballot((sm & live_c) != 0ull);   // chunks to read, back to front
-        while (todo != 0ull) {
+        // up to NB chunks per batch: their masks and values are fetched one
+        // batch ahead (in flight while the current batch's hits are
+        // processed), then the records the rays need
+        uint32_t chk_n[NB], rec_n[NB], r_n[NB];
+        uint64_t lv_n[NB], m_n[NB];
+        int nb_n = 0;
+        auto fetch = [&]() {
+            nb_n = 0;
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                chk_n[k] = 0u;
+                lv_n[k] = 0ull;
+                if (todo != 0ull) {
+                    const int hi = 63 - __builtin_clzll(todo);
+                    todo &= ~(1ull << hi);
+                    chk_n[k] = (uint32_t)g0 + (uint32_t)hi;
+                    const uint32_t l0 =
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)live_c, hi);
+                    const uint32_t l1 =
+                        (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(live_c >> 32), hi);
+                    lv_n[k] = ((uint64_t)l1 << 32) | l0;
+                    nb_n = k + 1;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NB; ++k) {
+                const uint32_t e = chk_n[k] * WAVE + lane;
+                const bool in = k < nb_n && e >= rg.x && e < e_end;
+                m_n[k] = in ? pmask[e] : 0ull;
+                rec_n[k] = in ? pvals[e] : 0u;
+                if constexpr (DET) r_n[k] = in ? rp.ppos[e] : 0u;
+                else r_n[k] = rec_n[k];
+            }
+        };
+        fetch();
+        while (nb_n > 0) {
             ++n_batch;
             uint32_t got = 0u;
-            int nb = 0;
+            const int nb = nb_n;
             uint64_t m[NB];   // lane = entry: the cells it covers
             {
                 uint32_t chk[NB];
                 uint64_t lv[NB];
                 uint32_t* r = r_cur;
-#pragma unroll
-                for (int k = 0; k < NB; ++k) {
-                    chk[k] = 0u;
-                    lv[k] = 0ull;
-                    if (todo != 0ull) {
-                        const int hi = 63 - __builtin_clzll(todo);
-                        todo &= ~(1ull << hi);
-                        chk[k] = (uint32_t)g0 + (uint32_t)hi;
-                        const uint32_t l0 =
-                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)live_c, hi);
-                        const uint32_t l1 =
-                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(live_c >> 32), hi);
-                        lv[k] = ((uint64_t)l1 << 32) | l0;
-                        nb = k + 1;
-                    }
-                }
                 uint32_t rec[NB];
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
-                    const uint32_t e = chk[k] * WAVE + lane;
-                    const bool in = k < nb && e >= rg.x && e < e_end;
-                    m[k] = in ? pmask[e] : 0ull;
-                    rec[k] = in ? pvals[e] : 0u;
-                    if constexpr (DET) r[k] = in ? rp.ppos[e] : 0u;
-                    else r[k] = rec[k];
+                    chk[k] = chk_n[k];
+                    lv[k] = lv_n[k];
+                    m[k] = m_n[k];
+                    rec[k] = rec_n[k];
+                    r[k] = r_n[k];
                 }
                 // records straight into LDS, all in flight together (entries
                 // no ray needs read record 0 of the view, one shared line)
@@ -1082,6 +1117,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
             }
             wait_all_memory();
             wave_lds_sync();
+            fetch();   // the next batch's masks and values
             flush(false);
             got_prev = got;
 #pragma unroll
