@@ -281,8 +281,7 @@ struct Bufs {
     float* tau = nullptr;
     uint32_t* nlast = nullptr;
     // geometry: records, sorted lists and tile ranges
-    float4* cq = nullptr;
-    float2* cw = nullptr;
+    CRec* crec = nullptr;           // computation-plane records
     float4* iq = nullptr;
     float2* iw = nullptr;
     uint32_t* pval[2] = {nullptr, nullptr};
@@ -355,8 +354,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
     b.nlast = st.take<uint32_t>(P.rays);
     auto geo = [&](Arena& a) {
         b.active = a.take<uint32_t>(R);   // records pass A used
-        b.cq = a.take<float4>(R);
-        b.cw = a.take<float2>(R);
+        b.crec = a.take<CRec>(R);
         b.iq = a.take<float4>(R);
         b.iw = a.take<float2>(R);
         b.pval[0] = a.take<uint32_t>(K);
@@ -498,7 +496,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool z
     SDGR_HIP(launch_fill_u32(b.status + ST_RECORDS, (uint32_t)R, 1, s));
     {
         StageTimer t(SG_PREPROCESS, s);
-        SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, true, b.cq, b.cw, b.iq,
+        SDGR_HIP(launch_preprocess(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, true, b.crec, b.iq,
                                    b.iw, b.rect_c, b.rect_i, b.dkey[0],
                                    zero_A ? b.A : nullptr, b.prec, b.slots,
                                    reinterpret_cast<unsigned long long*>(b.status + ST_COUNT),
@@ -549,7 +547,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool z
     SDGR_HIP(launch_tile_ranges(pk[pw], plan->pairs_c, b.status + ST_PAIRS_C, P.tiles_c,
                                 b.ranges, s));
     SDGR_HIP(launch_pair_masks(b.views, P.nv, plan->pairs_c, P.rp, b.status, pk[pw], pv[pw],
-                               b.cq, b.cw, b.pmask, b.psum, s));
+                               b.crec, b.pmask, b.psum, s));
     SDGR_HIP(launch_tile_worklist(b.ranges, P.tiles_c, b.worklist, b.status + WL_BINS, b.status, s));
     return SDGR_OK;
 }
@@ -598,7 +596,7 @@ int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan
         StageTimer t(SG_QUERY, s);
         SDGR_HIP(launch_preprocess(dviews, dscenes, P.nv, P.ns, P.items, P.rp, false, nullptr,
                                    nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                                   nullptr, slots, totals, s));
+                                   slots, totals, s));
     }
     unsigned long long host_tot[2] = {0, 0};
     SDGR_HIP(hipMemcpyAsync(host_tot, totals, sizeof(host_tot), hipMemcpyDeviceToHost, s));
@@ -797,7 +795,7 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
             rp.part = b.part_a;
         }
         SDGR_HIP(launch_raster_a_fwd(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
-                                     b.ranges, b.pval[pw], b.pmask, b.psum, b.cq, b.cw, b.A,
+                                     b.ranges, b.pval[pw], b.pmask, b.psum, b.crec, b.A,
                                      b.tau, b.nlast, s));
         if (P.det)
             SDGR_HIP(launch_reduce_pairs(b.dord, b.poff, P.records, b.status, b.part_a, 1,
@@ -884,7 +882,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
             rp.part_stride = plan->pairs_c;
         }
         SDGR_HIP(launch_raster_a_bwd(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
-                                     b.ranges, b.pval[pw], b.pmask, b.psum, b.cq, b.cw, b.tau,
+                                     b.ranges, b.pval[pw], b.pmask, b.psum, b.crec, b.tau,
                                      b.nlast, b.cbwd, b.grad_c, P.records, s));
         if (P.det)
             SDGR_HIP(launch_reduce_pairs(b.dord, b.poff, P.records, b.status, b.part_g, 6,

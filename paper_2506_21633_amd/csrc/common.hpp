@@ -53,6 +53,15 @@ struct DevScene {
     int32_t sh_stride;  // floats between consecutive rows of sh and d_sh
 };
 
+// Computation-plane record of one (view, Gaussian), gathered whole by the
+// footprint masks and both pass A kernels (one 32-byte piece instead of one
+// line per field): centre and conic (cx, cy, a, b), then the conic's c and
+// the extinction kappa, padded to a full 32-byte write.
+struct alignas(32) CRec {
+    float4 q;   // cx, cy, a, b
+    float4 w;   // c, kappa, 0, 0
+};
+
 struct RasterParams {
     float q_max;       // footprint cutoff
     float eps;         // exp(-q_max / 2)
@@ -265,7 +274,7 @@ namespace sdgr {
 constexpr int TOTAL_SLOTS = 1024;
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv, int nscenes,
                              int64_t items, const RasterParams& rp,
-                             bool write_records, float4* cq, float2* cw, float4* iq,
+                             bool write_records, CRec* crec, float4* iq,
                              float2* iw, uint2* rect_c, uint2* rect_i, uint32_t* dkey,
                              float* A_zero, float* prec, unsigned long long* slots,
                              unsigned long long* totals, hipStream_t s);
@@ -347,7 +356,7 @@ hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s
 
 hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const RasterParams& rp,
                              const uint32_t* status, const uint32_t* pkey,
-                             const uint32_t* pvals, const float4* cq, const float2* cw,
+                             const uint32_t* pvals, const CRec* crec,
                              uint64_t* pmask, uint64_t* psum, hipStream_t s);
 hipError_t launch_tile_worklist(const uint2* ranges, int64_t tiles_c, uint32_t* worklist,
                                 uint32_t* bins, uint32_t* status, hipStream_t s);
@@ -355,7 +364,7 @@ hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask,
-                               const uint64_t* psum, const float4* cq, const float2* cw,
+                               const uint64_t* psum, const CRec* crec,
                                float* A, float* tau, uint32_t* nlast, hipStream_t s);
 hipError_t launch_raster_b_fwd(const DevView* views, int nv, int64_t pixels, int64_t cap_c,
                                int64_t cap_i, const RasterParams& rp, const uint32_t* status,
@@ -381,7 +390,7 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask,
-                               const uint64_t* psum, const float4* cq, const float2* cw,
+                               const uint64_t* psum, const CRec* crec,
                                const float* tau, const uint32_t* nlast, const float* cbwd,
                                float* grad_c, int64_t stride, hipStream_t s);
 

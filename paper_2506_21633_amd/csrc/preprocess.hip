@@ -198,7 +198,7 @@ constexpr int PRE_VIEWS = 8;
 __global__ void __launch_bounds__(256)
 k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ scenes, int nv,
              int nscenes, int64_t items, RasterParams rp, int write_records,
-             float4* __restrict__ cq, float2* __restrict__ cw, float4* __restrict__ iq,
+             CRec* __restrict__ crec, float4* __restrict__ iq,
              float2* __restrict__ iw, uint2* __restrict__ rect_c, uint2* __restrict__ rect_i,
              uint32_t* __restrict__ dkey, float* __restrict__ A_zero,
              float* __restrict__ prec, unsigned long long* __restrict__ totals)
@@ -286,8 +286,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
                 prec[r] = P * (float)V.pscale;
             }
             if (write_records) {
-                cq[r] = vc_q;
-                cw[r] = vc_w;
+                crec[r] = CRec{vc_q, make_float4(vc_w.x, vc_w.y, 0.0f, 0.0f)};
                 iq[r] = vi_q;
                 iw[r] = vi_w;
                 rect_c[r] = rc;
@@ -625,7 +624,7 @@ __global__ void __launch_bounds__(256) k_fill_u64(unsigned long long* p, int n)
 
 hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int nv, int nscenes,
                              int64_t items, const RasterParams& rp, bool write_records,
-                             float4* cq, float2* cw, float4* iq, float2* iw, uint2* rect_c,
+                             CRec* crec, float4* iq, float2* iw, uint2* rect_c,
                              uint2* rect_i, uint32_t* dkey, float* A_zero, float* prec,
                              unsigned long long* slots, unsigned long long* totals,
                              hipStream_t s)
@@ -636,7 +635,7 @@ hipError_t launch_preprocess(const DevView* views, const DevScene* scenes, int n
         hipLaunchKernelGGL(k_preprocess,
                            dim3(blocks_for(items, 256), (unsigned)((nv + PRE_VIEWS - 1) / PRE_VIEWS)),
                            dim3(256), 0, s, views, scenes, nv, nscenes, items, rp,
-                           write_records ? 1 : 0, cq, cw, iq, iw, rect_c, rect_i, dkey,
+                           write_records ? 1 : 0, crec, iq, iw, rect_c, rect_i, dkey,
                            write_records ? A_zero : nullptr, write_records ? prec : nullptr,
                            slots);
     hipLaunchKernelGGL(k_sum_slots, dim3(1), dim3(TOTAL_SLOTS), 0, s, slots, totals);

@@ -301,9 +301,8 @@ constexpr int PM_ITEMS = 4;
 __global__ void __launch_bounds__(256)
 k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParams rp,
              const uint32_t* __restrict__ status, const uint32_t* __restrict__ pkey,
-             const uint32_t* __restrict__ pvals, const float4* __restrict__ cq,
-             const float2* __restrict__ cw, uint64_t* __restrict__ pmask,
-             uint64_t* __restrict__ psum)
+             const uint32_t* __restrict__ pvals, const CRec* __restrict__ crec,
+             uint64_t* __restrict__ pmask, uint64_t* __restrict__ psum)
 {
     constexpr int BP = 256 * PM_ITEMS;
     const int64_t kc = min(cap, (int64_t)status[ST_PAIRS_C]);
@@ -317,13 +316,12 @@ k_pair_masks(const DevView* __restrict__ views, int nv, int64_t cap, RasterParam
         bucket[k] = p < kc ? pkey[p] : 0u;
         r[k] = p < kc ? pvals[p] : 0u;
     }
-    float4 g[PM_ITEMS];
-    float2 g2[PM_ITEMS];
+    float4 g[PM_ITEMS], g2[PM_ITEMS];
 #pragma unroll
     for (int k = 0; k < PM_ITEMS; ++k) {
         if (base + k * 256 < kc) {
-            g[k] = cq[r[k]];
-            g2[k] = cw[r[k]];
+            g[k] = crec[r[k]].q;
+            g2[k] = crec[r[k]].w;
         }
     }
 #pragma unroll
@@ -367,7 +365,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                const uint32_t* __restrict__ status, const uint32_t* __restrict__ worklist,
                const uint2* __restrict__ ranges, const uint32_t* __restrict__ pvals,
                const uint64_t* __restrict__ pmask, const uint64_t* __restrict__ psum,
-               const float4* __restrict__ cq, const float2* __restrict__ cw,
+               const CRec* __restrict__ crec,
                float* __restrict__ A, float* __restrict__ tau, uint32_t* __restrict__ nlast)
 {
     constexpr int NB = 2 * A_BATCH;   // the forward keeps less per chunk in LDS
@@ -481,8 +479,8 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     const bool need = (m[k] & live) != 0ull;
                     got |= need ? 1u << k : 0u;
                     const uint32_t rk = need ? r[k] : 0u;
-                    const float* w = reinterpret_cast<const float*>(cw + rk);
-                    load16_to_lds(cq + rk, &s_q[k][0]);
+                    const float* w = reinterpret_cast<const float*>(&crec[rk].w);
+                    load16_to_lds(&crec[rk].q, &s_q[k][0]);
                     load4_to_lds(w, &s_wc[k][0]);
                     load4_to_lds(w + 1, &s_wk[k][0]);
                 }
@@ -914,10 +912,9 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                RasterParams rp, const uint32_t* __restrict__ status,
                const uint32_t* __restrict__ worklist, const uint2* __restrict__ ranges,
                const uint32_t* __restrict__ pvals, const uint64_t* __restrict__ pmask,
-               const uint64_t* __restrict__ psum, const float4* __restrict__ cq,
-               const float2* __restrict__ cw, const float* __restrict__ tau,
-               const uint32_t* __restrict__ nlast, const float* __restrict__ cbwd,
-               float* __restrict__ grad_c, int64_t stride)
+               const uint64_t* __restrict__ psum, const CRec* __restrict__ crec,
+               const float* __restrict__ tau, const uint32_t* __restrict__ nlast,
+               const float* __restrict__ cbwd, float* __restrict__ grad_c, int64_t stride)
 {
     constexpr int NB = 2 * A_BATCH;
     constexpr int HKB = NB <= 8 ? 3 : 4;   // bits of a hit's chunk index
@@ -1105,8 +1102,8 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                     const bool need = (m[k] & lv[k]) != 0ull;
                     got |= need ? 1u << k : 0u;
                     const uint32_t rk = need ? rec[k] : (uint32_t)V.rec_off;
-                    const float* w = reinterpret_cast<const float*>(cw + rk);
-                    load16_to_lds(cq + rk, &s_q[k][0]);
+                    const float* w = reinterpret_cast<const float*>(&crec[rk].w);
+                    load16_to_lds(&crec[rk].q, &s_q[k][0]);
                     load4_to_lds(w, &s_wc[k][0]);
                     load4_to_lds(w + 1, &s_wk[k][0]);
                     load4_to_lds(cbwd + rk, &s_c[k][0]);
@@ -1317,13 +1314,13 @@ inline unsigned grid256(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const RasterParams& rp,
                              const uint32_t* status, const uint32_t* pkey,
-                             const uint32_t* pvals, const float4* cq, const float2* cw,
+                             const uint32_t* pvals, const CRec* crec,
                              uint64_t* pmask, uint64_t* psum, hipStream_t s)
 {
     if (cap_c <= 0) return hipSuccess;
     const unsigned grid = (unsigned)((cap_c + 256 * PM_ITEMS - 1) / (256 * PM_ITEMS));
     hipLaunchKernelGGL(k_pair_masks, dim3(grid), dim3(256), 0, s, views, nv, cap_c, rp, status,
-                       pkey, pvals, cq, cw, pmask, psum);
+                       pkey, pvals, crec, pmask, psum);
     return hipGetLastError();
 }
 
@@ -1346,17 +1343,17 @@ hipError_t launch_raster_a_fwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask,
-                               const uint64_t* psum, const float4* cq, const float2* cw,
+                               const uint64_t* psum, const CRec* crec,
                                float* A, float* tau, uint32_t* nlast, hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
     if (rp.ppos)
         hipLaunchKernelGGL(k_raster_a_fwd<true>, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views,
-                           nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, A, tau,
+                           nv, rp, status, worklist, ranges, pvals, pmask, psum, crec, A, tau,
                            nlast);
     else
         hipLaunchKernelGGL(k_raster_a_fwd<false>, dim3((unsigned)tiles_c), dim3(WAVE), 0, s, views,
-                           nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw, A, tau,
+                           nv, rp, status, worklist, ranges, pvals, pmask, psum, crec, A, tau,
                            nlast);
     return hipGetLastError();
 }
@@ -1411,7 +1408,7 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask,
-                               const uint64_t* psum, const float4* cq, const float2* cw,
+                               const uint64_t* psum, const CRec* crec,
                                const float* tau, const uint32_t* nlast, const float* cbwd,
                                float* grad_c, int64_t stride, hipStream_t s)
 {
@@ -1420,10 +1417,10 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
     auto two = [&](auto det) {
         constexpr bool D = decltype(det)::value;
         hipLaunchKernelGGL((k_raster_a_bwd<true, D>), dim3((unsigned)tiles_c), dim3(2 * WAVE), 0,
-                           s, views, nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw,
+                           s, views, nv, rp, status, worklist, ranges, pvals, pmask, psum, crec,
                            tau, nlast, cbwd, grad_c, stride);
         hipLaunchKernelGGL((k_raster_a_bwd<false, D>), dim3((unsigned)tiles_c), dim3(WAVE), 0, s,
-                           views, nv, rp, status, worklist, ranges, pvals, pmask, psum, cq, cw,
+                           views, nv, rp, status, worklist, ranges, pvals, pmask, psum, crec,
                            tau, nlast, cbwd, grad_c, stride);
     };
     if (rp.ppos)
