@@ -287,6 +287,15 @@ int sdgr_forward_static(const sdgr_scene* scenes, int32_t nscenes,
  * that used `state` found more pairs than planned, else SDGR_OK. */
 int sdgr_status(const sdgr_plan* plan, const void* state, void* stream);
 
+/* The same check without synchronising: enqueues on `stream` an OR of the
+ * state's overflow flag into the device word *flags (a caller-owned uint32
+ * that starts at 0). A loop can accumulate the flags of many steps and read
+ * the word once: nonzero means some forward or backward found more pairs
+ * than planned (its results are incomplete and the step must be redone with
+ * a larger plan). */
+int sdgr_status_accumulate(const sdgr_plan* plan, const void* state, uint32_t* flags,
+                           void* stream);
+
 /* Copies the per-view scattering shares A (float32, plan->records entries,
  * view-major: view v's entries start at the sum of the n of the scenes of
  * views 0..v-1) out of `state` into the device buffer `out`. Asynchronous.

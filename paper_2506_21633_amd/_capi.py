@@ -22,7 +22,7 @@ EXPORTED = ("sdgr_version", "sdgr_last_error", "sdgr_default_options",
             "sdgr_backward", "sdgr_status", "sdgr_read_intensity",
             "sdgr_read_optical_depth", "sdgr_profile_enable", "sdgr_profile_read",
             "sdgr_profile_stage", "sdgr_profile_count", "sdgr_read_work",
-            "sdgr_plan_resize", "sdgr_forward_static", "sdgr_plan_host",
+            "sdgr_plan_resize", "sdgr_forward_static", "sdgr_plan_host", "sdgr_status_accumulate",
             # reconstruction loop and metrics
             "sdgr_adam_step", "sdgr_densify_stats", "sdgr_densify_workspace_bytes",
             "sdgr_densify", "sdgr_nearest_sq", "sdgr_image_metrics")
@@ -145,6 +145,8 @@ def lib():
     L.sdgr_forward_static.argtypes = [P(Scene), ctypes.c_int32, P(View), ctypes.c_int32,
                                       P(Options), vp, vp]
     L.sdgr_status.argtypes = [P(Plan), vp, vp]
+    L.sdgr_status_accumulate.argtypes = [P(Plan), vp, vp, vp]
+    L.sdgr_status_accumulate.restype = ctypes.c_int
     L.sdgr_read_intensity.argtypes = [P(Plan), vp, vp, vp]
     L.sdgr_read_optical_depth.argtypes = [P(Plan), vp, vp, vp]
     L.sdgr_profile_enable.argtypes = [ctypes.c_int32]

@@ -287,6 +287,15 @@ class Renderer:
         C.check(self.lib.sdgr_status(ctypes.byref(fwd.plan), fwd.state.data_ptr(),
                                      _stream_ptr(self.device)))
 
+    def status_into(self, fwd: ForwardResult, flags: torch.Tensor):
+        """The overflow check without a host sync: ORs the flag into the
+        device int32 tensor `flags` (one element, starting at 0), so a loop
+        can read it once for many steps."""
+        if flags.dtype != torch.int32 or flags.numel() < 1 or not flags.is_cuda:
+            raise ValueError("flags must be a CUDA int32 tensor")
+        C.check(self.lib.sdgr_status_accumulate(ctypes.byref(fwd.plan), fwd.state.data_ptr(),
+                                                flags.data_ptr(), _stream_ptr(self.device)))
+
     def intensity_shares(self, fwd: ForwardResult) -> torch.Tensor:
         """A per record, view-major (flat)."""
         out = torch.empty(max(int(fwd.plan.records), 1), dtype=torch.float32,

@@ -932,6 +932,16 @@ int sdgr_status(const sdgr_plan* plan, const void* state, void* stream)
     return SDGR_OK;
 }
 
+int sdgr_status_accumulate(const sdgr_plan* plan, const void* state, uint32_t* flags,
+                           void* stream)
+{
+    g_last_error.clear();
+    if (!plan || !state || !flags) return fail(SDGR_EINVAL, "null plan, state or flags");
+    SDGR_HIP(launch_or_word(reinterpret_cast<const uint32_t*>(state), flags,
+                            (hipStream_t)stream));
+    return SDGR_OK;
+}
+
 static int read_state_array(const sdgr_plan* plan, const void* state, float* out, int which,
                             void* stream)
 {

@@ -352,6 +352,7 @@ hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
 hipError_t launch_tile_ranges(const uint32_t* keys, int64_t cap, const uint32_t* n_dev,
                               int64_t buckets, uint2* ranges, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_or_word(const uint32_t* src, uint32_t* dst, hipStream_t s);
 hipError_t launch_upload(void* dst, const void* src, size_t bytes, hipStream_t s);
 
 hipError_t launch_pair_masks(const DevView* views, int nv, int64_t cap_c, const RasterParams& rp,

@@ -961,6 +961,23 @@ hipError_t launch_seg_setup(const DevView* views, int nv, int64_t records, const
     return hipGetLastError();
 }
 
+namespace {
+// dst |= src[0] (one word; for accumulating a status flag on the device)
+__global__ void k_or_word(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t v = src[0];
+        if (v) dst[0] |= v;
+    }
+}
+}  // namespace
+
+hipError_t launch_or_word(const uint32_t* src, uint32_t* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_or_word, dim3(1), dim3(64), 0, s, src, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
