@@ -790,6 +790,8 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
 // Deterministic sums over the computation-plane pairs: thread = depth rank
 // p, its record's pairs are [poff[p], next) before the pair sort (one
 // record's tiles, row by row); their partials are added in that order.
+// After a pair overflow the lists are empty and no partial was written:
+// nothing is summed (the call's results are void anyway).
 __global__ void __launch_bounds__(256)
 k_reduce_pairs(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ poff,
                int64_t records, const uint32_t* __restrict__ status,
@@ -797,7 +799,7 @@ k_reduce_pairs(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ p
                float* __restrict__ out, int64_t out_stride)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= records) return;
+    if (p >= records || status[ST_OVERFLOW]) return;
     const uint32_t kc = status[ST_PAIRS_C];
     const uint32_t lo = min(poff[p], kc);
     const uint32_t hi = p + 1 < records ? min(poff[p + 1], kc) : kc;

@@ -119,6 +119,47 @@ def test_ragged_sizes_and_custom_computation_grid(cuda):
     check_forward(sc, views, out)
 
 
+@pytest.mark.parametrize("deterministic", [False, True])
+@pytest.mark.parametrize("plane", ["computation", "imaging"])
+def test_pair_overflow_is_reported_and_recovered(cuda, plane, deterministic):
+    """A plan with too few pairs on one plane: the kernels clamp to empty
+    lists, sdgr_status reports SDGR_EOVERFLOW and the asynchronous check sets
+    its device flag; the exact plan then renders as the oracle does and
+    leaves a fresh flag clear."""
+    import ctypes
+    A_ = api()
+    from paper_2506_21633_amd import _capi as C
+    sc = _small_scene(31)
+    views = [scenes.View.from_degrees(20.0, 45.0, 64, 0.06),
+             scenes.View.from_degrees(200.0, 30.0, 48, 0.06)]
+    r = A_.Renderer([A_.GaussianTensors.from_numpy(sc, cuda)], views,
+                    A_.RenderOptions(deterministic=deterministic))
+    exact = r.plan()
+    small = C.Plan()
+    ctypes.pointer(small)[0] = exact
+    pc, pi = (exact.pairs_c // 2, exact.pairs_i) if plane == "computation" else \
+        (exact.pairs_c, exact.pairs_i // 2)
+    C.check(C.lib().sdgr_plan_resize(ctypes.byref(small), pc, pi))
+    flags = torch.zeros(1, dtype=torch.int32, device=cuda)
+    res = r.forward(small)
+    r.backward(res, torch.ones_like(res.images))
+    r.status_into(res, flags)
+    torch.cuda.synchronize()
+    assert int(flags.item()) != 0
+    with pytest.raises(C.SDGRError) as err:
+        r.status(res)
+    assert err.value.code == C.SDGR_EOVERFLOW
+    ok = r.forward(exact)
+    clear = torch.zeros(1, dtype=torch.int32, device=cuda)
+    r.status_into(ok, clear)
+    torch.cuda.synchronize()
+    assert int(clear.item()) == 0
+    r.status(ok)
+    _, _, S_ref = oracle.forward(sc, views)
+    for v in range(len(views)):
+        assert img_err(ok.image(v).cpu().numpy(), S_ref[v]) <= IMG_TOL
+
+
 def test_tiny_and_one_pixel_images(cuda):
     sc = _small_scene(8, n=50, half=0.2)
     views = [scenes.View(azimuth=0.0, grazing=0.7, img_w=1, img_h=1, d_az=0.1, d_rg=0.1),
