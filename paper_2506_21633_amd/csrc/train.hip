@@ -314,10 +314,11 @@ k_image_metrics(const float* __restrict__ x, const float* __restrict__ ref, int 
     const float* X = x + img * (int64_t)h * w;
     const float* Y = ref + img * (int64_t)h * w;
     const int vh = h - SSIM_WIN + 1, vw = w - SSIM_WIN + 1;
+    const int64_t npos = (int64_t)vh * vw, npix = (int64_t)h * w;
     double acc = 0.0, err = 0.0;
     float mx = -INFINITY;
-    for (int p = threadIdx.x; p < vh * vw; p += blockDim.x) {
-        const int r0 = p / vw, c0 = p % vw;
+    for (int64_t p = threadIdx.x; p < npos; p += blockDim.x) {
+        const int r0 = (int)(p / vw), c0 = (int)(p % vw);
         float ma = 0.f, mb = 0.f;
         for (int r = 0; r < SSIM_WIN; ++r)
             for (int c = 0; c < SSIM_WIN; ++c) {
@@ -338,7 +339,7 @@ k_image_metrics(const float* __restrict__ x, const float* __restrict__ ref, int 
         acc += (double)(((2.f * ma * mb + c1) * (2.f * cv + c2)) /
                         ((ma * ma + mb * mb + c1) * (va + vb + c2)));
     }
-    for (int p = threadIdx.x; p < h * w; p += blockDim.x) {
+    for (int64_t p = threadIdx.x; p < npix; p += blockDim.x) {
         const float d = X[p] - Y[p];
         err += (double)d * d;
         mx = fmaxf(mx, Y[p]);
@@ -356,8 +357,8 @@ k_image_metrics(const float* __restrict__ x, const float* __restrict__ ref, int 
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        ssim[img] = (float)(s_a[0] / ((double)vh * vw));
-        mse[img] = (float)(s_b[0] / ((double)h * w));
+        ssim[img] = (float)(s_a[0] / (double)npos);
+        mse[img] = (float)(s_b[0] / (double)npix);
         rmax[img] = s_m[0];
     }
 }
