@@ -188,6 +188,19 @@ typedef struct sdgr_plan {
     int32_t deterministic;     /* copy of options.deterministic */
     int32_t sh_coeffs;         /* most SH coefficients of any scene (0: no
                                   scene has sh); sizes the backward scratch */
+    int64_t hit_bytes;         /* part of the state in which the forward keeps
+                                  the footprint hits each computation-plane
+                                  tile's rays used (Sec. II-A compositing
+                                  order), so that the backward (Sec. II-B)
+                                  reads them instead of re-deriving them from
+                                  the footprint masks. The plan calls set 8
+                                  bytes per computation-plane pair plus 16 MiB,
+                                  and 0 in recompute or deterministic mode
+                                  (where it is always taken as 0). A caller
+                                  may lower it (>= 0; the state shrinks to
+                                  match): tiles that find it full, and all
+                                  tiles at 0, re-derive their hits, with the
+                                  same results up to float rounding. */
 } sdgr_plan;
 
 /* Library version (SDGR_VERSION). */
@@ -331,10 +344,12 @@ const char* sdgr_profile_stage(int32_t i);
  * batches whose footprint hits did not fit one compaction round, counted
  * once per extra group, in pass A forward and backward (out[10], out[11]),
  * the rays stopped at tau_max (out[12]), the longest list prefix one
- * tile used (out[13]) and the tiles the pass A backward ran as long lists
- * (at least 2048 entries) and as short ones (out[14], out[15]). The
+ * tile used (out[13]), the tiles the pass A backward ran as long lists
+ * (at least 2048 entries) and as short ones (out[14], out[15]), and the
+ * tiles whose pass A backward read the forward's stored hits and those
+ * that re-derived them from the footprint masks (out[16], out[17]). The
  * counting adds atomics, so timed runs leave it off.
- * sdgr_read_work synchronises `stream` and copies min(n, 16) counters of
+ * sdgr_read_work synchronises `stream` and copies min(n, 18) counters of
  * the last forward (and backward) that used `state`. */
 int sdgr_profile_count(int32_t on);
 int sdgr_read_work(const sdgr_plan* plan, const void* state, uint64_t* out, int32_t n,

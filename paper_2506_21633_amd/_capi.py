@@ -75,7 +75,8 @@ class Plan(ctypes.Structure):
                 ("tiles_i", ctypes.c_int64), ("rays", ctypes.c_int64),
                 ("gaussians", ctypes.c_int64), ("nviews", ctypes.c_int32), ("nscenes", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("recompute", ctypes.c_int32),
-                ("deterministic", ctypes.c_int32), ("sh_coeffs", ctypes.c_int32)]
+                ("deterministic", ctypes.c_int32), ("sh_coeffs", ctypes.c_int32),
+                ("hit_bytes", ctypes.c_int64)]
 
 
 ADAM_MAX_GROUPS = 16   # SDGR_ADAM_MAX_GROUPS

@@ -307,8 +307,9 @@ class Renderer:
     def work_counters(self, fwd: ForwardResult) -> dict:
         """Work counters of the last forward (and backward) on `fwd`'s state;
         filled only for calls made while count_work(True) was in effect."""
-        wk = (ctypes.c_uint64 * 16)()
-        C.check(self.lib.sdgr_read_work(ctypes.byref(fwd.plan), fwd.state.data_ptr(), wk, 16,
+        wk = (ctypes.c_uint64 * len(WORK_NAMES))()
+        C.check(self.lib.sdgr_read_work(ctypes.byref(fwd.plan), fwd.state.data_ptr(), wk,
+                                        len(WORK_NAMES),
                                         _stream_ptr(self.device)))
         return dict(zip(WORK_NAMES, list(wk)))
 
@@ -322,7 +323,8 @@ class Renderer:
 WORK_NAMES = ("hits_a_fwd", "hits_a_bwd", "hits_b_fwd", "hits_b_bwd", "rounds_a_fwd",
               "rounds_a_bwd", "rounds_b_fwd", "list_prefix_a", "max_batches_a_fwd",
               "max_batches_a_bwd", "extra_hit_groups_a_fwd", "extra_hit_groups_a_bwd",
-              "rays_stopped_tau_max", "max_list_prefix_a", "tiles_a_bwd_long", "tiles_a_bwd_short")
+              "rays_stopped_tau_max", "max_list_prefix_a", "tiles_a_bwd_long", "tiles_a_bwd_short",
+              "tiles_a_bwd_stored", "tiles_a_bwd_rederived")
 
 
 def count_work(on: bool) -> None:

@@ -121,7 +121,22 @@ struct Problem {
     bool seg = false;       // depth and pair sorts segmented by view
     int cbits = 0;          // bits of the computation-plane tile within a view
     int ikey_bits = 0;      // bits of the tile within a view
+    int64_t hit_units = 0;  // 16-byte units of the stored-hit stream (0: none)
 };
+
+// The stored-hit stream of a plan (RasterParams::hits): only where the
+// forward's lists survive to the backward (not in recompute mode) and the
+// sums are unordered (not in deterministic mode, whose results must not
+// depend on which tiles found room). The default holds 8 bytes per
+// computation-plane pair plus 16 MiB (a used hit takes 8 bytes, and rays
+// stop long before using every pair in their tile); a tile that finds the
+// stream full has its backward re-derive the hits from the footprint masks.
+int64_t hit_units_for(const Problem& P, int64_t pairs_c, int64_t hit_bytes)
+{
+    if (P.det || P.recompute) return 0;
+    const int64_t bytes = hit_bytes < 0 ? 8 * pairs_c + (int64_t(16) << 20) : hit_bytes;
+    return std::min<int64_t>(bytes / 16, int64_t(UINT32_MAX) - 64);
+}
 
 // Rows of the world-to-radar rotation R_r(phi, theta) (Sec. II-A).
 void radar_axes(double phi, double theta, double* ex, double* ey, double* ez)
@@ -320,6 +335,11 @@ struct Bufs {
     float* part_a = nullptr;
     float* part_g = nullptr;
     uint2* ranges_i = nullptr;
+    // stored hits of pass A's forward for its backward (RasterParams::hits)
+    uint4* hits = nullptr;
+    uint32_t* hit_tail = nullptr;   // per computation-plane tile
+    float* hit_part = nullptr;      // backward: per-pair partials, see RasterParams::hit_part
+    unsigned char* hit_touched = nullptr;
 };
 
 struct Arena {
@@ -364,11 +384,15 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         b.ranges = a.take<uint2>(P.tiles_c);
         b.worklist = a.take<uint32_t>(P.tiles_c);
         if (P.shc > 0) b.prec = a.take<float>(R);
-        if (P.det) {
+        if (P.det || P.hit_units > 0) {
             b.ppos[0] = a.take<uint32_t>(cap_c);
             b.ppos[1] = a.take<uint32_t>(cap_c);
             b.dord = a.take<uint32_t>(R);
             b.poff = a.take<uint32_t>(R);
+        }
+        if (P.hit_units > 0) {
+            b.hits = a.take<uint4>(P.hit_units + 16);   // slack for the backward's part copies
+            b.hit_tail = a.take<uint32_t>(P.tiles_c);
         }
     };
     auto transient = [&](Arena& a) {
@@ -402,11 +426,15 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
             geo(sc);
             transient(sc);
         }
-        b.grad_c = sc.take<float>(6 * R);   // plane-major, see launch_params_backward
+        b.grad_c = sc.take<float>(GC_STRIDE * R);   // record-major, see launch_params_backward
         b.grad_i = sc.take<float>(6 * R);
         b.cbwd = sc.take<float>(R);
         b.pgrad = sc.take<float>((int64_t)params_part_floats(P.nv, P.items, P.shc));
         if (P.det) b.part_g = sc.take<float>(6 * cap_c);
+        if (P.hit_units > 0) {
+            b.hit_part = sc.take<float>(6 * cap_c);
+            b.hit_touched = sc.take<unsigned char>(cap_c + 4);
+        }
     }
     if (state_bytes) *state_bytes = st.off;
     if (scratch_bytes) *scratch_bytes = sc.off;
@@ -447,7 +475,7 @@ int upload_tables(const Problem& P, const Bufs& b, hipStream_t s, const void* st
     return SDGR_OK;
 }
 
-int check_plan(const Problem& P, const sdgr_plan* plan)
+int check_plan(Problem& P, const sdgr_plan* plan)
 {
     if (!plan) return fail(SDGR_EINVAL, "plan is null");
     if (plan->records != P.records || plan->rays != P.rays || plan->tiles_c != P.tiles_c ||
@@ -455,8 +483,10 @@ int check_plan(const Problem& P, const sdgr_plan* plan)
         plan->nscenes != P.ns ||
         plan->tile != TILE || plan->recompute != (P.recompute ? 1 : 0) ||
         plan->deterministic != (P.det ? 1 : 0) || plan->sh_coeffs != P.shc ||
-        plan->pairs_c < 0 || plan->pairs_i < 0 || plan->pairs_c + plan->pairs_i > INT32_MAX)
+        plan->pairs_c < 0 || plan->pairs_i < 0 || plan->pairs_c + plan->pairs_i > INT32_MAX ||
+        plan->hit_bytes < 0)
         return fail(SDGR_EINVAL, "plan does not match the scenes, views and options");
+    P.hit_units = hit_units_for(P, plan->pairs_c, plan->hit_bytes);
     // the workspaces the plan promises must hold the layout of its capacities
     Bufs b;
     size_t st = 0, fs = 0, bs = 0;
@@ -539,7 +569,7 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool z
         SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_c, b.status + ST_PAIRS_C,
                                        bits_pairs_c(P), false, b.hist, &pw, s, 0,
                                        P.seg ? &b.segt[1] : nullptr, P.nv, true,
-                                       P.det ? pp : nullptr));
+                                       b.ppos[0] ? pp : nullptr));
     }
     if (plan->pairs_c > 0 && pw != final_buffer_c(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
@@ -580,7 +610,8 @@ int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
 // Pair counts of the projection (count-only preprocess into `query`, which
 // holds sdgr_query_bytes(ns, nv)), read back with one stream
 // synchronisation, and the workspace sizes they imply.
-void fill_plan(const Problem& P, int64_t pairs_c, int64_t pairs_i, sdgr_plan* plan);
+void fill_plan(const Problem& P, int64_t pairs_c, int64_t pairs_i, sdgr_plan* plan,
+               int64_t hit_bytes = -1);
 
 int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan)
 {
@@ -607,10 +638,15 @@ int count_and_plan(const Problem& P, char* query, hipStream_t s, sdgr_plan* plan
     return SDGR_OK;
 }
 
-// The plan of a problem at given pair capacities (host data only).
-void fill_plan(const Problem& P, int64_t pairs_c, int64_t pairs_i, sdgr_plan* plan)
+// The plan of a problem at given pair capacities (host data only);
+// hit_bytes < 0 takes the default stored-hit stream.
+void fill_plan(const Problem& P0, int64_t pairs_c, int64_t pairs_i, sdgr_plan* plan,
+               int64_t hit_bytes)
 {
+    Problem P = P0;
+    P.hit_units = hit_units_for(P, pairs_c, hit_bytes);
     sdgr_plan out{};
+    out.hit_bytes = P.hit_units * 16;
     out.records = P.records;
     out.pairs_c = pairs_c;
     out.pairs_i = pairs_i;
@@ -751,8 +787,10 @@ int sdgr_plan_resize(sdgr_plan* plan, int64_t pairs_c, int64_t pairs_i)
     P.det = plan->deterministic != 0;
     P.shc = plan->sh_coeffs;
     if (P.shc < 0 || P.shc > 16) return fail(SDGR_EINVAL, "plan's sh_coeffs outside 0..16");
+    P.hit_units = hit_units_for(P, pairs_c, -1);
     plan->pairs_c = pairs_c;
     plan->pairs_i = pairs_i;
+    plan->hit_bytes = P.hit_units * 16;
     Bufs b;
     layout(P, pairs_c, pairs_i, FWD, nullptr, nullptr, b, &plan->state_bytes,
            &plan->fwd_scratch_bytes);
@@ -788,6 +826,12 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
     {
         StageTimer t(SG_RASTER_A_FWD, s);
         RasterParams rp = P.rp;
+        if (b.hits) {
+            rp.hits = b.hits;
+            rp.hit_tail = b.hit_tail;
+            rp.hit_top = reinterpret_cast<unsigned long long*>(b.status + ST_HIT_TOP);
+            rp.hit_cap = (uint32_t)P.hit_units;
+        }
         if (P.det) {
             // one partial per (tile, record) pair, summed per record in list order
             SDGR_HIP(launch_fill_u32((uint32_t*)b.part_a, 0u, plan->pairs_c, s));
@@ -799,7 +843,7 @@ int sdgr_forward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vie
                                      b.tau, b.nlast, s));
         if (P.det)
             SDGR_HIP(launch_reduce_pairs(b.dord, b.poff, P.records, b.status, b.part_a, 1,
-                                         plan->pairs_c, b.A, P.records, s));
+                                         plan->pairs_c, b.A, 0, 1, s));
     }
     {
         StageTimer t(SG_INTENSITY, s);
@@ -875,6 +919,16 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
     {
         StageTimer t(SG_RASTER_A_BWD, s);
         RasterParams rp = P.rp;
+        if (b.hits) {
+            rp.hits = b.hits;
+            rp.hit_tail = b.hit_tail;
+            rp.hit_cap = (uint32_t)P.hit_units;
+            rp.hit_ppos = b.ppos[pw];
+            rp.hit_part = b.hit_part;
+            rp.hit_touched = b.hit_touched;
+            SDGR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(b.hit_touched), 0u,
+                                     (plan->pairs_c + 3) / 4, s));
+        }
         if (P.det) {
             SDGR_HIP(launch_fill_u32((uint32_t*)b.part_g, 0u, 6 * plan->pairs_c, s));
             rp.ppos = b.ppos[pw];
@@ -886,7 +940,10 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
                                      b.nlast, b.cbwd, b.grad_c, P.records, s));
         if (P.det)
             SDGR_HIP(launch_reduce_pairs(b.dord, b.poff, P.records, b.status, b.part_g, 6,
-                                         plan->pairs_c, b.grad_c, P.records, s));
+                                         plan->pairs_c, b.grad_c, 1, GC_STRIDE, s));
+        if (b.hits)
+            SDGR_HIP(launch_reduce_touched(b.dord, b.poff, P.records, b.status, b.hit_touched,
+                                           b.hit_part, b.grad_c, s));
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,
@@ -910,6 +967,7 @@ int sdgr_forward_static(const sdgr_scene* scenes, int32_t nscenes, const sdgr_vi
     hipStream_t s = (hipStream_t)stream;
     sdgr_plan plan{};
     if ((rc = count_and_plan(P, base, s, &plan))) return rc;
+    fill_plan(P, plan.pairs_c, plan.pairs_i, &plan, 0);   // forward only: no stored hits
     const size_t sb = (plan.state_bytes + 255) & ~size_t(255);
     const size_t need = qb + sb + plan.fwd_scratch_bytes;
     if (need > STATIC_SCRATCH_BYTES)

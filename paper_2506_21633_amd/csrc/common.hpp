@@ -77,7 +77,9 @@ struct RasterParams {
     // [11] hit groups beyond the first of a batch (batches whose hits
     // overflow the compaction buffer) in pass A forward, backward; [12] rays
     // stopped at tau_max; [13] longest list prefix one tile used; [14], [15]
-    // tiles the pass A backward ran as long and as short lists
+    // tiles the pass A backward ran as long and as short lists; [16], [17]
+    // tiles the pass A backward read from stored hits and re-derived from
+    // the footprint masks
     unsigned long long* work = nullptr;
     // deterministic mode (null = off): every computation-plane pair's
     // position before the pair sort; pass A writes its per-(tile, record)
@@ -86,7 +88,34 @@ struct RasterParams {
     const uint32_t* ppos = nullptr;
     float* part = nullptr;
     int64_t part_stride = 0;
+    // stored hits (null = off): pass A's forward keeps the hits each tile's
+    // rays processed, hit group by hit group, in `hits` (hit_cap 16-byte
+    // units, taken in blocks through the counter at status[ST_HIT_TOP]) as a
+    // chain of records whose last one is hit_tail[tile]; the backward walks
+    // each chain back to front instead of re-deriving the hits from the
+    // footprint masks. A record is three header units (the previous record
+    // or HIT_NONE and the hit count; the list positions / 64 of the batch's
+    // eight chunks) and then one 8-byte word per hit in processing order
+    // (ray-major, each ray front to back): the record id in bits 0..31, the
+    // ray (cell of the tile) in bits 32..37, the entry's slot in the batch
+    // (chunk * 64 + entry) in bits 40..48.
+    uint4* hits = nullptr;
+    uint32_t* hit_tail = nullptr;
+    unsigned long long* hit_top = nullptr;
+    uint32_t hit_cap = 0;
+    // the stored-hit backward's output: per list entry it touched, its six
+    // sums (plain stores at 6 * the pair's position before the pair sort,
+    // hit_ppos) and a mark in hit_touched, added per record afterwards
+    // (launch_reduce_touched), so that no float atomics are needed
+    const uint32_t* hit_ppos = nullptr;
+    float* hit_part = nullptr;
+    unsigned char* hit_touched = nullptr;
 };
+
+constexpr uint32_t HIT_NONE = 0xFFFFFFFFu;       // chain end / a tile with no hits
+constexpr uint32_t HIT_OVERFLOW = 0xFFFFFFFEu;   // the stream was full: backward re-derives
+constexpr uint32_t HIT_HEADER_UNITS = 3;
+constexpr int GC_STRIDE = 8;   // floats per record in the computation-plane gradient sums
 
 // The calling thread's error message of the C ABI (sdgr_last_error): set
 // with a code to return, or cleared at the start of a call.
@@ -98,7 +127,7 @@ constexpr int WORK_WORD = 16;    // work counters live at status + 16
 // by the bit length of the list length, bins[33..65] (after placement) the
 // number of tiles whose list has at least that bit length
 constexpr int WL_BINS_WORD = 64;
-constexpr int WORK_COUNTERS = 16;   // u64 each: status words 16 .. 47
+constexpr int WORK_COUNTERS = 18;   // u64 each: status words 16 .. 51
 
 // Device-side scalars kept at the start of the state buffer.
 enum StatusSlot : int {
@@ -107,6 +136,7 @@ enum StatusSlot : int {
     ST_PAIRS_I = 2,    // imaging-plane pairs of records with nonzero intensity
     ST_WORK_TILES = 4, // non-empty computation-plane tiles in the worklist
     ST_ACTIVE = 5,     // records pass A used (backward list length)
+    ST_HIT_TOP = 6,    // u64 (words 6, 7): 16-byte units of the hit stream taken so far
     ST_COUNT = 8       // u64 pair totals of the projection at status + 8
 };
 
@@ -285,9 +315,11 @@ hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, in
                                 uint32_t* bsum_i, uint32_t* status, uint32_t* active,
                                 hipStream_t s);
 
-// Per-record gradient buffers are plane-major: component k of record r at
-// [k * records + r]; grad_c = (dcx, dcy, da, db, dc, dkappa) on the
-// computation plane, grad_i = (dcx, dcy, da, db, dc, dI) on the imaging plane.
+// Per-record gradient buffers: grad_c = (dcx, dcy, da, db, dc, dkappa) on
+// the computation plane, record-major (component k of record r at
+// [r * GC_STRIDE + k], so that the six sums pass A adds per list entry share
+// one 32-byte sector), and grad_i = (dcx, dcy, da, db, dc, dI) on the imaging
+// plane, plane-major ([k * records + r]).
 hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, int nv,
                                   int nscenes, int64_t scene_items,
                                   const RasterParams& rp, const float* A,
@@ -337,13 +369,19 @@ hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
                                const uint32_t* bscan_c, int64_t cap_c, const uint32_t* status,
                                uint32_t* pkey, uint32_t* pval, uint32_t* seg, uint32_t* dord,
                                uint32_t* poff, hipStream_t s);
-// out[k * out_stride + dord[p]] = sum of part[k * part_stride + i] over the
-// pairs i in [poff[p], poff[p + 1]) in order (the last record's end is
-// status[ST_PAIRS_C]), for every depth rank p < records and k < ncomp.
+// out[k * out_comp + dord[p] * out_rec] = sum of part[k * part_stride + i]
+// over the pairs i in [poff[p], poff[p + 1]) in order (the last record's end
+// is status[ST_PAIRS_C]), for every depth rank p < records and k < ncomp.
 hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64_t records,
                                const uint32_t* status, const float* part, int ncomp,
-                               int64_t part_stride, float* out, int64_t out_stride,
-                               hipStream_t s);
+                               int64_t part_stride, float* out, int64_t out_comp,
+                               int64_t out_rec, hipStream_t s);
+// Sums of the per-pair partials the stored-hit pass A backward wrote:
+// grad_c[dord[p] * GC_STRIDE + k] += the partials part[i * 6 + k] of the
+// pairs i in [poff[p], poff[p + 1]) marked in `touched`, in order.
+hipError_t launch_reduce_touched(const uint32_t* dord, const uint32_t* poff, int64_t records,
+                                 const uint32_t* status, const unsigned char* touched,
+                                 const float* part, float* grad_c, hipStream_t s);
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
                                const uint2* rect_i, const uint32_t* cnt_i,
                                const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i, bool vm,

@@ -372,6 +372,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     constexpr int HKB = NB <= 8 ? 3 : 4;   // bits of a hit's chunk index
     constexpr int HRS = 6 + HKB;           // shift of a hit's ray index
     static_assert(NB <= 16, "hits are packed in 16 bits");
+    static_assert(NB == 8, "stored-hit records carry eight chunk ids");
     __shared__ float4 s_q[NB][WAVE];
     __shared__ float s_wc[NB][WAVE], s_wk[NB][WAVE];   // conic c and extinction
     // per-entry sums in GC copies picked by ray (as in the backward; one
@@ -379,6 +380,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     constexpr int GC = 1;
     __shared__ float s_A[GC][NB][WAVE + 1];
     __shared__ uint64_t s_m[NB][WAVE];
+    __shared__ uint32_t s_r[NB][WAVE];        // record of each entry (stored hits)
     __shared__ uint32_t s_chk[NB];
     __shared__ uint16_t s_hit[WAVE * WAVE];   // (ray, chunk, entry) packed, ray-major
     // per ray during a chunk: first hit in s_hit, optical depth, transmittance,
@@ -408,6 +410,12 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     uint32_t got_prev = 0u;
     uint32_t r_prev[NB], r_cur[NB];   // record of my entry in each chunk
     uint32_t d_prev[NB], d_cur[NB];   // deterministic mode: its pair's position before the sort
+    // stored hits: this tile's chain of batch records (h_on while the stream
+    // has room; h_prev becomes HIT_OVERFLOW when it runs out), the block of
+    // the stream the tile writes into [h_top, h_end) and the block size it
+    // takes next, the current record and its hit count
+    bool h_on = !DET && rp.hits != nullptr;
+    uint32_t h_top = 0u, h_end = 0u, h_blk = 256u, h_prev = HIT_NONE, h_rec = 0u, h_kept = 0u;
     auto flush = [&]() {
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
@@ -487,6 +495,7 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     s_m[k][lane] = m[k];
+                    if (h_on) s_r[k][lane] = r[k];
                     if (lane == k) s_chk[k] = chk[k];
                 }
             }
@@ -513,11 +522,40 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     (int)(wave_excl_scan_u32((uint32_t)__popcll(col[k])) + (uint32_t)__popcll(col[k])),
                     WAVE - 1);
             }
+            if (h_on) {
+                // room for the batch's records, one per hit group (so that no
+                // ray's hits interleave with another group's in a record):
+                // their headers and at most every hit; a new block when the
+                // tile's is short (sizes doubling up to 64 KB, so short tiles
+                // waste little and long ones seldom ask)
+                uint32_t H = 0u;
+#pragma unroll
+                for (int k = 0; k < NB; ++k) H += hk[k];
+                const uint32_t units = NB * (HIT_HEADER_UNITS + 1u) + (H + 1u) / 2u;
+                if (h_end - h_top < units) {
+                    const uint32_t take = max(units, h_blk);
+                    h_blk = min(2u * h_blk, 4096u);
+                    unsigned long long base = 0ull;
+                    if (lane == 0) base = atomicAdd(rp.hit_top, (unsigned long long)take);
+                    base = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane(
+                                (int)(uint32_t)(base >> 32)) << 32) |
+                           (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)base);
+                    if (base + take > (unsigned long long)rp.hit_cap) {
+                        h_on = false;
+                        h_prev = HIT_OVERFLOW;
+                    } else {
+                        h_top = (uint32_t)base;
+                        h_end = h_top + take;
+                    }
+                }
+            }
             // groups of consecutive chunks whose hits fit s_hit; each group's
             // hits are compacted ray-major (chunk by chunk, front to back) and
             // taken 64 per round
             for (int g0 = 0; g0 < nb && live != 0ull;) {
                 ++n_group;
+                h_rec = h_top;
+                h_kept = 0u;
                 int g1 = g0;
                 uint32_t H = 0;
                 bool open = true;
@@ -586,6 +624,17 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                             __ballot(valid && rp.shadowing && !(tr + excl < rp.tau_max));
                         const uint64_t after = stop & (~0ull << seg0);
                         const bool proc = valid && (after == 0ull || lane < __builtin_ctzll(after));
+                        if (h_on) {
+                            // the processed hits, in processing order: record,
+                            // ray and the entry's slot in the batch
+                            const uint64_t kb = __ballot(proc);
+                            if (proc)
+                                reinterpret_cast<unsigned long long*>(
+                                    rp.hits + h_rec + HIT_HEADER_UNITS)[h_kept + lanes_below(kb)] =
+                                    (unsigned long long)s_r[k][j] | ((unsigned long long)rr << 32) |
+                                    ((unsigned long long)(k * WAVE + j) << 40);
+                            h_kept += (uint32_t)__popcll(kb);
+                        }
                         if (proc && real) {
                             // at least FLT_MIN, so that A > 0 marks exactly the
                             // records some ray used (the exact alpha T is > 0
@@ -615,12 +664,22 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
                     live = __ballot(alive);
                     wave_lds_sync();
                 }
+                if (h_on && h_kept > 0u) {   // the group's record
+                    if (lane == 0) rp.hits[h_rec] = make_uint4(h_prev, h_kept, 0u, 0u);
+                    if (lane == 1)
+                        rp.hits[h_rec + 1] = make_uint4(s_chk[0], s_chk[1], s_chk[2], s_chk[3]);
+                    if (lane == 2)
+                        rp.hits[h_rec + 2] = make_uint4(s_chk[4], s_chk[5], s_chk[6], s_chk[7]);
+                    h_prev = h_rec;
+                    h_top = h_rec + HIT_HEADER_UNITS + (h_kept + 1u) / 2u;
+                }
                 g0 = g1;
             }
             wave_lds_sync();
         }
     }
     flush();
+    if (!DET && rp.hits != nullptr && lane == 0) rp.hit_tail[bucket] = h_prev;
     if (rp.work) {
         n_hits = wave_sum_u64(n_hits);
         const uint32_t used = wave_max_u32(last);   // list prefix any ray used
@@ -875,8 +934,9 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
     // c = P dL/dI for pass A (P the record's phase factor)
     cbwd[r] = (prec ? prec[r] : scenes[V.scene].amp[r - V.rec_off] * (float)V.pscale) * dI;
     // pass A backward adds into the record's computation-plane sums
-#pragma unroll
-    for (int k = 0; k < 6; ++k) grad_c[k * records + r] = 0.0f;
+    float4* gc = reinterpret_cast<float4*>(grad_c + r * GC_STRIDE);
+    gc[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    gc[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     if (rp.work) {   // one atomic per wave
 #pragma unroll
@@ -947,6 +1007,8 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
     if (2u * nlong >= ntiles) nlong = ntiles;
     const uint32_t wi = FLUSHER ? blockIdx.x : nlong + blockIdx.x;
     if (wi >= (FLUSHER ? nlong : ntiles)) return;
+    // tiles whose hits the forward stored run in k_raster_a_bwd_hits
+    if (!DET && rp.hits != nullptr && rp.hit_tail[worklist[wi]] != HIT_OVERFLOW) return;
     constexpr uint32_t LAST = 1u << 31;
     if (FLUSHER && threadIdx.x >= WAVE) {
         // the flusher: per hand-off, the six sums of every handed-off entry
@@ -969,7 +1031,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                     }
                     if (v == 0.0f) continue;
                     if constexpr (DET) rp.part[c * rp.part_stride + rk] = v;
-                    else unsafeAtomicAdd(&grad_c[c * stride + rk], v);
+                    else unsafeAtomicAdd(&grad_c[(int64_t)rk * GC_STRIDE + c], v);
                 }
             }
             if (cmd & LAST) return;
@@ -1023,12 +1085,76 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                     s_G[0][0][k][c][lane] = 0.0f;
                     if (v == 0.0f) continue;
                     if constexpr (DET) rp.part[c * rp.part_stride + r_prev[k]] = v;
-                    else unsafeAtomicAdd(&grad_c[c * stride + r_prev[k]], v);
+                    else unsafeAtomicAdd(&grad_c[(int64_t)r_prev[k] * GC_STRIDE + c], v);
                 }
             }
             wave_lds_sync();
         }
         got_prev = 0u;
+    };
+    // One round of up to 64 hits, lane = hit (each ray's hits contiguous,
+    // back to front; `head` marks a ray's first hit in the round, rs is its
+    // state before the round): optical depths and U by segmented scans, the
+    // per-entry gradient sums into LDS, each ray's state after its last hit
+    // back to s_ray.
+    auto hit_round = [&](const uint32_t hv, const bool valid, const bool head, const RayB rs) {
+        const int rr = (int)(hv >> HRS), k = (int)((hv >> 6) & ((1u << HKB) - 1u)),
+                  j = (int)(hv & 63u);
+        const float4 g = s_q[k][j];
+        const float2 g2 = make_float2(s_wc[k][j], s_wk[k][j]);
+        const float cj = s_c[k][j];
+        bool real = false;
+        float x = 0.0f, E = 1.0f, ex = 0.0f, f = 0.0f, dx = 0.0f, dy = 0.0f;
+        float c = 0.0f;
+        if (valid) {
+            dx = x0 + (float)(rr & (TILE - 1)) - g.x;
+            dy = y0 + (float)(rr / TILE) - g.y;
+            const float q = quadform(g, g2.x, dx, dy);
+            if (q < rp.q_max) {
+                real = true;
+                c = cj;
+                ex = __expf(-0.5f * q);
+                f = (ex - rp.eps) * rp.inv1meps;
+                x = g2.y * f;
+                E = __expf(-x);
+            }
+        }
+        const float sx = seg_incl_scan(x, head);   // this and the later hits
+        float sa = E, sb = real ? c * (1.0f - E) : 0.0f;
+        seg_incl_affine(sa, sb, head);
+        float ea = __int_as_float(from_lane_below(__float_as_int(sa)));
+        float eb = __int_as_float(from_lane_below(__float_as_int(sb)));
+        if (head) {
+            ea = 1.0f;
+            eb = 0.0f;
+        }
+        const float tr = valid ? rs.t : 0.0f;
+        const float Ur = valid ? rs.U : 0.0f;
+        if (real) {
+            float dalpha;
+            if (rp.shadowing) {
+                const float Tn = __expf(-fmaxf(tr - sx, 0.0f));
+                dalpha = Tn * (c - (ea * Ur + eb));
+            } else {
+                dalpha = c;
+            }
+            const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
+            const float dq = dxx * g2.y * (-0.5f * ex * rp.inv1meps);
+            const int gc = (rr + (rr >> 3)) & (GC - 1);
+            atomicAdd(&s_G[hb][gc][k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
+            atomicAdd(&s_G[hb][gc][k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
+            atomicAdd(&s_G[hb][gc][k][2][j], dq * dx * dx);
+            atomicAdd(&s_G[hb][gc][k][3][j], 2.0f * dq * dx * dy);
+            atomicAdd(&s_G[hb][gc][k][4][j], dq * dy * dy);
+            atomicAdd(&s_G[hb][gc][k][5][j], dxx * f);
+        }
+        const uint64_t hbits = __ballot(real);
+        if (lane == 0) n_hits += (unsigned long long)__popcll(hbits);
+        const int nxt = from_lane_above(valid ? (int)hv : -1);
+        const bool endseg = valid && (lane == WAVE - 1 || (nxt >> HRS) != rr);
+        wave_lds_sync();
+        if (endseg && rp.shadowing) s_ray[rr] = RayB{rs.o, tr - sx, sa * Ur + sb, 0.0f};
+        wave_lds_sync();
     };
     const int64_t c_first = rg.x / WAVE, c_end = (int64_t)(e_end + WAVE - 1) / WAVE;
     for (int64_t g1 = c_end; g1 > c_first && n_max > 0u; g1 -= WAVE) {
@@ -1179,67 +1305,10 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                         const uint32_t L = base + lane;
                         const bool valid = L < H;
                         const uint32_t hv = valid ? (uint32_t)s_hit[L] : 0u;
-                        const int rr = (int)(hv >> HRS), k = (int)((hv >> 6) & ((1u << HKB) - 1u)),
-                                  j = (int)(hv & 63u);
-                        // ray state and entry record, read together (lanes past
-                        // the last hit read entry 0 of ray 0 and ignore it)
-                        const RayB rs = s_ray[rr];
-                        const float4 g = s_q[k][j];
-                        const float2 g2 = make_float2(s_wc[k][j], s_wk[k][j]);
-                        const float cj = s_c[k][j];
+                        // ray state (lanes past the last hit read ray 0 and ignore it)
+                        const RayB rs = s_ray[hv >> HRS];
                         const int seg0 = valid ? max((int)rs.o - (int)base, 0) : lane;
-                        bool real = false;
-                        float x = 0.0f, E = 1.0f, ex = 0.0f, f = 0.0f, dx = 0.0f, dy = 0.0f;
-                        float c = 0.0f;
-                        if (valid) {
-                            dx = x0 + (float)(rr & (TILE - 1)) - g.x;
-                            dy = y0 + (float)(rr / TILE) - g.y;
-                            const float q = quadform(g, g2.x, dx, dy);
-                            if (q < rp.q_max) {
-                                real = true;
-                                c = cj;
-                                ex = __expf(-0.5f * q);
-                                f = (ex - rp.eps) * rp.inv1meps;
-                                x = g2.y * f;
-                                E = __expf(-x);
-                            }
-                        }
-                        const float sx = seg_incl_scan(x, lane == seg0);   // this and the later hits
-                        float sa = E, sb = real ? c * (1.0f - E) : 0.0f;
-                        seg_incl_affine(sa, sb, lane == seg0);
-                        float ea = __int_as_float(from_lane_below(__float_as_int(sa)));
-                        float eb = __int_as_float(from_lane_below(__float_as_int(sb)));
-                        if (lane == seg0) {
-                            ea = 1.0f;
-                            eb = 0.0f;
-                        }
-                        const float tr = valid ? rs.t : 0.0f;
-                        const float Ur = valid ? rs.U : 0.0f;
-                        if (real) {
-                            float dalpha;
-                            if (rp.shadowing) {
-                                const float Tn = __expf(-fmaxf(tr - sx, 0.0f));
-                                dalpha = Tn * (c - (ea * Ur + eb));
-                            } else {
-                                dalpha = c;
-                            }
-                            const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
-                            const float dq = dxx * g2.y * (-0.5f * ex * rp.inv1meps);
-                            const int gc = (rr + (rr >> 3)) & (GC - 1);
-                            atomicAdd(&s_G[hb][gc][k][0][j], -2.0f * dq * (g.z * dx + g.w * dy));
-                            atomicAdd(&s_G[hb][gc][k][1][j], -2.0f * dq * (g.w * dx + g2.x * dy));
-                            atomicAdd(&s_G[hb][gc][k][2][j], dq * dx * dx);
-                            atomicAdd(&s_G[hb][gc][k][3][j], 2.0f * dq * dx * dy);
-                            atomicAdd(&s_G[hb][gc][k][4][j], dq * dy * dy);
-                            atomicAdd(&s_G[hb][gc][k][5][j], dxx * f);
-                        }
-                        const uint64_t hb = __ballot(real);
-                        if (lane == 0) n_hits += (unsigned long long)__popcll(hb);
-                        const int nxt = from_lane_above(valid ? (int)hv : -1);
-                        const bool endseg = valid && (lane == WAVE - 1 || (nxt >> HRS) != rr);
-                        wave_lds_sync();
-                        if (endseg && rp.shadowing) s_ray[rr] = RayB{rs.o, tr - sx, sa * Ur + sb, 0.0f};
-                        wave_lds_sync();
+                        hit_round(hv, valid, lane == seg0, rs);
                     }
                     {
                         const RayB rs = s_ray[lane];
@@ -1262,7 +1331,276 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
             atomicMax(&rp.work[9], n_batch);
             atomicAdd(&rp.work[11], n_group - n_batch);
             atomicAdd(&rp.work[FLUSHER ? 14 : 15], 1ull);
+            atomicAdd(&rp.work[17], 1ull);
         }
+    }
+}
+
+// Pass A backward over the hits the forward stored (RasterParams::hits).
+// The tile's records are walked back to front, 64 hits a round, each round
+// from the back of one record (one hit group of the forward, so each ray's
+// hits are contiguous and back to front, as the segmented scans need). A
+// hit gathers its list entry's record into registers; loads run ahead of
+// the arithmetic (hit words HB_HIT_AHEAD rounds, records HB_REC_AHEAD
+// rounds). The six gradient terms collect per entry slot of the record in
+// LDS; once per record a second wave, while the first goes on, stores each
+// touched entry's six sums with plain stores at its pair's position before
+// the pair sort and marks it (float atomics, one per sum, would cost
+// several times the whole pass), and launch_reduce_touched adds them per
+// record. Only these sums and the rays' state live in LDS, so many tiles
+// run per CU. Records that do not fit the stream, links that do not go
+// back in it, record ids past the record count and list positions past the
+// pair count end the walk or are skipped, so a stream that holds anything
+// else cannot send the kernel out of bounds.
+constexpr int HB_HIT_AHEAD = 4, HB_REC_AHEAD = 2;
+constexpr int HB_SLOTS = 8 * WAVE;   // entry slots of a record (chunks x entries)
+
+__device__ __forceinline__ unsigned long long uniform_u64(unsigned long long v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__global__ void __launch_bounds__(2 * WAVE)
+k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
+                    const uint32_t* __restrict__ status, const uint32_t* __restrict__ worklist,
+                    const CRec* __restrict__ crec, const float* __restrict__ tau,
+                    const float* __restrict__ cbwd, float* __restrict__ grad_c, int64_t stride)
+{
+    // two buffers of per-slot sums and the record of each touched slot
+    // (HIT_NONE: untouched); the flusher empties one while the main wave
+    // fills the other
+    __shared__ float s_G[2][6][HB_SLOTS];
+    __shared__ uint32_t s_rec[2][HB_SLOTS];
+    __shared__ uint32_t s_last[2], s_hrec[2];   // per hand-off: last one?, the stream record
+    __shared__ float2 s_ray[WAVE];   // per ray: optical depth, U
+    if (blockIdx.x >= status[ST_WORK_TILES]) return;
+    const int64_t bucket = worklist[blockIdx.x];
+    const uint32_t tail = rp.hit_tail[bucket];
+    if (tail == HIT_OVERFLOW) return;   // k_raster_a_bwd re-derives this tile's hits
+    for (int i = threadIdx.x; i < 2 * HB_SLOTS; i += 2 * WAVE) {
+        (&s_rec[0][0])[i] = HIT_NONE;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s_G[i / HB_SLOTS][c][i % HB_SLOTS] = 0.0f;
+    }
+    __syncthreads();
+    if (threadIdx.x >= WAVE) {
+        // the flusher: per hand-off, each touched slot's sums to its pair's
+        // partial (slot = chunk * 64 + entry; the record's header holds the
+        // chunks' list positions), and the buffer cleared for reuse
+        const int fl = threadIdx.x - WAVE;
+        const uint32_t kc = status[ST_PAIRS_C];
+        const uint32_t* hw32 = reinterpret_cast<const uint32_t*>(rp.hits);
+        for (int fb = 0;; fb ^= 1) {
+            __syncthreads();
+            const uint32_t hr = s_hrec[fb];
+            const uint32_t chw = hr != HIT_NONE && fl < 8 ? hw32[((uint64_t)hr + 1) * 4 + fl] : 0u;
+#pragma unroll
+            for (int i = 0; i < HB_SLOTS / WAVE; ++i) {
+                const int sl = i * WAVE + fl;
+                const uint32_t rk = s_rec[fb][sl];
+                const uint32_t pos = (uint32_t)__builtin_amdgcn_readlane((int)chw, i) * WAVE + fl;
+                if (rk == HIT_NONE) continue;
+                s_rec[fb][sl] = HIT_NONE;
+                float v[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    v[c] = s_G[fb][c][sl];
+                    s_G[fb][c][sl] = 0.0f;
+                }
+                if (pos >= kc) continue;
+                const uint32_t pp = rp.hit_ppos[pos];
+                if (pp >= kc) continue;
+                float2* dst = reinterpret_cast<float2*>(rp.hit_part + (uint64_t)pp * 6);
+                dst[0] = make_float2(v[0], v[1]);
+                dst[1] = make_float2(v[2], v[3]);
+                dst[2] = make_float2(v[4], v[5]);
+                rp.hit_touched[pp] = 1;
+            }
+            if (s_last[fb]) return;
+        }
+    }
+    const int lane = threadIdx.x;
+    const TileCell tc = tile_cell(views, nv, bucket, true);
+    const DevView& V = views[tc.v];
+    const uint32_t rec0 = (uint32_t)V.rec_off;   // read by lanes without a hit
+    const float x0 = (float)(tc.tx * TILE) + 0.5f, y0 = (float)(tc.ty * TILE) + 0.5f;
+    const int64_t ray = V.ray_off + (int64_t)tc.row * V.Wc + tc.col;
+    s_ray[lane] = make_float2(tc.inside ? tau[ray] : 0.0f, 0.0f);
+    const unsigned long long* hw = reinterpret_cast<const unsigned long long*>(rp.hits);
+    const uint64_t cap = rp.hit_cap;
+    unsigned long long n_iter = 0, n_hits = 0, n_batch = 0;   // work counters
+
+    // the cursor (wave-uniform): the record rounds are taken from, its hits
+    // not yet taken, the record before it and that one's header, loaded
+    // when the cursor enters a record
+    uint32_t cur = HIT_NONE, left = 0u, prev = HIT_NONE;
+    unsigned long long pend = 0ull;
+    auto enter = [&](uint32_t r, unsigned long long h) {
+        const uint32_t kept = (uint32_t)(h >> 32), pv = (uint32_t)h;
+        if (kept == 0u || (uint64_t)r + HIT_HEADER_UNITS + (kept + 1u) / 2u > cap) {
+            cur = HIT_NONE;
+            return;
+        }
+        ++n_batch;
+        cur = r;
+        left = kept;
+        prev = pv < r ? pv : HIT_NONE;
+        if (prev != HIT_NONE) pend = hw[(uint64_t)prev * 2];
+    };
+    // the next round: index of its first hit word in the stream, its hit
+    // count (0 once the chain is done; lane i takes word base + n - 1 - i),
+    // whether it ends its record and the record
+    auto next = [&](uint64_t& base, uint32_t& n, bool& last, uint32_t& rec) {
+        if (cur != HIT_NONE && left == 0u) {
+            if (prev == HIT_NONE) cur = HIT_NONE;
+            else enter(prev, uniform_u64(pend));
+        }
+        rec = cur;
+        if (cur == HIT_NONE) {
+            base = 0;
+            n = 0u;
+            last = true;
+            return;
+        }
+        n = min(left, (uint32_t)WAVE);
+        left -= n;
+        base = ((uint64_t)cur + HIT_HEADER_UNITS) * 2 + left;
+        last = left == 0u;
+    };
+    if ((uint64_t)tail + HIT_HEADER_UNITS <= cap) enter(tail, uniform_u64(hw[(uint64_t)tail * 2]));
+
+    struct Rec { float4 q; float2 w; float c; };
+    auto load_hit = [&](uint64_t base, uint32_t n) {
+        return (uint32_t)lane < n ? hw[base + n - 1u - (uint32_t)lane] : 0ull;
+    };
+    auto gather = [&](unsigned long long h, uint32_t n) {
+        const uint32_t id = (uint32_t)h;
+        const uint32_t rk = ((uint32_t)lane < n && (int64_t)id < stride) ? id : rec0;
+        Rec g;
+        g.q = crec[rk].q;
+        const float4 w = crec[rk].w;
+        g.w = make_float2(w.x, w.y);
+        g.c = cbwd[rk];
+        return g;
+    };
+    uint64_t b[HB_HIT_AHEAD + 1];
+    uint32_t nn[HB_HIT_AHEAD + 1];
+    bool ends[HB_HIT_AHEAD + 1];
+    uint32_t rc[HB_HIT_AHEAD + 1];
+    unsigned long long h[HB_HIT_AHEAD + 1];
+    Rec g[HB_REC_AHEAD + 1];
+#pragma unroll
+    for (int i = 0; i <= HB_HIT_AHEAD; ++i) {
+        next(b[i], nn[i], ends[i], rc[i]);
+        h[i] = load_hit(b[i], nn[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < HB_REC_AHEAD; ++i) g[i] = gather(h[i], nn[i]);
+    wave_lds_sync();
+    int hb = 0;   // buffer the current record's sums go to
+    while (nn[0] > 0u) {
+        ++n_iter;
+        g[HB_REC_AHEAD] = gather(h[HB_REC_AHEAD], nn[HB_REC_AHEAD]);
+        // the round: lane = hit, each ray's hits back to front
+        const bool valid = (uint32_t)lane < nn[0];
+        const uint32_t id = (uint32_t)h[0];
+        const int rr = valid ? (int)((h[0] >> 32) & (uint64_t)(WAVE - 1)) : 0;
+        const int sl = (int)((h[0] >> 40) & (uint64_t)(HB_SLOTS - 1));
+        const float2 rs = s_ray[rr];
+        // the neighbours' rays, read by every lane (a cross-lane read inside
+        // a condition would see the lanes it skips as zero)
+        const int key = valid ? rr : -1;
+        const int below = from_lane_below(key), above = from_lane_above(key);
+        const bool head = !valid || lane == 0 || below != rr;
+        const float4 q = g[0].q;
+        const float2 w = g[0].w;   // conic c, extinction
+        bool real = false;
+        float x = 0.0f, E = 1.0f, ex = 0.0f, f = 0.0f, dx = 0.0f, dy = 0.0f, c = 0.0f;
+        if (valid && (int64_t)id < stride) {
+            dx = x0 + (float)(rr & (TILE - 1)) - q.x;
+            dy = y0 + (float)(rr / TILE) - q.y;
+            const float qf = quadform(q, w.x, dx, dy);
+            if (qf < rp.q_max) {
+                real = true;
+                c = g[0].c;
+                ex = __expf(-0.5f * qf);
+                f = (ex - rp.eps) * rp.inv1meps;
+                x = w.y * f;
+                E = __expf(-x);
+            }
+        }
+        const float sx = seg_incl_scan(x, head);   // this and the later hits
+        float sa = E, sb = real ? c * (1.0f - E) : 0.0f;
+        seg_incl_affine(sa, sb, head);
+        float ea = __int_as_float(from_lane_below(__float_as_int(sa)));
+        float eb = __int_as_float(from_lane_below(__float_as_int(sb)));
+        if (head) {
+            ea = 1.0f;
+            eb = 0.0f;
+        }
+        const float tr = valid ? rs.x : 0.0f;
+        const float Ur = valid ? rs.y : 0.0f;
+        if (real) {
+            float dalpha;
+            if (rp.shadowing) {
+                const float Tn = __expf(-fmaxf(tr - sx, 0.0f));
+                dalpha = Tn * (c - (ea * Ur + eb));
+            } else {
+                dalpha = c;
+            }
+            const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
+            const float dq = dxx * w.y * (-0.5f * ex * rp.inv1meps);
+            s_rec[hb][sl] = id;
+            atomicAdd(&s_G[hb][0][sl], -2.0f * dq * (q.z * dx + q.w * dy));
+            atomicAdd(&s_G[hb][1][sl], -2.0f * dq * (q.w * dx + w.x * dy));
+            atomicAdd(&s_G[hb][2][sl], dq * dx * dx);
+            atomicAdd(&s_G[hb][3][sl], 2.0f * dq * dx * dy);
+            atomicAdd(&s_G[hb][4][sl], dq * dy * dy);
+            atomicAdd(&s_G[hb][5][sl], dxx * f);
+        }
+        const uint64_t hbits = __ballot(real);
+        if (lane == 0) n_hits += (unsigned long long)__popcll(hbits);
+        const bool endseg = valid && (lane == WAVE - 1 || above != rr);
+        wave_lds_sync();
+        if (endseg && rp.shadowing) s_ray[rr] = make_float2(tr - sx, sa * Ur + sb);
+        wave_lds_sync();
+        if (ends[0]) {
+            // the record's sums to the flusher (the barrier also returns the
+            // buffer it emptied last)
+            if (lane == 0) {
+                s_last[hb] = nn[1] == 0u ? 1u : 0u;
+                s_hrec[hb] = rc[0];
+            }
+            __syncthreads();
+            hb ^= 1;
+        }
+#pragma unroll
+        for (int i = 0; i < HB_HIT_AHEAD; ++i) {
+            b[i] = b[i + 1];
+            nn[i] = nn[i + 1];
+            ends[i] = ends[i + 1];
+            rc[i] = rc[i + 1];
+            h[i] = h[i + 1];
+        }
+#pragma unroll
+        for (int i = 0; i < HB_REC_AHEAD; ++i) g[i] = g[i + 1];
+        next(b[HB_HIT_AHEAD], nn[HB_HIT_AHEAD], ends[HB_HIT_AHEAD], rc[HB_HIT_AHEAD]);
+        h[HB_HIT_AHEAD] = load_hit(b[HB_HIT_AHEAD], nn[HB_HIT_AHEAD]);
+    }
+    if (n_iter == 0) {   // no round: release the flusher
+        if (lane == 0) {
+            s_last[hb] = 1u;
+            s_hrec[hb] = HIT_NONE;
+        }
+        __syncthreads();
+    }
+    if (rp.work && lane == 0) {
+        atomicAdd(&rp.work[5], n_iter);
+        atomicAdd(&rp.work[1], n_hits);
+        atomicMax(&rp.work[9], n_batch);
+        atomicAdd(&rp.work[16], 1ull);
     }
 }
 
@@ -1413,7 +1751,11 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                float* grad_c, int64_t stride, hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
-    // long lists (the front of the worklist), then the short ones
+    // tiles with stored hits, then the others: long lists (the front of the
+    // worklist), then the short ones
+    if (rp.hits && !rp.ppos)
+        hipLaunchKernelGGL(k_raster_a_bwd_hits, dim3((unsigned)tiles_c), dim3(2 * WAVE), 0, s, views,
+                           nv, rp, status, worklist, crec, tau, cbwd, grad_c, stride);
     auto two = [&](auto det) {
         constexpr bool D = decltype(det)::value;
         hipLaunchKernelGGL((k_raster_a_bwd<true, D>), dim3((unsigned)tiles_c), dim3(2 * WAVE), 0,

@@ -796,7 +796,7 @@ __global__ void __launch_bounds__(256)
 k_reduce_pairs(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ poff,
                int64_t records, const uint32_t* __restrict__ status,
                const float* __restrict__ part, int ncomp, int64_t part_stride,
-               float* __restrict__ out, int64_t out_stride)
+               float* __restrict__ out, int64_t out_comp, int64_t out_rec)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= records || status[ST_OVERFLOW]) return;
@@ -808,8 +808,43 @@ k_reduce_pairs(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ p
         const float* src = part + (int64_t)k * part_stride;
         float acc = 0.0f;
         for (uint32_t i = lo; i < hi; ++i) acc += src[i];
-        out[(int64_t)k * out_stride + r] = acc;
+        out[(int64_t)k * out_comp + (int64_t)r * out_rec] = acc;
     }
+}
+
+// The stored-hit pass A backward's per-pair partials, thread = depth rank
+// p: the pairs [poff[p], next) of its record that the backward touched,
+// added in list order to the record's computation-plane sums (which already
+// hold the atomics of tiles whose hits were re-derived). Skipped after a
+// pair overflow, as above.
+__global__ void __launch_bounds__(256)
+k_reduce_touched(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ poff,
+                 int64_t records, const uint32_t* __restrict__ status,
+                 const unsigned char* __restrict__ touched, const float* __restrict__ part,
+                 float* __restrict__ grad_c)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= records || status[ST_OVERFLOW]) return;
+    const uint32_t kc = status[ST_PAIRS_C];
+    const uint32_t lo = min(poff[p], kc);
+    const uint32_t hi = p + 1 < records ? min(poff[p + 1], kc) : kc;
+    float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    bool any = false;
+    for (uint32_t i = lo; i < hi; ++i) {
+        if (!touched[i]) continue;
+        any = true;
+        const float2* src = reinterpret_cast<const float2*>(part + (uint64_t)i * 6);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float2 v = src[k];
+            acc[2 * k] += v.x;
+            acc[2 * k + 1] += v.y;
+        }
+    }
+    if (!any) return;
+    float* g = grad_c + (int64_t)dord[p] * GC_STRIDE;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g[k] += acc[k];
 }
 
 // Imaging-plane tile ranges (deterministic pass B): runs of equal keys in
@@ -1027,12 +1062,22 @@ hipError_t launch_emit_pairs_c(const DevView* views, int nv, int64_t records,
 
 hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64_t records,
                                const uint32_t* status, const float* part, int ncomp,
-                               int64_t part_stride, float* out, int64_t out_stride,
-                               hipStream_t s)
+                               int64_t part_stride, float* out, int64_t out_comp,
+                               int64_t out_rec, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_reduce_pairs, dim3(grid256(records)), dim3(256), 0, s, dord, poff,
-                       records, status, part, ncomp, part_stride, out, out_stride);
+                       records, status, part, ncomp, part_stride, out, out_comp, out_rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_touched(const uint32_t* dord, const uint32_t* poff, int64_t records,
+                                 const uint32_t* status, const unsigned char* touched,
+                                 const float* part, float* grad_c, hipStream_t s)
+{
+    if (records <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_touched, dim3(grid256(records)), dim3(256), 0, s, dord, poff,
+                       records, status, touched, part, grad_c);
     return hipGetLastError();
 }
 

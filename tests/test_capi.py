@@ -230,6 +230,37 @@ def test_forward_rejects_plan_with_short_workspaces():
     assert rc == C.SDGR_EWORKSPACE
 
 
+def test_plan_stored_hit_stream():
+    """The stream in which the forward keeps each tile's used hits for the
+    backward: 8 bytes per computation-plane pair plus 16 MiB by default, none
+    in recompute or deterministic mode; a caller may lower it (down to 0)
+    but not make it negative or larger than its state holds; a resize takes
+    the default for the new capacities."""
+    L = C.lib()
+    sc, views, o = _args(nv=3)
+    p = C.Plan()
+    C.check(L.sdgr_plan_host(sc, 1, views, 3, ctypes.byref(o), 5000, 700, ctypes.byref(p)))
+    assert p.hit_bytes == 8 * 5000 + (16 << 20)
+
+    def forward_rc(plan):   # stops at the null workspaces once the plan is accepted
+        return L.sdgr_forward(sc, 1, views, 3, ctypes.byref(o), ctypes.byref(plan), None, None,
+                              None, None)
+    q = C.Plan()
+    for hb, rc in ((0, C.SDGR_EINVAL), (4096, C.SDGR_EINVAL), (-16, C.SDGR_EINVAL),
+                   (p.hit_bytes + (1 << 30), C.SDGR_EWORKSPACE)):
+        ctypes.pointer(q)[0] = p
+        q.hit_bytes = hb
+        assert forward_rc(q) == rc, hb
+        assert (b"workspace" in L.sdgr_last_error()) == (hb >= 0), hb
+    C.check(L.sdgr_plan_resize(ctypes.byref(p), 10000, 700))
+    assert p.hit_bytes == 8 * 10000 + (16 << 20)
+    for field in ("recompute", "deterministic"):
+        _, _, o2 = _args(nv=3)
+        setattr(o2, field, 1)
+        C.check(L.sdgr_plan_host(sc, 1, views, 3, ctypes.byref(o2), 5000, 700, ctypes.byref(q)))
+        assert q.hit_bytes == 0, field
+
+
 # ---------------------------------------------------- reconstruction loop
 
 def test_adam_rejects_bad_arguments():

@@ -82,15 +82,20 @@ def dense_scene(seed, n, half, smin, smax, kmin, kmax):
         rng.uniform(kmin, kmax, n).astype(np.float32))
 
 
-def gpu_run(scene, views, G, options, cuda, view_ids=None):
+def gpu_run(scene, views, G, options, cuda, view_ids=None, hit_bytes=None):
     """Forward + backward of `views` in one launch with the work counters
-    on; returns images, A [V, n], gradients, counters."""
+    on; returns images, A [V, n], gradients, counters. hit_bytes: the
+    plan's stored-hit stream, lowered from its default."""
     A_ = api()
     g = A_.GaussianTensors.from_numpy(scene, cuda)
     r = A_.Renderer([g], views, options)
     A_.count_work(True)
     try:
-        res = r.forward()
+        plan = r.plan()
+        if hit_bytes is not None:
+            assert 0 <= hit_bytes <= plan.hit_bytes
+            plan.hit_bytes = hit_bytes
+        res = r.forward(plan)
         flat = np.zeros(int(res.plan.image_floats), np.float32)
         for v, Gv in (G.items() if isinstance(G, dict) else enumerate(G)):
             off, h, w = res.shapes[v]
@@ -137,16 +142,23 @@ def check_report(report):
             assert val <= IMG_ELEM, (k, val)
 
 
-def check_deep_paths(work, bwd_groups=True):
+def check_deep_paths(work, bwd_groups=True, stored=True):
     # several batches of 8 list chunks in one tile, batches split into hit
     # groups, rays stopped at the optical-depth cut-off, the long-list
-    # backward kernel
+    # backward kernel; the backward over the forward's stored hits (or, in
+    # recompute and deterministic mode, over hits re-derived from the masks)
     assert work["max_batches_a_fwd"] >= 2 and work["max_batches_a_bwd"] >= 2, work
+    # the re-derived tiles run as long or short lists
+    rederived = work["tiles_a_bwd_long"] + work["tiles_a_bwd_short"]
+    assert work["tiles_a_bwd_rederived"] == rederived, work
+    if stored:
+        assert work["tiles_a_bwd_stored"] > 0, work
+    else:
+        assert work["tiles_a_bwd_stored"] == 0 and work["tiles_a_bwd_long"] > 0, work
     assert work["extra_hit_groups_a_fwd"] > 0, work
-    assert work["extra_hit_groups_a_bwd"] > 0 or not bwd_groups, work
+    assert work["extra_hit_groups_a_bwd"] > 0 or not bwd_groups or stored, work
     assert work["rays_stopped_tau_max"] > 0, work
     assert work["max_list_prefix_a"] > 2048, work
-    assert work["tiles_a_bwd_long"] > 0, work
 
 
 # --------------------------------------------------------- dense small scenes
@@ -180,7 +192,37 @@ def test_dense_lists_elementwise(cuda, kappa, recompute, deterministic):
     check_report(report)
     # the backward's batches overflow the compaction buffer only where rays
     # walk deep (thin extinction)
-    check_deep_paths(out["work"], bwd_groups=kappa[1] < 1.0)
+    check_deep_paths(out["work"], bwd_groups=kappa[1] < 1.0,
+                     stored=not (recompute or deterministic))
+
+
+@pytest.mark.parametrize("kappa", [(0.05, 0.3), (1.0, 4.0)])
+def test_stored_hits_match_rederived(cuda, kappa):
+    """The backward over the forward's stored hits, over hits re-derived from
+    the footprint masks (an empty stream), and with a stream too small for
+    every tile (tiles that run out mid-list fall back; their partial chains
+    are ignored): the same A, images and gradients up to float rounding."""
+    sc = dense_scene(61, 20_000, 0.6, 0.02, 0.1, *kappa)
+    rng = scenes.make_rng(63)
+    G = [rng.standard_normal((64, 64)) for _ in DENSE_VIEWS]
+    opts = api().RenderOptions()
+    full = gpu_run(sc, DENSE_VIEWS, G, opts, cuda)
+    none = gpu_run(sc, DENSE_VIEWS, G, opts, cuda, hit_bytes=0)
+    # the stored hits include every real hit (2 bytes each): half of their
+    # bytes cannot hold them all, so at least one tile runs out
+    short = gpu_run(sc, DENSE_VIEWS, G, opts, cuda, hit_bytes=int(full["work"]["hits_a_bwd"]))
+    w = {k: (r["work"]["tiles_a_bwd_stored"], r["work"]["tiles_a_bwd_rederived"])
+         for k, r in (("full", full), ("none", none), ("short", short))}
+    print(f"\nkappa={kappa} (stored, re-derived) tiles: {w}")
+    assert w["full"][0] > 0 and w["none"][0] == 0 and w["short"][1] > 0, w
+    for k in ("none", "short"):
+        other = none if k == "none" else short
+        assert other["work"]["hits_a_bwd"] == full["work"]["hits_a_bwd"], k
+        for v in range(len(DENSE_VIEWS)):
+            assert elem_err(other["A"][v], full["A"][v]) <= 1e-6, (k, v)
+            assert elem_err(other["images"][v], full["images"][v]) <= 1e-6, (k, v)
+        for name in GROUPS:
+            assert elem_err(other["grads"][name], full["grads"][name]) <= 1e-5, (k, name)
 
 
 # ---------------------------------------- headline workload, one view's gradient
@@ -213,7 +255,9 @@ def test_vehicle_view_gradient_elementwise(cuda, vehicle_ref, recompute):
     grad_report(out, g_ref, *near_cutoff([aux]), report)
     print(f"\nvehicle view {VIEW} recompute={recompute}: {report} work={out['work']}")
     check_report(report)
-    check_deep_paths(out["work"], bwd_groups=False)
+    check_deep_paths(out["work"], bwd_groups=False, stored=not recompute)
+    if not recompute:   # the default stream holds every tile's hits
+        assert out["work"]["tiles_a_bwd_rederived"] == 0, out["work"]
 
 
 @pytest.mark.timeout(900)
