@@ -935,15 +935,19 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
             rp.part = b.part_g;
             rp.part_stride = plan->pairs_c;
         }
+        // stored hits first (their sums are stored, not added), then the
+        // tiles whose hits are re-derived (atomics)
+        SDGR_HIP(launch_raster_a_bwd_hits(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
+                                          b.crec, b.tau, b.cbwd, b.grad_c, P.records, s));
+        if (b.hits)
+            SDGR_HIP(launch_reduce_touched(b.dord, b.poff, P.records, b.status,
+                                           b.hit_touched, b.hit_part, b.grad_c, s));
         SDGR_HIP(launch_raster_a_bwd(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
                                      b.ranges, b.pval[pw], b.pmask, b.psum, b.crec, b.tau,
                                      b.nlast, b.cbwd, b.grad_c, P.records, s));
         if (P.det)
             SDGR_HIP(launch_reduce_pairs(b.dord, b.poff, P.records, b.status, b.part_g, 6,
                                          plan->pairs_c, b.grad_c, 1, GC_STRIDE, s));
-        if (b.hits)
-            SDGR_HIP(launch_reduce_touched(b.dord, b.poff, P.records, b.status, b.hit_touched,
-                                           b.hit_part, b.grad_c, s));
     }
     StageTimer t(SG_PARAMS_BWD, s);
     SDGR_HIP(launch_params_backward(b.views, b.scenes, P.nv, P.ns, P.items, P.rp, b.A,

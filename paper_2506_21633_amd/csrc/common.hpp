@@ -59,7 +59,7 @@ struct DevScene {
 // the extinction kappa, padded to a full 32-byte write.
 struct alignas(32) CRec {
     float4 q;   // cx, cy, a, b
-    float4 w;   // c, kappa, 0, 0
+    float4 w;   // c, kappa, the record's tile count (bits of a uint32), 0
 };
 
 struct RasterParams {
@@ -377,8 +377,9 @@ hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64
                                int64_t part_stride, float* out, int64_t out_comp,
                                int64_t out_rec, hipStream_t s);
 // Sums of the per-pair partials the stored-hit pass A backward wrote:
-// grad_c[dord[p] * GC_STRIDE + k] += the partials part[i * 6 + k] of the
-// pairs i in [poff[p], poff[p + 1]) marked in `touched`, in order.
+// grad_c[dord[p] * GC_STRIDE + k] = the sum of the partials part[i * 6 + k]
+// of the pairs i in [poff[p], poff[p + 1]) marked in `touched`, in order
+// (records with none are left alone).
 hipError_t launch_reduce_touched(const uint32_t* dord, const uint32_t* poff, int64_t records,
                                  const uint32_t* status, const unsigned char* touched,
                                  const float* part, float* grad_c, hipStream_t s);
@@ -425,6 +426,14 @@ hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv
                             const uint32_t* active, const float4* iq, const float2* iw,
                             const float* prec, const float* dimg, float* grad_i, float* cbwd,
                             float* grad_c, hipStream_t s);
+// the tiles with stored hits (rp.hits): per-pair partials, and the sums of
+// records with one tile
+hipError_t launch_raster_a_bwd_hits(const DevView* views, int nv, int64_t tiles_c,
+                                    const RasterParams& rp, const uint32_t* status,
+                                    const uint32_t* worklist, const CRec* crec,
+                                    const float* tau, const float* cbwd, float* grad_c,
+                                    int64_t stride, hipStream_t s);
+// the other tiles (all without stored hits), adding into grad_c with atomics
 hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,

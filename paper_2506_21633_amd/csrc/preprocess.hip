@@ -245,7 +245,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
             float4 vc_q = make_float4(0.f, 0.f, 0.f, 0.f), vi_q = vc_q;
             float2 vc_w = make_float2(0.f, 0.f), vi_w = vc_w;
             uint2 rc = make_uint2(0, 0), ri = make_uint2(0, 0);
-            uint32_t zbits = 0u;
+            uint32_t zbits = 0u, ntc = 0u;
             if (valid) {
                 const float ex[3] = {(float)V.ex[0], (float)V.ex[1], (float)V.ex[2]};
                 const float ey[3] = {(float)V.ey[0], (float)V.ey[1], (float)V.ey[2]};
@@ -260,7 +260,8 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
                     const double zr = range_coordinate(V.ez, m0, m1, m2);
                     const float cCx = xr * iAc + (float)V.hWc, cCy = yr * iEc + (float)V.hHc;
                     const float cIx = xr * iA + (float)V.hW, cIy = (float)zr * iR + (float)V.hH;
-                    nc += tile_rect(cCx, cCy, C.sxx, C.syy, rp.q_max, V.Wc, V.Hc, &rc);
+                    ntc = tile_rect(cCx, cCy, C.sxx, C.syy, rp.q_max, V.Wc, V.Hc, &rc);
+                    nc += ntc;
                     ni += tile_rect(cIx, cIy, I.sxx, I.syy, rp.q_max, V.W, V.H, &ri);
                     zbits = __float_as_uint(__double2float_rn(zr));
                     if (zbits == 0x80000000u) zbits = 0u;   // -0 -> +0
@@ -286,7 +287,7 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
                 prec[r] = P * (float)V.pscale;
             }
             if (write_records) {
-                crec[r] = CRec{vc_q, make_float4(vc_w.x, vc_w.y, 0.0f, 0.0f)};
+                crec[r] = CRec{vc_q, make_float4(vc_w.x, vc_w.y, __uint_as_float(ntc), 0.0f)};
                 iq[r] = vi_q;
                 iw[r] = vi_w;
                 rect_c[r] = rc;

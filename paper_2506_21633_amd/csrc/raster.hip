@@ -1345,9 +1345,10 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
 // rounds). The six gradient terms collect per entry slot of the record in
 // LDS; once per record a second wave, while the first goes on, stores each
 // touched entry's six sums with plain stores at its pair's position before
-// the pair sort and marks it (float atomics, one per sum, would cost
-// several times the whole pass), and launch_reduce_touched adds them per
-// record. Only these sums and the rays' state live in LDS, so many tiles
+// the pair sort and marks it, and launch_reduce_touched adds them per
+// record (float atomics, one per sum, would cost several times the whole
+// pass); an entry whose record has no other tile stores its sums as the
+// record's directly. Only these sums and the rays' state live in LDS, so many tiles
 // run per CU. Records that do not fit the stream, links that do not go
 // back in it, record ids past the record count and list positions past the
 // pair count end the walk or are skipped, so a stream that holds anything
@@ -1373,6 +1374,7 @@ k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
     // fills the other
     __shared__ float s_G[2][6][HB_SLOTS];
     __shared__ uint32_t s_rec[2][HB_SLOTS];
+    __shared__ unsigned char s_one[2][HB_SLOTS];   // the record has only this tile
     __shared__ uint32_t s_last[2], s_hrec[2];   // per hand-off: last one?, the stream record
     __shared__ float2 s_ray[WAVE];   // per ray: optical depth, U
     if (blockIdx.x >= status[ST_WORK_TILES]) return;
@@ -1408,6 +1410,12 @@ k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
                 for (int c = 0; c < 6; ++c) {
                     v[c] = s_G[fb][c][sl];
                     s_G[fb][c][sl] = 0.0f;
+                }
+                if (s_one[fb][sl]) {   // no other tile adds to this record
+                    float* g = grad_c + (int64_t)rk * GC_STRIDE;
+                    reinterpret_cast<float4*>(g)[0] = make_float4(v[0], v[1], v[2], v[3]);
+                    reinterpret_cast<float2*>(g)[2] = make_float2(v[4], v[5]);
+                    continue;
                 }
                 if (pos >= kc) continue;
                 const uint32_t pp = rp.hit_ppos[pos];
@@ -1471,7 +1479,7 @@ k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
     };
     if ((uint64_t)tail + HIT_HEADER_UNITS <= cap) enter(tail, uniform_u64(hw[(uint64_t)tail * 2]));
 
-    struct Rec { float4 q; float2 w; float c; };
+    struct Rec { float4 q; float2 w; float c; bool one; };
     auto load_hit = [&](uint64_t base, uint32_t n) {
         return (uint32_t)lane < n ? hw[base + n - 1u - (uint32_t)lane] : 0ull;
     };
@@ -1482,6 +1490,7 @@ k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
         g.q = crec[rk].q;
         const float4 w = crec[rk].w;
         g.w = make_float2(w.x, w.y);
+        g.one = __float_as_uint(w.z) == 1u;
         g.c = cbwd[rk];
         return g;
     };
@@ -1553,6 +1562,7 @@ k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
             const float dxx = dalpha * E;   // d alpha / d x = exp(-x)
             const float dq = dxx * w.y * (-0.5f * ex * rp.inv1meps);
             s_rec[hb][sl] = id;
+            s_one[hb][sl] = g[0].one ? 1 : 0;
             atomicAdd(&s_G[hb][0][sl], -2.0f * dq * (q.z * dx + q.w * dy));
             atomicAdd(&s_G[hb][1][sl], -2.0f * dq * (q.w * dx + w.x * dy));
             atomicAdd(&s_G[hb][2][sl], dq * dx * dx);
@@ -1742,6 +1752,18 @@ hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv
     return hipGetLastError();
 }
 
+hipError_t launch_raster_a_bwd_hits(const DevView* views, int nv, int64_t tiles_c,
+                                    const RasterParams& rp, const uint32_t* status,
+                                    const uint32_t* worklist, const CRec* crec,
+                                    const float* tau, const float* cbwd, float* grad_c,
+                                    int64_t stride, hipStream_t s)
+{
+    if (tiles_c <= 0 || !rp.hits || rp.ppos) return hipSuccess;
+    hipLaunchKernelGGL(k_raster_a_bwd_hits, dim3((unsigned)tiles_c), dim3(2 * WAVE), 0, s, views,
+                       nv, rp, status, worklist, crec, tau, cbwd, grad_c, stride);
+    return hipGetLastError();
+}
+
 hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
@@ -1751,11 +1773,7 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                float* grad_c, int64_t stride, hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
-    // tiles with stored hits, then the others: long lists (the front of the
-    // worklist), then the short ones
-    if (rp.hits && !rp.ppos)
-        hipLaunchKernelGGL(k_raster_a_bwd_hits, dim3((unsigned)tiles_c), dim3(2 * WAVE), 0, s, views,
-                           nv, rp, status, worklist, crec, tau, cbwd, grad_c, stride);
+    // long lists (the front of the worklist), then the short ones
     auto two = [&](auto det) {
         constexpr bool D = decltype(det)::value;
         hipLaunchKernelGGL((k_raster_a_bwd<true, D>), dim3((unsigned)tiles_c), dim3(2 * WAVE), 0,

@@ -814,9 +814,9 @@ k_reduce_pairs(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ p
 
 // The stored-hit pass A backward's per-pair partials, thread = depth rank
 // p: the pairs [poff[p], next) of its record that the backward touched,
-// added in list order to the record's computation-plane sums (which already
-// hold the atomics of tiles whose hits were re-derived). Skipped after a
-// pair overflow, as above.
+// summed in list order into the record's computation-plane sums (stored,
+// not added: this runs before the tiles whose hits are re-derived add
+// theirs with atomics). Skipped after a pair overflow, as above.
 __global__ void __launch_bounds__(256)
 k_reduce_touched(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ poff,
                  int64_t records, const uint32_t* __restrict__ status,
@@ -843,8 +843,8 @@ k_reduce_touched(const uint32_t* __restrict__ dord, const uint32_t* __restrict__
     }
     if (!any) return;
     float* g = grad_c + (int64_t)dord[p] * GC_STRIDE;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) g[k] += acc[k];
+    reinterpret_cast<float4*>(g)[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    reinterpret_cast<float2*>(g)[2] = make_float2(acc[4], acc[5]);
 }
 
 // Imaging-plane tile ranges (deterministic pass B): runs of equal keys in
