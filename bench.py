@@ -480,11 +480,12 @@ def reconstruction_bench(dev, iterations):
 
 HIT_KERNELS = {"raster_a_fwd": 0, "raster_a_bwd": 1, "raster_b_fwd": 2, "raster_b_bwd": 3}
 ENTRY_KERNELS = {"raster_a_fwd": 4, "raster_a_bwd": 5, "raster_b_fwd": 6}
-SOURCES = {"raster_a_fwd": "raster.hip", "raster_b_fwd": "raster.hip",
-           "raster_b_bwd": "raster.hip", "raster_a_bwd": "raster.hip",
-           "pair_sort": "sort.hip", "depth_sort": "sort.hip", "bin_pairs": "sort.hip",
-           "preprocess": "preprocess.hip", "plan_query": "preprocess.hip",
-           "params_bwd": "preprocess.hip"}
+# the sources of each stage's kernels (the stored counters are taken on them)
+SOURCES = {"raster_a_fwd": ("raster.hip",), "raster_b_fwd": ("raster.hip",),
+           "raster_b_bwd": ("raster.hip",), "raster_a_bwd": ("raster.hip", "sort.hip"),
+           "pair_sort": ("sort.hip",), "depth_sort": ("sort.hip",), "bin_pairs": ("sort.hip",),
+           "preprocess": ("preprocess.hip",), "plan_query": ("preprocess.hip",),
+           "params_bwd": ("preprocess.hip",)}
 
 # Lane-operations the definition needs per footprint hit ((cell, Gaussian)
 # evaluation with q < q_max), each exp weighted 4 (quarter-rate unit):
@@ -542,7 +543,7 @@ def roofline(kernel, ms, u, work):
     HIP events on the launching stream. The lane-operation count of the
     rasterizers against the VALU peak is a secondary figure."""
     src = SOURCES.get(kernel)
-    traffic = stored_traffic(kernel, 1, source_hash(src)) if src else None
+    traffic = stored_traffic(kernel, 1, source_hash(*src)) if src else None
     out = {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": None, "traffic": traffic, "kernel": kernel, "ms": ms}
     if kernel in ALGO_BYTES:
