@@ -1394,37 +1394,51 @@ k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
         const int fl = threadIdx.x - WAVE;
         const uint32_t kc = status[ST_PAIRS_C];
         const uint32_t* hw32 = reinterpret_cast<const uint32_t*>(rp.hits);
+        constexpr int NBLK = HB_SLOTS / WAVE;
         for (int fb = 0;; fb ^= 1) {
             __syncthreads();
             const uint32_t hr = s_hrec[fb];
             const uint32_t chw = hr != HIT_NONE && fl < 8 ? hw32[((uint64_t)hr + 1) * 4 + fl] : 0u;
+            // every slot's pair position in flight together (one latency),
+            // the sums read and cleared, then all the stores (no store waits
+            // on another)
+            uint32_t rk[NBLK], pp[NBLK];
+            bool one[NBLK];
 #pragma unroll
-            for (int i = 0; i < HB_SLOTS / WAVE; ++i) {
+            for (int i = 0; i < NBLK; ++i) {
                 const int sl = i * WAVE + fl;
-                const uint32_t rk = s_rec[fb][sl];
+                rk[i] = s_rec[fb][sl];
+                one[i] = s_one[fb][sl] != 0;
                 const uint32_t pos = (uint32_t)__builtin_amdgcn_readlane((int)chw, i) * WAVE + fl;
-                if (rk == HIT_NONE) continue;
+                pp[i] = rk[i] != HIT_NONE && !one[i] && pos < kc ? rp.hit_ppos[pos] : kc;
+            }
+            float v[NBLK][6];
+#pragma unroll
+            for (int i = 0; i < NBLK; ++i) {
+                const int sl = i * WAVE + fl;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) v[i][c] = 0.0f;
+                if (rk[i] == HIT_NONE) continue;
                 s_rec[fb][sl] = HIT_NONE;
-                float v[6];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
-                    v[c] = s_G[fb][c][sl];
+                    v[i][c] = s_G[fb][c][sl];
                     s_G[fb][c][sl] = 0.0f;
                 }
-                if (s_one[fb][sl]) {   // no other tile adds to this record
-                    float* g = grad_c + (int64_t)rk * GC_STRIDE;
-                    reinterpret_cast<float4*>(g)[0] = make_float4(v[0], v[1], v[2], v[3]);
-                    reinterpret_cast<float2*>(g)[2] = make_float2(v[4], v[5]);
-                    continue;
-                }
-                if (pos >= kc) continue;
-                const uint32_t pp = rp.hit_ppos[pos];
-                if (pp >= kc) continue;
-                float2* dst = reinterpret_cast<float2*>(rp.hit_part + (uint64_t)pp * 6);
-                dst[0] = make_float2(v[0], v[1]);
-                dst[1] = make_float2(v[2], v[3]);
-                dst[2] = make_float2(v[4], v[5]);
-                rp.hit_touched[pp] = 1;
+            }
+            // one store path: a record with no other tile takes its sums
+            // directly (the first six of its eight floats), any other entry
+            // its pair's partial; the mark of a direct store lands in the
+            // spare byte at the pair count, which the reduction never reads
+#pragma unroll
+            for (int i = 0; i < NBLK; ++i) {
+                if (rk[i] == HIT_NONE || (!one[i] && pp[i] >= kc)) continue;
+                float2* dst = reinterpret_cast<float2*>(
+                    one[i] ? grad_c + (int64_t)rk[i] * GC_STRIDE : rp.hit_part + (uint64_t)pp[i] * 6);
+                dst[0] = make_float2(v[i][0], v[i][1]);
+                dst[1] = make_float2(v[i][2], v[i][3]);
+                dst[2] = make_float2(v[i][4], v[i][5]);
+                rp.hit_touched[one[i] ? kc : pp[i]] = 1;
             }
             if (s_last[fb]) return;
         }
