@@ -104,9 +104,10 @@ struct RasterParams {
     unsigned long long* hit_top = nullptr;
     uint32_t hit_cap = 0;
     // the stored-hit backward's output: per list entry it touched, its six
-    // sums (plain stores at 6 * the pair's position before the pair sort,
-    // hit_ppos) and a mark in hit_touched, added per record afterwards
-    // (launch_reduce_touched), so that no float atomics are needed
+    // sums and its record (plain stores of a row of HIT_PART_STRIDE floats
+    // at the pair's position before the pair sort, hit_ppos) and a mark in
+    // hit_touched, added per record afterwards (launch_reduce_touched), so
+    // that no float atomics are needed
     const uint32_t* hit_ppos = nullptr;
     float* hit_part = nullptr;
     unsigned char* hit_touched = nullptr;
@@ -116,6 +117,7 @@ constexpr uint32_t HIT_NONE = 0xFFFFFFFFu;       // chain end / a tile with no h
 constexpr uint32_t HIT_OVERFLOW = 0xFFFFFFFEu;   // the stream was full: backward re-derives
 constexpr uint32_t HIT_HEADER_UNITS = 3;
 constexpr int GC_STRIDE = 8;   // floats per record in the computation-plane gradient sums
+constexpr int HIT_PART_STRIDE = 8;   // floats per pair partial: six sums, the record, spare
 
 // The calling thread's error message of the C ABI (sdgr_last_error): set
 // with a code to return, or cleared at the start of a call.
@@ -376,11 +378,11 @@ hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64
                                const uint32_t* status, const float* part, int ncomp,
                                int64_t part_stride, float* out, int64_t out_comp,
                                int64_t out_rec, hipStream_t s);
-// Sums of the per-pair partials the stored-hit pass A backward wrote:
-// grad_c[dord[p] * GC_STRIDE + k] = the sum of the partials part[i * 6 + k]
-// of the pairs i in [poff[p], poff[p + 1]) marked in `touched`, in order
-// (records with none are left alone).
-hipError_t launch_reduce_touched(const uint32_t* dord, const uint32_t* poff, int64_t records,
+// Sums of the per-pair partials the stored-hit pass A backward wrote: for
+// each depth rank p, the rows part[i * HIT_PART_STRIDE ..] of the pairs i in
+// [poff[p], poff[p + 1]) marked in `touched`, summed in order into the
+// six sums of the record the rows name (ranks with none are left alone).
+hipError_t launch_reduce_touched(const uint32_t* poff, int64_t records,
                                  const uint32_t* status, const unsigned char* touched,
                                  const float* part, float* grad_c, hipStream_t s);
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,

@@ -1427,17 +1427,18 @@ k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
                 }
             }
             // one store path: a record with no other tile takes its sums
-            // directly (the first six of its eight floats), any other entry
-            // its pair's partial; the mark of a direct store lands in the
-            // spare byte at the pair count, which the reduction never reads
+            // directly (its eight floats: six sums and two spare), any other
+            // entry its pair's partial row (six sums, the record, a spare);
+            // the mark of a direct store lands in the spare byte at the pair
+            // count, which the reduction never reads
 #pragma unroll
             for (int i = 0; i < NBLK; ++i) {
                 if (rk[i] == HIT_NONE || (!one[i] && pp[i] >= kc)) continue;
-                float2* dst = reinterpret_cast<float2*>(
-                    one[i] ? grad_c + (int64_t)rk[i] * GC_STRIDE : rp.hit_part + (uint64_t)pp[i] * 6);
-                dst[0] = make_float2(v[i][0], v[i][1]);
-                dst[1] = make_float2(v[i][2], v[i][3]);
-                dst[2] = make_float2(v[i][4], v[i][5]);
+                float4* dst = reinterpret_cast<float4*>(
+                    one[i] ? grad_c + (int64_t)rk[i] * GC_STRIDE
+                           : rp.hit_part + (uint64_t)pp[i] * HIT_PART_STRIDE);
+                dst[0] = make_float4(v[i][0], v[i][1], v[i][2], v[i][3]);
+                dst[1] = make_float4(v[i][4], v[i][5], __uint_as_float(rk[i]), 0.0f);
                 rp.hit_touched[one[i] ? kc : pp[i]] = 1;
             }
             if (s_last[fb]) return;

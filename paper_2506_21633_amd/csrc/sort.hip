@@ -741,10 +741,10 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
     uint32_t tot;
     const uint32_t ex = block_excl_scan_256((tx1 - tx0) * (ty1 - ty0), s_w, tot);
     if (p >= records) return;
-    if (poff) {   // deterministic mode: the record at this depth rank and its first pair
-        poff[p] = bscan[blockIdx.x] + ex;
-        dord[p] = dval[p];
-    }
+    // the first pair of this depth rank's record (deterministic mode and the
+    // stored-hit backward) and the record (deterministic mode)
+    if (poff) poff[p] = bscan[blockIdx.x] + ex;
+    if (dord) dord[p] = dval[p];
     int vp = -1;   // the view of position p, when the order is view-major
     if (seg && cached) {
         // view-major order (segmented depth sort): the first record of each
@@ -818,10 +818,9 @@ k_reduce_pairs(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ p
 // not added: this runs before the tiles whose hits are re-derived add
 // theirs with atomics). Skipped after a pair overflow, as above.
 __global__ void __launch_bounds__(256)
-k_reduce_touched(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ poff,
-                 int64_t records, const uint32_t* __restrict__ status,
-                 const unsigned char* __restrict__ touched, const float* __restrict__ part,
-                 float* __restrict__ grad_c)
+k_reduce_touched(const uint32_t* __restrict__ poff, int64_t records,
+                 const uint32_t* __restrict__ status, const unsigned char* __restrict__ touched,
+                 const float* __restrict__ part, float* __restrict__ grad_c)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= records || status[ST_OVERFLOW]) return;
@@ -829,20 +828,21 @@ k_reduce_touched(const uint32_t* __restrict__ dord, const uint32_t* __restrict__
     const uint32_t lo = min(poff[p], kc);
     const uint32_t hi = p + 1 < records ? min(poff[p + 1], kc) : kc;
     float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    bool any = false;
+    uint32_t rec = UINT32_MAX;
     for (uint32_t i = lo; i < hi; ++i) {
         if (!touched[i]) continue;
-        any = true;
-        const float2* src = reinterpret_cast<const float2*>(part + (uint64_t)i * 6);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float2 v = src[k];
-            acc[2 * k] += v.x;
-            acc[2 * k + 1] += v.y;
-        }
+        const float4* src = reinterpret_cast<const float4*>(part + (uint64_t)i * HIT_PART_STRIDE);
+        const float4 a = src[0], b = src[1];
+        acc[0] += a.x;
+        acc[1] += a.y;
+        acc[2] += a.z;
+        acc[3] += a.w;
+        acc[4] += b.x;
+        acc[5] += b.y;
+        rec = __float_as_uint(b.z);
     }
-    if (!any) return;
-    float* g = grad_c + (int64_t)dord[p] * GC_STRIDE;
+    if (rec >= (uint64_t)records) return;   // nothing touched (or not a record)
+    float* g = grad_c + (int64_t)rec * GC_STRIDE;
     reinterpret_cast<float4*>(g)[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
     reinterpret_cast<float2*>(g)[2] = make_float2(acc[4], acc[5]);
 }
@@ -1071,13 +1071,13 @@ hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_touched(const uint32_t* dord, const uint32_t* poff, int64_t records,
+hipError_t launch_reduce_touched(const uint32_t* poff, int64_t records,
                                  const uint32_t* status, const unsigned char* touched,
                                  const float* part, float* grad_c, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_touched, dim3(grid256(records)), dim3(256), 0, s, dord, poff,
-                       records, status, touched, part, grad_c);
+    hipLaunchKernelGGL(k_reduce_touched, dim3(grid256(records)), dim3(256), 0, s, poff, records,
+                       status, touched, part, grad_c);
     return hipGetLastError();
 }
 
