@@ -196,16 +196,18 @@ def test_dense_lists_elementwise(cuda, kappa, recompute, deterministic):
                      stored=not (recompute or deterministic))
 
 
-@pytest.mark.parametrize("kappa", [(0.05, 0.3), (1.0, 4.0)])
-def test_stored_hits_match_rederived(cuda, kappa):
+@pytest.mark.parametrize("kappa,shadowing", [((0.05, 0.3), True), ((1.0, 4.0), True),
+                                             ((1.0, 4.0), False)])
+def test_stored_hits_match_rederived(cuda, kappa, shadowing):
     """The backward over the forward's stored hits, over hits re-derived from
     the footprint masks (an empty stream), and with a stream too small for
     every tile (tiles that run out mid-list fall back; their partial chains
-    are ignored): the same A, images and gradients up to float rounding."""
+    are ignored): the same A, images and gradients up to float rounding.
+    Without shadowing no ray stops, so the forward stores every hit."""
     sc = dense_scene(61, 20_000, 0.6, 0.02, 0.1, *kappa)
     rng = scenes.make_rng(63)
     G = [rng.standard_normal((64, 64)) for _ in DENSE_VIEWS]
-    opts = api().RenderOptions()
+    opts = api().RenderOptions(shadowing=shadowing)
     full = gpu_run(sc, DENSE_VIEWS, G, opts, cuda)
     none = gpu_run(sc, DENSE_VIEWS, G, opts, cuda, hit_bytes=0)
     # the stored hits include every real hit (2 bytes each): half of their
@@ -213,7 +215,7 @@ def test_stored_hits_match_rederived(cuda, kappa):
     short = gpu_run(sc, DENSE_VIEWS, G, opts, cuda, hit_bytes=int(full["work"]["hits_a_bwd"]))
     w = {k: (r["work"]["tiles_a_bwd_stored"], r["work"]["tiles_a_bwd_rederived"])
          for k, r in (("full", full), ("none", none), ("short", short))}
-    print(f"\nkappa={kappa} (stored, re-derived) tiles: {w}")
+    print(f"\nkappa={kappa} shadowing={shadowing} (stored, re-derived) tiles: {w}")
     assert w["full"][0] > 0 and w["none"][0] == 0 and w["short"][1] > 0, w
     for k in ("none", "short"):
         other = none if k == "none" else short
