@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import collections
 import ctypes
+import gc
 import itertools
 import queue
 import threading
@@ -274,10 +275,22 @@ class Server:
     hbm_budget: bytes that in-flight launches may use together.
     max_views: views per fused launch. slots: launches in flight at once.
     batching=False gives the plain form: one request per launch, FIFO, one
-    launch in flight."""
+    launch in flight.
+
+    gc_freeze: move every object alive at construction (imported modules,
+    resident scenes, whatever the caller built before) to the collector's
+    permanent generation (``gc.freeze``). The collector's full passes run on
+    whichever thread happens to allocate and hold the interpreter lock
+    meanwhile; over the few hundred thousand objects a process with torch
+    holds, one pass stalls the scheduler (and the planners) for 40-60 ms,
+    which alone makes the latency tail. Frozen objects are never collected;
+    the setting is process-wide and is not undone by close()."""
 
     def __init__(self, executor, hbm_budget: int, max_views: int = 64, slots: int = 2,
-                 batching: bool = True, planners: int = 2):
+                 batching: bool = True, planners: int = 2, gc_freeze: bool = True):
+        if gc_freeze:
+            gc.collect()
+            gc.freeze()
         self.ex = executor
         self.budget = int(hbm_budget)
         self.max_views = max_views if batching else 1 << 30

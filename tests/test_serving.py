@@ -42,6 +42,19 @@ def test_two_slots_overlap_launches():
     assert len(ex.launched) == 2
 
 
+def test_gc_freeze_moves_existing_objects_out_of_the_collectors_passes():
+    import gc
+    before = gc.get_freeze_count()
+    srv = Server(FakeExecutor(base_s=0.0), hbm_budget=1 << 40, gc_freeze=False)
+    srv.close()
+    assert gc.get_freeze_count() == before
+    keep = [[i] for i in range(1000)]                 # tracked containers alive now
+    srv = Server(FakeExecutor(base_s=0.0), hbm_budget=1 << 40)
+    assert gc.get_freeze_count() >= before + len(keep)
+    assert srv.submit(Request("a", views(1))).result(5).images
+    srv.close()
+
+
 def test_hbm_budget_limits_batches():
     ex = FakeExecutor(bytes_per_view=100, base_s=0.02, per_view_s=0.0)
     srv = Server(ex, hbm_budget=350, max_views=64, slots=1)
