@@ -387,9 +387,11 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
         if (P.det || P.hit_units > 0) {
             b.ppos[0] = a.take<uint32_t>(cap_c);
             b.ppos[1] = a.take<uint32_t>(cap_c);
+        }
+        if (P.det) {
+            b.dord = a.take<uint32_t>(R);
             b.poff = a.take<uint32_t>(R);
         }
-        if (P.det) b.dord = a.take<uint32_t>(R);
         if (P.hit_units > 0) {
             b.hits = a.take<uint4>(P.hit_units + 16);   // slack for the backward's part copies
             b.hit_tail = a.take<uint32_t>(P.tiles_c);
@@ -940,7 +942,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         SDGR_HIP(launch_raster_a_bwd_hits(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
                                           b.crec, b.tau, b.cbwd, b.grad_c, P.records, s));
         if (b.hits)
-            SDGR_HIP(launch_reduce_touched(b.poff, P.records, b.status,
+            SDGR_HIP(launch_reduce_touched(plan->pairs_c, P.records, b.status,
                                            b.hit_touched, b.hit_part, b.grad_c, s));
         SDGR_HIP(launch_raster_a_bwd(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
                                      b.ranges, b.pval[pw], b.pmask, b.psum, b.crec, b.tau,

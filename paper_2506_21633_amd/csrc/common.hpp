@@ -197,6 +197,43 @@ __device__ __forceinline__ float wave_sum(float v)
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// Value of the lane a DPP row shift or row broadcast names, 0 where there
+// is none (bound control) or the row is masked off.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_from(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+
+__device__ __forceinline__ int from_lane_below(int v) { return dpp_from<0x138, 0xF>(v); }  // lane - 1
+__device__ __forceinline__ int from_lane_above(int v) { return dpp_from<0x130, 0xF>(v); }  // lane + 1
+
+// Scans over the 64 lanes in lane order: shifts by 1, 2, 4, 8 within rows
+// of 16 lanes, then the last lane of a row into the next row (row_bcast 15)
+// and of the first two rows into the last two (row_bcast 31).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_sum_step(float& x, int& f)
+{
+    const float xl = __int_as_float(dpp_from<CTRL, ROWS>(__float_as_int(x)));
+    const int fl = dpp_from<CTRL, ROWS>(f);
+    x = f ? x : xl + x;
+    f |= fl;
+}
+
+// Segmented inclusive prefix sum: `head` marks the first lane of a segment
+// (lane 0 must be one); each lane gets the sum over its segment up to itself.
+__device__ __forceinline__ float seg_incl_scan(float x, bool head)
+{
+    int f = head ? 1 : 0;
+    seg_sum_step<0x111, 0xF>(x, f);
+    seg_sum_step<0x112, 0xF>(x, f);
+    seg_sum_step<0x114, 0xF>(x, f);
+    seg_sum_step<0x118, 0xF>(x, f);
+    seg_sum_step<0x142, 0xA>(x, f);
+    seg_sum_step<0x143, 0xC>(x, f);
+    return x;
+}
+
 // Workgroups go to the eight XCDs (each with its own L2) round-robin by id.
 // For a grid whose first n workgroups have work, this renumbering hands each
 // XCD one contiguous range of [0, n), so workgroups that read the same
@@ -378,13 +415,16 @@ hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64
                                const uint32_t* status, const float* part, int ncomp,
                                int64_t part_stride, float* out, int64_t out_comp,
                                int64_t out_rec, hipStream_t s);
-// Sums of the per-pair partials the stored-hit pass A backward wrote: for
-// each depth rank p, the rows part[i * HIT_PART_STRIDE ..] of the pairs i in
-// [poff[p], poff[p + 1]) marked in `touched`, summed in order into the
-// six sums of the record the rows name (ranks with none are left alone).
-hipError_t launch_reduce_touched(const uint32_t* poff, int64_t records,
-                                 const uint32_t* status, const unsigned char* touched,
-                                 const float* part, float* grad_c, hipStream_t s);
+// Sums of the per-pair partials the stored-hit pass A backward wrote: the
+// rows part[i * HIT_PART_STRIDE ..] of the pair positions i < min(cap,
+// status[ST_PAIRS_C]) marked in `touched`, summed per record (the record a
+// row names; each record's positions are contiguous) into its six sums in
+// grad_c. Records whose rows all fall in one wave's positions are stored;
+// the others are added, so the rows of every record that can have touched
+// pairs must start at zero. Records with no touched pair are left alone.
+hipError_t launch_reduce_touched(int64_t cap, int64_t records, const uint32_t* status,
+                                 const unsigned char* touched, const float* part, float* grad_c,
+                                 hipStream_t s);
 hipError_t launch_emit_pairs_i(const DevView* views, int nv, int64_t records,
                                const uint2* rect_i, const uint32_t* cnt_i,
                                const uint32_t* bscan_i, int64_t cap_c, int64_t cap_i, bool vm,

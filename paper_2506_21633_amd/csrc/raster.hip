@@ -137,43 +137,6 @@ __device__ __forceinline__ uint64_t wave_or_u64(uint64_t v)
     return v;
 }
 
-// Value of the lane a DPP row shift or row broadcast names, 0 where there
-// is none (bound control) or the row is masked off.
-template <int CTRL, int ROWS>
-__device__ __forceinline__ int dpp_from(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
-}
-
-__device__ __forceinline__ int from_lane_below(int v) { return dpp_from<0x138, 0xF>(v); }  // lane - 1
-__device__ __forceinline__ int from_lane_above(int v) { return dpp_from<0x130, 0xF>(v); }  // lane + 1
-
-// Scans over the 64 lanes in lane order: shifts by 1, 2, 4, 8 within rows
-// of 16 lanes, then the last lane of a row into the next row (row_bcast 15)
-// and of the first two rows into the last two (row_bcast 31).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ void seg_sum_step(float& x, int& f)
-{
-    const float xl = __int_as_float(dpp_from<CTRL, ROWS>(__float_as_int(x)));
-    const int fl = dpp_from<CTRL, ROWS>(f);
-    x = f ? x : xl + x;
-    f |= fl;
-}
-
-// Segmented inclusive prefix sum: `head` marks the first lane of a segment
-// (lane 0 must be one); each lane gets the sum over its segment up to itself.
-__device__ __forceinline__ float seg_incl_scan(float x, bool head)
-{
-    int f = head ? 1 : 0;
-    seg_sum_step<0x111, 0xF>(x, f);
-    seg_sum_step<0x112, 0xF>(x, f);
-    seg_sum_step<0x114, 0xF>(x, f);
-    seg_sum_step<0x118, 0xF>(x, f);
-    seg_sum_step<0x142, 0xA>(x, f);
-    seg_sum_step<0x143, 0xC>(x, f);
-    return x;
-}
-
 template <int CTRL, int ROWS>
 __device__ __forceinline__ void seg_affine_step(float& a, float& b, int& f)
 {

@@ -812,39 +812,187 @@ k_reduce_pairs(const uint32_t* __restrict__ dord, const uint32_t* __restrict__ p
     }
 }
 
-// The stored-hit pass A backward's per-pair partials, thread = depth rank
-// p: the pairs [poff[p], next) of its record that the backward touched,
-// summed in list order into the record's computation-plane sums (stored,
-// not added: this runs before the tiles whose hits are re-derived add
-// theirs with atomics). Skipped after a pair overflow, as above.
-__global__ void __launch_bounds__(256)
-k_reduce_touched(const uint32_t* __restrict__ poff, int64_t records,
-                 const uint32_t* __restrict__ status, const unsigned char* __restrict__ touched,
-                 const float* __restrict__ part, float* __restrict__ grad_c)
+// The stored-hit pass A backward's per-pair partials, summed per record.
+// A wave takes RT_ROUNDS x 256 consecutive pair positions (pre-sort order,
+// where each record's pairs are contiguous); per round each lane reads the
+// touched marks and rows of four consecutive positions, coalesced. The
+// rows name their record, and runs of equal record over the touched rows
+// are summed: in the lane first, where a run with a run of another record
+// on both sides is complete and stored at once; then across the lanes, by
+// a segmented scan of each lane's last run (a lane's first run closes with
+// the sum carried from the lanes below), the run still open after the last
+// lane carrying into the next round. A run with a run of another record
+// before and after it inside the wave has every pair in the wave, and its
+// sums are stored (this runs before the tiles whose hits are re-derived add
+// theirs with atomics). The wave's first and last runs may go on in the
+// neighbouring waves and are added with atomics, which is why the rows of
+// the records pass A visits start at zero (the image backward clears them).
+// Skipped after a pair overflow.
+constexpr int RT_ROUNDS = 4;
+constexpr int RT_LANE = 4;   // consecutive positions per lane and round
+constexpr int RT_WAVE = RT_ROUNDS * WAVE * RT_LANE;
+
+// Six segmented inclusive lane sums that share their segment flags (the
+// DPP steps of seg_incl_scan).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_sum6_step(float (&x)[6], int& f)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= records || status[ST_OVERFLOW]) return;
-    const uint32_t kc = status[ST_PAIRS_C];
-    const uint32_t lo = min(poff[p], kc);
-    const uint32_t hi = p + 1 < records ? min(poff[p + 1], kc) : kc;
-    float acc[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-    uint32_t rec = UINT32_MAX;
-    for (uint32_t i = lo; i < hi; ++i) {
-        if (!touched[i]) continue;
-        const float4* src = reinterpret_cast<const float4*>(part + (uint64_t)i * HIT_PART_STRIDE);
-        const float4 a = src[0], b = src[1];
-        acc[0] += a.x;
-        acc[1] += a.y;
-        acc[2] += a.z;
-        acc[3] += a.w;
-        acc[4] += b.x;
-        acc[5] += b.y;
-        rec = __float_as_uint(b.z);
+    const int fl = dpp_from<CTRL, ROWS>(f);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const float xl = __int_as_float(dpp_from<CTRL, ROWS>(__float_as_int(x[k])));
+        x[k] = f ? x[k] : xl + x[k];
     }
-    if (rec >= (uint64_t)records) return;   // nothing touched (or not a record)
-    float* g = grad_c + (int64_t)rec * GC_STRIDE;
-    reinterpret_cast<float4*>(g)[0] = make_float4(acc[0], acc[1], acc[2], acc[3]);
-    reinterpret_cast<float2*>(g)[2] = make_float2(acc[4], acc[5]);
+    f |= fl;
+}
+
+__device__ __forceinline__ void seg_incl_scan6(float (&x)[6], bool head)
+{
+    int f = head ? 1 : 0;
+    seg_sum6_step<0x111, 0xF>(x, f);
+    seg_sum6_step<0x112, 0xF>(x, f);
+    seg_sum6_step<0x114, 0xF>(x, f);
+    seg_sum6_step<0x118, 0xF>(x, f);
+    seg_sum6_step<0x142, 0xA>(x, f);
+    seg_sum6_step<0x143, 0xC>(x, f);
+}
+
+__global__ void __launch_bounds__(256)
+k_reduce_touched(int64_t cap, int64_t records, const uint32_t* __restrict__ status,
+                 const unsigned char* __restrict__ touched, const float* __restrict__ part,
+                 float* __restrict__ grad_c)
+{
+    constexpr uint32_t NONE = 0xFFFFFFFFu;
+    const int lane = lane_id();
+    const int64_t base = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE) * RT_WAVE;
+    if (status[ST_OVERFLOW]) return;
+    const int64_t kc = min((int64_t)status[ST_PAIRS_C], cap);
+    if (base >= kc) return;   // wave-uniform
+    // touched marks of the lane's four positions per round, one word each
+    // (the marks array has four bytes of slack past the capacity)
+    uint32_t tw[RT_ROUNDS];
+#pragma unroll
+    for (int r = 0; r < RT_ROUNDS; ++r) {
+        const int64_t i = base + (int64_t)(r * WAVE + lane) * RT_LANE;
+        uint32_t w = 0u;
+        if (i < kc) {
+            w = *reinterpret_cast<const uint32_t*>(touched + i);
+            const int64_t left = kc - i;   // marks past the pair count are not read
+            if (left < RT_LANE) w &= (1u << (8 * left)) - 1u;
+        }
+        tw[r] = w;
+    }
+    auto put = [&](uint32_t rec, const float (&v)[6], bool add) {
+        if ((int64_t)rec >= records) return;
+        float* g = grad_c + (int64_t)rec * GC_STRIDE;
+        if (add) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) unsafeAtomicAdd(&g[k], v[k]);
+        } else {
+            reinterpret_cast<float4*>(g)[0] = make_float4(v[0], v[1], v[2], v[3]);
+            reinterpret_cast<float2*>(g)[2] = make_float2(v[4], v[5]);
+        }
+    };
+    uint32_t ckey = NONE;      // record of the run open after the last lane (wave-uniform)
+    float cs[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // its sums so far
+    bool first = true;         // no run of the wave has closed yet
+#pragma unroll
+    for (int r = 0; r < RT_ROUNDS; ++r) {
+        const int64_t i0 = base + (int64_t)(r * WAVE + lane) * RT_LANE;
+        float4 ra[RT_LANE], rb[RT_LANE];
+#pragma unroll
+        for (int j = 0; j < RT_LANE; ++j) {
+            ra[j] = rb[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if ((tw[r] >> (8 * j)) & 0xFFu) {
+                const float4* src = reinterpret_cast<const float4*>(
+                    part + (uint64_t)(i0 + j) * HIT_PART_STRIDE);
+                ra[j] = src[0];
+                rb[j] = src[1];
+            }
+        }
+        // the lane's runs: the first one's sums, the last (open) one's sums
+        int nr = 0;
+        uint32_t fkey = NONE, lkey = NONE;
+        float fs[6], ls[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) fs[k] = ls[k] = 0.0f;
+#pragma unroll
+        for (int j = 0; j < RT_LANE; ++j) {
+            if (!((tw[r] >> (8 * j)) & 0xFFu)) continue;
+            const uint32_t key = __float_as_uint(rb[j].z);
+            const float v[6] = {ra[j].x, ra[j].y, ra[j].z, ra[j].w, rb[j].x, rb[j].y};
+            if (nr > 0 && key == lkey) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) ls[k] += v[k];
+                continue;
+            }
+            if (nr == 1) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) fs[k] = ls[k];   // the first run ends
+            } else if (nr > 1) {
+                put(lkey, ls, false);   // a run between two others in the lane
+            }
+            if (nr == 0) fkey = key;
+            ++nr;
+            lkey = key;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) ls[k] = v[k];
+        }
+        const uint64_t m = __ballot(nr > 0);
+        if (m) {
+            // the open run ends where this round's first touched row names
+            // another record
+            const uint32_t fk = (uint32_t)__builtin_amdgcn_readlane((int)fkey,
+                                                                    __ffsll((long long)m) - 1);
+            if (ckey != NONE && fk != ckey) {
+                if (lane == 0) put(ckey, cs, first);
+                first = false;
+                ckey = NONE;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) cs[k] = 0.0f;
+            }
+        }
+        const uint64_t below = m & ((1ull << lane) - 1ull);
+        const uint64_t above = lane == WAVE - 1 ? 0ull : m & ~((2ull << lane) - 1ull);
+        // the open record at the nearest lane with rows below, and the first
+        // record of the nearest one above (every lane takes part)
+        const int lb = below ? 63 - __clzll((long long)below) : lane;
+        const int la = above ? __ffsll((long long)above) - 1 : lane;
+        const uint32_t pk_ = (uint32_t)__shfl((int)lkey, lb, WAVE);
+        const uint32_t nk = (uint32_t)__shfl((int)fkey, la, WAVE);
+        const uint32_t prev = below ? pk_ : ckey;
+        const bool head = nr > 1 || (nr == 1 && fkey != prev);
+        float x[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) x[k] = ls[k] + (lane == 0 && !head ? cs[k] : 0.0f);
+        seg_incl_scan6(x, head || lane == 0);
+        // the sums carried into the lane: the open run after the lane below
+        float cin[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const float xb = __int_as_float(from_lane_below(__float_as_int(x[k])));
+            cin[k] = lane == 0 ? cs[k] : xb;
+        }
+        // closings: a lane's first run when a second one starts in it, and
+        // its last run when the next lane with rows starts another record
+        const bool close_first = nr > 1;
+        const bool close_last = nr > 0 && above && nk != lkey;
+        const uint64_t cm = __ballot(close_first || close_last);
+        const bool lead = first && cm && lane == __ffsll((long long)cm) - 1;
+        if (close_first) {
+            float t[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) t[k] = fs[k] + (prev == fkey ? cin[k] : 0.0f);
+            put(fkey, t, lead);
+        }
+        if (close_last) put(lkey, x, lead && !close_first);
+        if (cm) first = false;
+        if (m) ckey = (uint32_t)__builtin_amdgcn_readlane((int)lkey, 63 - __clzll((long long)m));
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            cs[k] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x[k]), WAVE - 1));
+    }
+    if (ckey != NONE && lane == 0) put(ckey, cs, true);
 }
 
 // Imaging-plane tile ranges (deterministic pass B): runs of equal keys in
@@ -1071,12 +1219,15 @@ hipError_t launch_reduce_pairs(const uint32_t* dord, const uint32_t* poff, int64
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_touched(const uint32_t* poff, int64_t records,
-                                 const uint32_t* status, const unsigned char* touched,
-                                 const float* part, float* grad_c, hipStream_t s)
+hipError_t launch_reduce_touched(int64_t cap, int64_t records, const uint32_t* status,
+                                 const unsigned char* touched, const float* part, float* grad_c,
+                                 hipStream_t s)
 {
-    if (records <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_touched, dim3(grid256(records)), dim3(256), 0, s, poff, records,
+    if (records <= 0 || cap <= 0) return hipSuccess;
+    constexpr int64_t per_block = 4 * (int64_t)RT_WAVE;   // four waves of 256 threads
+    const int64_t grid = (cap + per_block - 1) / per_block;
+    if (grid > 0x7FFFFFFF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reduce_touched, dim3((unsigned)grid), dim3(256), 0, s, cap, records,
                        status, touched, part, grad_c);
     return hipGetLastError();
 }
