@@ -321,7 +321,6 @@ struct Bufs {
     float* grad_c = nullptr;
     float* grad_i = nullptr;
     float* pgrad = nullptr;         // per-view-group parts of the parameter gradients
-    float* cbwd = nullptr;          // c = P dL/dI per record (pass A backward)
     float* prec = nullptr;          // phase factor per record (scenes with SH)
     uint32_t* active = nullptr;     // records with A > 0 (backward)
     // deterministic mode: the computation-plane pairs' positions before the
@@ -429,8 +428,7 @@ void layout(const Problem& P, int64_t cap_c, int64_t cap_i, Phase ph, char* stat
             transient(sc);
         }
         b.grad_c = sc.take<float>(GC_STRIDE * R);   // record-major, see launch_params_backward
-        b.grad_i = sc.take<float>(6 * R);
-        b.cbwd = sc.take<float>(R);
+        b.grad_i = sc.take<float>(GC_STRIDE * R);   // record-major, as grad_c
         b.pgrad = sc.take<float>((int64_t)params_part_floats(P.nv, P.items, P.shc));
         if (P.det) b.part_g = sc.take<float>(6 * cap_c);
         if (P.hit_units > 0) {
@@ -915,7 +913,7 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         // only the records pass A used (listed by the intensity pass) carry
         // gradients; this pass also clears their computation-plane sums
         SDGR_HIP(launch_image_bwd(b.views, b.scenes, P.nv, P.records, P.rp, b.status, b.active,
-                                  b.iq, b.iw, b.prec, dL_dimages, b.grad_i, b.cbwd, b.grad_c,
+                                  b.iq, b.iw, b.prec, dL_dimages, b.grad_i, b.crec, b.grad_c,
                                   s));
     }
     {
@@ -940,13 +938,13 @@ int sdgr_backward(const sdgr_scene* scenes, int32_t nscenes, const sdgr_view* vi
         // stored hits first (their sums are stored, not added), then the
         // tiles whose hits are re-derived (atomics)
         SDGR_HIP(launch_raster_a_bwd_hits(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
-                                          b.crec, b.tau, b.cbwd, b.grad_c, P.records, s));
+                                          b.crec, b.tau, b.grad_c, P.records, s));
         if (b.hits)
             SDGR_HIP(launch_reduce_touched(plan->pairs_c, P.records, b.status,
                                            b.hit_touched, b.hit_part, b.grad_c, s));
         SDGR_HIP(launch_raster_a_bwd(b.views, P.nv, P.tiles_c, rp, b.status, b.worklist,
                                      b.ranges, b.pval[pw], b.pmask, b.psum, b.crec, b.tau,
-                                     b.nlast, b.cbwd, b.grad_c, P.records, s));
+                                     b.nlast, b.grad_c, P.records, s));
         if (P.det)
             SDGR_HIP(launch_reduce_pairs(b.dord, b.poff, P.records, b.status, b.part_g, 6,
                                          plan->pairs_c, b.grad_c, 1, GC_STRIDE, s));

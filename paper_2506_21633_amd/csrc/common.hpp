@@ -55,11 +55,13 @@ struct DevScene {
 
 // Computation-plane record of one (view, Gaussian), gathered whole by the
 // footprint masks and both pass A kernels (one 32-byte piece instead of one
-// line per field): centre and conic (cx, cy, a, b), then the conic's c and
-// the extinction kappa, padded to a full 32-byte write.
+// line per field): centre and conic (cx, cy, a, b), then the conic's c, the
+// extinction kappa, the record's tile count and, once the image backward has
+// run, the record's c = P dL/dI that pass A's backward needs per hit (0 from
+// the projection), so that it comes with the same gather.
 struct alignas(32) CRec {
     float4 q;   // cx, cy, a, b
-    float4 w;   // c, kappa, the record's tile count (bits of a uint32), 0
+    float4 w;   // c, kappa, the record's tile count (bits of a uint32), P dL/dI
 };
 
 struct RasterParams {
@@ -116,7 +118,7 @@ struct RasterParams {
 constexpr uint32_t HIT_NONE = 0xFFFFFFFFu;       // chain end / a tile with no hits
 constexpr uint32_t HIT_OVERFLOW = 0xFFFFFFFEu;   // the stream was full: backward re-derives
 constexpr uint32_t HIT_HEADER_UNITS = 3;
-constexpr int GC_STRIDE = 8;   // floats per record in the computation-plane gradient sums
+constexpr int GC_STRIDE = 8;   // floats per record in grad_c and grad_i
 constexpr int HIT_PART_STRIDE = 8;   // floats per pair partial: six sums, the record, spare
 
 // The calling thread's error message of the C ABI (sdgr_last_error): set
@@ -355,10 +357,11 @@ hipError_t launch_set_intensity(const DevView* views, const DevScene* scenes, in
                                 hipStream_t s);
 
 // Per-record gradient buffers: grad_c = (dcx, dcy, da, db, dc, dkappa) on
-// the computation plane, record-major (component k of record r at
-// [r * GC_STRIDE + k], so that the six sums pass A adds per list entry share
-// one 32-byte sector), and grad_i = (dcx, dcy, da, db, dc, dI) on the imaging
-// plane, plane-major ([k * records + r]).
+// the computation plane and grad_i = (dcx, dcy, da, db, dc, dI) on the
+// imaging plane, both record-major (component k of record r at
+// [r * GC_STRIDE + k]), so that the sums of one record share one 32-byte
+// sector: the six pass A adds per list entry, and the image backward's
+// single write of each used record's.
 hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, int nv,
                                   int nscenes, int64_t scene_items,
                                   const RasterParams& rp, const float* A,
@@ -466,22 +469,22 @@ hipError_t launch_raster_b_tiles(const DevView* views, int nv, int64_t pixels, i
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
                             int64_t records, const RasterParams& rp, const uint32_t* status,
                             const uint32_t* active, const float4* iq, const float2* iw,
-                            const float* prec, const float* dimg, float* grad_i, float* cbwd,
+                            const float* prec, const float* dimg, float* grad_i, CRec* crec,
                             float* grad_c, hipStream_t s);
 // the tiles with stored hits (rp.hits): per-pair partials, and the sums of
 // records with one tile
 hipError_t launch_raster_a_bwd_hits(const DevView* views, int nv, int64_t tiles_c,
                                     const RasterParams& rp, const uint32_t* status,
                                     const uint32_t* worklist, const CRec* crec,
-                                    const float* tau, const float* cbwd, float* grad_c,
-                                    int64_t stride, hipStream_t s);
+                                    const float* tau, float* grad_c, int64_t stride,
+                                    hipStream_t s);
 // the other tiles (all without stored hits), adding into grad_c with atomics
 hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const RasterParams& rp, const uint32_t* status,
                                const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask,
                                const uint64_t* psum, const CRec* crec,
-                               const float* tau, const uint32_t* nlast, const float* cbwd,
-                               float* grad_c, int64_t stride, hipStream_t s);
+                               const float* tau, const uint32_t* nlast, float* grad_c,
+                               int64_t stride, hipStream_t s);
 
 }  // namespace sdgr

@@ -511,7 +511,9 @@ k_params_backward(const DevView* __restrict__ views, const DevScene* __restrict_
         const float4 c0 = reinterpret_cast<const float4*>(grad_c + r * GC_STRIDE)[0];
         const float2 c1 = reinterpret_cast<const float2*>(grad_c + r * GC_STRIDE)[2];
         gc[0] = c0.x, gc[1] = c0.y, gc[2] = c0.z, gc[3] = c0.w, gc[4] = c1.x, gc[5] = c1.y;
-        for (int k = 0; k < 6; ++k) gi[k] = grad_i[k * records + r];
+        const float4 i0 = reinterpret_cast<const float4*>(grad_i + r * GC_STRIDE)[0];
+        const float2 i1 = reinterpret_cast<const float2*>(grad_i + r * GC_STRIDE)[2];
+        gi[0] = i0.x, gi[1] = i0.y, gi[2] = i0.z, gi[3] = i0.w, gi[4] = i1.x, gi[5] = i1.y;
         plane_adjoint(QC, gc, V.ex, V.ey, V.iAc, V.iEc, dS, dmu);
         plane_adjoint(QI, gi, V.ex, V.ez, V.iA, V.iR, dS, dmu);
         dk += gc[5];

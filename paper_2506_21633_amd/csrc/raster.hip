@@ -842,7 +842,7 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
             const uint32_t* __restrict__ active, const float4* __restrict__ iq,
             const float2* __restrict__ iw, const float* __restrict__ prec,
             const float* __restrict__ dimg, float* __restrict__ grad_i,
-            float* __restrict__ cbwd, float* __restrict__ grad_c)
+            CRec* __restrict__ crec, float* __restrict__ grad_c)
 {
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if ((int64_t)blockIdx.x * blockDim.x >= (int64_t)status[ST_ACTIVE]) return;
@@ -888,14 +888,13 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
             }
         }
     }
-    grad_i[r] = dcx;
-    grad_i[records + r] = dcy;
-    grad_i[2 * records + r] = da;
-    grad_i[3 * records + r] = db;
-    grad_i[4 * records + r] = dc;
-    grad_i[5 * records + r] = dI;
-    // c = P dL/dI for pass A (P the record's phase factor)
-    cbwd[r] = (prec ? prec[r] : scenes[V.scene].amp[r - V.rec_off] * (float)V.pscale) * dI;
+    float4* gi = reinterpret_cast<float4*>(grad_i + r * GC_STRIDE);
+    gi[0] = make_float4(dcx, dcy, da, db);
+    gi[1] = make_float4(dc, dI, 0.0f, 0.0f);
+    // c = P dL/dI for pass A (P the record's phase factor), in the record
+    // pass A's backward gathers per hit
+    reinterpret_cast<float*>(&crec[r].w)[3] =
+        (prec ? prec[r] : scenes[V.scene].amp[r - V.rec_off] * (float)V.pscale) * dI;
     // pass A backward adds into the record's computation-plane sums
     float4* gc = reinterpret_cast<float4*>(grad_c + r * GC_STRIDE);
     gc[0] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -937,7 +936,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                const uint32_t* __restrict__ pvals, const uint64_t* __restrict__ pmask,
                const uint64_t* __restrict__ psum, const CRec* __restrict__ crec,
                const float* __restrict__ tau, const uint32_t* __restrict__ nlast,
-               const float* __restrict__ cbwd, float* __restrict__ grad_c, int64_t stride)
+               float* __restrict__ grad_c, int64_t stride)
 {
     constexpr int NB = 2 * A_BATCH;
     constexpr int HKB = NB <= 8 ? 3 : 4;   // bits of a hit's chunk index
@@ -1195,7 +1194,7 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
                     load16_to_lds(&crec[rk].q, &s_q[k][0]);
                     load4_to_lds(w, &s_wc[k][0]);
                     load4_to_lds(w + 1, &s_wk[k][0]);
-                    load4_to_lds(cbwd + rk, &s_c[k][0]);
+                    load4_to_lds(w + 3, &s_c[k][0]);
                 }
 #pragma unroll
                 for (int k = 0; k < NB; ++k)
@@ -1330,7 +1329,7 @@ __global__ void __launch_bounds__(2 * WAVE)
 k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
                     const uint32_t* __restrict__ status, const uint32_t* __restrict__ worklist,
                     const CRec* __restrict__ crec, const float* __restrict__ tau,
-                    const float* __restrict__ cbwd, float* __restrict__ grad_c, int64_t stride)
+                    float* __restrict__ grad_c, int64_t stride)
 {
     // two buffers of per-slot sums and the record of each touched slot
     // (HIT_NONE: untouched); the flusher empties one while the main wave
@@ -1469,7 +1468,7 @@ k_raster_a_bwd_hits(const DevView* __restrict__ views, int nv, RasterParams rp,
         const float4 w = crec[rk].w;
         g.w = make_float2(w.x, w.y);
         g.one = __float_as_uint(w.z) == 1u;
-        g.c = cbwd[rk];
+        g.c = w.w;
         return g;
     };
     uint64_t b[HB_HIT_AHEAD + 1];
@@ -1721,24 +1720,24 @@ hipError_t launch_raster_b_tiles(const DevView* views, int nv, int64_t pixels, i
 hipError_t launch_image_bwd(const DevView* views, const DevScene* scenes, int nv,
                             int64_t records, const RasterParams& rp, const uint32_t* status,
                             const uint32_t* active, const float4* iq, const float2* iw,
-                            const float* prec, const float* dimg, float* grad_i, float* cbwd,
+                            const float* prec, const float* dimg, float* grad_i, CRec* crec,
                             float* grad_c, hipStream_t s)
 {
     if (records <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_image_bwd, dim3(grid256(records)), dim3(256), 0, s, views, scenes, nv,
-                       records, rp, status, active, iq, iw, prec, dimg, grad_i, cbwd, grad_c);
+                       records, rp, status, active, iq, iw, prec, dimg, grad_i, crec, grad_c);
     return hipGetLastError();
 }
 
 hipError_t launch_raster_a_bwd_hits(const DevView* views, int nv, int64_t tiles_c,
                                     const RasterParams& rp, const uint32_t* status,
                                     const uint32_t* worklist, const CRec* crec,
-                                    const float* tau, const float* cbwd, float* grad_c,
-                                    int64_t stride, hipStream_t s)
+                                    const float* tau, float* grad_c, int64_t stride,
+                                    hipStream_t s)
 {
     if (tiles_c <= 0 || !rp.hits || rp.ppos) return hipSuccess;
     hipLaunchKernelGGL(k_raster_a_bwd_hits, dim3((unsigned)tiles_c), dim3(2 * WAVE), 0, s, views,
-                       nv, rp, status, worklist, crec, tau, cbwd, grad_c, stride);
+                       nv, rp, status, worklist, crec, tau, grad_c, stride);
     return hipGetLastError();
 }
 
@@ -1747,8 +1746,8 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
                                const uint32_t* worklist, const uint2* ranges,
                                const uint32_t* pvals, const uint64_t* pmask,
                                const uint64_t* psum, const CRec* crec,
-                               const float* tau, const uint32_t* nlast, const float* cbwd,
-                               float* grad_c, int64_t stride, hipStream_t s)
+                               const float* tau, const uint32_t* nlast, float* grad_c,
+                               int64_t stride, hipStream_t s)
 {
     if (tiles_c <= 0) return hipSuccess;
     // long lists (the front of the worklist), then the short ones
@@ -1756,10 +1755,10 @@ hipError_t launch_raster_a_bwd(const DevView* views, int nv, int64_t tiles_c,
         constexpr bool D = decltype(det)::value;
         hipLaunchKernelGGL((k_raster_a_bwd<true, D>), dim3((unsigned)tiles_c), dim3(2 * WAVE), 0,
                            s, views, nv, rp, status, worklist, ranges, pvals, pmask, psum, crec,
-                           tau, nlast, cbwd, grad_c, stride);
+                           tau, nlast, grad_c, stride);
         hipLaunchKernelGGL((k_raster_a_bwd<false, D>), dim3((unsigned)tiles_c), dim3(WAVE), 0, s,
                            views, nv, rp, status, worklist, ranges, pvals, pmask, psum, crec,
-                           tau, nlast, cbwd, grad_c, stride);
+                           tau, nlast, grad_c, stride);
     };
     if (rp.ppos)
         two(std::true_type{});
