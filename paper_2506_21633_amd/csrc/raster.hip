@@ -91,14 +91,19 @@ __device__ __forceinline__ uint64_t xor_lane64(uint64_t v)
     return ((uint64_t)xor_lane<S>((uint32_t)(v >> 32)) << 32) | xor_lane<S>((uint32_t)v);
 }
 
+// Lanes with bit S clear keep their own LO blocks and take the partner's LO
+// blocks moved up; the others keep their high blocks and take the partner's
+// high blocks moved down. Both results are formed and one is picked by a
+// lane mask, so the step has no branch (a select between the two shifted
+// forms compiles to divergent half-wave paths).
 template <int S, uint64_t LO>
 __device__ __forceinline__ uint64_t transpose_step(uint64_t v)
 {
     const uint64_t p = xor_lane64<S>(v);
-    const bool up = (lane_id() & S) != 0;
-    const uint64_t keep = up ? ~LO : LO;
-    const uint64_t moved = up ? ((p & ~LO) >> S) : ((p & LO) << S);
-    return (v & keep) | moved;
+    const uint64_t lo = (v & LO) | ((p & LO) << S);
+    const uint64_t hi = (v & ~LO) | ((p & ~LO) >> S);
+    const uint64_t up = (lane_id() & S) ? ~0ull : 0ull;
+    return (lo & ~up) | (hi & up);
 }
 
 // 64x64 bit-matrix transpose across the wave: on return, bit j of lane i is
@@ -113,6 +118,26 @@ __device__ __forceinline__ uint64_t transpose64(uint64_t v)
     v = transpose_step<2, 0x3333333333333333ull>(v);
     v = transpose_step<1, 0x5555555555555555ull>(v);
     return v;
+}
+
+// N independent transposes, step by step over all of them, so that their
+// cross-lane moves and bit operations interleave (one transpose after the
+// other is a chain of dependent instructions).
+template <int N>
+__device__ __forceinline__ void transpose64_n(uint64_t (&v)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = transpose_step<32, 0x00000000FFFFFFFFull>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = transpose_step<16, 0x0000FFFF0000FFFFull>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = transpose_step<8, 0x00FF00FF00FF00FFull>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = transpose_step<4, 0x0F0F0F0F0F0F0F0Full>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = transpose_step<2, 0x3333333333333333ull>(v[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = transpose_step<1, 0x5555555555555555ull>(v[i]);
 }
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
@@ -169,6 +194,27 @@ template <int CTRL, int ROWS>
 __device__ __forceinline__ void sum_step_u32(uint32_t& x)
 {
     x += (uint32_t)dpp_from<CTRL, ROWS>((int)x);
+}
+
+// Wave totals of N values at once (inclusive scans, step by step over all
+// of them, read at the last lane).
+template <int N>
+__device__ __forceinline__ void wave_total_u32_n(uint32_t (&x)[N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i) sum_step_u32<0x111, 0xF>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sum_step_u32<0x112, 0xF>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sum_step_u32<0x114, 0xF>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sum_step_u32<0x118, 0xF>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sum_step_u32<0x142, 0xA>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) sum_step_u32<0x143, 0xC>(x[i]);
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = (uint32_t)__builtin_amdgcn_readlane((int)x[i], WAVE - 1);
 }
 
 // Exclusive prefix sum of small unsigned counts over the 64 lanes.
@@ -476,14 +522,26 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
             // chunk k covering my cell (rays already out of play keep none)
             uint64_t col[NB];
             uint32_t hk[NB];   // hits of each chunk over the wave
+            // every chunk slot is transposed (the unused ones' stale masks are
+            // dropped), all eight together; the chunks' hit totals (at most
+            // 4096 each) are summed two to a word
 #pragma unroll
-            for (int k = 0; k < NB; ++k) {
-                col[k] = 0ull;
-                if (k < nb) col[k] = transpose64(s_m[k][lane]);
-                if (!alive) col[k] = 0ull;
-                hk[k] = (uint32_t)__builtin_amdgcn_readlane(
-                    (int)(wave_excl_scan_u32((uint32_t)__popcll(col[k])) + (uint32_t)__popcll(col[k])),
-                    WAVE - 1);
+            for (int k = 0; k < NB; ++k) col[k] = s_m[k][lane];
+            transpose64_n(col);
+#pragma unroll
+            for (int k = 0; k < NB; ++k) col[k] = (k < nb && alive) ? col[k] : 0ull;
+            {
+                uint32_t tot[NB / 2];
+#pragma unroll
+                for (int i = 0; i < NB / 2; ++i)
+                    tot[i] = (uint32_t)__popcll(col[2 * i]) |
+                             ((uint32_t)__popcll(col[2 * i + 1]) << 16);
+                wave_total_u32_n(tot);
+#pragma unroll
+                for (int i = 0; i < NB / 2; ++i) {
+                    hk[2 * i] = tot[i] & 0xFFFFu;
+                    hk[2 * i + 1] = tot[i] >> 16;
+                }
             }
             if (h_on) {
                 // room for the batch's records, one per hit group (so that no
