@@ -1267,21 +1267,36 @@ k_raster_a_bwd(const DevView* __restrict__ views, int nv,
             for (int k = 0; k < NB; ++k) r_prev[k] = r_cur[k];
             // the batch's chunks, transposed: bit j of col[k] is entry j of
             // chunk k covering my cell that my ray used in the forward
+            // (all eight transposed together, as in the forward; the hit
+            // totals summed two to a word)
+            static_assert(NB % 2 == 0, "hit totals are summed in pairs");
             uint64_t col[NB];
             uint32_t hk[NB];   // hits of each chunk over the wave
 #pragma unroll
+            for (int k = 0; k < NB; ++k) col[k] = m[k];
+            transpose64_n(col);
+#pragma unroll
             for (int k = 0; k < NB; ++k) {
-                col[k] = 0ull;
+                uint64_t used = 0ull;
                 if (k < nb) {
                     const int64_t pos0 = (int64_t)s_chk[k] * WAVE - rg.x;
                     const int64_t nu = (int64_t)n_mine - pos0;   // used: positions < n_mine
-                    const uint64_t used =
-                        nu >= WAVE ? ~0ull : (nu <= 0 ? 0ull : ((1ull << nu) - 1ull));
-                    col[k] = transpose64(m[k]) & used;
+                    used = nu >= WAVE ? ~0ull : (nu <= 0 ? 0ull : ((1ull << nu) - 1ull));
                 }
-                hk[k] = (uint32_t)__builtin_amdgcn_readlane(
-                    (int)(wave_excl_scan_u32((uint32_t)__popcll(col[k])) + (uint32_t)__popcll(col[k])),
-                    WAVE - 1);
+                col[k] &= used;
+            }
+            {
+                uint32_t tot[NB / 2];
+#pragma unroll
+                for (int i = 0; i < NB / 2; ++i)
+                    tot[i] = (uint32_t)__popcll(col[2 * i]) |
+                             ((uint32_t)__popcll(col[2 * i + 1]) << 16);
+                wave_total_u32_n(tot);
+#pragma unroll
+                for (int i = 0; i < NB / 2; ++i) {
+                    hk[2 * i] = tot[i] & 0xFFFFu;
+                    hk[2 * i + 1] = tot[i] >> 16;
+                }
             }
             // groups of consecutive chunks whose hits fit s_hit; each group's
             // hits are compacted ray-major, back to front (the batch's chunks
