@@ -416,7 +416,6 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     // per-entry sums of the last processed batch leave with one atomic each;
     // they are sent once the next batch's loads have landed, so the wait for
     // those loads never waits for the atomics
-    uint32_t got_prev = 0u;
     uint32_t r_prev[NB], r_cur[NB];   // record of my entry in each chunk
     uint32_t d_prev[NB], d_cur[NB];   // deterministic mode: its pair's position before the sort
     // stored hits: this tile's chain of batch records (h_on while the stream
@@ -425,23 +424,28 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
     // takes next, the current record and its hit count
     bool h_on = !DET && rp.hits != nullptr;
     uint32_t h_top = 0u, h_end = 0u, h_blk = 256u, h_prev = HIT_NONE, h_rec = 0u, h_kept = 0u;
+    // (a nonzero sum means a live ray hit the entry, so its record was
+    // gathered and r_prev holds it: all eight sums are read at once, without
+    // a branch per chunk)
     auto flush = [&]() {
+        float a[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            if (got_prev & (1u << k)) {
-                float a = 0.0f;
+            a[k] = 0.0f;
 #pragma unroll
-                for (int g = 0; g < GC; ++g) {
-                    a += s_A[g][k][lane];
-                    s_A[g][k][lane] = 0.0f;
-                }
-                if (a != 0.0f) {
-                    if constexpr (DET) rp.part[d_prev[k]] = a;
-                    else unsafeAtomicAdd(&A[r_prev[k]], a);
-                }
+            for (int g = 0; g < GC; ++g) a[k] += s_A[g][k][lane];
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+#pragma unroll
+            for (int g = 0; g < GC; ++g) s_A[g][k][lane] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            if (a[k] != 0.0f) {
+                if constexpr (DET) rp.part[d_prev[k]] = a[k];
+                else unsafeAtomicAdd(&A[r_prev[k]], a[k]);
             }
         }
-        got_prev = 0u;
     };
     const uint32_t c_first = rg.x / WAVE, c_end = (rg.y + WAVE - 1) / WAVE;
     for (uint32_t g0 = c_first; g0 < c_end && live != 0ull; g0 += WAVE) {
@@ -476,7 +480,6 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
         fetch();
         while (nb_n > 0 && live != 0ull) {
             ++n_batch;
-            uint32_t got = 0u;   // bit k: this lane's entry of chunk k was gathered
             const int nb = nb_n;
             {
                 uint32_t chk[NB];
@@ -494,7 +497,6 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
 #pragma unroll
                 for (int k = 0; k < NB; ++k) {
                     const bool need = (m[k] & live) != 0ull;
-                    got |= need ? 1u << k : 0u;
                     const uint32_t rk = need ? r[k] : 0u;
                     const float* w = reinterpret_cast<const float*>(&crec[rk].w);
                     load16_to_lds(&crec[rk].q, &s_q[k][0]);
@@ -512,7 +514,6 @@ k_raster_a_fwd(const DevView* __restrict__ views, int nv, RasterParams rp,
             wave_lds_sync();
             fetch();   // the next batch's masks and values
             flush();
-            got_prev = got;
 #pragma unroll
             for (int k = 0; k < NB; ++k) {
                 r_prev[k] = r_cur[k];
