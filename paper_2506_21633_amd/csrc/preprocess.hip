@@ -360,29 +360,45 @@ k_set_intensity(const DevView* __restrict__ views, const DevScene* __restrict__ 
     const int v0 = wave0 < records ? find_view(nv, wave0, [&](int k) { return views[k].rec_off; })
                                    : 0;
     const int64_t v0_end = v0 + 1 < nv ? views[v0 + 1].rec_off : records;
+    // all groups' loads first (A and the phase factors, then the rectangles
+    // of the records with an intensity), so that a wave waits for two
+    // memory latencies instead of two per group
+    float a[INT_GROUPS], I[INT_GROUPS];
 #pragma unroll
     for (int g = 0; g < INT_GROUPS; ++g) {
         const int64_t r = wave0 + g * WAVE + lane;
-        float a = 0.0f;
-        uint32_t cnt = 0u;
+        a[g] = 0.0f;
+        I[g] = 0.0f;
         if (r < records) {
-            a = A[r];
+            a[g] = A[r];
             const int v = r < v0_end ? v0
                                      : find_view(nv, r, [&](int k) { return views[k].rec_off; });
             const DevView& V = views[v];
-            const float P = prec ? prec[r]
-                                 : scenes[V.scene].amp[r - V.rec_off] * (float)V.pscale;
-            const float I = P * a;
-            iw[r].y = I;
+            I[g] = prec ? prec[r] : scenes[V.scene].amp[r - V.rec_off] * (float)V.pscale;
+        }
+    }
+    uint2 ri[INT_GROUPS];
+#pragma unroll
+    for (int g = 0; g < INT_GROUPS; ++g) {
+        const int64_t r = wave0 + g * WAVE + lane;
+        I[g] *= a[g];
+        ri[g] = make_uint2(0u, 0u);
+        if (cnt_i && r < records && I[g] != 0.0f) ri[g] = rect_i[r];
+    }
+#pragma unroll
+    for (int g = 0; g < INT_GROUPS; ++g) {
+        const int64_t r = wave0 + g * WAVE + lane;
+        uint32_t cnt = 0u;
+        if (r < records) {
+            iw[r].y = I[g];
             if (cnt_i) {
-                if (I != 0.0f) {
-                    const uint2 ri = rect_i[r];
-                    cnt = ((ri.x >> 16) - (ri.x & 0xFFFF)) * ((ri.y >> 16) - (ri.y & 0xFFFF));
-                }
+                if (I[g] != 0.0f)
+                    cnt = ((ri[g].x >> 16) - (ri[g].x & 0xFFFF)) *
+                          ((ri[g].y >> 16) - (ri[g].y & 0xFFFF));
                 cnt_i[r] = cnt;
             }
         }
-        m[g] = __ballot(a != 0.0f);
+        m[g] = __ballot(a[g] != 0.0f);
         n += (uint32_t)__popcll(m[g]);
         if (cnt_i) {
             // the imaging-plane pair count of each 256 records (four groups)
