@@ -564,12 +564,12 @@ int build_lists_c(const Problem& P, const sdgr_plan* plan, const Bufs& b, bool z
         StageTimer t(SG_PAIR_SORT, s);
         if (P.seg)
             SDGR_HIP(launch_seg_setup(b.views, P.nv, R, b.status + ST_PAIRS_C, true, &b.segt[1],
-                                      s));
+                                      s, PAIR_SORT_BLOCKS));
         uint32_t* pp[2] = {b.ppos[0], b.ppos[1]};
         SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_c, b.status + ST_PAIRS_C,
                                        bits_pairs_c(P), false, b.hist, &pw, s, 0,
                                        P.seg ? &b.segt[1] : nullptr, P.nv, true,
-                                       b.ppos[0] ? pp : nullptr));
+                                       b.ppos[0] ? pp : nullptr, PAIR_SORT_BLOCKS));
     }
     if (plan->pairs_c > 0 && pw != final_buffer_c(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
@@ -600,7 +600,8 @@ int build_lists_i(const Problem& P, const sdgr_plan* plan, const Bufs& b, hipStr
     int pw = 0;
     StageTimer t(SG_PAIR_SORT_I, s);
     SDGR_HIP(launch_radix_sort_u32(pk, pv, plan->pairs_i, b.status + ST_PAIRS_I, bits_pairs_i(P),
-                                   false, b.hist, &pw, s, P.ikey_vm ? 8 : 0));
+                                   false, b.hist, &pw, s, P.ikey_vm ? 8 : 0, nullptr, 0, true,
+                                   nullptr, PAIR_SORT_BLOCKS));
     if (plan->pairs_i > 0 && pw != final_buffer_i(P))
         return fail(SDGR_EHIP, "internal: pair buffer parity");
     return SDGR_OK;

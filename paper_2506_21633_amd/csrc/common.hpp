@@ -372,6 +372,13 @@ hipError_t launch_params_backward(const DevView* views, const DevScene* scenes, 
 // sh_coeffs: the most SH coefficients of any scene.
 size_t params_part_floats(int nv, int64_t items, int sh_coeffs);
 
+// Sort grids have at most max_blocks blocks (each takes a contiguous run of
+// 4096-item tiles), between 256 and MAX_SORT_BLOCKS. Fewer, longer blocks
+// write longer runs per digit; more blocks hide more latency. Measured on
+// the 72-view vehicle: the depth sorts (four 8-bit passes) are fastest at
+// 2048, the pair sorts (one pass with wider digits) at 1024.
+constexpr unsigned MAX_SORT_BLOCKS = 2048;
+constexpr unsigned PAIR_SORT_BLOCKS = 1024;
 // stable LSD radix sort of (key, value) pairs on the low `bits` key bits.
 // n_dev points at the device-side element count (<= cap). Buffers [0] hold
 // the input; returns in *which the index of the buffer holding the output.
@@ -387,12 +394,14 @@ hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t c
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  int* which, hipStream_t s, int shift0 = 0,
                                  const SegTable* segt = nullptr, int S = 0,
-                                 bool keys_out = true, uint32_t* const* vals2 = nullptr);
+                                 bool keys_out = true, uint32_t* const* vals2 = nullptr,
+                                 unsigned max_blocks = MAX_SORT_BLOCKS);
 // Segment table of a segmented sort over the views: records (pairs = false)
 // or computation-plane pairs (pairs = true; seg[] as the emission wrote it),
 // n_dev items in all.
 hipError_t launch_seg_setup(const DevView* views, int nv, int64_t records, const uint32_t* n_dev,
-                            bool pairs, SegTable* segt, hipStream_t s);
+                            bool pairs, SegTable* segt, hipStream_t s,
+                            unsigned max_blocks = MAX_SORT_BLOCKS);
 
 // Tile rectangles of the records in depth order, and the computation-plane
 // pair count of every 256 of them (bsum).

@@ -52,12 +52,14 @@ inline int digit_bits(int bits)
     return d < 8 ? 8 : d;
 }
 
-// Sort grids have at most MAX_SORT_BLOCKS blocks; each takes a contiguous
+// Sort grids have at most max_blocks blocks; each takes a contiguous
 // run of 4096-item tiles of the actual item count, so the per-block digit
 // counts (digit-major, R x nb words) and their scan stay small however long
 // the array is.
-constexpr unsigned MAX_SORT_BLOCKS = 2048;
-inline unsigned sort_grid(int64_t cap) { return std::min(nblocks(cap), MAX_SORT_BLOCKS); }
+inline unsigned sort_grid(int64_t cap, unsigned max_blocks)
+{
+    return std::min(nblocks(cap), max_blocks);
+}
 
 struct SortSpan {
     int64_t n;      // items
@@ -126,7 +128,8 @@ __device__ __forceinline__ bool seg_items(const SegTable* t, int S, uint32_t* s_
 // many tiles per block as keep the blocks near MAX_SORT_BLOCKS.
 __global__ void __launch_bounds__(SEG_MAX)
 k_seg_setup(const DevView* __restrict__ views, int nv, int64_t records,
-            const uint32_t* __restrict__ n_dev, int pairs, SegTable* __restrict__ t)
+            const uint32_t* __restrict__ n_dev, int pairs, uint32_t max_blocks,
+            SegTable* __restrict__ t)
 {
     __shared__ uint32_t s_seg[SEG_MAX + 1];
     __shared__ uint8_t s_empty[SEG_MAX];
@@ -156,7 +159,7 @@ k_seg_setup(const DevView* __restrict__ views, int nv, int64_t records,
     const uint32_t tiles = (len + SN - 1) / SN;
     uint32_t all_tiles, total;
     (void)block_excl_scan_256(tiles, s_w, all_tiles);
-    const uint32_t tpb = max(1u, (all_tiles + MAX_SORT_BLOCKS - 1) / MAX_SORT_BLOCKS);
+    const uint32_t tpb = max(1u, (all_tiles + max_blocks - 1) / max_blocks);
     __syncthreads();   // s_w is reused by the second scan
     const uint32_t tp = block_excl_scan_256((tiles + tpb - 1) / tpb, s_w, total);
     if (tid < nv) {
@@ -448,19 +451,19 @@ k_radix_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ v
 
 // Grid of a sort pass: a segmented sort's blocks take a run of tiles of
 // their segment, and every segment may end in a shorter block.
-inline unsigned pass_grid(int64_t cap, int S, bool seg)
+inline unsigned pass_grid(int64_t cap, int S, bool seg, unsigned max_blocks)
 {
-    return seg ? sort_grid(cap) + (unsigned)S : sort_grid(cap);
+    return seg ? sort_grid(cap, max_blocks) + (unsigned)S : sort_grid(cap, max_blocks);
 }
 
 template <int BITS, bool SEG>
 hipError_t radix_passes(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
                         int shift0, const SegTable* segt, int S, bool keys_out,
-                        uint32_t* const* vals2)
+                        uint32_t* const* vals2, unsigned max_blocks)
 {
     constexpr int R = 1 << BITS;
-    const unsigned grid = pass_grid(cap, S, SEG);
+    const unsigned grid = pass_grid(cap, S, SEG, max_blocks);
     uint32_t* tot = hist + (int64_t)MAX_RADIX * grid;   // digit totals after the counts
     for (int shift = shift0; shift < shift0 + bits; shift += BITS) {
         hipLaunchKernelGGL((k_radix_hist<BITS, SEG>), dim3(grid), dim3(SB), 0, s, keys[*cur],
@@ -489,25 +492,25 @@ template <bool SEG>
 hipError_t radix_sort_t(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                         int bits, bool iota_vals, uint32_t* hist, int* cur, hipStream_t s,
                         int shift0, const SegTable* segt, int S, bool keys_out,
-                        uint32_t* const* vals2)
+                        uint32_t* const* vals2, unsigned max_blocks)
 {
     switch (digit_bits(bits)) {
     case 8:
         return radix_passes<8, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
-                                    segt, S, keys_out, vals2);
+                                    segt, S, keys_out, vals2, max_blocks);
     case 9:
         return radix_passes<9, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s, shift0,
-                                    segt, S, keys_out, vals2);
+                                    segt, S, keys_out, vals2, max_blocks);
     default:
         return radix_passes<10, SEG>(keys, vals, cap, n_dev, bits, iota_vals, hist, cur, s,
-                                     shift0, segt, S, keys_out, vals2);
+                                     shift0, segt, S, keys_out, vals2, max_blocks);
     }
 }
 
 hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const uint32_t* n_dev,
                       int bits, bool iota_vals, uint32_t* hist, int* which, hipStream_t s,
                       int shift0, const SegTable* segt, int S, bool keys_out,
-                      uint32_t* const* vals2)
+                      uint32_t* const* vals2, unsigned max_blocks)
 {
     int cur = 0;
     *which = 0;
@@ -515,9 +518,9 @@ hipError_t radix_sort(uint32_t* keys[2], uint32_t* vals[2], int64_t cap, const u
     if (segt && (S < 1 || S > SEG_MAX)) return hipErrorInvalidValue;
     const hipError_t e =
         segt ? radix_sort_t<true>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
-                                  segt, S, keys_out, vals2)
+                                  segt, S, keys_out, vals2, max_blocks)
              : radix_sort_t<false>(keys, vals, cap, n_dev, bits, iota_vals, hist, &cur, s, shift0,
-                                   nullptr, 0, keys_out, vals2);
+                                   nullptr, 0, keys_out, vals2, max_blocks);
     *which = cur;
     return e;
 }
@@ -1118,7 +1121,7 @@ size_t radix_hist_words(int64_t cap)
 {
     // counts (up to one block per tile and a partial tile per segment),
     // digit totals
-    return (size_t)MAX_RADIX * (pass_grid(cap > 0 ? cap : 1, SEG_MAX, true) + 1);
+    return (size_t)MAX_RADIX * (pass_grid(cap > 0 ? cap : 1, SEG_MAX, true, MAX_SORT_BLOCKS) + 1);
 }
 
 int radix_passes_for(int bits)
@@ -1131,18 +1134,21 @@ int radix_passes_for(int bits)
 hipError_t launch_radix_sort_u32(uint32_t* keys[2], uint32_t* vals[2], int64_t cap,
                                  const uint32_t* n_dev, int bits, bool iota_vals, uint32_t* hist,
                                  int* which, hipStream_t s, int shift0, const SegTable* segt,
-                                 int S, bool keys_out, uint32_t* const* vals2)
+                                 int S, bool keys_out, uint32_t* const* vals2,
+                                 unsigned max_blocks)
 {
+    if (max_blocks < SB || max_blocks > MAX_SORT_BLOCKS) return hipErrorInvalidValue;
     return radix_sort(keys, vals, cap, n_dev, bits, iota_vals, hist, which, s, shift0, segt, S,
-                      keys_out, vals2);
+                      keys_out, vals2, max_blocks);
 }
 
 hipError_t launch_seg_setup(const DevView* views, int nv, int64_t records, const uint32_t* n_dev,
-                            bool pairs, SegTable* segt, hipStream_t s)
+                            bool pairs, SegTable* segt, hipStream_t s, unsigned max_blocks)
 {
     if (nv < 1 || nv > SEG_MAX) return hipErrorInvalidValue;
+    if (max_blocks < SB || max_blocks > MAX_SORT_BLOCKS) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_seg_setup, dim3(1), dim3(SEG_MAX), 0, s, views, nv, records, n_dev,
-                       pairs ? 1 : 0, segt);
+                       pairs ? 1 : 0, (uint32_t)max_blocks, segt);
     return hipGetLastError();
 }
 
