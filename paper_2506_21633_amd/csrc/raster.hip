@@ -918,32 +918,47 @@ k_image_bwd(const DevView* __restrict__ views, const DevScene* __restrict__ scen
     if (det > 0.0f && a > 0.0f) {
         const float qm = rp.q_max;
         const float ry = sqrtf(qm * a / det);
+        const int W = V.W;
         // clamp in float before converting (far-away centres stay in range)
         const int row0 = (int)fmaxf(0.0f, ceilf(g.y - ry - 0.5f) - 1.0f);
         const int row1 = (int)fminf((float)(V.H - 1), floorf(g.y + ry - 0.5f) + 1.0f);
+        // the column span only bounds the pixels tested (one pixel of slack
+        // each side; q < q_max decides), so 1/a by one reciprocal is enough
+        const float inv_a = 1.0f / a;
         const float* G = dimg + V.img_off;
         for (int row = row0; row <= row1; ++row) {
             const float dy = row + 0.5f - g.y;
             const float D = a * qm - det * dy * dy;
             if (D < -1e-4f * a * qm) continue;   // rows an FP32 q < q_max can still reach
-            const float half = sqrtf(fmaxf(D, 0.0f)) / a;
-            const float xc = g.x - b * dy / a;
+            const float half = sqrtf(fmaxf(D, 0.0f)) * inv_a;
+            const float xc = g.x - b * dy * inv_a;
             const int col0 = (int)fmaxf(0.0f, ceilf(xc - half - 0.5f) - 1.0f);
-            const int col1 = (int)fminf((float)(V.W - 1), floorf(xc + half - 0.5f) + 1.0f);
-            for (int col = col0; col <= col1; ++col) {
-                const float dx = col + 0.5f - g.x;
-                const float q = quadform(g, c, dx, dy);
-                if (!(q < qm)) continue;
-                ++hits;
-                const float Gp = G[(int64_t)row * V.W + col];
-                const float e = __expf(-0.5f * q);
-                dI += Gp * (e - rp.eps) * rp.inv1meps;
-                const float dq = Gp * I * (-0.5f * e * rp.inv1meps);
-                dcx += -2.0f * dq * (a * dx + b * dy);
-                dcy += -2.0f * dq * (b * dx + c * dy);
-                da += dq * dx * dx;
-                db += 2.0f * dq * dx * dy;
-                dc += dq * dy * dy;
+            const int col1 = (int)fminf((float)(W - 1), floorf(xc + half - 0.5f) + 1.0f);
+            const float* Grow = G + (int64_t)row * W;
+            // four columns' cotangents load together (a load per pixel, each
+            // waited for, left every pixel a full memory latency)
+            for (int c0 = col0; c0 <= col1; c0 += 4) {
+                float Gq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) Gq[u] = c0 + u <= col1 ? Grow[c0 + u] : 0.0f;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int col = c0 + u;
+                    if (col > col1) break;
+                    const float dx = col + 0.5f - g.x;
+                    const float q = quadform(g, c, dx, dy);
+                    if (!(q < qm)) continue;
+                    ++hits;
+                    const float Gp = Gq[u];
+                    const float e = __expf(-0.5f * q);
+                    dI += Gp * (e - rp.eps) * rp.inv1meps;
+                    const float dq = Gp * I * (-0.5f * e * rp.inv1meps);
+                    dcx += -2.0f * dq * (a * dx + b * dy);
+                    dcy += -2.0f * dq * (b * dx + c * dy);
+                    da += dq * dx * dx;
+                    db += 2.0f * dq * dx * dy;
+                    dc += dq * dy * dy;
+                }
             }
         }
     }
