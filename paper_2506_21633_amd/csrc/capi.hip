@@ -323,11 +323,12 @@ struct Bufs {
     float* pgrad = nullptr;         // per-view-group parts of the parameter gradients
     float* prec = nullptr;          // phase factor per record (scenes with SH)
     uint32_t* active = nullptr;     // records with A > 0 (backward)
-    // deterministic mode: the computation-plane pairs' positions before the
-    // pair sort (where each (tile, record) partial lands, so that a record's
-    // partials are contiguous), the records in depth order and the first
-    // pair of each, the partials of A and of the six plane-C gradient sums,
-    // and the imaging-plane tile ranges
+    // the computation-plane pairs' positions before the pair sort (where each
+    // (tile, record) partial lands, so that a record's partials are
+    // contiguous; deterministic mode and the stored-hit backward), and for
+    // deterministic mode only the records in depth order and the first pair
+    // of each, the partials of A and of the six plane-C gradient sums, and
+    // the imaging-plane tile ranges
     uint32_t* ppos[2] = {nullptr, nullptr};
     uint32_t* dord = nullptr;
     uint32_t* poff = nullptr;

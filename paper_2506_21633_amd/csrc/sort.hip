@@ -744,8 +744,8 @@ k_emit_c(const DevView* __restrict__ views, int nv, int64_t records,
     uint32_t tot;
     const uint32_t ex = block_excl_scan_256((tx1 - tx0) * (ty1 - ty0), s_w, tot);
     if (p >= records) return;
-    // the first pair of this depth rank's record (deterministic mode and the
-    // stored-hit backward) and the record (deterministic mode)
+    // the first pair of this depth rank's record and the record
+    // (deterministic mode)
     if (poff) poff[p] = bscan[blockIdx.x] + ex;
     if (dord) dord[p] = dval[p];
     int vp = -1;   // the view of position p, when the order is view-major
