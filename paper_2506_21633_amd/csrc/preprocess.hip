@@ -469,9 +469,11 @@ __device__ void plane_adjoint(const double* Q, const float* gq, const double* u,
 // Per-Gaussian gradient outputs: d_means (3), d_scales (3), d_quats (4),
 // d_amp, d_ext (d_ext_back is the same), then the SH coefficients' (up to
 // SH_MAX) for scenes with a phase-function expansion. The backward takes the
-// views PB_VIEWS at a time (grid y).
+// views PB_VIEWS at a time (grid y): a thread's Gaussian frame serves more
+// views, fewer parts are summed; on the 72-view vehicle 16 was fastest
+// (0.216 ms at 8, 0.191 at 16, 0.201 at 24, 0.253 at 72).
 constexpr int PB_OUT = 12;
-constexpr int PB_VIEWS = 8;
+constexpr int PB_VIEWS = 16;
 
 template <bool SH>
 __device__ __forceinline__ void store_param_grads(const DevScene& S, int64_t i, const float* o)

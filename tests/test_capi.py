@@ -147,12 +147,13 @@ def test_plan_must_carry_the_sh_coefficient_count():
 
 
 def test_sh_plans_hold_the_coefficient_parts():
-    """More than one group of views: the parameter-gradient parts grow by
-    the coefficient count per Gaussian and group."""
+    """More than one group of views (40 views: at least two groups of up to
+    16): the parameter-gradient parts grow by the coefficient count per
+    Gaussian and group."""
     L = C.lib()
     got = []
     for shc in (0, 16):
-        p = _host_plan(100_000, 16, 256)
+        p = _host_plan(100_000, 40, 256)
         p.sh_coeffs = shc
         C.check(L.sdgr_plan_resize(ctypes.byref(p), 1_000_000, 1_000_000))
         got.append(p.bwd_scratch_bytes)
@@ -206,15 +207,15 @@ def test_plan_resize_keeps_parameter_gradient_scratch(recompute):
     L = C.lib()
     sizes = []
     for n in (1000, 2_000_000):
-        p = _host_plan(n, 16, 1024, recompute)
-        p.records = 16 * 2_000_000   # same records: only the Gaussian count differs
+        p = _host_plan(n, 32, 1024, recompute)
+        p.records = 32 * 2_000_000   # same records: only the Gaussian count differs
         C.check(L.sdgr_plan_resize(ctypes.byref(p), 5_000_000, 4_000_000))
         sizes.append(p.bwd_scratch_bytes)
         again = C.Plan()
         ctypes.pointer(again)[0] = p
         C.check(L.sdgr_plan_resize(ctypes.byref(again), 5_000_000, 4_000_000))
         assert again.bwd_scratch_bytes == p.bwd_scratch_bytes
-    # two groups of 8 views: at least 2 x 12 floats per extra Gaussian
+    # 32 views, at least two groups: at least 2 x 12 floats per extra Gaussian
     assert sizes[1] - sizes[0] >= 2 * 12 * 4 * (2_000_000 - 1000)
 
 
